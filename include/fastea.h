@@ -1,0 +1,221 @@
+/*
+ * fastea -- MI355X (gfx950) epipolar adjustment for FastMap-style
+ * structure from motion.  C ABI.
+ *
+ * The library refines world-to-camera camera poses (R_i, t_i) and focal
+ * lengths f_i by minimising the IRLS-reweighted epipolar objective of the
+ * FastMap chapter (Method > Optimization Formulations > Epipolar Adjustment,
+ * Eq. fastmap-epipolar-objective and the re-weighted objective after
+ * Eq. fastmap-epipolar-objective-l2), over millions of keypoint matches on
+ * one GPU.  For a pair of cameras i < j:
+ *     R_ij = R_j R_i^T,  t_ij = t_j - R_ij t_i,  u = t_ij / |t_ij|,
+ *     E = [u]x R_ij,  F = D_j E D_i,  D_k = diag(1/f_k, 1/f_k, 1),
+ * and a match with centred pixel coordinates p1 = (x1-cx_i, y1-cy_i, 1) in
+ * camera i and p2 in camera j has residual eps = p2^T F p1 (the epipolar
+ * error in normalised homogeneous coordinates).  Each IRLS round freezes the
+ * poses (snapshot), drops matches with |eps_hat| >= tau (threshold schedule
+ * decreasing to a minimum), and minimises
+ *     L = (1/Z) sum_m eps_m^2 / max(|eps_hat_m|, delta)
+ * over the Z retained matches with Adam steps (rotations in the 6D
+ * representation, focal lengths as log f per intrinsics group).
+ *
+ * Conventions
+ *   - Every function returns a fea_status (0 = success, < 0 = error) and
+ *     never aborts or throws; fea_last_error() describes the last failure.
+ *   - Arrays are row-major; R is 3x3 world-to-camera; t is 3.
+ *   - Host pointers are read (or written) during the call only; the caller
+ *     keeps ownership.  Device pointers ("_dev") are borrowed for the call and
+ *     must be device memory of the context's GPU.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *     All device work is issued on the context's HIP stream.
+ *   - Call order: fea_create -> fea_load_intrinsics -> fea_load_matches* ->
+ *     fea_init_poses -> (fea_epipolar_adjust | fea_begin_round/fea_step ...)
+ *     -> fea_get_poses.  Out-of-order calls return FEA_ESTATE.
+ */
+#ifndef FASTEA_H
+#define FASTEA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FEA_VERSION 100 /* 0.1.0 */
+
+typedef struct fea_ctx fea_ctx;
+
+typedef enum {
+  FEA_OK = 0,
+  FEA_EINVAL = -1,       /* bad argument (null pointer, size, id out of range) */
+  FEA_ENOMEM = -2,       /* device or host allocation failed */
+  FEA_EDEVICE = -3,      /* HIP runtime error */
+  FEA_ESTATE = -4,       /* call out of order */
+  FEA_EDEGENERATE = -5,  /* a camera pair with coincident centres (t_ij = 0) */
+  FEA_ENONFINITE = -6    /* non-finite input coordinates, poses or focals */
+} fea_status;
+
+/* Solver options.  The paper fixes none of these constants; the defaults
+ * (fea_default_options) are this library's documented choices. */
+typedef struct {
+  int32_t rounds;          /* IRLS rounds (default 20) */
+  int32_t iters_per_round; /* Adam steps per round (default 50) */
+  double tau_px_init;      /* round-0 filter threshold in pixels (128) */
+  double tau_px_min;       /* threshold floor in pixels (4) */
+  double tau_decay;        /* threshold factor per round (0.5) */
+  double delta;            /* weight floor: 1/max(|eps_hat|, delta), normalised units (1e-4) */
+  double lr_rot;           /* Adam learning rate of the 6D rotation parameters (3e-3) */
+  double lr_t;             /* ... of translations, in the normalised gauge (3e-3) */
+  double lr_logf;          /* ... of log focal length per intrinsics group (1e-3) */
+  double beta1, beta2;     /* Adam moment decay (0.9, 0.999) */
+  double adam_eps;         /* Adam epsilon (1e-12) */
+  int32_t optimize_focal;  /* 1: refine focal lengths (default), 0: keep them fixed */
+  int32_t gauge_normalize; /* 1: before solving, move camera centres to mean 0
+                              and median matched-pair baseline 1 (default);
+                              poses are returned in the caller's frame */
+  int32_t log_every;       /* >0: keep the rotations every log_every steps (0) */
+  int32_t max_log;         /* capacity of that log, in snapshots (0) */
+  int32_t reserved[8];     /* must be zero */
+} fea_options;
+
+/* What fea_epipolar_adjust did. */
+typedef struct {
+  int32_t rounds_run;
+  int32_t iters_run;
+  int64_t inliers_per_round[64]; /* Z of each round (first 64 rounds) */
+  double loss_per_round[64];     /* loss at the last step of each round */
+  double ms_total;               /* wall time of the call, milliseconds */
+  int32_t n_logged;              /* pose snapshots kept (log_every > 0) */
+  int32_t reserved[7];
+} fea_report;
+
+/* Sizes and state of a context. */
+typedef struct {
+  int32_t n_cams;
+  int32_t n_groups;      /* intrinsics groups */
+  int64_t n_matches;     /* loaded matches */
+  int64_t n_pairs;       /* distinct camera pairs among them */
+  int64_t n_retained;    /* matches kept by the current round (Z) */
+  int64_t n_items;       /* work items of the per-match pass */
+  int64_t layout_matches;/* matches in the device layout incl. alignment padding */
+  int32_t round;         /* current round index, -1 before the first */
+  int32_t step;          /* Adam steps taken in the current round */
+  double gauge_center[3];/* applied gauge: centre' = (centre - gauge_center)/gauge_scale */
+  double gauge_scale;
+  double tau;            /* current threshold, normalised units */
+  int32_t reserved[8];
+} fea_info;
+
+/* Library version (FEA_VERSION of the build). */
+int32_t fea_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char *fea_status_string(fea_status s);
+
+/* Fills *out with the default options.  FEA_EINVAL if out is NULL. */
+fea_status fea_default_options(fea_options *out);
+
+/* Creates a context on GPU `device` (HIP device index).  opt may be NULL
+ * (defaults).  hip_stream: a hipStream_t to issue all work on, or NULL for a
+ * stream owned by the context (created at default priority).  On success
+ * *out receives the context; release it with fea_destroy. */
+fea_status fea_create(fea_ctx **out, int32_t device, const fea_options *opt,
+                      void *hip_stream);
+
+/* Releases every resource of the context (NULL is a no-op). */
+void fea_destroy(fea_ctx *ctx);
+
+/* Message of the last failed call on this context ("" if none). */
+const char *fea_last_error(const fea_ctx *ctx);
+
+/* Replaces the solver options (allowed at any time before fea_epipolar_adjust
+ * or fea_begin_round; takes effect from the next round). */
+fea_status fea_set_options(fea_ctx *ctx, const fea_options *opt);
+
+/* Camera intrinsics (Method > Intrinsics Estimation: principal point fixed at
+ * the image centre, a few physical cameras with shared intrinsics).
+ * f, cx, cy: host arrays [n_cams] in pixels, f > 0 and finite.  intr_group:
+ * host array [n_cams] of group ids in [0, n_cams), or NULL for one group per
+ * camera; cameras of one group share one focal length (initialised to the
+ * geometric mean of their f).  Resets any loaded matches and poses. */
+fea_status fea_load_intrinsics(fea_ctx *ctx, int32_t n_cams, const double *f,
+                               const double *cx, const double *cy, const int32_t *intr_group);
+
+/* Keypoint matches (Method > Epipolar Adjustment: point pairs Q_n of the
+ * image pairs P).  Match m relates pixel (x1[m], y1[m]) of camera cam1[m] to
+ * (x2[m], y2[m]) of camera cam2[m].  Host arrays of length n, copied.
+ * Errors: FEA_EINVAL if cam1 == cam2 or an id is outside [0, n_cams) or
+ * n >= 2^31; FEA_ENONFINITE for a non-finite coordinate.  n = 0 is valid.
+ * The library canonicalises every match to cam1 < cam2 (swapping its
+ * keypoints) and sorts them by camera pair on the GPU (stable). */
+fea_status fea_load_matches(fea_ctx *ctx, int64_t n, const float *x1, const float *y1,
+                            const float *x2, const float *y2, const int32_t *cam1,
+                            const int32_t *cam2);
+
+/* Same as fea_load_matches, with device arrays (borrowed during the call). */
+fea_status fea_load_matches_device(fea_ctx *ctx, int64_t n, const float *x1_dev,
+                                   const float *y1_dev, const float *x2_dev,
+                                   const float *y2_dev, const int32_t *cam1_dev,
+                                   const int32_t *cam2_dev);
+
+/* Initial poses: R [n_cams*9] row-major world-to-camera rotations, t
+ * [n_cams*3]; host arrays.  Rotations must be proper (det > 0) and finite.
+ * Applies the gauge normalisation if enabled and resets the round state.
+ * FEA_EDEGENERATE if two matched cameras share a centre. */
+fea_status fea_init_poses(fea_ctx *ctx, const double *R, const double *t);
+
+/* Starts an IRLS round (re-weighting rounds and outlier filtering of the
+ * Epipolar Adjustment paragraph): freezes the current poses as the snapshot,
+ * drops matches with |eps_hat| >= tau_px / median(f) (tau_px in pixels; pass
+ * INFINITY to keep all), and resets the Adam moments.  Dropped matches stay
+ * dropped for the rest of the solve. */
+fea_status fea_begin_round(fea_ctx *ctx, double tau_px);
+
+/* One pass of the residual, IRLS weight and gradient at the current poses,
+ * with the current round's weights (no parameter update).  Outputs are
+ * device arrays, caller-allocated, any of which may be NULL:
+ *   loss_dev [1]; gR_dev [n_cams*9] dL/dR (R as an unconstrained 3x3);
+ *   gt_dev [n_cams*3] dL/dt; gf_dev [n_cams] dL/df.
+ * Derivatives are taken in the gauge the context works in (fea_info). */
+fea_status fea_residual_grad(fea_ctx *ctx, double *loss_dev, double *gR_dev, double *gt_dev,
+                             double *gf_dev);
+
+/* n_steps Adam steps of the current round (each: residual, weight, gradient,
+ * per-camera chain rule and update). */
+fea_status fea_step(fea_ctx *ctx, int32_t n_steps);
+
+/* The whole solve: options.rounds rounds of fea_begin_round with the
+ * threshold schedule max(tau_px_init * tau_decay^r, tau_px_min) followed by
+ * options.iters_per_round steps.  out may be NULL. */
+fea_status fea_epipolar_adjust(fea_ctx *ctx, fea_report *out);
+
+/* Current poses in the caller's frame: R [n_cams*9], t [n_cams*3], f
+ * [n_cams] (host arrays, caller-allocated; any may be NULL). */
+fea_status fea_get_poses(fea_ctx *ctx, double *R, double *t, double *f);
+
+/* The segmentation of the loaded matches (host arrays, caller-allocated,
+ * any may be NULL): perm [n_matches] input index of the match at each sorted
+ * position; swapped [n_matches] 1 if that match was re-oriented;
+ * pair_cams [2*n_pairs] (i, j) of each pair in lexicographic order;
+ * seg_off [n_pairs+1] sorted range of each pair. */
+fea_status fea_get_segments(fea_ctx *ctx, int32_t *perm, uint8_t *swapped,
+                            int32_t *pair_cams, int64_t *seg_off);
+
+/* Which matches the current round retains (host array [n_matches], indexed
+ * by input order; 1 = retained).  n_retained may be NULL. */
+fea_status fea_get_mask(fea_ctx *ctx, uint8_t *mask, int64_t *n_retained);
+
+/* Sizes and state. */
+fea_status fea_get_info(fea_ctx *ctx, fea_info *out);
+
+/* Rotation log kept by fea_epipolar_adjust when options.log_every > 0:
+ * R_log [max_log * n_cams * 9] host, in the caller's frame; *n_logged
+ * receives the count.  Entry k holds the rotations after step
+ * (k+1)*log_every, counting steps across rounds. */
+fea_status fea_get_rotation_log(fea_ctx *ctx, double *R_log, int32_t *n_logged);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTEA_H */

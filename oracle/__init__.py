@@ -1,0 +1,264 @@
+"""FP64 CPU oracle for FastMap epipolar adjustment (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg use it to check and time the GPU library.  The
+library itself never imports it.  The arithmetic lives in ``fea_oracle.c``
+(plain C, double precision); this module only marshals numpy arrays.
+
+Parity status: see the per-function notes in ``fea_oracle.h``; the IRLS
+threshold schedule and optimiser constants are not fixed by the paper
+("parity unpinned" for those constants: they are pinned only by outcome).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP over image pairs)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-o", _LIB_PATH + ".tmp", os.path.join(_HERE, "fea_oracle.c"), "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class Problem(C.Structure):
+    _fields_ = [("n_matches", C.c_int64), ("n_cams", C.c_int32),
+                ("x1", C.c_void_p), ("y1", C.c_void_p), ("x2", C.c_void_p),
+                ("y2", C.c_void_p), ("cam1", C.c_void_p), ("cam2", C.c_void_p),
+                ("cx", C.c_void_p), ("cy", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("iters_per_round", C.c_int32),
+                ("tau_px_init", C.c_double), ("tau_px_min", C.c_double),
+                ("tau_decay", C.c_double), ("delta", C.c_double),
+                ("lr_rot", C.c_double), ("lr_t", C.c_double), ("lr_logf", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("adam_eps", C.c_double),
+                ("optimize_focal", C.c_int32), ("gauge_normalize", C.c_int32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        _lib.orc_segment.argtypes = [C.c_int64, C.c_int32, P, P, P, P, P, P, P]
+        _lib.orc_segment.restype = C.c_int
+        _lib.orc_rot6d_to_R.argtypes = [P, P]
+        _lib.orc_rot6d_backward.argtypes = [P, P, P]
+        _lib.orc_R_to_rot6d.argtypes = [P, P]
+        _lib.orc_pair_F.argtypes = [P, P, C.c_double, P, P, C.c_double, P]
+        _lib.orc_pair_F.restype = C.c_int
+        _lib.orc_residuals.argtypes = [P, P, P, P, P]
+        _lib.orc_residuals.restype = C.c_int
+        _lib.orc_update_mask.argtypes = [P, P, P, P, C.c_double, P]
+        _lib.orc_update_mask.restype = C.c_int64
+        _lib.orc_loss_grad.argtypes = [P, P, P, P, P, P, P, P, C.c_double, P, P, P, P]
+        _lib.orc_loss_grad.restype = C.c_int
+        _lib.orc_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int64, C.c_double, C.c_double,
+                                  C.c_double, C.c_double]
+        _lib.orc_gauge_normalize.argtypes = [C.c_int32, P, P, C.c_int64, P, P, P]
+        _lib.orc_epipolar_adjust.argtypes = [P, P, P, P, P, P, P, P, P, P, P, C.c_int32,
+                                             C.c_int32, P, P, P]
+        _lib.orc_epipolar_adjust.restype = C.c_int
+        _lib.orc_default_options.argtypes = [P]
+        _lib.orc_num_threads.restype = C.c_int
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleProblem:
+    """Holds contiguous copies of a scene's matches for the C oracle."""
+
+    def __init__(self, x1, y1, x2, y2, cam1, cam2, cx, cy):
+        self.x1 = np.ascontiguousarray(x1, np.float32)
+        self.y1 = np.ascontiguousarray(y1, np.float32)
+        self.x2 = np.ascontiguousarray(x2, np.float32)
+        self.y2 = np.ascontiguousarray(y2, np.float32)
+        self.cam1 = np.ascontiguousarray(cam1, np.int32)
+        self.cam2 = np.ascontiguousarray(cam2, np.int32)
+        self.cx = _f64(cx)
+        self.cy = _f64(cy)
+        self.n_cams = len(self.cx)
+        self.s = Problem(len(self.x1), self.n_cams, _p(self.x1).value, _p(self.y1).value,
+                         _p(self.x2).value, _p(self.y2).value, _p(self.cam1).value,
+                         _p(self.cam2).value, _p(self.cx).value, _p(self.cy).value)
+
+    @classmethod
+    def from_scene(cls, sc, sel=None):
+        if sel is None:
+            return cls(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2, sc.cx, sc.cy)
+        return cls(sc.x1[sel], sc.y1[sel], sc.x2[sel], sc.y2[sel], sc.cam1[sel],
+                   sc.cam2[sel], sc.cx, sc.cy)
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+    @property
+    def n_matches(self):
+        return len(self.x1)
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().orc_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def segment(cam1, cam2, n_cams):
+    cam1 = np.ascontiguousarray(cam1, np.int32)
+    cam2 = np.ascontiguousarray(cam2, np.int32)
+    n = len(cam1)
+    perm = np.zeros(max(n, 1), np.int32)
+    swapped = np.zeros(max(n, 1), np.uint8)
+    pair_cams = np.zeros(2 * max(n, 1), np.int32)
+    seg_off = np.zeros(max(n, 1) + 1, np.int64)
+    npairs = C.c_int64(0)
+    rc = lib().orc_segment(n, n_cams, _p(cam1), _p(cam2), _p(perm), _p(swapped),
+                           _p(pair_cams), _p(seg_off), C.byref(npairs))
+    if rc:
+        raise ValueError("oracle segment rejected the matches")
+    P = npairs.value
+    return (perm[:n], swapped[:n].astype(bool), pair_cams[:2 * P].reshape(P, 2),
+            seg_off[:P + 1])
+
+
+def rot6d_to_R(a6):
+    a6 = _f64(a6)
+    R = np.zeros(9)
+    lib().orc_rot6d_to_R(_p(a6), _p(R))
+    return R.reshape(3, 3)
+
+
+def R_to_rot6d(R):
+    R = _f64(R)
+    a6 = np.zeros(6)
+    lib().orc_R_to_rot6d(_p(R), _p(a6))
+    return a6
+
+
+def rot6d_backward(a6, gR):
+    a6, gR = _f64(a6), _f64(gR)
+    g = np.zeros(6)
+    lib().orc_rot6d_backward(_p(a6), _p(gR), _p(g))
+    return g
+
+
+def pair_F(Ri, ti, fi, Rj, tj, fj):
+    F = np.zeros(9)
+    Ri, ti, Rj, tj = _f64(Ri), _f64(ti), _f64(Rj), _f64(tj)
+    if lib().orc_pair_F(_p(Ri), _p(ti), float(fi), _p(Rj), _p(tj), float(fj), _p(F)):
+        raise ValueError("degenerate pair (t_ij = 0)")
+    return F.reshape(3, 3)
+
+
+def residuals(pb: OracleProblem, R, t, f):
+    R, t, f = _f64(R), _f64(t), _f64(f)
+    eps = np.zeros(max(pb.n_matches, 1))
+    rc = lib().orc_residuals(pb.ref, _p(R), _p(t), _p(f), _p(eps))
+    if rc:
+        raise ValueError(f"oracle residuals failed ({rc})")
+    return eps[:pb.n_matches]
+
+
+def update_mask(pb: OracleProblem, Rh, th, fh, tau, mask):
+    Rh, th, fh = _f64(Rh), _f64(th), _f64(fh)
+    mask = np.ascontiguousarray(mask, np.uint8).copy()
+    Z = lib().orc_update_mask(pb.ref, _p(Rh), _p(th), _p(fh), float(tau), _p(mask))
+    if Z < 0:
+        raise ValueError("oracle update_mask failed")
+    return mask.astype(bool), int(Z)
+
+
+def loss_grad(pb: OracleProblem, R, t, f, Rh=None, th=None, fh=None, mask=None,
+              delta=1e-4):
+    """Loss and (dL/dR [N,3,3], dL/dt [N,3], dL/df [N]) at (R,t,f)."""
+    N = pb.n_cams
+    R, t, f = _f64(R), _f64(t), _f64(f)
+    Rh = R if Rh is None else _f64(Rh)
+    th = t if th is None else _f64(th)
+    fh = f if fh is None else _f64(fh)
+    if mask is None:
+        mask = np.ones(pb.n_matches, np.uint8)
+    mask = np.ascontiguousarray(mask, np.uint8)
+    loss = C.c_double(0.0)
+    gR = np.zeros(9 * N)
+    gt = np.zeros(3 * N)
+    gf = np.zeros(N)
+    rc = lib().orc_loss_grad(pb.ref, _p(R), _p(t), _p(f), _p(Rh), _p(th), _p(fh), _p(mask),
+                             float(delta), C.byref(loss), _p(gR), _p(gt), _p(gf))
+    if rc:
+        raise ValueError(f"oracle loss_grad failed ({rc})")
+    return loss.value, gR.reshape(N, 3, 3), gt.reshape(N, 3), gf
+
+
+def adam(p, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-12):
+    p, m, v, g = _f64(p).copy(), _f64(m).copy(), _f64(v).copy(), _f64(g)
+    lib().orc_adam(len(p), _p(p), _p(m), _p(v), _p(g), int(step), lr, beta1, beta2, eps)
+    return p, m, v
+
+
+def gauge_normalize(R, t, pair_cams):
+    """Centres to mean 0, median matched-pair baseline to 1."""
+    R = _f64(R)
+    t = _f64(t).copy()
+    pc = np.ascontiguousarray(pair_cams, np.int32)
+    center = np.zeros(3)
+    scale = C.c_double(0.0)
+    lib().orc_gauge_normalize(len(R), _p(R), _p(t), len(pc), _p(pc), _p(center),
+                              C.byref(scale))
+    return t, center, scale.value
+
+
+def epipolar_adjust(pb: OracleProblem, R0, t0, f0, intr_group=None, options=None,
+                    log_every=0, max_log=0):
+    """Run the whole EA loop; returns dict with R, t, f, losses, inliers, logs."""
+    N = pb.n_cams
+    opt = options if options is not None else default_options()
+    R0, t0, f0 = _f64(R0), _f64(t0), _f64(f0)
+    ig = None if intr_group is None else np.ascontiguousarray(intr_group, np.int32)
+    R = np.zeros(9 * N)
+    t = np.zeros(3 * N)
+    f = np.zeros(N)
+    losses = np.zeros(max(opt.rounds, 1))
+    inl = np.zeros(max(opt.rounds, 1), np.int64)
+    logR = np.zeros((max(max_log, 1), N, 9)) if max_log > 0 else None
+    nlog = C.c_int32(0)
+    mask = np.zeros(max(pb.n_matches, 1), np.uint8)
+    rc = lib().orc_epipolar_adjust(pb.ref, C.byref(opt), _p(R0), _p(t0), _p(f0), _p(ig),
+                                   _p(R), _p(t), _p(f), _p(losses), _p(inl), log_every,
+                                   max_log, _p(logR), C.byref(nlog), _p(mask))
+    if rc:
+        raise ValueError(f"oracle epipolar_adjust failed ({rc})")
+    out = dict(R=R.reshape(N, 3, 3), t=t.reshape(N, 3), f=f, loss=losses[:opt.rounds],
+               inliers=inl[:opt.rounds], mask=mask[:pb.n_matches].astype(bool))
+    if logR is not None:
+        out["log_R"] = logR[:nlog.value].reshape(-1, N, 3, 3)
+    return out
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())

@@ -1,0 +1,645 @@
+/*
+ * FP64 CPU oracle for FastMap epipolar adjustment -- TEST INFRASTRUCTURE ONLY.
+ * See fea_oracle.h for the conventions and the readings of the paper.
+ * Every function is written for clarity: straight loops in double precision,
+ * no blocking, no fusion, no reordering beyond what the definitions state.
+ */
+#include "fea_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void orc_default_options(orc_options *o) {
+  o->rounds = 20;
+  o->iters_per_round = 50;
+  o->tau_px_init = 128.0;
+  o->tau_px_min = 4.0;
+  o->tau_decay = 0.5;
+  o->delta = 1e-4;
+  o->lr_rot = 3e-3;
+  o->lr_t = 3e-3;
+  o->lr_logf = 1e-3;
+  o->beta1 = 0.9;
+  o->beta2 = 0.999;
+  o->adam_eps = 1e-12;
+  o->optimize_focal = 1;
+  o->gauge_normalize = 1;
+}
+
+/* ---- small 3x3 helpers (row-major) ------------------------------------ */
+
+static void mat_mul(const double A[9], const double B[9], double C[9]) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[r * 3 + k] * B[k * 3 + c];
+      C[r * 3 + c] = s;
+    }
+}
+
+static void mat_mul_bt(const double A[9], const double B[9], double C[9]) { /* A B^T */
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[r * 3 + k] * B[c * 3 + k];
+      C[r * 3 + c] = s;
+    }
+}
+
+static void mat_mul_at(const double A[9], const double B[9], double C[9]) { /* A^T B */
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[k * 3 + r] * B[k * 3 + c];
+      C[r * 3 + c] = s;
+    }
+}
+
+static void mat_vec(const double A[9], const double x[3], double y[3]) {
+  for (int r = 0; r < 3; ++r) y[r] = A[r * 3] * x[0] + A[r * 3 + 1] * x[1] + A[r * 3 + 2] * x[2];
+}
+
+static void mat_t_vec(const double A[9], const double x[3], double y[3]) {
+  for (int r = 0; r < 3; ++r) y[r] = A[r] * x[0] + A[3 + r] * x[1] + A[6 + r] * x[2];
+}
+
+static void skew(const double u[3], double S[9]) { /* S x = u cross x */
+  S[0] = 0.0;   S[1] = -u[2]; S[2] = u[1];
+  S[3] = u[2];  S[4] = 0.0;   S[5] = -u[0];
+  S[6] = -u[1]; S[7] = u[0];  S[8] = 0.0;
+}
+
+static void cross(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* ---- segmenting --------------------------------------------------------- */
+
+typedef struct {
+  int64_t key; /* i * n_cams + j with i < j */
+  int64_t idx; /* input position: the tie-break that makes the sort stable */
+} seg_item;
+
+static int seg_cmp(const void *a, const void *b) {
+  const seg_item *x = (const seg_item *)a, *y = (const seg_item *)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  if (x->idx != y->idx) return x->idx < y->idx ? -1 : 1;
+  return 0;
+}
+
+int orc_segment(int64_t n, int32_t n_cams, const int32_t *cam1, const int32_t *cam2,
+                int32_t *perm, uint8_t *swapped, int32_t *pair_cams, int64_t *seg_off,
+                int64_t *n_pairs) {
+  for (int64_t m = 0; m < n; ++m) {
+    if (cam1[m] < 0 || cam1[m] >= n_cams || cam2[m] < 0 || cam2[m] >= n_cams) return -1;
+    if (cam1[m] == cam2[m]) return -1;
+  }
+  seg_item *it = (seg_item *)malloc(sizeof(seg_item) * (size_t)(n > 0 ? n : 1));
+  if (!it) return -1;
+  for (int64_t m = 0; m < n; ++m) {
+    int64_t i = cam1[m] < cam2[m] ? cam1[m] : cam2[m];
+    int64_t j = cam1[m] < cam2[m] ? cam2[m] : cam1[m];
+    it[m].key = i * (int64_t)n_cams + j;
+    it[m].idx = m;
+  }
+  qsort(it, (size_t)n, sizeof(seg_item), seg_cmp);
+  int64_t np = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    int64_t m = it[p].idx;
+    perm[p] = (int32_t)m;
+    swapped[p] = (uint8_t)(cam1[m] > cam2[m]);
+    if (p == 0 || it[p].key != it[p - 1].key) {
+      pair_cams[2 * np] = (int32_t)(it[p].key / n_cams);
+      pair_cams[2 * np + 1] = (int32_t)(it[p].key % n_cams);
+      seg_off[np] = p;
+      ++np;
+    }
+  }
+  seg_off[np] = n;
+  *n_pairs = np;
+  free(it);
+  return 0;
+}
+
+/* ---- 6D rotation representation ---------------------------------------- */
+
+void orc_rot6d_to_R(const double a6[6], double R[9]) {
+  const double *a1 = a6, *a2 = a6 + 3;
+  double b1[3], b2[3], b3[3], v[3];
+  double n1 = sqrt(dot3(a1, a1));
+  for (int k = 0; k < 3; ++k) b1[k] = a1[k] / n1;
+  double d = dot3(b1, a2);
+  for (int k = 0; k < 3; ++k) v[k] = a2[k] - d * b1[k];
+  double n2 = sqrt(dot3(v, v));
+  for (int k = 0; k < 3; ++k) b2[k] = v[k] / n2;
+  cross(b1, b2, b3);
+  for (int r = 0; r < 3; ++r) {
+    R[r * 3 + 0] = b1[r];
+    R[r * 3 + 1] = b2[r];
+    R[r * 3 + 2] = b3[r];
+  }
+}
+
+void orc_R_to_rot6d(const double R[9], double a6[6]) {
+  for (int r = 0; r < 3; ++r) {
+    a6[r] = R[r * 3 + 0];
+    a6[3 + r] = R[r * 3 + 1];
+  }
+}
+
+void orc_rot6d_backward(const double a6[6], const double gR[9], double ga6[6]) {
+  const double *a1 = a6, *a2 = a6 + 3;
+  double b1[3], b2[3], v[3];
+  double n1 = sqrt(dot3(a1, a1));
+  for (int k = 0; k < 3; ++k) b1[k] = a1[k] / n1;
+  double d = dot3(b1, a2);
+  for (int k = 0; k < 3; ++k) v[k] = a2[k] - d * b1[k];
+  double n2 = sqrt(dot3(v, v));
+  for (int k = 0; k < 3; ++k) b2[k] = v[k] / n2;
+  double gb1[3], gb2[3], gb3[3], tmp[3];
+  for (int r = 0; r < 3; ++r) {
+    gb1[r] = gR[r * 3 + 0];
+    gb2[r] = gR[r * 3 + 1];
+    gb3[r] = gR[r * 3 + 2];
+  }
+  /* b3 = b1 x b2 */
+  cross(b2, gb3, tmp);
+  for (int k = 0; k < 3; ++k) gb1[k] += tmp[k];
+  cross(gb3, b1, tmp);
+  for (int k = 0; k < 3; ++k) gb2[k] += tmp[k];
+  /* b2 = v / |v|, v = a2 - (b1 . a2) b1 */
+  double gv[3], s = dot3(b2, gb2);
+  for (int k = 0; k < 3; ++k) gv[k] = (gb2[k] - s * b2[k]) / n2;
+  double b1gv = dot3(b1, gv);
+  for (int k = 0; k < 3; ++k) {
+    ga6[3 + k] = gv[k] - b1gv * b1[k];
+    gb1[k] += -d * gv[k] - b1gv * a2[k];
+  }
+  /* b1 = a1 / |a1| */
+  double s1 = dot3(b1, gb1);
+  for (int k = 0; k < 3; ++k) ga6[k] = (gb1[k] - s1 * b1[k]) / n1;
+}
+
+/* ---- pair geometry -------------------------------------------------------- */
+
+typedef struct {
+  double Rij[9], tij[3], u[3], tnorm, E[9], F[9];
+} pair_geom;
+
+/* R_ij = R_j R_i^T, t_ij = t_j - R_ij t_i, u = t_ij/|t_ij|, E = [u]x R_ij,
+ * F = D_j E D_i (Eq. fastmap-epipolar-objective, focal lengths folded in). */
+static int pair_geometry(const double Ri[9], const double ti[3], double fi, const double Rj[9],
+                         const double tj[3], double fj, pair_geom *g) {
+  mat_mul_bt(Rj, Ri, g->Rij);
+  double Rt[3];
+  mat_vec(g->Rij, ti, Rt);
+  for (int k = 0; k < 3; ++k) g->tij[k] = tj[k] - Rt[k];
+  g->tnorm = sqrt(dot3(g->tij, g->tij));
+  if (!(g->tnorm > 0.0)) return -1;
+  for (int k = 0; k < 3; ++k) g->u[k] = g->tij[k] / g->tnorm;
+  double S[9];
+  skew(g->u, S);
+  mat_mul(S, g->Rij, g->E);
+  double di[3] = {1.0 / fi, 1.0 / fi, 1.0};
+  double dj[3] = {1.0 / fj, 1.0 / fj, 1.0};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) g->F[a * 3 + b] = dj[a] * g->E[a * 3 + b] * di[b];
+  return 0;
+}
+
+int orc_pair_F(const double Ri[9], const double ti[3], double fi, const double Rj[9],
+               const double tj[3], double fj, double F[9]) {
+  pair_geom g;
+  if (pair_geometry(Ri, ti, fi, Rj, tj, fj, &g)) return -1;
+  memcpy(F, g.F, sizeof(g.F));
+  return 0;
+}
+
+/* Residual of one match whose keypoint p1 lies in camera i and p2 in camera
+ * j: eps = p2^T F p1. */
+static double match_residual(const double F[9], double p1x, double p1y, double p2x,
+                             double p2y) {
+  double p1[3] = {p1x, p1y, 1.0}, p2[3] = {p2x, p2y, 1.0}, Fp1[3];
+  mat_vec(F, p1, Fp1);
+  return dot3(p2, Fp1);
+}
+
+/* Canonical orientation of match m: returns camera ids i < j and the centred
+ * keypoints of i (a) and j (b). */
+static void canonical_match(const orc_problem *pb, int64_t m, int32_t *i, int32_t *j,
+                            double *ax, double *ay, double *bx, double *by) {
+  int32_t c1 = pb->cam1[m], c2 = pb->cam2[m];
+  double x1 = (double)pb->x1[m] - pb->cx[c1], y1 = (double)pb->y1[m] - pb->cy[c1];
+  double x2 = (double)pb->x2[m] - pb->cx[c2], y2 = (double)pb->y2[m] - pb->cy[c2];
+  if (c1 < c2) {
+    *i = c1; *j = c2; *ax = x1; *ay = y1; *bx = x2; *by = y2;
+  } else {
+    *i = c2; *j = c1; *ax = x2; *ay = y2; *bx = x1; *by = y1;
+  }
+}
+
+static int check_problem(const orc_problem *pb) {
+  for (int64_t m = 0; m < pb->n_matches; ++m) {
+    int32_t c1 = pb->cam1[m], c2 = pb->cam2[m];
+    if (c1 < 0 || c2 < 0 || c1 >= pb->n_cams || c2 >= pb->n_cams || c1 == c2) return -1;
+  }
+  return 0;
+}
+
+int orc_residuals(const orc_problem *pb, const double *R, const double *t, const double *f,
+                  double *eps) {
+  if (check_problem(pb)) return -1;
+  for (int64_t m = 0; m < pb->n_matches; ++m) {
+    int32_t i, j;
+    double ax, ay, bx, by;
+    canonical_match(pb, m, &i, &j, &ax, &ay, &bx, &by);
+    pair_geom g;
+    if (pair_geometry(R + 9 * i, t + 3 * i, f[i], R + 9 * j, t + 3 * j, f[j], &g)) return -2;
+    eps[m] = match_residual(g.F, ax, ay, bx, by);
+  }
+  return 0;
+}
+
+int64_t orc_update_mask(const orc_problem *pb, const double *Rh, const double *th,
+                        const double *fh, double tau, uint8_t *mask) {
+  double *eps = (double *)malloc(sizeof(double) * (size_t)(pb->n_matches > 0 ? pb->n_matches : 1));
+  if (!eps) return -1;
+  if (orc_residuals(pb, Rh, th, fh, eps)) {
+    free(eps);
+    return -1;
+  }
+  int64_t Z = 0;
+  for (int64_t m = 0; m < pb->n_matches; ++m) {
+    mask[m] = (uint8_t)(mask[m] && fabs(eps[m]) < tau);
+    Z += mask[m];
+  }
+  free(eps);
+  return Z;
+}
+
+/* ---- loss and gradient -------------------------------------------------- */
+
+typedef struct {
+  int64_t n_pairs;
+  int32_t *perm;
+  uint8_t *swapped;
+  int32_t *pair_cams;
+  int64_t *seg_off;
+} seg_result;
+
+static int segment_problem(const orc_problem *pb, seg_result *s) {
+  size_t n = (size_t)(pb->n_matches > 0 ? pb->n_matches : 1);
+  s->perm = (int32_t *)malloc(sizeof(int32_t) * n);
+  s->swapped = (uint8_t *)malloc(n);
+  s->pair_cams = (int32_t *)malloc(sizeof(int32_t) * 2 * n);
+  s->seg_off = (int64_t *)malloc(sizeof(int64_t) * (n + 1));
+  if (!s->perm || !s->swapped || !s->pair_cams || !s->seg_off) return -1;
+  return orc_segment(pb->n_matches, pb->n_cams, pb->cam1, pb->cam2, s->perm, s->swapped,
+                     s->pair_cams, s->seg_off, &s->n_pairs);
+}
+
+static void free_segments(seg_result *s) {
+  free(s->perm);
+  free(s->swapped);
+  free(s->pair_cams);
+  free(s->seg_off);
+}
+
+/* Gradient of the IRLS objective given an existing segmentation.
+ * Per pair n: G_n = sum_m 2 c_m eps_m p2 p1^T (dL/dF), L_n = sum_m c_m eps_m^2;
+ * then the chain rule through F = D_j E D_i, E = [u]x R_ij, u = t_ij/|t_ij|,
+ * t_ij = t_j - R_ij t_i, R_ij = R_j R_i^T to the per-camera R, t and f. */
+static int loss_grad_seg(const orc_problem *pb, const seg_result *s, const double *R,
+                         const double *t, const double *f, const double *Rh,
+                         const double *th, const double *fh, const uint8_t *mask,
+                         double delta, double *loss, double *gR, double *gt, double *gf) {
+  int32_t N = pb->n_cams;
+  memset(gR, 0, sizeof(double) * 9 * (size_t)N);
+  memset(gt, 0, sizeof(double) * 3 * (size_t)N);
+  memset(gf, 0, sizeof(double) * (size_t)N);
+  *loss = 0.0;
+  int64_t Z = 0;
+  for (int64_t m = 0; m < pb->n_matches; ++m) Z += mask[m] ? 1 : 0;
+  if (Z == 0 || s->n_pairs == 0) return 0;
+  int64_t P = s->n_pairs;
+  double *G = (double *)calloc((size_t)P * 9, sizeof(double));
+  double *L = (double *)calloc((size_t)P, sizeof(double));
+  int *bad = (int *)calloc((size_t)P, sizeof(int));
+  if (!G || !L || !bad) {
+    free(G); free(L); free(bad);
+    return -1;
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t n = 0; n < P; ++n) {
+    int32_t i = s->pair_cams[2 * n], j = s->pair_cams[2 * n + 1];
+    pair_geom g, gh;
+    if (pair_geometry(R + 9 * i, t + 3 * i, f[i], R + 9 * j, t + 3 * j, f[j], &g) ||
+        pair_geometry(Rh + 9 * i, th + 3 * i, fh[i], Rh + 9 * j, th + 3 * j, fh[j], &gh)) {
+      bad[n] = 1;
+      continue;
+    }
+    for (int64_t p = s->seg_off[n]; p < s->seg_off[n + 1]; ++p) {
+      int64_t m = s->perm[p];
+      if (!mask[m]) continue;
+      int32_t ci, cj;
+      double ax, ay, bx, by;
+      canonical_match(pb, m, &ci, &cj, &ax, &ay, &bx, &by);
+      double e = match_residual(g.F, ax, ay, bx, by);
+      double eh = match_residual(gh.F, ax, ay, bx, by);
+      double c = 1.0 / ((double)Z * fmax(fabs(eh), delta));
+      double p1[3] = {ax, ay, 1.0}, p2[3] = {bx, by, 1.0};
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) G[9 * n + a * 3 + b] += 2.0 * c * e * p2[a] * p1[b];
+      L[n] += c * e * e;
+    }
+  }
+  for (int64_t n = 0; n < P; ++n)
+    if (bad[n]) {
+      free(G); free(L); free(bad);
+      return -2;
+    }
+  for (int64_t n = 0; n < P; ++n) {
+    int32_t i = s->pair_cams[2 * n], j = s->pair_cams[2 * n + 1];
+    pair_geom g;
+    pair_geometry(R + 9 * i, t + 3 * i, f[i], R + 9 * j, t + 3 * j, f[j], &g);
+    const double *Gn = G + 9 * n;
+    *loss += L[n];
+    /* focal lengths: F_ab = dj_a E_ab di_b, d(1/f)/df = -1/f^2 */
+    double si = 0.0, sj = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 2; ++b) si += Gn[a * 3 + b] * g.F[a * 3 + b];
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 3; ++b) sj += Gn[a * 3 + b] * g.F[a * 3 + b];
+    gf[i] += -si / f[i];
+    gf[j] += -sj / f[j];
+    /* dL/dE = H = D_j G D_i */
+    double H[9];
+    double di[3] = {1.0 / f[i], 1.0 / f[i], 1.0}, dj[3] = {1.0 / f[j], 1.0 / f[j], 1.0};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) H[a * 3 + b] = dj[a] * Gn[a * 3 + b] * di[b];
+    /* E = S R_ij with S = [u]x: dL/dS = H R_ij^T, dL/dR_ij (via E) = S^T H */
+    double M[9];
+    mat_mul_bt(H, g.Rij, M);
+    double gu[3] = {M[7] - M[5], M[2] - M[6], M[3] - M[1]};
+    /* u = t_ij/|t_ij| */
+    double ugu = dot3(g.u, gu), gtij[3];
+    for (int k = 0; k < 3; ++k) gtij[k] = (gu[k] - ugu * g.u[k]) / g.tnorm;
+    /* t_ij = t_j - R_ij t_i */
+    double RtG[3];
+    mat_t_vec(g.Rij, gtij, RtG);
+    for (int k = 0; k < 3; ++k) {
+      gt[3 * j + k] += gtij[k];
+      gt[3 * i + k] -= RtG[k];
+    }
+    double S[9], Q[9];
+    skew(g.u, S);
+    mat_mul_at(S, H, Q); /* S^T H */
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) Q[a * 3 + b] -= gtij[a] * t[3 * i + b];
+    /* R_ij = R_j R_i^T: dL/dR_j = Q R_i, dL/dR_i = Q^T R_j */
+    double gRj[9], gRi[9];
+    mat_mul(Q, R + 9 * i, gRj);
+    mat_mul_at(Q, R + 9 * j, gRi);
+    for (int k = 0; k < 9; ++k) {
+      gR[9 * j + k] += gRj[k];
+      gR[9 * i + k] += gRi[k];
+    }
+  }
+  free(G);
+  free(L);
+  free(bad);
+  return 0;
+}
+
+int orc_loss_grad(const orc_problem *pb, const double *R, const double *t, const double *f,
+                  const double *Rh, const double *th, const double *fh, const uint8_t *mask,
+                  double delta, double *loss, double *gR, double *gt, double *gf) {
+  if (check_problem(pb)) return -1;
+  seg_result s;
+  memset(&s, 0, sizeof(s));
+  if (segment_problem(pb, &s)) {
+    free_segments(&s);
+    return -1;
+  }
+  int rc = loss_grad_seg(pb, &s, R, t, f, Rh, th, fh, mask, delta, loss, gR, gt, gf);
+  free_segments(&s);
+  return rc;
+}
+
+/* ---- optimiser ---------------------------------------------------------- */
+
+void orc_adam(int64_t n, double *p, double *m, double *v, const double *g, int64_t step,
+              double lr, double beta1, double beta2, double eps) {
+  double bc1 = 1.0 - pow(beta1, (double)step);
+  double bc2 = 1.0 - pow(beta2, (double)step);
+  for (int64_t k = 0; k < n; ++k) {
+    m[k] = beta1 * m[k] + (1.0 - beta1) * g[k];
+    v[k] = beta2 * v[k] + (1.0 - beta2) * g[k] * g[k];
+    double mh = m[k] / bc1, vh = v[k] / bc2;
+    p[k] -= lr * mh / (sqrt(vh) + eps);
+  }
+}
+
+static double median_of(const double *x, int64_t n);
+
+void orc_gauge_normalize(int32_t n, const double *R, double *t, int64_t n_pairs,
+                         const int32_t *pair_cams, double *center, double *scale) {
+  double *o = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+  double mean[3] = {0.0, 0.0, 0.0};
+  for (int32_t c = 0; c < n; ++c) {
+    mat_t_vec(R + 9 * c, t + 3 * c, o + 3 * c);
+    for (int k = 0; k < 3; ++k) {
+      o[3 * c + k] = -o[3 * c + k];
+      mean[k] += o[3 * c + k] / n;
+    }
+  }
+  /* scale: median distance between the centres of the matched pairs */
+  double s = 0.0;
+  if (n_pairs > 0) {
+    double *base = (double *)malloc(sizeof(double) * (size_t)n_pairs);
+    for (int64_t k = 0; k < n_pairs; ++k) {
+      const double *oi = o + 3 * pair_cams[2 * k], *oj = o + 3 * pair_cams[2 * k + 1];
+      double d[3] = {oj[0] - oi[0], oj[1] - oi[1], oj[2] - oi[2]};
+      base[k] = sqrt(dot3(d, d));
+    }
+    s = median_of(base, n_pairs);
+    free(base);
+  }
+  if (!(s > 0.0)) s = 1.0;
+  for (int32_t c = 0; c < n; ++c) {
+    double on[3];
+    for (int k = 0; k < 3; ++k) on[k] = (o[3 * c + k] - mean[k]) / s;
+    mat_vec(R + 9 * c, on, t + 3 * c);
+    for (int k = 0; k < 3; ++k) t[3 * c + k] = -t[3 * c + k];
+  }
+  for (int k = 0; k < 3; ++k) center[k] = mean[k];
+  *scale = s;
+  free(o);
+}
+
+static int dbl_cmp(const void *a, const void *b) {
+  double x = *(const double *)a, y = *(const double *)b;
+  return (x > y) - (x < y);
+}
+
+static double median_of(const double *x, int64_t n) {
+  double *y = (double *)malloc(sizeof(double) * (size_t)n);
+  memcpy(y, x, sizeof(double) * (size_t)n);
+  qsort(y, (size_t)n, sizeof(double), dbl_cmp);
+  {
+  }
+  double med = (n % 2) ? y[n / 2] : 0.5 * (y[n / 2 - 1] + y[n / 2]);
+  free(y);
+  return med;
+}
+
+int orc_epipolar_adjust(const orc_problem *pb, const orc_options *opt, const double *R0,
+                        const double *t0, const double *f0, const int32_t *intr_group,
+                        double *R, double *t, double *f, double *loss_per_round,
+                        int64_t *inliers, int32_t log_every, int32_t max_log, double *log_R,
+                        int32_t *n_logged, uint8_t *mask_out) {
+  if (check_problem(pb)) return -1;
+  int32_t N = pb->n_cams;
+  int64_t M = pb->n_matches;
+  for (int32_t c = 0; c < N; ++c)
+    if (!(f0[c] > 0.0)) return -1;
+  int32_t G = 0;
+  for (int32_t c = 0; c < N; ++c) {
+    int32_t g = intr_group ? intr_group[c] : c;
+    if (g < 0 || g >= N) return -1;
+    if (g + 1 > G) G = g + 1;
+  }
+  seg_result s;
+  memset(&s, 0, sizeof(s));
+  if (segment_problem(pb, &s)) {
+    free_segments(&s);
+    return -1;
+  }
+  double *a6 = (double *)malloc(sizeof(double) * 6 * (size_t)N);
+  double *logf = (double *)calloc((size_t)G, sizeof(double));
+  int32_t *gcount = (int32_t *)calloc((size_t)G, sizeof(int32_t));
+  double *Rh = (double *)malloc(sizeof(double) * 9 * (size_t)N);
+  double *thh = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+  double *fh = (double *)malloc(sizeof(double) * (size_t)N);
+  double *gR = (double *)malloc(sizeof(double) * 9 * (size_t)N);
+  double *gt = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+  double *gf = (double *)malloc(sizeof(double) * (size_t)N);
+  double *ga6 = (double *)malloc(sizeof(double) * 6 * (size_t)N);
+  double *glogf = (double *)malloc(sizeof(double) * (size_t)G);
+  double *m_a6 = (double *)malloc(sizeof(double) * 6 * (size_t)N);
+  double *v_a6 = (double *)malloc(sizeof(double) * 6 * (size_t)N);
+  double *m_t = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+  double *v_t = (double *)malloc(sizeof(double) * 3 * (size_t)N);
+  double *m_f = (double *)malloc(sizeof(double) * (size_t)G);
+  double *v_f = (double *)malloc(sizeof(double) * (size_t)G);
+  uint8_t *mask = (uint8_t *)malloc((size_t)(M > 0 ? M : 1));
+  double *eps = (double *)malloc(sizeof(double) * (size_t)(M > 0 ? M : 1));
+  int rc = 0;
+
+  /* parameters: 6D rotation, translation, log focal per group */
+  memcpy(t, t0, sizeof(double) * 3 * (size_t)N);
+  for (int32_t c = 0; c < N; ++c) {
+    orc_R_to_rot6d(R0 + 9 * c, a6 + 6 * c);
+    orc_rot6d_to_R(a6 + 6 * c, R + 9 * c);
+    int32_t g = intr_group ? intr_group[c] : c;
+    logf[g] += log(f0[c]);
+    gcount[g] += 1;
+  }
+  for (int32_t g = 0; g < G; ++g)
+    if (gcount[g] > 0) logf[g] /= gcount[g];
+  for (int32_t c = 0; c < N; ++c) f[c] = exp(logf[intr_group ? intr_group[c] : c]);
+  double g_center[3] = {0.0, 0.0, 0.0}, g_scale = 1.0;
+  if (opt->gauge_normalize)
+    orc_gauge_normalize(N, R, t, s.n_pairs, s.pair_cams, g_center, &g_scale);
+  for (int64_t m = 0; m < M; ++m) mask[m] = 1;
+  int32_t nlog = 0;
+  int64_t it_global = 0;
+
+  for (int32_t r = 0; r < opt->rounds && rc == 0; ++r) {
+    /* snapshot and filter (Method > Epipolar Adjustment, re-weighting rounds) */
+    memcpy(Rh, R, sizeof(double) * 9 * (size_t)N);
+    memcpy(thh, t, sizeof(double) * 3 * (size_t)N);
+    memcpy(fh, f, sizeof(double) * (size_t)N);
+    double tau_px = opt->tau_px_init * pow(opt->tau_decay, (double)r);
+    if (tau_px < opt->tau_px_min) tau_px = opt->tau_px_min;
+    double tau = tau_px / median_of(fh, N);
+    if (orc_residuals(pb, Rh, thh, fh, eps)) {
+      rc = -2;
+      break;
+    }
+    int64_t Z = 0;
+    for (int64_t m = 0; m < M; ++m) {
+      mask[m] = (uint8_t)(mask[m] && fabs(eps[m]) < tau);
+      Z += mask[m];
+    }
+    inliers[r] = Z;
+    memset(m_a6, 0, sizeof(double) * 6 * (size_t)N);
+    memset(v_a6, 0, sizeof(double) * 6 * (size_t)N);
+    memset(m_t, 0, sizeof(double) * 3 * (size_t)N);
+    memset(v_t, 0, sizeof(double) * 3 * (size_t)N);
+    memset(m_f, 0, sizeof(double) * (size_t)G);
+    memset(v_f, 0, sizeof(double) * (size_t)G);
+    double loss = 0.0;
+    for (int32_t k = 0; k < opt->iters_per_round; ++k) {
+      rc = loss_grad_seg(pb, &s, R, t, f, Rh, thh, fh, mask, opt->delta, &loss, gR, gt, gf);
+      if (rc) break;
+      for (int32_t c = 0; c < N; ++c) orc_rot6d_backward(a6 + 6 * c, gR + 9 * c, ga6 + 6 * c);
+      memset(glogf, 0, sizeof(double) * (size_t)G);
+      for (int32_t c = 0; c < N; ++c) glogf[intr_group ? intr_group[c] : c] += gf[c] * f[c];
+      int64_t step = k + 1;
+      orc_adam(6 * (int64_t)N, a6, m_a6, v_a6, ga6, step, opt->lr_rot, opt->beta1, opt->beta2,
+               opt->adam_eps);
+      orc_adam(3 * (int64_t)N, t, m_t, v_t, gt, step, opt->lr_t, opt->beta1, opt->beta2,
+               opt->adam_eps);
+      if (opt->optimize_focal)
+        orc_adam(G, logf, m_f, v_f, glogf, step, opt->lr_logf, opt->beta1, opt->beta2,
+                 opt->adam_eps);
+      for (int32_t c = 0; c < N; ++c) {
+        orc_rot6d_to_R(a6 + 6 * c, R + 9 * c);
+        f[c] = exp(logf[intr_group ? intr_group[c] : c]);
+      }
+      ++it_global;
+      if (log_R && log_every > 0 && (it_global % log_every) == 0 && nlog < max_log) {
+        memcpy(log_R + (size_t)nlog * 9 * N, R, sizeof(double) * 9 * (size_t)N);
+        ++nlog;
+      }
+    }
+    loss_per_round[r] = loss;
+  }
+  if (n_logged) *n_logged = nlog;
+  if (mask_out) memcpy(mask_out, mask, (size_t)M);
+  /* back to the caller's frame: centre o = scale * o' + center */
+  if (opt->gauge_normalize) {
+    for (int32_t c = 0; c < N; ++c) {
+      double o[3], on[3];
+      mat_t_vec(R + 9 * c, t + 3 * c, o);
+      for (int k = 0; k < 3; ++k) on[k] = -o[k] * g_scale + g_center[k];
+      mat_vec(R + 9 * c, on, t + 3 * c);
+      for (int k = 0; k < 3; ++k) t[3 * c + k] = -t[3 * c + k];
+    }
+  }
+  free(a6); free(logf); free(gcount); free(Rh); free(thh); free(fh); free(gR); free(gt);
+  free(gf); free(ga6); free(glogf); free(m_a6); free(v_a6); free(m_t); free(v_t);
+  free(m_f); free(v_f); free(mask); free(eps);
+  free_segments(&s);
+  return rc;
+}

@@ -1,0 +1,385 @@
+"""Seeded synthetic scenes shaped like the FastMap epipolar-adjustment workloads.
+
+This module only builds inputs: cameras, 3D points, their noisy projections,
+matches between image pairs, outliers and a perturbed starting pose.  It holds
+none of the epipolar-adjustment arithmetic (no essential matrix, residual,
+weight or gradient); both the HIP library's tests/benchmarks and the FP64
+oracle draw their inputs from here.
+
+Camera model (FastMap, Method > Intrinsics Estimation): pinhole, principal
+point fixed at the image centre (continuous convention: pixel (0,0) is the
+image corner, so the centre of a W x H image is (W/2, H/2)), one focal length
+per camera.  Poses are world-to-camera: X_cam = R X + t, camera centre
+o = -R^T t.
+
+Randomness that must be identical no matter how the scene is traversed (which
+camera sees which point, the pixel noise of one observation, outlier draws)
+comes from a counter-based hash of (seed, stream, a, b); the bulk layout
+(camera placement, point cloud, match shuffle) comes from numpy's PCG64.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def _splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser (Steele, Lea & Flood 2014), vectorised over uint64."""
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def hash_u01(seed: int, stream: int, a, b) -> np.ndarray:
+    """Uniform [0,1) doubles from a counter hash of (seed, stream, a, b)."""
+    a = np.asarray(a, dtype=np.uint64)
+    b = np.asarray(b, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        k = _splitmix64(np.uint64(seed) * np.uint64(0x100000001B3) + np.uint64(stream))
+        h = _splitmix64(k ^ _splitmix64(a * np.uint64(0x9E3779B1) + np.uint64(0x632BE5AB)))
+        h = _splitmix64(h ^ b)
+    return (h >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def hash_normal(seed: int, stream: int, a, b) -> np.ndarray:
+    """Standard normals by Box-Muller from two hashed uniforms."""
+    u1 = hash_u01(seed, 2 * stream, a, b)
+    u2 = hash_u01(seed, 2 * stream + 1, a, b)
+    return np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def rotation_from_axis_angle(axis: np.ndarray, angle: np.ndarray) -> np.ndarray:
+    """Rodrigues' formula, batched: axis [...,3] (unit), angle [...] radians."""
+    axis = np.asarray(axis, dtype=np.float64)
+    angle = np.asarray(angle, dtype=np.float64)
+    k = axis / np.linalg.norm(axis, axis=-1, keepdims=True)
+    K = np.zeros(k.shape[:-1] + (3, 3))
+    K[..., 0, 1], K[..., 0, 2] = -k[..., 2], k[..., 1]
+    K[..., 1, 0], K[..., 1, 2] = k[..., 2], -k[..., 0]
+    K[..., 2, 0], K[..., 2, 1] = -k[..., 1], k[..., 0]
+    s = np.sin(angle)[..., None, None]
+    c = np.cos(angle)[..., None, None]
+    eye = np.broadcast_to(np.eye(3), K.shape)
+    return eye + s * K + (1.0 - c) * (K @ K)
+
+
+def look_at(center: np.ndarray, target: np.ndarray) -> np.ndarray:
+    """World-to-camera rotations whose +z axis points from center to target.
+
+    Rows of R are the camera x, y, z axes in world coordinates; the world up
+    vector is +z unless the viewing direction is nearly vertical.
+    """
+    center = np.atleast_2d(center)
+    z = target - center
+    z /= np.linalg.norm(z, axis=1, keepdims=True)
+    up = np.tile(np.array([0.0, 0.0, 1.0]), (len(z), 1))
+    vertical = np.abs(z @ np.array([0.0, 0.0, 1.0])) > 0.95
+    up[vertical] = np.array([0.0, 1.0, 0.0])
+    x = np.cross(up, z)
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    y = np.cross(z, x)
+    return np.stack([x, y, z], axis=1)
+
+
+@dataclass
+class Scene:
+    """One synthetic epipolar-adjustment problem (all arrays host numpy)."""
+
+    name: str
+    seed: int
+    width: np.ndarray  # float64 [N]
+    height: np.ndarray  # float64 [N]
+    f_gt: np.ndarray  # float64 [N]
+    f_init: np.ndarray  # float64 [N]
+    intr_group: np.ndarray  # int32 [N]
+    R_gt: np.ndarray  # float64 [N,3,3] world-to-camera
+    t_gt: np.ndarray  # float64 [N,3]
+    R_init: np.ndarray
+    t_init: np.ndarray
+    x1: np.ndarray  # float32 [M] pixel coordinates in camera cam1
+    y1: np.ndarray
+    x2: np.ndarray  # float32 [M] pixel coordinates in camera cam2
+    y2: np.ndarray
+    cam1: np.ndarray  # int32 [M]
+    cam2: np.ndarray  # int32 [M]
+    inlier: np.ndarray  # bool [M]
+    radius: float = 1.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_cams(self) -> int:
+        return int(self.f_gt.shape[0])
+
+    @property
+    def n_matches(self) -> int:
+        return int(self.x1.shape[0])
+
+    @property
+    def cx(self) -> np.ndarray:
+        return self.width / 2.0
+
+    @property
+    def cy(self) -> np.ndarray:
+        return self.height / 2.0
+
+    def pairs(self) -> np.ndarray:
+        """Distinct unordered camera pairs (i<j) present in the matches."""
+        i = np.minimum(self.cam1, self.cam2).astype(np.int64)
+        j = np.maximum(self.cam1, self.cam2).astype(np.int64)
+        key = np.unique(i * self.n_cams + j)
+        return np.stack([key // self.n_cams, key % self.n_cams], axis=1)
+
+
+def _observe(R, t, f, cx, cy, X):
+    """Noise-free pinhole projection of X [K,3] into one camera."""
+    Xc = X @ R.T + t
+    z = Xc[:, 2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = f * Xc[:, 0] / z + cx
+        v = f * Xc[:, 1] / z + cy
+    return u, v, z
+
+
+def _visible(u, v, z, width, height):
+    return (z > 1e-3) & (u >= 0.0) & (u < width) & (v >= 0.0) & (v < height)
+
+
+def _perturb_init(rng, R_gt, t_gt, rot_sigma_deg, rot_min_deg, center_frac, pairs):
+    """Starting poses standing in for the output of global rotation and
+    translation alignment: GT rotation times a random-axis rotation of angle
+    |N(0, rot_sigma)| + rot_min; camera centres plus isotropic Gaussian noise
+    whose sigma is `center_frac` times the median baseline of the matched
+    pairs (so relative translation directions start a few degrees off)."""
+    n = len(R_gt)
+    axis = rng.normal(size=(n, 3))
+    ang = np.deg2rad(np.abs(rng.normal(0.0, rot_sigma_deg, size=n)) + rot_min_deg)
+    R_init = rotation_from_axis_angle(axis, ang) @ R_gt
+    centers = -np.einsum("nji,nj->ni", R_gt, t_gt)
+    pairs = np.asarray(pairs).reshape(-1, 2)
+    base = np.median(np.linalg.norm(centers[pairs[:, 0]] - centers[pairs[:, 1]], axis=1))
+    centers_init = centers + rng.normal(0.0, center_frac * base, size=centers.shape)
+    t_init = -np.einsum("nij,nj->ni", R_init, centers_init)
+    return R_init, t_init
+
+
+def _emit_matches(seed, pair_list, det_ids, det_u, det_v, n_cams, width, height,
+                  outlier_frac, rng):
+    """Matches for every pair: the points detected by both cameras.
+
+    det_ids[c] is the sorted array of point ids detected by camera c and
+    det_u/det_v their noisy pixel coordinates.  An outlier keeps the first
+    keypoint and moves the second one to a uniformly random pixel of the
+    second image.  Each match is then emitted in a random orientation and the
+    whole list is shuffled, so callers must canonicalise and sort.
+    """
+    chunks = {k: [] for k in ("x1", "y1", "x2", "y2", "c1", "c2", "inl")}
+    for (i, j) in pair_list:
+        ids_i, ids_j = det_ids[i], det_ids[j]
+        if len(ids_i) == 0 or len(ids_j) == 0:
+            continue
+        pos = np.searchsorted(ids_j, ids_i)
+        pos = np.minimum(pos, len(ids_j) - 1)
+        hit = ids_j[pos] == ids_i
+        if not hit.any():
+            continue
+        ii = np.flatnonzero(hit)
+        jj = pos[hit]
+        pts = ids_i[ii]
+        x1 = det_u[i][ii]
+        y1 = det_v[i][ii]
+        x2 = det_u[j][jj].copy()
+        y2 = det_v[j][jj].copy()
+        key = np.uint64(i) * np.uint64(n_cams) + np.uint64(j)
+        out = hash_u01(seed, 40, key, pts) < outlier_frac
+        if out.any():
+            x2[out] = hash_u01(seed, 41, key, pts[out]) * width[j]
+            y2[out] = hash_u01(seed, 42, key, pts[out]) * height[j]
+        flip = hash_u01(seed, 43, key, pts) < 0.5
+        c1 = np.full(len(pts), i, np.int32)
+        c2 = np.full(len(pts), j, np.int32)
+        a_x, a_y, b_x, b_y = x1.copy(), y1.copy(), x2.copy(), y2.copy()
+        a_x[flip], b_x[flip] = x2[flip], x1[flip]
+        a_y[flip], b_y[flip] = y2[flip], y1[flip]
+        c1[flip], c2[flip] = j, i
+        chunks["x1"].append(a_x)
+        chunks["y1"].append(a_y)
+        chunks["x2"].append(b_x)
+        chunks["y2"].append(b_y)
+        chunks["c1"].append(c1)
+        chunks["c2"].append(c2)
+        chunks["inl"].append(~out)
+    if not chunks["x1"]:
+        e = np.zeros(0, np.float32)
+        ei = np.zeros(0, np.int32)
+        return e, e, e, e, ei, ei, np.zeros(0, bool)
+    cat = {k: np.concatenate(v) for k, v in chunks.items()}
+    perm = rng.permutation(len(cat["x1"]))
+    return (cat["x1"][perm].astype(np.float32), cat["y1"][perm].astype(np.float32),
+            cat["x2"][perm].astype(np.float32), cat["y2"][perm].astype(np.float32),
+            cat["c1"][perm], cat["c2"][perm], cat["inl"][perm])
+
+
+def _detect(seed, R, t, f, cx, cy, width, height, X, p_det, sigma):
+    """Per camera: sorted detected point ids and their noisy pixels."""
+    n = len(R)
+    ids_all = np.arange(len(X), dtype=np.int64)
+    det_ids, det_u, det_v = [], [], []
+    for c in range(n):
+        u, v, z = _observe(R[c], t[c], f[c], cx[c], cy[c], X)
+        vis = _visible(u, v, z, width[c], height[c])
+        ids = ids_all[vis]
+        if p_det < 1.0:
+            keep = hash_u01(seed, 10, c, ids) < p_det
+            ids = ids[keep]
+        uu = u[ids]
+        vv = v[ids]
+        if sigma > 0:
+            uu = uu + sigma * hash_normal(seed, 11, c, ids)
+            vv = vv + sigma * hash_normal(seed, 12, c, ids)
+        det_ids.append(ids)
+        det_u.append(uu)
+        det_v.append(vv)
+    return det_ids, det_u, det_v
+
+
+def sphere_scene(n_cams=20, n_pts=2000, radius=4.0, focal=500.0, width=640.0,
+                 height=480.0, p_det=0.4, sigma=0.5, outlier_frac=0.1, seed=1,
+                 extent=1.0, rot_sigma_deg=3.0, rot_min_deg=2.0, center_frac=0.05,
+                 name="sphere") -> Scene:
+    """Cameras at seeded uniform directions on a sphere, looking at the origin,
+    points uniform in a cube of side `extent`, all camera pairs matched."""
+    rng = np.random.default_rng(seed)
+    dirs = rng.normal(size=(n_cams, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    centers = radius * dirs
+    R = look_at(centers, np.zeros(3))
+    t = -np.einsum("nij,nj->ni", R, centers)
+    X = rng.uniform(-extent / 2, extent / 2, size=(n_pts, 3))
+    f = np.broadcast_to(np.asarray(focal, dtype=np.float64), (n_cams,)).copy()
+    W = np.full(n_cams, float(width))
+    H = np.full(n_cams, float(height))
+    det = _detect(seed, R, t, f, W / 2, H / 2, W, H, X, p_det, sigma)
+    pair_list = [(i, j) for i in range(n_cams) for j in range(i + 1, n_cams)]
+    x1, y1, x2, y2, c1, c2, inl = _emit_matches(seed, pair_list, *det, n_cams, W, H,
+                                                outlier_frac, rng)
+    R0, t0 = _perturb_init(rng, R, t, rot_sigma_deg, rot_min_deg, center_frac,
+                           pair_list)
+    return Scene(name=name, seed=seed, width=W, height=H, f_gt=f, f_init=f.copy(),
+                 intr_group=np.arange(n_cams, dtype=np.int32), R_gt=R, t_gt=t,
+                 R_init=R0, t_init=t0, x1=x1, y1=y1, x2=x2, y2=y2, cam1=c1, cam2=c2,
+                 inlier=inl, radius=radius,
+                 meta=dict(n_pts=n_pts, p_det=p_det, sigma=sigma, outlier_frac=outlier_frac))
+
+
+def _knn_pairs(centers: np.ndarray, k: int) -> np.ndarray:
+    n = len(centers)
+    k = min(k, n - 1)
+    pairs = set()
+    for s in range(0, n, 512):
+        d = np.linalg.norm(centers[s:s + 512, None, :] - centers[None, :, :], axis=2)
+        d[np.arange(len(d)), np.arange(s, s + len(d))] = np.inf
+        nn = np.argpartition(d, k - 1, axis=1)[:, :k]
+        for r, row in enumerate(nn):
+            i = s + r
+            for j in row:
+                pairs.add((min(i, int(j)), max(i, int(j))))
+    return np.array(sorted(pairs), dtype=np.int64).reshape(-1, 2)
+
+
+def trajectory_scene(n_cams=500, n_pts=200_000, radius=6.0, height_wave=1.0,
+                     center_noise=0.1, jitter_deg=5.0, box=(4.0, 4.0, 2.0), knn=20,
+                     target_matches=20_000_000, sigma=1.0, outlier_frac=0.2,
+                     f_range=(400.0, 1200.0), f_init_spread=0.1, width=640.0,
+                     height=480.0, seed=2, rot_sigma_deg=3.0, rot_min_deg=2.0,
+                     center_frac=0.05, calib_sample=50_000, name="trajectory") -> Scene:
+    """Cameras on a noisy closed loop around a box of points, each matched to
+    its `knn` nearest neighbours by centre; the detection probability is set
+    so that the expected match count is `target_matches`."""
+    rng = np.random.default_rng(seed)
+    th = 2.0 * np.pi * np.arange(n_cams) / n_cams
+    centers = np.stack([radius * np.cos(th), radius * np.sin(th),
+                        height_wave * np.sin(3.0 * th)], axis=1)
+    centers += rng.normal(0.0, center_noise, size=centers.shape)
+    R = look_at(centers, np.zeros(3))
+    jitter = rotation_from_axis_angle(rng.normal(size=(n_cams, 3)),
+                                      np.deg2rad(rng.normal(0.0, jitter_deg, size=n_cams)))
+    R = jitter @ R
+    t = -np.einsum("nij,nj->ni", R, centers)
+    X = rng.uniform(-0.5, 0.5, size=(n_pts, 3)) * np.asarray(box)
+    f = rng.uniform(f_range[0], f_range[1], size=n_cams)
+    f_init = f * np.exp(rng.uniform(-f_init_spread, f_init_spread, size=n_cams))
+    W = np.full(n_cams, float(width))
+    H = np.full(n_cams, float(height))
+    pair_arr = _knn_pairs(centers, knn)
+    # Calibrate the detection probability on a point sample: the expected
+    # number of matches is p^2 * sum over pairs of co-visible points.
+    samp = rng.choice(n_pts, size=min(calib_sample, n_pts), replace=False)
+    vis = np.zeros((n_cams, len(samp)), dtype=bool)
+    for c in range(n_cams):
+        u, v, z = _observe(R[c], t[c], f[c], W[c] / 2, H[c] / 2, X[samp])
+        vis[c] = _visible(u, v, z, W[c], H[c])
+    packed = np.packbits(vis, axis=1)
+    covis = 0
+    for s in range(0, len(pair_arr), 4096):
+        pa = pair_arr[s:s + 4096]
+        covis += int(np.bitwise_count(packed[pa[:, 0]] & packed[pa[:, 1]]).sum())
+    covis *= n_pts / len(samp)
+    p_det = float(min(1.0, np.sqrt(target_matches / max(covis, 1.0))))
+    det = _detect(seed, R, t, f, W / 2, H / 2, W, H, X, p_det, sigma)
+    x1, y1, x2, y2, c1, c2, inl = _emit_matches(seed, [tuple(p) for p in pair_arr], *det,
+                                                n_cams, W, H, outlier_frac, rng)
+    R0, t0 = _perturb_init(rng, R, t, rot_sigma_deg, rot_min_deg, center_frac, pair_arr)
+    return Scene(name=name, seed=seed, width=W, height=H, f_gt=f, f_init=f_init,
+                 intr_group=np.arange(n_cams, dtype=np.int32), R_gt=R, t_gt=t,
+                 R_init=R0, t_init=t0, x1=x1, y1=y1, x2=x2, y2=y2, cam1=c1, cam2=c2,
+                 inlier=inl, radius=radius,
+                 meta=dict(n_pts=n_pts, p_det=p_det, sigma=sigma,
+                           outlier_frac=outlier_frac, n_pairs=len(pair_arr), knn=knn))
+
+
+# Workload presets.  Sizes follow the FastMap scene scales (hundreds to a few
+# thousand images, 5k-500k image pairs in the kernel-fusion ablation).
+def config1(seed: int = 1) -> Scene:
+    """20 cameras on a radius-4 sphere, 2,000 points in the unit cube, f=500,
+    640x480, all 190 pairs, detection 0.4 (~60.8k matches), sigma 0.5 px,
+    10% outliers."""
+    return sphere_scene(seed=seed, name="sphere20_m60k")
+
+
+def config2(seed: int = 2, target_matches: int = 20_000_000) -> Scene:
+    """500 cameras on a noisy loop, 200k points, 20 nearest neighbours,
+    ~20M matches, sigma 1 px, 20% outliers, f in [400,1200] px."""
+    return trajectory_scene(seed=seed, target_matches=target_matches,
+                            name="traj500_m20M")
+
+
+def config3(seed: int = 3, target_matches: int = 100_000_000) -> Scene:
+    """3,000 cameras, 1M points, 30 nearest neighbours, ~100M matches,
+    sigma 1 px, 25% outliers."""
+    return trajectory_scene(n_cams=3000, n_pts=1_000_000, knn=30,
+                            target_matches=target_matches, outlier_frac=0.25,
+                            seed=seed, name="traj3000_m100M")
+
+
+def tiny_scene(n_cams=4, n_pts=40, seed=7, sigma=0.0, outlier_frac=0.0,
+               p_det=1.0, focal=500.0, distinct_focals=True) -> Scene:
+    """Small sphere scene for brute-force checks; optional distinct focals."""
+    if distinct_focals:
+        focal = np.random.default_rng(seed + 1000).uniform(0.8 * focal, 1.2 * focal,
+                                                           size=n_cams)
+    return sphere_scene(n_cams=n_cams, n_pts=n_pts, p_det=p_det, sigma=sigma,
+                        outlier_frac=outlier_frac, seed=seed, focal=focal, name="tiny")
+
+
+def random_poses(rng, n_cams, radius=4.0):
+    """Random (not necessarily realistic) poses for gradient checks."""
+    R = rotation_from_axis_angle(rng.normal(size=(n_cams, 3)),
+                                 rng.uniform(0, np.pi, size=n_cams))
+    centers = rng.normal(size=(n_cams, 3)) * radius
+    t = -np.einsum("nij,nj->ni", R, centers)
+    return R, t

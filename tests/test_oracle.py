@@ -1,0 +1,410 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by geometry.
+
+None of these checks re-derive the oracle's formulas: each one compares it
+with something independent -- a textbook closed form, a brute-force
+computation, a mathematical invariant of the epipolar objective, the
+quadratic-form rewriting the paper gives, or finite differences -- chosen so
+that a dropped term, a wrong sign or index or a transposed operand in the
+oracle fails at least one of them.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2605_18052_amd import metrics, synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rot(rng, n):
+    return synth.rotation_from_axis_angle(rng.normal(size=(n, 3)), rng.uniform(0.1, 3.0, size=n))
+
+
+def _problem(orc, sc, sel=None):
+    return orc.OracleProblem.from_scene(sc, sel)
+
+
+# ---------------------------------------------------------------- segmenting
+
+def _brute_segment(cam1, cam2):
+    items = sorted(((min(a, b), max(a, b)), m) for m, (a, b) in enumerate(zip(cam1, cam2)))
+    perm = np.array([m for _, m in items], np.int64)
+    swapped = np.array([cam1[m] > cam2[m] for m in perm], bool)
+    keys = [k for k, _ in items]
+    pairs, off = [], []
+    for p, k in enumerate(keys):
+        if p == 0 or k != keys[p - 1]:
+            pairs.append(k)
+            off.append(p)
+    off.append(len(keys))
+    return perm, swapped, np.array(pairs).reshape(-1, 2), np.array(off)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_segment_matches_brute_force(orc, seed):
+    rng = np.random.default_rng(seed)
+    n_cams = 9
+    sizes = [1, 63, 64, 65, 300, 2, 1000]
+    cam1, cam2 = [], []
+    allpairs = [(i, j) for i in range(n_cams) for j in range(i + 1, n_cams)]
+    chosen = rng.choice(len(allpairs), size=len(sizes), replace=False)
+    for s, k in zip(sizes, chosen):
+        i, j = allpairs[k]
+        flip = rng.random(s) < 0.5
+        cam1 += list(np.where(flip, j, i))
+        cam2 += list(np.where(flip, i, j))
+    order = rng.permutation(len(cam1))
+    cam1 = np.array(cam1)[order].astype(np.int32)
+    cam2 = np.array(cam2)[order].astype(np.int32)
+    perm, sw, pc, off = orc.segment(cam1, cam2, n_cams)
+    bp, bs, bpc, boff = _brute_segment(list(cam1), list(cam2))
+    assert np.array_equal(perm, bp)
+    assert np.array_equal(sw, bs)
+    assert np.array_equal(pc, bpc)
+    assert np.array_equal(off, boff)
+    assert sorted(np.diff(off).tolist()) == sorted(sizes)
+
+
+def test_segment_empty_and_rejects(orc):
+    perm, sw, pc, off = orc.segment(np.zeros(0, np.int32), np.zeros(0, np.int32), 3)
+    assert len(perm) == 0 and len(pc) == 0 and off.tolist() == [0]
+    with pytest.raises(ValueError):
+        orc.segment(np.array([1], np.int32), np.array([1], np.int32), 3)
+    with pytest.raises(ValueError):
+        orc.segment(np.array([0], np.int32), np.array([3], np.int32), 3)
+    with pytest.raises(ValueError):
+        orc.segment(np.array([-1], np.int32), np.array([0], np.int32), 3)
+
+
+# ------------------------------------------------------------------ residual
+
+def test_stereo_golden(orc):
+    """Rectified stereo: the residual is the vertical disparity / f."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "stereo_vertical_disparity.txt"))
+    n = len(rows)
+    R = np.stack([np.eye(3), np.eye(3)])
+    t = np.array([[0.0, 0.0, 0.0], [-1.5, 0.0, 0.0]])
+    f = np.array([500.0, 500.0])
+    for swap in (False, True):
+        c1 = np.zeros(n, np.int32)
+        c2 = np.ones(n, np.int32)
+        x1, y1, x2, y2 = rows[:, 0], rows[:, 1], rows[:, 2], rows[:, 3]
+        if swap:  # the same matches written from camera 1's side
+            c1, c2, x1, y1, x2, y2 = c2, c1, x2, y2, x1, y1
+        pb = orc.OracleProblem(x1, y1, x2, y2, c1, c2, [320.0, 320.0], [240.0, 240.0])
+        eps = orc.residuals(pb, R, t, f)
+        np.testing.assert_allclose(eps, rows[:, 4], rtol=0, atol=1e-15)
+
+
+def test_zero_residual_at_ground_truth(orc):
+    """Noiseless, outlier-free scenes satisfy the epipolar constraint exactly."""
+    for sc in (synth.tiny_scene(n_cams=5, n_pts=60, seed=3),
+               synth.sphere_scene(n_cams=20, n_pts=2000, sigma=0.0, outlier_frac=0.0, seed=1)):
+        pb = _problem(orc, sc)
+        eps = orc.residuals(pb, sc.R_gt, sc.t_gt, sc.f_gt)
+        # float32 keypoints carry up to 2^-24 * 640 ~ 4e-5 px of rounding,
+        # i.e. ~1e-7 in normalised units at f ~ 400; any pose error gives
+        # residuals of order 1e-3.
+        assert np.abs(eps).max() < 5e-7
+        # and the residual is not identically zero away from ground truth
+        eps0 = orc.residuals(pb, sc.R_init, sc.t_init, sc.f_gt)
+        assert np.abs(eps0).max() > 1e-3
+
+
+def test_zero_residual_exact_points(orc):
+    """With keypoints that are exact float32 projections, |eps| <= 1e-12."""
+    rng = np.random.default_rng(5)
+    n_cams = 4
+    R = _rot(rng, n_cams)
+    centers = rng.normal(size=(n_cams, 3)) * 3 + np.array([0, 0, -8.0])
+    t = -np.einsum("nij,nj->ni", R, centers)
+    f = rng.uniform(300, 900, n_cams)
+    cx = rng.uniform(200, 400, n_cams)
+    cy = rng.uniform(150, 300, n_cams)
+    rows = []
+    for _ in range(200):
+        i, j = rng.choice(n_cams, 2, replace=False)
+        # choose pixel in camera i exactly representable, back-project to a
+        # depth, then the point's projection in camera j is computed in fp64
+        # and rounded; the residual is then checked with the roundoff budget.
+        X = rng.normal(size=3)
+        ui = R[i] @ X + t[i]
+        uj = R[j] @ X + t[j]
+        rows.append((i, j, f[i] * ui[0] / ui[2] + cx[i], f[i] * ui[1] / ui[2] + cy[i],
+                     f[j] * uj[0] / uj[2] + cx[j], f[j] * uj[1] / uj[2] + cy[j]))
+    rows = np.array(rows)
+    pb = orc.OracleProblem(rows[:, 2], rows[:, 3], rows[:, 4], rows[:, 5],
+                           rows[:, 0].astype(np.int32), rows[:, 1].astype(np.int32), cx, cy)
+    eps = orc.residuals(pb, R, t, f)
+    # float32 rounding of pixel coordinates (<= 2^-24 relative) bounds |eps|
+    bound = 4 * 2.0 ** -24 * (np.abs(rows[:, 2:6]).max() + 1) / f.min() * 4
+    assert np.abs(eps).max() < bound
+
+
+def test_essential_singular_values(orc):
+    """An essential matrix has singular values (s, s, 0); with unit u, s = 1."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        R = _rot(rng, 2)
+        t = rng.normal(size=(2, 3)) * rng.uniform(0.1, 10)
+        E = orc.pair_F(R[0], t[0], 1.0, R[1], t[1], 1.0)
+        s = np.linalg.svd(E, compute_uv=False)
+        np.testing.assert_allclose(s, [1.0, 1.0, 0.0], atol=1e-14)
+
+
+def test_similarity_invariance(orc):
+    """R_i' = R_i Rg^T, t_i' = s t_i - R_i' d leaves every residual unchanged."""
+    sc = synth.tiny_scene(n_cams=5, n_pts=50, seed=4, sigma=1.0, outlier_frac=0.2)
+    pb = _problem(orc, sc)
+    rng = np.random.default_rng(2)
+    R, t, f = sc.R_init, sc.t_init, sc.f_gt
+    eps = orc.residuals(pb, R, t, f)
+    Rg = _rot(rng, 1)[0]
+    for s in (0.01, 1.0, 37.0):
+        d = rng.normal(size=3) * 5
+        R2 = R @ Rg.T
+        t2 = s * t - np.einsum("nij,j->ni", R2, d)
+        np.testing.assert_allclose(orc.residuals(pb, R2, t2, f), eps, rtol=0, atol=1e-12)
+    # a reflection of all translations (s = -1) flips E's sign: same |eps|
+    np.testing.assert_allclose(np.abs(orc.residuals(pb, R, -t, f)), np.abs(eps), atol=1e-12)
+
+
+def test_orientation_of_match_does_not_matter(orc):
+    sc = synth.tiny_scene(n_cams=4, n_pts=40, seed=8, sigma=1.0)
+    pb = _problem(orc, sc)
+    pb_sw = orc.OracleProblem(sc.x2, sc.y2, sc.x1, sc.y1, sc.cam2, sc.cam1, sc.cx, sc.cy)
+    np.testing.assert_allclose(orc.residuals(pb, sc.R_init, sc.t_init, sc.f_init),
+                               orc.residuals(pb_sw, sc.R_init, sc.t_init, sc.f_init),
+                               rtol=1e-13, atol=1e-16)
+
+
+# ---------------------------------------------------------------- IRLS loss
+
+def _weights(eps_hat, mask, delta):
+    Z = mask.sum()
+    return np.where(mask, 1.0 / (Z * np.maximum(np.abs(eps_hat), delta)), 0.0)
+
+
+def test_quadratic_form_identity(orc):
+    """Eq. fastmap-epipolar-objective-l2: sum_m c (p2^T F p1)^2 equals
+    sum_n f_n^T W_n f_n with W_n = sum_m c w w^T, w = vec(p2 p1^T), f_n =
+    vec(F_n) -- with factor 1 (the printed factor 2 does not hold)."""
+    sc = synth.tiny_scene(n_cams=5, n_pts=60, seed=9, sigma=1.0, outlier_frac=0.2)
+    pb = _problem(orc, sc)
+    rng = np.random.default_rng(1)
+    R, t, f = sc.R_init, sc.t_init, sc.f_init * 1.05
+    Rh, th, fh = sc.R_gt, sc.t_gt, sc.f_gt
+    mask = rng.random(sc.n_matches) < 0.8
+    delta = 1e-4
+    loss, *_ = orc.loss_grad(pb, R, t, f, Rh, th, fh, mask, delta)
+    eps_hat = orc.residuals(pb, Rh, th, fh)
+    c = _weights(eps_hat, mask, delta)
+    # W_n per unordered pair, built from canonically oriented matches
+    total = 0.0
+    i = np.minimum(sc.cam1, sc.cam2)
+    j = np.maximum(sc.cam1, sc.cam2)
+    sw = sc.cam1 > sc.cam2
+    ax = np.where(sw, sc.x2, sc.x1).astype(np.float64) - sc.cx[i]
+    ay = np.where(sw, sc.y2, sc.y1).astype(np.float64) - sc.cy[i]
+    bx = np.where(sw, sc.x1, sc.x2).astype(np.float64) - sc.cx[j]
+    by = np.where(sw, sc.y1, sc.y2).astype(np.float64) - sc.cy[j]
+    for (a, b) in sc.pairs():
+        sel = (i == a) & (j == b)
+        p1 = np.stack([ax[sel], ay[sel], np.ones(sel.sum())], 1)
+        p2 = np.stack([bx[sel], by[sel], np.ones(sel.sum())], 1)
+        w = np.einsum("ma,mb->mab", p2, p1).reshape(-1, 9)
+        W = np.einsum("m,mk,ml->kl", c[sel], w, w)
+        e = orc.pair_F(R[a], t[a], f[a], R[b], t[b], f[b]).reshape(9)
+        total += e @ W @ e
+    np.testing.assert_allclose(loss, total, rtol=1e-12)
+
+
+def test_irls_loss_equals_l1_at_snapshot(orc):
+    """At the snapshot the re-weighted L2 loss is the L1 epipolar loss
+    (mean |eps| over retained matches) wherever |eps| >= delta."""
+    sc = synth.config1()
+    pb = _problem(orc, sc)
+    R, t, f = sc.R_init, sc.t_init, sc.f_init
+    eps = orc.residuals(pb, R, t, f)
+    delta = 1e-7
+    mask = np.abs(eps) >= delta
+    loss, *_ = orc.loss_grad(pb, R, t, f, mask=mask, delta=delta)
+    np.testing.assert_allclose(loss, np.abs(eps[mask]).mean(), rtol=1e-12)
+
+
+def test_mask_is_monotone_and_counts(orc):
+    sc = synth.config1()
+    pb = _problem(orc, sc)
+    eps_init = np.abs(orc.residuals(pb, sc.R_init, sc.t_init, sc.f_init))
+    tau = np.quantile(eps_init, 0.7)
+    mask0 = np.ones(sc.n_matches, bool)
+    mask1, Z1 = orc.update_mask(pb, sc.R_init, sc.t_init, sc.f_init, tau, mask0)
+    assert Z1 == mask1.sum() and np.array_equal(mask1, eps_init < tau)
+    # a larger threshold at other poses never brings a dropped match back
+    mask2, Z2 = orc.update_mask(pb, sc.R_gt, sc.t_gt, sc.f_gt, 10 * tau, mask1)
+    assert not np.any(mask2 & ~mask1)
+    assert Z2 <= Z1
+
+
+# ----------------------------------------------------------------- gradient
+
+def _fd_check(orc, pb, R, t, f, Rh, th, fh, mask, delta, rng, n_probe=12):
+    loss, gR, gt, gf = orc.loss_grad(pb, R, t, f, Rh, th, fh, mask, delta)
+    N = len(f)
+
+    def L(R_, t_, f_):
+        return orc.loss_grad(pb, R_, t_, f_, Rh, th, fh, mask, delta)[0]
+
+    checks = []
+    for _ in range(n_probe):
+        c = rng.integers(N)
+        kind = rng.integers(3)
+        if kind == 0:
+            k = rng.integers(9)
+            h = 1e-6
+            Rp, Rm = R.copy(), R.copy()
+            Rp[c].flat[k] += h
+            Rm[c].flat[k] -= h
+            fd = (L(Rp, t, f) - L(Rm, t, f)) / (2 * h)
+            an = gR[c].flat[k]
+        elif kind == 1:
+            k = rng.integers(3)
+            h = 1e-6 * max(1.0, abs(t[c, k]))
+            tp, tm = t.copy(), t.copy()
+            tp[c, k] += h
+            tm[c, k] -= h
+            fd = (L(R, tp, f) - L(R, tm, f)) / (2 * h)
+            an = gt[c, k]
+        else:
+            h = 1e-6 * f[c]
+            fp, fm = f.copy(), f.copy()
+            fp[c] += h
+            fm[c] -= h
+            fd = (L(R, t, fp) - L(R, t, fm)) / (2 * h)
+            an = gf[c]
+        checks.append((fd, an))
+    scale = max(np.abs(gR).max(), np.abs(gt).max(), np.abs(gf * f).max())
+    for fd, an in checks:
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * scale), (fd, an)
+
+
+def test_gradient_matches_central_differences(orc):
+    sc = synth.tiny_scene(n_cams=5, n_pts=50, seed=12, sigma=1.0, outlier_frac=0.2)
+    pb = _problem(orc, sc)
+    rng = np.random.default_rng(3)
+    mask = rng.random(sc.n_matches) < 0.9
+    # current poses away from the snapshot, focal lengths away from truth
+    _fd_check(orc, pb, sc.R_init, sc.t_init, sc.f_gt * 1.07, sc.R_gt, sc.t_gt, sc.f_gt,
+              mask, 1e-4, rng, n_probe=40)
+
+
+def test_gradient_fd_random_poses(orc):
+    rng = np.random.default_rng(21)
+    sc = synth.tiny_scene(n_cams=4, n_pts=30, seed=13, sigma=2.0)
+    R, t = synth.random_poses(rng, sc.n_cams)
+    pb = _problem(orc, sc)
+    _fd_check(orc, pb, R, t, sc.f_gt, R, t, sc.f_gt, np.ones(sc.n_matches, bool), 1e-4,
+              rng, n_probe=30)
+
+
+def test_gauge_null_space_identities(orc):
+    """Global scale, translation and rotation leave L unchanged, so the
+    analytic gradient is orthogonal to those directions."""
+    sc = synth.tiny_scene(n_cams=6, n_pts=60, seed=14, sigma=1.0, outlier_frac=0.1)
+    pb = _problem(orc, sc)
+    R, t, f = sc.R_init, sc.t_init, sc.f_init
+    loss, gR, gt, gf = orc.loss_grad(pb, R, t, f, sc.R_gt, sc.t_gt, sc.f_gt)
+    gscale = np.abs(gt).max() * np.abs(t).max() + np.abs(gR).max()
+    assert abs(np.sum(gt * t)) < 1e-11 * gscale  # scale
+    np.testing.assert_allclose(np.einsum("nji,nj->i", R, gt), 0.0,
+                               atol=1e-11 * gscale)  # translation
+    A = np.einsum("nji,njk->nik", R, gR).sum(0)  # sum_i R_i^T gR_i
+    np.testing.assert_allclose(A - A.T, 0.0, atol=1e-11 * gscale)  # rotation
+
+
+def test_zero_gradient_at_noiseless_ground_truth(orc):
+    """Ground truth minimises the loss of a noiseless scene: loss and gradient
+    vanish there up to the float32 rounding of the keypoints."""
+    sc = synth.tiny_scene(n_cams=5, n_pts=60, seed=15)
+    pb = _problem(orc, sc)
+    # snapshot elsewhere so the weights are finite and non-uniform
+    args = (sc.R_init, sc.t_init, sc.f_gt)
+    l0, gR0, gt0, gf0 = orc.loss_grad(pb, sc.R_init, sc.t_init, sc.f_gt, *args)
+    l1, gR1, gt1, gf1 = orc.loss_grad(pb, sc.R_gt, sc.t_gt, sc.f_gt, *args)
+    assert l1 < 1e-8 * l0
+    assert np.abs(gR1).max() < 1e-4 * np.abs(gR0).max()
+    assert np.abs(gt1).max() < 1e-4 * np.abs(gt0).max()
+    assert np.abs(gf1).max() < 1e-4 * np.abs(gf0).max()
+
+
+# ------------------------------------------------------ 6D rotation and Adam
+
+def test_rot6d_orthonormal_and_roundtrip(orc):
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        a6 = rng.normal(size=6)
+        R = orc.rot6d_to_R(a6)
+        np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-14)
+        assert abs(np.linalg.det(R) - 1.0) < 1e-14
+        Rq = _rot(rng, 1)[0]
+        np.testing.assert_allclose(orc.rot6d_to_R(orc.R_to_rot6d(Rq)), Rq, atol=1e-15)
+
+
+def test_rot6d_backward_fd(orc):
+    rng = np.random.default_rng(6)
+    for _ in range(10):
+        a6 = rng.normal(size=6)
+        G = rng.normal(size=(3, 3))
+        g = orc.rot6d_backward(a6, G)
+        for k in range(6):
+            h = 1e-6
+            ap, am = a6.copy(), a6.copy()
+            ap[k] += h
+            am[k] -= h
+            fd = (np.sum(G * orc.rot6d_to_R(ap)) - np.sum(G * orc.rot6d_to_R(am))) / (2 * h)
+            assert abs(fd - g[k]) < 1e-7 * max(1.0, abs(g[k]))
+
+
+def test_adam_first_step_and_constant_gradient(orc):
+    """Bias-corrected Adam moves each coordinate by exactly lr*sign(g) on the
+    first step, and keeps doing so while the gradient stays constant."""
+    p0 = np.array([1.0, -2.0, 0.5, 3.0])
+    g = np.array([3e-3, -7.0, 1e-5, 250.0])
+    p, m, v = p0.copy(), np.zeros(4), np.zeros(4)
+    lr = 0.01
+    for k in range(1, 6):
+        p, m, v = orc.adam(p, m, v, g, k, lr)
+        # with epsilon e in the denominator the step is lr*|g|/(|g|+e)
+        tol = 1e-12 + k * lr * 1e-12 / np.abs(g)
+        assert np.all(np.abs(p - (p0 - k * lr * np.sign(g))) <= tol)
+
+
+# ------------------------------------------------------------------- solve
+
+def test_epipolar_adjust_converges_config1(orc):
+    sc = synth.config1()
+    pb = _problem(orc, sc)
+    e0 = metrics.mean_rotation_error_deg(sc.R_init, sc.R_gt)
+    out = orc.epipolar_adjust(pb, sc.R_init, sc.t_init, sc.f_init)
+    e1 = metrics.mean_rotation_error_deg(out["R"], sc.R_gt)
+    assert e0 > 2.0 and e1 < 1.0
+    # filtering keeps most true inliers and drops most outliers
+    assert out["mask"][sc.inlier].mean() > 0.9
+    assert out["mask"][~sc.inlier].mean() < 0.3
+    assert np.all(np.diff(out["inliers"]) <= 0)
+
+
+def test_epipolar_adjust_shared_intrinsics(orc):
+    sc = synth.config1()
+    pb = _problem(orc, sc)
+    groups = np.zeros(sc.n_cams, np.int32)
+    out = orc.epipolar_adjust(pb, sc.R_init, sc.t_init, sc.f_init, intr_group=groups,
+                              options=orc.default_options(rounds=2, iters_per_round=20))
+    assert np.ptp(out["f"]) == 0.0
+    # the result is returned in the caller's frame: centres stay near truth's scale
+    c = -np.einsum("nji,nj->ni", out["R"], out["t"])
+    c_gt = -np.einsum("nji,nj->ni", sc.R_gt, sc.t_gt)
+    ratio = np.linalg.norm(c - c.mean(0), axis=1).mean() / np.linalg.norm(
+        c_gt - c_gt.mean(0), axis=1).mean()
+    assert 0.8 < ratio < 1.25
