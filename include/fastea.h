@@ -165,6 +165,13 @@ fea_status fea_load_matches_device(fea_ctx *ctx, int64_t n, const float *x1_dev,
  * FEA_EDEGENERATE if two matched cameras share a centre. */
 fea_status fea_init_poses(fea_ctx *ctx, const double *R, const double *t);
 
+/* Replaces the current poses (caller's frame, host arrays: R [n_cams*9],
+ * t [n_cams*3], f [n_cams] or NULL to keep the focal lengths) without
+ * touching the round: the snapshot, the retained matches and the Adam moments
+ * stay as they are.  Used to evaluate the objective at arbitrary poses and by
+ * optimisers that run outside the library.  Requires fea_init_poses. */
+fea_status fea_set_poses(fea_ctx *ctx, const double *R, const double *t, const double *f);
+
 /* Starts an IRLS round (re-weighting rounds and outlier filtering of the
  * Epipolar Adjustment paragraph): freezes the current poses as the snapshot,
  * drops matches with |eps_hat| >= tau_px / median(f) (tau_px in pixels; pass
@@ -208,6 +215,17 @@ fea_status fea_get_mask(fea_ctx *ctx, uint8_t *mask, int64_t *n_retained);
 
 /* Sizes and state. */
 fea_status fea_get_info(fea_ctx *ctx, fea_info *out);
+
+/* Blocks until all work issued on the context's stream has finished. */
+fea_status fea_synchronize(fea_ctx *ctx);
+
+/* Kernel timing for measurement.  While enabled, every launch of the
+ * per-match residual/gradient kernel is bracketed by HIP events recorded on
+ * the context's stream.  fea_set_kernel_timing(ctx, 1) clears earlier
+ * records; fea_get_kernel_timing synchronises the stream and returns the
+ * summed event time (ms) and the number of timed launches. */
+fea_status fea_set_kernel_timing(fea_ctx *ctx, int32_t enable);
+fea_status fea_get_kernel_timing(fea_ctx *ctx, double *resgrad_ms, int64_t *resgrad_launches);
 
 /* Rotation log kept by fea_epipolar_adjust when options.log_every > 0:
  * R_log [max_log * n_cams * 9] host, in the caller's frame; *n_logged

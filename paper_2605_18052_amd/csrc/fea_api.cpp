@@ -1,0 +1,780 @@
+// C ABI of libfastea: context lifetime, input validation, the IRLS round
+// loop of FastMap's epipolar adjustment (Method > Epipolar Adjustment:
+// re-weighting rounds, outlier filtering with a decreasing threshold, focal
+// lengths folded into the essential matrix) and the host-side bookkeeping of
+// the O(pairs + cameras) metadata.  All O(matches) work runs in the HIP
+// kernels of fea_segment.hip, fea_resgrad.hip and fea_camera.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fea_ctx.h"
+
+using fea::DBuf;
+
+namespace {
+
+fea_status fail(fea_ctx* c, fea_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIP_OR_FAIL(c, expr)                                                                    \
+  do {                                                                                          \
+    hipError_t _e = (expr);                                                                     \
+    if (_e != hipSuccess) return fail((c), FEA_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int now = -1;
+    if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+  }
+};
+
+hipError_t dalloc(DBuf& b, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 16);
+  if (b.p && b.bytes >= bytes) return hipSuccess;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e == hipSuccess) b.bytes = bytes;
+  return e;
+}
+
+void dfree(DBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+template <class T>
+hipError_t upload(fea_ctx* c, DBuf& b, const T* src, size_t n) {
+  hipError_t e = dalloc(b, n * sizeof(T));
+  if (e != hipSuccess || n == 0) return e;
+  return hipMemcpyAsync(b.p, src, n * sizeof(T), hipMemcpyHostToDevice, c->stream);
+}
+
+template <class T>
+hipError_t download(fea_ctx* c, std::vector<T>& dst, const DBuf& b, size_t n) {
+  dst.resize(n);
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(dst.data(), b.p, n * sizeof(T), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+std::vector<DBuf*> all_bufs(fea_ctx* c) {
+  std::vector<DBuf*> v;
+  for (int b = 0; b < 3; ++b) {
+    for (int a = 0; a < 4; ++a) v.push_back(&c->lay[b][a]);
+    v.push_back(&c->lpos[b]);
+  }
+  DBuf* one[] = {&c->perm, &c->swp, &c->item_pair, &c->item_start, &c->item_count, &c->pair_item_off,
+                 &c->item_keep, &c->item_base, &c->part, &c->d_pair_i, &c->d_pair_j, &c->d_cam_off,
+                 &c->d_cam_ent, &c->d_group, &c->d_grp_off, &c->d_grp_cams, &c->d_cx, &c->d_cy, &c->a6,
+                 &c->tp, &c->logf, &c->m_a6, &c->v_a6, &c->m_t, &c->v_t, &c->m_f, &c->v_f, &c->R[0],
+                 &c->R[1], &c->T[0], &c->T[1], &c->Fc[0], &c->Fc[1], &c->Rh, &c->Th, &c->Fh, &c->gR,
+                 &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag};
+  for (DBuf* b : one) v.push_back(b);
+  return v;
+}
+
+bool options_valid(const fea_options* o, std::string* why) {
+  auto bad = [&](const char* s) {
+    *why = s;
+    return false;
+  };
+  if (o->rounds < 0 || o->rounds > 100000) return bad("rounds must be in [0, 100000]");
+  if (o->iters_per_round < 0) return bad("iters_per_round must be >= 0");
+  if (!(o->tau_px_init > 0) || !(o->tau_px_min > 0)) return bad("tau_px_init and tau_px_min must be > 0");
+  if (!(o->tau_decay > 0 && o->tau_decay <= 1)) return bad("tau_decay must be in (0, 1]");
+  if (!(o->delta > 0) || !std::isfinite(o->delta)) return bad("delta must be finite and > 0");
+  if (!(o->lr_rot >= 0) || !(o->lr_t >= 0) || !(o->lr_logf >= 0)) return bad("learning rates must be >= 0");
+  if (!(o->beta1 >= 0 && o->beta1 < 1) || !(o->beta2 >= 0 && o->beta2 < 1)) return bad("betas must be in [0,1)");
+  if (!(o->adam_eps >= 0)) return bad("adam_eps must be >= 0");
+  if (o->log_every < 0 || o->max_log < 0) return bad("log_every and max_log must be >= 0");
+  for (int k = 0; k < 8; ++k)
+    if (o->reserved[k] != 0) return bad("reserved option fields must be zero");
+  return true;
+}
+
+double median(std::vector<double> v) {
+  if (v.empty()) return 1.0;
+  std::sort(v.begin(), v.end());
+  const size_t n = v.size();
+  return (n % 2) ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
+}
+
+// Work items of the current layout: runs of <= kItemMatches matches of one
+// pair; pairs with no retained match get none.
+hipError_t build_items(fea_ctx* c) {
+  c->h_item_pair.clear();
+  c->h_item_start.clear();
+  c->h_item_count.clear();
+  c->h_pair_item_off.assign(c->P + 1, 0);
+  for (int64_t n = 0; n < c->P; ++n) {
+    c->h_pair_item_off[n] = (int32_t)c->h_item_pair.size();
+    for (int64_t s = 0; s < c->cur_len[n]; s += fea::kItemMatches) {
+      c->h_item_pair.push_back((int32_t)n);
+      c->h_item_start.push_back((int32_t)(c->phys_off[n] + s));
+      c->h_item_count.push_back((int32_t)std::min<int64_t>(fea::kItemMatches, c->cur_len[n] - s));
+    }
+  }
+  c->h_pair_item_off[c->P] = (int32_t)c->h_item_pair.size();
+  c->n_items = (int64_t)c->h_item_pair.size();
+  hipError_t e;
+  if ((e = upload(c, c->item_pair, c->h_item_pair.data(), c->n_items)) != hipSuccess) return e;
+  if ((e = upload(c, c->item_start, c->h_item_start.data(), c->n_items)) != hipSuccess) return e;
+  if ((e = upload(c, c->item_count, c->h_item_count.data(), c->n_items)) != hipSuccess) return e;
+  if ((e = upload(c, c->pair_item_off, c->h_pair_item_off.data(), c->P + 1)) != hipSuccess) return e;
+  if ((e = dalloc(c->part, std::max<int64_t>(c->n_items, 1) * fea::kPartStride * sizeof(double))) != hipSuccess)
+    return e;
+  if ((e = dalloc(c->item_keep, std::max<int64_t>(c->n_items, 1) * sizeof(int32_t))) != hipSuccess) return e;
+  return dalloc(c->item_base, std::max<int64_t>(c->n_items, 1) * sizeof(int32_t));
+}
+
+// Back to the full (unfiltered) layout.
+hipError_t reset_layout(fea_ctx* c) {
+  c->cur = 0;
+  int64_t off = 0;
+  for (int64_t n = 0; n < c->P; ++n) {
+    c->cur_len[n] = c->seg_off[n + 1] - c->seg_off[n];
+    c->phys_off[n] = off;
+    off += (c->cur_len[n] + fea::kAlign - 1) / fea::kAlign * fea::kAlign;
+  }
+  c->layout_len = off;
+  c->Z = c->M;
+  return build_items(c);
+}
+
+void reset_round_state(fea_ctx* c) {
+  c->round = -1;
+  c->step = 0;
+  c->global_step = 0;
+  c->n_logged = 0;
+  c->tau = std::numeric_limits<double>::infinity();
+}
+
+fea_status load_matches_common(fea_ctx* c, int64_t n, const float* x1, const float* y1, const float* x2,
+                               const float* y2, const int32_t* cam1, const int32_t* cam2) {
+  c->have_matches = false;
+  c->have_poses = false;
+  c->M = n;
+  int bad = 0;
+  hipError_t e = fea::segment_matches(c, x1, y1, x2, y2, cam1, cam2, &bad);
+  if (e != hipSuccess) return fail(c, FEA_EDEVICE, std::string("segmenting: ") + hipGetErrorString(e));
+  if (bad & fea::kErrRange) return fail(c, FEA_EINVAL, "a camera id is outside [0, n_cams)");
+  if (bad & fea::kErrSameCam) return fail(c, FEA_EINVAL, "a match has cam1 == cam2");
+  if (bad & fea::kErrNonFinite) return fail(c, FEA_ENONFINITE, "a keypoint coordinate is not finite");
+  if (c->layout_len >= (int64_t)1 << 31) return fail(c, FEA_EINVAL, "too many matches for 32-bit offsets");
+  // pristine full layout lives in buffer 0; buffers 1 and 2 take the
+  // filtered layouts of successive rounds
+  for (int b = 1; b < 3; ++b) {
+    for (int a = 0; a < 4; ++a)
+      HIP_OR_FAIL(c, dalloc(c->lay[b][a], std::max<int64_t>(c->layout_len, 1) * sizeof(float)));
+    HIP_OR_FAIL(c, dalloc(c->lpos[b], std::max<int64_t>(c->layout_len, 1) * sizeof(int32_t)));
+  }
+  // camera -> incident (pair, side) entries, in pair order
+  const int N = c->N;
+  c->cam_off.assign(N + 1, 0);
+  for (int64_t k = 0; k < c->P; ++k) {
+    c->cam_off[c->pair_i[k] + 1]++;
+    c->cam_off[c->pair_j[k] + 1]++;
+  }
+  for (int i = 0; i < N; ++i) c->cam_off[i + 1] += c->cam_off[i];
+  c->cam_ent.assign(2 * c->P, 0);
+  std::vector<int32_t> fill(c->cam_off.begin(), c->cam_off.end() - 1);
+  for (int64_t k = 0; k < c->P; ++k) {
+    c->cam_ent[fill[c->pair_i[k]]++] = (int32_t)(2 * k);
+    c->cam_ent[fill[c->pair_j[k]]++] = (int32_t)(2 * k + 1);
+  }
+  HIP_OR_FAIL(c, upload(c, c->d_pair_i, c->pair_i.data(), c->P));
+  HIP_OR_FAIL(c, upload(c, c->d_pair_j, c->pair_j.data(), c->P));
+  HIP_OR_FAIL(c, upload(c, c->d_cam_off, c->cam_off.data(), N + 1));
+  HIP_OR_FAIL(c, upload(c, c->d_cam_ent, c->cam_ent.data(), 2 * c->P));
+  HIP_OR_FAIL(c, reset_layout(c));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  reset_round_state(c);
+  c->have_matches = true;
+  return FEA_OK;
+}
+
+void rot6d_to_R_host(const double a[6], double R[9]) {
+  const double n1 = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  const double b1[3] = {a[0] / n1, a[1] / n1, a[2] / n1};
+  const double d = b1[0] * a[3] + b1[1] * a[4] + b1[2] * a[5];
+  const double v[3] = {a[3] - d * b1[0], a[4] - d * b1[1], a[5] - d * b1[2]};
+  const double n2 = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const double b2[3] = {v[0] / n2, v[1] / n2, v[2] / n2};
+  R[0] = b1[0]; R[3] = b1[1]; R[6] = b1[2];
+  R[1] = b2[0]; R[4] = b2[1]; R[7] = b2[2];
+  R[2] = b1[1] * b2[2] - b1[2] * b2[1];
+  R[5] = b1[2] * b2[0] - b1[0] * b2[2];
+  R[8] = b1[0] * b2[1] - b1[1] * b2[0];
+}
+
+fea_status run_steps(fea_ctx* c, int32_t n_steps) {
+  for (int32_t s = 0; s < n_steps; ++s) {
+    c->step += 1;
+    const double bc1 = 1.0 - std::pow(c->opt.beta1, (double)c->step);
+    const double bc2 = 1.0 - std::pow(c->opt.beta2, (double)c->step);
+    HIP_OR_FAIL(c, fea::launch_resgrad(c));
+    HIP_OR_FAIL(c, fea::launch_camgrad(c, 1, bc1, bc2));
+    HIP_OR_FAIL(c, fea::launch_focal_loss(c, 1, bc1, bc2));
+    c->pcur ^= 1;
+    c->global_step += 1;
+    if (c->opt.log_every > 0 && c->global_step % c->opt.log_every == 0 && c->n_logged < c->opt.max_log) {
+      HIP_OR_FAIL(c, hipMemcpyAsync(c->logR.as<double>() + (size_t)c->n_logged * 9 * c->N, c->R[c->pcur].p,
+                                    sizeof(double) * 9 * c->N, hipMemcpyDeviceToDevice, c->stream));
+      c->n_logged += 1;
+    }
+  }
+  return FEA_OK;
+}
+
+fea_status begin_round(fea_ctx* c, double tau_px) {
+  const size_t N = c->N;
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->Rh.p, c->R[c->pcur].p, 9 * N * sizeof(double), hipMemcpyDeviceToDevice,
+                                c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->Th.p, c->T[c->pcur].p, 3 * N * sizeof(double), hipMemcpyDeviceToDevice,
+                                c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->Fh.p, c->Fc[c->pcur].p, N * sizeof(double), hipMemcpyDeviceToDevice,
+                                c->stream));
+  std::vector<double> fnow;
+  HIP_OR_FAIL(c, download(c, fnow, c->Fc[c->pcur], N));
+  const double tau = std::isinf(tau_px) ? std::numeric_limits<double>::infinity() : tau_px / median(fnow);
+  // pass 1: survivors per item
+  HIP_OR_FAIL(c, fea::launch_filter_count(c, tau));
+  std::vector<int32_t> keep;
+  HIP_OR_FAIL(c, download(c, keep, c->item_keep, c->n_items));
+  // new per-pair lengths, aligned offsets and per-item destinations
+  std::vector<int64_t> new_len(c->P, 0), new_off(c->P, 0);
+  std::vector<int32_t> base(c->n_items, 0);
+  for (int64_t n = 0; n < c->P; ++n)
+    for (int32_t it = c->h_pair_item_off[n]; it < c->h_pair_item_off[n + 1]; ++it) new_len[n] += keep[it];
+  int64_t off = 0;
+  for (int64_t n = 0; n < c->P; ++n) {
+    new_off[n] = off;
+    int64_t run = off;
+    for (int32_t it = c->h_pair_item_off[n]; it < c->h_pair_item_off[n + 1]; ++it) {
+      base[it] = (int32_t)run;
+      run += keep[it];
+    }
+    off += (new_len[n] + fea::kAlign - 1) / fea::kAlign * fea::kAlign;
+  }
+  const int dst = (c->cur == 1) ? 2 : 1;
+  const size_t span = (size_t)std::max<int64_t>(off, 1);
+  for (int a = 0; a < 4; ++a) HIP_OR_FAIL(c, hipMemsetAsync(c->lay[dst][a].p, 0, span * sizeof(float), c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(c->lpos[dst].p, 0xFF, span * sizeof(int32_t), c->stream));
+  HIP_OR_FAIL(c, upload(c, c->item_base, base.data(), c->n_items));
+  HIP_OR_FAIL(c, fea::launch_filter_scatter(c, tau, dst));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->cur = dst;
+  c->cur_len = new_len;
+  c->phys_off = new_off;
+  c->layout_len = off;
+  int64_t Z = 0;
+  for (int64_t n = 0; n < c->P; ++n) Z += new_len[n];
+  c->Z = Z;
+  c->tau = tau;
+  HIP_OR_FAIL(c, build_items(c));
+  // fresh Adam moments for the new round's objective
+  DBuf* mom[] = {&c->m_a6, &c->v_a6, &c->m_t, &c->v_t, &c->m_f, &c->v_f};
+  for (DBuf* b : mom) HIP_OR_FAIL(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->round += 1;
+  c->step = 0;
+  return FEA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fea_version(void) { return FEA_VERSION; }
+
+const char* fea_status_string(fea_status s) {
+  switch (s) {
+    case FEA_OK: return "ok";
+    case FEA_EINVAL: return "invalid argument";
+    case FEA_ENOMEM: return "out of memory";
+    case FEA_EDEVICE: return "HIP device error";
+    case FEA_ESTATE: return "call out of order";
+    case FEA_EDEGENERATE: return "degenerate camera pair (coincident centres)";
+    case FEA_ENONFINITE: return "non-finite input";
+  }
+  return "unknown status";
+}
+
+fea_status fea_default_options(fea_options* o) {
+  if (!o) return FEA_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->rounds = 20;
+  o->iters_per_round = 50;
+  o->tau_px_init = 128.0;
+  o->tau_px_min = 4.0;
+  o->tau_decay = 0.5;
+  o->delta = 1e-4;
+  o->lr_rot = 3e-3;
+  o->lr_t = 3e-3;
+  o->lr_logf = 1e-3;
+  o->beta1 = 0.9;
+  o->beta2 = 0.999;
+  o->adam_eps = 1e-12;
+  o->optimize_focal = 1;
+  o->gauge_normalize = 1;
+  o->log_every = 0;
+  o->max_log = 0;
+  return FEA_OK;
+}
+
+fea_status fea_create(fea_ctx** out, int32_t device, const fea_options* opt, void* hip_stream) {
+  if (!out) return FEA_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FEA_EDEVICE;
+  if (device < 0 || device >= ndev) return FEA_EINVAL;
+  fea_options o;
+  if (opt) {
+    o = *opt;
+    std::string why;
+    if (!options_valid(&o, &why)) return FEA_EINVAL;
+  } else {
+    fea_default_options(&o);
+  }
+  fea_ctx* c = new (std::nothrow) fea_ctx();
+  if (!c) return FEA_ENOMEM;
+  c->device = device;
+  c->opt = o;
+  DeviceGuard g(device);
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return FEA_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  if (dalloc(c->errflag, sizeof(int)) != hipSuccess || dalloc(c->loss, sizeof(double)) != hipSuccess) {
+    fea_destroy(c);
+    return FEA_ENOMEM;
+  }
+  *out = c;
+  return FEA_OK;
+}
+
+void fea_destroy(fea_ctx* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (DBuf* b : all_bufs(c)) dfree(*b);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* fea_last_error(const fea_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+fea_status fea_set_options(fea_ctx* c, const fea_options* opt) {
+  if (!c || !opt) return fail(c, FEA_EINVAL, "null argument");
+  std::string why;
+  if (!options_valid(opt, &why)) return fail(c, FEA_EINVAL, why);
+  c->opt = *opt;
+  return FEA_OK;
+}
+
+fea_status fea_load_intrinsics(fea_ctx* c, int32_t n_cams, const double* f, const double* cx, const double* cy,
+                               const int32_t* intr_group) {
+  if (!c) return FEA_EINVAL;
+  if (n_cams < 2 || n_cams > 65535) return fail(c, FEA_EINVAL, "n_cams must be in [2, 65535]");
+  if (!f || !cx || !cy) return fail(c, FEA_EINVAL, "f, cx and cy are required");
+  DeviceGuard g(c->device);
+  for (int i = 0; i < n_cams; ++i) {
+    if (!std::isfinite(f[i]) || !std::isfinite(cx[i]) || !std::isfinite(cy[i]))
+      return fail(c, FEA_ENONFINITE, "non-finite intrinsics");
+    if (!(f[i] > 0)) return fail(c, FEA_EINVAL, "focal lengths must be > 0");
+    if (intr_group && (intr_group[i] < 0 || intr_group[i] >= n_cams))
+      return fail(c, FEA_EINVAL, "intrinsics group id outside [0, n_cams)");
+  }
+  c->have_intr = c->have_matches = c->have_poses = false;
+  c->N = n_cams;
+  c->f_in.assign(f, f + n_cams);
+  c->cx.assign(cx, cx + n_cams);
+  c->cy.assign(cy, cy + n_cams);
+  c->group.resize(n_cams);
+  int G = 0;
+  for (int i = 0; i < n_cams; ++i) {
+    c->group[i] = intr_group ? intr_group[i] : i;
+    G = std::max(G, c->group[i] + 1);
+  }
+  c->G = G;
+  c->grp_off.assign(G + 1, 0);
+  for (int i = 0; i < n_cams; ++i) c->grp_off[c->group[i] + 1]++;
+  for (int k = 0; k < G; ++k) c->grp_off[k + 1] += c->grp_off[k];
+  c->grp_cams.assign(n_cams, 0);
+  std::vector<int32_t> fill(c->grp_off.begin(), c->grp_off.end() - 1);
+  for (int i = 0; i < n_cams; ++i) c->grp_cams[fill[c->group[i]]++] = i;
+  HIP_OR_FAIL(c, upload(c, c->d_cx, c->cx.data(), n_cams));
+  HIP_OR_FAIL(c, upload(c, c->d_cy, c->cy.data(), n_cams));
+  HIP_OR_FAIL(c, upload(c, c->d_group, c->group.data(), n_cams));
+  HIP_OR_FAIL(c, upload(c, c->d_grp_off, c->grp_off.data(), G + 1));
+  HIP_OR_FAIL(c, upload(c, c->d_grp_cams, c->grp_cams.data(), n_cams));
+  const size_t N = n_cams;
+  DBuf* per_cam[] = {&c->a6, &c->m_a6, &c->v_a6};
+  for (DBuf* b : per_cam) HIP_OR_FAIL(c, dalloc(*b, 6 * N * sizeof(double)));
+  DBuf* per_cam3[] = {&c->tp, &c->m_t, &c->v_t, &c->T[0], &c->T[1], &c->Th, &c->gt};
+  for (DBuf* b : per_cam3) HIP_OR_FAIL(c, dalloc(*b, 3 * N * sizeof(double)));
+  DBuf* per_cam9[] = {&c->R[0], &c->R[1], &c->Rh, &c->gR};
+  for (DBuf* b : per_cam9) HIP_OR_FAIL(c, dalloc(*b, 9 * N * sizeof(double)));
+  DBuf* per_cam1[] = {&c->Fc[0], &c->Fc[1], &c->Fh, &c->gf, &c->loss_cam};
+  for (DBuf* b : per_cam1) HIP_OR_FAIL(c, dalloc(*b, N * sizeof(double)));
+  DBuf* per_grp[] = {&c->logf, &c->m_f, &c->v_f};
+  for (DBuf* b : per_grp) HIP_OR_FAIL(c, dalloc(*b, (size_t)G * sizeof(double)));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->have_intr = true;
+  return FEA_OK;
+}
+
+fea_status fea_load_matches(fea_ctx* c, int64_t n, const float* x1, const float* y1, const float* x2,
+                            const float* y2, const int32_t* cam1, const int32_t* cam2) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_intr) return fail(c, FEA_ESTATE, "load intrinsics first");
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(c, FEA_EINVAL, "n must be in [0, 2^31)");
+  if (n > 0 && (!x1 || !y1 || !x2 || !y2 || !cam1 || !cam2)) return fail(c, FEA_EINVAL, "null match array");
+  DeviceGuard g(c->device);
+  DBuf t[6];
+  struct Free {
+    DBuf* t;
+    ~Free() {
+      for (int k = 0; k < 6; ++k) dfree(t[k]);
+    }
+  } fr{t};
+  const void* src[6] = {x1, y1, x2, y2, cam1, cam2};
+  for (int k = 0; k < 6; ++k) {
+    HIP_OR_FAIL(c, dalloc(t[k], std::max<int64_t>(n, 1) * 4));
+    if (n > 0) HIP_OR_FAIL(c, hipMemcpyAsync(t[k].p, src[k], n * 4, hipMemcpyHostToDevice, c->stream));
+  }
+  fea_status s = load_matches_common(c, n, t[0].as<float>(), t[1].as<float>(), t[2].as<float>(),
+                                     t[3].as<float>(), t[4].as<int32_t>(), t[5].as<int32_t>());
+  (void)hipStreamSynchronize(c->stream);
+  return s;
+}
+
+fea_status fea_load_matches_device(fea_ctx* c, int64_t n, const float* x1, const float* y1, const float* x2,
+                                   const float* y2, const int32_t* cam1, const int32_t* cam2) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_intr) return fail(c, FEA_ESTATE, "load intrinsics first");
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(c, FEA_EINVAL, "n must be in [0, 2^31)");
+  if (n > 0 && (!x1 || !y1 || !x2 || !y2 || !cam1 || !cam2)) return fail(c, FEA_EINVAL, "null match array");
+  DeviceGuard g(c->device);
+  return load_matches_common(c, n, x1, y1, x2, y2, cam1, cam2);
+}
+
+namespace {
+
+// Validates caller-frame poses, writes the 6D parameters, the derived R/t
+// (internal gauge) and, if f is given, log f per group and f per camera.
+// With set_gauge the gauge (centre, scale) is recomputed from these poses.
+fea_status put_poses(fea_ctx* c, const double* R, const double* t, const double* f, bool set_gauge) {
+  const int N = c->N;
+  std::vector<double> tt(t, t + 3 * N);
+  for (int i = 0; i < 9 * N; ++i)
+    if (!std::isfinite(R[i])) return fail(c, FEA_ENONFINITE, "non-finite rotation");
+  for (int i = 0; i < 3 * N; ++i)
+    if (!std::isfinite(t[i])) return fail(c, FEA_ENONFINITE, "non-finite translation");
+  if (f)
+    for (int i = 0; i < N; ++i)
+      if (!std::isfinite(f[i]) || !(f[i] > 0)) return fail(c, FEA_EINVAL, "focal lengths must be finite and > 0");
+  std::vector<double> a6(6 * N), Rc(9 * N);
+  for (int i = 0; i < N; ++i) {
+    const double* r = R + 9 * i;
+    const double det = r[0] * (r[4] * r[8] - r[5] * r[7]) - r[1] * (r[3] * r[8] - r[5] * r[6]) +
+                       r[2] * (r[3] * r[7] - r[4] * r[6]);
+    if (!(det > 0)) return fail(c, FEA_EINVAL, "rotations must have det > 0");
+    for (int k = 0; k < 3; ++k) {
+      a6[6 * i + k] = r[3 * k];
+      a6[6 * i + 3 + k] = r[3 * k + 1];
+    }
+    rot6d_to_R_host(&a6[6 * i], &Rc[9 * i]);
+  }
+  // camera centres o = -R^T t
+  std::vector<double> o(3 * N);
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < 3; ++k)
+      o[3 * i + k] = -(Rc[9 * i + k] * tt[3 * i] + Rc[9 * i + 3 + k] * tt[3 * i + 1] + Rc[9 * i + 6 + k] * tt[3 * i + 2]);
+  std::vector<double> base(c->P);
+  double maxd = 0.0;
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < 3; ++k) maxd = std::max(maxd, std::fabs(o[3 * i + k]));
+  for (int64_t n = 0; n < c->P; ++n) {
+    const double* oi = &o[3 * c->pair_i[n]];
+    const double* oj = &o[3 * c->pair_j[n]];
+    const double d = std::sqrt((oi[0] - oj[0]) * (oi[0] - oj[0]) + (oi[1] - oj[1]) * (oi[1] - oj[1]) +
+                               (oi[2] - oj[2]) * (oi[2] - oj[2]));
+    if (!(d > 1e-12 * std::max(1.0, maxd))) return fail(c, FEA_EDEGENERATE, "two matched cameras share a centre");
+    base[n] = d;
+  }
+  if (set_gauge) {
+    c->gauge_c[0] = c->gauge_c[1] = c->gauge_c[2] = 0.0;
+    c->gauge_s = 1.0;
+    if (c->opt.gauge_normalize) {
+      for (int i = 0; i < N; ++i)
+        for (int k = 0; k < 3; ++k) c->gauge_c[k] += o[3 * i + k] / N;
+      const double s = median(base);
+      c->gauge_s = (s > 0) ? s : 1.0;
+    }
+  }
+  for (int i = 0; i < N; ++i) {
+    double on[3];
+    for (int k = 0; k < 3; ++k) on[k] = (o[3 * i + k] - c->gauge_c[k]) / c->gauge_s;
+    for (int k = 0; k < 3; ++k)
+      tt[3 * i + k] = -(Rc[9 * i + 3 * k] * on[0] + Rc[9 * i + 3 * k + 1] * on[1] + Rc[9 * i + 3 * k + 2] * on[2]);
+  }
+  HIP_OR_FAIL(c, upload(c, c->a6, a6.data(), 6 * N));
+  HIP_OR_FAIL(c, upload(c, c->tp, tt.data(), 3 * N));
+  HIP_OR_FAIL(c, upload(c, c->R[c->pcur], Rc.data(), 9 * N));
+  HIP_OR_FAIL(c, upload(c, c->T[c->pcur], tt.data(), 3 * N));
+  if (f) {
+    // one focal length per group: geometric mean of its cameras' values
+    std::vector<double> logf(c->G, 0.0), fc(N);
+    for (int gi = 0; gi < c->G; ++gi) {
+      const int b = c->grp_off[gi], e = c->grp_off[gi + 1];
+      for (int k = b; k < e; ++k) logf[gi] += std::log(f[c->grp_cams[k]]);
+      if (e > b) logf[gi] /= (e - b);
+    }
+    for (int i = 0; i < N; ++i) fc[i] = std::exp(logf[c->group[i]]);
+    HIP_OR_FAIL(c, upload(c, c->Fc[c->pcur], fc.data(), N));
+    HIP_OR_FAIL(c, upload(c, c->logf, logf.data(), c->G));
+  }
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return FEA_OK;
+}
+
+}  // namespace
+
+fea_status fea_init_poses(fea_ctx* c, const double* R, const double* t) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_matches) return fail(c, FEA_ESTATE, "load matches first");
+  if (!R || !t) return fail(c, FEA_EINVAL, "R and t are required");
+  DeviceGuard g(c->device);
+  c->have_poses = false;
+  c->pcur = 0;
+  fea_status s = put_poses(c, R, t, c->f_in.data(), true);
+  if (s != FEA_OK) return s;
+  HIP_OR_FAIL(c, reset_layout(c));
+  if (c->opt.log_every > 0 && c->opt.max_log > 0)
+    HIP_OR_FAIL(c, dalloc(c->logR, (size_t)c->opt.max_log * 9 * c->N * sizeof(double)));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  reset_round_state(c);
+  c->have_poses = true;
+  return FEA_OK;
+}
+
+fea_status fea_set_poses(fea_ctx* c, const double* R, const double* t, const double* f) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
+  if (!R || !t) return fail(c, FEA_EINVAL, "R and t are required");
+  DeviceGuard g(c->device);
+  return put_poses(c, R, t, f, false);
+}
+
+fea_status fea_begin_round(fea_ctx* c, double tau_px) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
+  if (std::isnan(tau_px) || !(tau_px > 0)) return fail(c, FEA_EINVAL, "tau_px must be > 0 (or INFINITY)");
+  DeviceGuard g(c->device);
+  return begin_round(c, tau_px);
+}
+
+fea_status fea_residual_grad(fea_ctx* c, double* loss_dev, double* gR_dev, double* gt_dev, double* gf_dev) {
+  if (!c) return FEA_EINVAL;
+  if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
+  DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, fea::launch_resgrad(c));
+  HIP_OR_FAIL(c, fea::launch_camgrad(c, 0, 1.0, 1.0));
+  HIP_OR_FAIL(c, fea::launch_focal_loss(c, 0, 1.0, 1.0));
+  const size_t N = c->N;
+  if (loss_dev)
+    HIP_OR_FAIL(c, hipMemcpyAsync(loss_dev, c->loss.p, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (gR_dev)
+    HIP_OR_FAIL(c, hipMemcpyAsync(gR_dev, c->gR.p, 9 * N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (gt_dev)
+    HIP_OR_FAIL(c, hipMemcpyAsync(gt_dev, c->gt.p, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (gf_dev)
+    HIP_OR_FAIL(c, hipMemcpyAsync(gf_dev, c->gf.p, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return FEA_OK;
+}
+
+fea_status fea_step(fea_ctx* c, int32_t n_steps) {
+  if (!c) return FEA_EINVAL;
+  if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
+  if (n_steps < 0) return fail(c, FEA_EINVAL, "n_steps must be >= 0");
+  DeviceGuard g(c->device);
+  return run_steps(c, n_steps);
+}
+
+fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
+  DeviceGuard g(c->device);
+  const auto t0 = std::chrono::steady_clock::now();
+  fea_report rep;
+  std::memset(&rep, 0, sizeof(rep));
+  for (int r = 0; r < c->opt.rounds; ++r) {
+    const double tau_px = std::max(c->opt.tau_px_init * std::pow(c->opt.tau_decay, (double)r), c->opt.tau_px_min);
+    fea_status s = begin_round(c, tau_px);
+    if (s != FEA_OK) return s;
+    s = run_steps(c, c->opt.iters_per_round);
+    if (s != FEA_OK) return s;
+    if (r < 64) {
+      rep.inliers_per_round[r] = c->Z;
+      HIP_OR_FAIL(c, hipMemcpyAsync(&rep.loss_per_round[r], c->loss.p, sizeof(double), hipMemcpyDeviceToHost,
+                                    c->stream));
+    }
+    rep.rounds_run = r + 1;
+    rep.iters_run += c->opt.iters_per_round;
+  }
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  rep.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  rep.n_logged = c->n_logged;
+  if (out) *out = rep;
+  return FEA_OK;
+}
+
+fea_status fea_get_poses(fea_ctx* c, double* R, double* t, double* f) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
+  DeviceGuard g(c->device);
+  const int N = c->N;
+  std::vector<double> Rh, th, fh;
+  HIP_OR_FAIL(c, download(c, Rh, c->R[c->pcur], 9 * N));
+  HIP_OR_FAIL(c, download(c, th, c->T[c->pcur], 3 * N));
+  HIP_OR_FAIL(c, download(c, fh, c->Fc[c->pcur], N));
+  for (int i = 0; i < N; ++i) {
+    const double* r = &Rh[9 * i];
+    double o[3], tw[3];
+    for (int k = 0; k < 3; ++k)
+      o[k] = -(r[k] * th[3 * i] + r[3 + k] * th[3 * i + 1] + r[6 + k] * th[3 * i + 2]) * c->gauge_s + c->gauge_c[k];
+    for (int k = 0; k < 3; ++k) tw[k] = -(r[3 * k] * o[0] + r[3 * k + 1] * o[1] + r[3 * k + 2] * o[2]);
+    if (t)
+      for (int k = 0; k < 3; ++k) t[3 * i + k] = tw[k];
+  }
+  if (R) std::memcpy(R, Rh.data(), sizeof(double) * 9 * N);
+  if (f) std::memcpy(f, fh.data(), sizeof(double) * N);
+  return FEA_OK;
+}
+
+fea_status fea_get_segments(fea_ctx* c, int32_t* perm, uint8_t* swapped, int32_t* pair_cams, int64_t* seg_off) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_matches) return fail(c, FEA_ESTATE, "load matches first");
+  DeviceGuard g(c->device);
+  if (perm && c->M > 0) {
+    HIP_OR_FAIL(c, hipMemcpyAsync(perm, c->perm.p, c->M * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  }
+  if (swapped && c->M > 0) {
+    HIP_OR_FAIL(c, hipMemcpyAsync(swapped, c->swp.p, c->M, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (pair_cams)
+    for (int64_t k = 0; k < c->P; ++k) {
+      pair_cams[2 * k] = c->pair_i[k];
+      pair_cams[2 * k + 1] = c->pair_j[k];
+    }
+  if (seg_off) std::memcpy(seg_off, c->seg_off.data(), sizeof(int64_t) * (c->P + 1));
+  return FEA_OK;
+}
+
+fea_status fea_get_mask(fea_ctx* c, uint8_t* mask, int64_t* n_retained) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_matches) return fail(c, FEA_ESTATE, "load matches first");
+  DeviceGuard g(c->device);
+  if (n_retained) *n_retained = c->Z;
+  if (!mask) return FEA_OK;
+  std::vector<int32_t> pos, perm;
+  HIP_OR_FAIL(c, download(c, pos, c->lpos[c->cur], c->layout_len));
+  HIP_OR_FAIL(c, download(c, perm, c->perm, c->M));
+  std::memset(mask, 0, (size_t)c->M);
+  for (int64_t n = 0; n < c->P; ++n)
+    for (int64_t k = 0; k < c->cur_len[n]; ++k) {
+      const int32_t p = pos[c->phys_off[n] + k];
+      if (p >= 0 && p < c->M) mask[perm[p]] = 1;
+    }
+  return FEA_OK;
+}
+
+fea_status fea_get_info(fea_ctx* c, fea_info* out) {
+  if (!c || !out) return fail(c, FEA_EINVAL, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  out->n_cams = c->N;
+  out->n_groups = c->G;
+  out->n_matches = c->have_matches ? c->M : 0;
+  out->n_pairs = c->have_matches ? c->P : 0;
+  out->n_retained = c->have_matches ? c->Z : 0;
+  out->n_items = c->have_matches ? c->n_items : 0;
+  out->layout_matches = c->have_matches ? c->layout_len : 0;
+  out->round = c->round;
+  out->step = c->step;
+  for (int k = 0; k < 3; ++k) out->gauge_center[k] = c->gauge_c[k];
+  out->gauge_scale = c->gauge_s;
+  out->tau = c->tau;
+  return FEA_OK;
+}
+
+fea_status fea_synchronize(fea_ctx* c) {
+  if (!c) return FEA_EINVAL;
+  DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return FEA_OK;
+}
+
+fea_status fea_set_kernel_timing(fea_ctx* c, int32_t enable) {
+  if (!c) return FEA_EINVAL;
+  DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->timing = enable != 0;
+  c->ev_used = 0;
+  return FEA_OK;
+}
+
+fea_status fea_get_kernel_timing(fea_ctx* c, double* resgrad_ms, int64_t* resgrad_launches) {
+  if (!c) return FEA_EINVAL;
+  DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  double total = 0.0;
+  for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+    float ms = 0.f;
+    HIP_OR_FAIL(c, hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+    total += ms;
+  }
+  if (resgrad_ms) *resgrad_ms = total;
+  if (resgrad_launches) *resgrad_launches = (int64_t)(c->ev_used / 2);
+  return FEA_OK;
+}
+
+fea_status fea_get_rotation_log(fea_ctx* c, double* R_log, int32_t* n_logged) {
+  if (!c) return FEA_EINVAL;
+  if (n_logged) *n_logged = c->n_logged;
+  if (!R_log || c->n_logged == 0) return FEA_OK;
+  DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, hipMemcpyAsync(R_log, c->logR.p, sizeof(double) * 9 * c->N * c->n_logged,
+                                hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return FEA_OK;
+}
+
+}  // extern "C"

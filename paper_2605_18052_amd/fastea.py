@@ -1,0 +1,280 @@
+"""ctypes binding of libfastea (the C ABI declared in include/fastea.h).
+
+Argument marshalling only: every step of epipolar adjustment runs in the HIP
+kernels of the library.  The raw ``fea_*`` functions keep the C names; the
+``Context`` class wraps them for numpy (host) and torch (device) arrays.
+Loading fails loudly when the library has not been built -- there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastea.so")
+
+FEA_OK, FEA_EINVAL, FEA_ENOMEM, FEA_EDEVICE, FEA_ESTATE, FEA_EDEGENERATE, FEA_ENONFINITE = (
+    0, -1, -2, -3, -4, -5, -6)
+
+
+class fea_options(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("iters_per_round", C.c_int32),
+                ("tau_px_init", C.c_double), ("tau_px_min", C.c_double),
+                ("tau_decay", C.c_double), ("delta", C.c_double), ("lr_rot", C.c_double),
+                ("lr_t", C.c_double), ("lr_logf", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("adam_eps", C.c_double),
+                ("optimize_focal", C.c_int32), ("gauge_normalize", C.c_int32),
+                ("log_every", C.c_int32), ("max_log", C.c_int32),
+                ("reserved", C.c_int32 * 8)]
+
+
+class fea_report(C.Structure):
+    _fields_ = [("rounds_run", C.c_int32), ("iters_run", C.c_int32),
+                ("inliers_per_round", C.c_int64 * 64), ("loss_per_round", C.c_double * 64),
+                ("ms_total", C.c_double), ("n_logged", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class fea_info(C.Structure):
+    _fields_ = [("n_cams", C.c_int32), ("n_groups", C.c_int32), ("n_matches", C.c_int64),
+                ("n_pairs", C.c_int64), ("n_retained", C.c_int64), ("n_items", C.c_int64),
+                ("layout_matches", C.c_int64), ("round", C.c_int32), ("step", C.c_int32),
+                ("gauge_center", C.c_double * 3), ("gauge_scale", C.c_double),
+                ("tau", C.c_double), ("reserved", C.c_int32 * 8)]
+
+
+class FeaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fastea error {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+_P = C.c_void_p
+_SIGNATURES = {
+    "fea_version": ([], C.c_int32),
+    "fea_status_string": ([C.c_int], C.c_char_p),
+    "fea_default_options": ([_P], C.c_int),
+    "fea_create": ([_P, C.c_int32, _P, _P], C.c_int),
+    "fea_destroy": ([_P], None),
+    "fea_last_error": ([_P], C.c_char_p),
+    "fea_set_options": ([_P, _P], C.c_int),
+    "fea_load_intrinsics": ([_P, C.c_int32, _P, _P, _P, _P], C.c_int),
+    "fea_load_matches": ([_P, C.c_int64, _P, _P, _P, _P, _P, _P], C.c_int),
+    "fea_load_matches_device": ([_P, C.c_int64, _P, _P, _P, _P, _P, _P], C.c_int),
+    "fea_init_poses": ([_P, _P, _P], C.c_int),
+    "fea_set_poses": ([_P, _P, _P, _P], C.c_int),
+    "fea_begin_round": ([_P, C.c_double], C.c_int),
+    "fea_residual_grad": ([_P, _P, _P, _P, _P], C.c_int),
+    "fea_step": ([_P, C.c_int32], C.c_int),
+    "fea_epipolar_adjust": ([_P, _P], C.c_int),
+    "fea_get_poses": ([_P, _P, _P, _P], C.c_int),
+    "fea_get_segments": ([_P, _P, _P, _P, _P], C.c_int),
+    "fea_get_mask": ([_P, _P, _P], C.c_int),
+    "fea_get_info": ([_P, _P], C.c_int),
+    "fea_synchronize": ([_P], C.c_int),
+    "fea_get_rotation_log": ([_P, _P, _P], C.c_int),
+    "fea_set_kernel_timing": ([_P, C.c_int32], C.c_int),
+    "fea_get_kernel_timing": ([_P, _P, _P], C.c_int),
+}
+
+
+def lib():
+    """Load libfastea.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2605_18052_amd.build`")
+        h = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = h
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+def default_options(**kw) -> fea_options:
+    o = fea_options()
+    lib().fea_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+class Context:
+    """One solver context on one GPU (wraps a fea_ctx*)."""
+
+    def __init__(self, device: int = 0, options: fea_options | None = None, stream=None):
+        self._h = C.c_void_p()
+        opt = options if options is not None else default_options()
+        st = C.c_void_p(stream) if stream else None
+        rc = lib().fea_create(C.byref(self._h), int(device), C.byref(opt), st)
+        if rc != FEA_OK:
+            raise FeaError(rc, lib().fea_status_string(rc).decode())
+        self.device = device
+        self.n_cams = 0
+
+    def _check(self, rc):
+        if rc != FEA_OK:
+            raise FeaError(rc, lib().fea_last_error(self._h).decode())
+
+    def close(self):
+        if self._h:
+            lib().fea_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_options(self, options: fea_options):
+        self._check(lib().fea_set_options(self._h, C.byref(options)))
+
+    def load_intrinsics(self, f, cx, cy, groups=None):
+        f, pf = _host(f, np.float64)
+        cx, pcx = _host(cx, np.float64)
+        cy, pcy = _host(cy, np.float64)
+        pg = None
+        if groups is not None:
+            groups, pg = _host(groups, np.int32)
+        self._check(lib().fea_load_intrinsics(self._h, len(f), pf, pcx, pcy, pg))
+        self.n_cams = len(f)
+
+    def load_matches(self, x1, y1, x2, y2, cam1, cam2):
+        if _is_torch(x1) and x1.is_cuda:
+            import torch
+            arrs = [x1, y1, x2, y2, cam1, cam2]
+            dts = [torch.float32] * 4 + [torch.int32] * 2
+            arrs = [a.to(dtype=d).contiguous() for a, d in zip(arrs, dts)]
+            torch.cuda.current_stream().synchronize()
+            ptrs = [C.c_void_p(a.data_ptr()) for a in arrs]
+            self._check(lib().fea_load_matches_device(self._h, arrs[0].numel(), *ptrs))
+            return
+        keep = [_host(x1, np.float32), _host(y1, np.float32), _host(x2, np.float32),
+                _host(y2, np.float32), _host(cam1, np.int32), _host(cam2, np.int32)]
+        self._check(lib().fea_load_matches(self._h, len(keep[0][0]), *[p for _, p in keep]))
+
+    def init_poses(self, R, t):
+        R, pR = _host(R, np.float64)
+        t, pt = _host(t, np.float64)
+        self._check(lib().fea_init_poses(self._h, pR, pt))
+
+    def set_poses(self, R, t, f=None):
+        R, pR = _host(R, np.float64)
+        t, pt = _host(t, np.float64)
+        pf = None
+        if f is not None:
+            f, pf = _host(f, np.float64)
+        self._check(lib().fea_set_poses(self._h, pR, pt, pf))
+
+    def begin_round(self, tau_px=math.inf):
+        self._check(lib().fea_begin_round(self._h, float(tau_px)))
+
+    def residual_grad(self):
+        """Loss and dL/dR [N,3,3], dL/dt [N,3], dL/df [N] as torch device tensors."""
+        import torch
+        N = self.n_cams
+        dev = torch.device("cuda", self.device)
+        loss = torch.empty(1, dtype=torch.float64, device=dev)
+        gR = torch.empty(N, 3, 3, dtype=torch.float64, device=dev)
+        gt = torch.empty(N, 3, dtype=torch.float64, device=dev)
+        gf = torch.empty(N, dtype=torch.float64, device=dev)
+        torch.cuda.current_stream().synchronize()
+        self._check(lib().fea_residual_grad(self._h, C.c_void_p(loss.data_ptr()),
+                                            C.c_void_p(gR.data_ptr()), C.c_void_p(gt.data_ptr()),
+                                            C.c_void_p(gf.data_ptr())))
+        self.synchronize()
+        return loss, gR, gt, gf
+
+    def step(self, n=1):
+        self._check(lib().fea_step(self._h, int(n)))
+
+    def synchronize(self):
+        self._check(lib().fea_synchronize(self._h))
+
+    def epipolar_adjust(self):
+        rep = fea_report()
+        self._check(lib().fea_epipolar_adjust(self._h, C.byref(rep)))
+        r = rep.rounds_run
+        return dict(rounds_run=r, iters_run=rep.iters_run,
+                    inliers=np.array(rep.inliers_per_round[:min(r, 64)]),
+                    loss=np.array(rep.loss_per_round[:min(r, 64)]), ms_total=rep.ms_total,
+                    n_logged=rep.n_logged)
+
+    def get_poses(self):
+        N = self.n_cams
+        R = np.zeros((N, 3, 3))
+        t = np.zeros((N, 3))
+        f = np.zeros(N)
+        self._check(lib().fea_get_poses(self._h, R.ctypes.data_as(_P), t.ctypes.data_as(_P),
+                                        f.ctypes.data_as(_P)))
+        return R, t, f
+
+    def info(self) -> dict:
+        i = fea_info()
+        self._check(lib().fea_get_info(self._h, C.byref(i)))
+        return {k: (list(getattr(i, k)) if k == "gauge_center" else getattr(i, k))
+                for k, _ in fea_info._fields_ if k != "reserved"}
+
+    def get_segments(self):
+        inf = self.info()
+        M, P = inf["n_matches"], inf["n_pairs"]
+        perm = np.zeros(max(M, 1), np.int32)
+        sw = np.zeros(max(M, 1), np.uint8)
+        pc = np.zeros(2 * max(P, 1), np.int32)
+        so = np.zeros(P + 1, np.int64)
+        self._check(lib().fea_get_segments(self._h, perm.ctypes.data_as(_P), sw.ctypes.data_as(_P),
+                                           pc.ctypes.data_as(_P), so.ctypes.data_as(_P)))
+        return perm[:M], sw[:M].astype(bool), pc[:2 * P].reshape(P, 2), so
+
+    def get_mask(self):
+        M = self.info()["n_matches"]
+        mask = np.zeros(max(M, 1), np.uint8)
+        z = C.c_int64(0)
+        self._check(lib().fea_get_mask(self._h, mask.ctypes.data_as(_P), C.byref(z)))
+        return mask[:M].astype(bool), z.value
+
+    def set_kernel_timing(self, enable=True):
+        self._check(lib().fea_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_timing(self):
+        """(summed ms, launches) of the timed per-match kernel launches."""
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        self._check(lib().fea_get_kernel_timing(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def get_rotation_log(self, max_log):
+        N = self.n_cams
+        buf = np.zeros((max(max_log, 1), N, 3, 3))
+        n = C.c_int32(0)
+        self._check(lib().fea_get_rotation_log(self._h, buf.ctypes.data_as(_P), C.byref(n)))
+        return buf[:n.value]

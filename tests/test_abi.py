@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every symbol include/fastea.h declares
+(no compute call: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fastea.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fea_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def so():
+    from paper_2605_18052_amd import fastea
+    if not os.path.exists(fastea.LIB_PATH):
+        from paper_2605_18052_amd import build
+        build.build()
+    return ctypes.CDLL(fastea.LIB_PATH)
+
+
+def test_every_declared_symbol_is_exported(so):
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(so, n), n
+
+
+def test_binding_covers_header():
+    from paper_2605_18052_amd import fastea
+    assert sorted(fastea.exported_symbols()) == _declared()
+
+
+def test_version_and_defaults(so):
+    from paper_2605_18052_amd import fastea
+    assert fastea.lib().fea_version() == 100
+    o = fastea.default_options()
+    assert o.rounds == 20 and o.iters_per_round == 50 and o.tau_px_init == 128.0
+    assert fastea.lib().fea_default_options(None) == fastea.FEA_EINVAL
+    assert fastea.lib().fea_status_string(fastea.FEA_ESTATE) == b"call out of order"
+
+
+def test_struct_sizes_match_c_layout():
+    from paper_2605_18052_amd import fastea
+    # int32 x2 + double x10 + int32 x4 + int32 x8
+    assert ctypes.sizeof(fastea.fea_options) == 8 + 80 + 16 + 32
+    assert ctypes.sizeof(fastea.fea_report) == 8 + 512 + 512 + 8 + 4 + 28
+    assert ctypes.sizeof(fastea.fea_info) == 8 + 40 + 8 + 24 + 8 + 8 + 32
+
+
+def test_null_handles_are_rejected(so):
+    from paper_2605_18052_amd import fastea
+    L = fastea.lib()
+    assert L.fea_step(None, 1) == fastea.FEA_EINVAL
+    assert L.fea_begin_round(None, 1.0) == fastea.FEA_EINVAL
+    assert L.fea_get_poses(None, None, None, None) == fastea.FEA_EINVAL
+    L.fea_destroy(None)

@@ -1,0 +1,298 @@
+"""GPU path (through the C ABI) against the FP64 oracle.
+
+Bit-exact: segmenting (permutation, orientation, pair table, offsets) and
+the filter's retained set.  Floating point: loss to 1e-5 relative and, per
+camera, ||g_gpu - g_ref|| <= 1e-5 * max(||g_ref||, 1e-3 max ||g_ref||) for
+dL/dR, dL/dt and dL/df separately, at poses away from the snapshot.  Every
+oracle input is built here from the seeded generator.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_18052_amd import fastea, metrics, synth
+
+from gpu_helpers import make_context, oracle_problem, per_camera_close, tau_in_gap
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+
+
+def _scenes():
+    return {
+        "sphere20_m60k": synth.config1(),
+        # few pairs with many matches: several work items per pair, ragged tails
+        "multi_item": synth.sphere_scene(n_cams=4, n_pts=13000, p_det=1.0, sigma=1.0,
+                                         outlier_frac=0.15, seed=21, name="multi_item"),
+        "tiny_focals": synth.tiny_scene(n_cams=6, n_pts=70, seed=5, sigma=1.0, outlier_frac=0.2),
+    }
+
+
+SCENES = _scenes()
+
+
+def _perturbed(sc, seed=0, deg=1.0):
+    rng = np.random.default_rng(seed)
+    dR = synth.rotation_from_axis_angle(rng.normal(size=(sc.n_cams, 3)),
+                                        np.deg2rad(deg) * np.ones(sc.n_cams))
+    R = dR @ sc.R_init
+    t = sc.t_init + rng.normal(scale=0.02, size=sc.t_init.shape)
+    f = sc.f_init * np.exp(rng.uniform(-0.02, 0.02, sc.n_cams))
+    return R, t, f
+
+
+# ------------------------------------------------------------- segmenting
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_segments_bit_exact(name):
+    sc = SCENES[name]
+    ctx = make_context(sc)
+    perm, sw, pc, so = ctx.get_segments()
+    operm, osw, opc, oso = oracle.segment(sc.cam1, sc.cam2, sc.n_cams)
+    assert np.array_equal(perm, operm)
+    assert np.array_equal(sw, osw)
+    assert np.array_equal(pc, opc)
+    assert np.array_equal(so, oso)
+    ctx.close()
+
+
+def test_segments_adversarial_sizes():
+    """Segment sizes 1, 63, 64, 65, 4095, 4096, 4097, 9000 in random order and
+    orientation (runs shorter and longer than a wave and a work item)."""
+    rng = np.random.default_rng(7)
+    sizes = [1, 63, 64, 65, 4095, 4096, 4097, 9000]
+    n_cams = 7
+    allp = [(i, j) for i in range(n_cams) for j in range(i + 1, n_cams)]
+    pick = rng.choice(len(allp), size=len(sizes), replace=False)
+    c1, c2 = [], []
+    for s, k in zip(sizes, pick):
+        i, j = allp[k]
+        fl = rng.random(s) < 0.5
+        c1.append(np.where(fl, j, i))
+        c2.append(np.where(fl, i, j))
+    c1 = np.concatenate(c1).astype(np.int32)
+    c2 = np.concatenate(c2).astype(np.int32)
+    order = rng.permutation(len(c1))
+    c1, c2 = c1[order], c2[order]
+    M = len(c1)
+    xy = rng.uniform(0, 640, size=(4, M)).astype(np.float32)
+    ctx = fastea.Context(0, fastea.default_options())
+    ctx.load_intrinsics(np.full(n_cams, 500.0), np.full(n_cams, 320.0), np.full(n_cams, 240.0))
+    ctx.load_matches(xy[0], xy[1], xy[2], xy[3], c1, c2)
+    perm, sw, pc, so = ctx.get_segments()
+    operm, osw, opc, oso = oracle.segment(c1, c2, n_cams)
+    assert np.array_equal(perm, operm) and np.array_equal(sw, osw)
+    assert np.array_equal(pc, opc) and np.array_equal(so, oso)
+    assert sorted(np.diff(so).tolist()) == sorted(sizes)
+    ctx.close()
+
+
+def test_load_rejects_bad_matches():
+    sc = SCENES["tiny_focals"]
+    ctx = fastea.Context(0, fastea.default_options())
+    ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+    c1 = sc.cam1.copy()
+    c1[3] = sc.cam2[3]
+    with pytest.raises(fastea.FeaError) as e:
+        ctx.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, c1, sc.cam2)
+    assert e.value.status == fastea.FEA_EINVAL
+    c1 = sc.cam1.copy()
+    c1[0] = sc.n_cams
+    with pytest.raises(fastea.FeaError) as e:
+        ctx.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, c1, sc.cam2)
+    assert e.value.status == fastea.FEA_EINVAL
+    x = sc.x1.copy()
+    x[5] = np.nan
+    with pytest.raises(fastea.FeaError) as e:
+        ctx.load_matches(x, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+    assert e.value.status == fastea.FEA_ENONFINITE
+    with pytest.raises(fastea.FeaError) as e:
+        ctx.step(1)
+    assert e.value.status == fastea.FEA_ESTATE
+    ctx.close()
+
+
+def test_degenerate_pose_rejected():
+    sc = SCENES["tiny_focals"]
+    ctx = make_context(sc)
+    t = sc.t_gt.copy()
+    R = sc.R_gt.copy()
+    # camera 1 placed at camera 0's centre
+    o0 = -R[0].T @ t[0]
+    t[1] = -R[1] @ o0
+    with pytest.raises(fastea.FeaError) as e:
+        ctx.init_poses(R, t)
+    assert e.value.status == fastea.FEA_EDEGENERATE
+    ctx.close()
+
+
+def test_zero_matches():
+    sc = SCENES["tiny_focals"]
+    ctx = fastea.Context(0, fastea.default_options(gauge_normalize=0))
+    ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+    e = np.zeros(0, np.float32)
+    ei = np.zeros(0, np.int32)
+    ctx.load_matches(e, e, e, e, ei, ei)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    ctx.begin_round(math.inf)
+    loss, gR, gt, gf = ctx.residual_grad()
+    assert float(loss.item()) == 0.0
+    assert float(gR.abs().max()) == 0.0 and float(gt.abs().max()) == 0.0
+    ctx.step(3)
+    R, t, f = ctx.get_poses()
+    np.testing.assert_allclose(R, sc.R_init, atol=1e-12)
+    ctx.close()
+
+
+# ------------------------------------------------------- residual + gradient
+
+def _parity(sc, R_snap, t_snap, f_snap, R, t, f, tau_px, gauge=0):
+    ctx = make_context(sc, gauge=gauge, f=f_snap)
+    ctx.init_poses(R_snap, t_snap)
+    ctx.begin_round(tau_px)
+    ctx.set_poses(R, t, f)
+    loss, gR, gt, gf = ctx.residual_grad()
+    mask_gpu, Z = ctx.get_mask()
+    pb = oracle_problem(sc)
+    tau = tau_px / np.median(f_snap) if math.isfinite(tau_px) else math.inf
+    mask_ref, Z_ref = oracle.update_mask(pb, R_snap, t_snap, f_snap, tau,
+                                         np.ones(sc.n_matches, bool))
+    assert np.array_equal(mask_gpu, mask_ref) and Z == Z_ref
+    lref, gRr, gtr, gfr = oracle.loss_grad(pb, R, t, f, R_snap, t_snap, f_snap, mask_ref,
+                                           delta=fastea.default_options().delta)
+    ctx.close()
+    return (float(loss.item()), gR.cpu().numpy(), gt.cpu().numpy(), gf.cpu().numpy()), \
+        (lref, gRr, gtr, gfr)
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_residual_grad_parity_no_filter(name):
+    sc = SCENES[name]
+    R, t, f = _perturbed(sc)
+    (l, gR, gt, gf), (lr, gRr, gtr, gfr) = _parity(sc, sc.R_init, sc.t_init, sc.f_init,
+                                                   R, t, f, math.inf)
+    assert abs(l - lr) <= 1e-5 * abs(lr)
+    for a, b in ((gR, gRr), (gt, gtr), (gf[:, None], gfr[:, None])):
+        ok, worst = per_camera_close(a, b)
+        assert ok, worst
+
+
+@pytest.mark.parametrize("name", ["sphere20_m60k", "multi_item"])
+def test_residual_grad_parity_filtered(name):
+    sc = SCENES[name]
+    pb = oracle_problem(sc)
+    eps = np.abs(oracle.residuals(pb, sc.R_init, sc.t_init, sc.f_init))
+    med_f = np.median(sc.f_init)
+    tau = tau_in_gap(eps, np.quantile(eps, 0.8))
+    R, t, f = _perturbed(sc, seed=3)
+    (l, gR, gt, gf), (lr, gRr, gtr, gfr) = _parity(sc, sc.R_init, sc.t_init, sc.f_init,
+                                                   R, t, f, tau * med_f)
+    assert abs(l - lr) <= 1e-5 * abs(lr)
+    for a, b in ((gR, gRr), (gt, gtr), (gf[:, None], gfr[:, None])):
+        ok, worst = per_camera_close(a, b)
+        assert ok, worst
+
+
+def test_parity_at_snapshot_is_l1():
+    """At the snapshot the GPU loss is the L1 epipolar loss (mean |eps|)."""
+    sc = SCENES["sphere20_m60k"]
+    (l, *_), (lr, *_) = _parity(sc, sc.R_init, sc.t_init, sc.f_init, sc.R_init, sc.t_init,
+                                sc.f_init, math.inf)
+    eps = np.abs(oracle.residuals(oracle_problem(sc), sc.R_init, sc.t_init, sc.f_init))
+    assert abs(l - lr) <= 1e-5 * lr
+    assert abs(l - np.mean(np.maximum(eps, 0) ** 2 / np.maximum(eps, 1e-4))) <= 1e-5 * l
+
+
+def test_gauge_normalised_gradient():
+    """With gauge normalisation the library works on normalised poses; the
+    oracle evaluated at the same normalised poses agrees."""
+    sc = SCENES["sphere20_m60k"]
+    pb = oracle_problem(sc)
+    _, _, pairs, _ = oracle.segment(sc.cam1, sc.cam2, sc.n_cams)
+    ctx = make_context(sc, gauge=1)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    ctx.begin_round(math.inf)
+    loss, gR, gt, gf = ctx.residual_grad()
+    tn, center, scale = oracle.gauge_normalize(sc.R_init, sc.t_init, pairs)
+    info = ctx.info()
+    np.testing.assert_allclose(info["gauge_center"], center, rtol=1e-12, atol=1e-12)
+    assert abs(info["gauge_scale"] - scale) <= 1e-12 * scale
+    lr, gRr, gtr, gfr = oracle.loss_grad(pb, sc.R_init, tn.reshape(-1, 3), sc.f_init)
+    assert abs(float(loss.item()) - lr) <= 1e-5 * lr
+    for a, b in ((gR.cpu().numpy(), gRr), (gt.cpu().numpy(), gtr)):
+        ok, worst = per_camera_close(a, b)
+        assert ok, worst
+    ctx.close()
+
+
+# ------------------------------------------------------------- Adam step
+
+def test_first_steps_match_oracle_adam():
+    """Three Adam steps on the GPU equal three oracle steps composed from the
+    oracle's gradient, 6D backward and Adam (within fp32-gradient tolerance)."""
+    sc = SCENES["sphere20_m60k"]
+    opt = fastea.default_options(gauge_normalize=0)
+    ctx = make_context(sc, gauge=0)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    ctx.begin_round(math.inf)
+    ctx.step(3)
+    R_gpu, t_gpu, f_gpu = ctx.get_poses()
+    ctx.close()
+    pb = oracle_problem(sc)
+    N = sc.n_cams
+    a6 = np.stack([oracle.R_to_rot6d(r) for r in sc.R_init])
+    t = sc.t_init.copy()
+    logf = np.log(sc.f_init)
+    m = [np.zeros_like(a6), np.zeros_like(t), np.zeros_like(logf)]
+    v = [np.zeros_like(a6), np.zeros_like(t), np.zeros_like(logf)]
+    R = np.stack([oracle.rot6d_to_R(a) for a in a6])
+    f = np.exp(logf)
+    Rh, th, fh = R.copy(), t.copy(), f.copy()
+    for k in range(1, 4):
+        _, gR, gt, gf = oracle.loss_grad(pb, R, t, f, Rh, th, fh, delta=opt.delta)
+        ga6 = np.stack([oracle.rot6d_backward(a6[c], gR[c]) for c in range(N)])
+        a6f, m[0], v[0] = oracle.adam(a6.ravel(), m[0].ravel(), v[0].ravel(), ga6.ravel(), k,
+                                      opt.lr_rot, opt.beta1, opt.beta2, opt.adam_eps)
+        tf, m[1], v[1] = oracle.adam(t.ravel(), m[1].ravel(), v[1].ravel(), gt.ravel(), k,
+                                     opt.lr_t, opt.beta1, opt.beta2, opt.adam_eps)
+        lf, m[2], v[2] = oracle.adam(logf, m[2], v[2], gf * f, k, opt.lr_logf, opt.beta1,
+                                     opt.beta2, opt.adam_eps)
+        a6, t, logf = a6f.reshape(N, 6), tf.reshape(N, 3), lf
+        m[0], v[0] = m[0].reshape(N, 6), v[0].reshape(N, 6)
+        m[1], v[1] = m[1].reshape(N, 3), v[1].reshape(N, 3)
+        R = np.stack([oracle.rot6d_to_R(a) for a in a6])
+        f = np.exp(logf)
+    # a step moves a coordinate by <= lr; an fp32-level gradient difference
+    # can only change a step through Adam's sign-like normalisation by ~1e-5
+    assert np.abs(R_gpu - R).max() < 1e-6
+    assert np.abs(t_gpu - t).max() < 1e-6
+    np.testing.assert_allclose(f_gpu, f, rtol=1e-8)
+
+
+# ----------------------------------------------------------------- solve
+
+def test_epipolar_adjust_converges_config1():
+    sc = SCENES["sphere20_m60k"]
+    ctx = make_context(sc, gauge=1)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    rep = ctx.epipolar_adjust()
+    R, t, f = ctx.get_poses()
+    mask, Z = ctx.get_mask()
+    ctx.close()
+    err = metrics.mean_rotation_error_deg(R, sc.R_gt)
+    out = oracle.epipolar_adjust(oracle_problem(sc), sc.R_init, sc.t_init, sc.f_init)
+    err_ref = metrics.mean_rotation_error_deg(out["R"], sc.R_gt)
+    assert err < 1.0 and err_ref < 1.0
+    assert abs(err - err_ref) < 0.1
+    assert np.all(np.diff(rep["inliers"]) <= 0)
+    # the retained sets agree up to matches within rounding of the threshold
+    assert np.mean(mask != out["mask"]) < 1e-3
