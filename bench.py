@@ -1,0 +1,198 @@
+"""Benchmark: one epipolar-adjustment step of FastMap on one MI355X.
+
+A step is one pass of the whole hot path over the retained matches of the
+first IRLS round: the fused residual / IRLS-weight / dL/dF kernel over every
+match, the per-camera adjoint and Adam update, and the focal/loss kernel.
+The workload is the 500-camera trajectory scene (200k points, 20 nearest
+neighbours, ~20M matches, sigma 1 px, 20% outliers, unknown focal lengths in
+[400, 1200] px), generated synthetically and resident in HBM before timing.
+
+Prints ONE JSON line on stdout (progress goes to stderr):
+  value       retained matches processed per second (whole job = 1 GPU)
+  roofline    the per-match kernel: algorithmic bytes (16 B/match) / its
+              mean HIP-event duration, against the 8 TB/s HBM peak
+  cpu_baseline the FP64 oracle timed on the host on a 2M-match sample
+  solve       wall time until the mean rotation error first drops to <= 1 deg
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "residual+grad matches/s and HBM GB/s vs peak; wall time to ≤1° mean rot error"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_MATCH = 16  # x1, y1, x2, y2 as fp32: the algorithmic minimum per match
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--matches", type=int, default=20_000_000, help="target match count")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1-degree solve")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_baseline(sc, n_sample, iters):
+    """The FP64 oracle, timed as it stands, on a random sample of matches."""
+    import oracle
+    oracle.build(force=False)
+    rng = np.random.default_rng(12345)
+    sel = np.sort(rng.choice(sc.n_matches, size=min(n_sample, sc.n_matches), replace=False))
+    pb = oracle.OracleProblem.from_scene(sc, sel)
+    opt = oracle.default_options(rounds=1, iters_per_round=iters,
+                                 tau_px_init=oracle.default_options().tau_px_init)
+    t0 = time.perf_counter()
+    oracle.epipolar_adjust(pb, sc.R_init, sc.t_init, sc.f_init, options=opt)
+    dt = time.perf_counter() - t0
+    return {"value": pb.n_matches * iters / dt, "unit": "matches/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{pb.n_matches} random matches of the same scene, 1 round x {iters} "
+                      f"steps of the FP64 C oracle incl. its one-time segmenting, "
+                      f"{dt:.1f} s wall"}
+
+
+def time_to_one_degree(sc, fastea, metrics, chunk=10):
+    """Full solve from the initial poses; rotation error checked every
+    `chunk` steps (the check runs on the host after the timed solve)."""
+    opt = fastea.default_options()
+    ctx = fastea.Context(0, opt)
+    ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+    ctx.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    ctx.synchronize()
+    snaps = []
+    t0 = time.perf_counter()
+    it = 0
+    for r in range(opt.rounds):
+        tau = max(opt.tau_px_init * opt.tau_decay ** r, opt.tau_px_min)
+        ctx.begin_round(tau)
+        done = 0
+        while done < opt.iters_per_round:
+            k = min(chunk, opt.iters_per_round - done)
+            ctx.step(k)
+            done += k
+            it += k
+            R, _, _ = ctx.get_poses()  # synchronises
+            snaps.append((it, time.perf_counter() - t0, R))
+    total = time.perf_counter() - t0
+    errs = [(i, t, metrics.mean_rotation_error_deg(R, sc.R_gt)) for i, t, R in snaps]
+    ctx.close()
+    first = next(((i, t, e) for i, t, e in errs if e <= 1.0), None)
+    return {"wall_to_1deg_s": None if first is None else round(first[1], 4),
+            "iters_to_1deg": None if first is None else first[0],
+            "init_rot_err_deg": round(metrics.mean_rotation_error_deg(sc.R_init, sc.R_gt), 4),
+            "final_rot_err_deg": round(errs[-1][2], 4),
+            "solve_wall_s": round(total, 4), "iters": it,
+            "note": "plain IRLS form; poses read back every 10 steps"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "design is described in DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2605_18052_amd import fastea, metrics, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    t0 = time.perf_counter()
+    sc = synth.config2(target_matches=args.matches)
+    log(f"[bench] scene {sc.name}: {sc.n_cams} cams, {sc.n_matches} matches, "
+        f"{len(sc.pairs())} pairs ({time.perf_counter() - t0:.1f} s)")
+
+    opt = fastea.default_options()
+    ctx = fastea.Context(0, opt)
+    ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+    ctx.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    ctx.begin_round(opt.tau_px_init)
+    info = ctx.info()
+    Z = info["n_retained"]
+    log(f"[bench] round 0: {Z} of {sc.n_matches} matches retained, {info['n_items']} items")
+    ctx.step(args.warmup)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    ctx.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ctx.step(args.steps)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    k_ms, k_n = ctx.kernel_timing()
+    ctx.set_kernel_timing(False)
+    ctx.close()
+    ms_step = 1e3 * wall / args.steps
+    value = Z * args.steps / wall
+    k_avg_s = k_ms / 1e3 / max(k_n, 1)
+    achieved = BYTES_PER_MATCH * Z / k_avg_s / 1e9
+    log(f"[bench] {args.steps} steps in {wall:.4f} s ({ms_step:.4f} ms/step); "
+        f"k_resgrad {1e3 * k_avg_s:.4f} ms avg over {k_n} launches = {achieved:.1f} GB/s")
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calib_copy_mib} MiB read + written, 3 launches")
+
+    solve = None
+    if not args.no_solve:
+        log("[bench] solve to <= 1 deg ...")
+        solve = time_to_one_degree(sc, fastea, metrics)
+        log(f"[bench] solve: {solve}")
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline ...")
+        cpu = cpu_baseline(sc, args.cpu_sample, args.cpu_iters)
+        log(f"[bench] cpu: {cpu}")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "matches/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "traj500_m20M: 500 cameras, 200k points, 20-NN pairs, "
+                               "~20M matches, sigma 1 px, 20% outliers, f in [400,1200] px",
+                   "matches_loaded": sc.n_matches, "matches_per_step": Z,
+                   "pairs": info["n_pairs"], "items": info["n_items"], "round": 0,
+                   "tau_px": opt.tau_px_init},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_resgrad", "kernel_ms": 1e3 * k_avg_s,
+                     "bytes_per_launch": BYTES_PER_MATCH * Z},
+        "cpu_baseline": cpu,
+        "solve": solve,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

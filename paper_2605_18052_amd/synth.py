@@ -177,51 +177,56 @@ def _emit_matches(seed, pair_list, det_ids, det_u, det_v, n_cams, width, height,
     second image.  Each match is then emitted in a random orientation and the
     whole list is shuffled, so callers must canonicalise and sort.
     """
-    chunks = {k: [] for k in ("x1", "y1", "x2", "y2", "c1", "c2", "inl")}
-    for (i, j) in pair_list:
-        ids_i, ids_j = det_ids[i], det_ids[j]
-        if len(ids_i) == 0 or len(ids_j) == 0:
+    pairs = np.asarray(pair_list, dtype=np.int64).reshape(-1, 2)
+    sizes = np.array([len(d) for d in det_ids], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    n_pts = int(max((d.max() + 1 for d in det_ids if len(d)), default=0))
+    all_ids = np.concatenate(det_ids) if n_pts else np.zeros(0, np.int64)
+    all_u = np.concatenate(det_u) if n_pts else np.zeros(0)
+    all_v = np.concatenate(det_v) if n_pts else np.zeros(0)
+    # visit pairs grouped by their second camera, with a dense point -> slot
+    # map of that camera
+    pos = np.full(max(n_pts, 1), -1, dtype=np.int64)
+    a_parts, b_parts, k_parts = [], [], []
+    cur = -1
+    for k in np.argsort(pairs[:, 1], kind="stable"):
+        i, j = int(pairs[k, 0]), int(pairs[k, 1])
+        if j != cur:
+            if cur >= 0:
+                pos[det_ids[cur]] = -1
+            pos[det_ids[j]] = np.arange(len(det_ids[j]))
+            cur = j
+        h = pos[det_ids[i]]
+        hit = np.flatnonzero(h >= 0)
+        if len(hit) == 0:
             continue
-        pos = np.searchsorted(ids_j, ids_i)
-        pos = np.minimum(pos, len(ids_j) - 1)
-        hit = ids_j[pos] == ids_i
-        if not hit.any():
-            continue
-        ii = np.flatnonzero(hit)
-        jj = pos[hit]
-        pts = ids_i[ii]
-        x1 = det_u[i][ii]
-        y1 = det_v[i][ii]
-        x2 = det_u[j][jj].copy()
-        y2 = det_v[j][jj].copy()
-        key = np.uint64(i) * np.uint64(n_cams) + np.uint64(j)
-        out = hash_u01(seed, 40, key, pts) < outlier_frac
-        if out.any():
-            x2[out] = hash_u01(seed, 41, key, pts[out]) * width[j]
-            y2[out] = hash_u01(seed, 42, key, pts[out]) * height[j]
-        flip = hash_u01(seed, 43, key, pts) < 0.5
-        c1 = np.full(len(pts), i, np.int32)
-        c2 = np.full(len(pts), j, np.int32)
-        a_x, a_y, b_x, b_y = x1.copy(), y1.copy(), x2.copy(), y2.copy()
-        a_x[flip], b_x[flip] = x2[flip], x1[flip]
-        a_y[flip], b_y[flip] = y2[flip], y1[flip]
-        c1[flip], c2[flip] = j, i
-        chunks["x1"].append(a_x)
-        chunks["y1"].append(a_y)
-        chunks["x2"].append(b_x)
-        chunks["y2"].append(b_y)
-        chunks["c1"].append(c1)
-        chunks["c2"].append(c2)
-        chunks["inl"].append(~out)
-    if not chunks["x1"]:
+        a_parts.append(offs[i] + hit)
+        b_parts.append(offs[j] + h[hit])
+        k_parts.append(np.full(len(hit), k, dtype=np.int64))
+    if not a_parts:
         e = np.zeros(0, np.float32)
         ei = np.zeros(0, np.int32)
         return e, e, e, e, ei, ei, np.zeros(0, bool)
-    cat = {k: np.concatenate(v) for k, v in chunks.items()}
-    perm = rng.permutation(len(cat["x1"]))
-    return (cat["x1"][perm].astype(np.float32), cat["y1"][perm].astype(np.float32),
-            cat["x2"][perm].astype(np.float32), cat["y2"][perm].astype(np.float32),
-            cat["c1"][perm], cat["c2"][perm], cat["inl"][perm])
+    A = np.concatenate(a_parts)
+    B = np.concatenate(b_parts)
+    K = np.concatenate(k_parts)
+    ci, cj = pairs[K, 0], pairs[K, 1]
+    pts = all_ids[A]
+    x1, y1 = all_u[A], all_v[A]
+    x2, y2 = all_u[B].copy(), all_v[B].copy()
+    key = ci.astype(np.uint64) * np.uint64(n_cams) + cj.astype(np.uint64)
+    out = hash_u01(seed, 40, key, pts) < outlier_frac
+    x2[out] = hash_u01(seed, 41, key[out], pts[out]) * width[cj[out]]
+    y2[out] = hash_u01(seed, 42, key[out], pts[out]) * height[cj[out]]
+    flip = hash_u01(seed, 43, key, pts) < 0.5
+    c1 = np.where(flip, cj, ci).astype(np.int32)
+    c2 = np.where(flip, ci, cj).astype(np.int32)
+    ax, ay = np.where(flip, x2, x1), np.where(flip, y2, y1)
+    bx, by = np.where(flip, x1, x2), np.where(flip, y1, y2)
+    perm = rng.permutation(len(A))
+    return (ax[perm].astype(np.float32), ay[perm].astype(np.float32),
+            bx[perm].astype(np.float32), by[perm].astype(np.float32),
+            c1[perm], c2[perm], ~out[perm])
 
 
 def _detect(seed, R, t, f, cx, cy, width, height, X, p_det, sigma):
