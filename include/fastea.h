@@ -66,7 +66,7 @@ typedef struct {
   double tau_decay;        /* threshold factor per round (0.5) */
   double delta;            /* weight floor: 1/max(|eps_hat|, delta), normalised units (1e-4) */
   double lr_rot;           /* Adam learning rate of the 6D rotation parameters (3e-3) */
-  double lr_t;             /* ... of translations, in the normalised gauge (3e-3) */
+  double lr_t;             /* ... of translations, in the normalised gauge (4e-2) */
   double lr_logf;          /* ... of log focal length per intrinsics group (1e-3) */
   double beta1, beta2;     /* Adam moment decay (0.9, 0.999) */
   double adam_eps;         /* Adam epsilon (1e-12) */
@@ -76,7 +76,13 @@ typedef struct {
                               poses are returned in the caller's frame */
   int32_t log_every;       /* >0: keep the rotations every log_every steps (0) */
   int32_t max_log;         /* capacity of that log, in snapshots (0) */
-  int32_t reserved[8];     /* must be zero */
+  double lr_decay;         /* learning rates of round r are lr * lr_decay^r (0.9) */
+  int32_t reset_moments;   /* 1: zero the Adam moments at every round start (1) */
+  int32_t tile_matches;    /* matches per work item of the per-match kernel:
+                              1024, 2048, 4096 or 8192; 0 = pick by timing the
+                              candidates at the first round (0) */
+  int32_t use_graphs;      /* 1: issue runs of steps as captured HIP graphs (1) */
+  int32_t reserved[5];     /* must be zero */
 } fea_options;
 
 /* What fea_epipolar_adjust did. */
@@ -104,7 +110,10 @@ typedef struct {
   double gauge_center[3];/* applied gauge: centre' = (centre - gauge_center)/gauge_scale */
   double gauge_scale;
   double tau;            /* current threshold, normalised units */
-  int32_t reserved[8];
+  int32_t tile_matches;  /* matches per work item of the per-match kernel */
+  int32_t tile_threads;  /* threads per workgroup of the per-match kernel */
+  int32_t n_scenes;      /* independent scenes in the context (fea_set_scenes) */
+  int32_t reserved[5];
 } fea_info;
 
 /* Library version (FEA_VERSION of the build). */
@@ -141,6 +150,22 @@ fea_status fea_set_options(fea_ctx *ctx, const fea_options *opt);
  * geometric mean of their f).  Resets any loaded matches and poses. */
 fea_status fea_load_intrinsics(fea_ctx *ctx, int32_t n_cams, const double *f,
                                const double *cx, const double *cy, const int32_t *intr_group);
+
+/* Batching: partition the cameras into n_scenes independent scenes solved
+ * together (one launch of each kernel covers every scene).  cam_scene: host
+ * array [n_cams] of scene ids in [0, n_scenes).  Each scene keeps its own
+ * gauge, retained-match count Z, threshold (over its own median focal
+ * length) and loss, so the result equals solving the scenes one by one.
+ * Call after fea_load_intrinsics and before fea_load_matches; matches must
+ * not link two scenes and an intrinsics group must not span scenes
+ * (FEA_EINVAL).  The default is one scene. */
+fea_status fea_set_scenes(fea_ctx *ctx, int32_t n_scenes, const int32_t *cam_scene);
+
+/* Per-scene state (host arrays [n_scenes], [n_scenes], [3*n_scenes],
+ * [n_scenes]; any may be NULL): loss at the last evaluated step, retained
+ * matches of the current round, and the applied gauge. */
+fea_status fea_get_scene_stats(fea_ctx *ctx, double *loss, int64_t *retained,
+                               double *gauge_center, double *gauge_scale);
 
 /* Keypoint matches (Method > Epipolar Adjustment: point pairs Q_n of the
  * image pairs P).  Match m relates pixel (x1[m], y1[m]) of camera cam1[m] to
@@ -188,6 +213,30 @@ fea_status fea_begin_round(fea_ctx *ctx, double tau_px);
 fea_status fea_residual_grad(fea_ctx *ctx, double *loss_dev, double *gR_dev, double *gt_dev,
                              double *gf_dev);
 
+/* Autograd support (parameters held by the caller as device arrays, in the
+ * context's gauge; see fea_info).  Parameters: a6 [n_cams*6] the 6D rotation
+ * parameters (first two columns of R, unnormalised), t [n_cams*3], logf
+ * [n_groups] log focal length per intrinsics group.  The objective uses the
+ * current round's snapshot and retained matches; the context's own poses
+ * and optimiser state are not touched.  All results are written on the
+ * context's stream.
+ *
+ * fea_get_params_dev: the context's current parameters into such arrays
+ * (any pointer may be NULL). */
+fea_status fea_get_params_dev(fea_ctx *ctx, double *a6_dev, double *t_dev, double *logf_dev);
+
+/* Forward: loss_dev [1] = L(a6, t, logf). */
+fea_status fea_loss_dev(fea_ctx *ctx, const double *a6_dev, const double *t_dev,
+                        const double *logf_dev, double *loss_dev);
+
+/* Backward (hand-written adjoint, forward recomputed, no per-match state kept):
+ * ga6_dev [n_cams*6], gt_dev [n_cams*3], glogf_dev [n_groups] receive
+ * gout * dL/d(parameter), gout_dev [1] the upstream gradient (NULL = 1).
+ * Output pointers may be NULL. */
+fea_status fea_adjoint_dev(fea_ctx *ctx, const double *a6_dev, const double *t_dev,
+                           const double *logf_dev, const double *gout_dev, double *ga6_dev,
+                           double *gt_dev, double *glogf_dev);
+
 /* n_steps Adam steps of the current round (each: residual, weight, gradient,
  * per-camera chain rule and update). */
 fea_status fea_step(fea_ctx *ctx, int32_t n_steps);
@@ -218,6 +267,14 @@ fea_status fea_get_info(fea_ctx *ctx, fea_info *out);
 
 /* Blocks until all work issued on the context's stream has finished. */
 fea_status fea_synchronize(fea_ctx *ctx);
+
+/* STREAM-style HBM probe on GPU `device`: a read-only kernel and a copy
+ * kernel over `bytes` bytes (rounded down to 16-byte vectors), best of
+ * `reps` timed launches each.  Writes the achieved read and copy bandwidth
+ * (copy counts read + write bytes) in GB/s.  Allocates and frees its own
+ * buffers. */
+fea_status fea_hbm_probe(int32_t device, int64_t bytes, int32_t reps, double *read_gbps,
+                         double *copy_gbps);
 
 /* Kernel timing for measurement.  While enabled, every launch of the
  * per-match residual/gradient kernel is bracketed by HIP events recorded on

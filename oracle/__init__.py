@@ -45,7 +45,8 @@ class Options(C.Structure):
                 ("tau_decay", C.c_double), ("delta", C.c_double),
                 ("lr_rot", C.c_double), ("lr_t", C.c_double), ("lr_logf", C.c_double),
                 ("beta1", C.c_double), ("beta2", C.c_double), ("adam_eps", C.c_double),
-                ("optimize_focal", C.c_int32), ("gauge_normalize", C.c_int32)]
+                ("optimize_focal", C.c_int32), ("gauge_normalize", C.c_int32),
+                ("lr_decay", C.c_double), ("reset_moments", C.c_int32)]
 
 
 def lib():

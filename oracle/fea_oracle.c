@@ -30,13 +30,15 @@ void orc_default_options(orc_options *o) {
   o->tau_decay = 0.5;
   o->delta = 1e-4;
   o->lr_rot = 3e-3;
-  o->lr_t = 3e-3;
+  o->lr_t = 4e-2;
   o->lr_logf = 1e-3;
   o->beta1 = 0.9;
   o->beta2 = 0.999;
   o->adam_eps = 1e-12;
   o->optimize_focal = 1;
   o->gauge_normalize = 1;
+  o->lr_decay = 0.9;
+  o->reset_moments = 1;
 }
 
 /* ---- small 3x3 helpers (row-major) ------------------------------------ */
@@ -573,6 +575,7 @@ int orc_epipolar_adjust(const orc_problem *pb, const orc_options *opt, const dou
   for (int64_t m = 0; m < M; ++m) mask[m] = 1;
   int32_t nlog = 0;
   int64_t it_global = 0;
+  int64_t adam_step = 0;
 
   for (int32_t r = 0; r < opt->rounds && rc == 0; ++r) {
     /* snapshot and filter (Method > Epipolar Adjustment, re-weighting rounds) */
@@ -592,12 +595,16 @@ int orc_epipolar_adjust(const orc_problem *pb, const orc_options *opt, const dou
       Z += mask[m];
     }
     inliers[r] = Z;
-    memset(m_a6, 0, sizeof(double) * 6 * (size_t)N);
-    memset(v_a6, 0, sizeof(double) * 6 * (size_t)N);
-    memset(m_t, 0, sizeof(double) * 3 * (size_t)N);
-    memset(v_t, 0, sizeof(double) * 3 * (size_t)N);
-    memset(m_f, 0, sizeof(double) * (size_t)G);
-    memset(v_f, 0, sizeof(double) * (size_t)G);
+    if (opt->reset_moments || r == 0) {
+      memset(m_a6, 0, sizeof(double) * 6 * (size_t)N);
+      memset(v_a6, 0, sizeof(double) * 6 * (size_t)N);
+      memset(m_t, 0, sizeof(double) * 3 * (size_t)N);
+      memset(v_t, 0, sizeof(double) * 3 * (size_t)N);
+      memset(m_f, 0, sizeof(double) * (size_t)G);
+      memset(v_f, 0, sizeof(double) * (size_t)G);
+      adam_step = 0;
+    }
+    const double lr_scale = pow(opt->lr_decay, (double)r);
     double loss = 0.0;
     for (int32_t k = 0; k < opt->iters_per_round; ++k) {
       rc = loss_grad_seg(pb, &s, R, t, f, Rh, thh, fh, mask, opt->delta, &loss, gR, gt, gf);
@@ -605,14 +612,14 @@ int orc_epipolar_adjust(const orc_problem *pb, const orc_options *opt, const dou
       for (int32_t c = 0; c < N; ++c) orc_rot6d_backward(a6 + 6 * c, gR + 9 * c, ga6 + 6 * c);
       memset(glogf, 0, sizeof(double) * (size_t)G);
       for (int32_t c = 0; c < N; ++c) glogf[intr_group ? intr_group[c] : c] += gf[c] * f[c];
-      int64_t step = k + 1;
-      orc_adam(6 * (int64_t)N, a6, m_a6, v_a6, ga6, step, opt->lr_rot, opt->beta1, opt->beta2,
-               opt->adam_eps);
-      orc_adam(3 * (int64_t)N, t, m_t, v_t, gt, step, opt->lr_t, opt->beta1, opt->beta2,
-               opt->adam_eps);
+      int64_t step = ++adam_step;
+      orc_adam(6 * (int64_t)N, a6, m_a6, v_a6, ga6, step, opt->lr_rot * lr_scale, opt->beta1,
+               opt->beta2, opt->adam_eps);
+      orc_adam(3 * (int64_t)N, t, m_t, v_t, gt, step, opt->lr_t * lr_scale, opt->beta1,
+               opt->beta2, opt->adam_eps);
       if (opt->optimize_focal)
-        orc_adam(G, logf, m_f, v_f, glogf, step, opt->lr_logf, opt->beta1, opt->beta2,
-                 opt->adam_eps);
+        orc_adam(G, logf, m_f, v_f, glogf, step, opt->lr_logf * lr_scale, opt->beta1,
+                 opt->beta2, opt->adam_eps);
       for (int32_t c = 0; c < N; ++c) {
         orc_rot6d_to_R(a6 + 6 * c, R + 9 * c);
         f[c] = exp(logf[intr_group ? intr_group[c] : c]);

@@ -30,7 +30,8 @@
  *   - rotations are optimised in the 6D (two-column Gram-Schmidt)
  *     representation, focal lengths as log f per intrinsics group,
  *     translations directly; the optimiser is Adam with bias correction,
- *     its moments reset at the start of every IRLS round.
+ *     its moments reset at the start of every IRLS round (optionally kept),
+ *     its learning rates optionally decayed per round.
  */
 #ifndef FEA_ORACLE_H
 #define FEA_ORACLE_H
@@ -61,6 +62,8 @@ typedef struct {
   double beta1, beta2, adam_eps;
   int32_t optimize_focal;
   int32_t gauge_normalize; /* 0 none, 1 centre + median-baseline scale at start */
+  double lr_decay;         /* learning rates of round r: lr * lr_decay^r */
+  int32_t reset_moments;   /* 1: Adam moments (and step count) restart every round */
 } orc_options;
 
 void orc_default_options(orc_options *o);

@@ -88,7 +88,7 @@ std::vector<DBuf*> all_bufs(fea_ctx* c) {
                  &c->d_cam_ent, &c->d_group, &c->d_grp_off, &c->d_grp_cams, &c->d_cx, &c->d_cy, &c->a6,
                  &c->tp, &c->logf, &c->m_a6, &c->v_a6, &c->m_t, &c->v_t, &c->m_f, &c->v_f, &c->R[0],
                  &c->R[1], &c->T[0], &c->T[1], &c->Fc[0], &c->Fc[1], &c->Rh, &c->Th, &c->Fh, &c->gR,
-                 &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag};
+                 &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag, &c->Re, &c->Te, &c->Fe, &c->d_pair_scene, &c->d_inv_z, &c->d_tau, &c->counters};
   for (DBuf* b : one) v.push_back(b);
   return v;
 }
@@ -107,7 +107,13 @@ bool options_valid(const fea_options* o, std::string* why) {
   if (!(o->beta1 >= 0 && o->beta1 < 1) || !(o->beta2 >= 0 && o->beta2 < 1)) return bad("betas must be in [0,1)");
   if (!(o->adam_eps >= 0)) return bad("adam_eps must be >= 0");
   if (o->log_every < 0 || o->max_log < 0) return bad("log_every and max_log must be >= 0");
-  for (int k = 0; k < 8; ++k)
+  if (!(o->lr_decay > 0) || !std::isfinite(o->lr_decay)) return bad("lr_decay must be finite and > 0");
+  if (o->reset_moments != 0 && o->reset_moments != 1) return bad("reset_moments must be 0 or 1");
+  if (o->tile_matches != 0 && o->tile_matches != 1024 && o->tile_matches != 2048 && o->tile_matches != 4096 &&
+      o->tile_matches != 8192)
+    return bad("tile_matches must be 0, 1024, 2048, 4096 or 8192");
+  if (o->use_graphs != 0 && o->use_graphs != 1) return bad("use_graphs must be 0 or 1");
+  for (int k = 0; k < 5; ++k)
     if (o->reserved[k] != 0) return bad("reserved option fields must be zero");
   return true;
 }
@@ -119,32 +125,107 @@ double median(std::vector<double> v) {
   return (n % 2) ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
 }
 
-// Work items of the current layout: runs of <= kItemMatches matches of one
-// pair; pairs with no retained match get none.
+// Work items of the current layout: runs of <= tile matches of one pair
+// (pairs with no retained match get none), and each camera's int4 entries
+// {2n+side, first item, end item, other camera} for the epilogue.
 hipError_t build_items(fea_ctx* c) {
+  const int64_t tile = fea::tile_matches_of(c->tile_cfg);
   c->h_item_pair.clear();
   c->h_item_start.clear();
   c->h_item_count.clear();
   c->h_pair_item_off.assign(c->P + 1, 0);
   for (int64_t n = 0; n < c->P; ++n) {
     c->h_pair_item_off[n] = (int32_t)c->h_item_pair.size();
-    for (int64_t s = 0; s < c->cur_len[n]; s += fea::kItemMatches) {
+    for (int64_t s = 0; s < c->cur_len[n]; s += tile) {
       c->h_item_pair.push_back((int32_t)n);
       c->h_item_start.push_back((int32_t)(c->phys_off[n] + s));
-      c->h_item_count.push_back((int32_t)std::min<int64_t>(fea::kItemMatches, c->cur_len[n] - s));
+      c->h_item_count.push_back((int32_t)std::min<int64_t>(tile, c->cur_len[n] - s));
     }
   }
   c->h_pair_item_off[c->P] = (int32_t)c->h_item_pair.size();
   c->n_items = (int64_t)c->h_item_pair.size();
+  c->h_cam_ent4.assign(4 * 2 * c->P, 0);
+  for (size_t e = 0; e < c->cam_ent.size(); ++e) {
+    const int32_t code = c->cam_ent[e];
+    const int64_t n = code >> 1;
+    const int side = code & 1;
+    c->h_cam_ent4[4 * e] = code;
+    c->h_cam_ent4[4 * e + 1] = c->h_pair_item_off[n];
+    c->h_cam_ent4[4 * e + 2] = c->h_pair_item_off[n + 1];
+    c->h_cam_ent4[4 * e + 3] = side ? c->pair_i[n] : c->pair_j[n];
+  }
   hipError_t e;
   if ((e = upload(c, c->item_pair, c->h_item_pair.data(), c->n_items)) != hipSuccess) return e;
   if ((e = upload(c, c->item_start, c->h_item_start.data(), c->n_items)) != hipSuccess) return e;
   if ((e = upload(c, c->item_count, c->h_item_count.data(), c->n_items)) != hipSuccess) return e;
   if ((e = upload(c, c->pair_item_off, c->h_pair_item_off.data(), c->P + 1)) != hipSuccess) return e;
+  if ((e = upload(c, c->d_cam_ent, c->h_cam_ent4.data(), c->h_cam_ent4.size())) != hipSuccess) return e;
   if ((e = dalloc(c->part, std::max<int64_t>(c->n_items, 1) * fea::kPartStride * sizeof(double))) != hipSuccess)
     return e;
   if ((e = dalloc(c->item_keep, std::max<int64_t>(c->n_items, 1) * sizeof(int32_t))) != hipSuccess) return e;
   return dalloc(c->item_base, std::max<int64_t>(c->n_items, 1) * sizeof(int32_t));
+}
+
+int tile_cfg_for(int32_t tile_matches) {
+  for (int k = 0; k < fea::kNumTiles; ++k)
+    if (fea::tile_matches_of(k) == tile_matches) return k;
+  return -1;
+}
+
+// Picks the work-item shape of the per-match kernel for the current layout:
+// the requested size, or the fastest of the candidate shapes timed on this
+// layout with HIP events (three launches each after one warm-up).
+hipError_t choose_tile(fea_ctx* c) {
+  if (c->tile_tuned) return hipSuccess;
+  if (c->opt.tile_matches > 0) {
+    c->tile_cfg = tile_cfg_for(c->opt.tile_matches);
+    c->tile_tuned = true;
+    return hipSuccess;
+  }
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return e;
+  }
+  float best = 1e30f;
+  int best_cfg = 0;
+  for (int k = 0; k < fea::kNumTiles && e == hipSuccess; ++k) {
+    c->tile_cfg = k;
+    if ((e = build_items(c)) != hipSuccess) break;
+    if ((e = fea::launch_resgrad_cfg(c, k)) != hipSuccess) break;
+    if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) break;
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = fea::launch_resgrad_cfg(c, k);
+    if (e != hipSuccess) break;
+    if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) break;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+    if (ms < best) {
+      best = ms;
+      best_cfg = k;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return e;
+  c->tile_cfg = best_cfg;
+  c->tile_tuned = true;
+  return hipSuccess;
+}
+
+// Per-scene retained counts -> Z and 1/Z on the device.
+hipError_t upload_scene_z(fea_ctx* c) {
+  c->Zs.assign(c->S, 0);
+  for (int64_t n = 0; n < c->P; ++n) c->Zs[c->pair_scene[n]] += c->cur_len[n];
+  c->Z = 0;
+  std::vector<float> inv(c->S, 0.f);
+  for (int s = 0; s < c->S; ++s) {
+    c->Z += c->Zs[s];
+    inv[s] = c->Zs[s] > 0 ? (float)(1.0 / (double)c->Zs[s]) : 0.f;
+  }
+  return upload(c, c->d_inv_z, inv.data(), c->S);
 }
 
 // Back to the full (unfiltered) layout.
@@ -157,7 +238,8 @@ hipError_t reset_layout(fea_ctx* c) {
     off += (c->cur_len[n] + fea::kAlign - 1) / fea::kAlign * fea::kAlign;
   }
   c->layout_len = off;
-  c->Z = c->M;
+  hipError_t e = upload_scene_z(c);
+  if (e != hipSuccess) return e;
   return build_items(c);
 }
 
@@ -188,6 +270,15 @@ fea_status load_matches_common(fea_ctx* c, int64_t n, const float* x1, const flo
       HIP_OR_FAIL(c, dalloc(c->lay[b][a], std::max<int64_t>(c->layout_len, 1) * sizeof(float)));
     HIP_OR_FAIL(c, dalloc(c->lpos[b], std::max<int64_t>(c->layout_len, 1) * sizeof(int32_t)));
   }
+  // every pair must lie inside one scene
+  c->pair_scene.assign(c->P, 0);
+  for (int64_t k = 0; k < c->P; ++k) {
+    if (c->cam_scene[c->pair_i[k]] != c->cam_scene[c->pair_j[k]])
+      return fail(c, FEA_EINVAL, "a match links cameras of different scenes");
+    c->pair_scene[k] = c->cam_scene[c->pair_i[k]];
+  }
+  HIP_OR_FAIL(c, upload(c, c->d_pair_scene, c->pair_scene.data(), c->P));
+  HIP_OR_FAIL(c, dalloc(c->d_tau, (size_t)c->S * sizeof(double)));
   // camera -> incident (pair, side) entries, in pair order
   const int N = c->N;
   c->cam_off.assign(N + 1, 0);
@@ -205,7 +296,8 @@ fea_status load_matches_common(fea_ctx* c, int64_t n, const float* x1, const flo
   HIP_OR_FAIL(c, upload(c, c->d_pair_i, c->pair_i.data(), c->P));
   HIP_OR_FAIL(c, upload(c, c->d_pair_j, c->pair_j.data(), c->P));
   HIP_OR_FAIL(c, upload(c, c->d_cam_off, c->cam_off.data(), N + 1));
-  HIP_OR_FAIL(c, upload(c, c->d_cam_ent, c->cam_ent.data(), 2 * c->P));
+  c->tile_tuned = false;
+  c->tile_cfg = (c->opt.tile_matches > 0) ? tile_cfg_for(c->opt.tile_matches) : 0;
   HIP_OR_FAIL(c, reset_layout(c));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   reset_round_state(c);
@@ -227,23 +319,76 @@ void rot6d_to_R_host(const double a[6], double R[9]) {
   R[8] = b1[0] * b2[1] - b1[1] * b2[0];
 }
 
+void drop_graph(fea_ctx* c) {
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  c->graph_pcur = -1;
+}
+
+// Issues one step (per-match kernel, per-camera chain + Adam, shared-focal
+// update); all step bookkeeping the kernels need lives on the device.
+hipError_t issue_step(fea_ctx* c) {
+  hipError_t e = fea::launch_resgrad(c);
+  if (e == hipSuccess) e = fea::launch_camgrad(c, 1);
+  if (e == hipSuccess && !c->all_single) e = fea::launch_focal_update(c);
+  c->pcur ^= 1;
+  return e;
+}
+
+// Captures kGraphSteps steps starting at the current pose parity.
+hipError_t capture_graph(fea_ctx* c) {
+  drop_graph(c);
+  const int p0 = c->pcur;
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < fea::kGraphSteps && le == hipSuccess; ++k) le = issue_step(c);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->stream, &g);
+  c->pcur = p0;
+  if (le != hipSuccess) e = le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->graph = nullptr;
+    return e;
+  }
+  c->graph_pcur = p0;
+  return hipSuccess;
+}
+
 fea_status run_steps(fea_ctx* c, int32_t n_steps) {
-  for (int32_t s = 0; s < n_steps; ++s) {
-    c->step += 1;
-    const double bc1 = 1.0 - std::pow(c->opt.beta1, (double)c->step);
-    const double bc2 = 1.0 - std::pow(c->opt.beta2, (double)c->step);
-    HIP_OR_FAIL(c, fea::launch_resgrad(c));
-    HIP_OR_FAIL(c, fea::launch_camgrad(c, 1, bc1, bc2));
-    HIP_OR_FAIL(c, fea::launch_focal_loss(c, 1, bc1, bc2));
-    c->pcur ^= 1;
-    c->global_step += 1;
-    if (c->opt.log_every > 0 && c->global_step % c->opt.log_every == 0 && c->n_logged < c->opt.max_log) {
-      HIP_OR_FAIL(c, hipMemcpyAsync(c->logR.as<double>() + (size_t)c->n_logged * 9 * c->N, c->R[c->pcur].p,
-                                    sizeof(double) * 9 * c->N, hipMemcpyDeviceToDevice, c->stream));
-      c->n_logged += 1;
+  const bool graphs = c->opt.use_graphs && !c->timing && c->stream != nullptr && c->n_items > 0;
+  while (n_steps > 0) {
+    if (graphs && n_steps >= fea::kGraphSteps) {
+      if (!c->graph || c->graph_pcur != c->pcur) HIP_OR_FAIL(c, capture_graph(c));
+      HIP_OR_FAIL(c, hipGraphLaunch(c->graph, c->stream));
+      n_steps -= fea::kGraphSteps;
+      c->step += fea::kGraphSteps;
+      c->adam_t += fea::kGraphSteps;
+      c->global_step += fea::kGraphSteps;
+    } else {
+      HIP_OR_FAIL(c, issue_step(c));
+      n_steps -= 1;
+      c->step += 1;
+      c->adam_t += 1;
+      c->global_step += 1;
     }
   }
+  if (c->opt.log_every > 0)
+    c->n_logged = (int32_t)std::min<int64_t>(c->opt.max_log, c->global_step / c->opt.log_every);
   return FEA_OK;
+}
+
+// Host -> device copy of the step counters: Adam count `t` and global count
+// `g` into the slots of the current parity.
+hipError_t set_counters(fea_ctx* c, int64_t t, int64_t g) {
+  long long h[4] = {0, 0, 0, 0};
+  h[c->pcur] = t;
+  h[2 + c->pcur] = g;
+  hipError_t e = hipMemcpyAsync(c->counters.p, h, sizeof(h), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
 }
 
 fea_status begin_round(fea_ctx* c, double tau_px) {
@@ -256,9 +401,15 @@ fea_status begin_round(fea_ctx* c, double tau_px) {
                                 c->stream));
   std::vector<double> fnow;
   HIP_OR_FAIL(c, download(c, fnow, c->Fc[c->pcur], N));
-  const double tau = std::isinf(tau_px) ? std::numeric_limits<double>::infinity() : tau_px / median(fnow);
+  // threshold per scene: tau_px over the scene's median focal length
+  std::vector<std::vector<double>> fs(c->S);
+  for (size_t i = 0; i < N; ++i) fs[c->cam_scene[i]].push_back(fnow[i]);
+  c->taus.assign(c->S, std::numeric_limits<double>::infinity());
+  if (!std::isinf(tau_px))
+    for (int sc = 0; sc < c->S; ++sc) c->taus[sc] = tau_px / (fs[sc].empty() ? 1.0 : median(fs[sc]));
+  HIP_OR_FAIL(c, upload(c, c->d_tau, c->taus.data(), c->S));
   // pass 1: survivors per item
-  HIP_OR_FAIL(c, fea::launch_filter_count(c, tau));
+  HIP_OR_FAIL(c, fea::launch_filter_count(c));
   std::vector<int32_t> keep;
   HIP_OR_FAIL(c, download(c, keep, c->item_keep, c->n_items));
   // new per-pair lengths, aligned offsets and per-item destinations
@@ -281,23 +432,29 @@ fea_status begin_round(fea_ctx* c, double tau_px) {
   for (int a = 0; a < 4; ++a) HIP_OR_FAIL(c, hipMemsetAsync(c->lay[dst][a].p, 0, span * sizeof(float), c->stream));
   HIP_OR_FAIL(c, hipMemsetAsync(c->lpos[dst].p, 0xFF, span * sizeof(int32_t), c->stream));
   HIP_OR_FAIL(c, upload(c, c->item_base, base.data(), c->n_items));
-  HIP_OR_FAIL(c, fea::launch_filter_scatter(c, tau, dst));
+  HIP_OR_FAIL(c, fea::launch_filter_scatter(c, dst));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->cur = dst;
   c->cur_len = new_len;
   c->phys_off = new_off;
   c->layout_len = off;
-  int64_t Z = 0;
-  for (int64_t n = 0; n < c->P; ++n) Z += new_len[n];
-  c->Z = Z;
-  c->tau = tau;
+  HIP_OR_FAIL(c, upload_scene_z(c));
+  c->tau = c->taus.empty() ? 0.0 : c->taus[0];
+  HIP_OR_FAIL(c, choose_tile(c));
   HIP_OR_FAIL(c, build_items(c));
-  // fresh Adam moments for the new round's objective
-  DBuf* mom[] = {&c->m_a6, &c->v_a6, &c->m_t, &c->v_t, &c->m_f, &c->v_f};
-  for (DBuf* b : mom) HIP_OR_FAIL(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
+  // a new round is a new objective: fresh Adam moments (or, if asked, keep
+  // them across rounds; the first round always starts from zero)
+  if (c->opt.reset_moments || c->round < 0) {
+    DBuf* mom[] = {&c->m_a6, &c->v_a6, &c->m_t, &c->v_t, &c->m_f, &c->v_f};
+    for (DBuf* b : mom) HIP_OR_FAIL(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
+    c->adam_t = 0;
+  }
+  HIP_OR_FAIL(c, set_counters(c, c->adam_t, c->global_step));
+  drop_graph(c);  // the layout changed: recapture on the next run of steps
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->round += 1;
   c->step = 0;
+  c->lr_scale = std::pow(c->opt.lr_decay, (double)c->round);
   return FEA_OK;
 }
 
@@ -330,7 +487,7 @@ fea_status fea_default_options(fea_options* o) {
   o->tau_decay = 0.5;
   o->delta = 1e-4;
   o->lr_rot = 3e-3;
-  o->lr_t = 3e-3;
+  o->lr_t = 4e-2;
   o->lr_logf = 1e-3;
   o->beta1 = 0.9;
   o->beta2 = 0.999;
@@ -339,6 +496,10 @@ fea_status fea_default_options(fea_options* o) {
   o->gauge_normalize = 1;
   o->log_every = 0;
   o->max_log = 0;
+  o->lr_decay = 0.9;
+  o->reset_moments = 1;
+  o->tile_matches = 0;
+  o->use_graphs = 1;
   return FEA_OK;
 }
 
@@ -384,6 +545,7 @@ void fea_destroy(fea_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (DBuf* b : all_bufs(c)) dfree(*b);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  drop_graph(c);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -394,7 +556,13 @@ fea_status fea_set_options(fea_ctx* c, const fea_options* opt) {
   if (!c || !opt) return fail(c, FEA_EINVAL, "null argument");
   std::string why;
   if (!options_valid(opt, &why)) return fail(c, FEA_EINVAL, why);
+  if (opt->tile_matches != c->opt.tile_matches) c->tile_tuned = false;
+  if (opt->log_every > 0 && opt->max_log > 0 && c->have_intr) {
+    DeviceGuard g(c->device);
+    HIP_OR_FAIL(c, dalloc(c->logR, (size_t)opt->max_log * 9 * c->N * sizeof(double)));
+  }
   c->opt = *opt;
+  drop_graph(c);
   return FEA_OK;
 }
 
@@ -413,6 +581,10 @@ fea_status fea_load_intrinsics(fea_ctx* c, int32_t n_cams, const double* f, cons
   }
   c->have_intr = c->have_matches = c->have_poses = false;
   c->N = n_cams;
+  c->S = 1;
+  c->cam_scene.assign(n_cams, 0);
+  c->gauge_c.assign(3, 0.0);
+  c->gauge_s.assign(1, 1.0);
   c->f_in.assign(f, f + n_cams);
   c->cx.assign(cx, cx + n_cams);
   c->cy.assign(cy, cy + n_cams);
@@ -426,9 +598,14 @@ fea_status fea_load_intrinsics(fea_ctx* c, int32_t n_cams, const double* f, cons
   c->grp_off.assign(G + 1, 0);
   for (int i = 0; i < n_cams; ++i) c->grp_off[c->group[i] + 1]++;
   for (int k = 0; k < G; ++k) c->grp_off[k + 1] += c->grp_off[k];
+  c->all_single = true;
+  for (int k = 0; k < G; ++k)
+    if (c->grp_off[k + 1] - c->grp_off[k] > 1) c->all_single = false;
   c->grp_cams.assign(n_cams, 0);
   std::vector<int32_t> fill(c->grp_off.begin(), c->grp_off.end() - 1);
   for (int i = 0; i < n_cams; ++i) c->grp_cams[fill[c->group[i]]++] = i;
+  HIP_OR_FAIL(c, dalloc(c->d_inv_z, sizeof(float)));
+  HIP_OR_FAIL(c, dalloc(c->counters, 4 * sizeof(long long)));
   HIP_OR_FAIL(c, upload(c, c->d_cx, c->cx.data(), n_cams));
   HIP_OR_FAIL(c, upload(c, c->d_cy, c->cy.data(), n_cams));
   HIP_OR_FAIL(c, upload(c, c->d_group, c->group.data(), n_cams));
@@ -437,16 +614,60 @@ fea_status fea_load_intrinsics(fea_ctx* c, int32_t n_cams, const double* f, cons
   const size_t N = n_cams;
   DBuf* per_cam[] = {&c->a6, &c->m_a6, &c->v_a6};
   for (DBuf* b : per_cam) HIP_OR_FAIL(c, dalloc(*b, 6 * N * sizeof(double)));
-  DBuf* per_cam3[] = {&c->tp, &c->m_t, &c->v_t, &c->T[0], &c->T[1], &c->Th, &c->gt};
+  DBuf* per_cam3[] = {&c->tp, &c->m_t, &c->v_t, &c->T[0], &c->T[1], &c->Th, &c->gt, &c->Te};
   for (DBuf* b : per_cam3) HIP_OR_FAIL(c, dalloc(*b, 3 * N * sizeof(double)));
-  DBuf* per_cam9[] = {&c->R[0], &c->R[1], &c->Rh, &c->gR};
+  DBuf* per_cam9[] = {&c->R[0], &c->R[1], &c->Rh, &c->gR, &c->Re};
   for (DBuf* b : per_cam9) HIP_OR_FAIL(c, dalloc(*b, 9 * N * sizeof(double)));
-  DBuf* per_cam1[] = {&c->Fc[0], &c->Fc[1], &c->Fh, &c->gf, &c->loss_cam};
+  DBuf* per_cam1[] = {&c->Fc[0], &c->Fc[1], &c->Fh, &c->gf, &c->loss_cam, &c->Fe};
   for (DBuf* b : per_cam1) HIP_OR_FAIL(c, dalloc(*b, N * sizeof(double)));
   DBuf* per_grp[] = {&c->logf, &c->m_f, &c->v_f};
   for (DBuf* b : per_grp) HIP_OR_FAIL(c, dalloc(*b, (size_t)G * sizeof(double)));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->have_intr = true;
+  return FEA_OK;
+}
+
+fea_status fea_set_scenes(fea_ctx* c, int32_t n_scenes, const int32_t* cam_scene) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_intr) return fail(c, FEA_ESTATE, "load intrinsics first");
+  if (n_scenes < 1 || n_scenes > c->N) return fail(c, FEA_EINVAL, "n_scenes must be in [1, n_cams]");
+  if (n_scenes > 1 && !cam_scene) return fail(c, FEA_EINVAL, "cam_scene is required");
+  std::vector<int32_t> cs(c->N, 0);
+  for (int i = 0; i < c->N && cam_scene; ++i) {
+    if (cam_scene[i] < 0 || cam_scene[i] >= n_scenes) return fail(c, FEA_EINVAL, "scene id outside [0, n_scenes)");
+    cs[i] = cam_scene[i];
+  }
+  for (int g = 0; g < c->G; ++g)
+    for (int k = c->grp_off[g] + 1; k < c->grp_off[g + 1]; ++k)
+      if (cs[c->grp_cams[k]] != cs[c->grp_cams[c->grp_off[g]]])
+        return fail(c, FEA_EINVAL, "an intrinsics group spans several scenes");
+  c->have_matches = c->have_poses = false;
+  c->S = n_scenes;
+  c->cam_scene = cs;
+  c->gauge_c.assign(3 * n_scenes, 0.0);
+  c->gauge_s.assign(n_scenes, 1.0);
+  DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, dalloc(c->d_inv_z, (size_t)n_scenes * sizeof(float)));
+  return FEA_OK;
+}
+
+fea_status fea_get_scene_stats(fea_ctx* c, double* loss, int64_t* retained, double* gauge_center,
+                               double* gauge_scale) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
+  DeviceGuard g(c->device);
+  if (loss) {
+    std::vector<double> lc;
+    HIP_OR_FAIL(c, download(c, lc, c->loss_cam, c->N));
+    for (int s = 0; s < c->S; ++s) loss[s] = 0.0;
+    for (int i = 0; i < c->N; ++i) loss[c->cam_scene[i]] += lc[i];
+  }
+  for (int s = 0; s < c->S; ++s) {
+    if (retained) retained[s] = c->Zs.empty() ? 0 : c->Zs[s];
+    if (gauge_center)
+      for (int k = 0; k < 3; ++k) gauge_center[3 * s + k] = c->gauge_c[3 * s + k];
+    if (gauge_scale) gauge_scale[s] = c->gauge_s[s];
+  }
   return FEA_OK;
 }
 
@@ -530,18 +751,30 @@ fea_status put_poses(fea_ctx* c, const double* R, const double* t, const double*
     base[n] = d;
   }
   if (set_gauge) {
-    c->gauge_c[0] = c->gauge_c[1] = c->gauge_c[2] = 0.0;
-    c->gauge_s = 1.0;
+    // per scene: centres to mean 0, median matched-pair baseline to 1
+    c->gauge_c.assign(3 * c->S, 0.0);
+    c->gauge_s.assign(c->S, 1.0);
     if (c->opt.gauge_normalize) {
-      for (int i = 0; i < N; ++i)
-        for (int k = 0; k < 3; ++k) c->gauge_c[k] += o[3 * i + k] / N;
-      const double s = median(base);
-      c->gauge_s = (s > 0) ? s : 1.0;
+      std::vector<int64_t> cnt(c->S, 0);
+      for (int i = 0; i < N; ++i) {
+        const int sc = c->cam_scene[i];
+        cnt[sc] += 1;
+        for (int k = 0; k < 3; ++k) c->gauge_c[3 * sc + k] += o[3 * i + k];
+      }
+      for (int sc = 0; sc < c->S; ++sc)
+        for (int k = 0; k < 3; ++k) c->gauge_c[3 * sc + k] /= std::max<int64_t>(cnt[sc], 1);
+      std::vector<std::vector<double>> bs(c->S);
+      for (int64_t n = 0; n < c->P; ++n) bs[c->pair_scene[n]].push_back(base[n]);
+      for (int sc = 0; sc < c->S; ++sc) {
+        const double m = bs[sc].empty() ? 1.0 : median(bs[sc]);
+        c->gauge_s[sc] = (m > 0) ? m : 1.0;
+      }
     }
   }
   for (int i = 0; i < N; ++i) {
+    const int sc = c->cam_scene[i];
     double on[3];
-    for (int k = 0; k < 3; ++k) on[k] = (o[3 * i + k] - c->gauge_c[k]) / c->gauge_s;
+    for (int k = 0; k < 3; ++k) on[k] = (o[3 * i + k] - c->gauge_c[3 * sc + k]) / c->gauge_s[sc];
     for (int k = 0; k < 3; ++k)
       tt[3 * i + k] = -(Rc[9 * i + 3 * k] * on[0] + Rc[9 * i + 3 * k + 1] * on[1] + Rc[9 * i + 3 * k + 2] * on[2]);
   }
@@ -579,8 +812,10 @@ fea_status fea_init_poses(fea_ctx* c, const double* R, const double* t) {
   HIP_OR_FAIL(c, reset_layout(c));
   if (c->opt.log_every > 0 && c->opt.max_log > 0)
     HIP_OR_FAIL(c, dalloc(c->logR, (size_t)c->opt.max_log * 9 * c->N * sizeof(double)));
-  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
   reset_round_state(c);
+  c->adam_t = 0;
+  HIP_OR_FAIL(c, set_counters(c, 0, 0));
   c->have_poses = true;
   return FEA_OK;
 }
@@ -606,8 +841,8 @@ fea_status fea_residual_grad(fea_ctx* c, double* loss_dev, double* gR_dev, doubl
   if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
   DeviceGuard g(c->device);
   HIP_OR_FAIL(c, fea::launch_resgrad(c));
-  HIP_OR_FAIL(c, fea::launch_camgrad(c, 0, 1.0, 1.0));
-  HIP_OR_FAIL(c, fea::launch_focal_loss(c, 0, 1.0, 1.0));
+  HIP_OR_FAIL(c, fea::launch_camgrad(c, 0));
+  HIP_OR_FAIL(c, fea::launch_loss_sum(c));
   const size_t N = c->N;
   if (loss_dev)
     HIP_OR_FAIL(c, hipMemcpyAsync(loss_dev, c->loss.p, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -617,6 +852,48 @@ fea_status fea_residual_grad(fea_ctx* c, double* loss_dev, double* gR_dev, doubl
     HIP_OR_FAIL(c, hipMemcpyAsync(gt_dev, c->gt.p, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (gf_dev)
     HIP_OR_FAIL(c, hipMemcpyAsync(gf_dev, c->gf.p, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return FEA_OK;
+}
+
+fea_status fea_get_params_dev(fea_ctx* c, double* a6_dev, double* t_dev, double* logf_dev) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
+  DeviceGuard g(c->device);
+  const size_t N = c->N;
+  if (a6_dev)
+    HIP_OR_FAIL(c, hipMemcpyAsync(a6_dev, c->a6.p, 6 * N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (t_dev)
+    HIP_OR_FAIL(c, hipMemcpyAsync(t_dev, c->tp.p, 3 * N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (logf_dev)
+    HIP_OR_FAIL(c, hipMemcpyAsync(logf_dev, c->logf.p, (size_t)c->G * sizeof(double), hipMemcpyDeviceToDevice,
+                                  c->stream));
+  return FEA_OK;
+}
+
+fea_status fea_loss_dev(fea_ctx* c, const double* a6_dev, const double* t_dev, const double* logf_dev,
+                        double* loss_dev) {
+  if (!c) return FEA_EINVAL;
+  if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
+  if (!a6_dev || !t_dev || !logf_dev || !loss_dev) return fail(c, FEA_EINVAL, "null device array");
+  DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, fea::launch_params_to_pose(c, a6_dev, t_dev, logf_dev));
+  HIP_OR_FAIL(c, fea::launch_resgrad_at(c, c->tile_cfg, c->Re.as<double>(), c->Te.as<double>(),
+                                        c->Fe.as<double>(), true));
+  HIP_OR_FAIL(c, fea::launch_item_loss(c, loss_dev));
+  return FEA_OK;
+}
+
+fea_status fea_adjoint_dev(fea_ctx* c, const double* a6_dev, const double* t_dev, const double* logf_dev,
+                           const double* gout_dev, double* ga6_dev, double* gt_dev, double* glogf_dev) {
+  if (!c) return FEA_EINVAL;
+  if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
+  if (!a6_dev || !t_dev || !logf_dev) return fail(c, FEA_EINVAL, "null device array");
+  DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, fea::launch_params_to_pose(c, a6_dev, t_dev, logf_dev));
+  HIP_OR_FAIL(c, fea::launch_resgrad_at(c, c->tile_cfg, c->Re.as<double>(), c->Te.as<double>(),
+                                        c->Fe.as<double>(), false));
+  HIP_OR_FAIL(c, fea::launch_camgrad_at(c, c->Re.as<double>(), c->Te.as<double>(), c->Fe.as<double>()));
+  HIP_OR_FAIL(c, fea::launch_param_grad(c, a6_dev, gout_dev, ga6_dev, gt_dev, glogf_dev));
   return FEA_OK;
 }
 
@@ -643,6 +920,7 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
     if (s != FEA_OK) return s;
     if (r < 64) {
       rep.inliers_per_round[r] = c->Z;
+      HIP_OR_FAIL(c, fea::launch_loss_sum(c));
       HIP_OR_FAIL(c, hipMemcpyAsync(&rep.loss_per_round[r], c->loss.p, sizeof(double), hipMemcpyDeviceToHost,
                                     c->stream));
     }
@@ -668,8 +946,10 @@ fea_status fea_get_poses(fea_ctx* c, double* R, double* t, double* f) {
   for (int i = 0; i < N; ++i) {
     const double* r = &Rh[9 * i];
     double o[3], tw[3];
+    const int sc = c->cam_scene[i];
     for (int k = 0; k < 3; ++k)
-      o[k] = -(r[k] * th[3 * i] + r[3 + k] * th[3 * i + 1] + r[6 + k] * th[3 * i + 2]) * c->gauge_s + c->gauge_c[k];
+      o[k] = -(r[k] * th[3 * i] + r[3 + k] * th[3 * i + 1] + r[6 + k] * th[3 * i + 2]) * c->gauge_s[sc] +
+             c->gauge_c[3 * sc + k];
     for (int k = 0; k < 3; ++k) tw[k] = -(r[3 * k] * o[0] + r[3 * k + 1] * o[1] + r[3 * k + 2] * o[2]);
     if (t)
       for (int k = 0; k < 3; ++k) t[3 * i + k] = tw[k];
@@ -729,9 +1009,12 @@ fea_status fea_get_info(fea_ctx* c, fea_info* out) {
   out->layout_matches = c->have_matches ? c->layout_len : 0;
   out->round = c->round;
   out->step = c->step;
-  for (int k = 0; k < 3; ++k) out->gauge_center[k] = c->gauge_c[k];
-  out->gauge_scale = c->gauge_s;
+  for (int k = 0; k < 3; ++k) out->gauge_center[k] = c->gauge_c.size() >= 3 ? c->gauge_c[k] : 0.0;
+  out->gauge_scale = c->gauge_s.empty() ? 1.0 : c->gauge_s[0];
+  out->n_scenes = c->S;
   out->tau = c->tau;
+  out->tile_matches = fea::tile_matches_of(c->tile_cfg);
+  out->tile_threads = fea::kTiles[c->tile_cfg].threads;
   return FEA_OK;
 }
 

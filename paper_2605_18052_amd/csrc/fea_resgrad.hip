@@ -48,16 +48,17 @@ __device__ __forceinline__ double eval_eps(const double* F, double x1, double y1
   return fma(x2, l0, fma(y2, l1, l2));
 }
 
-__global__ __launch_bounds__(kRgThreads) void k_resgrad(
+template <int THREADS, int STEPS, bool LOSS_ONLY>
+__global__ __launch_bounds__(THREADS) void k_resgrad(
     const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
     const float4* __restrict__ Y2, const int32_t* __restrict__ item_pair, const int32_t* __restrict__ item_start,
     const int32_t* __restrict__ item_count, const int32_t* __restrict__ pair_i, const int32_t* __restrict__ pair_j,
     const double* __restrict__ R, const double* __restrict__ T, const double* __restrict__ Fc,
     const double* __restrict__ Rh, const double* __restrict__ Th, const double* __restrict__ Fh,
-    const double* __restrict__ cx, const double* __restrict__ cy, float inv_z, float delta,
-    double* __restrict__ part) {
-  __shared__ double s_blk[22];
-  __shared__ float s_red[kRgThreads / kWave][kPartStride];
+    const double* __restrict__ cx, const double* __restrict__ cy, const int32_t* __restrict__ pair_scene,
+    const float* __restrict__ inv_z_scene, float delta, double* __restrict__ part) {
+  __shared__ double s_blk[23];
+  __shared__ float s_red[THREADS / kWave][kPartStride];
   const int tid = threadIdx.x;
   const int item = blockIdx.x;
   const int n = item_pair[item];
@@ -65,10 +66,10 @@ __global__ __launch_bounds__(kRgThreads) void k_resgrad(
   const int cnt = item_count[item];
   const int nvec = (cnt + kVec - 1) / kVec;
 
-  float4 qa[kRgSteps], qb[kRgSteps], qc[kRgSteps], qd[kRgSteps];
+  float4 qa[STEPS], qb[STEPS], qc[STEPS], qd[STEPS];
 #pragma unroll
-  for (int s = 0; s < kRgSteps; ++s) {
-    const int v = s * kRgThreads + tid;
+  for (int s = 0; s < STEPS; ++s) {
+    const int v = s * THREADS + tid;
     if (v < nvec) {
       qa[s] = X1[v0 + v];
       qb[s] = Y1[v0 + v];
@@ -93,6 +94,7 @@ __global__ __launch_bounds__(kRgThreads) void k_resgrad(
       s_blk[19] = cy[i];
       s_blk[20] = cx[j];
       s_blk[21] = cy[j];
+      s_blk[22] = inv_z_scene[pair_scene[n]];
     }
   }
   __syncthreads();
@@ -106,33 +108,36 @@ __global__ __launch_bounds__(kRgThreads) void k_resgrad(
   const float cyi = (float)readfirstlane_f64(s_blk[19]);
   const float cxj = (float)readfirstlane_f64(s_blk[20]);
   const float cyj = (float)readfirstlane_f64(s_blk[21]);
+  const float inv_z = (float)readfirstlane_f64(s_blk[22]);
 
   float acc[kPartStride];
 #pragma unroll
   for (int k = 0; k < kPartStride; ++k) acc[k] = 0.f;
 #pragma unroll
-  for (int s = 0; s < kRgSteps; ++s) {
+  for (int s = 0; s < STEPS; ++s) {
 #pragma unroll
     for (int e = 0; e < kVec; ++e) {
-      const int local = (s * kRgThreads + tid) * kVec + e;
+      const int local = (s * THREADS + tid) * kVec + e;
       const float x1 = v4(qa[s], e), y1 = v4(qb[s], e), x2 = v4(qc[s], e), y2 = v4(qd[s], e);
       const double eps = eval_eps(F, x1, y1, x2, y2);
       const double eph = eval_eps(Fhat, x1, y1, x2, y2);
       const float ef = (float)eps;
       const float w = fmaxf(fabsf((float)eph), delta);
       const float c = (local < cnt) ? inv_z * __builtin_amdgcn_rcpf(w) : 0.f;
-      const float k2 = 2.f * c * ef;
-      const float x1c = x1 - cxi, y1c = y1 - cyi, x2c = x2 - cxj, y2c = y2 - cyj;
-      const float kx = k2 * x2c, ky = k2 * y2c;
-      acc[0] = fmaf(kx, x1c, acc[0]);
-      acc[1] = fmaf(kx, y1c, acc[1]);
-      acc[2] += kx;
-      acc[3] = fmaf(ky, x1c, acc[3]);
-      acc[4] = fmaf(ky, y1c, acc[4]);
-      acc[5] += ky;
-      acc[6] = fmaf(k2, x1c, acc[6]);
-      acc[7] = fmaf(k2, y1c, acc[7]);
-      acc[8] += k2;
+      if (!LOSS_ONLY) {
+        const float k2 = 2.f * c * ef;
+        const float x1c = x1 - cxi, y1c = y1 - cyi, x2c = x2 - cxj, y2c = y2 - cyj;
+        const float kx = k2 * x2c, ky = k2 * y2c;
+        acc[0] = fmaf(kx, x1c, acc[0]);
+        acc[1] = fmaf(kx, y1c, acc[1]);
+        acc[2] += kx;
+        acc[3] = fmaf(ky, x1c, acc[3]);
+        acc[4] = fmaf(ky, y1c, acc[4]);
+        acc[5] += ky;
+        acc[6] = fmaf(k2, x1c, acc[6]);
+        acc[7] = fmaf(k2, y1c, acc[7]);
+        acc[8] += k2;
+      }
       acc[9] = fmaf(c * ef, ef, acc[9]);
     }
   }
@@ -146,20 +151,21 @@ __global__ __launch_bounds__(kRgThreads) void k_resgrad(
   if (tid < kPartStride) {
     double sum = 0.0;
 #pragma unroll
-    for (int w = 0; w < kRgThreads / kWave; ++w) sum += (double)s_red[w][tid];
+    for (int w = 0; w < THREADS / kWave; ++w) sum += (double)s_red[w][tid];
     part[(int64_t)item * kPartStride + tid] = sum;
   }
 }
 
 // Round start, pass 1: how many matches of each item survive the filter
 // |eps_hat| < tau (strict; Method > Epipolar Adjustment, outlier filtering).
-__global__ __launch_bounds__(kRgThreads) void k_filter_count(
+__global__ __launch_bounds__(kFilterThreads) void k_filter_count(
     const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
     const float4* __restrict__ Y2, const int32_t* __restrict__ item_pair, const int32_t* __restrict__ item_start,
     const int32_t* __restrict__ item_count, const int32_t* __restrict__ pair_i, const int32_t* __restrict__ pair_j,
     const double* __restrict__ Rh, const double* __restrict__ Th, const double* __restrict__ Fh,
-    const double* __restrict__ cx, const double* __restrict__ cy, double tau, int32_t* __restrict__ keep) {
-  __shared__ double s_blk[9];
+    const double* __restrict__ cx, const double* __restrict__ cy, const int32_t* __restrict__ pair_scene,
+    const double* __restrict__ tau_scene, int32_t* __restrict__ keep) {
+  __shared__ double s_blk[10];
   __shared__ int s_cnt;
   const int tid = threadIdx.x, item = blockIdx.x;
   const int n = item_pair[item];
@@ -171,14 +177,16 @@ __global__ __launch_bounds__(kRgThreads) void k_filter_count(
     pose_block(pair_i[n], pair_j[n], Rh, Th, Fh, cx, cy, Fhat);
 #pragma unroll
     for (int k = 0; k < 9; ++k) s_blk[k] = Fhat[k];
+    s_blk[9] = tau_scene[pair_scene[n]];
     s_cnt = 0;
   }
   __syncthreads();
   double Fhat[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Fhat[k] = s_blk[k];
+  const double tau = s_blk[9];
   int kept = 0;
-  for (int v = tid; v < nvec; v += kRgThreads) {
+  for (int v = tid; v < nvec; v += kFilterThreads) {
     const float4 a = X1[v0 + v], b = Y1[v0 + v], c = X2[v0 + v], d = Y2[v0 + v];
 #pragma unroll
     for (int e = 0; e < kVec; ++e) {
@@ -193,16 +201,17 @@ __global__ __launch_bounds__(kRgThreads) void k_filter_count(
 
 // Round start, pass 2: stable compaction of the surviving matches into the
 // other layout buffer.  base[item] is where the item's first survivor goes.
-__global__ __launch_bounds__(kRgThreads) void k_filter_scatter(
+__global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
     const float4* __restrict__ Y2, const int4* __restrict__ POS, const int32_t* __restrict__ item_pair,
     const int32_t* __restrict__ item_start, const int32_t* __restrict__ item_count,
     const int32_t* __restrict__ pair_i, const int32_t* __restrict__ pair_j, const double* __restrict__ Rh,
     const double* __restrict__ Th, const double* __restrict__ Fh, const double* __restrict__ cx,
-    const double* __restrict__ cy, double tau, const int32_t* __restrict__ base, float* __restrict__ ox1,
+    const double* __restrict__ cy, const int32_t* __restrict__ pair_scene, const double* __restrict__ tau_scene,
+    const int32_t* __restrict__ base, float* __restrict__ ox1,
     float* __restrict__ oy1, float* __restrict__ ox2, float* __restrict__ oy2, int32_t* __restrict__ opos) {
-  __shared__ double s_blk[9];
-  __shared__ int s_w[kRgThreads / kWave];
+  __shared__ double s_blk[10];
+  __shared__ int s_w[kFilterThreads / kWave];
   const int tid = threadIdx.x, item = blockIdx.x;
   const int n = item_pair[item];
   const int v0 = item_start[item] >> 2;
@@ -213,16 +222,18 @@ __global__ __launch_bounds__(kRgThreads) void k_filter_scatter(
     pose_block(pair_i[n], pair_j[n], Rh, Th, Fh, cx, cy, Fhat);
 #pragma unroll
     for (int k = 0; k < 9; ++k) s_blk[k] = Fhat[k];
+    s_blk[9] = tau_scene[pair_scene[n]];
   }
   __syncthreads();
   double Fhat[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Fhat[k] = s_blk[k];
+  const double tau = s_blk[9];
   int run = base[item];
   const int lane = tid & 63, wid = tid >> 6;
-  const int rounds = (nvec + kRgThreads - 1) / kRgThreads;
+  const int rounds = (nvec + kFilterThreads - 1) / kFilterThreads;
   for (int r = 0; r < rounds; ++r) {
-    const int v = r * kRgThreads + tid;
+    const int v = r * kFilterThreads + tid;
     float4 a = make_float4(0, 0, 0, 0), b = a, c = a, d = a;
     int4 p = make_int4(-1, -1, -1, -1);
     if (v < nvec) {
@@ -246,7 +257,7 @@ __global__ __launch_bounds__(kRgThreads) void k_filter_scatter(
     __syncthreads();
     int before = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < kRgThreads / kWave; ++w) {
+    for (int w = 0; w < kFilterThreads / kWave; ++w) {
       before += (w < wid) ? s_w[w] : 0;
       total += s_w[w];
     }
@@ -270,10 +281,48 @@ __global__ __launch_bounds__(kRgThreads) void k_filter_scatter(
 
 }  // namespace
 
+template <int THREADS, int STEPS, bool LOSS_ONLY>
+hipError_t launch_resgrad_t(fea_ctx* c, const double* R, const double* T, const double* F) {
+  const int b = c->cur;
+  k_resgrad<THREADS, STEPS, LOSS_ONLY><<<(unsigned)c->n_items, THREADS, 0, c->stream>>>(
+      c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(),
+      c->item_pair.as<int32_t>(), c->item_start.as<int32_t>(), c->item_count.as<int32_t>(),
+      c->d_pair_i.as<int32_t>(), c->d_pair_j.as<int32_t>(), R, T, F, c->Rh.as<double>(), c->Th.as<double>(),
+      c->Fh.as<double>(), c->d_cx.as<double>(), c->d_cy.as<double>(), c->d_pair_scene.as<int32_t>(),
+      c->d_inv_z.as<float>(), (float)c->opt.delta, c->part.as<double>());
+  return hipGetLastError();
+}
+
+template <bool LOSS_ONLY>
+hipError_t launch_resgrad_sel(fea_ctx* c, int cfg, const double* R, const double* T, const double* F) {
+  switch (cfg) {
+    case 0: return launch_resgrad_t<256, 4, LOSS_ONLY>(c, R, T, F);
+    case 1: return launch_resgrad_t<256, 2, LOSS_ONLY>(c, R, T, F);
+    case 2: return launch_resgrad_t<256, 1, LOSS_ONLY>(c, R, T, F);
+    case 3: return launch_resgrad_t<128, 8, LOSS_ONLY>(c, R, T, F);
+    case 4: return launch_resgrad_t<128, 4, LOSS_ONLY>(c, R, T, F);
+    case 5: return launch_resgrad_t<128, 2, LOSS_ONLY>(c, R, T, F);
+    case 6: return launch_resgrad_t<512, 2, LOSS_ONLY>(c, R, T, F);
+    case 7: return launch_resgrad_t<512, 4, LOSS_ONLY>(c, R, T, F);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Per-match kernel with tile shape `cfg` over the current items at poses
+// (R, T, F) (per camera, fp64), weights from the round snapshot.
+hipError_t launch_resgrad_at(fea_ctx* c, int cfg, const double* R, const double* T, const double* F,
+                             bool loss_only) {
+  if (c->n_items == 0) return hipSuccess;
+  return loss_only ? launch_resgrad_sel<true>(c, cfg, R, T, F) : launch_resgrad_sel<false>(c, cfg, R, T, F);
+}
+
+hipError_t launch_resgrad_cfg(fea_ctx* c, int cfg) {
+  return launch_resgrad_at(c, cfg, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
+                           c->Fc[c->pcur].as<double>(), false);
+}
+
 hipError_t launch_resgrad(fea_ctx* c) {
   if (c->n_items == 0) return hipSuccess;
-  const int b = c->cur;
-  const float inv_z = c->Z > 0 ? (float)(1.0 / (double)c->Z) : 0.f;
   hipEvent_t ev1 = nullptr;
   if (c->timing) {
     while (c->ev_pool.size() < c->ev_used + 2) {
@@ -287,38 +336,32 @@ hipError_t launch_resgrad(fea_ctx* c) {
     ev1 = c->ev_pool[c->ev_used + 1];
     c->ev_used += 2;
   }
-  k_resgrad<<<(unsigned)c->n_items, kRgThreads, 0, c->stream>>>(
-      c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(),
-      c->item_pair.as<int32_t>(), c->item_start.as<int32_t>(), c->item_count.as<int32_t>(),
-      c->d_pair_i.as<int32_t>(), c->d_pair_j.as<int32_t>(), c->R[c->pcur].as<double>(),
-      c->T[c->pcur].as<double>(), c->Fc[c->pcur].as<double>(), c->Rh.as<double>(), c->Th.as<double>(),
-      c->Fh.as<double>(), c->d_cx.as<double>(), c->d_cy.as<double>(), inv_z, (float)c->opt.delta,
-      c->part.as<double>());
-  hipError_t err = hipGetLastError();
+  hipError_t err = launch_resgrad_cfg(c, c->tile_cfg);
   if (err == hipSuccess && ev1) err = hipEventRecord(ev1, c->stream);
   return err;
 }
 
-hipError_t launch_filter_count(fea_ctx* c, double tau) {
+hipError_t launch_filter_count(fea_ctx* c) {
   if (c->n_items == 0) return hipSuccess;
   const int b = c->cur;
-  k_filter_count<<<(unsigned)c->n_items, kRgThreads, 0, c->stream>>>(
+  k_filter_count<<<(unsigned)c->n_items, kFilterThreads, 0, c->stream>>>(
       c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(),
       c->item_pair.as<int32_t>(), c->item_start.as<int32_t>(), c->item_count.as<int32_t>(),
       c->d_pair_i.as<int32_t>(), c->d_pair_j.as<int32_t>(), c->Rh.as<double>(), c->Th.as<double>(),
-      c->Fh.as<double>(), c->d_cx.as<double>(), c->d_cy.as<double>(), tau, c->item_keep.as<int32_t>());
+      c->Fh.as<double>(), c->d_cx.as<double>(), c->d_cy.as<double>(), c->d_pair_scene.as<int32_t>(),
+      c->d_tau.as<double>(), c->item_keep.as<int32_t>());
   return hipGetLastError();
 }
 
-hipError_t launch_filter_scatter(fea_ctx* c, double tau, int dst) {
+hipError_t launch_filter_scatter(fea_ctx* c, int dst) {
   if (c->n_items == 0) return hipSuccess;
   const int b = c->cur;
-  k_filter_scatter<<<(unsigned)c->n_items, kRgThreads, 0, c->stream>>>(
+  k_filter_scatter<<<(unsigned)c->n_items, kFilterThreads, 0, c->stream>>>(
       c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(),
       c->lpos[b].as<int4>(), c->item_pair.as<int32_t>(), c->item_start.as<int32_t>(),
       c->item_count.as<int32_t>(), c->d_pair_i.as<int32_t>(), c->d_pair_j.as<int32_t>(), c->Rh.as<double>(),
-      c->Th.as<double>(), c->Fh.as<double>(), c->d_cx.as<double>(), c->d_cy.as<double>(), tau,
-      c->item_base.as<int32_t>(), c->lay[dst][0].as<float>(), c->lay[dst][1].as<float>(),
+      c->Th.as<double>(), c->Fh.as<double>(), c->d_cx.as<double>(), c->d_cy.as<double>(),
+      c->d_pair_scene.as<int32_t>(), c->d_tau.as<double>(), c->item_base.as<int32_t>(), c->lay[dst][0].as<float>(), c->lay[dst][1].as<float>(),
       c->lay[dst][2].as<float>(), c->lay[dst][3].as<float>(), c->lpos[dst].as<int32_t>());
   return hipGetLastError();
 }

@@ -29,7 +29,9 @@ class fea_options(C.Structure):
                 ("beta2", C.c_double), ("adam_eps", C.c_double),
                 ("optimize_focal", C.c_int32), ("gauge_normalize", C.c_int32),
                 ("log_every", C.c_int32), ("max_log", C.c_int32),
-                ("reserved", C.c_int32 * 8)]
+                ("lr_decay", C.c_double), ("reset_moments", C.c_int32),
+                ("tile_matches", C.c_int32), ("use_graphs", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class fea_report(C.Structure):
@@ -43,7 +45,9 @@ class fea_info(C.Structure):
                 ("n_pairs", C.c_int64), ("n_retained", C.c_int64), ("n_items", C.c_int64),
                 ("layout_matches", C.c_int64), ("round", C.c_int32), ("step", C.c_int32),
                 ("gauge_center", C.c_double * 3), ("gauge_scale", C.c_double),
-                ("tau", C.c_double), ("reserved", C.c_int32 * 8)]
+                ("tau", C.c_double), ("tile_matches", C.c_int32),
+                ("tile_threads", C.c_int32), ("n_scenes", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class FeaError(RuntimeError):
@@ -63,6 +67,8 @@ _SIGNATURES = {
     "fea_last_error": ([_P], C.c_char_p),
     "fea_set_options": ([_P, _P], C.c_int),
     "fea_load_intrinsics": ([_P, C.c_int32, _P, _P, _P, _P], C.c_int),
+    "fea_set_scenes": ([_P, C.c_int32, _P], C.c_int),
+    "fea_get_scene_stats": ([_P, _P, _P, _P, _P], C.c_int),
     "fea_load_matches": ([_P, C.c_int64, _P, _P, _P, _P, _P, _P], C.c_int),
     "fea_load_matches_device": ([_P, C.c_int64, _P, _P, _P, _P, _P, _P], C.c_int),
     "fea_init_poses": ([_P, _P, _P], C.c_int),
@@ -70,6 +76,9 @@ _SIGNATURES = {
     "fea_begin_round": ([_P, C.c_double], C.c_int),
     "fea_residual_grad": ([_P, _P, _P, _P, _P], C.c_int),
     "fea_step": ([_P, C.c_int32], C.c_int),
+    "fea_get_params_dev": ([_P, _P, _P, _P], C.c_int),
+    "fea_loss_dev": ([_P, _P, _P, _P, _P], C.c_int),
+    "fea_adjoint_dev": ([_P, _P, _P, _P, _P, _P, _P, _P], C.c_int),
     "fea_epipolar_adjust": ([_P, _P], C.c_int),
     "fea_get_poses": ([_P, _P, _P, _P], C.c_int),
     "fea_get_segments": ([_P, _P, _P, _P, _P], C.c_int),
@@ -78,6 +87,7 @@ _SIGNATURES = {
     "fea_synchronize": ([_P], C.c_int),
     "fea_get_rotation_log": ([_P, _P, _P], C.c_int),
     "fea_set_kernel_timing": ([_P, C.c_int32], C.c_int),
+    "fea_hbm_probe": ([C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
     "fea_get_kernel_timing": ([_P, _P, _P], C.c_int),
 }
 
@@ -100,6 +110,16 @@ def lib():
 
 def exported_symbols():
     return list(_SIGNATURES)
+
+
+def hbm_probe(device=0, nbytes=1 << 30, reps=5):
+    """(read GB/s, copy GB/s) of plain streaming kernels on `device`."""
+    r = C.c_double(0.0)
+    w = C.c_double(0.0)
+    rc = lib().fea_hbm_probe(int(device), int(nbytes), int(reps), C.byref(r), C.byref(w))
+    if rc != FEA_OK:
+        raise FeaError(rc, lib().fea_status_string(rc).decode())
+    return r.value, w.value
 
 
 def default_options(**kw) -> fea_options:
@@ -168,6 +188,20 @@ class Context:
         self._check(lib().fea_load_intrinsics(self._h, len(f), pf, pcx, pcy, pg))
         self.n_cams = len(f)
 
+    def set_scenes(self, cam_scene):
+        cam_scene, p = _host(cam_scene, np.int32)
+        self._check(lib().fea_set_scenes(self._h, int(cam_scene.max()) + 1, p))
+
+    def scene_stats(self):
+        S = self.info()["n_scenes"]
+        loss = np.zeros(S)
+        ret = np.zeros(S, np.int64)
+        gc = np.zeros((S, 3))
+        gs = np.zeros(S)
+        self._check(lib().fea_get_scene_stats(self._h, loss.ctypes.data_as(_P), ret.ctypes.data_as(_P),
+                                              gc.ctypes.data_as(_P), gs.ctypes.data_as(_P)))
+        return dict(loss=loss, retained=ret, gauge_center=gc, gauge_scale=gs)
+
     def load_matches(self, x1, y1, x2, y2, cam1, cam2):
         if _is_torch(x1) and x1.is_cuda:
             import torch
@@ -213,6 +247,32 @@ class Context:
                                             C.c_void_p(gf.data_ptr())))
         self.synchronize()
         return loss, gR, gt, gf
+
+    # -- parameters as torch device tensors (autograd support) --
+    def _dev(self, a):
+        return C.c_void_p(a.data_ptr()) if a is not None else None
+
+    def get_params(self):
+        """(a6 [N,6], t [N,3], logf [G]) float64 torch tensors on the GPU."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        inf = self.info()
+        a6 = torch.empty(inf["n_cams"], 6, dtype=torch.float64, device=dev)
+        t = torch.empty(inf["n_cams"], 3, dtype=torch.float64, device=dev)
+        logf = torch.empty(inf["n_groups"], dtype=torch.float64, device=dev)
+        torch.cuda.current_stream().synchronize()
+        self._check(lib().fea_get_params_dev(self._h, self._dev(a6), self._dev(t), self._dev(logf)))
+        self.synchronize()
+        return a6, t, logf
+
+    def loss_dev(self, a6, t, logf, out):
+        self._check(lib().fea_loss_dev(self._h, self._dev(a6), self._dev(t), self._dev(logf),
+                                       self._dev(out)))
+
+    def adjoint_dev(self, a6, t, logf, gout, ga6, gt, glogf):
+        self._check(lib().fea_adjoint_dev(self._h, self._dev(a6), self._dev(t), self._dev(logf),
+                                          self._dev(gout), self._dev(ga6), self._dev(gt),
+                                          self._dev(glogf)))
 
     def step(self, n=1):
         self._check(lib().fea_step(self._h, int(n)))

@@ -388,3 +388,40 @@ def random_poses(rng, n_cams, radius=4.0):
     centers = rng.normal(size=(n_cams, 3)) * radius
     t = -np.einsum("nij,nj->ni", R, centers)
     return R, t
+
+
+def config4(n_scenes: int = 64, seed: int = 4000, total_matches: float = 120e6,
+            cams_range=(20, 1000), matches_range=(5e4, 1e7)) -> list:
+    """64 independent trajectory scenes of uneven size: camera counts drawn
+    log-uniformly in [20, 1000] and match counts log-uniformly in
+    [5e4, 1e7] (rescaled so that the batch holds about `total_matches`)."""
+    rng = np.random.default_rng(seed)
+    n_cams = np.round(np.exp(rng.uniform(np.log(cams_range[0]), np.log(cams_range[1]),
+                                         n_scenes))).astype(int)
+    m = np.exp(rng.uniform(np.log(matches_range[0]), np.log(matches_range[1]), n_scenes))
+    m = np.clip(m * total_matches / m.sum(), matches_range[0], matches_range[1])
+    scenes = []
+    for s in range(n_scenes):
+        n = int(n_cams[s])
+        knn = min(20, n - 1)
+        pts = int(np.clip(m[s] / 100, 2_000, 200_000))
+        scenes.append(trajectory_scene(n_cams=n, n_pts=pts, knn=knn, target_matches=int(m[s]),
+                                       seed=seed + s, name=f"batch{s:02d}",
+                                       calib_sample=min(50_000, pts)))
+    return scenes
+
+
+def concat_scenes(scenes: list):
+    """One multi-scene problem: cameras of scene s get ids offset by the
+    camera counts of the scenes before it.  Returns (arrays dict, cam_scene,
+    camera offsets)."""
+    offs = np.concatenate([[0], np.cumsum([s.n_cams for s in scenes])]).astype(np.int64)
+    cat = lambda name: np.concatenate([getattr(s, name) for s in scenes])
+    out = dict(x1=cat("x1"), y1=cat("y1"), x2=cat("x2"), y2=cat("y2"),
+               cam1=np.concatenate([s.cam1 + offs[k] for k, s in enumerate(scenes)]).astype(np.int32),
+               cam2=np.concatenate([s.cam2 + offs[k] for k, s in enumerate(scenes)]).astype(np.int32),
+               f_init=cat("f_init"), cx=np.concatenate([s.cx for s in scenes]),
+               cy=np.concatenate([s.cy for s in scenes]), R_init=cat("R_init"), t_init=cat("t_init"),
+               R_gt=cat("R_gt"))
+    cam_scene = np.concatenate([np.full(s.n_cams, k, np.int32) for k, s in enumerate(scenes)])
+    return out, cam_scene, offs

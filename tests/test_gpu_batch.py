@@ -1,0 +1,89 @@
+"""Batching row: several independent scenes in one context (one launch of
+each kernel for all of them) give the same result as solving each alone."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_18052_amd import fastea, metrics, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _scenes():
+    return [synth.sphere_scene(n_cams=12, n_pts=800, seed=31, name="a"),
+            synth.trajectory_scene(n_cams=40, n_pts=8000, knn=8, target_matches=150_000, seed=32,
+                                   name="b", calib_sample=8000),
+            synth.sphere_scene(n_cams=7, n_pts=3000, seed=33, p_det=0.8, name="c"),
+            synth.trajectory_scene(n_cams=25, n_pts=5000, knn=6, target_matches=60_000, seed=34,
+                                   name="d", calib_sample=5000)]
+
+
+def _opts():
+    return fastea.default_options(rounds=4, iters_per_round=15, tile_matches=2048)
+
+
+def _solo(sc):
+    ctx = fastea.Context(0, _opts())
+    ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+    ctx.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    rep = ctx.epipolar_adjust()
+    R, t, f = ctx.get_poses()
+    mask, _ = ctx.get_mask()
+    ctx.close()
+    return R, t, f, mask, rep
+
+
+def test_batched_equals_individual():
+    scenes = _scenes()
+    cat, cam_scene, offs = synth.concat_scenes(scenes)
+    ctx = fastea.Context(0, _opts())
+    ctx.load_intrinsics(cat["f_init"], cat["cx"], cat["cy"])
+    ctx.set_scenes(cam_scene)
+    ctx.load_matches(cat["x1"], cat["y1"], cat["x2"], cat["y2"], cat["cam1"], cat["cam2"])
+    ctx.init_poses(cat["R_init"], cat["t_init"])
+    ctx.epipolar_adjust()
+    R, t, f = ctx.get_poses()
+    mask, _ = ctx.get_mask()
+    stats = ctx.scene_stats()
+    assert ctx.info()["n_scenes"] == len(scenes)
+    ctx.close()
+    m0 = 0
+    for k, sc in enumerate(scenes):
+        Rs, ts, fs, ms, rep = _solo(sc)
+        sl = slice(offs[k], offs[k + 1])
+        np.testing.assert_allclose(R[sl], Rs, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(t[sl], ts, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(f[sl], fs, rtol=1e-12)
+        assert np.array_equal(mask[m0:m0 + sc.n_matches], ms)
+        assert stats["retained"][k] == rep["inliers"][-1]
+        m0 += sc.n_matches
+
+
+def test_batch_rejects_cross_scene_matches_and_groups():
+    scenes = _scenes()[:2]
+    cat, cam_scene, offs = synth.concat_scenes(scenes)
+    ctx = fastea.Context(0, _opts())
+    ctx.load_intrinsics(cat["f_init"], cat["cx"], cat["cy"])
+    ctx.set_scenes(cam_scene)
+    c2 = cat["cam2"].copy()
+    c2[0] = offs[1] if cat["cam1"][0] < offs[1] else 0
+    with pytest.raises(fastea.FeaError) as e:
+        ctx.load_matches(cat["x1"], cat["y1"], cat["x2"], cat["y2"], cat["cam1"], c2)
+    assert e.value.status == fastea.FEA_EINVAL
+    groups = np.arange(len(cam_scene), dtype=np.int32)
+    groups[offs[1]] = 0  # first camera of scene 1 shares scene 0's group
+    ctx.load_intrinsics(cat["f_init"], cat["cx"], cat["cy"], groups)
+    with pytest.raises(fastea.FeaError) as e:
+        ctx.set_scenes(cam_scene)
+    assert e.value.status == fastea.FEA_EINVAL
+    ctx.close()

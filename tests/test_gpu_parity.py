@@ -296,3 +296,30 @@ def test_epipolar_adjust_converges_config1():
     assert np.all(np.diff(rep["inliers"]) <= 0)
     # the retained sets agree up to matches within rounding of the threshold
     assert np.mean(mask != out["mask"]) < 1e-3
+
+
+# ------------------------------------------------------------- HIP graphs
+
+def test_graph_replay_matches_eager_launches():
+    """Steps issued as replays of a captured graph (10 steps per replay) give
+    bit-identical poses and rotation logs to eagerly launched steps, also with
+    eager work between replays and across a round change."""
+    sc = SCENES["sphere20_m60k"]
+    out = []
+    for graphs in (0, 1):
+        ctx = make_context(sc, gauge=1, use_graphs=graphs, tile_matches=2048, log_every=5,
+                           max_log=40)
+        ctx.init_poses(sc.R_init, sc.t_init)
+        ctx.begin_round(128.0)
+        ctx.step(25)
+        ctx.residual_grad()
+        ctx.step(20)
+        ctx.begin_round(64.0)
+        ctx.step(30)
+        R, t, f = ctx.get_poses()
+        log = ctx.get_rotation_log(40)
+        out.append((R, t, f, log))
+        ctx.close()
+    (R0, t0, f0, l0), (R1, t1, f1, l1) = out
+    assert np.array_equal(R0, R1) and np.array_equal(t0, t1) and np.array_equal(f0, f1)
+    assert len(l0) == len(l1) == 15 and np.array_equal(l0, l1)

@@ -402,9 +402,18 @@ def test_epipolar_adjust_shared_intrinsics(orc):
     out = orc.epipolar_adjust(pb, sc.R_init, sc.t_init, sc.f_init, intr_group=groups,
                               options=orc.default_options(rounds=2, iters_per_round=20))
     assert np.ptp(out["f"]) == 0.0
-    # the result is returned in the caller's frame: centres stay near truth's scale
+    # the result is returned in the caller's rotation frame (no alignment
+    # needed) and the relative geometry is close to truth; the global scale
+    # of the translations is a free direction of the objective
+    unaligned = metrics.geodesic_deg(out["R"], sc.R_gt).mean()
+    aligned = metrics.mean_rotation_error_deg(out["R"], sc.R_gt)
+    assert abs(unaligned - aligned) < 0.5
+    assert aligned < metrics.mean_rotation_error_deg(sc.R_init, sc.R_gt)
     c = -np.einsum("nji,nj->ni", out["R"], out["t"])
     c_gt = -np.einsum("nji,nj->ni", sc.R_gt, sc.t_gt)
-    ratio = np.linalg.norm(c - c.mean(0), axis=1).mean() / np.linalg.norm(
-        c_gt - c_gt.mean(0), axis=1).mean()
-    assert 0.8 < ratio < 1.25
+    d = (c[:, None] - c[None]).reshape(-1, 3)
+    d_gt = (c_gt[:, None] - c_gt[None]).reshape(-1, 3)
+    keep = np.linalg.norm(d_gt, axis=1) > 0
+    cosang = np.sum(d[keep] * d_gt[keep], 1) / (np.linalg.norm(d[keep], axis=1) *
+                                                 np.linalg.norm(d_gt[keep], axis=1))
+    assert np.median(np.degrees(np.arccos(np.clip(cosang, -1, 1)))) < 5.0
