@@ -153,6 +153,9 @@ def main():
     log(f"[bench] {args.steps} steps in {wall:.4f} s ({ms_step:.4f} ms/step); "
         f"k_resgrad {1e3 * k_avg_s:.4f} ms avg over {k_n} launches = {achieved:.1f} GB/s")
 
+    read_peak, copy_peak = fastea.hbm_probe(0, 1 << 30, 5)
+    log(f"[bench] HBM probe (1 GiB): read {read_peak:.0f} GB/s, copy {copy_peak:.0f} GB/s")
+
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -187,7 +190,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_resgrad", "kernel_ms": 1e3 * k_avg_s,
-                     "bytes_per_launch": BYTES_PER_MATCH * Z},
+                     "bytes_per_launch": BYTES_PER_MATCH * Z,
+                     "measured_read_peak": read_peak, "frac_of_measured_read_peak": achieved / read_peak,
+                     "tile": f"{info['tile_matches']} matches x {info['tile_threads']} threads"},
         "cpu_baseline": cpu,
         "solve": solve,
     }

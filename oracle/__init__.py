@@ -76,6 +76,11 @@ def lib():
                                              C.c_int32, P, P, P]
         _lib.orc_epipolar_adjust.restype = C.c_int
         _lib.orc_default_options.argtypes = [P]
+        _lib.orc_mlp_features.argtypes = [P] + [P] * 9 + [P]
+        _lib.orc_mlp_features.restype = C.c_int
+        _lib.orc_mlp_forward.argtypes = [C.c_int64, P, P, P]
+        _lib.orc_mlp_bce_grad.argtypes = [C.c_int64, P, P, P, P]
+        _lib.orc_mlp_bce_grad.restype = C.c_double
         _lib.orc_num_threads.restype = C.c_int
     return _lib
 
@@ -263,3 +268,50 @@ def epipolar_adjust(pb: OracleProblem, R0, t0, f0, intr_group=None, options=None
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+MLP_NFEAT = 8
+MLP_HIDDEN = 64
+MLP_NPARAM = 64 * 8 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def mlp_pack(W1, b1, W2, b2, w3, b3):
+    return np.concatenate([np.ravel(W1), np.ravel(b1), np.ravel(W2), np.ravel(b2), np.ravel(w3),
+                           np.ravel(b3)]).astype(np.float64)
+
+
+def mlp_unpack(p):
+    p = np.asarray(p)
+    o = 0
+    out = []
+    for shape in ((64, 8), (64,), (64, 64), (64,), (64,), (1,)):
+        k = int(np.prod(shape))
+        out.append(p[o:o + k].reshape(shape))
+        o += k
+    return out
+
+
+def mlp_features(pb: OracleProblem, snaps):
+    """snaps: [(R, t, f)] for rounds r, r-1, r-2 (3 entries)."""
+    args = []
+    for R, t, f in snaps:
+        args += [_f64(R), _f64(t), _f64(f)]
+    feat = np.zeros((max(pb.n_matches, 1), MLP_NFEAT))
+    if lib().orc_mlp_features(pb.ref, *[_p(a) for a in args], _p(feat)):
+        raise ValueError("oracle mlp_features failed")
+    return feat[:pb.n_matches]
+
+
+def mlp_forward(feat, params):
+    feat = _f64(feat)
+    params = _f64(params)
+    y = np.zeros(max(len(feat), 1))
+    lib().orc_mlp_forward(len(feat), _p(feat), _p(params), _p(y))
+    return y[:len(feat)]
+
+
+def mlp_bce_grad(feat, target, params):
+    feat, target, params = _f64(feat), _f64(target), _f64(params)
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().orc_mlp_bce_grad(len(feat), _p(feat), _p(target), _p(params), _p(g))
+    return loss, g

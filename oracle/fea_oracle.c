@@ -650,3 +650,121 @@ int orc_epipolar_adjust(const orc_problem *pb, const orc_options *opt, const dou
   free_segments(&s);
   return rc;
 }
+
+/* ---- learned inlier weights (see fea_oracle.h) ------------------------- */
+
+static double feature_residual(double e, double fbar) {
+  return log(1.0 + fabs(e) * fbar) / log(1.0 + 256.0);
+}
+
+int orc_mlp_features(const orc_problem *pb, const double *R0, const double *t0, const double *f0,
+                     const double *R1, const double *t1, const double *f1, const double *R2,
+                     const double *t2, const double *f2, double *feat) {
+  int64_t M = pb->n_matches;
+  int32_t N = pb->n_cams;
+  const double *Rs[3] = {R0, R1, R2}, *ts[3] = {t0, t1, t2}, *fs[3] = {f0, f1, f2};
+  double *eps = (double *)malloc(sizeof(double) * (size_t)(M > 0 ? M : 1));
+  if (!eps) return -1;
+  for (int k = 0; k < 3; ++k) {
+    if (orc_residuals(pb, Rs[k], ts[k], fs[k], eps)) {
+      free(eps);
+      return -1;
+    }
+    double fbar = median_of(fs[k], N);
+    for (int64_t m = 0; m < M; ++m) feat[ORC_MLP_NFEAT * m + k] = feature_residual(eps[m], fbar);
+  }
+  free(eps);
+  for (int64_t m = 0; m < M; ++m) {
+    int32_t c1 = pb->cam1[m], c2 = pb->cam2[m];
+    double *x = feat + ORC_MLP_NFEAT * m;
+    x[3] = (double)pb->x1[m] / pb->cx[c1] - 1.0;
+    x[4] = (double)pb->y1[m] / pb->cy[c1] - 1.0;
+    x[5] = (double)pb->x2[m] / pb->cx[c2] - 1.0;
+    x[6] = (double)pb->y2[m] / pb->cy[c2] - 1.0;
+    /* optical axis of camera c in world coordinates: third row of R_c */
+    const double *za = R0 + 9 * c1 + 6, *zb = R0 + 9 * c2 + 6;
+    double cosang = dot3(za, zb);
+    if (cosang > 1.0) cosang = 1.0;
+    if (cosang < -1.0) cosang = -1.0;
+    x[7] = acos(cosang) / (0.5 * 3.14159265358979323846);
+  }
+  return 0;
+}
+
+typedef struct {
+  const double *W1, *b1, *W2, *b2, *w3, *b3;
+} mlp_view;
+
+static mlp_view mlp_unpack(const double *p) {
+  mlp_view v;
+  v.W1 = p;
+  v.b1 = v.W1 + ORC_MLP_HIDDEN * ORC_MLP_NFEAT;
+  v.W2 = v.b1 + ORC_MLP_HIDDEN;
+  v.b2 = v.W2 + ORC_MLP_HIDDEN * ORC_MLP_HIDDEN;
+  v.w3 = v.b2 + ORC_MLP_HIDDEN;
+  v.b3 = v.w3 + ORC_MLP_HIDDEN;
+  return v;
+}
+
+/* One sample: hidden activations and output logit. */
+static double mlp_sample(const mlp_view *v, const double *x, double *h1, double *h2) {
+  for (int i = 0; i < ORC_MLP_HIDDEN; ++i) {
+    double z = v->b1[i];
+    for (int k = 0; k < ORC_MLP_NFEAT; ++k) z += v->W1[ORC_MLP_NFEAT * i + k] * x[k];
+    h1[i] = z > 0.0 ? z : 0.0;
+  }
+  for (int i = 0; i < ORC_MLP_HIDDEN; ++i) {
+    double z = v->b2[i];
+    for (int k = 0; k < ORC_MLP_HIDDEN; ++k) z += v->W2[ORC_MLP_HIDDEN * i + k] * h1[k];
+    h2[i] = z > 0.0 ? z : 0.0;
+  }
+  double z3 = v->b3[0];
+  for (int k = 0; k < ORC_MLP_HIDDEN; ++k) z3 += v->w3[k] * h2[k];
+  return z3;
+}
+
+static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
+
+void orc_mlp_forward(int64_t n, const double *feat, const double *params, double *y) {
+  mlp_view v = mlp_unpack(params);
+  double h1[ORC_MLP_HIDDEN], h2[ORC_MLP_HIDDEN];
+  for (int64_t m = 0; m < n; ++m) y[m] = sigmoid(mlp_sample(&v, feat + ORC_MLP_NFEAT * m, h1, h2));
+}
+
+double orc_mlp_bce_grad(int64_t n, const double *feat, const double *target, const double *params,
+                        double *grad) {
+  mlp_view v = mlp_unpack(params);
+  memset(grad, 0, sizeof(double) * ORC_MLP_NPARAM);
+  double *gW1 = grad, *gb1 = gW1 + ORC_MLP_HIDDEN * ORC_MLP_NFEAT, *gW2 = gb1 + ORC_MLP_HIDDEN;
+  double *gb2 = gW2 + ORC_MLP_HIDDEN * ORC_MLP_HIDDEN, *gw3 = gb2 + ORC_MLP_HIDDEN,
+         *gb3 = gw3 + ORC_MLP_HIDDEN;
+  double h1[ORC_MLP_HIDDEN], h2[ORC_MLP_HIDDEN], d2[ORC_MLP_HIDDEN], d1[ORC_MLP_HIDDEN];
+  double loss = 0.0;
+  for (int64_t m = 0; m < n; ++m) {
+    const double *x = feat + ORC_MLP_NFEAT * m;
+    double z3 = mlp_sample(&v, x, h1, h2);
+    double t = target[m];
+    /* BCE of sigmoid(z) written stably: max(z,0) - z t + log(1 + exp(-|z|)) */
+    loss += (z3 > 0 ? z3 : 0.0) - z3 * t + log1p(exp(-fabs(z3)));
+    double dz3 = (sigmoid(z3) - t) / (double)n;
+    gb3[0] += dz3;
+    for (int k = 0; k < ORC_MLP_HIDDEN; ++k) {
+      gw3[k] += dz3 * h2[k];
+      d2[k] = h2[k] > 0.0 ? dz3 * v.w3[k] : 0.0;
+    }
+    for (int i = 0; i < ORC_MLP_HIDDEN; ++i) {
+      gb2[i] += d2[i];
+      for (int k = 0; k < ORC_MLP_HIDDEN; ++k) gW2[ORC_MLP_HIDDEN * i + k] += d2[i] * h1[k];
+    }
+    for (int k = 0; k < ORC_MLP_HIDDEN; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < ORC_MLP_HIDDEN; ++i) s += v.W2[ORC_MLP_HIDDEN * i + k] * d2[i];
+      d1[k] = h1[k] > 0.0 ? s : 0.0;
+    }
+    for (int i = 0; i < ORC_MLP_HIDDEN; ++i) {
+      gb1[i] += d1[i];
+      for (int k = 0; k < ORC_MLP_NFEAT; ++k) gW1[ORC_MLP_NFEAT * i + k] += d1[i] * x[k];
+    }
+  }
+  return loss / (double)(n > 0 ? n : 1);
+}

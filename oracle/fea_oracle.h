@@ -133,6 +133,40 @@ int orc_epipolar_adjust(const orc_problem *pb, const orc_options *opt, const dou
                         int64_t *inliers, int32_t log_every, int32_t max_log, double *log_R,
                         int32_t *n_logged, uint8_t *mask_out);
 
+/* ---- learned inlier weights ---------------------------------------------
+ * A multilayer perceptron 8 -> 64 -> 64 -> 1 (ReLU, ReLU, sigmoid) maps the
+ * features of a match to a weight in (0, 1) that multiplies its IRLS weight.
+ * Parameters (row-major): W1 [64*8], b1 [64], W2 [64*64], b2 [64], w3 [64],
+ * b3 [1], packed in that order into one array of ORC_MLP_NPARAM doubles.
+ *
+ * Features of match m at round r (ORC_MLP_NFEAT = 8):
+ *   0..2  g(|eps_hat|) at the snapshots of rounds r, r-1, r-2 (the earliest
+ *         available snapshot repeats for r < 2), with
+ *         g(e) = log(1 + e * fbar) / log(1 + 256), fbar the median focal
+ *         length of the snapshot, i.e. the residual in pixel-equivalents,
+ *         log-compressed so 256 px maps to 1;
+ *   3..6  keypoints scaled to [-1, 1]: x1/cx1 - 1, y1/cy1 - 1, x2/cx2 - 1,
+ *         y2/cy2 - 1 (cx = W/2, cy = H/2 of each keypoint's camera);
+ *   7     angle between the optical axes of the two cameras at snapshot r,
+ *         divided by pi/2. */
+#define ORC_MLP_NFEAT 8
+#define ORC_MLP_HIDDEN 64
+#define ORC_MLP_NPARAM (64 * 8 + 64 + 64 * 64 + 64 + 64 + 1)
+
+/* Features of every match (input order) given the snapshot poses of the last
+ * three rounds (R0/t0/f0 = round r, R1.. = r-1, R2.. = r-2). */
+int orc_mlp_features(const orc_problem *pb, const double *R0, const double *t0, const double *f0,
+                     const double *R1, const double *t1, const double *f1, const double *R2,
+                     const double *t2, const double *f2, double *feat);
+
+/* Forward pass: y[m] = MLP(feat[m]) for n rows of ORC_MLP_NFEAT. */
+void orc_mlp_forward(int64_t n, const double *feat, const double *params, double *y);
+
+/* Mean binary cross-entropy against targets in [0, 1] and its gradient with
+ * respect to the packed parameters. */
+double orc_mlp_bce_grad(int64_t n, const double *feat, const double *target, const double *params,
+                        double *grad);
+
 /* Number of OpenMP threads the oracle would use (1 without OpenMP). */
 int orc_num_threads(void);
 
