@@ -69,6 +69,8 @@ def lib():
         _lib.orc_update_mask.restype = C.c_int64
         _lib.orc_loss_grad.argtypes = [P, P, P, P, P, P, P, P, C.c_double, P, P, P, P]
         _lib.orc_loss_grad.restype = C.c_int
+        _lib.orc_loss_grad_weighted.argtypes = [P, P, P, P, P, P, P, P, P, C.c_double, P, P, P, P]
+        _lib.orc_loss_grad_weighted.restype = C.c_int
         _lib.orc_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int64, C.c_double, C.c_double,
                                   C.c_double, C.c_double]
         _lib.orc_gauge_normalize.argtypes = [C.c_int32, P, P, C.c_int64, P, P, P]
@@ -200,8 +202,10 @@ def update_mask(pb: OracleProblem, Rh, th, fh, tau, mask):
 
 
 def loss_grad(pb: OracleProblem, R, t, f, Rh=None, th=None, fh=None, mask=None,
-              delta=1e-4):
-    """Loss and (dL/dR [N,3,3], dL/dt [N,3], dL/df [N]) at (R,t,f)."""
+              delta=1e-4, weights=None):
+    """Loss and (dL/dR [N,3,3], dL/dt [N,3], dL/df [N]) at (R,t,f); with
+    `weights` (one per match, input order) each match's IRLS factor is scaled
+    by its weight and Z is the sum of the retained matches' weights."""
     N = pb.n_cams
     R, t, f = _f64(R), _f64(t), _f64(f)
     Rh = R if Rh is None else _f64(Rh)
@@ -214,8 +218,16 @@ def loss_grad(pb: OracleProblem, R, t, f, Rh=None, th=None, fh=None, mask=None,
     gR = np.zeros(9 * N)
     gt = np.zeros(3 * N)
     gf = np.zeros(N)
-    rc = lib().orc_loss_grad(pb.ref, _p(R), _p(t), _p(f), _p(Rh), _p(th), _p(fh), _p(mask),
-                             float(delta), C.byref(loss), _p(gR), _p(gt), _p(gf))
+    if weights is None:
+        rc = lib().orc_loss_grad(pb.ref, _p(R), _p(t), _p(f), _p(Rh), _p(th), _p(fh), _p(mask),
+                                 float(delta), C.byref(loss), _p(gR), _p(gt), _p(gf))
+    else:
+        w = _f64(weights)
+        if w.shape != (pb.n_matches,):
+            raise ValueError("one weight per match")
+        rc = lib().orc_loss_grad_weighted(pb.ref, _p(R), _p(t), _p(f), _p(Rh), _p(th), _p(fh),
+                                          _p(mask), _p(w), float(delta), C.byref(loss), _p(gR),
+                                          _p(gt), _p(gf))
     if rc:
         raise ValueError(f"oracle loss_grad failed ({rc})")
     return loss.value, gR.reshape(N, 3, 3), gt.reshape(N, 3), gf

@@ -330,18 +330,24 @@ static void free_segments(seg_result *s) {
  * Per pair n: G_n = sum_m 2 c_m eps_m p2 p1^T (dL/dF), L_n = sum_m c_m eps_m^2;
  * then the chain rule through F = D_j E D_i, E = [u]x R_ij, u = t_ij/|t_ij|,
  * t_ij = t_j - R_ij t_i, R_ij = R_j R_i^T to the per-camera R, t and f. */
+/* With weight == NULL every retained match counts once and Z is their
+ * number; otherwise match m counts weight[m] and Z is the sum of the
+ * retained matches' weights (the learned inlier weight taking the place of
+ * the 0/1 mask, the IRLS factor kept). */
 static int loss_grad_seg(const orc_problem *pb, const seg_result *s, const double *R,
                          const double *t, const double *f, const double *Rh,
                          const double *th, const double *fh, const uint8_t *mask,
-                         double delta, double *loss, double *gR, double *gt, double *gf) {
+                         const double *weight, double delta, double *loss, double *gR,
+                         double *gt, double *gf) {
   int32_t N = pb->n_cams;
   memset(gR, 0, sizeof(double) * 9 * (size_t)N);
   memset(gt, 0, sizeof(double) * 3 * (size_t)N);
   memset(gf, 0, sizeof(double) * (size_t)N);
   *loss = 0.0;
-  int64_t Z = 0;
-  for (int64_t m = 0; m < pb->n_matches; ++m) Z += mask[m] ? 1 : 0;
-  if (Z == 0 || s->n_pairs == 0) return 0;
+  double Z = 0.0;
+  for (int64_t m = 0; m < pb->n_matches; ++m)
+    if (mask[m]) Z += weight ? weight[m] : 1.0;
+  if (!(Z > 0.0) || s->n_pairs == 0) return 0;
   int64_t P = s->n_pairs;
   double *G = (double *)calloc((size_t)P * 9, sizeof(double));
   double *L = (double *)calloc((size_t)P, sizeof(double));
@@ -367,7 +373,7 @@ static int loss_grad_seg(const orc_problem *pb, const seg_result *s, const doubl
       canonical_match(pb, m, &ci, &cj, &ax, &ay, &bx, &by);
       double e = match_residual(g.F, ax, ay, bx, by);
       double eh = match_residual(gh.F, ax, ay, bx, by);
-      double c = 1.0 / ((double)Z * fmax(fabs(eh), delta));
+      double c = (weight ? weight[m] : 1.0) / (Z * fmax(fabs(eh), delta));
       double p1[3] = {ax, ay, 1.0}, p2[3] = {bx, by, 1.0};
       for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) G[9 * n + a * 3 + b] += 2.0 * c * e * p2[a] * p1[b];
@@ -442,7 +448,25 @@ int orc_loss_grad(const orc_problem *pb, const double *R, const double *t, const
     free_segments(&s);
     return -1;
   }
-  int rc = loss_grad_seg(pb, &s, R, t, f, Rh, th, fh, mask, delta, loss, gR, gt, gf);
+  int rc = loss_grad_seg(pb, &s, R, t, f, Rh, th, fh, mask, NULL, delta, loss, gR, gt, gf);
+  free_segments(&s);
+  return rc;
+}
+
+int orc_loss_grad_weighted(const orc_problem *pb, const double *R, const double *t,
+                           const double *f, const double *Rh, const double *th,
+                           const double *fh, const uint8_t *mask, const double *weight,
+                           double delta, double *loss, double *gR, double *gt, double *gf) {
+  if (check_problem(pb)) return -1;
+  for (int64_t m = 0; m < pb->n_matches; ++m)
+    if (!(weight[m] >= 0.0)) return -3;
+  seg_result s;
+  memset(&s, 0, sizeof(s));
+  if (segment_problem(pb, &s)) {
+    free_segments(&s);
+    return -1;
+  }
+  int rc = loss_grad_seg(pb, &s, R, t, f, Rh, th, fh, mask, weight, delta, loss, gR, gt, gf);
   free_segments(&s);
   return rc;
 }
@@ -607,7 +631,7 @@ int orc_epipolar_adjust(const orc_problem *pb, const orc_options *opt, const dou
     const double lr_scale = pow(opt->lr_decay, (double)r);
     double loss = 0.0;
     for (int32_t k = 0; k < opt->iters_per_round; ++k) {
-      rc = loss_grad_seg(pb, &s, R, t, f, Rh, thh, fh, mask, opt->delta, &loss, gR, gt, gf);
+      rc = loss_grad_seg(pb, &s, R, t, f, Rh, thh, fh, mask, NULL, opt->delta, &loss, gR, gt, gf);
       if (rc) break;
       for (int32_t c = 0; c < N; ++c) orc_rot6d_backward(a6 + 6 * c, gR + 9 * c, ga6 + 6 * c);
       memset(glogf, 0, sizeof(double) * (size_t)G);
@@ -675,12 +699,25 @@ int orc_mlp_features(const orc_problem *pb, const double *R0, const double *t0, 
   }
   free(eps);
   for (int64_t m = 0; m < M; ++m) {
+    /* keypoints in the pair's own orientation: the camera with the lower
+     * index first, as the pair n = (i, j), i < j, is defined */
     int32_t c1 = pb->cam1[m], c2 = pb->cam2[m];
+    double u1 = pb->x1[m], v1 = pb->y1[m], u2 = pb->x2[m], v2 = pb->y2[m];
+    if (c1 > c2) {
+      int32_t tc = c1;
+      c1 = c2;
+      c2 = tc;
+      double tu = u1, tv = v1;
+      u1 = u2;
+      v1 = v2;
+      u2 = tu;
+      v2 = tv;
+    }
     double *x = feat + ORC_MLP_NFEAT * m;
-    x[3] = (double)pb->x1[m] / pb->cx[c1] - 1.0;
-    x[4] = (double)pb->y1[m] / pb->cy[c1] - 1.0;
-    x[5] = (double)pb->x2[m] / pb->cx[c2] - 1.0;
-    x[6] = (double)pb->y2[m] / pb->cy[c2] - 1.0;
+    x[3] = u1 / pb->cx[c1] - 1.0;
+    x[4] = v1 / pb->cy[c1] - 1.0;
+    x[5] = u2 / pb->cx[c2] - 1.0;
+    x[6] = v2 / pb->cy[c2] - 1.0;
     /* optical axis of camera c in world coordinates: third row of R_c */
     const double *za = R0 + 9 * c1 + 6, *zb = R0 + 9 * c2 + 6;
     double cosang = dot3(za, zb);

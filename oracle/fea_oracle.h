@@ -111,6 +111,15 @@ int orc_loss_grad(const orc_problem *pb, const double *R, const double *t, const
                   const double *Rh, const double *th, const double *fh, const uint8_t *mask,
                   double delta, double *loss, double *gR, double *gt, double *gf);
 
+/* As orc_loss_grad with a non-negative weight per match (input order): the
+ * IRLS factor of match m is weight[m] / (Z_w max(|eps_hat|, delta)) with Z_w
+ * the sum of the retained matches' weights -- the learned inlier weight in
+ * place of the 0/1 retained mask.  Returns -3 for a negative or NaN weight. */
+int orc_loss_grad_weighted(const orc_problem *pb, const double *R, const double *t,
+                           const double *f, const double *Rh, const double *th,
+                           const double *fh, const uint8_t *mask, const double *weight,
+                           double delta, double *loss, double *gR, double *gt, double *gf);
+
 /* One Adam step (Kingma & Ba, cited as the adaptive first-order optimiser)
  * on n parameters; step is the 1-based step index. */
 void orc_adam(int64_t n, double *p, double *m, double *v, const double *g, int64_t step,
@@ -154,7 +163,9 @@ int orc_epipolar_adjust(const orc_problem *pb, const orc_options *opt, const dou
 #define ORC_MLP_NPARAM (64 * 8 + 64 + 64 * 64 + 64 + 64 + 1)
 
 /* Features of every match (input order) given the snapshot poses of the last
- * three rounds (R0/t0/f0 = round r, R1.. = r-1, R2.. = r-2). */
+ * three rounds (R0/t0/f0 = round r, R1.. = r-1, R2.. = r-2).  Keypoint
+ * features follow the pair's orientation (lower camera index first), so a
+ * match and its swapped copy have the same features. */
 int orc_mlp_features(const orc_problem *pb, const double *R0, const double *t0, const double *f0,
                      const double *R1, const double *t1, const double *f1, const double *R2,
                      const double *t2, const double *f2, double *feat);

@@ -249,12 +249,12 @@ def test_mask_is_monotone_and_counts(orc):
 
 # ----------------------------------------------------------------- gradient
 
-def _fd_check(orc, pb, R, t, f, Rh, th, fh, mask, delta, rng, n_probe=12):
-    loss, gR, gt, gf = orc.loss_grad(pb, R, t, f, Rh, th, fh, mask, delta)
+def _fd_check(orc, pb, R, t, f, Rh, th, fh, mask, delta, rng, n_probe=12, weights=None):
+    loss, gR, gt, gf = orc.loss_grad(pb, R, t, f, Rh, th, fh, mask, delta, weights=weights)
     N = len(f)
 
     def L(R_, t_, f_):
-        return orc.loss_grad(pb, R_, t_, f_, Rh, th, fh, mask, delta)[0]
+        return orc.loss_grad(pb, R_, t_, f_, Rh, th, fh, mask, delta, weights=weights)[0]
 
     checks = []
     for _ in range(n_probe):
@@ -306,6 +306,45 @@ def test_gradient_fd_random_poses(orc):
     pb = _problem(orc, sc)
     _fd_check(orc, pb, R, t, sc.f_gt, R, t, sc.f_gt, np.ones(sc.n_matches, bool), 1e-4,
               rng, n_probe=30)
+
+
+def test_weighted_loss_special_cases(orc):
+    """Per-match weights (the learned inlier weight in place of the 0/1 mask):
+    a constant weight cancels in the normalisation; 0/1 weights are a mask;
+    at the snapshot the loss is the weighted mean of |eps|."""
+    sc = synth.tiny_scene(n_cams=5, n_pts=60, seed=17, sigma=1.0, outlier_frac=0.2)
+    pb = _problem(orc, sc)
+    rng = np.random.default_rng(8)
+    R, t, f = sc.R_init, sc.t_init, sc.f_init * 1.03
+    Rh, th, fh = sc.R_gt, sc.t_gt, sc.f_gt
+    mask = rng.random(sc.n_matches) < 0.85
+    ref = orc.loss_grad(pb, R, t, f, Rh, th, fh, mask, 1e-4)
+    got = orc.loss_grad(pb, R, t, f, Rh, th, fh, mask, 1e-4, weights=np.full(sc.n_matches, 0.37))
+    for a, b in zip(ref, got):
+        np.testing.assert_allclose(b, a, rtol=1e-12, atol=1e-300)
+    w01 = (rng.random(sc.n_matches) < 0.6).astype(float)
+    ref = orc.loss_grad(pb, R, t, f, Rh, th, fh, mask & (w01 > 0), 1e-4)
+    got = orc.loss_grad(pb, R, t, f, Rh, th, fh, mask, 1e-4, weights=w01)
+    for a, b in zip(ref, got):
+        np.testing.assert_allclose(b, a, rtol=1e-12, atol=1e-300)
+    w = rng.random(sc.n_matches)
+    eps = orc.residuals(pb, R, t, f)
+    delta = 1e-7
+    m2 = np.abs(eps) >= delta
+    loss = orc.loss_grad(pb, R, t, f, mask=m2, delta=delta, weights=w)[0]
+    np.testing.assert_allclose(loss, np.sum(w[m2] * np.abs(eps[m2])) / np.sum(w[m2]), rtol=1e-12)
+    with pytest.raises(ValueError):
+        orc.loss_grad(pb, R, t, f, weights=-w)
+
+
+def test_weighted_gradient_matches_central_differences(orc):
+    sc = synth.tiny_scene(n_cams=5, n_pts=50, seed=19, sigma=1.0, outlier_frac=0.2)
+    pb = _problem(orc, sc)
+    rng = np.random.default_rng(4)
+    mask = rng.random(sc.n_matches) < 0.9
+    w = rng.random(sc.n_matches)
+    _fd_check(orc, pb, sc.R_init, sc.t_init, sc.f_gt * 0.96, sc.R_gt, sc.t_gt, sc.f_gt,
+              mask, 1e-4, rng, n_probe=30, weights=w)
 
 
 def test_gauge_null_space_identities(orc):

@@ -100,7 +100,9 @@ def test_features_special_cases(orc):
     np.testing.assert_allclose(orc.mlp_features(q3, [(R, t, f)] * 3)[0, 3:7], 0.0, atol=0)
     q4 = orc.OracleProblem([640.0], [480.0], [640.0], [480.0], np.ones(1, np.int32),
                            np.zeros(1, np.int32), [320.0, 640.0], [240.0, 480.0])
-    np.testing.assert_allclose(orc.mlp_features(q4, [(R, t, f)] * 3)[0, 3:7], [0, 0, 1, 1], atol=0)
+    # a match given as (camera 1, camera 0) is read in the pair's orientation:
+    # the keypoint in camera 0 (640, 480 -> 1, 1) comes first
+    np.testing.assert_allclose(orc.mlp_features(q4, [(R, t, f)] * 3)[0, 3:7], [1, 1, 0, 0], atol=0)
     # rectified stereo with y2 - y1 = 256 px at f = 500: g = 1 exactly
     q2 = orc.OracleProblem([100.0], [100.0], [80.0], [356.0], np.zeros(1, np.int32),
                            np.ones(1, np.int32), [320.0, 320.0], [240.0, 240.0])
@@ -109,3 +111,22 @@ def test_features_special_cases(orc):
     Ry = synth.rotation_from_axis_angle(np.array([[0.0, 1.0, 0.0]]), np.array([np.pi / 2]))[0]
     R2 = np.stack([np.eye(3), Ry])
     assert abs(orc.mlp_features(q2, [(R2, t, f)] * 3)[0, 7] - 1.0) < 1e-12
+
+
+def test_features_invariant_to_match_orientation(orc):
+    """Swapping a match's cameras and keypoints leaves all 8 features (and the
+    residual) unchanged."""
+    sc = synth.tiny_scene(n_cams=6, n_pts=80, seed=7, sigma=1.0, outlier_frac=0.2)
+    pb = orc.OracleProblem.from_scene(sc)
+    rng = np.random.default_rng(2)
+    flip = rng.random(sc.n_matches) < 0.5
+    sw = lambda a, b: np.where(flip, b, a)
+    pb2 = orc.OracleProblem(sw(sc.x1, sc.x2), sw(sc.y1, sc.y2), sw(sc.x2, sc.x1), sw(sc.y2, sc.y1),
+                            sw(sc.cam1, sc.cam2).astype(np.int32),
+                            sw(sc.cam2, sc.cam1).astype(np.int32), sc.cx, sc.cy)
+    snaps = [(sc.R_init, sc.t_init, sc.f_init), (sc.R_gt, sc.t_gt, sc.f_gt),
+             (sc.R_init, sc.t_gt, sc.f_gt)]
+    a = orc.mlp_features(pb, snaps)
+    b = orc.mlp_features(pb2, snaps)
+    assert flip.any() and (~flip).any()
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-15)
