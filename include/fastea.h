@@ -82,7 +82,15 @@ typedef struct {
                               1024, 2048, 4096 or 8192; 0 = pick by timing the
                               candidates at the first round (0) */
   int32_t use_graphs;      /* 1: issue runs of steps as captured HIP graphs (1) */
-  int32_t reserved[5];     /* must be zero */
+  int32_t weight_mode;     /* 0: plain IRLS weights (default); 1: learned
+                              inlier weights (fea_set_mlp) judged by the plain
+                              objective each round, plain weights as fallback */
+  int32_t inner_loop;      /* 0: every step streams the retained matches
+                              (per-match residual and gradient, default);
+                              1: the weighted quadratic form of each pair,
+                              f^T W_n f with W_n summed over its matches once
+                              per round, so that a step costs O(pairs) */
+  int32_t reserved[3];     /* must be zero */
 } fea_options;
 
 /* What fea_epipolar_adjust did. */
@@ -93,7 +101,8 @@ typedef struct {
   double loss_per_round[64];     /* loss at the last step of each round */
   double ms_total;               /* wall time of the call, milliseconds */
   int32_t n_logged;              /* pose snapshots kept (log_every > 0) */
-  int32_t reserved[7];
+  int32_t fallbacks;             /* learned rounds rejected by the judge (all scenes) */
+  int32_t reserved[6];
 } fea_report;
 
 /* Sizes and state of a context. */
@@ -162,10 +171,11 @@ fea_status fea_load_intrinsics(fea_ctx *ctx, int32_t n_cams, const double *f,
 fea_status fea_set_scenes(fea_ctx *ctx, int32_t n_scenes, const int32_t *cam_scene);
 
 /* Per-scene state (host arrays [n_scenes], [n_scenes], [3*n_scenes],
- * [n_scenes]; any may be NULL): loss at the last evaluated step, retained
- * matches of the current round, and the applied gauge. */
+ * [n_scenes], [n_scenes]; any may be NULL): loss at the last evaluated step,
+ * retained matches of the current round, the applied gauge, and whether the
+ * scene still uses learned weights (0 once the judge fell back). */
 fea_status fea_get_scene_stats(fea_ctx *ctx, double *loss, int64_t *retained,
-                               double *gauge_center, double *gauge_scale);
+                               double *gauge_center, double *gauge_scale, int32_t *learned);
 
 /* Keypoint matches (Method > Epipolar Adjustment: point pairs Q_n of the
  * image pairs P).  Match m relates pixel (x1[m], y1[m]) of camera cam1[m] to
@@ -205,7 +215,8 @@ fea_status fea_set_poses(fea_ctx *ctx, const double *R, const double *t, const d
 fea_status fea_begin_round(fea_ctx *ctx, double tau_px);
 
 /* One pass of the residual, IRLS weight and gradient at the current poses,
- * with the current round's weights (no parameter update).  Outputs are
+ * with the current round's weights (no parameter update), by the inner loop
+ * the options select (per match, or the pairs' quadratic forms).  Outputs are
  * device arrays, caller-allocated, any of which may be NULL:
  *   loss_dev [1]; gR_dev [n_cams*9] dL/dR (R as an unconstrained 3x3);
  *   gt_dev [n_cams*3] dL/dt; gf_dev [n_cams] dL/df.
@@ -237,6 +248,51 @@ fea_status fea_adjoint_dev(fea_ctx *ctx, const double *a6_dev, const double *t_d
                            const double *logf_dev, const double *gout_dev, double *ga6_dev,
                            double *gt_dev, double *glogf_dev);
 
+/* ---- Learned inlier weights ------------------------------------------
+ * An MLP 8 -> 64 -> 64 -> 1 (ReLU, ReLU, sigmoid) maps each retained match's
+ * features to a weight in (0, 1) that multiplies its IRLS weight; the
+ * network runs once per round (matrix cores, bf16 activations).  Features:
+ * the match's residual at the last three round snapshots as
+ * log(1 + |eps| * median f) / log(257), its keypoints scaled to [-1, 1] by
+ * each camera's principal point (x/cx - 1, ...; the keypoint in the camera
+ * with the lower index first), and the angle between the
+ * pair's optical axes over pi/2.  Parameters: FEA_MLP_PARAMS floats packed
+ * as W1 [64*8], b1 [64], W2 [64*64], b2 [64], w3 [64], b3 (row-major).
+ * With options.weight_mode = 1, fea_epipolar_adjust uses the learned weights
+ * and judges every round with the plain objective: a scene whose plain
+ * objective did not decrease over the round is restored to the round's
+ * snapshot and continues with plain weights. */
+#define FEA_MLP_FEATURES 8
+#define FEA_MLP_PARAMS 4801
+
+/* Loads the network parameters (host array [FEA_MLP_PARAMS]). */
+fea_status fea_set_mlp(fea_ctx *ctx, const float *params);
+
+/* Features of the current round's layout (after fea_begin_round):
+ * feat_dev [layout_matches*8] and slot_pos_dev [layout_matches] (device,
+ * caller-allocated; fea_info.layout_matches), slot_pos = sorted position of
+ * the match in each layout slot or -1 for alignment padding. */
+fea_status fea_mlp_features_dev(fea_ctx *ctx, float *feat_dev, int32_t *slot_pos_dev);
+
+/* Learned weight of every match in input order for the current round (host
+ * [n_matches]; 0 for matches the filter dropped; 1 when not learned). */
+fea_status fea_get_learned_weights(fea_ctx *ctx, float *w);
+
+/* Trains the network on GPU `device` with the library's forward/backward
+ * kernels: mean binary cross-entropy of n samples (feat_dev [n*8],
+ * target_dev [n] in [0,1], device arrays), Adam (beta 0.9/0.999, eps 1e-8,
+ * learning rate lr), `epochs` passes in batches of `batch` samples in an
+ * order drawn from `seed`; params_dev [FEA_MLP_PARAMS] is updated in place;
+ * loss_per_epoch (host [epochs], nullable) receives the mean loss. */
+fea_status fea_mlp_train(int32_t device, const float *feat_dev, const float *target_dev, int64_t n,
+                         int32_t epochs, int32_t batch, double lr, uint64_t seed, float *params_dev,
+                         double *loss_per_epoch);
+
+/* Mean BCE loss and its gradient over samples [0, n) (device arrays;
+ * grad_dev [FEA_MLP_PARAMS]); loss written to *loss (host). */
+fea_status fea_mlp_grad(int32_t device, const float *feat_dev, const float *target_dev, int64_t n,
+                        const float *params_dev, float *grad_dev, double *loss);
+
 /* n_steps Adam steps of the current round (each: residual, weight, gradient,
  * per-camera chain rule and update). */
 fea_status fea_step(fea_ctx *ctx, int32_t n_steps);
@@ -261,6 +317,25 @@ fea_status fea_get_segments(fea_ctx *ctx, int32_t *perm, uint8_t *swapped,
 /* Which matches the current round retains (host array [n_matches], indexed
  * by input order; 1 = retained).  n_retained may be NULL. */
 fea_status fea_get_mask(fea_ctx *ctx, uint8_t *mask, int64_t *n_retained);
+
+/* ---- Checkpoint / resume ----------------------------------------------
+ * The solver state between calls, as an opaque byte string: parameters
+ * (6D rotations, translations, log f), Adam moments and step counts, the
+ * round snapshot and the two before it (learned features), round and step
+ * indices, per-scene thresholds, gauges and weighting modes, the options,
+ * and the retained matches of the round as one bit per sorted position.
+ * fea_get_state: with buf == NULL writes the required size to *len; else
+ * *len must be at least that size (FEA_EINVAL otherwise, with the size
+ * written back) and the state is copied to the caller's host buffer.
+ * Needs initialised poses (FEA_ESTATE).
+ * fea_set_state: restores a state into a context that loaded the same
+ * intrinsics groups, scenes and matches in the same order (checked by sizes
+ * and a hash of the pair table, segments and sorted order: FEA_EINVAL
+ * otherwise); for a state taken on learned weights the same network must be
+ * loaded first (FEA_ESTATE).  The next steps then reproduce bit for bit the
+ * steps the saved context would have taken.  The buffer is only read. */
+fea_status fea_get_state(fea_ctx *ctx, void *buf, size_t *len);
+fea_status fea_set_state(fea_ctx *ctx, const void *buf, size_t len);
 
 /* Sizes and state. */
 fea_status fea_get_info(fea_ctx *ctx, fea_info *out);

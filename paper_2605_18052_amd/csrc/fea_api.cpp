@@ -83,12 +83,14 @@ std::vector<DBuf*> all_bufs(fea_ctx* c) {
     for (int a = 0; a < 4; ++a) v.push_back(&c->lay[b][a]);
     v.push_back(&c->lpos[b]);
   }
-  DBuf* one[] = {&c->perm, &c->swp, &c->item_pair, &c->item_start, &c->item_count, &c->pair_item_off,
+  DBuf* one[] = {&c->perm, &c->swp, &c->item_pair, &c->item_start, &c->item_count, &c->item_rec, &c->pair_item_off,
                  &c->item_keep, &c->item_base, &c->part, &c->d_pair_i, &c->d_pair_j, &c->d_cam_off,
                  &c->d_cam_ent, &c->d_group, &c->d_grp_off, &c->d_grp_cams, &c->d_cx, &c->d_cy, &c->a6,
                  &c->tp, &c->logf, &c->m_a6, &c->v_a6, &c->m_t, &c->v_t, &c->m_f, &c->v_f, &c->R[0],
                  &c->R[1], &c->T[0], &c->T[1], &c->Fc[0], &c->Fc[1], &c->Rh, &c->Th, &c->Fh, &c->gR,
-                 &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag, &c->Re, &c->Te, &c->Fe, &c->d_pair_scene, &c->d_inv_z, &c->d_tau, &c->counters};
+                 &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag, &c->Re, &c->Te, &c->Fe, &c->d_pair_scene, &c->d_inv_z, &c->d_tau, &c->ptab, &c->qpart, &c->qW, &c->stab, &c->counters,
+                 &c->Rh1, &c->Th1, &c->Fh1, &c->Rh2, &c->Th2, &c->Fh2, &c->d_fbar, &c->mlp, &c->wlay,
+                 &c->item_wsum, &c->d_inv_zw, &c->d_scene_mode, &c->a6h, &c->tph, &c->logfh, &c->restore_flag};
   for (DBuf* b : one) v.push_back(b);
   return v;
 }
@@ -113,7 +115,9 @@ bool options_valid(const fea_options* o, std::string* why) {
       o->tile_matches != 8192)
     return bad("tile_matches must be 0, 1024, 2048, 4096 or 8192");
   if (o->use_graphs != 0 && o->use_graphs != 1) return bad("use_graphs must be 0 or 1");
-  for (int k = 0; k < 5; ++k)
+  if (o->weight_mode != 0 && o->weight_mode != 1) return bad("weight_mode must be 0 or 1");
+  if (o->inner_loop != 0 && o->inner_loop != 1) return bad("inner_loop must be 0 or 1");
+  for (int k = 0; k < 3; ++k)
     if (o->reserved[k] != 0) return bad("reserved option fields must be zero");
   return true;
 }
@@ -144,6 +148,12 @@ hipError_t build_items(fea_ctx* c) {
   }
   c->h_pair_item_off[c->P] = (int32_t)c->h_item_pair.size();
   c->n_items = (int64_t)c->h_item_pair.size();
+  c->h_item_rec.assign(4 * c->n_items, 0);
+  for (int64_t it = 0; it < c->n_items; ++it) {
+    c->h_item_rec[4 * it] = c->h_item_pair[it];
+    c->h_item_rec[4 * it + 1] = c->h_item_start[it];
+    c->h_item_rec[4 * it + 2] = c->h_item_count[it];
+  }
   c->h_cam_ent4.assign(4 * 2 * c->P, 0);
   for (size_t e = 0; e < c->cam_ent.size(); ++e) {
     const int32_t code = c->cam_ent[e];
@@ -158,12 +168,29 @@ hipError_t build_items(fea_ctx* c) {
   if ((e = upload(c, c->item_pair, c->h_item_pair.data(), c->n_items)) != hipSuccess) return e;
   if ((e = upload(c, c->item_start, c->h_item_start.data(), c->n_items)) != hipSuccess) return e;
   if ((e = upload(c, c->item_count, c->h_item_count.data(), c->n_items)) != hipSuccess) return e;
+  if ((e = upload(c, c->item_rec, c->h_item_rec.data(), c->h_item_rec.size())) != hipSuccess) return e;
   if ((e = upload(c, c->pair_item_off, c->h_pair_item_off.data(), c->P + 1)) != hipSuccess) return e;
   if ((e = upload(c, c->d_cam_ent, c->h_cam_ent4.data(), c->h_cam_ent4.size())) != hipSuccess) return e;
+  if ((e = dalloc(c->qpart, std::max<int64_t>(c->n_items, 1) * 45 * sizeof(double))) != hipSuccess) return e;
   if ((e = dalloc(c->part, std::max<int64_t>(c->n_items, 1) * fea::kPartStride * sizeof(double))) != hipSuccess)
     return e;
   if ((e = dalloc(c->item_keep, std::max<int64_t>(c->n_items, 1) * sizeof(int32_t))) != hipSuccess) return e;
+  if ((e = dalloc(c->item_wsum, std::max<int64_t>(c->n_items, 1) * sizeof(double))) != hipSuccess) return e;
   return dalloc(c->item_base, std::max<int64_t>(c->n_items, 1) * sizeof(int32_t));
+}
+
+// Per-scene device arrays sized by the number of scenes.
+hipError_t alloc_scene_arrays(fea_ctx* c) {
+  hipError_t e;
+  if ((e = dalloc(c->d_inv_z, (size_t)c->S * sizeof(float))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_inv_zw, (size_t)c->S * sizeof(float))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_scene_mode, (size_t)c->S * sizeof(int32_t))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_fbar, 3 * (size_t)c->S * sizeof(float))) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(c->d_inv_zw.p, 0, c->d_inv_zw.bytes, c->stream)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(c->d_scene_mode.p, 0, c->d_scene_mode.bytes, c->stream)) != hipSuccess) return e;
+  c->scene_mode.assign(c->S, 0);
+  c->scene_learned_ok.assign(c->S, 1);
+  return hipSuccess;
 }
 
 int tile_cfg_for(int32_t tile_matches) {
@@ -279,6 +306,10 @@ fea_status load_matches_common(fea_ctx* c, int64_t n, const float* x1, const flo
   }
   HIP_OR_FAIL(c, upload(c, c->d_pair_scene, c->pair_scene.data(), c->P));
   HIP_OR_FAIL(c, dalloc(c->d_tau, (size_t)c->S * sizeof(double)));
+  HIP_OR_FAIL(c, dalloc(c->ptab, (size_t)std::max<int64_t>(c->P, 1) * fea::kPairRow * sizeof(double)));
+  HIP_OR_FAIL(c, dalloc(c->qW, (size_t)std::max<int64_t>(c->P, 1) * 45 * sizeof(double)));
+  HIP_OR_FAIL(c, dalloc(c->stab, (size_t)std::max<int64_t>(c->P, 1) * 40 * sizeof(double)));
+  HIP_OR_FAIL(c, dalloc(c->wlay, std::max<int64_t>(c->layout_len, 4) * sizeof(uint16_t)));
   // camera -> incident (pair, side) entries, in pair order
   const int N = c->N;
   c->cam_off.assign(N + 1, 0);
@@ -328,8 +359,10 @@ void drop_graph(fea_ctx* c) {
 // Issues one step (per-match kernel, per-camera chain + Adam, shared-focal
 // update); all step bookkeeping the kernels need lives on the device.
 hipError_t issue_step(fea_ctx* c) {
-  hipError_t e = fea::launch_resgrad(c);
-  if (e == hipSuccess) e = fea::launch_camgrad(c, 1);
+  // quadratic form: the camera kernel evaluates each pair's form itself
+  const bool quad = c->opt.inner_loop == 1;
+  hipError_t e = quad ? hipSuccess : fea::launch_resgrad(c);
+  if (e == hipSuccess) e = fea::launch_camgrad(c, 1, quad);
   if (e == hipSuccess && !c->all_single) e = fea::launch_focal_update(c);
   c->pcur ^= 1;
   return e;
@@ -383,35 +416,30 @@ fea_status run_steps(fea_ctx* c, int32_t n_steps) {
 // Host -> device copy of the step counters: Adam count `t` and global count
 // `g` into the slots of the current parity.
 hipError_t set_counters(fea_ctx* c, int64_t t, int64_t g) {
-  long long h[4] = {0, 0, 0, 0};
-  h[c->pcur] = t;
-  h[2 + c->pcur] = g;
-  hipError_t e = hipMemcpyAsync(c->counters.p, h, sizeof(h), hipMemcpyHostToDevice, c->stream);
+  fea::StepCounters h;
+  std::memset(&h, 0, sizeof(h));
+  h.adam_t[c->pcur] = t;
+  h.global_t[c->pcur] = g;
+  h.b1t[c->pcur] = std::pow(c->opt.beta1, (double)t);
+  h.b2t[c->pcur] = std::pow(c->opt.beta2, (double)t);
+  hipError_t e = hipMemcpyAsync(c->counters.p, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(c->stream);
 }
 
-fea_status begin_round(fea_ctx* c, double tau_px) {
-  const size_t N = c->N;
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->Rh.p, c->R[c->pcur].p, 9 * N * sizeof(double), hipMemcpyDeviceToDevice,
-                                c->stream));
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->Th.p, c->T[c->pcur].p, 3 * N * sizeof(double), hipMemcpyDeviceToDevice,
-                                c->stream));
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->Fh.p, c->Fc[c->pcur].p, N * sizeof(double), hipMemcpyDeviceToDevice,
-                                c->stream));
-  std::vector<double> fnow;
-  HIP_OR_FAIL(c, download(c, fnow, c->Fc[c->pcur], N));
-  // threshold per scene: tau_px over the scene's median focal length
-  std::vector<std::vector<double>> fs(c->S);
-  for (size_t i = 0; i < N; ++i) fs[c->cam_scene[i]].push_back(fnow[i]);
-  c->taus.assign(c->S, std::numeric_limits<double>::infinity());
-  if (!std::isinf(tau_px))
-    for (int sc = 0; sc < c->S; ++sc) c->taus[sc] = tau_px / (fs[sc].empty() ? 1.0 : median(fs[sc]));
-  HIP_OR_FAIL(c, upload(c, c->d_tau, c->taus.data(), c->S));
-  // pass 1: survivors per item
-  HIP_OR_FAIL(c, fea::launch_filter_count(c));
+hipError_t d2d(fea_ctx* c, DBuf& dst, const DBuf& src, size_t bytes) {
+  return hipMemcpyAsync(dst.p, src.p, bytes, hipMemcpyDeviceToDevice, c->stream);
+}
+
+// Stable compaction of the live layout into the other filtered buffer: the
+// matches that pass the snapshot threshold (mask == nullptr; the pose table
+// must hold this round's F_hat and tau) or whose sorted position is set in the
+// device bit mask.  Leaves the new layout live with its per-pair lengths.
+hipError_t compact_layout(fea_ctx* c, const uint32_t* mask) {
+  hipError_t e = fea::launch_filter_count(c, mask);
+  if (e != hipSuccess) return e;
   std::vector<int32_t> keep;
-  HIP_OR_FAIL(c, download(c, keep, c->item_keep, c->n_items));
+  if ((e = download(c, keep, c->item_keep, c->n_items)) != hipSuccess) return e;
   // new per-pair lengths, aligned offsets and per-item destinations
   std::vector<int64_t> new_len(c->P, 0), new_off(c->P, 0);
   std::vector<int32_t> base(c->n_items, 0);
@@ -429,15 +457,95 @@ fea_status begin_round(fea_ctx* c, double tau_px) {
   }
   const int dst = (c->cur == 1) ? 2 : 1;
   const size_t span = (size_t)std::max<int64_t>(off, 1);
-  for (int a = 0; a < 4; ++a) HIP_OR_FAIL(c, hipMemsetAsync(c->lay[dst][a].p, 0, span * sizeof(float), c->stream));
-  HIP_OR_FAIL(c, hipMemsetAsync(c->lpos[dst].p, 0xFF, span * sizeof(int32_t), c->stream));
-  HIP_OR_FAIL(c, upload(c, c->item_base, base.data(), c->n_items));
-  HIP_OR_FAIL(c, fea::launch_filter_scatter(c, dst));
-  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  for (int a = 0; a < 4; ++a)
+    if ((e = hipMemsetAsync(c->lay[dst][a].p, 0, span * sizeof(float), c->stream)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(c->lpos[dst].p, 0xFF, span * sizeof(int32_t), c->stream)) != hipSuccess) return e;
+  if ((e = upload(c, c->item_base, base.data(), c->n_items)) != hipSuccess) return e;
+  if ((e = fea::launch_filter_scatter(c, dst, mask)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
   c->cur = dst;
   c->cur_len = new_len;
   c->phys_off = new_off;
   c->layout_len = off;
+  return hipSuccess;
+}
+
+// Per-scene weighting mode of the round (chosen now, or kept as restored
+// from a checkpoint) and, for scenes on learned weights, the network's weight
+// of every retained match and 1 / (sum of weights).
+hipError_t round_weights(fea_ctx* c, bool choose_mode) {
+  c->learned_any = false;
+  for (int sc = 0; sc < c->S; ++sc) {
+    if (choose_mode)
+      c->scene_mode[sc] = (c->opt.weight_mode == 1 && c->have_mlp && c->scene_learned_ok[sc]) ? 1 : 0;
+    c->learned_any = c->learned_any || c->scene_mode[sc];
+  }
+  hipError_t e = upload(c, c->d_scene_mode, c->scene_mode.data(), c->S);
+  if (e != hipSuccess || !c->learned_any) return e;
+  std::vector<float> fb(c->fbar_hist.begin(), c->fbar_hist.end());
+  if ((e = upload(c, c->d_fbar, fb.data(), fb.size())) != hipSuccess) return e;
+  if ((e = fea::launch_mlp_weights(c, c->mlp.as<float>(), c->wlay.as<unsigned short>(),
+                                   c->item_wsum.as<double>(), nullptr)) != hipSuccess)
+    return e;
+  std::vector<double> ws;
+  if ((e = download(c, ws, c->item_wsum, c->n_items)) != hipSuccess) return e;
+  std::vector<double> zw(c->S, 0.0);
+  for (int64_t it = 0; it < c->n_items; ++it) zw[c->pair_scene[c->h_item_pair[it]]] += ws[it];
+  std::vector<float> inv(c->S, 0.f);
+  for (int sc = 0; sc < c->S; ++sc) inv[sc] = zw[sc] > 0 ? (float)(1.0 / zw[sc]) : 0.f;
+  return upload(c, c->d_inv_zw, inv.data(), c->S);
+}
+
+fea_status begin_round(fea_ctx* c, double tau_px) {
+  const size_t N = c->N;
+  // snapshot history for the learned features: (r-1, r-2) <- (r, r-1)
+  if (c->round >= 0) {
+    HIP_OR_FAIL(c, d2d(c, c->Rh2, c->Rh1, 9 * N * sizeof(double)));
+    HIP_OR_FAIL(c, d2d(c, c->Th2, c->Th1, 3 * N * sizeof(double)));
+    HIP_OR_FAIL(c, d2d(c, c->Fh2, c->Fh1, N * sizeof(double)));
+    HIP_OR_FAIL(c, d2d(c, c->Rh1, c->Rh, 9 * N * sizeof(double)));
+    HIP_OR_FAIL(c, d2d(c, c->Th1, c->Th, 3 * N * sizeof(double)));
+    HIP_OR_FAIL(c, d2d(c, c->Fh1, c->Fh, N * sizeof(double)));
+  }
+  HIP_OR_FAIL(c, d2d(c, c->a6h, c->a6, 6 * N * sizeof(double)));
+  HIP_OR_FAIL(c, d2d(c, c->tph, c->tp, 3 * N * sizeof(double)));
+  HIP_OR_FAIL(c, d2d(c, c->logfh, c->logf, (size_t)c->G * sizeof(double)));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->Rh.p, c->R[c->pcur].p, 9 * N * sizeof(double), hipMemcpyDeviceToDevice,
+                                c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->Th.p, c->T[c->pcur].p, 3 * N * sizeof(double), hipMemcpyDeviceToDevice,
+                                c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->Fh.p, c->Fc[c->pcur].p, N * sizeof(double), hipMemcpyDeviceToDevice,
+                                c->stream));
+  std::vector<double> fnow;
+  HIP_OR_FAIL(c, download(c, fnow, c->Fc[c->pcur], N));
+  // threshold per scene: tau_px over the scene's median focal length
+  std::vector<std::vector<double>> fs(c->S);
+  for (size_t i = 0; i < N; ++i) fs[c->cam_scene[i]].push_back(fnow[i]);
+  if (c->round < 0) {
+    // first round: the earlier snapshots are this one
+    HIP_OR_FAIL(c, d2d(c, c->Rh1, c->Rh, 9 * N * sizeof(double)));
+    HIP_OR_FAIL(c, d2d(c, c->Th1, c->Th, 3 * N * sizeof(double)));
+    HIP_OR_FAIL(c, d2d(c, c->Fh1, c->Fh, N * sizeof(double)));
+    HIP_OR_FAIL(c, d2d(c, c->Rh2, c->Rh, 9 * N * sizeof(double)));
+    HIP_OR_FAIL(c, d2d(c, c->Th2, c->Th, 3 * N * sizeof(double)));
+    HIP_OR_FAIL(c, d2d(c, c->Fh2, c->Fh, N * sizeof(double)));
+    c->fbar_hist.assign(3 * c->S, 0.0);
+    for (int sc = 0; sc < c->S; ++sc)
+      for (int k = 0; k < 3; ++k) c->fbar_hist[k * c->S + sc] = fs[sc].empty() ? 1.0 : median(fs[sc]);
+  } else {
+    for (int sc = 0; sc < c->S; ++sc) {
+      c->fbar_hist[2 * c->S + sc] = c->fbar_hist[c->S + sc];
+      c->fbar_hist[c->S + sc] = c->fbar_hist[sc];
+      c->fbar_hist[sc] = fs[sc].empty() ? 1.0 : median(fs[sc]);
+    }
+  }
+  c->taus.assign(c->S, std::numeric_limits<double>::infinity());
+  if (!std::isinf(tau_px))
+    for (int sc = 0; sc < c->S; ++sc) c->taus[sc] = tau_px / (fs[sc].empty() ? 1.0 : median(fs[sc]));
+  HIP_OR_FAIL(c, upload(c, c->d_tau, c->taus.data(), c->S));
+  // pose table at the snapshot: F_hat, principal points and tau of each pair
+  HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), true));
+  HIP_OR_FAIL(c, compact_layout(c, nullptr));
   HIP_OR_FAIL(c, upload_scene_z(c));
   c->tau = c->taus.empty() ? 0.0 : c->taus[0];
   HIP_OR_FAIL(c, choose_tile(c));
@@ -451,11 +559,92 @@ fea_status begin_round(fea_ctx* c, double tau_px) {
   }
   HIP_OR_FAIL(c, set_counters(c, c->adam_t, c->global_step));
   drop_graph(c);  // the layout changed: recapture on the next run of steps
+  // learned weights of this round's retained matches
+  HIP_OR_FAIL(c, round_weights(c, true));
+  if (c->opt.inner_loop == 1) HIP_OR_FAIL(c, fea::launch_quad_build(c));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->round += 1;
   c->step = 0;
   c->lr_scale = std::pow(c->opt.lr_decay, (double)c->round);
   return FEA_OK;
+}
+
+
+constexpr char kStateMagic[8] = {'F', 'E', 'A', 'S', 'T', 'A', 'T', 'E'};
+constexpr int32_t kStateVersion = 1;
+
+// Fixed header of a checkpoint; the sections listed in state_sections and
+// the retained-match bit mask follow it.
+struct StateHdr {
+  char magic[8];
+  int32_t version, N, G, S;
+  int64_t P, M;
+  uint64_t structure;  // hash of the loaded problem's structure
+  fea_options opt;
+  int32_t round, step, n_logged, fallbacks, tile_cfg, pcur, learned_any, have_mlp;
+  int64_t adam_t, global_step;
+  double tau, lr_scale;
+};
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const uint8_t* b = static_cast<const uint8_t*>(p);
+  for (size_t k = 0; k < n; ++k) {
+    h ^= b[k];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// Pair table, segment ranges, scene partition, intrinsics groups and the
+// sorted order of the matches: a checkpoint only fits a context that loaded
+// the same problem.
+hipError_t structure_hash(fea_ctx* c, uint64_t* out) {
+  std::vector<int32_t> perm;
+  hipError_t e = download(c, perm, c->perm, (size_t)c->M);
+  if (e != hipSuccess) return e;
+  uint64_t h = 1469598103934665603ull;
+  h = fnv1a(h, c->pair_i.data(), c->pair_i.size() * sizeof(int32_t));
+  h = fnv1a(h, c->pair_j.data(), c->pair_j.size() * sizeof(int32_t));
+  h = fnv1a(h, c->seg_off.data(), c->seg_off.size() * sizeof(int64_t));
+  h = fnv1a(h, c->cam_scene.data(), c->cam_scene.size() * sizeof(int32_t));
+  h = fnv1a(h, c->group.data(), c->group.size() * sizeof(int32_t));
+  h = fnv1a(h, perm.data(), perm.size() * sizeof(int32_t));
+  *out = h;
+  return hipSuccess;
+}
+
+// Device arrays of the solver state, in checkpoint order, with their sizes.
+std::vector<std::pair<DBuf*, size_t>> state_sections(fea_ctx* c) {
+  const size_t N = c->N, G = c->G, d = sizeof(double);
+  const int p = c->pcur;
+  return {{&c->a6, 6 * N * d},  {&c->tp, 3 * N * d},   {&c->logf, G * d},   {&c->m_a6, 6 * N * d},
+          {&c->v_a6, 6 * N * d}, {&c->m_t, 3 * N * d},  {&c->v_t, 3 * N * d}, {&c->m_f, G * d},
+          {&c->v_f, G * d},      {&c->R[p], 9 * N * d}, {&c->T[p], 3 * N * d}, {&c->Fc[p], N * d},
+          {&c->Rh, 9 * N * d},   {&c->Th, 3 * N * d},   {&c->Fh, N * d},      {&c->Rh1, 9 * N * d},
+          {&c->Th1, 3 * N * d},  {&c->Fh1, N * d},      {&c->Rh2, 9 * N * d}, {&c->Th2, 3 * N * d},
+          {&c->Fh2, N * d},      {&c->a6h, 6 * N * d},  {&c->tph, 3 * N * d}, {&c->logfh, G * d},
+          {&c->counters, sizeof(fea::StepCounters)}};
+}
+
+size_t state_bytes(fea_ctx* c) {
+  size_t n = sizeof(StateHdr);
+  for (auto& sec : state_sections(c)) n += sec.second;
+  const size_t S = c->S;
+  n += S * sizeof(double) + 3 * S * sizeof(double) + 2 * S * sizeof(int32_t) + 4 * S * sizeof(double);
+  n += (size_t)((c->M + 31) / 32) * sizeof(uint32_t);
+  return n;
+}
+
+template <class T>
+void put(uint8_t*& w, const T* src, size_t n) {
+  std::memcpy(w, src, n * sizeof(T));
+  w += n * sizeof(T);
+}
+
+template <class T>
+void take(const uint8_t*& r, T* dst, size_t n) {
+  std::memcpy(dst, r, n * sizeof(T));
+  r += n * sizeof(T);
 }
 
 }  // namespace
@@ -500,6 +689,8 @@ fea_status fea_default_options(fea_options* o) {
   o->reset_moments = 1;
   o->tile_matches = 0;
   o->use_graphs = 1;
+  o->weight_mode = 0;
+  o->inner_loop = 0;
   return FEA_OK;
 }
 
@@ -604,23 +795,26 @@ fea_status fea_load_intrinsics(fea_ctx* c, int32_t n_cams, const double* f, cons
   c->grp_cams.assign(n_cams, 0);
   std::vector<int32_t> fill(c->grp_off.begin(), c->grp_off.end() - 1);
   for (int i = 0; i < n_cams; ++i) c->grp_cams[fill[c->group[i]]++] = i;
-  HIP_OR_FAIL(c, dalloc(c->d_inv_z, sizeof(float)));
-  HIP_OR_FAIL(c, dalloc(c->counters, 4 * sizeof(long long)));
+  HIP_OR_FAIL(c, alloc_scene_arrays(c));
+  HIP_OR_FAIL(c, dalloc(c->counters, sizeof(fea::StepCounters)));
+  HIP_OR_FAIL(c, dalloc(c->mlp, fea::kMlpParams * sizeof(float)));
+  HIP_OR_FAIL(c, hipMemsetAsync(c->mlp.p, 0, c->mlp.bytes, c->stream));
   HIP_OR_FAIL(c, upload(c, c->d_cx, c->cx.data(), n_cams));
   HIP_OR_FAIL(c, upload(c, c->d_cy, c->cy.data(), n_cams));
   HIP_OR_FAIL(c, upload(c, c->d_group, c->group.data(), n_cams));
   HIP_OR_FAIL(c, upload(c, c->d_grp_off, c->grp_off.data(), G + 1));
   HIP_OR_FAIL(c, upload(c, c->d_grp_cams, c->grp_cams.data(), n_cams));
   const size_t N = n_cams;
-  DBuf* per_cam[] = {&c->a6, &c->m_a6, &c->v_a6};
+  DBuf* per_cam[] = {&c->a6, &c->m_a6, &c->v_a6, &c->a6h};
   for (DBuf* b : per_cam) HIP_OR_FAIL(c, dalloc(*b, 6 * N * sizeof(double)));
-  DBuf* per_cam3[] = {&c->tp, &c->m_t, &c->v_t, &c->T[0], &c->T[1], &c->Th, &c->gt, &c->Te};
+  DBuf* per_cam3[] = {&c->tp, &c->m_t, &c->v_t, &c->T[0], &c->T[1], &c->Th, &c->gt, &c->Te, &c->Th1, &c->Th2,
+                      &c->tph};
   for (DBuf* b : per_cam3) HIP_OR_FAIL(c, dalloc(*b, 3 * N * sizeof(double)));
-  DBuf* per_cam9[] = {&c->R[0], &c->R[1], &c->Rh, &c->gR, &c->Re};
+  DBuf* per_cam9[] = {&c->R[0], &c->R[1], &c->Rh, &c->gR, &c->Re, &c->Rh1, &c->Rh2};
   for (DBuf* b : per_cam9) HIP_OR_FAIL(c, dalloc(*b, 9 * N * sizeof(double)));
-  DBuf* per_cam1[] = {&c->Fc[0], &c->Fc[1], &c->Fh, &c->gf, &c->loss_cam, &c->Fe};
+  DBuf* per_cam1[] = {&c->Fc[0], &c->Fc[1], &c->Fh, &c->gf, &c->loss_cam, &c->Fe, &c->Fh1, &c->Fh2};
   for (DBuf* b : per_cam1) HIP_OR_FAIL(c, dalloc(*b, N * sizeof(double)));
-  DBuf* per_grp[] = {&c->logf, &c->m_f, &c->v_f};
+  DBuf* per_grp[] = {&c->logf, &c->m_f, &c->v_f, &c->logfh};
   for (DBuf* b : per_grp) HIP_OR_FAIL(c, dalloc(*b, (size_t)G * sizeof(double)));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->have_intr = true;
@@ -647,12 +841,12 @@ fea_status fea_set_scenes(fea_ctx* c, int32_t n_scenes, const int32_t* cam_scene
   c->gauge_c.assign(3 * n_scenes, 0.0);
   c->gauge_s.assign(n_scenes, 1.0);
   DeviceGuard g(c->device);
-  HIP_OR_FAIL(c, dalloc(c->d_inv_z, (size_t)n_scenes * sizeof(float)));
+  HIP_OR_FAIL(c, alloc_scene_arrays(c));
   return FEA_OK;
 }
 
 fea_status fea_get_scene_stats(fea_ctx* c, double* loss, int64_t* retained, double* gauge_center,
-                               double* gauge_scale) {
+                               double* gauge_scale, int32_t* learned) {
   if (!c) return FEA_EINVAL;
   if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
   DeviceGuard g(c->device);
@@ -667,6 +861,7 @@ fea_status fea_get_scene_stats(fea_ctx* c, double* loss, int64_t* retained, doub
     if (gauge_center)
       for (int k = 0; k < 3; ++k) gauge_center[3 * s + k] = c->gauge_c[3 * s + k];
     if (gauge_scale) gauge_scale[s] = c->gauge_s[s];
+    if (learned) learned[s] = c->scene_mode.empty() ? 0 : (c->scene_mode[s] && c->scene_learned_ok[s]);
   }
   return FEA_OK;
 }
@@ -816,6 +1011,10 @@ fea_status fea_init_poses(fea_ctx* c, const double* R, const double* t) {
   reset_round_state(c);
   c->adam_t = 0;
   HIP_OR_FAIL(c, set_counters(c, 0, 0));
+  c->scene_learned_ok.assign(c->S, 1);
+  c->scene_mode.assign(c->S, 0);
+  c->learned_any = false;
+  c->fallbacks = 0;
   c->have_poses = true;
   return FEA_OK;
 }
@@ -840,8 +1039,9 @@ fea_status fea_residual_grad(fea_ctx* c, double* loss_dev, double* gR_dev, doubl
   if (!c) return FEA_EINVAL;
   if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
   DeviceGuard g(c->device);
-  HIP_OR_FAIL(c, fea::launch_resgrad(c));
-  HIP_OR_FAIL(c, fea::launch_camgrad(c, 0));
+  const bool quad = c->opt.inner_loop == 1;
+  if (!quad) HIP_OR_FAIL(c, fea::launch_resgrad(c));
+  HIP_OR_FAIL(c, fea::launch_camgrad(c, 0, quad));
   HIP_OR_FAIL(c, fea::launch_loss_sum(c));
   const size_t N = c->N;
   if (loss_dev)
@@ -878,7 +1078,7 @@ fea_status fea_loss_dev(fea_ctx* c, const double* a6_dev, const double* t_dev, c
   DeviceGuard g(c->device);
   HIP_OR_FAIL(c, fea::launch_params_to_pose(c, a6_dev, t_dev, logf_dev));
   HIP_OR_FAIL(c, fea::launch_resgrad_at(c, c->tile_cfg, c->Re.as<double>(), c->Te.as<double>(),
-                                        c->Fe.as<double>(), true));
+                                        c->Fe.as<double>(), true, false));
   HIP_OR_FAIL(c, fea::launch_item_loss(c, loss_dev));
   return FEA_OK;
 }
@@ -891,7 +1091,7 @@ fea_status fea_adjoint_dev(fea_ctx* c, const double* a6_dev, const double* t_dev
   DeviceGuard g(c->device);
   HIP_OR_FAIL(c, fea::launch_params_to_pose(c, a6_dev, t_dev, logf_dev));
   HIP_OR_FAIL(c, fea::launch_resgrad_at(c, c->tile_cfg, c->Re.as<double>(), c->Te.as<double>(),
-                                        c->Fe.as<double>(), false));
+                                        c->Fe.as<double>(), false, false));
   HIP_OR_FAIL(c, fea::launch_camgrad_at(c, c->Re.as<double>(), c->Te.as<double>(), c->Fe.as<double>()));
   HIP_OR_FAIL(c, fea::launch_param_grad(c, a6_dev, gout_dev, ga6_dev, gt_dev, glogf_dev));
   return FEA_OK;
@@ -905,6 +1105,23 @@ fea_status fea_step(fea_ctx* c, int32_t n_steps) {
   return run_steps(c, n_steps);
 }
 
+namespace {
+
+// Plain IRLS objective per scene at poses (R, T, F) with this round's
+// snapshot weights (loss-only pass, learned weights ignored).
+fea_status plain_loss_per_scene(fea_ctx* c, const double* R, const double* T, const double* F,
+                                std::vector<double>& out) {
+  HIP_OR_FAIL(c, fea::launch_resgrad_at(c, c->tile_cfg, R, T, F, true, true));
+  std::vector<double> part;
+  HIP_OR_FAIL(c, download(c, part, c->part, (size_t)c->n_items * fea::kPartStride));
+  out.assign(c->S, 0.0);
+  for (int64_t it = 0; it < c->n_items; ++it)
+    out[c->pair_scene[c->h_item_pair[it]]] += part[it * fea::kPartStride + 9];
+  return FEA_OK;
+}
+
+}  // namespace
+
 fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
   if (!c) return FEA_EINVAL;
   if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
@@ -916,8 +1133,31 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
     const double tau_px = std::max(c->opt.tau_px_init * std::pow(c->opt.tau_decay, (double)r), c->opt.tau_px_min);
     fea_status s = begin_round(c, tau_px);
     if (s != FEA_OK) return s;
+    std::vector<double> l0, l1;
+    if (c->learned_any) {
+      s = plain_loss_per_scene(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), l0);
+      if (s != FEA_OK) return s;
+    }
     s = run_steps(c, c->opt.iters_per_round);
     if (s != FEA_OK) return s;
+    if (c->learned_any) {
+      // judge: a learned round must lower the plain objective of its scene
+      s = plain_loss_per_scene(c, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
+                               c->Fc[c->pcur].as<double>(), l1);
+      if (s != FEA_OK) return s;
+      std::vector<int32_t> reject(c->N, 0);
+      bool any = false;
+      for (int sc = 0; sc < c->S; ++sc)
+        if (c->scene_mode[sc] && !(l1[sc] <= l0[sc])) {
+          c->scene_learned_ok[sc] = 0;
+          c->fallbacks += 1;
+          any = true;
+        }
+      if (any) {
+        for (int i = 0; i < c->N; ++i) reject[i] = c->scene_mode[c->cam_scene[i]] && !c->scene_learned_ok[c->cam_scene[i]];
+        HIP_OR_FAIL(c, fea::launch_restore(c, reject));
+      }
+    }
     if (r < 64) {
       rep.inliers_per_round[r] = c->Z;
       HIP_OR_FAIL(c, fea::launch_loss_sum(c));
@@ -930,6 +1170,7 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   rep.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   rep.n_logged = c->n_logged;
+  rep.fallbacks = c->fallbacks;
   if (out) *out = rep;
   return FEA_OK;
 }
@@ -997,6 +1238,157 @@ fea_status fea_get_mask(fea_ctx* c, uint8_t* mask, int64_t* n_retained) {
   return FEA_OK;
 }
 
+fea_status fea_get_state(fea_ctx* c, void* buf, size_t* len) {
+  if (!c || !len) return fail(c, FEA_EINVAL, "null argument");
+  if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
+  const size_t need = state_bytes(c);
+  if (!buf) {
+    *len = need;
+    return FEA_OK;
+  }
+  if (*len < need) {
+    *len = need;
+    return fail(c, FEA_EINVAL, "buffer too small for the state (size written to *len)");
+  }
+  DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  StateHdr h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kStateMagic, sizeof(kStateMagic));
+  h.version = kStateVersion;
+  h.N = c->N;
+  h.G = c->G;
+  h.S = c->S;
+  h.P = c->P;
+  h.M = c->M;
+  HIP_OR_FAIL(c, structure_hash(c, &h.structure));
+  h.opt = c->opt;
+  h.round = c->round;
+  h.step = c->step;
+  h.n_logged = c->n_logged;
+  h.fallbacks = c->fallbacks;
+  h.tile_cfg = c->tile_cfg;
+  h.pcur = c->pcur;
+  h.learned_any = c->learned_any ? 1 : 0;
+  h.have_mlp = c->have_mlp ? 1 : 0;
+  h.adam_t = c->adam_t;
+  h.global_step = c->global_step;
+  h.tau = c->tau;
+  h.lr_scale = c->lr_scale;
+  uint8_t* w = static_cast<uint8_t*>(buf);
+  put(w, &h, 1);
+  for (auto& sec : state_sections(c)) {
+    HIP_OR_FAIL(c, hipMemcpyAsync(w, sec.first->p, sec.second, hipMemcpyDeviceToHost, c->stream));
+    w += sec.second;
+  }
+  const size_t S = c->S;
+  std::vector<double> taus(c->taus), fb(c->fbar_hist), gc(c->gauge_c), gs(c->gauge_s);
+  std::vector<int32_t> mode(c->scene_mode), ok(c->scene_learned_ok);
+  taus.resize(S, std::numeric_limits<double>::infinity());
+  fb.resize(3 * S, 1.0);
+  gc.resize(3 * S, 0.0);
+  gs.resize(S, 1.0);
+  mode.resize(S, 0);
+  ok.resize(S, 1);
+  put(w, taus.data(), S);
+  put(w, fb.data(), 3 * S);
+  put(w, mode.data(), S);
+  put(w, ok.data(), S);
+  put(w, gc.data(), 3 * S);
+  put(w, gs.data(), S);
+  // retained matches of the live layout, one bit per sorted position
+  std::vector<uint32_t> bits((size_t)((c->M + 31) / 32), 0u);
+  if (c->round >= 0) {
+    std::vector<int32_t> pos;
+    HIP_OR_FAIL(c, download(c, pos, c->lpos[c->cur], c->layout_len));
+    for (int64_t n = 0; n < c->P; ++n)
+      for (int64_t k = 0; k < c->cur_len[n]; ++k) {
+        const int32_t q = pos[c->phys_off[n] + k];
+        if (q >= 0 && q < c->M) bits[q >> 5] |= 1u << (q & 31);
+      }
+  }
+  put(w, bits.data(), bits.size());
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  *len = need;
+  return FEA_OK;
+}
+
+fea_status fea_set_state(fea_ctx* c, const void* buf, size_t len) {
+  if (!c || !buf) return fail(c, FEA_EINVAL, "null argument");
+  if (!c->have_matches) return fail(c, FEA_ESTATE, "load intrinsics and matches first");
+  if (len < sizeof(StateHdr)) return fail(c, FEA_EINVAL, "state too short");
+  StateHdr h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, kStateMagic, sizeof(kStateMagic)) != 0 || h.version != kStateVersion)
+    return fail(c, FEA_EINVAL, "not a state of this library version");
+  if (h.N != c->N || h.G != c->G || h.S != c->S || h.P != c->P || h.M != c->M)
+    return fail(c, FEA_EINVAL, "state is of a problem with other sizes");
+  if (len != state_bytes(c)) return fail(c, FEA_EINVAL, "state has the wrong length");
+  std::string why;
+  if (!options_valid(&h.opt, &why)) return fail(c, FEA_EINVAL, "state options: " + why);
+  if (h.tile_cfg < 0 || h.tile_cfg >= fea::kNumTiles || (h.pcur != 0 && h.pcur != 1) || h.round < -1)
+    return fail(c, FEA_EINVAL, "state header is corrupt");
+  if (h.learned_any && !c->have_mlp) return fail(c, FEA_ESTATE, "load the network (fea_set_mlp) first");
+  DeviceGuard g(c->device);
+  uint64_t hs = 0;
+  HIP_OR_FAIL(c, structure_hash(c, &hs));
+  if (hs != h.structure) return fail(c, FEA_EINVAL, "state is of another set of matches");
+  if (h.opt.log_every > 0 && h.opt.max_log > 0)
+    HIP_OR_FAIL(c, dalloc(c->logR, (size_t)h.opt.max_log * 9 * c->N * sizeof(double)));
+  c->opt = h.opt;
+  c->pcur = h.pcur;
+  const uint8_t* r = static_cast<const uint8_t*>(buf) + sizeof(StateHdr);
+  for (auto& sec : state_sections(c)) {
+    HIP_OR_FAIL(c, hipMemcpyAsync(sec.first->p, r, sec.second, hipMemcpyHostToDevice, c->stream));
+    r += sec.second;
+  }
+  const size_t S = c->S;
+  c->taus.resize(S);
+  c->fbar_hist.resize(3 * S);
+  c->scene_mode.resize(S);
+  c->scene_learned_ok.resize(S);
+  c->gauge_c.resize(3 * S);
+  c->gauge_s.resize(S);
+  take(r, c->taus.data(), S);
+  take(r, c->fbar_hist.data(), 3 * S);
+  take(r, c->scene_mode.data(), S);
+  take(r, c->scene_learned_ok.data(), S);
+  take(r, c->gauge_c.data(), 3 * S);
+  take(r, c->gauge_s.data(), S);
+  std::vector<uint32_t> bits((size_t)((c->M + 31) / 32));
+  take(r, bits.data(), bits.size());
+  c->round = h.round;
+  c->step = h.step;
+  c->n_logged = h.n_logged;
+  c->fallbacks = h.fallbacks;
+  c->adam_t = h.adam_t;
+  c->global_step = h.global_step;
+  c->tau = h.tau;
+  c->lr_scale = h.lr_scale;
+  c->have_poses = true;
+  drop_graph(c);
+  // rebuild the live layout: the full one, then the saved retained set
+  c->tile_cfg = h.tile_cfg;
+  c->tile_tuned = true;
+  HIP_OR_FAIL(c, reset_layout(c));
+  if (c->round >= 0) {
+    DBuf d_bits;
+    hipError_t e = upload(c, d_bits, bits.data(), bits.size());
+    if (e == hipSuccess) e = compact_layout(c, d_bits.as<uint32_t>());
+    dfree(d_bits);
+    HIP_OR_FAIL(c, e);
+    HIP_OR_FAIL(c, upload_scene_z(c));
+    HIP_OR_FAIL(c, build_items(c));
+    HIP_OR_FAIL(c, upload(c, c->d_tau, c->taus.data(), S));
+    HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), true));
+    HIP_OR_FAIL(c, round_weights(c, false));
+    if (c->opt.inner_loop == 1) HIP_OR_FAIL(c, fea::launch_quad_build(c));
+  }
+  // the step counters (with their running powers) came with the sections
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return FEA_OK;
+}
+
 fea_status fea_get_info(fea_ctx* c, fea_info* out) {
   if (!c || !out) return fail(c, FEA_EINVAL, "null argument");
   std::memset(out, 0, sizeof(*out));
@@ -1023,6 +1415,148 @@ fea_status fea_synchronize(fea_ctx* c) {
   DeviceGuard g(c->device);
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   return FEA_OK;
+}
+
+fea_status fea_set_mlp(fea_ctx* c, const float* params) {
+  if (!c || !params) return fail(c, FEA_EINVAL, "null argument");
+  if (!c->have_intr) return fail(c, FEA_ESTATE, "load intrinsics first");
+  for (int k = 0; k < fea::kMlpParams; ++k)
+    if (!std::isfinite(params[k])) return fail(c, FEA_ENONFINITE, "non-finite network parameter");
+  DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, upload(c, c->mlp, params, fea::kMlpParams));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->have_mlp = true;
+  return FEA_OK;
+}
+
+fea_status fea_mlp_features_dev(fea_ctx* c, float* feat_dev, int32_t* slot_pos_dev) {
+  if (!c) return FEA_EINVAL;
+  if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
+  if (!feat_dev) return fail(c, FEA_EINVAL, "feat_dev is required");
+  DeviceGuard g(c->device);
+  std::vector<float> fb(c->fbar_hist.begin(), c->fbar_hist.end());
+  HIP_OR_FAIL(c, upload(c, c->d_fbar, fb.data(), fb.size()));
+  HIP_OR_FAIL(c, hipMemsetAsync(feat_dev, 0, (size_t)c->layout_len * fea::kMlpFeat * sizeof(float), c->stream));
+  HIP_OR_FAIL(c, fea::launch_mlp_weights(c, c->mlp.as<float>(), c->wlay.as<unsigned short>(),
+                                         c->item_wsum.as<double>(), feat_dev));
+  if (slot_pos_dev)
+    HIP_OR_FAIL(c, hipMemcpyAsync(slot_pos_dev, c->lpos[c->cur].p, (size_t)c->layout_len * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, c->stream));
+  return FEA_OK;
+}
+
+fea_status fea_get_learned_weights(fea_ctx* c, float* w) {
+  if (!c || !w) return fail(c, FEA_EINVAL, "null argument");
+  if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
+  DeviceGuard g(c->device);
+  std::vector<int32_t> pos, perm;
+  std::vector<uint16_t> wl;
+  HIP_OR_FAIL(c, download(c, pos, c->lpos[c->cur], c->layout_len));
+  HIP_OR_FAIL(c, download(c, perm, c->perm, c->M));
+  HIP_OR_FAIL(c, download(c, wl, c->wlay, c->layout_len));
+  for (int64_t m = 0; m < c->M; ++m) w[m] = 0.f;
+  for (int64_t n = 0; n < c->P; ++n) {
+    const bool learned = c->scene_mode[c->pair_scene[n]] != 0;
+    for (int64_t k = 0; k < c->cur_len[n]; ++k) {
+      const int64_t slot = c->phys_off[n] + k;
+      const int32_t p = pos[slot];
+      if (p < 0 || p >= c->M) continue;
+      float v = 1.f;
+      if (learned) {
+        const uint32_t u = (uint32_t)wl[slot] << 16;
+        std::memcpy(&v, &u, sizeof(v));
+      }
+      w[perm[p]] = v;
+    }
+  }
+  return FEA_OK;
+}
+
+namespace {
+
+struct MlpScratch {
+  float *gpart = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+  double *lpart = nullptr, *loss = nullptr;
+  ~MlpScratch() {
+    for (void* p : {(void*)gpart, (void*)grad, (void*)m, (void*)v, (void*)lpart, (void*)loss})
+      if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(int64_t parts) {
+    hipError_t e;
+    if ((e = hipMalloc(&gpart, std::max<int64_t>(parts, 1) * fea::kMlpParams * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc(&grad, fea::kMlpParams * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc(&m, fea::kMlpParams * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc(&v, fea::kMlpParams * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc(&lpart, std::max<int64_t>(parts, 1) * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&loss, sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMemset(m, 0, fea::kMlpParams * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMemset(v, 0, fea::kMlpParams * sizeof(float))) != hipSuccess) return e;
+    return hipMemset(loss, 0, sizeof(double));
+  }
+};
+
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+}  // namespace
+
+fea_status fea_mlp_train(int32_t device, const float* feat_dev, const float* target_dev, int64_t n, int32_t epochs,
+                         int32_t batch, double lr, uint64_t seed, float* params_dev, double* loss_per_epoch) {
+  if (!feat_dev || !target_dev || !params_dev || n < 1 || n >= ((int64_t)1 << 31) || epochs < 0 || batch < 1 ||
+      !(lr > 0))
+    return FEA_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FEA_EINVAL;
+  DeviceGuard g(device);
+  const int64_t B = std::min<int64_t>(batch, n);
+  const int64_t parts = (B + fea::mlp_train_threads() - 1) / fea::mlp_train_threads();
+  MlpScratch sc;
+  if (sc.alloc(parts) != hipSuccess) return FEA_ENOMEM;
+  const int64_t nb = n / B;
+  uint64_t st = seed * 0x9E3779B97F4A7C15ull + 1;
+  int64_t t = 0;
+  for (int32_t ep = 0; ep < epochs; ++ep) {
+    // a stride coprime with n gives this epoch's visiting order
+    st = st * 6364136223846793005ull + 1442695040888963407ull;
+    int64_t stride = (int64_t)((st >> 17) % (uint64_t)n);
+    if (stride == 0) stride = 1;
+    while (gcd64(stride, n) != 1) stride = (stride + 1) % n ? (stride + 1) % n : 1;
+    if (hipMemset(sc.loss, 0, sizeof(double)) != hipSuccess) return FEA_EDEVICE;
+    for (int64_t b = 0; b < nb; ++b) {
+      ++t;
+      if (fea::mlp_train_step(nullptr, feat_dev, target_dev, n, B, stride, b, params_dev, sc.m, sc.v, sc.gpart,
+                              sc.lpart, sc.grad, sc.loss, (float)lr, t) != hipSuccess)
+        return FEA_EDEVICE;
+    }
+    double L = 0.0;
+    if (hipMemcpy(&L, sc.loss, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return FEA_EDEVICE;
+    if (loss_per_epoch) loss_per_epoch[ep] = L / (double)(nb * B);
+  }
+  return hipDeviceSynchronize() == hipSuccess ? FEA_OK : FEA_EDEVICE;
+}
+
+fea_status fea_mlp_grad(int32_t device, const float* feat_dev, const float* target_dev, int64_t n,
+                        const float* params_dev, float* grad_dev, double* loss) {
+  if (!feat_dev || !target_dev || !params_dev || !grad_dev || n < 1 || n >= ((int64_t)1 << 31)) return FEA_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FEA_EINVAL;
+  DeviceGuard g(device);
+  const int64_t parts = (n + fea::mlp_train_threads() - 1) / fea::mlp_train_threads();
+  MlpScratch sc;
+  if (sc.alloc(parts) != hipSuccess) return FEA_ENOMEM;
+  if (fea::mlp_grad_once(nullptr, feat_dev, target_dev, n, params_dev, sc.gpart, sc.lpart, grad_dev, sc.loss) !=
+      hipSuccess)
+    return FEA_EDEVICE;
+  double L = 0.0;
+  if (hipMemcpy(&L, sc.loss, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return FEA_EDEVICE;
+  if (loss) *loss = L / (double)n;
+  return hipDeviceSynchronize() == hipSuccess ? FEA_OK : FEA_EDEVICE;
 }
 
 fea_status fea_set_kernel_timing(fea_ctx* c, int32_t enable) {

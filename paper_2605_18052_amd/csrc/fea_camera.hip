@@ -3,18 +3,25 @@
 // k_camgrad: one wavefront per camera.  Lanes walk the camera's incident
 // pairs (a fixed list of int4 entries {2n+side, first item, end item, other
 // camera}, so a lane needs one dependent load before it can fetch everything
-// else), sum the pair's item partials (dL/dF and the loss, fixed order),
-// recompute the pair's pose block in fp64 and apply the adjoint of
-// F = D_j [u]x R_j R_i^T D_i to get this camera's share of dL/dR, dL/dt and
-// dL/df.  The 14 sums are reduced across the wave by a fixed butterfly, so
-// the gradient is bit-reproducible.  With do_update, lane 0 takes the Adam
-// step (Kingma & Ba, bias-corrected) on the 6D rotation and the translation
-// and, when every intrinsics group holds one camera, on log f as well.
+// else), take the pair's dL/dF -- the sum of its item partials from the
+// per-match kernel (fixed order) or, with QUAD, 2 W_n f from the pair's
+// quadratic form at the current poses -- recompute the pair's pose block in
+// fp64 and apply the adjoint of F = D_j [u]x R_j R_i^T D_i to get this
+// camera's share of dL/dR, dL/dt and dL/df.  The 14 sums are reduced across
+// the wave with DPP in a fixed order, so the gradient is bit-reproducible.
+// With do_update, lanes 0, 1 and 2 take the Adam steps (Kingma & Ba,
+// bias-corrected) on the 6D rotation, the translation and, when every
+// intrinsics group holds one camera, log f; their optimiser state is loaded
+// before the pair loop, and the bias corrections come from running powers
+// beta^t kept with the step counters.
 //
 // k_focal_update: Adam on log f for intrinsics groups shared by several
 // cameras (dL/dlog f = sum over the group of f_c dL/df_c).
 // k_loss_sum: the loss, summed over cameras in a fixed order (run on demand).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "fea_ctx.h"
 #include "fea_device.h"
@@ -34,29 +41,86 @@ struct AdamArgs {
 };
 
 // Step bookkeeping kept on the device so that a captured multi-step graph
-// can be replayed: ctr[p] is the Adam step count and ctr[2+p] the global step
-// count before this step, where p is the step's parity (which of the two
-// pose buffers is current); the step writes the incremented counts to slot
-// p^1 for the next step.  Rotations are logged every log_every global steps.
+// can be replayed: slot p of the counters holds the Adam step count, the
+// global step count and beta1^t, beta2^t before this step, where p is the
+// step's parity (which of the two pose buffers is current); the step writes
+// the advanced values to slot p^1 for the next step.  Rotations are logged
+// every log_every global steps.
 struct StepCtl {
-  long long* ctr;
+  StepCounters* ctr;
   int p;
   int log_every, max_log;
   double* logR;
 };
 
+constexpr int kQuad = 45;  // distinct entries of the symmetric 9x9 W_n
+
+// dL/dF = 2 W f and the loss f^T W f of a pair from its quadratic form.
+__device__ __forceinline__ void quad_partials(const double* __restrict__ W, const double F[9],
+                                              double G[kPartStride]) {
+  double Wf[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) Wf[r] = 0.0;
+  int k = 0;
+#pragma unroll
+  for (int r = 0; r < 9; ++r)
+#pragma unroll
+    for (int s = r; s < 9; ++s, ++k) {
+      const double w = W[k];
+      Wf[r] = fma(w, F[s], Wf[r]);
+      if (s != r) Wf[s] = fma(w, F[r], Wf[s]);
+    }
+  double L = 0.0;
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    G[r] = 2.0 * Wf[r];
+    L = fma(F[r], Wf[r], L);
+  }
+  G[9] = L;
+}
+
+template <bool QUAD>
 __global__ __launch_bounds__(256) void k_camgrad(
     int N, const int32_t* __restrict__ cam_off, const int4* __restrict__ cam_ent,
-    const double* __restrict__ part, const double* __restrict__ R, const double* __restrict__ T,
-    const double* __restrict__ Fc, double* __restrict__ gR_out, double* __restrict__ gt_out,
-    double* __restrict__ gf_out, double* __restrict__ loss_cam, int do_update, int focal_inline,
-    int optimize_focal, const int32_t* __restrict__ group, double* __restrict__ a6, double* __restrict__ tp,
-    double* __restrict__ logf, double* __restrict__ m_a6, double* __restrict__ v_a6,
+    const double* __restrict__ part, const double* __restrict__ qW, const double* __restrict__ R,
+    const double* __restrict__ T, const double* __restrict__ Fc, double* __restrict__ gR_out,
+    double* __restrict__ gt_out, double* __restrict__ gf_out, double* __restrict__ loss_cam, int do_update,
+    int focal_inline, int optimize_focal, const int32_t* __restrict__ group, double* __restrict__ a6,
+    double* __restrict__ tp, double* __restrict__ logf, double* __restrict__ m_a6, double* __restrict__ v_a6,
     double* __restrict__ m_t, double* __restrict__ v_t, double* __restrict__ m_f, double* __restrict__ v_f,
     AdamArgs ad, StepCtl sc, double* __restrict__ Rn, double* __restrict__ Tn, double* __restrict__ Fn) {
   const int cam = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (cam >= N) return;  // uniform per wave
+  // optimiser state of the update lanes, fetched before the pair loop:
+  // lane 0 the 6D rotation, lane 1 the translation, lane 2 log f
+  const bool upd = do_update && lane < 3;
+  double ps[6], pm[6], pv[6];
+  int grp = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ps[k] = pm[k] = pv[k] = 0.0;
+  if (upd) {
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        ps[k] = a6[6 * cam + k];
+        pm[k] = m_a6[6 * cam + k];
+        pv[k] = v_a6[6 * cam + k];
+      }
+    } else if (lane == 1) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ps[k] = tp[3 * cam + k];
+        pm[k] = m_t[3 * cam + k];
+        pv[k] = v_t[3 * cam + k];
+      }
+    } else if (focal_inline) {
+      grp = group[cam];
+      ps[0] = logf[grp];
+      pm[0] = m_f[grp];
+      pv[0] = v_f[grp];
+    }
+  }
   double gR[9], gt[3], gf = 0.0, L = 0.0;
 #pragma unroll
   for (int k = 0; k < 9; ++k) gR[k] = 0.0;
@@ -67,82 +131,93 @@ __global__ __launch_bounds__(256) void k_camgrad(
     const int side = en.x & 1;
     const int i = side ? en.w : cam;
     const int j = side ? cam : en.w;
-    double G[kPartStride];
-#pragma unroll
-    for (int k = 0; k < kPartStride; ++k) G[k] = 0.0;
-    for (int it = en.y; it < en.z; ++it) {
-#pragma unroll
-      for (int k = 0; k < kPartStride; ++k) G[k] += part[(int64_t)it * kPartStride + k];
-    }
     Geo g;
     if (!pair_geo(R + 9 * i, T + 3 * i, Fc[i], R + 9 * j, T + 3 * j, Fc[j], g)) continue;
+    double G[kPartStride];
+    if (QUAD) {
+      quad_partials(qW + (int64_t)(en.x >> 1) * kQuad, g.F, G);
+    } else {
+#pragma unroll
+      for (int k = 0; k < kPartStride; ++k) G[k] = 0.0;
+      for (int it = en.y; it < en.z; ++it) {
+#pragma unroll
+        for (int k = 0; k < kPartStride; ++k) G[k] += part[(int64_t)it * kPartStride + k];
+      }
+    }
     pair_adjoint(g, G, R + 9 * i, T + 3 * i, R + 9 * j, Fc[i], Fc[j], side, gR, gt, gf);
     if (side == 0) L += G[9];
   }
+  double red[14];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) gR[k] = wave_sum_f64(gR[k]);
+  for (int k = 0; k < 9; ++k) red[k] = gR[k];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) gt[k] = wave_sum_f64(gt[k]);
-  gf = wave_sum_f64(gf);
-  L = wave_sum_f64(L);
-  if (lane != 0) return;
+  for (int k = 0; k < 3; ++k) red[9 + k] = gt[k];
+  red[12] = gf;
+  red[13] = L;
+  wave_sum_f64_multi<14>(red);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) gR_out[9 * cam + k] = gR[k];
+  for (int k = 0; k < 9; ++k) gR[k] = red[k];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) gt_out[3 * cam + k] = gt[k];
-  gf_out[cam] = gf;
-  loss_cam[cam] = L;
-  if (!do_update) return;
-  const long long t_adam = sc.ctr[sc.p] + 1;
-  const long long t_glob = sc.ctr[2 + sc.p] + 1;
-  if (cam == 0) {
-    sc.ctr[sc.p ^ 1] = t_adam;
-    sc.ctr[2 + (sc.p ^ 1)] = t_glob;
+  for (int k = 0; k < 3; ++k) gt[k] = red[9 + k];
+  gf = red[12];
+  L = red[13];
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) gR_out[9 * cam + k] = gR[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gt_out[3 * cam + k] = gt[k];
+    gf_out[cam] = gf;
+    loss_cam[cam] = L;
   }
-  const double bc1 = 1.0 - pow(ad.b1, (double)t_adam);
-  const double bc2 = 1.0 - pow(ad.b2, (double)t_adam);
-  double a[6], ga[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) a[k] = a6[6 * cam + k];
-  rot6d_vjp(a, gR, ga);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    double m = m_a6[6 * cam + k], v = v_a6[6 * cam + k];
-    adam_step(a[k], m, v, ga[k], ad.lr_rot, ad.b1, ad.b2, ad.eps, bc1, bc2);
-    m_a6[6 * cam + k] = m;
-    v_a6[6 * cam + k] = v;
-    a6[6 * cam + k] = a[k];
+  if (!upd) return;
+  const int p = sc.p;
+  const long long t_adam = sc.ctr->adam_t[p] + 1;
+  const long long t_glob = sc.ctr->global_t[p] + 1;
+  const double b1t = sc.ctr->b1t[p] * ad.b1, b2t = sc.ctr->b2t[p] * ad.b2;
+  if (cam == 0 && lane == 0) {
+    sc.ctr->adam_t[p ^ 1] = t_adam;
+    sc.ctr->global_t[p ^ 1] = t_glob;
+    sc.ctr->b1t[p ^ 1] = b1t;
+    sc.ctr->b2t[p ^ 1] = b2t;
   }
-  double Rnew[9];
-  rot6d_forward(a, Rnew);
+  const double bc1 = 1.0 - b1t, bc2 = 1.0 - b2t;
+  if (lane == 0) {
+    double ga[6];
+    rot6d_vjp(ps, gR, ga);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) Rn[9 * cam + k] = Rnew[k];
-  if (sc.log_every > 0 && t_glob % sc.log_every == 0) {
-    const long long slot = t_glob / sc.log_every - 1;
-    if (slot < sc.max_log)
-#pragma unroll
-      for (int k = 0; k < 9; ++k) sc.logR[(slot * N + cam) * 9 + k] = Rnew[k];
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    double p = tp[3 * cam + k], m = m_t[3 * cam + k], v = v_t[3 * cam + k];
-    adam_step(p, m, v, gt[k], ad.lr_t, ad.b1, ad.b2, ad.eps, bc1, bc2);
-    tp[3 * cam + k] = p;
-    m_t[3 * cam + k] = m;
-    v_t[3 * cam + k] = v;
-    Tn[3 * cam + k] = p;
-  }
-  if (focal_inline) {
-    const int g = group[cam];
-    double p = logf[g];
-    if (optimize_focal) {
-      double m = m_f[g], v = v_f[g];
-      adam_step(p, m, v, gf * Fc[cam], ad.lr_f, ad.b1, ad.b2, ad.eps, bc1, bc2);
-      logf[g] = p;
-      m_f[g] = m;
-      v_f[g] = v;
+    for (int k = 0; k < 6; ++k) {
+      adam_step(ps[k], pm[k], pv[k], ga[k], ad.lr_rot, ad.b1, ad.b2, ad.eps, bc1, bc2);
+      m_a6[6 * cam + k] = pm[k];
+      v_a6[6 * cam + k] = pv[k];
+      a6[6 * cam + k] = ps[k];
     }
-    Fn[cam] = exp(p);
+    double Rnew[9];
+    rot6d_forward(ps, Rnew);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rn[9 * cam + k] = Rnew[k];
+    if (sc.log_every > 0 && t_glob % sc.log_every == 0) {
+      const long long slot = t_glob / sc.log_every - 1;
+      if (slot < sc.max_log)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) sc.logR[(slot * N + cam) * 9 + k] = Rnew[k];
+    }
+  } else if (lane == 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      adam_step(ps[k], pm[k], pv[k], gt[k], ad.lr_t, ad.b1, ad.b2, ad.eps, bc1, bc2);
+      tp[3 * cam + k] = ps[k];
+      m_t[3 * cam + k] = pm[k];
+      v_t[3 * cam + k] = pv[k];
+      Tn[3 * cam + k] = ps[k];
+    }
+  } else if (focal_inline) {
+    if (optimize_focal) {
+      adam_step(ps[0], pm[0], pv[0], gf * Fc[cam], ad.lr_f, ad.b1, ad.b2, ad.eps, bc1, bc2);
+      logf[grp] = ps[0];
+      m_f[grp] = pm[0];
+      v_f[grp] = pv[0];
+    }
+    Fn[cam] = exp(ps[0]);
   }
 }
 
@@ -152,7 +227,7 @@ constexpr int kFocalThreads = 256;
 __global__ __launch_bounds__(kFocalThreads) void k_focal_update(
     int G, const int32_t* __restrict__ grp_off, const int32_t* __restrict__ grp_cams,
     const double* __restrict__ gf, const double* __restrict__ Fc, int optimize_focal, double* __restrict__ logf,
-    double* __restrict__ m_f, double* __restrict__ v_f, AdamArgs ad, const long long* __restrict__ t_adam_now,
+    double* __restrict__ m_f, double* __restrict__ v_f, AdamArgs ad, const StepCounters* __restrict__ ctr, int pn,
     double* __restrict__ Fn) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
@@ -165,9 +240,9 @@ __global__ __launch_bounds__(kFocalThreads) void k_focal_update(
       const int c = grp_cams[k];
       s += gf[c] * Fc[c];
     }
-    const double t = (double)t_adam_now[0];
+    // the camera kernel of this step has advanced the counters to slot pn
     double m = m_f[g], v = v_f[g];
-    adam_step(p, m, v, s, ad.lr_f, ad.b1, ad.b2, ad.eps, 1.0 - pow(ad.b1, t), 1.0 - pow(ad.b2, t));
+    adam_step(p, m, v, s, ad.lr_f, ad.b1, ad.b2, ad.eps, 1.0 - ctr->b1t[pn], 1.0 - ctr->b2t[pn]);
     logf[g] = p;
     m_f[g] = m;
     v_f[g] = v;
@@ -200,34 +275,84 @@ AdamArgs adam_args(const fea_ctx* c) {
 }
 
 StepCtl step_ctl(fea_ctx* c) {
-  return StepCtl{c->counters.as<long long>(), c->pcur, c->opt.log_every, c->opt.max_log, c->logR.as<double>()};
+  return StepCtl{c->counters.as<StepCounters>(), c->pcur, c->opt.log_every, c->opt.max_log, c->logR.as<double>()};
+}
+
+// Restores the round-snapshot parameters of flagged cameras (and their
+// intrinsics groups): used when the judge rejects a learned round.
+__global__ void k_restore(int N, const int32_t* __restrict__ flag, const int32_t* __restrict__ group,
+                          const double* __restrict__ a6h, const double* __restrict__ tph,
+                          const double* __restrict__ logfh, const double* __restrict__ Rh,
+                          const double* __restrict__ Th, const double* __restrict__ Fh, double* __restrict__ a6,
+                          double* __restrict__ tp, double* __restrict__ logf, double* __restrict__ R,
+                          double* __restrict__ T, double* __restrict__ F) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N || !flag[c]) return;
+  for (int k = 0; k < 6; ++k) a6[6 * c + k] = a6h[6 * c + k];
+  for (int k = 0; k < 3; ++k) {
+    tp[3 * c + k] = tph[3 * c + k];
+    T[3 * c + k] = Th[3 * c + k];
+  }
+  for (int k = 0; k < 9; ++k) R[9 * c + k] = Rh[9 * c + k];
+  F[c] = Fh[c];
+  logf[group[c]] = logfh[group[c]];  // identical value from every camera of the group
 }
 
 }  // namespace
 
-hipError_t launch_camgrad(fea_ctx* c, int do_update) {
+hipError_t launch_restore(fea_ctx* c, const std::vector<int32_t>& flag) {
+  hipError_t e = hipSuccess;
+  if (c->restore_flag.bytes < flag.size() * sizeof(int32_t)) {
+    if (c->restore_flag.p) (void)hipFree(c->restore_flag.p);
+    c->restore_flag.p = nullptr;
+    c->restore_flag.bytes = 0;
+    e = hipMalloc(&c->restore_flag.p, std::max<size_t>(flag.size(), 1) * sizeof(int32_t));
+    if (e != hipSuccess) return e;
+    c->restore_flag.bytes = std::max<size_t>(flag.size(), 1) * sizeof(int32_t);
+  }
+  e = hipMemcpyAsync(c->restore_flag.p, flag.data(), flag.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                     c->stream);
+  if (e != hipSuccess) return e;
+  k_restore<<<(unsigned)((c->N + 255) / 256), 256, 0, c->stream>>>(
+      c->N, c->restore_flag.as<int32_t>(), c->d_group.as<int32_t>(), c->a6h.as<double>(), c->tph.as<double>(),
+      c->logfh.as<double>(), c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), c->a6.as<double>(),
+      c->tp.as<double>(), c->logf.as<double>(), c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
+      c->Fc[c->pcur].as<double>());
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+// quad: dL/dF of each pair from its quadratic form W_n (built for the round)
+// instead of the per-match kernel's item partials.
+hipError_t launch_camgrad(fea_ctx* c, int do_update, bool quad) {
   if (c->N == 0) return hipSuccess;
   const int per_block = 256 / kWave;
   const unsigned blocks = (unsigned)((c->N + per_block - 1) / per_block);
   const int nx = c->pcur ^ 1;
-  k_camgrad<<<blocks, 256, 0, c->stream>>>(
-      c->N, c->d_cam_off.as<int32_t>(), c->d_cam_ent.as<int4>(), c->part.as<double>(), c->R[c->pcur].as<double>(),
-      c->T[c->pcur].as<double>(), c->Fc[c->pcur].as<double>(), c->gR.as<double>(), c->gt.as<double>(),
-      c->gf.as<double>(), c->loss_cam.as<double>(), do_update, c->all_single ? 1 : 0, c->opt.optimize_focal,
-      c->d_group.as<int32_t>(), c->a6.as<double>(), c->tp.as<double>(), c->logf.as<double>(),
-      c->m_a6.as<double>(), c->v_a6.as<double>(), c->m_t.as<double>(), c->v_t.as<double>(), c->m_f.as<double>(),
-      c->v_f.as<double>(), adam_args(c), step_ctl(c), c->R[nx].as<double>(), c->T[nx].as<double>(),
-      c->Fc[nx].as<double>());
+#define FEA_CAMGRAD_ARGS                                                                                      \
+  c->N, c->d_cam_off.as<int32_t>(), c->d_cam_ent.as<int4>(), c->part.as<double>(), c->qW.as<double>(),         \
+      c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(), c->Fc[c->pcur].as<double>(), c->gR.as<double>(), \
+      c->gt.as<double>(), c->gf.as<double>(), c->loss_cam.as<double>(), do_update, c->all_single ? 1 : 0,       \
+      c->opt.optimize_focal, c->d_group.as<int32_t>(), c->a6.as<double>(), c->tp.as<double>(),                 \
+      c->logf.as<double>(), c->m_a6.as<double>(), c->v_a6.as<double>(), c->m_t.as<double>(),                   \
+      c->v_t.as<double>(), c->m_f.as<double>(), c->v_f.as<double>(), adam_args(c), step_ctl(c),                \
+      c->R[nx].as<double>(), c->T[nx].as<double>(), c->Fc[nx].as<double>()
+  if (quad)
+    k_camgrad<true><<<blocks, 256, 0, c->stream>>>(FEA_CAMGRAD_ARGS);
+  else
+    k_camgrad<false><<<blocks, 256, 0, c->stream>>>(FEA_CAMGRAD_ARGS);
+#undef FEA_CAMGRAD_ARGS
   return hipGetLastError();
 }
 
-// Gradient only (no update) at the poses (R, T, F).
+// Gradient only (no update) at the poses (R, T, F), from the item partials.
 hipError_t launch_camgrad_at(fea_ctx* c, const double* R, const double* T, const double* F) {
   if (c->N == 0) return hipSuccess;
   const int per_block = 256 / kWave;
   const unsigned blocks = (unsigned)((c->N + per_block - 1) / per_block);
-  k_camgrad<<<blocks, 256, 0, c->stream>>>(
-      c->N, c->d_cam_off.as<int32_t>(), c->d_cam_ent.as<int4>(), c->part.as<double>(), R, T, F,
+  k_camgrad<false><<<blocks, 256, 0, c->stream>>>(
+      c->N, c->d_cam_off.as<int32_t>(), c->d_cam_ent.as<int4>(), c->part.as<double>(), nullptr, R, T, F,
       c->gR.as<double>(), c->gt.as<double>(), c->gf.as<double>(), c->loss_cam.as<double>(), 0, 0, 0,
       c->d_group.as<int32_t>(), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
       adam_args(c), step_ctl(c), nullptr, nullptr, nullptr);
@@ -240,7 +365,7 @@ hipError_t launch_focal_update(fea_ctx* c) {
   k_focal_update<<<(unsigned)((c->G + kFocalThreads - 1) / kFocalThreads), kFocalThreads, 0, c->stream>>>(
       c->G, c->d_grp_off.as<int32_t>(), c->d_grp_cams.as<int32_t>(), c->gf.as<double>(),
       c->Fc[c->pcur].as<double>(), c->opt.optimize_focal, c->logf.as<double>(), c->m_f.as<double>(),
-      c->v_f.as<double>(), adam_args(c), c->counters.as<long long>() + (c->pcur ^ 1), c->Fc[nx].as<double>());
+      c->v_f.as<double>(), adam_args(c), c->counters.as<StepCounters>(), c->pcur ^ 1, c->Fc[nx].as<double>());
   return hipGetLastError();
 }
 

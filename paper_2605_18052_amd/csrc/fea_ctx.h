@@ -21,6 +21,15 @@ constexpr int kAlign = 4;
 constexpr int kFilterThreads = 256;
 constexpr int kPartStride = 10;  // per item: dL/dF (9, centred coords) and the loss
 
+// Pose table: one row of kPairRow doubles per camera pair.  F (current poses)
+// and F_hat (round snapshot) are the pair's epipolar matrices folded for raw
+// pixel coordinates; then the scene's 1/Z for plain and learned weights, the
+// learned flag, the principal points (cx_i, cy_i, cx_j, cy_j) and tau.
+constexpr int kRowF = 0, kRowFh = 9, kRowInvZ = 18, kRowInvZw = 19, kRowMode = 20, kRowCx = 21,
+              kRowTau = 25;
+constexpr int kPairRow = 32;
+constexpr int kPairThreads = 256;
+
 // Work-item shapes of the per-match kernel: threads per workgroup and 16-byte
 // loads per thread per array; matches per item = threads * 4 * steps.
 struct TileCfg {
@@ -30,7 +39,24 @@ constexpr TileCfg kTiles[] = {{256, 4}, {256, 2}, {256, 1}, {128, 8},
                               {128, 4}, {128, 2}, {512, 2}, {512, 4}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 constexpr int kGraphSteps = 10;  // steps per captured graph (even: the pose parity is preserved)
+
+// Learned inlier weights: MLP 8 -> 64 -> 64 -> 1, parameters packed as
+// W1 [64*8], b1 [64], W2 [64*64], b2 [64], w3 [64], b3.
+constexpr int kMlpFeat = 8;
+constexpr int kMlpHidden = 64;
+constexpr int kMlpParams = kMlpHidden * kMlpFeat + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
+                           kMlpHidden + 1;
 constexpr int tile_matches_of(int cfg) { return kTiles[cfg].threads * kVec * kTiles[cfg].steps; }
+
+// Device-side step counters, one slot per pose parity p (see the camera
+// kernel): Adam steps since the moments were zeroed, global steps, and the
+// running powers beta1^t, beta2^t of the bias corrections.
+struct StepCounters {
+  long long adam_t[2];
+  long long global_t[2];
+  double b1t[2];
+  double b2t[2];
+};
 
 // Thin owner of one device allocation.
 struct DBuf {
@@ -72,6 +98,7 @@ struct fea_ctx {
   // items of the current layout
   int64_t n_items = 0;
   std::vector<int32_t> h_item_pair, h_item_start, h_item_count, h_pair_item_off;
+  std::vector<int32_t> h_item_rec;  // per item {pair, start, count, 0}
   int tile_cfg = 0;        // index into kTiles
   bool tile_tuned = false; // tile_cfg chosen for this set of matches
   std::vector<int32_t> h_cam_ent4;  // per camera entry: {2n+side, item_begin, item_end, other}
@@ -107,10 +134,15 @@ struct fea_ctx {
   fea::DBuf perm;        // int32 [M] input index of each sorted position
   fea::DBuf swp;         // uint8 [M]
   fea::DBuf item_pair, item_start, item_count, pair_item_off, item_keep, item_base;
+  fea::DBuf item_rec;  // int4 per item: {pair, start, count, 0}
   fea::DBuf part;        // double [n_items * kPartStride]
   fea::DBuf d_pair_i, d_pair_j, d_cam_off, d_cam_ent, d_group, d_grp_off, d_grp_cams;
   fea::DBuf d_cx, d_cy;
   fea::DBuf d_pair_scene, d_inv_z, d_tau;  // int32 [P], float [S], double [S]
+  fea::DBuf ptab;  // double [P * kPairRow], the pose table
+  fea::DBuf stab;  // double [P * 40]: per-pair rows for the learned features
+  fea::DBuf qpart;           // double [n_items * 45]: per-item sums of c w w^T (quadratic form)
+  fea::DBuf qW;              // double [P * 45]: W_n of every pair for the round
   fea::DBuf a6, tp, logf, m_a6, v_a6, m_t, v_t, m_f, v_f;
   fea::DBuf R[2], T[2], Fc[2];  // derived current/next R (N*9), t (N*3), f (N)
   fea::DBuf Rh, Th, Fh;         // round snapshot
@@ -119,6 +151,23 @@ struct fea_ctx {
   fea::DBuf errflag;
   fea::DBuf Re, Te, Fe;  // poses built from caller-given parameters
   fea::DBuf counters;    // int64 [4]: Adam step count and global step count, two parities
+
+  // learned weights
+  fea::DBuf Rh1, Th1, Fh1, Rh2, Th2, Fh2;  // snapshots of the two previous rounds
+  fea::DBuf d_fbar;                       // float [3*S]: median f per scene at the 3 snapshots
+  fea::DBuf mlp;                          // float [kMlpParams]
+  fea::DBuf wlay;                         // bf16 [layout] learned weight of each layout slot
+  fea::DBuf item_wsum;                    // double [n_items]
+  fea::DBuf d_inv_zw;                     // float [S]: 1 / sum of learned weights per scene
+  fea::DBuf d_scene_mode;                 // int32 [S]: 1 = learned weights this round, 0 = plain
+  fea::DBuf a6h, tph, logfh;              // parameters at the round snapshot (judge fallback)
+  fea::DBuf restore_flag;                 // int32 [N] cameras to restore
+  bool have_mlp = false;
+  bool learned_any = false;               // some scene uses learned weights this round
+  std::vector<int32_t> scene_mode;        // host copy of d_scene_mode
+  std::vector<int32_t> scene_learned_ok;  // 0 once the judge rejected a scene's learned round
+  int32_t fallbacks = 0;                  // rejected learned rounds (all scenes)
+  std::vector<double> fbar_hist;          // [3*S] median f per scene, snapshots r, r-1, r-2
 
   // captured step graph (kGraphSteps steps of the current round)
   hipGraphExec_t graph = nullptr;
@@ -140,17 +189,21 @@ hipError_t segment_matches(fea_ctx* c, const float* x1, const float* y1, const f
                            const int32_t* cam1, const int32_t* cam2, int* bad_bits);
 
 // --- per-match pass (fea_resgrad.hip) ---
+hipError_t launch_pair_pose(fea_ctx* c, const double* R, const double* T, const double* F, bool snap);
+hipError_t launch_resgrad_kernel(fea_ctx* c, int cfg, bool loss_only, bool force_plain);
 hipError_t launch_resgrad(fea_ctx* c);
 hipError_t launch_resgrad_cfg(fea_ctx* c, int cfg);
 hipError_t launch_resgrad_at(fea_ctx* c, int cfg, const double* R, const double* T, const double* F,
-                             bool loss_only);
-hipError_t launch_filter_count(fea_ctx* c);
-hipError_t launch_filter_scatter(fea_ctx* c, int dst);
+                             bool loss_only, bool force_plain);
+hipError_t launch_filter_count(fea_ctx* c, const uint32_t* mask);
+hipError_t launch_filter_scatter(fea_ctx* c, int dst, const uint32_t* mask);
 
 // --- per-camera epilogue (fea_camera.hip) ---
-hipError_t launch_camgrad(fea_ctx* c, int do_update);
+hipError_t launch_camgrad(fea_ctx* c, int do_update, bool quad);
+hipError_t launch_quad_build(fea_ctx* c);
 hipError_t launch_focal_update(fea_ctx* c);
 hipError_t launch_loss_sum(fea_ctx* c);
+hipError_t launch_restore(fea_ctx* c, const std::vector<int32_t>& flag);
 hipError_t launch_camgrad_at(fea_ctx* c, const double* R, const double* T, const double* F);
 
 // --- parameters given as device arrays (fea_autograd.hip) ---
@@ -158,5 +211,15 @@ hipError_t launch_params_to_pose(fea_ctx* c, const double* a6, const double* t, 
 hipError_t launch_item_loss(fea_ctx* c, double* loss_out);
 hipError_t launch_param_grad(fea_ctx* c, const double* a6, const double* gout, double* ga6, double* gt,
                              double* glogf);
+
+// --- learned weights (fea_mlp.hip) ---
+hipError_t launch_mlp_weights(fea_ctx* c, const float* params, unsigned short* wout, double* item_wsum,
+                              float* feat_out);
+hipError_t mlp_train_step(hipStream_t st, const float* feat, const float* target, int64_t n, int64_t batch,
+                          int64_t stride, int64_t batch_index, float* params, float* m, float* v, float* gpart,
+                          double* lpart, float* grad, double* loss_acc, float lr, int64_t t);
+hipError_t mlp_grad_once(hipStream_t st, const float* feat, const float* target, int64_t n, const float* params,
+                         float* gpart, double* lpart, float* grad, double* loss_acc);
+int mlp_train_threads();
 
 }  // namespace fea

@@ -58,6 +58,38 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Wave sums of n fp64 values at once, every lane receiving the results.
+// Each DPP stage is applied to all n values before the next, so the n
+// reductions overlap instead of waiting on each other; the fixed order makes
+// the sums reproducible.
+template <int NV>
+__device__ __forceinline__ void wave_sum_f64_multi(double (&v)[NV]) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0xB1>(v[k]);  // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0x4E>(v[k]);  // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0x141>(v[k]);  // row_half_mirror
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0x140>(v[k]);  // row_mirror
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    v[k] = (readlane_f64(v[k], 0) + readlane_f64(v[k], 16)) + (readlane_f64(v[k], 32) + readlane_f64(v[k], 48));
+}
+
 __device__ __forceinline__ double readfirstlane_f64(double v) {
   const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
   const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));

@@ -1,0 +1,486 @@
+// Learned per-match inlier weights for gfx950: an MLP 8 -> 64 -> 64 -> 1
+// (ReLU, ReLU, sigmoid) on each match's features (its epipolar residual at
+// the last three round snapshots, its keypoints scaled to [-1, 1] and the
+// angle between the pair's optical axes).  The weight multiplies the match's
+// IRLS weight in the learned solve.
+//
+// Inference (k_mlp_weights) is a dense contraction, so it runs on the matrix
+// cores: each wave takes 32 matches at a time and evaluates
+//   H1^T = relu(W1 X^T + b1),  H2^T = relu(W2 H1^T + b2),  y = sigmoid(w3.H2 + b3)
+// with v_mfma_f32_32x32x8 bf16 (bf16 activations and weights, fp32
+// accumulation).  With the weights as the A operand and the activations as
+// the B operand, the accumulator of one layer is already laid out as the B
+// operand of the next (lane l holds match l%32 and hidden units
+// 8s + 4(l/32) + 0..3 of K-slice s), so no data moves between layers.
+//
+// Training (k_mlp_fwd_bwd, k_mlp_grad_reduce, k_mlp_adam) runs on the vector
+// units in fp32: one thread per sample for the forward and backward passes,
+// the weight gradients of a workgroup's 128 samples formed from LDS-staged
+// activations, per-workgroup partials summed in a fixed order, then Adam.
+#include <hip/hip_runtime.h>
+
+#include "fea_ctx.h"
+#include "fea_device.h"
+
+namespace fea {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kNF = kMlpFeat;    // 8
+constexpr int kNH = kMlpHidden;  // 64
+constexpr int kOffB1 = kNH * kNF;
+constexpr int kOffW2 = kOffB1 + kNH;
+constexpr int kOffB2 = kOffW2 + kNH * kNH;
+constexpr int kOffW3 = kOffB2 + kNH;
+constexpr int kOffB3 = kOffW3 + kNH;
+
+// fp32 -> bf16, round to nearest even (inputs are finite).
+__device__ __forceinline__ short to_bf16(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float sigmoidf_(float z) { return 1.f / (1.f + __expf(-z)); }
+
+__device__ __forceinline__ double eps_at(const double* F, double x1, double y1, double x2, double y2) {
+  const double l0 = fma(F[0], x1, fma(F[1], y1, F[2]));
+  const double l1 = fma(F[3], x1, fma(F[4], y1, F[5]));
+  const double l2 = fma(F[6], x1, fma(F[7], y1, F[8]));
+  return fma(x2, l0, fma(y2, l1, l2));
+}
+
+// Residual feature: log(1 + |eps| * fbar) / log(257), the residual in pixel
+// equivalents, log-compressed so that 256 px maps to 1 (fp32: the feature
+// enters the network in bf16).
+__device__ __forceinline__ float res_feature(double e, float fbar) {
+  return log1pf((float)fabs(e) * fbar) * 0.18021021f;  // 1 / log(257)
+}
+
+struct Snap3 {
+  const double *R0, *T0, *F0, *R1, *T1, *F1, *R2, *T2, *F2;
+};
+
+__device__ void folded_F(int i, int j, const double* R, const double* T, const double* Fc,
+                         const double* cx, const double* cy, double out[9]) {
+  Geo g;
+  if (pair_geo(R + 9 * i, T + 3 * i, Fc[i], R + 9 * j, T + 3 * j, Fc[j], g))
+    fold_principal_point(g.F, cx[i], cy[i], cx[j], cy[j], out);
+  else
+    for (int k = 0; k < 9; ++k) out[k] = 0.0;
+}
+
+// Per-pair row of the feature table: F folded for raw pixels at the round
+// snapshots r, r-1, r-2; the angle between the optical axes at r over pi/2;
+// 1/cx, 1/cy of both cameras; the scene's median f at the three snapshots.
+constexpr int kSnapRow = 40;
+constexpr int kSnapAng = 27, kSnapInvC = 28, kSnapFbar = 32;
+
+__global__ __launch_bounds__(kPairThreads) void k_snap3(int32_t P, const int32_t* __restrict__ pair_i,
+                                                        const int32_t* __restrict__ pair_j,
+                                                        const int32_t* __restrict__ pair_scene, Snap3 sn,
+                                                        const double* __restrict__ cx,
+                                                        const double* __restrict__ cy,
+                                                        const float* __restrict__ fbar, int n_scenes,
+                                                        double* __restrict__ stab) {
+  const int n = blockIdx.x * kPairThreads + threadIdx.x;
+  if (n >= P) return;
+  const int i = pair_i[n], j = pair_j[n], sc = pair_scene[n];
+  double* row = stab + (int64_t)n * kSnapRow;
+  double F[9];
+  folded_F(i, j, sn.R0, sn.T0, sn.F0, cx, cy, F);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) row[k] = F[k];
+  folded_F(i, j, sn.R1, sn.T1, sn.F1, cx, cy, F);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) row[9 + k] = F[k];
+  folded_F(i, j, sn.R2, sn.T2, sn.F2, cx, cy, F);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) row[18 + k] = F[k];
+  // optical axes are the third rows of the snapshot rotations
+  const double* zi = sn.R0 + 9 * i + 6;
+  const double* zj = sn.R0 + 9 * j + 6;
+  const double cs = fmin(1.0, fmax(-1.0, zi[0] * zj[0] + zi[1] * zj[1] + zi[2] * zj[2]));
+  row[kSnapAng] = acos(cs) / 1.5707963267948966;
+  row[kSnapInvC + 0] = 1.0 / cx[i];
+  row[kSnapInvC + 1] = 1.0 / cy[i];
+  row[kSnapInvC + 2] = 1.0 / cx[j];
+  row[kSnapInvC + 3] = 1.0 / cy[j];
+  row[kSnapFbar + 0] = fbar[sc];
+  row[kSnapFbar + 1] = fbar[n_scenes + sc];
+  row[kSnapFbar + 2] = fbar[2 * n_scenes + sc];
+}
+
+constexpr int kInferThreads = 256;
+
+// Moves 4 floats from lane l^32 (ds_bpermute).
+__device__ __forceinline__ void swap_half(const float (&src)[4], float (&dst)[4]) {
+  const int addr = ((int)__lane_id() ^ 32) << 2;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dst[q] = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(src[q])));
+}
+
+// Inference over one work item.  Each wave takes 64 matches per iteration,
+// one per lane: the lane computes all 8 features of its match once (the
+// residuals in fp64 with the pair's snapshot matrices read by scalar loads),
+// then lanes l and l^32 trade halves so that the two groups of 32 matches
+// are in the B layout of v_mfma_f32_32x32x8bf16 (lane l: features
+// 4(l/32)..+3 of match l%32).  Layer 1 (K = 8) uses that instruction; layer
+// 2 (K = 64) uses v_mfma_f32_32x32x16_bf16, whose B operand takes 8 units per
+// lane: with the contraction index permuted identically in W2's columns, the
+// layer-1 accumulator registers of a lane are that operand as they stand.
+// The next iteration's coordinates are loaded before this one is computed.
+template <bool STORE_FEAT>
+__global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
+    const float* __restrict__ X1, const float* __restrict__ Y1, const float* __restrict__ X2,
+    const float* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ stab,
+    const float* __restrict__ params, unsigned short* __restrict__ Wout, double* __restrict__ item_wsum,
+    float* __restrict__ feat_out) {
+  __shared__ float s_w3[kNH];
+  __shared__ float s_sum[kInferThreads / kWave];
+  const int item = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int4 rec = items[item];
+  const int n = rec.x, start = rec.y, cnt = rec.z;
+  const double* row = stab + (int64_t)n * kSnapRow;
+  if (tid < kNH) s_w3[tid] = params[kOffW3 + tid];
+  // weights in the A layout: row (lane%32) + 32*tile; layer 1 k = 4h + q;
+  // layer 2 slice (t2, g) value j <-> hidden-in unit 32 t2 + 16 g + 8 (j/4) + 4 h + j%4
+  const int r32 = lane & 31, h = lane >> 5;
+  bf16x4 a1[2];
+  bf16x8 a2[2][4];
+  f32x16 b1v[2], b2v[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int orow = r32 + 32 * t;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a1[t][q] = to_bf16(params[orow * kNF + 4 * h + q]);
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+      const int t2 = sl >> 1, g = sl & 1;
+#pragma unroll
+      for (int jv = 0; jv < 8; ++jv) {
+        const int unit = 32 * t2 + 16 * g + 8 * (jv >> 2) + 4 * h + (jv & 3);
+        a2[t][sl][jv] = to_bf16(params[kOffW2 + orow * kNH + unit]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int u = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);  // hidden unit of accumulator r
+      b1v[t][r] = params[kOffB1 + u];
+      b2v[t][r] = params[kOffB2 + u];
+    }
+  }
+  const float b3 = params[kOffB3];
+  double F0[9], F1[9], F2[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    F0[k] = row[k];
+    F1[k] = row[9 + k];
+    F2[k] = row[18 + k];
+  }
+  const float ang = (float)row[kSnapAng];
+  const float icxi = (float)row[kSnapInvC + 0], icyi = (float)row[kSnapInvC + 1];
+  const float icxj = (float)row[kSnapInvC + 2], icyj = (float)row[kSnapInvC + 3];
+  const float fb0 = (float)row[kSnapFbar + 0], fb1 = (float)row[kSnapFbar + 1], fb2 = (float)row[kSnapFbar + 2];
+  __syncthreads();
+
+  constexpr int kStride = kInferThreads;  // matches per iteration of the workgroup
+  float wsum = 0.f;
+  int m = wid * kWave + lane;
+  int idx = start + (m < cnt ? m : 0);
+  float x1 = X1[idx], y1 = Y1[idx], x2 = X2[idx], y2 = Y2[idx];
+  for (int base = wid * kWave; base < cnt; base += kStride) {
+    const bool valid = m < cnt;
+    const int cur = idx;
+    const float cx1 = x1, cy1 = y1, cx2 = x2, cy2 = y2;
+    // prefetch the next iteration's match
+    m += kStride;
+    idx = start + (m < cnt ? m : 0);
+    x1 = X1[idx];
+    y1 = Y1[idx];
+    x2 = X2[idx];
+    y2 = Y2[idx];
+    float f[8];
+    f[0] = res_feature(eps_at(F0, cx1, cy1, cx2, cy2), fb0);
+    f[1] = res_feature(eps_at(F1, cx1, cy1, cx2, cy2), fb1);
+    f[2] = res_feature(eps_at(F2, cx1, cy1, cx2, cy2), fb2);
+    f[3] = fmaf(cx1, icxi, -1.f);
+    f[4] = fmaf(cy1, icyi, -1.f);
+    f[5] = fmaf(cx2, icxj, -1.f);
+    f[6] = fmaf(cy2, icyj, -1.f);
+    f[7] = ang;
+    if (STORE_FEAT && valid) {
+      float4* fo = reinterpret_cast<float4*>(feat_out + (int64_t)cur * kNF);
+      fo[0] = make_float4(f[0], f[1], f[2], f[3]);
+      fo[1] = make_float4(f[4], f[5], f[6], f[7]);
+    }
+    // lanes l and l^32 trade halves: group A = matches of lanes 0..31,
+    // group B = lanes 32..63
+    float send[4], recv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) send[q] = h ? f[q] : f[4 + q];
+    swap_half(send, recv);
+    float zg[2];
+#pragma unroll
+    for (int grp = 0; grp < 2; ++grp) {
+      bf16x4 bx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // group A: h=0 own f[0..3], h=1 partner's f[4..7]; group B: h=0
+        // partner's f[0..3], h=1 own f[4..7]
+        const float v = (grp == 0) ? (h ? recv[q] : f[q]) : (h ? f[4 + q] : recv[q]);
+        bx[q] = to_bf16(v);
+      }
+      f32x16 acc1[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[t], bx, b1v[t], 0, 0, 0);
+      bf16x8 hb[4];
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        const int t2 = sl >> 1, g = sl & 1;
+#pragma unroll
+        for (int jv = 0; jv < 8; ++jv) hb[sl][jv] = to_bf16(fmaxf(acc1[t2][4 * (2 * g + (jv >> 2)) + (jv & 3)], 0.f));
+      }
+      float z = 0.f;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        f32x16 acc = b2v[t];
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t][sl], hb[sl], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int u = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);
+          z = fmaf(s_w3[u], fmaxf(acc[r], 0.f), z);
+        }
+      }
+      // lanes l and l^32 hold the two halves of the group's match l%32
+      z += __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, __float_as_int(z)));
+      zg[grp] = z;
+    }
+    // lane l's own match is in group h
+    const float w = sigmoidf_((h ? zg[1] : zg[0]) + b3);
+    if (valid) {
+      Wout[cur] = (unsigned short)to_bf16(w);
+      wsum += w;
+    }
+  }
+  wsum = wave_sum_f32(wsum);
+  if (lane == 0) s_sum[wid] = wsum;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kInferThreads / kWave; ++w) s += (double)s_sum[w];
+    item_wsum[item] = s;
+  }
+}
+
+// ---- training ---------------------------------------------------------------
+
+constexpr int kTrainThreads = 64;
+
+// Sample k of batch b: ((b*B + k) * stride) mod n, a bijection of [0, n) when
+// gcd(stride, n) = 1, so an epoch visits every sample once (n, stride < 2^31,
+// so the product fits in 64 bits).
+__device__ __forceinline__ int64_t sample_index(int64_t b, int64_t k, int64_t B, int64_t stride, int64_t n) {
+  const uint64_t pos = (uint64_t)(b * B + k) % (uint64_t)n;
+  return (int64_t)((pos * (uint64_t)stride) % (uint64_t)n);
+}
+
+// Forward + backward of the BCE loss for one batch chunk of kTrainThreads
+// samples (one wave); writes this workgroup's gradient partial (kMlpParams
+// floats) and loss partial.  The per-sample gradient is scaled by inv_total
+// (1/batch).  W2 is read from global memory (16 KB, cache-resident).
+__global__ __launch_bounds__(kTrainThreads) void k_mlp_fwd_bwd(
+    const float* __restrict__ feat, const float* __restrict__ target, int64_t n, int64_t batch_begin,
+    int64_t batch_size, int64_t stride, int64_t batch_index, const float* __restrict__ params,
+    float inv_total, float* __restrict__ gpart, double* __restrict__ lpart) {
+  const float* __restrict__ sW2 = params + kOffW2;
+  __shared__ float sH1[kTrainThreads][kNH + 1];
+  __shared__ float sH2[kTrainThreads][kNH + 1];  // later reused for dL/dh1
+  __shared__ float sD2[kTrainThreads][kNH + 1];
+  __shared__ float sX[kTrainThreads][kNF];
+  __shared__ float sDz[kTrainThreads];
+  __shared__ double sL[kTrainThreads / kWave];
+  const int tid = threadIdx.x;
+  const int64_t local = (int64_t)blockIdx.x * kTrainThreads + tid;
+  const bool valid = local < batch_size;
+  const int64_t s = valid ? sample_index(batch_index, local, batch_size, stride, n) : 0;
+  float x[kNF];
+#pragma unroll
+  for (int k = 0; k < kNF; ++k) {
+    x[k] = valid ? feat[s * kNF + k] : 0.f;
+    sX[tid][k] = x[k];
+  }
+  const float t = valid ? target[s] : 0.f;
+  __syncthreads();
+  float h1[kNH];
+#pragma unroll
+  for (int i = 0; i < kNH; ++i) {
+    float z = params[kOffB1 + i];
+#pragma unroll
+    for (int k = 0; k < kNF; ++k) z = fmaf(params[i * kNF + k], x[k], z);
+    h1[i] = fmaxf(z, 0.f);
+    sH1[tid][i] = h1[i];
+  }
+  float z3 = params[kOffB3];
+  float h2[kNH];
+  for (int i = 0; i < kNH; ++i) {
+    float z = params[kOffB2 + i];
+#pragma unroll
+    for (int k = 0; k < kNH; ++k) z = fmaf(sW2[i * kNH + k], h1[k], z);
+    h2[i] = fmaxf(z, 0.f);
+    sH2[tid][i] = h2[i];
+    z3 = fmaf(params[kOffW3 + i], h2[i], z3);
+  }
+  // stable BCE: max(z,0) - z t + log(1 + exp(-|z|))
+  const double li = valid ? (double)(fmaxf(z3, 0.f) - z3 * t + log1pf(__expf(-fabsf(z3)))) : 0.0;
+  const float dz = valid ? (sigmoidf_(z3) - t) * inv_total : 0.f;
+  sDz[tid] = dz;
+  float d2[kNH];
+#pragma unroll
+  for (int i = 0; i < kNH; ++i) {
+    d2[i] = h2[i] > 0.f ? dz * params[kOffW3 + i] : 0.f;
+    sD2[tid][i] = d2[i];
+  }
+  __syncthreads();  // sH2 fully written and read for dw3 below before reuse
+  // dw3 and b3 partials need h2 of every sample: one thread per hidden unit
+  float gw3 = 0.f, gb3 = 0.f;
+  if (tid < kNH)
+    for (int q = 0; q < kTrainThreads; ++q) gw3 = fmaf(sDz[q], sH2[q][tid], gw3);
+  if (tid == 0)
+    for (int q = 0; q < kTrainThreads; ++q) gb3 += sDz[q];
+  __syncthreads();
+  // dL/dh1 (masked by ReLU) into the sH2 slot
+  for (int k = 0; k < kNH; ++k) {
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < kNH; ++i) acc = fmaf(sW2[i * kNH + k], d2[i], acc);
+    sH2[tid][k] = h1[k] > 0.f ? acc : 0.f;
+  }
+  // loss partial
+  double lw = wave_sum_f64(li);
+  if ((tid & 63) == 0) sL[tid >> 6] = lw;
+  __syncthreads();
+  float* gp = gpart + (int64_t)blockIdx.x * kMlpParams;
+  // dW2[i][k] = sum_q D2[q][i] H1[q][k]
+  for (int e = tid; e < kNH * kNH; e += kTrainThreads) {
+    const int i = e / kNH, k = e % kNH;
+    float acc = 0.f;
+    for (int q = 0; q < kTrainThreads; ++q) acc = fmaf(sD2[q][i], sH1[q][k], acc);
+    gp[kOffW2 + e] = acc;
+  }
+  // dW1[i][k] = sum_q D1[q][i] X[q][k]; db1, db2
+  for (int e = tid; e < kNH * kNF; e += kTrainThreads) {
+    const int i = e / kNF, k = e % kNF;
+    float acc = 0.f;
+    for (int q = 0; q < kTrainThreads; ++q) acc = fmaf(sH2[q][i], sX[q][k], acc);
+    gp[e] = acc;
+  }
+  if (tid < kNH) {
+    float a = 0.f, b = 0.f;
+    for (int q = 0; q < kTrainThreads; ++q) {
+      a += sH2[q][tid];
+      b += sD2[q][tid];
+    }
+    gp[kOffB1 + tid] = a;
+    gp[kOffB2 + tid] = b;
+    gp[kOffW3 + tid] = gw3;
+  }
+  if (tid == 0) {
+    gp[kOffB3] = gb3;
+    double L = 0.0;
+    for (int w = 0; w < kTrainThreads / kWave; ++w) L += sL[w];
+    lpart[blockIdx.x] = L;
+  }
+}
+
+// grad[p] = sum over workgroups of their partial (fixed order).
+__global__ void k_mlp_grad_reduce(int n_parts, const float* __restrict__ gpart, float* __restrict__ grad,
+                                  const double* __restrict__ lpart, double* __restrict__ loss_acc) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < kMlpParams) {
+    float s = 0.f;
+    for (int w = 0; w < n_parts; ++w) s += gpart[(int64_t)w * kMlpParams + p];
+    grad[p] = s;
+  }
+  if (p == 0) {
+    double L = 0.0;
+    for (int w = 0; w < n_parts; ++w) L += lpart[w];
+    loss_acc[0] += L;
+  }
+}
+
+__global__ void k_mlp_adam(float* __restrict__ params, float* __restrict__ m, float* __restrict__ v,
+                           const float* __restrict__ grad, float lr, float b1, float b2, float eps, float bc1,
+                           float bc2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kMlpParams) return;
+  const float g = grad[p];
+  const float mm = b1 * m[p] + (1.f - b1) * g;
+  const float vv = b2 * v[p] + (1.f - b2) * g * g;
+  m[p] = mm;
+  v[p] = vv;
+  params[p] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+}
+
+}  // namespace
+
+hipError_t launch_mlp_weights(fea_ctx* c, const float* params, unsigned short* wout, double* item_wsum,
+                              float* feat_out) {
+  if (c->n_items == 0) return hipSuccess;
+  const int b = c->cur;
+  Snap3 sn{c->Rh.as<double>(),  c->Th.as<double>(),  c->Fh.as<double>(),  c->Rh1.as<double>(), c->Th1.as<double>(),
+           c->Fh1.as<double>(), c->Rh2.as<double>(), c->Th2.as<double>(), c->Fh2.as<double>()};
+  k_snap3<<<(unsigned)((c->P + kPairThreads - 1) / kPairThreads), kPairThreads, 0, c->stream>>>(
+      (int32_t)c->P, c->d_pair_i.as<int32_t>(), c->d_pair_j.as<int32_t>(), c->d_pair_scene.as<int32_t>(), sn,
+      c->d_cx.as<double>(), c->d_cy.as<double>(), c->d_fbar.as<float>(), c->S, c->stab.as<double>());
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+#define FEA_MLP_ARGS                                                                                       \
+  c->lay[b][0].as<float>(), c->lay[b][1].as<float>(), c->lay[b][2].as<float>(), c->lay[b][3].as<float>(), \
+      c->item_rec.as<int4>(), c->stab.as<double>(), params, wout, item_wsum
+  if (feat_out)
+    k_mlp_weights<true><<<(unsigned)c->n_items, kInferThreads, 0, c->stream>>>(FEA_MLP_ARGS, feat_out);
+  else
+    k_mlp_weights<false><<<(unsigned)c->n_items, kInferThreads, 0, c->stream>>>(FEA_MLP_ARGS, nullptr);
+#undef FEA_MLP_ARGS
+  return hipGetLastError();
+}
+
+// One training step on `batch` samples: gradient (fixed-order reduction of
+// per-workgroup partials) then Adam (step index t, 1-based).
+hipError_t mlp_train_step(hipStream_t st, const float* feat, const float* target, int64_t n, int64_t batch,
+                          int64_t stride, int64_t batch_index, float* params, float* m, float* v,
+                          float* gpart, double* lpart, float* grad, double* loss_acc, float lr, int64_t t) {
+  const int parts = (int)((batch + kTrainThreads - 1) / kTrainThreads);
+  k_mlp_fwd_bwd<<<parts, kTrainThreads, 0, st>>>(feat, target, n, 0, batch, stride, batch_index, params,
+                                                 1.f / (float)batch, gpart, lpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_mlp_grad_reduce<<<(kMlpParams + 255) / 256, 256, 0, st>>>(parts, gpart, grad, lpart, loss_acc);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float bc1 = 1.f - powf(b1, (float)t), bc2 = 1.f - powf(b2, (float)t);
+  k_mlp_adam<<<(kMlpParams + 255) / 256, 256, 0, st>>>(params, m, v, grad, lr, b1, b2, 1e-8f, bc1, bc2);
+  return hipGetLastError();
+}
+
+// Gradient only (no update) of the mean BCE over samples [0, n) in order
+// (stride 1, one batch): used to check the kernels against the oracle.
+hipError_t mlp_grad_once(hipStream_t st, const float* feat, const float* target, int64_t n, const float* params,
+                         float* gpart, double* lpart, float* grad, double* loss_acc) {
+  const int parts = (int)((n + kTrainThreads - 1) / kTrainThreads);
+  k_mlp_fwd_bwd<<<parts, kTrainThreads, 0, st>>>(feat, target, n, 0, n, 1, 0, params, 1.f / (float)n, gpart,
+                                                 lpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_mlp_grad_reduce<<<(kMlpParams + 255) / 256, 256, 0, st>>>(parts, gpart, grad, lpart, loss_acc);
+  return hipGetLastError();
+}
+
+int mlp_train_threads() { return kTrainThreads; }
+
+}  // namespace fea

@@ -2,16 +2,21 @@
 // Adjustment, the IRLS-reweighted objective) and the round-start outlier
 // filter, for gfx950.
 //
+// k_pair_pose: one thread per camera pair builds the pair's pose block in
+// fp64 -- F at the current poses (every step) and F_hat at the round
+// snapshot (once per round), both with the principal points folded in so
+// they act on raw pixel coordinates -- into a per-pair row of the pose table,
+// with the scene's 1/Z and the pair's principal points.
+//
 // k_resgrad: one workgroup per work item (<= 4096 matches of one camera pair,
 // contiguous in the pair-sorted SoA layout).  Every thread issues all of its
-// 16-byte loads first; meanwhile wave 0 builds the pair's pose block in fp64
-// (F at the current poses and F_hat at the round snapshot, with the principal
-// points folded in) and stages it in LDS, from where every wave moves it to
-// scalar registers.  Per match: eps = q2^T F q1 and eps_hat in fp64 (the
-// residual of an inlier is ~1e-3 of its terms, so fp32 would lose ~4
+// 16-byte loads first; the pair's row is read with scalar loads (the item,
+// hence the pair, is uniform across the workgroup), so no wave waits on
+// another before streaming.  Per match: eps = q2^T F q1 and eps_hat in fp64
+// (the residual of an inlier is ~1e-3 of its terms, so fp32 would lose ~4
 // digits), weight c = 1/(Z max(|eps_hat|, delta)), then the contribution
 // 2 c eps p2 p1^T to dL/dF and c eps^2 to L accumulate per lane in fp32.
-// The 10 sums are reduced across each wave with DPP, across the 4 waves in
+// The 10 sums are reduced across each wave with DPP, across the waves in
 // LDS, and written as one fp64 partial per item -- no atomics, so the result
 // is deterministic.
 #include <hip/hip_runtime.h>
@@ -48,25 +53,56 @@ __device__ __forceinline__ double eval_eps(const double* F, double x1, double y1
   return fma(x2, l0, fma(y2, l1, l2));
 }
 
-template <int THREADS, int STEPS, bool LOSS_ONLY>
-__global__ __launch_bounds__(THREADS) void k_resgrad(
-    const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
-    const float4* __restrict__ Y2, const int32_t* __restrict__ item_pair, const int32_t* __restrict__ item_start,
-    const int32_t* __restrict__ item_count, const int32_t* __restrict__ pair_i, const int32_t* __restrict__ pair_j,
+// Pose block of pair n (i < j) into its row of the pose table: F at
+// (R, T, Fc) and the scene's weight normalisers, every step; with SNAP also
+// F_hat at the snapshot (Rh, Th, Fh), the principal points and the threshold.
+template <bool SNAP>
+__global__ __launch_bounds__(kPairThreads) void k_pair_pose(
+    int32_t P, const int32_t* __restrict__ pair_i, const int32_t* __restrict__ pair_j,
     const double* __restrict__ R, const double* __restrict__ T, const double* __restrict__ Fc,
     const double* __restrict__ Rh, const double* __restrict__ Th, const double* __restrict__ Fh,
     const double* __restrict__ cx, const double* __restrict__ cy, const int32_t* __restrict__ pair_scene,
-    const float* __restrict__ inv_z_scene, float delta, double* __restrict__ part) {
-  __shared__ double s_blk[23];
+    const float* __restrict__ inv_z_scene, const float* __restrict__ inv_zw_scene,
+    const int32_t* __restrict__ scene_mode, const double* __restrict__ tau_scene, double* __restrict__ ptab) {
+  const int n = blockIdx.x * kPairThreads + threadIdx.x;
+  if (n >= P) return;
+  const int i = pair_i[n], j = pair_j[n], sc = pair_scene[n];
+  double* row = ptab + (int64_t)n * kPairRow;
+  double Fp[9];
+  pose_block(i, j, R, T, Fc, cx, cy, Fp);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) row[kRowF + k] = Fp[k];
+  row[kRowInvZ] = (double)inv_z_scene[sc];
+  row[kRowInvZw] = (double)inv_zw_scene[sc];
+  row[kRowMode] = scene_mode[sc] != 0 ? 1.0 : 0.0;
+  if (SNAP) {
+    pose_block(i, j, Rh, Th, Fh, cx, cy, Fp);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) row[kRowFh + k] = Fp[k];
+    row[kRowCx + 0] = cx[i];
+    row[kRowCx + 1] = cy[i];
+    row[kRowCx + 2] = cx[j];
+    row[kRowCx + 3] = cy[j];
+    row[kRowTau] = tau_scene[sc];
+  }
+}
+
+template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
+__global__ __launch_bounds__(THREADS) void k_resgrad(
+    const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
+    const float4* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ ptab, float delta,
+    double* __restrict__ part, const ushort4* __restrict__ Wl) {
   __shared__ float s_red[THREADS / kWave][kPartStride];
   const int tid = threadIdx.x;
   const int item = blockIdx.x;
-  const int n = item_pair[item];
-  const int v0 = item_start[item] >> 2;
-  const int cnt = item_count[item];
+  const int4 rec = items[item];
+  const int n = rec.x;
+  const int v0 = rec.y >> 2;
+  const int cnt = rec.z;
   const int nvec = (cnt + kVec - 1) / kVec;
 
   float4 qa[STEPS], qb[STEPS], qc[STEPS], qd[STEPS];
+  ushort4 qw[WEIGHTED ? STEPS : 1];
 #pragma unroll
   for (int s = 0; s < STEPS; ++s) {
     const int v = s * THREADS + tid;
@@ -75,40 +111,25 @@ __global__ __launch_bounds__(THREADS) void k_resgrad(
       qb[s] = Y1[v0 + v];
       qc[s] = X2[v0 + v];
       qd[s] = Y2[v0 + v];
+      if (WEIGHTED) qw[s] = Wl[v0 + v];
     } else {
       qa[s] = qb[s] = qc[s] = qd[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (WEIGHTED) qw[s] = make_ushort4(0, 0, 0, 0);
     }
   }
-  if (tid < kWave) {
-    const int i = pair_i[n], j = pair_j[n];
-    double F[9], Fhat[9];
-    pose_block(i, j, R, T, Fc, cx, cy, F);
-    pose_block(i, j, Rh, Th, Fh, cx, cy, Fhat);
-    if (tid == 0) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        s_blk[k] = F[k];
-        s_blk[9 + k] = Fhat[k];
-      }
-      s_blk[18] = cx[i];
-      s_blk[19] = cy[i];
-      s_blk[20] = cx[j];
-      s_blk[21] = cy[j];
-      s_blk[22] = inv_z_scene[pair_scene[n]];
-    }
-  }
-  __syncthreads();
+  const double* row = ptab + (int64_t)n * kPairRow;
   double F[9], Fhat[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    F[k] = readfirstlane_f64(s_blk[k]);
-    Fhat[k] = readfirstlane_f64(s_blk[9 + k]);
+    F[k] = row[kRowF + k];
+    Fhat[k] = row[kRowFh + k];
   }
-  const float cxi = (float)readfirstlane_f64(s_blk[18]);
-  const float cyi = (float)readfirstlane_f64(s_blk[19]);
-  const float cxj = (float)readfirstlane_f64(s_blk[20]);
-  const float cyj = (float)readfirstlane_f64(s_blk[21]);
-  const float inv_z = (float)readfirstlane_f64(s_blk[22]);
+  const float cxi = (float)row[kRowCx + 0];
+  const float cyi = (float)row[kRowCx + 1];
+  const float cxj = (float)row[kRowCx + 2];
+  const float cyj = (float)row[kRowCx + 3];
+  const bool learned = WEIGHTED && row[kRowMode] != 0.0;
+  const float inv_z = (float)(learned ? row[kRowInvZw] : row[kRowInvZ]);
 
   float acc[kPartStride];
 #pragma unroll
@@ -123,7 +144,12 @@ __global__ __launch_bounds__(THREADS) void k_resgrad(
       const double eph = eval_eps(Fhat, x1, y1, x2, y2);
       const float ef = (float)eps;
       const float w = fmaxf(fabsf((float)eph), delta);
-      const float c = (local < cnt) ? inv_z * __builtin_amdgcn_rcpf(w) : 0.f;
+      float c = inv_z * __builtin_amdgcn_rcpf(w);
+      if (WEIGHTED && learned) {
+        const unsigned short wb = e == 0 ? qw[s].x : (e == 1 ? qw[s].y : (e == 2 ? qw[s].z : qw[s].w));
+        c *= __uint_as_float((uint32_t)wb << 16);
+      }
+      c = (local < cnt) ? c : 0.f;  // alignment padding holds no weight
       if (!LOSS_ONLY) {
         const float k2 = 2.f * c * ef;
         const float x1c = x1 - cxi, y1c = y1 - cyi, x2c = x2 - cxj, y2c = y2 - cyj;
@@ -156,42 +182,49 @@ __global__ __launch_bounds__(THREADS) void k_resgrad(
   }
 }
 
-// Round start, pass 1: how many matches of each item survive the filter
-// |eps_hat| < tau (strict; Method > Epipolar Adjustment, outlier filtering).
+// Whether slot value `pos` (a sorted position, -1 for padding) is set in the
+// bit mask over sorted positions.
+__device__ __forceinline__ bool mask_bit(const uint32_t* __restrict__ mask, int pos) {
+  return pos >= 0 && ((mask[pos >> 5] >> (pos & 31)) & 1u);
+}
+
+// Round start, pass 1: how many matches of each item survive -- the filter
+// |eps_hat| < tau (strict; Method > Epipolar Adjustment, outlier filtering),
+// or, with BY_MASK, membership in a saved retained set (resume from a
+// checkpoint).
+template <bool BY_MASK>
 __global__ __launch_bounds__(kFilterThreads) void k_filter_count(
     const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
-    const float4* __restrict__ Y2, const int32_t* __restrict__ item_pair, const int32_t* __restrict__ item_start,
-    const int32_t* __restrict__ item_count, const int32_t* __restrict__ pair_i, const int32_t* __restrict__ pair_j,
-    const double* __restrict__ Rh, const double* __restrict__ Th, const double* __restrict__ Fh,
-    const double* __restrict__ cx, const double* __restrict__ cy, const int32_t* __restrict__ pair_scene,
-    const double* __restrict__ tau_scene, int32_t* __restrict__ keep) {
-  __shared__ double s_blk[10];
+    const float4* __restrict__ Y2, const int4* __restrict__ POS, const int4* __restrict__ items,
+    const double* __restrict__ ptab, const uint32_t* __restrict__ mask, int32_t* __restrict__ keep) {
   __shared__ int s_cnt;
   const int tid = threadIdx.x, item = blockIdx.x;
-  const int n = item_pair[item];
-  const int v0 = item_start[item] >> 2;
-  const int cnt = item_count[item];
+  const int4 rec = items[item];
+  const int n = rec.x;
+  const int v0 = rec.y >> 2;
+  const int cnt = rec.z;
   const int nvec = (cnt + kVec - 1) / kVec;
-  if (tid == 0) {
-    double Fhat[9];
-    pose_block(pair_i[n], pair_j[n], Rh, Th, Fh, cx, cy, Fhat);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) s_blk[k] = Fhat[k];
-    s_blk[9] = tau_scene[pair_scene[n]];
-    s_cnt = 0;
-  }
-  __syncthreads();
+  const double* row = ptab + (int64_t)n * kPairRow;
   double Fhat[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) Fhat[k] = s_blk[k];
-  const double tau = s_blk[9];
+  for (int k = 0; k < 9; ++k) Fhat[k] = row[kRowFh + k];
+  const double tau = row[kRowTau];
+  if (tid == 0) s_cnt = 0;
+  __syncthreads();
   int kept = 0;
   for (int v = tid; v < nvec; v += kFilterThreads) {
-    const float4 a = X1[v0 + v], b = Y1[v0 + v], c = X2[v0 + v], d = Y2[v0 + v];
+    if (BY_MASK) {
+      const int4 p = POS[v0 + v];
+      const int pe[4] = {p.x, p.y, p.z, p.w};
 #pragma unroll
-    for (int e = 0; e < kVec; ++e) {
-      const double eph = eval_eps(Fhat, v4(a, e), v4(b, e), v4(c, e), v4(d, e));
-      kept += (v * kVec + e < cnt) && (fabs(eph) < tau);
+      for (int e = 0; e < kVec; ++e) kept += (v * kVec + e < cnt) && mask_bit(mask, pe[e]);
+    } else {
+      const float4 a = X1[v0 + v], b = Y1[v0 + v], c = X2[v0 + v], d = Y2[v0 + v];
+#pragma unroll
+      for (int e = 0; e < kVec; ++e) {
+        const double eph = eval_eps(Fhat, v4(a, e), v4(b, e), v4(c, e), v4(d, e));
+        kept += (v * kVec + e < cnt) && (fabs(eph) < tau);
+      }
     }
   }
   atomicAdd(&s_cnt, kept);
@@ -201,34 +234,25 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_count(
 
 // Round start, pass 2: stable compaction of the surviving matches into the
 // other layout buffer.  base[item] is where the item's first survivor goes.
+template <bool BY_MASK>
 __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
-    const float4* __restrict__ Y2, const int4* __restrict__ POS, const int32_t* __restrict__ item_pair,
-    const int32_t* __restrict__ item_start, const int32_t* __restrict__ item_count,
-    const int32_t* __restrict__ pair_i, const int32_t* __restrict__ pair_j, const double* __restrict__ Rh,
-    const double* __restrict__ Th, const double* __restrict__ Fh, const double* __restrict__ cx,
-    const double* __restrict__ cy, const int32_t* __restrict__ pair_scene, const double* __restrict__ tau_scene,
-    const int32_t* __restrict__ base, float* __restrict__ ox1,
-    float* __restrict__ oy1, float* __restrict__ ox2, float* __restrict__ oy2, int32_t* __restrict__ opos) {
-  __shared__ double s_blk[10];
+    const float4* __restrict__ Y2, const int4* __restrict__ POS, const int4* __restrict__ items,
+    const double* __restrict__ ptab, const uint32_t* __restrict__ mask, const int32_t* __restrict__ base,
+    float* __restrict__ ox1, float* __restrict__ oy1, float* __restrict__ ox2, float* __restrict__ oy2,
+    int32_t* __restrict__ opos) {
   __shared__ int s_w[kFilterThreads / kWave];
   const int tid = threadIdx.x, item = blockIdx.x;
-  const int n = item_pair[item];
-  const int v0 = item_start[item] >> 2;
-  const int cnt = item_count[item];
+  const int4 rec = items[item];
+  const int n = rec.x;
+  const int v0 = rec.y >> 2;
+  const int cnt = rec.z;
   const int nvec = (cnt + kVec - 1) / kVec;
-  if (tid == 0) {
-    double Fhat[9];
-    pose_block(pair_i[n], pair_j[n], Rh, Th, Fh, cx, cy, Fhat);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) s_blk[k] = Fhat[k];
-    s_blk[9] = tau_scene[pair_scene[n]];
-  }
-  __syncthreads();
+  const double* row = ptab + (int64_t)n * kPairRow;
   double Fhat[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) Fhat[k] = s_blk[k];
-  const double tau = s_blk[9];
+  for (int k = 0; k < 9; ++k) Fhat[k] = row[kRowFh + k];
+  const double tau = row[kRowTau];
   int run = base[item];
   const int lane = tid & 63, wid = tid >> 6;
   const int rounds = (nvec + kFilterThreads - 1) / kFilterThreads;
@@ -243,11 +267,18 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
       d = Y2[v0 + v];
       p = POS[v0 + v];
     }
+    const int pe[4] = {p.x, p.y, p.z, p.w};
     int flags = 0, mine = 0;
 #pragma unroll
     for (int e = 0; e < kVec; ++e) {
-      const double eph = eval_eps(Fhat, v4(a, e), v4(b, e), v4(c, e), v4(d, e));
-      const int k = (v < nvec) && (v * kVec + e < cnt) && (fabs(eph) < tau);
+      bool pass;
+      if (BY_MASK) {
+        pass = mask_bit(mask, pe[e]);
+      } else {
+        const double eph = eval_eps(Fhat, v4(a, e), v4(b, e), v4(c, e), v4(d, e));
+        pass = fabs(eph) < tau;
+      }
+      const int k = (v < nvec) && (v * kVec + e < cnt) && pass;
       flags |= k << e;
       mine += k;
     }
@@ -263,7 +294,6 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     }
     __syncthreads();
     int dst = run + before + inc - mine;
-    const int pe[4] = {p.x, p.y, p.z, p.w};
 #pragma unroll
     for (int e = 0; e < kVec; ++e) {
       if (flags & (1 << e)) {
@@ -281,88 +311,123 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
 
 }  // namespace
 
-template <int THREADS, int STEPS, bool LOSS_ONLY>
-hipError_t launch_resgrad_t(fea_ctx* c, const double* R, const double* T, const double* F) {
-  const int b = c->cur;
-  k_resgrad<THREADS, STEPS, LOSS_ONLY><<<(unsigned)c->n_items, THREADS, 0, c->stream>>>(
-      c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(),
-      c->item_pair.as<int32_t>(), c->item_start.as<int32_t>(), c->item_count.as<int32_t>(),
-      c->d_pair_i.as<int32_t>(), c->d_pair_j.as<int32_t>(), R, T, F, c->Rh.as<double>(), c->Th.as<double>(),
-      c->Fh.as<double>(), c->d_cx.as<double>(), c->d_cy.as<double>(), c->d_pair_scene.as<int32_t>(),
-      c->d_inv_z.as<float>(), (float)c->opt.delta, c->part.as<double>());
+hipError_t launch_pair_pose(fea_ctx* c, const double* R, const double* T, const double* F, bool snap) {
+  if (c->P == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((c->P + kPairThreads - 1) / kPairThreads);
+#define FEA_PAIR_POSE_ARGS                                                                                   \
+  (int32_t)c->P, c->d_pair_i.as<int32_t>(), c->d_pair_j.as<int32_t>(), R, T, F, c->Rh.as<double>(),          \
+      c->Th.as<double>(), c->Fh.as<double>(), c->d_cx.as<double>(), c->d_cy.as<double>(),                  \
+      c->d_pair_scene.as<int32_t>(), c->d_inv_z.as<float>(), c->d_inv_zw.as<float>(),                     \
+      c->d_scene_mode.as<int32_t>(), c->d_tau.as<double>(), c->ptab.as<double>()
+  if (snap)
+    k_pair_pose<true><<<blocks, kPairThreads, 0, c->stream>>>(FEA_PAIR_POSE_ARGS);
+  else
+    k_pair_pose<false><<<blocks, kPairThreads, 0, c->stream>>>(FEA_PAIR_POSE_ARGS);
+#undef FEA_PAIR_POSE_ARGS
   return hipGetLastError();
 }
 
-template <bool LOSS_ONLY>
-hipError_t launch_resgrad_sel(fea_ctx* c, int cfg, const double* R, const double* T, const double* F) {
+template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
+hipError_t launch_resgrad_t(fea_ctx* c) {
+  const int b = c->cur;
+  k_resgrad<THREADS, STEPS, LOSS_ONLY, WEIGHTED><<<(unsigned)c->n_items, THREADS, 0, c->stream>>>(
+      c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(),
+      c->item_rec.as<int4>(), c->ptab.as<double>(),
+      (float)c->opt.delta, c->part.as<double>(), c->wlay.as<ushort4>());
+  return hipGetLastError();
+}
+
+template <bool LOSS_ONLY, bool WEIGHTED>
+hipError_t launch_resgrad_sel(fea_ctx* c, int cfg) {
   switch (cfg) {
-    case 0: return launch_resgrad_t<256, 4, LOSS_ONLY>(c, R, T, F);
-    case 1: return launch_resgrad_t<256, 2, LOSS_ONLY>(c, R, T, F);
-    case 2: return launch_resgrad_t<256, 1, LOSS_ONLY>(c, R, T, F);
-    case 3: return launch_resgrad_t<128, 8, LOSS_ONLY>(c, R, T, F);
-    case 4: return launch_resgrad_t<128, 4, LOSS_ONLY>(c, R, T, F);
-    case 5: return launch_resgrad_t<128, 2, LOSS_ONLY>(c, R, T, F);
-    case 6: return launch_resgrad_t<512, 2, LOSS_ONLY>(c, R, T, F);
-    case 7: return launch_resgrad_t<512, 4, LOSS_ONLY>(c, R, T, F);
+    case 0: return launch_resgrad_t<256, 4, LOSS_ONLY, WEIGHTED>(c);
+    case 1: return launch_resgrad_t<256, 2, LOSS_ONLY, WEIGHTED>(c);
+    case 2: return launch_resgrad_t<256, 1, LOSS_ONLY, WEIGHTED>(c);
+    case 3: return launch_resgrad_t<128, 8, LOSS_ONLY, WEIGHTED>(c);
+    case 4: return launch_resgrad_t<128, 4, LOSS_ONLY, WEIGHTED>(c);
+    case 5: return launch_resgrad_t<128, 2, LOSS_ONLY, WEIGHTED>(c);
+    case 6: return launch_resgrad_t<512, 2, LOSS_ONLY, WEIGHTED>(c);
+    case 7: return launch_resgrad_t<512, 4, LOSS_ONLY, WEIGHTED>(c);
   }
   return hipErrorInvalidValue;
 }
 
-// Per-match kernel with tile shape `cfg` over the current items at poses
-// (R, T, F) (per camera, fp64), weights from the round snapshot.
-hipError_t launch_resgrad_at(fea_ctx* c, int cfg, const double* R, const double* T, const double* F,
-                             bool loss_only) {
+// The per-match kernel alone, with tile shape `cfg`, over the current items;
+// the pose table must hold F for the poses wanted.
+hipError_t launch_resgrad_kernel(fea_ctx* c, int cfg, bool loss_only, bool force_plain) {
   if (c->n_items == 0) return hipSuccess;
-  return loss_only ? launch_resgrad_sel<true>(c, cfg, R, T, F) : launch_resgrad_sel<false>(c, cfg, R, T, F);
+  const bool w = c->learned_any && !force_plain;
+  if (loss_only) return w ? launch_resgrad_sel<true, true>(c, cfg) : launch_resgrad_sel<true, false>(c, cfg);
+  return w ? launch_resgrad_sel<false, true>(c, cfg) : launch_resgrad_sel<false, false>(c, cfg);
+}
+
+// Pose table at poses (R, T, F) (per camera, fp64), then the per-match kernel
+// with tile shape `cfg`; weights from the round snapshot.
+hipError_t launch_resgrad_at(fea_ctx* c, int cfg, const double* R, const double* T, const double* F,
+                             bool loss_only, bool force_plain) {
+  if (c->n_items == 0) return hipSuccess;
+  hipError_t e = launch_pair_pose(c, R, T, F, false);
+  if (e != hipSuccess) return e;
+  return launch_resgrad_kernel(c, cfg, loss_only, force_plain);
 }
 
 hipError_t launch_resgrad_cfg(fea_ctx* c, int cfg) {
   return launch_resgrad_at(c, cfg, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
-                           c->Fc[c->pcur].as<double>(), false);
+                           c->Fc[c->pcur].as<double>(), false, false);
 }
 
+// One step's per-match pass at the current poses; with kernel timing on, HIP
+// events bracket the per-match kernel alone.
 hipError_t launch_resgrad(fea_ctx* c) {
   if (c->n_items == 0) return hipSuccess;
+  hipError_t err = launch_pair_pose(c, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
+                                    c->Fc[c->pcur].as<double>(), false);
+  if (err != hipSuccess) return err;
   hipEvent_t ev1 = nullptr;
   if (c->timing) {
     while (c->ev_pool.size() < c->ev_used + 2) {
       hipEvent_t e;
-      hipError_t err = hipEventCreate(&e);
+      err = hipEventCreate(&e);
       if (err != hipSuccess) return err;
       c->ev_pool.push_back(e);
     }
-    hipError_t err = hipEventRecord(c->ev_pool[c->ev_used], c->stream);
+    err = hipEventRecord(c->ev_pool[c->ev_used], c->stream);
     if (err != hipSuccess) return err;
     ev1 = c->ev_pool[c->ev_used + 1];
     c->ev_used += 2;
   }
-  hipError_t err = launch_resgrad_cfg(c, c->tile_cfg);
+  err = launch_resgrad_kernel(c, c->tile_cfg, false, false);
   if (err == hipSuccess && ev1) err = hipEventRecord(ev1, c->stream);
   return err;
 }
 
-hipError_t launch_filter_count(fea_ctx* c) {
+hipError_t launch_filter_count(fea_ctx* c, const uint32_t* mask) {
   if (c->n_items == 0) return hipSuccess;
   const int b = c->cur;
-  k_filter_count<<<(unsigned)c->n_items, kFilterThreads, 0, c->stream>>>(
-      c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(),
-      c->item_pair.as<int32_t>(), c->item_start.as<int32_t>(), c->item_count.as<int32_t>(),
-      c->d_pair_i.as<int32_t>(), c->d_pair_j.as<int32_t>(), c->Rh.as<double>(), c->Th.as<double>(),
-      c->Fh.as<double>(), c->d_cx.as<double>(), c->d_cy.as<double>(), c->d_pair_scene.as<int32_t>(),
-      c->d_tau.as<double>(), c->item_keep.as<int32_t>());
+#define FEA_FILTER_COUNT_ARGS                                                                                 \
+  c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(), \
+      c->lpos[b].as<int4>(), c->item_rec.as<int4>(), c->ptab.as<double>(), mask, c->item_keep.as<int32_t>()
+  if (mask)
+    k_filter_count<true><<<(unsigned)c->n_items, kFilterThreads, 0, c->stream>>>(FEA_FILTER_COUNT_ARGS);
+  else
+    k_filter_count<false><<<(unsigned)c->n_items, kFilterThreads, 0, c->stream>>>(FEA_FILTER_COUNT_ARGS);
+#undef FEA_FILTER_COUNT_ARGS
   return hipGetLastError();
 }
 
-hipError_t launch_filter_scatter(fea_ctx* c, int dst) {
+hipError_t launch_filter_scatter(fea_ctx* c, int dst, const uint32_t* mask) {
   if (c->n_items == 0) return hipSuccess;
   const int b = c->cur;
-  k_filter_scatter<<<(unsigned)c->n_items, kFilterThreads, 0, c->stream>>>(
-      c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(),
-      c->lpos[b].as<int4>(), c->item_pair.as<int32_t>(), c->item_start.as<int32_t>(),
-      c->item_count.as<int32_t>(), c->d_pair_i.as<int32_t>(), c->d_pair_j.as<int32_t>(), c->Rh.as<double>(),
-      c->Th.as<double>(), c->Fh.as<double>(), c->d_cx.as<double>(), c->d_cy.as<double>(),
-      c->d_pair_scene.as<int32_t>(), c->d_tau.as<double>(), c->item_base.as<int32_t>(), c->lay[dst][0].as<float>(), c->lay[dst][1].as<float>(),
-      c->lay[dst][2].as<float>(), c->lay[dst][3].as<float>(), c->lpos[dst].as<int32_t>());
+#define FEA_FILTER_SCATTER_ARGS                                                                               \
+  c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(), \
+      c->lpos[b].as<int4>(), c->item_rec.as<int4>(), c->ptab.as<double>(), mask, c->item_base.as<int32_t>(),  \
+      c->lay[dst][0].as<float>(), c->lay[dst][1].as<float>(), c->lay[dst][2].as<float>(),                    \
+      c->lay[dst][3].as<float>(), c->lpos[dst].as<int32_t>()
+  if (mask)
+    k_filter_scatter<true><<<(unsigned)c->n_items, kFilterThreads, 0, c->stream>>>(FEA_FILTER_SCATTER_ARGS);
+  else
+    k_filter_scatter<false><<<(unsigned)c->n_items, kFilterThreads, 0, c->stream>>>(FEA_FILTER_SCATTER_ARGS);
+#undef FEA_FILTER_SCATTER_ARGS
   return hipGetLastError();
 }
 

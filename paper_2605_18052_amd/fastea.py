@@ -31,13 +31,15 @@ class fea_options(C.Structure):
                 ("log_every", C.c_int32), ("max_log", C.c_int32),
                 ("lr_decay", C.c_double), ("reset_moments", C.c_int32),
                 ("tile_matches", C.c_int32), ("use_graphs", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("weight_mode", C.c_int32), ("inner_loop", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class fea_report(C.Structure):
     _fields_ = [("rounds_run", C.c_int32), ("iters_run", C.c_int32),
                 ("inliers_per_round", C.c_int64 * 64), ("loss_per_round", C.c_double * 64),
-                ("ms_total", C.c_double), ("n_logged", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("ms_total", C.c_double), ("n_logged", C.c_int32), ("fallbacks", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class fea_info(C.Structure):
@@ -68,7 +70,13 @@ _SIGNATURES = {
     "fea_set_options": ([_P, _P], C.c_int),
     "fea_load_intrinsics": ([_P, C.c_int32, _P, _P, _P, _P], C.c_int),
     "fea_set_scenes": ([_P, C.c_int32, _P], C.c_int),
-    "fea_get_scene_stats": ([_P, _P, _P, _P, _P], C.c_int),
+    "fea_get_scene_stats": ([_P, _P, _P, _P, _P, _P], C.c_int),
+    "fea_set_mlp": ([_P, _P], C.c_int),
+    "fea_mlp_features_dev": ([_P, _P, _P], C.c_int),
+    "fea_get_learned_weights": ([_P, _P], C.c_int),
+    "fea_mlp_train": ([C.c_int32, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_double, C.c_uint64, _P,
+                       _P], C.c_int),
+    "fea_mlp_grad": ([C.c_int32, _P, _P, C.c_int64, _P, _P, _P], C.c_int),
     "fea_load_matches": ([_P, C.c_int64, _P, _P, _P, _P, _P, _P], C.c_int),
     "fea_load_matches_device": ([_P, C.c_int64, _P, _P, _P, _P, _P, _P], C.c_int),
     "fea_init_poses": ([_P, _P, _P], C.c_int),
@@ -84,6 +92,8 @@ _SIGNATURES = {
     "fea_get_segments": ([_P, _P, _P, _P, _P], C.c_int),
     "fea_get_mask": ([_P, _P, _P], C.c_int),
     "fea_get_info": ([_P, _P], C.c_int),
+    "fea_get_state": ([_P, _P, _P], C.c_int),
+    "fea_set_state": ([_P, _P, C.c_size_t], C.c_int),
     "fea_synchronize": ([_P], C.c_int),
     "fea_get_rotation_log": ([_P, _P, _P], C.c_int),
     "fea_set_kernel_timing": ([_P, C.c_int32], C.c_int),
@@ -120,6 +130,42 @@ def hbm_probe(device=0, nbytes=1 << 30, reps=5):
     if rc != FEA_OK:
         raise FeaError(rc, lib().fea_status_string(rc).decode())
     return r.value, w.value
+
+
+MLP_FEATURES = 8
+MLP_PARAMS = 4801
+
+
+def mlp_train(feat, target, params, epochs=3, batch=16384, lr=1e-3, seed=0, device=0):
+    """Train in place on torch device tensors (feat [n,8] f32, target [n] f32,
+    params [4801] f32); returns the mean loss per epoch."""
+    import torch
+    n = int(feat.shape[0])
+    for x in (feat, target, params):
+        if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+            raise ValueError("feat, target and params must be contiguous float32 CUDA tensors")
+    losses = np.zeros(max(epochs, 1))
+    torch.cuda.current_stream().synchronize()
+    rc = lib().fea_mlp_train(int(device), C.c_void_p(feat.data_ptr()), C.c_void_p(target.data_ptr()),
+                             n, int(epochs), int(batch), float(lr), int(seed),
+                             C.c_void_p(params.data_ptr()), losses.ctypes.data_as(_P))
+    if rc != FEA_OK:
+        raise FeaError(rc, lib().fea_status_string(rc).decode())
+    return losses[:epochs]
+
+
+def mlp_grad(feat, target, params, device=0):
+    """(mean BCE loss, gradient [4801] torch tensor) over all samples."""
+    import torch
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feat.device)
+    loss = C.c_double(0.0)
+    torch.cuda.current_stream().synchronize()
+    rc = lib().fea_mlp_grad(int(device), C.c_void_p(feat.data_ptr()), C.c_void_p(target.data_ptr()),
+                            int(feat.shape[0]), C.c_void_p(params.data_ptr()),
+                            C.c_void_p(grad.data_ptr()), C.byref(loss))
+    if rc != FEA_OK:
+        raise FeaError(rc, lib().fea_status_string(rc).decode())
+    return loss.value, grad
 
 
 def default_options(**kw) -> fea_options:
@@ -198,9 +244,36 @@ class Context:
         ret = np.zeros(S, np.int64)
         gc = np.zeros((S, 3))
         gs = np.zeros(S)
+        lm = np.zeros(S, np.int32)
         self._check(lib().fea_get_scene_stats(self._h, loss.ctypes.data_as(_P), ret.ctypes.data_as(_P),
-                                              gc.ctypes.data_as(_P), gs.ctypes.data_as(_P)))
-        return dict(loss=loss, retained=ret, gauge_center=gc, gauge_scale=gs)
+                                              gc.ctypes.data_as(_P), gs.ctypes.data_as(_P),
+                                              lm.ctypes.data_as(_P)))
+        return dict(loss=loss, retained=ret, gauge_center=gc, gauge_scale=gs, learned=lm)
+
+    # -- learned inlier weights --
+    def set_mlp(self, params):
+        params, p = _host(params, np.float32)
+        if params.size != MLP_PARAMS:
+            raise ValueError(f"expected {MLP_PARAMS} parameters")
+        self._check(lib().fea_set_mlp(self._h, p))
+
+    def mlp_features(self):
+        """(features [layout,8], slot position [layout]) torch device tensors."""
+        import torch
+        L = self.info()["layout_matches"]
+        dev = torch.device("cuda", self.device)
+        feat = torch.empty(max(L, 1), MLP_FEATURES, dtype=torch.float32, device=dev)
+        pos = torch.empty(max(L, 1), dtype=torch.int32, device=dev)
+        torch.cuda.current_stream().synchronize()
+        self._check(lib().fea_mlp_features_dev(self._h, self._dev(feat), self._dev(pos)))
+        self.synchronize()
+        return feat[:L], pos[:L]
+
+    def learned_weights(self):
+        M = self.info()["n_matches"]
+        w = np.zeros(max(M, 1), np.float32)
+        self._check(lib().fea_get_learned_weights(self._h, w.ctypes.data_as(_P)))
+        return w[:M]
 
     def load_matches(self, x1, y1, x2, y2, cam1, cam2):
         if _is_torch(x1) and x1.is_cuda:
@@ -287,7 +360,7 @@ class Context:
         return dict(rounds_run=r, iters_run=rep.iters_run,
                     inliers=np.array(rep.inliers_per_round[:min(r, 64)]),
                     loss=np.array(rep.loss_per_round[:min(r, 64)]), ms_total=rep.ms_total,
-                    n_logged=rep.n_logged)
+                    n_logged=rep.n_logged, fallbacks=rep.fallbacks)
 
     def get_poses(self):
         N = self.n_cams
@@ -321,6 +394,18 @@ class Context:
         z = C.c_int64(0)
         self._check(lib().fea_get_mask(self._h, mask.ctypes.data_as(_P), C.byref(z)))
         return mask[:M].astype(bool), z.value
+
+    def get_state(self):
+        """Checkpoint of the solver state (bytes)."""
+        n = C.c_size_t(0)
+        self._check(lib().fea_get_state(self._h, None, C.byref(n)))
+        buf = np.zeros(n.value, np.uint8)
+        self._check(lib().fea_get_state(self._h, buf.ctypes.data_as(_P), C.byref(n)))
+        return buf.tobytes()
+
+    def set_state(self, state):
+        buf = np.frombuffer(state, np.uint8)
+        self._check(lib().fea_set_state(self._h, buf.ctypes.data_as(_P), len(buf)))
 
     def set_kernel_timing(self, enable=True):
         self._check(lib().fea_set_kernel_timing(self._h, 1 if enable else 0))

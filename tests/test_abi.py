@@ -42,7 +42,7 @@ def test_version_and_defaults(so):
     o = fastea.default_options()
     assert o.rounds == 20 and o.iters_per_round == 50 and o.tau_px_init == 128.0
     assert o.lr_decay == 0.9 and o.reset_moments == 1 and o.tile_matches == 0
-    assert o.use_graphs == 1
+    assert o.use_graphs == 1 and o.weight_mode == 0
     assert fastea.lib().fea_default_options(None) == fastea.FEA_EINVAL
     assert fastea.lib().fea_status_string(fastea.FEA_ESTATE) == b"call out of order"
 
@@ -51,7 +51,7 @@ def test_struct_sizes_match_c_layout():
     from paper_2605_18052_amd import fastea
     # int32 x2 + double x10 + int32 x4 + double + int32 x2 + int32 x6
     assert ctypes.sizeof(fastea.fea_options) == 8 + 80 + 16 + 8 + 8 + 24
-    assert ctypes.sizeof(fastea.fea_report) == 8 + 512 + 512 + 8 + 4 + 28
+    assert ctypes.sizeof(fastea.fea_report) == 8 + 512 + 512 + 8 + 4 + 4 + 24
     assert ctypes.sizeof(fastea.fea_info) == 8 + 40 + 8 + 24 + 8 + 8 + 32
 
 
