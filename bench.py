@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1-degree solve")
     ap.add_argument("--cpu-sample", type=int, default=6_000_000)
     ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--batch", action="store_true",
+                    help="also solve 64 uneven scenes (~120M matches) batched and one by one")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -97,32 +99,22 @@ def cpu_baseline(sc, n_sample, iters):
                       f"{dt:.1f} s wall"}
 
 
-def _solve(ctx, opt, n_iters):
-    """The library's IRLS schedule (begin_round + steps), stopped after
-    n_iters steps."""
-    it = 0
-    for r in range(opt.rounds):
-        if it >= n_iters:
-            break
-        ctx.begin_round(max(opt.tau_px_init * opt.tau_decay ** r, opt.tau_px_min))
-        k = min(opt.iters_per_round, n_iters - it)
-        ctx.step(k)
-        it += k
-    ctx.synchronize()
-    return it
-
-
 def time_to_one_degree(sc, fastea, metrics, every=10, **options):
-    """Wall time from the initial poses to the first logged step whose mean
+    """Wall time of fea_epipolar_adjust from the initial poses until the mean
     rotation error is <= 1 deg.  A first solve keeps every `every`-th step's
     rotations in the device-side log (ground truth never enters the solver;
-    errors are computed afterwards); a second, fresh solve of exactly that
-    many steps is timed, with nothing read back until it ends."""
+    errors are computed afterwards); a second, fresh solve runs the rounds up
+    to the one containing the first logged step at <= 1 deg and is timed,
+    with nothing read back until it returns."""
+    mlp = options.pop("mlp", None)
+
     def setup(**extra):
-        opt = fastea.default_options(**options, **extra)
+        opt = fastea.default_options(**{**options, **extra})
         ctx = fastea.Context(0, opt)
         ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
         ctx.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+        if mlp is not None:
+            ctx.set_mlp(mlp)
         ctx.init_poses(sc.R_init, sc.t_init)
         ctx.synchronize()
         return ctx, opt
@@ -131,27 +123,80 @@ def time_to_one_degree(sc, fastea, metrics, every=10, **options):
     total_iters = base.rounds * base.iters_per_round
     ctx, opt = setup(log_every=every, max_log=max(total_iters // every, 1))
     t0 = time.perf_counter()
-    _solve(ctx, opt, total_iters)
+    rep = ctx.epipolar_adjust()
+    ctx.synchronize()
     full = time.perf_counter() - t0
     log_R = ctx.get_rotation_log(total_iters // every)
     ctx.close()
     errs = [metrics.mean_rotation_error_deg(R, sc.R_gt) for R in log_R]
     k = next((i for i, e in enumerate(errs) if e <= 1.0), None)
-    out = {"wall_to_1deg_s": None, "iters_to_1deg": None,
+    out = {"wall_to_1deg_s": None, "iters_to_1deg": None, "rounds_timed": None,
            "init_rot_err_deg": round(metrics.mean_rotation_error_deg(sc.R_init, sc.R_gt), 4),
            "final_rot_err_deg": round(errs[-1], 4) if errs else None,
-           "solve_wall_s": round(full, 4), "iters": total_iters,
-           "note": f"rotations logged on the device every {every} steps; the time to the "
-                   "first logged step at <= 1 deg is measured on a second solve stopped there"}
+           "solve_wall_s": round(full, 4), "iters": total_iters, "judge_fallbacks": rep["fallbacks"],
+           "note": f"fea_epipolar_adjust; rotations logged on the device every {every} steps; the "
+                   "timed solve runs whole rounds up to the first logged step at <= 1 deg"}
     if k is not None:
         n = (k + 1) * every
-        ctx, opt = setup()
+        rounds = -(-n // base.iters_per_round)
+        ctx, opt = setup(rounds=rounds)
         t0 = time.perf_counter()
-        _solve(ctx, opt, n)
+        ctx.epipolar_adjust()
+        ctx.synchronize()
         out["wall_to_1deg_s"] = round(time.perf_counter() - t0, 4)
         out["iters_to_1deg"] = n
+        out["rounds_timed"] = rounds
         ctx.close()
     return out
+
+
+def batched_vs_sequential(fastea, metrics, synth, **options):
+    """64 independent scenes of uneven size solved in one context (every
+    kernel launch covers all scenes, steps replayed as HIP graphs) against
+    the same scenes solved one after another.  Setup (loading, segmenting)
+    is outside the timed regions; per-scene convergence is reported."""
+    t0 = time.perf_counter()
+    scenes = synth.config4()
+    log(f"[bench] batch: {len(scenes)} scenes, {sum(s.n_matches for s in scenes)} matches "
+        f"({time.perf_counter() - t0:.1f} s)")
+    cat, cam_scene, offs = synth.concat_scenes(scenes)
+    mlp = options.pop("mlp", None)
+    ctx = fastea.Context(0, fastea.default_options(**options))
+    ctx.load_intrinsics(cat["f_init"], cat["cx"], cat["cy"])
+    ctx.set_scenes(cam_scene)
+    if mlp is not None:
+        ctx.set_mlp(mlp)
+    ctx.load_matches(cat["x1"], cat["y1"], cat["x2"], cat["y2"], cat["cam1"], cat["cam2"])
+    ctx.init_poses(cat["R_init"], cat["t_init"])
+    ctx.synchronize()
+    t1 = time.perf_counter()
+    rep = ctx.epipolar_adjust()
+    ctx.synchronize()
+    batched = time.perf_counter() - t1
+    R, _, _ = ctx.get_poses()
+    learned_scenes = int(sum(ctx.scene_stats()["learned"])) if mlp is not None else 0
+    ctx.close()
+    per_scene = [metrics.mean_rotation_error_deg(R[offs[k]:offs[k + 1]], sc.R_gt)
+                 for k, sc in enumerate(scenes)]
+    seq = None if mlp is not None else 0.0
+    for sc in ([] if mlp is not None else scenes):
+        c = fastea.Context(0, fastea.default_options(**options))
+        c.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+        c.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+        c.init_poses(sc.R_init, sc.t_init)
+        c.synchronize()
+        t1 = time.perf_counter()
+        c.epipolar_adjust()
+        c.synchronize()
+        seq += time.perf_counter() - t1
+        c.close()
+    return {"scenes": len(scenes), "matches": int(sum(s.n_matches for s in scenes)),
+            "batched_s": round(batched, 4), "sequential_s": None if seq is None else round(seq, 4),
+            "learned_scenes_at_end": learned_scenes if mlp is not None else None,
+            "judge_fallbacks": rep["fallbacks"] if mlp is not None else None,
+            "per_scene_final_rot_err_deg": [round(e, 3) for e in per_scene],
+            "scenes_at_or_below_1deg": int(sum(e <= 1.0 for e in per_scene)),
+            "options": ({**options, "weight_mode": "learned"} if mlp is not None else options) or "defaults"}
 
 
 def main():
@@ -217,10 +262,24 @@ def main():
     solve = None
     if not args.no_solve:
         solve = {}
-        for name, o in (("per_match", {}), ("quadratic_form", {"inner_loop": 1})):
+        from paper_2605_18052_amd import learned
+        mlp = learned.load_weights()
+        for name, o in (("per_match", {}), ("quadratic_form", {"inner_loop": 1}),
+                        ("learned_quadratic_form", {"inner_loop": 1, "weight_mode": 1, "mlp": mlp})):
             log(f"[bench] solve to <= 1 deg, {name} inner loop ...")
             solve[name] = time_to_one_degree(sc, fastea, metrics, **o)
             log(f"[bench] solve {name}: {solve[name]}")
+
+    batch = None
+    if args.batch:
+        batch = {}
+        from paper_2605_18052_amd import learned
+        mlp = learned.load_weights()
+        for name, o in (("per_match", {}), ("quadratic_form", {"inner_loop": 1}),
+                        ("learned_quadratic_form", {"inner_loop": 1, "weight_mode": 1, "mlp": mlp})):
+            batch[name] = batched_vs_sequential(fastea, metrics, synth, **o)
+            log(f"[bench] batch {name}: batched {batch[name]['batched_s']} s, sequential "
+                f"{batch[name]['sequential_s']} s, {batch[name]['scenes_at_or_below_1deg']} scenes <= 1 deg")
 
     cpu = None
     if not args.no_cpu:
@@ -249,6 +308,8 @@ def main():
         "cpu_baseline": cpu,
         "solve": solve,
     }
+    if batch is not None:
+        out["batch"] = batch
     print(json.dumps(out), flush=True)
 
 

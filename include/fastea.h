@@ -80,7 +80,10 @@ typedef struct {
   int32_t reset_moments;   /* 1: zero the Adam moments at every round start (1) */
   int32_t tile_matches;    /* matches per work item of the per-match kernel:
                               1024, 2048, 4096 or 8192; 0 = pick by timing the
-                              candidates at the first round (0) */
+                              candidates at the first round, or reuse the pick
+                              made earlier in this process for a problem of
+                              the same size class; 8192 with inner_loop = 1
+                              (0) */
   int32_t use_graphs;      /* 1: issue runs of steps as captured HIP graphs (1) */
   int32_t weight_mode;     /* 0: plain IRLS weights (default); 1: learned
                               inlier weights (fea_set_mlp) judged by the plain
@@ -323,7 +326,8 @@ fea_status fea_get_mask(fea_ctx *ctx, uint8_t *mask, int64_t *n_retained);
  * (6D rotations, translations, log f), Adam moments and step counts, the
  * round snapshot and the two before it (learned features), round and step
  * indices, per-scene thresholds, gauges and weighting modes, the options,
- * and the retained matches of the round as one bit per sorted position.
+ * the pairs' quadratic forms of the round, and the retained matches of the
+ * round as one bit per sorted position.
  * fea_get_state: with buf == NULL writes the required size to *len; else
  * *len must be at least that size (FEA_EINVAL otherwise, with the size
  * written back) and the state is copied to the caller's host buffer.

@@ -11,6 +11,8 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -61,11 +63,38 @@ void dfree(DBuf& b) {
   b.bytes = 0;
 }
 
+// Small host-to-device copies (per-round tables, counters) go through a
+// pinned staging ring so that they are queued without blocking the host;
+// when the ring is full the stream is drained and the ring reused.
+constexpr size_t kStageBytes = 16u << 20;
+
+hipError_t stage_copy(fea_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes > kStageBytes) return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+  hipError_t e = hipSuccess;
+  if (!c->stage) {
+    if ((e = hipHostMalloc(&c->stage, kStageBytes, hipHostMallocDefault)) != hipSuccess) {
+      c->stage = nullptr;
+      return e;
+    }
+    c->stage_used = 0;
+  }
+  const size_t need = (bytes + 255) & ~(size_t)255;
+  if (c->stage_used + need > kStageBytes) {
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+    c->stage_used = 0;
+  }
+  uint8_t* p = static_cast<uint8_t*>(c->stage) + c->stage_used;
+  c->stage_used += need;
+  std::memcpy(p, src, bytes);
+  return hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, c->stream);
+}
+
 template <class T>
 hipError_t upload(fea_ctx* c, DBuf& b, const T* src, size_t n) {
   hipError_t e = dalloc(b, n * sizeof(T));
   if (e != hipSuccess || n == 0) return e;
-  return hipMemcpyAsync(b.p, src, n * sizeof(T), hipMemcpyHostToDevice, c->stream);
+  return stage_copy(c, b.p, src, n * sizeof(T));
 }
 
 template <class T>
@@ -83,13 +112,13 @@ std::vector<DBuf*> all_bufs(fea_ctx* c) {
     for (int a = 0; a < 4; ++a) v.push_back(&c->lay[b][a]);
     v.push_back(&c->lpos[b]);
   }
-  DBuf* one[] = {&c->perm, &c->swp, &c->item_pair, &c->item_start, &c->item_count, &c->item_rec, &c->pair_item_off,
+  DBuf* one[] = {&c->perm, &c->swp, &c->item_rec, &c->pair_item_off,
                  &c->item_keep, &c->item_base, &c->part, &c->d_pair_i, &c->d_pair_j, &c->d_cam_off,
                  &c->d_cam_ent, &c->d_group, &c->d_grp_off, &c->d_grp_cams, &c->d_cx, &c->d_cy, &c->a6,
                  &c->tp, &c->logf, &c->m_a6, &c->v_a6, &c->m_t, &c->v_t, &c->m_f, &c->v_f, &c->R[0],
                  &c->R[1], &c->T[0], &c->T[1], &c->Fc[0], &c->Fc[1], &c->Rh, &c->Th, &c->Fh, &c->gR,
                  &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag, &c->Re, &c->Te, &c->Fe, &c->d_pair_scene, &c->d_inv_z, &c->d_tau, &c->ptab, &c->qpart, &c->qW, &c->stab, &c->counters,
-                 &c->Rh1, &c->Th1, &c->Fh1, &c->Rh2, &c->Th2, &c->Fh2, &c->d_fbar, &c->mlp, &c->wlay,
+                 &c->Rh1, &c->Th1, &c->Fh1, &c->Rh2, &c->Th2, &c->Fh2, &c->d_fbar, &c->mlp, &c->wlay, &c->wlay_alt,
                  &c->item_wsum, &c->d_inv_zw, &c->d_scene_mode, &c->a6h, &c->tph, &c->logfh, &c->restore_flag};
   for (DBuf* b : one) v.push_back(b);
   return v;
@@ -165,9 +194,6 @@ hipError_t build_items(fea_ctx* c) {
     c->h_cam_ent4[4 * e + 3] = side ? c->pair_i[n] : c->pair_j[n];
   }
   hipError_t e;
-  if ((e = upload(c, c->item_pair, c->h_item_pair.data(), c->n_items)) != hipSuccess) return e;
-  if ((e = upload(c, c->item_start, c->h_item_start.data(), c->n_items)) != hipSuccess) return e;
-  if ((e = upload(c, c->item_count, c->h_item_count.data(), c->n_items)) != hipSuccess) return e;
   if ((e = upload(c, c->item_rec, c->h_item_rec.data(), c->h_item_rec.size())) != hipSuccess) return e;
   if ((e = upload(c, c->pair_item_off, c->h_pair_item_off.data(), c->P + 1)) != hipSuccess) return e;
   if ((e = upload(c, c->d_cam_ent, c->h_cam_ent4.data(), c->h_cam_ent4.size())) != hipSuccess) return e;
@@ -199,15 +225,49 @@ int tile_cfg_for(int32_t tile_matches) {
   return -1;
 }
 
+// Autotuner results of this process, keyed by device and by the layout's
+// size class (retained matches and pairs, each to a factor of 2^(1/4)): a
+// later context with a problem of the same class reuses the choice, so the
+// choice is deterministic within a process.
+struct TileKey {
+  int device, z_class, p_class;
+  bool operator<(const TileKey& o) const {
+    return device != o.device ? device < o.device : (z_class != o.z_class ? z_class < o.z_class : p_class < o.p_class);
+  }
+};
+std::mutex g_tile_mu;
+std::map<TileKey, int> g_tile_cache;
+
+int size_class(int64_t n) { return n > 0 ? (int)std::lround(4.0 * std::log2((double)n)) : -1; }
+
 // Picks the work-item shape of the per-match kernel for the current layout:
-// the requested size, or the fastest of the candidate shapes timed on this
-// layout with HIP events (three launches each after one warm-up).
+// the requested size, the shape chosen earlier in this process for a problem
+// of the same size class, or the fastest of the candidate shapes timed on
+// this layout with HIP events (three launches each after one warm-up).
 hipError_t choose_tile(fea_ctx* c) {
   if (c->tile_tuned) return hipSuccess;
   if (c->opt.tile_matches > 0) {
     c->tile_cfg = tile_cfg_for(c->opt.tile_matches);
     c->tile_tuned = true;
     return hipSuccess;
+  }
+  if (c->opt.inner_loop == 1) {
+    // steps do not stream the matches; the once-per-round passes (form
+    // build, filter) amortise their per-item reductions best over the
+    // largest items
+    c->tile_cfg = tile_cfg_for(8192);
+    c->tile_tuned = true;
+    return hipSuccess;
+  }
+  const TileKey key{c->device, size_class(c->Z), size_class(c->P)};
+  {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tile_cache.find(key);
+    if (it != g_tile_cache.end()) {
+      c->tile_cfg = it->second;
+      c->tile_tuned = true;
+      return hipSuccess;
+    }
   }
   hipEvent_t e0, e1;
   hipError_t e = hipEventCreate(&e0);
@@ -239,6 +299,8 @@ hipError_t choose_tile(fea_ctx* c) {
   if (e != hipSuccess) return e;
   c->tile_cfg = best_cfg;
   c->tile_tuned = true;
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tile_cache.emplace(key, best_cfg);
   return hipSuccess;
 }
 
@@ -350,7 +412,11 @@ void rot6d_to_R_host(const double a[6], double R[9]) {
   R[8] = b1[0] * b2[1] - b1[1] * b2[0];
 }
 
-void drop_graph(fea_ctx* c) {
+// Marks the captured steps out of date (their kernel arguments changed); the
+// executable graph is kept and updated in place by the next capture.
+void drop_graph(fea_ctx* c) { c->graph_pcur = -1; }
+
+void destroy_graph(fea_ctx* c) {
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   c->graph = nullptr;
   c->graph_pcur = -1;
@@ -368,9 +434,10 @@ hipError_t issue_step(fea_ctx* c) {
   return e;
 }
 
-// Captures kGraphSteps steps starting at the current pose parity.
+// Captures kGraphSteps steps starting at the current pose parity; an existing
+// executable graph of the same shape is updated with the new arguments
+// (cheaper than instantiating again each round).
 hipError_t capture_graph(fea_ctx* c) {
-  drop_graph(c);
   const int p0 = c->pcur;
   hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
@@ -380,10 +447,21 @@ hipError_t capture_graph(fea_ctx* c) {
   e = hipStreamEndCapture(c->stream, &g);
   c->pcur = p0;
   if (le != hipSuccess) e = le;
-  if (e == hipSuccess) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  bool updated = false;
+  if (e == hipSuccess && c->graph) {
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+    if (hipGraphExecUpdate(c->graph, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+      updated = true;
+    } else {
+      (void)hipGetLastError();  // a refused update is not an error of the next call
+      destroy_graph(c);
+    }
+  }
+  if (e == hipSuccess && !updated) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
   if (g) (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
-    c->graph = nullptr;
+    destroy_graph(c);
     return e;
   }
   c->graph_pcur = p0;
@@ -422,22 +500,19 @@ hipError_t set_counters(fea_ctx* c, int64_t t, int64_t g) {
   h.global_t[c->pcur] = g;
   h.b1t[c->pcur] = std::pow(c->opt.beta1, (double)t);
   h.b2t[c->pcur] = std::pow(c->opt.beta2, (double)t);
-  hipError_t e = hipMemcpyAsync(c->counters.p, &h, sizeof(h), hipMemcpyHostToDevice, c->stream);
-  if (e != hipSuccess) return e;
-  return hipStreamSynchronize(c->stream);
-}
-
-hipError_t d2d(fea_ctx* c, DBuf& dst, const DBuf& src, size_t bytes) {
-  return hipMemcpyAsync(dst.p, src.p, bytes, hipMemcpyDeviceToDevice, c->stream);
+  return stage_copy(c, c->counters.p, &h, sizeof(h));
 }
 
 // Stable compaction of the live layout into the other filtered buffer: the
 // matches that pass the snapshot threshold (mask == nullptr; the pose table
 // must hold this round's F_hat and tau) or whose sorted position is set in the
-// device bit mask.  Leaves the new layout live with its per-pair lengths.
-hipError_t compact_layout(fea_ctx* c, const uint32_t* mask) {
-  hipError_t e = fea::launch_filter_count(c, mask);
-  if (e != hipSuccess) return e;
+// device bit mask.  With `counted`, item_keep already holds each item's
+// survivor count (the quadratic form's round pass counts as it goes); with
+// `weights`, the learned weight of each survivor moves along.  Leaves the new
+// layout live with its per-pair lengths.
+hipError_t compact_layout(fea_ctx* c, const uint32_t* mask, bool counted, bool weights) {
+  hipError_t e = hipSuccess;
+  if (!counted && (e = fea::launch_filter_count(c, mask)) != hipSuccess) return e;
   std::vector<int32_t> keep;
   if ((e = download(c, keep, c->item_keep, c->n_items)) != hipSuccess) return e;
   // new per-pair lengths, aligned offsets and per-item destinations
@@ -460,14 +535,44 @@ hipError_t compact_layout(fea_ctx* c, const uint32_t* mask) {
   for (int a = 0; a < 4; ++a)
     if ((e = hipMemsetAsync(c->lay[dst][a].p, 0, span * sizeof(float), c->stream)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(c->lpos[dst].p, 0xFF, span * sizeof(int32_t), c->stream)) != hipSuccess) return e;
+  if (weights && (e = dalloc(c->wlay_alt, c->wlay.bytes)) != hipSuccess) return e;
   if ((e = upload(c, c->item_base, base.data(), c->n_items)) != hipSuccess) return e;
-  if ((e = fea::launch_filter_scatter(c, dst, mask)) != hipSuccess) return e;
+  if ((e = fea::launch_filter_scatter(c, dst, mask, weights)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  if (weights) std::swap(c->wlay, c->wlay_alt);
   c->cur = dst;
   c->cur_len = new_len;
   c->phys_off = new_off;
   c->layout_len = off;
   return hipSuccess;
+}
+
+// The quadratic form's round: one pass over the current layout tests the
+// threshold, counts the survivors and sums their weighted outer products;
+// the per-scene normalisers follow from the counts, W_n from the item sums,
+// and the survivors are then compacted for the next round.  The learned
+// weights (if any) were computed on the current layout before the pass.
+hipError_t quad_round(fea_ctx* c) {
+  hipError_t e = fea::launch_quad_build(c);
+  if (e != hipSuccess) return e;
+  std::vector<int32_t> keep;
+  if ((e = download(c, keep, c->item_keep, c->n_items)) != hipSuccess) return e;
+  c->Zs.assign(c->S, 0);
+  for (int64_t it = 0; it < c->n_items; ++it) c->Zs[c->pair_scene[c->h_item_pair[it]]] += keep[it];
+  std::vector<float> inv(c->S, 0.f);
+  for (int sc = 0; sc < c->S; ++sc) inv[sc] = c->Zs[sc] > 0 ? (float)(1.0 / (double)c->Zs[sc]) : 0.f;
+  if ((e = upload(c, c->d_inv_z, inv.data(), c->S)) != hipSuccess) return e;
+  if (c->learned_any) {
+    std::vector<double> ws;
+    if ((e = download(c, ws, c->item_wsum, c->n_items)) != hipSuccess) return e;
+    std::vector<double> zw(c->S, 0.0);
+    for (int64_t it = 0; it < c->n_items; ++it) zw[c->pair_scene[c->h_item_pair[it]]] += ws[it];
+    std::vector<float> invw(c->S, 0.f);
+    for (int sc = 0; sc < c->S; ++sc) invw[sc] = zw[sc] > 0 ? (float)(1.0 / zw[sc]) : 0.f;
+    if ((e = upload(c, c->d_inv_zw, invw.data(), c->S)) != hipSuccess) return e;
+  }
+  if ((e = fea::launch_quad_reduce(c, c->pair_item_off.as<int32_t>())) != hipSuccess) return e;
+  return compact_layout(c, nullptr, true, c->learned_any);
 }
 
 // Per-scene weighting mode of the round (chosen now, or kept as restored
@@ -498,37 +603,17 @@ hipError_t round_weights(fea_ctx* c, bool choose_mode) {
 
 fea_status begin_round(fea_ctx* c, double tau_px) {
   const size_t N = c->N;
-  // snapshot history for the learned features: (r-1, r-2) <- (r, r-1)
-  if (c->round >= 0) {
-    HIP_OR_FAIL(c, d2d(c, c->Rh2, c->Rh1, 9 * N * sizeof(double)));
-    HIP_OR_FAIL(c, d2d(c, c->Th2, c->Th1, 3 * N * sizeof(double)));
-    HIP_OR_FAIL(c, d2d(c, c->Fh2, c->Fh1, N * sizeof(double)));
-    HIP_OR_FAIL(c, d2d(c, c->Rh1, c->Rh, 9 * N * sizeof(double)));
-    HIP_OR_FAIL(c, d2d(c, c->Th1, c->Th, 3 * N * sizeof(double)));
-    HIP_OR_FAIL(c, d2d(c, c->Fh1, c->Fh, N * sizeof(double)));
-  }
-  HIP_OR_FAIL(c, d2d(c, c->a6h, c->a6, 6 * N * sizeof(double)));
-  HIP_OR_FAIL(c, d2d(c, c->tph, c->tp, 3 * N * sizeof(double)));
-  HIP_OR_FAIL(c, d2d(c, c->logfh, c->logf, (size_t)c->G * sizeof(double)));
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->Rh.p, c->R[c->pcur].p, 9 * N * sizeof(double), hipMemcpyDeviceToDevice,
-                                c->stream));
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->Th.p, c->T[c->pcur].p, 3 * N * sizeof(double), hipMemcpyDeviceToDevice,
-                                c->stream));
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->Fh.p, c->Fc[c->pcur].p, N * sizeof(double), hipMemcpyDeviceToDevice,
-                                c->stream));
+  // snapshot and its history (learned features), round parameters for the
+  // judge's restore, and (new objective) fresh Adam moments -- one kernel
+  const bool zero = c->opt.reset_moments || c->round < 0;
+  HIP_OR_FAIL(c, fea::launch_round_start(c, c->round >= 0, c->round < 0, zero));
+  if (zero) c->adam_t = 0;
   std::vector<double> fnow;
   HIP_OR_FAIL(c, download(c, fnow, c->Fc[c->pcur], N));
   // threshold per scene: tau_px over the scene's median focal length
   std::vector<std::vector<double>> fs(c->S);
   for (size_t i = 0; i < N; ++i) fs[c->cam_scene[i]].push_back(fnow[i]);
   if (c->round < 0) {
-    // first round: the earlier snapshots are this one
-    HIP_OR_FAIL(c, d2d(c, c->Rh1, c->Rh, 9 * N * sizeof(double)));
-    HIP_OR_FAIL(c, d2d(c, c->Th1, c->Th, 3 * N * sizeof(double)));
-    HIP_OR_FAIL(c, d2d(c, c->Fh1, c->Fh, N * sizeof(double)));
-    HIP_OR_FAIL(c, d2d(c, c->Rh2, c->Rh, 9 * N * sizeof(double)));
-    HIP_OR_FAIL(c, d2d(c, c->Th2, c->Th, 3 * N * sizeof(double)));
-    HIP_OR_FAIL(c, d2d(c, c->Fh2, c->Fh, N * sizeof(double)));
     c->fbar_hist.assign(3 * c->S, 0.0);
     for (int sc = 0; sc < c->S; ++sc)
       for (int k = 0; k < 3; ++k) c->fbar_hist[k * c->S + sc] = fs[sc].empty() ? 1.0 : median(fs[sc]);
@@ -543,25 +628,27 @@ fea_status begin_round(fea_ctx* c, double tau_px) {
   if (!std::isinf(tau_px))
     for (int sc = 0; sc < c->S; ++sc) c->taus[sc] = tau_px / (fs[sc].empty() ? 1.0 : median(fs[sc]));
   HIP_OR_FAIL(c, upload(c, c->d_tau, c->taus.data(), c->S));
-  // pose table at the snapshot: F_hat, principal points and tau of each pair
+  // quadratic form: the round's weighting modes and learned weights (of the
+  // current layout) come first, as its fused pass applies them
+  const bool quad = c->opt.inner_loop == 1;
+  if (quad) HIP_OR_FAIL(c, round_weights(c, true));
+  // pose table at the snapshot: F_hat, principal points, tau and mode of
+  // each pair
   HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), true));
-  HIP_OR_FAIL(c, compact_layout(c, nullptr));
+  if (quad) {
+    HIP_OR_FAIL(c, quad_round(c));
+  } else {
+    HIP_OR_FAIL(c, compact_layout(c, nullptr, false, false));
+  }
   HIP_OR_FAIL(c, upload_scene_z(c));
   c->tau = c->taus.empty() ? 0.0 : c->taus[0];
   HIP_OR_FAIL(c, choose_tile(c));
   HIP_OR_FAIL(c, build_items(c));
-  // a new round is a new objective: fresh Adam moments (or, if asked, keep
-  // them across rounds; the first round always starts from zero)
-  if (c->opt.reset_moments || c->round < 0) {
-    DBuf* mom[] = {&c->m_a6, &c->v_a6, &c->m_t, &c->v_t, &c->m_f, &c->v_f};
-    for (DBuf* b : mom) HIP_OR_FAIL(c, hipMemsetAsync(b->p, 0, b->bytes, c->stream));
-    c->adam_t = 0;
-  }
   HIP_OR_FAIL(c, set_counters(c, c->adam_t, c->global_step));
   drop_graph(c);  // the layout changed: recapture on the next run of steps
-  // learned weights of this round's retained matches
-  HIP_OR_FAIL(c, round_weights(c, true));
-  if (c->opt.inner_loop == 1) HIP_OR_FAIL(c, fea::launch_quad_build(c));
+  // learned weights of this round's retained matches (the quadratic form
+  // has them already, moved along with the compaction)
+  if (!quad) HIP_OR_FAIL(c, round_weights(c, true));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->round += 1;
   c->step = 0;
@@ -623,7 +710,7 @@ std::vector<std::pair<DBuf*, size_t>> state_sections(fea_ctx* c) {
           {&c->Rh, 9 * N * d},   {&c->Th, 3 * N * d},   {&c->Fh, N * d},      {&c->Rh1, 9 * N * d},
           {&c->Th1, 3 * N * d},  {&c->Fh1, N * d},      {&c->Rh2, 9 * N * d}, {&c->Th2, 3 * N * d},
           {&c->Fh2, N * d},      {&c->a6h, 6 * N * d},  {&c->tph, 3 * N * d}, {&c->logfh, G * d},
-          {&c->counters, sizeof(fea::StepCounters)}};
+          {&c->counters, sizeof(fea::StepCounters)}, {&c->qW, (size_t)c->P * 45 * d}};
 }
 
 size_t state_bytes(fea_ctx* c) {
@@ -736,7 +823,8 @@ void fea_destroy(fea_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (DBuf* b : all_bufs(c)) dfree(*b);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-  drop_graph(c);
+  destroy_graph(c);
+  if (c->stage) (void)hipHostFree(c->stage);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1374,7 +1462,7 @@ fea_status fea_set_state(fea_ctx* c, const void* buf, size_t len) {
   if (c->round >= 0) {
     DBuf d_bits;
     hipError_t e = upload(c, d_bits, bits.data(), bits.size());
-    if (e == hipSuccess) e = compact_layout(c, d_bits.as<uint32_t>());
+    if (e == hipSuccess) e = compact_layout(c, d_bits.as<uint32_t>(), false, false);
     dfree(d_bits);
     HIP_OR_FAIL(c, e);
     HIP_OR_FAIL(c, upload_scene_z(c));
@@ -1382,7 +1470,6 @@ fea_status fea_set_state(fea_ctx* c, const void* buf, size_t len) {
     HIP_OR_FAIL(c, upload(c, c->d_tau, c->taus.data(), S));
     HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), true));
     HIP_OR_FAIL(c, round_weights(c, false));
-    if (c->opt.inner_loop == 1) HIP_OR_FAIL(c, fea::launch_quad_build(c));
   }
   // the step counters (with their running powers) came with the sections
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));

@@ -92,33 +92,30 @@ __global__ __launch_bounds__(256) void k_camgrad(
   const int cam = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (cam >= N) return;  // uniform per wave
-  // optimiser state of the update lanes, fetched before the pair loop:
-  // lane 0 the 6D rotation, lane 1 the translation, lane 2 log f
-  const bool upd = do_update && lane < 3;
-  double ps[6], pm[6], pv[6];
+  // optimiser state, fetched before the pair loop: lane k < 6 owns 6D
+  // coordinate k, lanes 6..8 the translation, lane 9 log f (single-camera
+  // intrinsics groups); every update lane also needs the whole 6D vector
+  const bool upd = do_update && lane < (focal_inline ? 10 : 9);
+  double a_cur[6], p_own = 0.0, m_own = 0.0, v_own = 0.0;
   int grp = 0;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) ps[k] = pm[k] = pv[k] = 0.0;
+  for (int k = 0; k < 6; ++k) a_cur[k] = 0.0;
   if (upd) {
-    if (lane == 0) {
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        ps[k] = a6[6 * cam + k];
-        pm[k] = m_a6[6 * cam + k];
-        pv[k] = v_a6[6 * cam + k];
-      }
-    } else if (lane == 1) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        ps[k] = tp[3 * cam + k];
-        pm[k] = m_t[3 * cam + k];
-        pv[k] = v_t[3 * cam + k];
-      }
-    } else if (focal_inline) {
+    for (int k = 0; k < 6; ++k) a_cur[k] = a6[6 * cam + k];
+    if (lane < 6) {
+      p_own = a_cur[lane < 6 ? lane : 0];
+      m_own = m_a6[6 * cam + lane];
+      v_own = v_a6[6 * cam + lane];
+    } else if (lane < 9) {
+      p_own = tp[3 * cam + lane - 6];
+      m_own = m_t[3 * cam + lane - 6];
+      v_own = v_t[3 * cam + lane - 6];
+    } else {
       grp = group[cam];
-      ps[0] = logf[grp];
-      pm[0] = m_f[grp];
-      pv[0] = v_f[grp];
+      p_own = logf[grp];
+      m_own = m_f[grp];
+      v_own = v_f[grp];
     }
   }
   double gR[9], gt[3], gf = 0.0, L = 0.0;
@@ -180,19 +177,49 @@ __global__ __launch_bounds__(256) void k_camgrad(
     sc.ctr->b1t[p ^ 1] = b1t;
     sc.ctr->b2t[p ^ 1] = b2t;
   }
-  const double bc1 = 1.0 - b1t, bc2 = 1.0 - b2t;
-  if (lane == 0) {
-    double ga[6];
-    rot6d_vjp(ps, gR, ga);
+  // every update lane forms the 6D gradient (same instructions, no
+  // divergence) and steps its own coordinate
+  double ga[6];
+  rot6d_vjp(a_cur, gR, ga);
+  double g_own, lr;
+  if (lane < 6) {
+    g_own = ga[0];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      adam_step(ps[k], pm[k], pv[k], ga[k], ad.lr_rot, ad.b1, ad.b2, ad.eps, bc1, bc2);
-      m_a6[6 * cam + k] = pm[k];
-      v_a6[6 * cam + k] = pv[k];
-      a6[6 * cam + k] = ps[k];
+    for (int k = 1; k < 6; ++k) g_own = (lane == k) ? ga[k] : g_own;
+    lr = ad.lr_rot;
+  } else if (lane < 9) {
+    g_own = (lane == 6) ? gt[0] : ((lane == 7) ? gt[1] : gt[2]);
+    lr = ad.lr_t;
+  } else {
+    g_own = gf * Fc[cam];
+    lr = optimize_focal ? ad.lr_f : 0.0;
+  }
+  const bool step_own = lane < 9 || optimize_focal;
+  if (step_own) adam_step(p_own, m_own, v_own, g_own, lr, ad.b1, ad.b2, ad.eps, 1.0 - b1t, 1.0 - b2t);
+  if (lane < 6) {
+    a6[6 * cam + lane] = p_own;
+    m_a6[6 * cam + lane] = m_own;
+    v_a6[6 * cam + lane] = v_own;
+  } else if (lane < 9) {
+    tp[3 * cam + lane - 6] = p_own;
+    m_t[3 * cam + lane - 6] = m_own;
+    v_t[3 * cam + lane - 6] = v_own;
+    Tn[3 * cam + lane - 6] = p_own;
+  } else {
+    if (optimize_focal) {
+      logf[grp] = p_own;
+      m_f[grp] = m_own;
+      v_f[grp] = v_own;
     }
+    Fn[cam] = exp(p_own);
+  }
+  // the new rotation from the six updated coordinates (lanes 0..5)
+  double a_new[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) a_new[k] = readlane_f64(p_own, k);
+  if (lane == 0) {
     double Rnew[9];
-    rot6d_forward(ps, Rnew);
+    rot6d_forward(a_new, Rnew);
 #pragma unroll
     for (int k = 0; k < 9; ++k) Rn[9 * cam + k] = Rnew[k];
     if (sc.log_every > 0 && t_glob % sc.log_every == 0) {
@@ -201,23 +228,6 @@ __global__ __launch_bounds__(256) void k_camgrad(
 #pragma unroll
         for (int k = 0; k < 9; ++k) sc.logR[(slot * N + cam) * 9 + k] = Rnew[k];
     }
-  } else if (lane == 1) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      adam_step(ps[k], pm[k], pv[k], gt[k], ad.lr_t, ad.b1, ad.b2, ad.eps, bc1, bc2);
-      tp[3 * cam + k] = ps[k];
-      m_t[3 * cam + k] = pm[k];
-      v_t[3 * cam + k] = pv[k];
-      Tn[3 * cam + k] = ps[k];
-    }
-  } else if (focal_inline) {
-    if (optimize_focal) {
-      adam_step(ps[0], pm[0], pv[0], gf * Fc[cam], ad.lr_f, ad.b1, ad.b2, ad.eps, bc1, bc2);
-      logf[grp] = ps[0];
-      m_f[grp] = pm[0];
-      v_f[grp] = pv[0];
-    }
-    Fn[cam] = exp(ps[0]);
   }
 }
 
@@ -278,6 +288,50 @@ StepCtl step_ctl(fea_ctx* c) {
   return StepCtl{c->counters.as<StepCounters>(), c->pcur, c->opt.log_every, c->opt.max_log, c->logR.as<double>()};
 }
 
+// Round start on the device, one thread per camera (and per intrinsics
+// group): the snapshot history for the learned features (r-2 <- r-1 <- r
+// with `shift`; on the first round all three become the current poses), the
+// snapshot of the current poses and parameters, and with `zero` fresh Adam
+// moments.
+__global__ __launch_bounds__(256) void k_round_start(
+    int N, int G, int shift, int first, int zero, const double* __restrict__ R, const double* __restrict__ T,
+    const double* __restrict__ F, const double* __restrict__ a6, const double* __restrict__ tp,
+    const double* __restrict__ logf, double* __restrict__ Rh, double* __restrict__ Th, double* __restrict__ Fh,
+    double* __restrict__ Rh1, double* __restrict__ Th1, double* __restrict__ Fh1, double* __restrict__ Rh2,
+    double* __restrict__ Th2, double* __restrict__ Fh2, double* __restrict__ a6h, double* __restrict__ tph,
+    double* __restrict__ logfh, double* __restrict__ m_a6, double* __restrict__ v_a6, double* __restrict__ m_t,
+    double* __restrict__ v_t, double* __restrict__ m_f, double* __restrict__ v_f) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < N) {
+    auto snap = [&](double* h0, double* h1, double* h2, const double* cur, int k) {
+      const double now = cur[k];
+      if (first) {
+        h1[k] = now;
+        h2[k] = now;
+      } else if (shift) {
+        h2[k] = h1[k];
+        h1[k] = h0[k];
+      }
+      h0[k] = now;
+    };
+    for (int k = 9 * c; k < 9 * c + 9; ++k) snap(Rh, Rh1, Rh2, R, k);
+    for (int k = 3 * c; k < 3 * c + 3; ++k) snap(Th, Th1, Th2, T, k);
+    snap(Fh, Fh1, Fh2, F, c);
+    for (int k = 6 * c; k < 6 * c + 6; ++k) {
+      a6h[k] = a6[k];
+      if (zero) m_a6[k] = v_a6[k] = 0.0;
+    }
+    for (int k = 3 * c; k < 3 * c + 3; ++k) {
+      tph[k] = tp[k];
+      if (zero) m_t[k] = v_t[k] = 0.0;
+    }
+  }
+  if (c < G) {
+    logfh[c] = logf[c];
+    if (zero) m_f[c] = v_f[c] = 0.0;
+  }
+}
+
 // Restores the round-snapshot parameters of flagged cameras (and their
 // intrinsics groups): used when the judge rejects a learned round.
 __global__ void k_restore(int N, const int32_t* __restrict__ flag, const int32_t* __restrict__ group,
@@ -299,6 +353,20 @@ __global__ void k_restore(int N, const int32_t* __restrict__ flag, const int32_t
 }
 
 }  // namespace
+
+hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero) {
+  const int n = std::max(c->N, c->G);
+  if (n == 0) return hipSuccess;
+  const int p = c->pcur;
+  k_round_start<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
+      c->N, c->G, shift ? 1 : 0, first ? 1 : 0, zero ? 1 : 0, c->R[p].as<double>(), c->T[p].as<double>(),
+      c->Fc[p].as<double>(), c->a6.as<double>(), c->tp.as<double>(), c->logf.as<double>(), c->Rh.as<double>(),
+      c->Th.as<double>(), c->Fh.as<double>(), c->Rh1.as<double>(), c->Th1.as<double>(), c->Fh1.as<double>(),
+      c->Rh2.as<double>(), c->Th2.as<double>(), c->Fh2.as<double>(), c->a6h.as<double>(), c->tph.as<double>(),
+      c->logfh.as<double>(), c->m_a6.as<double>(), c->v_a6.as<double>(), c->m_t.as<double>(), c->v_t.as<double>(),
+      c->m_f.as<double>(), c->v_f.as<double>());
+  return hipGetLastError();
+}
 
 hipError_t launch_restore(fea_ctx* c, const std::vector<int32_t>& flag) {
   hipError_t e = hipSuccess;

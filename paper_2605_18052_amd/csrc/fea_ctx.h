@@ -13,11 +13,13 @@ namespace fea {
 
 // Device layout of the per-match stream: structure-of-arrays of raw pixel
 // coordinates (x1, y1, x2, y2 as fp32), sorted by camera pair, each pair's
-// run starting at a multiple of kAlign matches so that 16-byte vector loads
-// stay aligned.  A work item is a run of at most tile_matches matches of one
-// pair; one workgroup of the per-match kernel processes one item.
+// run starting at a multiple of kAlign matches: 128 bytes per array, one
+// cache line, so that a work item (a run of at most tile_matches matches of
+// one pair, tile_matches a multiple of kAlign) starts on a line and 16-byte
+// vector loads stay aligned.  One workgroup of the per-match kernel
+// processes one item.
 constexpr int kVec = 4;
-constexpr int kAlign = 4;
+constexpr int kAlign = 32;
 constexpr int kFilterThreads = 256;
 constexpr int kPartStride = 10;  // per item: dL/dF (9, centred coords) and the loss
 
@@ -133,7 +135,7 @@ struct fea_ctx {
   fea::DBuf lpos[3];     // int32: sorted position of each layout entry (-1 = padding)
   fea::DBuf perm;        // int32 [M] input index of each sorted position
   fea::DBuf swp;         // uint8 [M]
-  fea::DBuf item_pair, item_start, item_count, pair_item_off, item_keep, item_base;
+  fea::DBuf pair_item_off, item_keep, item_base;
   fea::DBuf item_rec;  // int4 per item: {pair, start, count, 0}
   fea::DBuf part;        // double [n_items * kPartStride]
   fea::DBuf d_pair_i, d_pair_j, d_cam_off, d_cam_ent, d_group, d_grp_off, d_grp_cams;
@@ -157,6 +159,7 @@ struct fea_ctx {
   fea::DBuf d_fbar;                       // float [3*S]: median f per scene at the 3 snapshots
   fea::DBuf mlp;                          // float [kMlpParams]
   fea::DBuf wlay;                         // bf16 [layout] learned weight of each layout slot
+  fea::DBuf wlay_alt;                     // bf16 [layout] the compaction's destination for wlay
   fea::DBuf item_wsum;                    // double [n_items]
   fea::DBuf d_inv_zw;                     // float [S]: 1 / sum of learned weights per scene
   fea::DBuf d_scene_mode;                 // int32 [S]: 1 = learned weights this round, 0 = plain
@@ -172,6 +175,10 @@ struct fea_ctx {
   // captured step graph (kGraphSteps steps of the current round)
   hipGraphExec_t graph = nullptr;
   int graph_pcur = -1;
+
+  // pinned staging ring for small host-to-device copies
+  void* stage = nullptr;
+  size_t stage_used = 0;
 
   // kernel timing (HIP events around each per-match pass)
   bool timing = false;
@@ -196,14 +203,16 @@ hipError_t launch_resgrad_cfg(fea_ctx* c, int cfg);
 hipError_t launch_resgrad_at(fea_ctx* c, int cfg, const double* R, const double* T, const double* F,
                              bool loss_only, bool force_plain);
 hipError_t launch_filter_count(fea_ctx* c, const uint32_t* mask);
-hipError_t launch_filter_scatter(fea_ctx* c, int dst, const uint32_t* mask);
+hipError_t launch_filter_scatter(fea_ctx* c, int dst, const uint32_t* mask, bool weights);
 
 // --- per-camera epilogue (fea_camera.hip) ---
 hipError_t launch_camgrad(fea_ctx* c, int do_update, bool quad);
 hipError_t launch_quad_build(fea_ctx* c);
+hipError_t launch_quad_reduce(fea_ctx* c, const int32_t* pair_item_off_dev);
 hipError_t launch_focal_update(fea_ctx* c);
 hipError_t launch_loss_sum(fea_ctx* c);
 hipError_t launch_restore(fea_ctx* c, const std::vector<int32_t>& flag);
+hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero);
 hipError_t launch_camgrad_at(fea_ctx* c, const double* R, const double* T, const double* F);
 
 // --- parameters given as device arrays (fea_autograd.hip) ---

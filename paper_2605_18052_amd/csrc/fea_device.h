@@ -251,12 +251,12 @@ __device__ __forceinline__ void pair_adjoint(const Geo& g, const double G[9], co
 // 6D rotation representation (two Gram-Schmidt columns, the parameterisation
 // FastMap uses for global rotations): a = (a1, a2) -> R = [b1 b2 b1 x b2].
 __device__ __forceinline__ void rot6d_forward(const double a[6], double R[9]) {
-  const double n1 = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
-  const double b1[3] = {a[0] / n1, a[1] / n1, a[2] / n1};
+  const double i1 = 1.0 / sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  const double b1[3] = {a[0] * i1, a[1] * i1, a[2] * i1};
   const double d = b1[0] * a[3] + b1[1] * a[4] + b1[2] * a[5];
   const double v[3] = {a[3] - d * b1[0], a[4] - d * b1[1], a[5] - d * b1[2]};
-  const double n2 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-  const double b2[3] = {v[0] / n2, v[1] / n2, v[2] / n2};
+  const double i2 = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const double b2[3] = {v[0] * i2, v[1] * i2, v[2] * i2};
   R[0] = b1[0]; R[3] = b1[1]; R[6] = b1[2];
   R[1] = b2[0]; R[4] = b2[1]; R[7] = b2[2];
   R[2] = b1[1] * b2[2] - b1[2] * b2[1];
@@ -266,12 +266,12 @@ __device__ __forceinline__ void rot6d_forward(const double a[6], double R[9]) {
 
 // Vector-Jacobian product of rot6d_forward: dL/da from dL/dR.
 __device__ __forceinline__ void rot6d_vjp(const double a[6], const double gR[9], double ga[6]) {
-  const double n1 = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
-  const double b1[3] = {a[0] / n1, a[1] / n1, a[2] / n1};
+  const double i1 = 1.0 / sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  const double b1[3] = {a[0] * i1, a[1] * i1, a[2] * i1};
   const double d = b1[0] * a[3] + b1[1] * a[4] + b1[2] * a[5];
   const double v[3] = {a[3] - d * b1[0], a[4] - d * b1[1], a[5] - d * b1[2]};
-  const double n2 = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-  const double b2[3] = {v[0] / n2, v[1] / n2, v[2] / n2};
+  const double i2 = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const double b2[3] = {v[0] * i2, v[1] * i2, v[2] * i2};
   // columns of gR
   double g1[3] = {gR[0], gR[3], gR[6]};
   double g2[3] = {gR[1], gR[4], gR[7]};
@@ -285,7 +285,7 @@ __device__ __forceinline__ void rot6d_vjp(const double a[6], const double gR[9],
   g2[2] += g3[0] * b1[1] - g3[1] * b1[0];
   // b2 = v/|v|
   const double p2 = b2[0] * g2[0] + b2[1] * g2[1] + b2[2] * g2[2];
-  const double gv[3] = {(g2[0] - p2 * b2[0]) / n2, (g2[1] - p2 * b2[1]) / n2, (g2[2] - p2 * b2[2]) / n2};
+  const double gv[3] = {(g2[0] - p2 * b2[0]) * i2, (g2[1] - p2 * b2[1]) * i2, (g2[2] - p2 * b2[2]) * i2};
   // v = a2 - (b1.a2) b1
   const double q = b1[0] * gv[0] + b1[1] * gv[1] + b1[2] * gv[2];
 #pragma unroll
@@ -296,7 +296,7 @@ __device__ __forceinline__ void rot6d_vjp(const double a[6], const double gR[9],
   // b1 = a1/|a1|
   const double p1 = b1[0] * g1[0] + b1[1] * g1[1] + b1[2] * g1[2];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) ga[k] = (g1[k] - p1 * b1[k]) / n1;
+  for (int k = 0; k < 3; ++k) ga[k] = (g1[k] - p1 * b1[k]) * i1;
 }
 
 }  // namespace fea

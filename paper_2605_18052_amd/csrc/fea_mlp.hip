@@ -26,6 +26,7 @@ namespace fea {
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));  // bf16 bit patterns
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
   // layer 2 slice (t2, g) value j <-> hidden-in unit 32 t2 + 16 g + 8 (j/4) + 4 h + j%4
   const int r32 = lane & 31, h = lane >> 5;
   bf16x4 a1[2];
-  bf16x8 a2[2][4];
+  s16x8 a2[2][4];
   f32x16 b1v[2], b2v[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
       f32x16 acc1[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[t], bx, b1v[t], 0, 0, 0);
-      bf16x8 hb[4];
+      s16x8 hb[4];
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) {
         const int t2 = sl >> 1, g = sl & 1;
@@ -248,7 +249,9 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
       for (int t = 0; t < 2; ++t) {
         f32x16 acc = b2v[t];
 #pragma unroll
-        for (int sl = 0; sl < 4; ++sl) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t][sl], hb[sl], acc, 0, 0, 0);
+        for (int sl = 0; sl < 4; ++sl)
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a2[t][sl]),
+                                                        __builtin_bit_cast(bf16x8, hb[sl]), acc, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int u = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);
@@ -262,8 +265,9 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
     // lane l's own match is in group h
     const float w = sigmoidf_((h ? zg[1] : zg[0]) + b3);
     if (valid) {
-      Wout[cur] = (unsigned short)to_bf16(w);
-      wsum += w;
+      const short wb = to_bf16(w);
+      Wout[cur] = (unsigned short)wb;
+      wsum += __uint_as_float((uint32_t)(unsigned short)wb << 16);  // the weight as stored
     }
   }
   wsum = wave_sum_f32(wsum);

@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     const float4* __restrict__ Y2, const int4* __restrict__ POS, const int4* __restrict__ items,
     const double* __restrict__ ptab, const uint32_t* __restrict__ mask, const int32_t* __restrict__ base,
     float* __restrict__ ox1, float* __restrict__ oy1, float* __restrict__ ox2, float* __restrict__ oy2,
-    int32_t* __restrict__ opos) {
+    int32_t* __restrict__ opos, const ushort4* __restrict__ Wl, unsigned short* __restrict__ owl) {
   __shared__ int s_w[kFilterThreads / kWave];
   const int tid = threadIdx.x, item = blockIdx.x;
   const int4 rec = items[item];
@@ -260,13 +260,16 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     const int v = r * kFilterThreads + tid;
     float4 a = make_float4(0, 0, 0, 0), b = a, c = a, d = a;
     int4 p = make_int4(-1, -1, -1, -1);
+    ushort4 wq = make_ushort4(0, 0, 0, 0);
     if (v < nvec) {
       a = X1[v0 + v];
       b = Y1[v0 + v];
       c = X2[v0 + v];
       d = Y2[v0 + v];
       p = POS[v0 + v];
+      if (owl) wq = Wl[v0 + v];
     }
+    const unsigned short we[4] = {wq.x, wq.y, wq.z, wq.w};
     const int pe[4] = {p.x, p.y, p.z, p.w};
     int flags = 0, mine = 0;
 #pragma unroll
@@ -302,6 +305,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
         ox2[dst] = v4(c, e);
         oy2[dst] = v4(d, e);
         opos[dst] = pe[e];
+        if (owl) owl[dst] = we[e];
         ++dst;
       }
     }
@@ -415,14 +419,15 @@ hipError_t launch_filter_count(fea_ctx* c, const uint32_t* mask) {
   return hipGetLastError();
 }
 
-hipError_t launch_filter_scatter(fea_ctx* c, int dst, const uint32_t* mask) {
+hipError_t launch_filter_scatter(fea_ctx* c, int dst, const uint32_t* mask, bool weights) {
   if (c->n_items == 0) return hipSuccess;
   const int b = c->cur;
 #define FEA_FILTER_SCATTER_ARGS                                                                               \
   c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(), \
       c->lpos[b].as<int4>(), c->item_rec.as<int4>(), c->ptab.as<double>(), mask, c->item_base.as<int32_t>(),  \
       c->lay[dst][0].as<float>(), c->lay[dst][1].as<float>(), c->lay[dst][2].as<float>(),                    \
-      c->lay[dst][3].as<float>(), c->lpos[dst].as<int32_t>()
+      c->lay[dst][3].as<float>(), c->lpos[dst].as<int32_t>(), c->wlay.as<ushort4>(),                       \
+      weights ? c->wlay_alt.as<unsigned short>() : nullptr
   if (mask)
     k_filter_scatter<true><<<(unsigned)c->n_items, kFilterThreads, 0, c->stream>>>(FEA_FILTER_SCATTER_ARGS);
   else

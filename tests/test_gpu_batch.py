@@ -87,3 +87,21 @@ def test_batch_rejects_cross_scene_matches_and_groups():
         ctx.set_scenes(cam_scene)
     assert e.value.status == fastea.FEA_EINVAL
     ctx.close()
+
+
+def test_autotuner_choice_is_reused_in_process():
+    """The timed pick of the work-item shape is remembered per size class:
+    a second context on a problem of the same size gets the same shape."""
+    sc = synth.trajectory_scene(n_cams=60, n_pts=20000, knn=8, target_matches=400_000, seed=36,
+                                name="tune", calib_sample=8000)
+    picks = []
+    for _ in range(2):
+        ctx = fastea.Context(0, fastea.default_options(tile_matches=0))
+        ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+        ctx.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+        ctx.init_poses(sc.R_init, sc.t_init)
+        ctx.begin_round(128.0)
+        info = ctx.info()
+        picks.append((info["tile_matches"], info["tile_threads"]))
+        ctx.close()
+    assert picks[0] == picks[1] and picks[0][0] in (1024, 2048, 4096, 8192)

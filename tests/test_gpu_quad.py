@@ -64,11 +64,14 @@ def _close(got, ref, rel):
         assert ok, worst
 
 
+@pytest.mark.parametrize("tile", [1024, 0])
 @pytest.mark.parametrize("name", list(SCENES))
-def test_quad_parity_no_filter(name):
+def test_quad_parity_no_filter(name, tile):
+    """tile 1024: several work items per pair; 0: the quadratic-form default
+    (8192-match items)."""
     sc = SCENES[name]
     R, t, f = _perturbed(sc)
-    got = _gpu_grad(sc, R, t, f, math.inf, 1)
+    got = _gpu_grad(sc, R, t, f, math.inf, 1, tile=tile)
     ref = oracle.loss_grad(oracle_problem(sc), R, t, f, sc.R_init, sc.t_init, sc.f_init,
                            delta=fastea.default_options().delta)
     _close(got, ref, 1e-6)
