@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1-degree solve")
     ap.add_argument("--cpu-sample", type=int, default=6_000_000)
     ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--ablation", action="store_true",
+                    help="also time the per-match pass with each design choice taken back")
     ap.add_argument("--batch", action="store_true",
                     help="also solve 64 uneven scenes (~120M matches) batched and one by one")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -270,6 +272,26 @@ def main():
             solve[name] = time_to_one_degree(sc, fastea, metrics, **o)
             log(f"[bench] solve {name}: {solve[name]}")
 
+    ablation = None
+    if args.ablation:
+        names = {0: "library kernel: pose table, DPP reduction, per-item partials",
+                 1: "pose block built per workgroup and staged in LDS",
+                 2: "per-match global atomics (sorted layout)",
+                 3: "unsorted input order, pair id per match, per-match atomics"}
+        actx = fastea.Context(0, fastea.default_options(tile_matches=2048))
+        actx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+        actx.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+        actx.init_poses(sc.R_init, sc.t_init)
+        actx.begin_round(opt.tau_px_init)
+        actx.step(3)
+        Za = actx.info()["n_retained"]
+        ablation = {}
+        for v, name in names.items():
+            ms, _ = actx.ablation(v, reps=10)
+            ablation[name] = {"kernel_ms": round(ms, 4), "GB_per_s_at_16B_per_match": round(16 * Za / ms / 1e6, 1)}
+            log(f"[bench] ablation {v}: {ms:.4f} ms ({name})")
+        actx.close()
+
     batch = None
     if args.batch:
         batch = {}
@@ -310,6 +332,8 @@ def main():
     }
     if batch is not None:
         out["batch"] = batch
+    if ablation is not None:
+        out["ablation"] = ablation
     print(json.dumps(out), flush=True)
 
 

@@ -321,6 +321,21 @@ fea_status fea_get_segments(fea_ctx *ctx, int32_t *perm, uint8_t *swapped,
  * by input order; 1 = retained).  n_retained may be NULL. */
 fea_status fea_get_mask(fea_ctx *ctx, uint8_t *mask, int64_t *n_retained);
 
+/* ---- Ablations (measurement) -------------------------------------------
+ * One per-match pass at the current poses and round weights with one design
+ * choice of the library's kernel taken back, for pricing that choice against
+ * HBM peak on the same data: 0 = the library's kernel (pair pose table read
+ * with scalar loads, per-lane sums, DPP wave reduction, one partial per work
+ * item); 1 = pose block built in every workgroup and staged in LDS (needs
+ * options.tile_matches = 2048); 2 = per-match global atomics into per-pair
+ * sums; 3 = matches in the caller's order with a pair id each and per-match
+ * atomics.  Runs reps + 1 launches (the first untimed) and writes the mean
+ * kernel time (HIP events, ms) to *ms_per_pass and, if pair_sums is not
+ * NULL, the per-pair sums (host [n_pairs*10] fp32: dL/dF for centred
+ * coordinates and the loss, plain weights).  Variant 3 allocates and frees
+ * ~20 bytes per match of scratch.  Needs a round (FEA_ESTATE). */
+fea_status fea_ablation(fea_ctx *ctx, int32_t variant, int32_t reps, double *ms_per_pass, float *pair_sums);
+
 /* ---- Checkpoint / resume ----------------------------------------------
  * The solver state between calls, as an opaque byte string: parameters
  * (6D rotations, translations, log f), Adam moments and step counts, the

@@ -112,13 +112,13 @@ std::vector<DBuf*> all_bufs(fea_ctx* c) {
     for (int a = 0; a < 4; ++a) v.push_back(&c->lay[b][a]);
     v.push_back(&c->lpos[b]);
   }
-  DBuf* one[] = {&c->perm, &c->swp, &c->item_rec, &c->pair_item_off,
+  DBuf* one[] = {&c->perm, &c->swp, &c->item_rec, &c->d_scene_item_off, &c->scene_loss, &c->pair_item_off,
                  &c->item_keep, &c->item_base, &c->part, &c->d_pair_i, &c->d_pair_j, &c->d_cam_off,
                  &c->d_cam_ent, &c->d_group, &c->d_grp_off, &c->d_grp_cams, &c->d_cx, &c->d_cy, &c->a6,
                  &c->tp, &c->logf, &c->m_a6, &c->v_a6, &c->m_t, &c->v_t, &c->m_f, &c->v_f, &c->R[0],
                  &c->R[1], &c->T[0], &c->T[1], &c->Fc[0], &c->Fc[1], &c->Rh, &c->Th, &c->Fh, &c->gR,
-                 &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag, &c->Re, &c->Te, &c->Fe, &c->d_pair_scene, &c->d_inv_z, &c->d_tau, &c->ptab, &c->qpart, &c->qW, &c->stab, &c->counters,
-                 &c->Rh1, &c->Th1, &c->Fh1, &c->Rh2, &c->Th2, &c->Fh2, &c->d_fbar, &c->mlp, &c->wlay, &c->wlay_alt,
+                 &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag, &c->Re, &c->Te, &c->Fe, &c->d_pair_scene, &c->d_inv_z, &c->d_tau, &c->ptab, &c->qpart, &c->qW, &c->qmask, &c->stab, &c->counters,
+                 &c->Rh1, &c->Th1, &c->Fh1, &c->Rh2, &c->Th2, &c->Fh2, &c->d_fbar, &c->mlp, &c->wlay,
                  &c->item_wsum, &c->d_inv_zw, &c->d_scene_mode, &c->a6h, &c->tph, &c->logfh, &c->restore_flag};
   for (DBuf* b : one) v.push_back(b);
   return v;
@@ -195,6 +195,16 @@ hipError_t build_items(fea_ctx* c) {
   }
   hipError_t e;
   if ((e = upload(c, c->item_rec, c->h_item_rec.data(), c->h_item_rec.size())) != hipSuccess) return e;
+  // items of each scene: pairs are sorted by their first camera, so when a
+  // scene's cameras have contiguous ids its items are a contiguous range
+  c->scene_items_contiguous = true;
+  for (int64_t it = 1; it < c->n_items; ++it)
+    if (c->pair_scene[c->h_item_pair[it]] < c->pair_scene[c->h_item_pair[it - 1]]) c->scene_items_contiguous = false;
+  std::vector<int32_t> soff(c->S + 1, (int32_t)c->n_items);
+  for (int64_t it = c->n_items - 1; it >= 0; --it) soff[c->pair_scene[c->h_item_pair[it]]] = (int32_t)it;
+  for (int sc = c->S - 1; sc >= 0; --sc) soff[sc] = std::min(soff[sc], soff[sc + 1]);
+  if ((e = upload(c, c->d_scene_item_off, soff.data(), soff.size())) != hipSuccess) return e;
+  if ((e = dalloc(c->scene_loss, (size_t)std::max(c->S, 1) * sizeof(double))) != hipSuccess) return e;
   if ((e = upload(c, c->pair_item_off, c->h_pair_item_off.data(), c->P + 1)) != hipSuccess) return e;
   if ((e = upload(c, c->d_cam_ent, c->h_cam_ent4.data(), c->h_cam_ent4.size())) != hipSuccess) return e;
   if ((e = dalloc(c->qpart, std::max<int64_t>(c->n_items, 1) * 45 * sizeof(double))) != hipSuccess) return e;
@@ -370,6 +380,8 @@ fea_status load_matches_common(fea_ctx* c, int64_t n, const float* x1, const flo
   HIP_OR_FAIL(c, dalloc(c->d_tau, (size_t)c->S * sizeof(double)));
   HIP_OR_FAIL(c, dalloc(c->ptab, (size_t)std::max<int64_t>(c->P, 1) * fea::kPairRow * sizeof(double)));
   HIP_OR_FAIL(c, dalloc(c->qW, (size_t)std::max<int64_t>(c->P, 1) * 45 * sizeof(double)));
+  HIP_OR_FAIL(c, dalloc(c->qmask, (size_t)std::max<int64_t>(c->layout_len, 4)));
+  c->ptab_current = false;
   HIP_OR_FAIL(c, dalloc(c->stab, (size_t)std::max<int64_t>(c->P, 1) * 40 * sizeof(double)));
   HIP_OR_FAIL(c, dalloc(c->wlay, std::max<int64_t>(c->layout_len, 4) * sizeof(uint16_t)));
   // camera -> incident (pair, side) entries, in pair order
@@ -425,12 +437,18 @@ void destroy_graph(fea_ctx* c) {
 // Issues one step (per-match kernel, per-camera chain + Adam, shared-focal
 // update); all step bookkeeping the kernels need lives on the device.
 hipError_t issue_step(fea_ctx* c) {
-  // quadratic form: the camera kernel evaluates each pair's form itself
+  // quadratic form: the camera kernel evaluates each pair's form itself.
+  // Per match: the pose table holds F at the current poses; after the
+  // update it is rebuilt at the new ones for the next step.
   const bool quad = c->opt.inner_loop == 1;
   hipError_t e = quad ? hipSuccess : fea::launch_resgrad(c);
   if (e == hipSuccess) e = fea::launch_camgrad(c, 1, quad);
   if (e == hipSuccess && !c->all_single) e = fea::launch_focal_update(c);
-  c->pcur ^= 1;
+  const int nx = c->pcur ^ 1;
+  if (e == hipSuccess && !quad)
+    e = fea::launch_pair_pose(c, c->R[nx].as<double>(), c->T[nx].as<double>(), c->Fc[nx].as<double>(), false);
+  c->pcur = nx;
+  c->ptab_current = !quad;
   return e;
 }
 
@@ -470,10 +488,14 @@ hipError_t capture_graph(fea_ctx* c) {
 
 fea_status run_steps(fea_ctx* c, int32_t n_steps) {
   const bool graphs = c->opt.use_graphs && !c->timing && c->stream != nullptr && c->n_items > 0;
+  if (n_steps > 0 && c->opt.inner_loop != 1 && !c->ptab_current)
+    HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
+                                         c->Fc[c->pcur].as<double>(), false));
   while (n_steps > 0) {
     if (graphs && n_steps >= fea::kGraphSteps) {
       if (!c->graph || c->graph_pcur != c->pcur) HIP_OR_FAIL(c, capture_graph(c));
       HIP_OR_FAIL(c, hipGraphLaunch(c->graph, c->stream));
+      c->ptab_current = c->opt.inner_loop != 1;
       n_steps -= fea::kGraphSteps;
       c->step += fea::kGraphSteps;
       c->adam_t += fea::kGraphSteps;
@@ -506,13 +528,10 @@ hipError_t set_counters(fea_ctx* c, int64_t t, int64_t g) {
 // Stable compaction of the live layout into the other filtered buffer: the
 // matches that pass the snapshot threshold (mask == nullptr; the pose table
 // must hold this round's F_hat and tau) or whose sorted position is set in the
-// device bit mask.  With `counted`, item_keep already holds each item's
-// survivor count (the quadratic form's round pass counts as it goes); with
-// `weights`, the learned weight of each survivor moves along.  Leaves the new
-// layout live with its per-pair lengths.
-hipError_t compact_layout(fea_ctx* c, const uint32_t* mask, bool counted, bool weights) {
-  hipError_t e = hipSuccess;
-  if (!counted && (e = fea::launch_filter_count(c, mask)) != hipSuccess) return e;
+// device bit mask.  Leaves the new layout live with its per-pair lengths.
+hipError_t compact_layout(fea_ctx* c, const uint32_t* mask) {
+  hipError_t e = fea::launch_filter_count(c, mask);
+  if (e != hipSuccess) return e;
   std::vector<int32_t> keep;
   if ((e = download(c, keep, c->item_keep, c->n_items)) != hipSuccess) return e;
   // new per-pair lengths, aligned offsets and per-item destinations
@@ -535,11 +554,9 @@ hipError_t compact_layout(fea_ctx* c, const uint32_t* mask, bool counted, bool w
   for (int a = 0; a < 4; ++a)
     if ((e = hipMemsetAsync(c->lay[dst][a].p, 0, span * sizeof(float), c->stream)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(c->lpos[dst].p, 0xFF, span * sizeof(int32_t), c->stream)) != hipSuccess) return e;
-  if (weights && (e = dalloc(c->wlay_alt, c->wlay.bytes)) != hipSuccess) return e;
   if ((e = upload(c, c->item_base, base.data(), c->n_items)) != hipSuccess) return e;
-  if ((e = fea::launch_filter_scatter(c, dst, mask, weights)) != hipSuccess) return e;
+  if ((e = fea::launch_filter_scatter(c, dst, mask)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
-  if (weights) std::swap(c->wlay, c->wlay_alt);
   c->cur = dst;
   c->cur_len = new_len;
   c->phys_off = new_off;
@@ -547,11 +564,12 @@ hipError_t compact_layout(fea_ctx* c, const uint32_t* mask, bool counted, bool w
   return hipSuccess;
 }
 
-// The quadratic form's round: one pass over the current layout tests the
-// threshold, counts the survivors and sums their weighted outer products;
-// the per-scene normalisers follow from the counts, W_n from the item sums,
-// and the survivors are then compacted for the next round.  The learned
-// weights (if any) were computed on the current layout before the pass.
+// The quadratic form's round: one pass over the whole layout tests the
+// threshold on the matches the retained mask still holds, updates the mask,
+// counts the survivors and sums their weighted outer products; the per-scene
+// normalisers follow from the counts and W_n from the item sums.  The layout
+// itself is never compacted (steps do not stream it).  The learned weights
+// (if any) were computed on the layout before the pass.
 hipError_t quad_round(fea_ctx* c) {
   hipError_t e = fea::launch_quad_build(c);
   if (e != hipSuccess) return e;
@@ -559,20 +577,23 @@ hipError_t quad_round(fea_ctx* c) {
   if ((e = download(c, keep, c->item_keep, c->n_items)) != hipSuccess) return e;
   c->Zs.assign(c->S, 0);
   for (int64_t it = 0; it < c->n_items; ++it) c->Zs[c->pair_scene[c->h_item_pair[it]]] += keep[it];
+  c->Z = 0;
   std::vector<float> inv(c->S, 0.f);
-  for (int sc = 0; sc < c->S; ++sc) inv[sc] = c->Zs[sc] > 0 ? (float)(1.0 / (double)c->Zs[sc]) : 0.f;
+  for (int sc = 0; sc < c->S; ++sc) {
+    c->Z += c->Zs[sc];
+    inv[sc] = c->Zs[sc] > 0 ? (float)(1.0 / (double)c->Zs[sc]) : 0.f;
+  }
   if ((e = upload(c, c->d_inv_z, inv.data(), c->S)) != hipSuccess) return e;
   if (c->learned_any) {
     std::vector<double> ws;
     if ((e = download(c, ws, c->item_wsum, c->n_items)) != hipSuccess) return e;
     std::vector<double> zw(c->S, 0.0);
     for (int64_t it = 0; it < c->n_items; ++it) zw[c->pair_scene[c->h_item_pair[it]]] += ws[it];
-    std::vector<float> invw(c->S, 0.f);
-    for (int sc = 0; sc < c->S; ++sc) invw[sc] = zw[sc] > 0 ? (float)(1.0 / zw[sc]) : 0.f;
-    if ((e = upload(c, c->d_inv_zw, invw.data(), c->S)) != hipSuccess) return e;
+    c->inv_zw_h.assign(c->S, 0.f);
+    for (int sc = 0; sc < c->S; ++sc) c->inv_zw_h[sc] = zw[sc] > 0 ? (float)(1.0 / zw[sc]) : 0.f;
+    if ((e = upload(c, c->d_inv_zw, c->inv_zw_h.data(), c->S)) != hipSuccess) return e;
   }
-  if ((e = fea::launch_quad_reduce(c, c->pair_item_off.as<int32_t>())) != hipSuccess) return e;
-  return compact_layout(c, nullptr, true, c->learned_any);
+  return fea::launch_quad_reduce(c, c->pair_item_off.as<int32_t>());
 }
 
 // Per-scene weighting mode of the round (chosen now, or kept as restored
@@ -596,9 +617,9 @@ hipError_t round_weights(fea_ctx* c, bool choose_mode) {
   if ((e = download(c, ws, c->item_wsum, c->n_items)) != hipSuccess) return e;
   std::vector<double> zw(c->S, 0.0);
   for (int64_t it = 0; it < c->n_items; ++it) zw[c->pair_scene[c->h_item_pair[it]]] += ws[it];
-  std::vector<float> inv(c->S, 0.f);
-  for (int sc = 0; sc < c->S; ++sc) inv[sc] = zw[sc] > 0 ? (float)(1.0 / zw[sc]) : 0.f;
-  return upload(c, c->d_inv_zw, inv.data(), c->S);
+  c->inv_zw_h.assign(c->S, 0.f);
+  for (int sc = 0; sc < c->S; ++sc) c->inv_zw_h[sc] = zw[sc] > 0 ? (float)(1.0 / zw[sc]) : 0.f;
+  return upload(c, c->d_inv_zw, c->inv_zw_h.data(), c->S);
 }
 
 fea_status begin_round(fea_ctx* c, double tau_px) {
@@ -628,27 +649,38 @@ fea_status begin_round(fea_ctx* c, double tau_px) {
   if (!std::isinf(tau_px))
     for (int sc = 0; sc < c->S; ++sc) c->taus[sc] = tau_px / (fs[sc].empty() ? 1.0 : median(fs[sc]));
   HIP_OR_FAIL(c, upload(c, c->d_tau, c->taus.data(), c->S));
-  // quadratic form: the round's weighting modes and learned weights (of the
-  // current layout) come first, as its fused pass applies them
+  c->tau = c->taus.empty() ? 0.0 : c->taus[0];
   const bool quad = c->opt.inner_loop == 1;
-  if (quad) HIP_OR_FAIL(c, round_weights(c, true));
-  // pose table at the snapshot: F_hat, principal points, tau and mode of
-  // each pair
-  HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), true));
   if (quad) {
+    // the full layout stays; a mask marks the retained matches.  The
+    // round's weighting modes and learned weights come first, as the fused
+    // pass applies them.
+    if (!c->tile_tuned) {
+      HIP_OR_FAIL(c, choose_tile(c));
+      HIP_OR_FAIL(c, build_items(c));
+    }
+    if (c->round < 0) HIP_OR_FAIL(c, fea::launch_mask_init(c));
+    HIP_OR_FAIL(c, round_weights(c, true));
+    HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), true));
     HIP_OR_FAIL(c, quad_round(c));
   } else {
-    HIP_OR_FAIL(c, compact_layout(c, nullptr, false, false));
+    // pose table at the snapshot (F_hat, principal points, tau), then the
+    // survivors compacted into the other buffer
+    HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), true));
+    HIP_OR_FAIL(c, compact_layout(c, nullptr));
+    HIP_OR_FAIL(c, upload_scene_z(c));
+    HIP_OR_FAIL(c, choose_tile(c));
+    HIP_OR_FAIL(c, build_items(c));
   }
-  HIP_OR_FAIL(c, upload_scene_z(c));
-  c->tau = c->taus.empty() ? 0.0 : c->taus[0];
-  HIP_OR_FAIL(c, choose_tile(c));
-  HIP_OR_FAIL(c, build_items(c));
   HIP_OR_FAIL(c, set_counters(c, c->adam_t, c->global_step));
-  drop_graph(c);  // the layout changed: recapture on the next run of steps
-  // learned weights of this round's retained matches (the quadratic form
-  // has them already, moved along with the compaction)
-  if (!quad) HIP_OR_FAIL(c, round_weights(c, true));
+  drop_graph(c);  // the layout or the weights changed: recapture on the next run of steps
+  if (!quad) {
+    // learned weights of this round's retained matches, then the pose
+    // table at the current poses with this round's normalisers
+    HIP_OR_FAIL(c, round_weights(c, true));
+    HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
+                                         c->Fc[c->pcur].as<double>(), false));
+  }
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->round += 1;
   c->step = 0;
@@ -719,6 +751,7 @@ size_t state_bytes(fea_ctx* c) {
   const size_t S = c->S;
   n += S * sizeof(double) + 3 * S * sizeof(double) + 2 * S * sizeof(int32_t) + 4 * S * sizeof(double);
   n += (size_t)((c->M + 31) / 32) * sizeof(uint32_t);
+  n += S * sizeof(float);  // 1 / sum of learned weights per scene
   return n;
 }
 
@@ -835,7 +868,9 @@ fea_status fea_set_options(fea_ctx* c, const fea_options* opt) {
   if (!c || !opt) return fail(c, FEA_EINVAL, "null argument");
   std::string why;
   if (!options_valid(opt, &why)) return fail(c, FEA_EINVAL, why);
-  if (opt->tile_matches != c->opt.tile_matches) c->tile_tuned = false;
+  if (opt->inner_loop != c->opt.inner_loop && c->round >= 0)
+    return fail(c, FEA_ESTATE, "inner_loop can change only before the first round (or after fea_init_poses)");
+  if (opt->tile_matches != c->opt.tile_matches || opt->inner_loop != c->opt.inner_loop) c->tile_tuned = false;
   if (opt->log_every > 0 && opt->max_log > 0 && c->have_intr) {
     DeviceGuard g(c->device);
     HIP_OR_FAIL(c, dalloc(c->logR, (size_t)opt->max_log * 9 * c->N * sizeof(double)));
@@ -996,6 +1031,7 @@ namespace {
 // With set_gauge the gauge (centre, scale) is recomputed from these poses.
 fea_status put_poses(fea_ctx* c, const double* R, const double* t, const double* f, bool set_gauge) {
   const int N = c->N;
+  c->ptab_current = false;
   std::vector<double> tt(t, t + 3 * N);
   for (int i = 0; i < 9 * N; ++i)
     if (!std::isfinite(R[i])) return fail(c, FEA_ENONFINITE, "non-finite rotation");
@@ -1128,7 +1164,12 @@ fea_status fea_residual_grad(fea_ctx* c, double* loss_dev, double* gR_dev, doubl
   if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
   DeviceGuard g(c->device);
   const bool quad = c->opt.inner_loop == 1;
-  if (!quad) HIP_OR_FAIL(c, fea::launch_resgrad(c));
+  if (!quad) {
+    if (!c->ptab_current)
+      HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
+                                           c->Fc[c->pcur].as<double>(), false));
+    HIP_OR_FAIL(c, fea::launch_resgrad(c));
+  }
   HIP_OR_FAIL(c, fea::launch_camgrad(c, 0, quad));
   HIP_OR_FAIL(c, fea::launch_loss_sum(c));
   const size_t N = c->N;
@@ -1200,6 +1241,12 @@ namespace {
 fea_status plain_loss_per_scene(fea_ctx* c, const double* R, const double* T, const double* F,
                                 std::vector<double>& out) {
   HIP_OR_FAIL(c, fea::launch_resgrad_at(c, c->tile_cfg, R, T, F, true, true));
+  if (c->scene_items_contiguous) {
+    HIP_OR_FAIL(c, fea::launch_scene_loss(c));
+    HIP_OR_FAIL(c, download(c, out, c->scene_loss, (size_t)c->S));
+    return FEA_OK;
+  }
+  // scenes with interleaved camera ids: sum the item losses on the host
   std::vector<double> part;
   HIP_OR_FAIL(c, download(c, part, c->part, (size_t)c->n_items * fea::kPartStride));
   out.assign(c->S, 0.0);
@@ -1308,21 +1355,41 @@ fea_status fea_get_segments(fea_ctx* c, int32_t* perm, uint8_t* swapped, int32_t
   return FEA_OK;
 }
 
+namespace {
+
+// Retained matches of the current round by sorted position: the live layout
+// (compacted rounds) or the full layout and its retained mask (quadratic
+// form; before the first round every match).
+hipError_t retained_by_position(fea_ctx* c, std::vector<uint8_t>& keep) {
+  keep.assign((size_t)c->M, 0);
+  std::vector<int32_t> pos;
+  hipError_t e = download(c, pos, c->lpos[c->cur], c->layout_len);
+  if (e != hipSuccess) return e;
+  std::vector<uint8_t> qm;
+  const bool masked = c->opt.inner_loop == 1 && c->round >= 0;
+  if (masked && (e = download(c, qm, c->qmask, c->layout_len)) != hipSuccess) return e;
+  for (int64_t n = 0; n < c->P; ++n)
+    for (int64_t k = 0; k < c->cur_len[n]; ++k) {
+      const int64_t slot = c->phys_off[n] + k;
+      const int32_t p = pos[slot];
+      if (p >= 0 && p < c->M && (!masked || qm[slot])) keep[p] = 1;
+    }
+  return hipSuccess;
+}
+
+}  // namespace
+
 fea_status fea_get_mask(fea_ctx* c, uint8_t* mask, int64_t* n_retained) {
   if (!c) return FEA_EINVAL;
   if (!c->have_matches) return fail(c, FEA_ESTATE, "load matches first");
   DeviceGuard g(c->device);
   if (n_retained) *n_retained = c->Z;
   if (!mask) return FEA_OK;
-  std::vector<int32_t> pos, perm;
-  HIP_OR_FAIL(c, download(c, pos, c->lpos[c->cur], c->layout_len));
+  std::vector<uint8_t> keep;
+  std::vector<int32_t> perm;
+  HIP_OR_FAIL(c, retained_by_position(c, keep));
   HIP_OR_FAIL(c, download(c, perm, c->perm, c->M));
-  std::memset(mask, 0, (size_t)c->M);
-  for (int64_t n = 0; n < c->P; ++n)
-    for (int64_t k = 0; k < c->cur_len[n]; ++k) {
-      const int32_t p = pos[c->phys_off[n] + k];
-      if (p >= 0 && p < c->M) mask[perm[p]] = 1;
-    }
+  for (int64_t p = 0; p < c->M; ++p) mask[perm[p]] = keep[p];
   return FEA_OK;
 }
 
@@ -1387,15 +1454,15 @@ fea_status fea_get_state(fea_ctx* c, void* buf, size_t* len) {
   // retained matches of the live layout, one bit per sorted position
   std::vector<uint32_t> bits((size_t)((c->M + 31) / 32), 0u);
   if (c->round >= 0) {
-    std::vector<int32_t> pos;
-    HIP_OR_FAIL(c, download(c, pos, c->lpos[c->cur], c->layout_len));
-    for (int64_t n = 0; n < c->P; ++n)
-      for (int64_t k = 0; k < c->cur_len[n]; ++k) {
-        const int32_t q = pos[c->phys_off[n] + k];
-        if (q >= 0 && q < c->M) bits[q >> 5] |= 1u << (q & 31);
-      }
+    std::vector<uint8_t> keep;
+    HIP_OR_FAIL(c, retained_by_position(c, keep));
+    for (int64_t q = 0; q < c->M; ++q)
+      if (keep[q]) bits[q >> 5] |= 1u << (q & 31);
   }
   put(w, bits.data(), bits.size());
+  std::vector<float> izw(c->inv_zw_h);
+  izw.resize(S, 0.f);
+  put(w, izw.data(), S);
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   *len = need;
   return FEA_OK;
@@ -1445,6 +1512,8 @@ fea_status fea_set_state(fea_ctx* c, const void* buf, size_t len) {
   take(r, c->gauge_s.data(), S);
   std::vector<uint32_t> bits((size_t)((c->M + 31) / 32));
   take(r, bits.data(), bits.size());
+  c->inv_zw_h.assign(S, 0.f);
+  take(r, c->inv_zw_h.data(), S);
   c->round = h.round;
   c->step = h.step;
   c->n_logged = h.n_logged;
@@ -1460,19 +1529,68 @@ fea_status fea_set_state(fea_ctx* c, const void* buf, size_t len) {
   c->tile_tuned = true;
   HIP_OR_FAIL(c, reset_layout(c));
   if (c->round >= 0) {
-    DBuf d_bits;
-    hipError_t e = upload(c, d_bits, bits.data(), bits.size());
-    if (e == hipSuccess) e = compact_layout(c, d_bits.as<uint32_t>(), false, false);
-    dfree(d_bits);
-    HIP_OR_FAIL(c, e);
-    HIP_OR_FAIL(c, upload_scene_z(c));
-    HIP_OR_FAIL(c, build_items(c));
+    if (c->opt.inner_loop == 1) {
+      // quadratic form: the full layout with the retained mask per slot
+      std::vector<int32_t> pos;
+      HIP_OR_FAIL(c, download(c, pos, c->lpos[0], c->layout_len));
+      std::vector<uint8_t> qm((size_t)c->layout_len, 0);
+      c->Zs.assign(S, 0);
+      for (int64_t n = 0; n < c->P; ++n)
+        for (int64_t k = 0; k < c->cur_len[n]; ++k) {
+          const int64_t slot = c->phys_off[n] + k;
+          const int32_t q = pos[slot];
+          if (q >= 0 && ((bits[q >> 5] >> (q & 31)) & 1u)) {
+            qm[slot] = 1;
+            c->Zs[c->pair_scene[n]] += 1;
+          }
+        }
+      HIP_OR_FAIL(c, upload(c, c->qmask, qm.data(), qm.size()));
+      c->Z = 0;
+      std::vector<float> inv(S, 0.f);
+      for (size_t sc = 0; sc < S; ++sc) {
+        c->Z += c->Zs[sc];
+        inv[sc] = c->Zs[sc] > 0 ? (float)(1.0 / (double)c->Zs[sc]) : 0.f;
+      }
+      HIP_OR_FAIL(c, upload(c, c->d_inv_z, inv.data(), S));
+    } else {
+      DBuf d_bits;
+      hipError_t e = upload(c, d_bits, bits.data(), bits.size());
+      if (e == hipSuccess) e = compact_layout(c, d_bits.as<uint32_t>());
+      dfree(d_bits);
+      HIP_OR_FAIL(c, e);
+      HIP_OR_FAIL(c, upload_scene_z(c));
+      HIP_OR_FAIL(c, build_items(c));
+    }
     HIP_OR_FAIL(c, upload(c, c->d_tau, c->taus.data(), S));
-    HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), true));
+    const std::vector<float> izw_saved(c->inv_zw_h);
     HIP_OR_FAIL(c, round_weights(c, false));
+    // the learned normalisers as they were (their sums ran over the
+    // retained matches of the round's pass)
+    c->inv_zw_h = izw_saved;
+    HIP_OR_FAIL(c, upload(c, c->d_inv_zw, c->inv_zw_h.data(), S));
+    HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), true));
   }
   // the step counters (with their running powers) came with the sections
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return FEA_OK;
+}
+
+fea_status fea_ablation(fea_ctx* c, int32_t variant, int32_t reps, double* ms_per_pass, float* pair_sums) {
+  if (!c || !ms_per_pass) return fail(c, FEA_EINVAL, "null argument");
+  if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
+  if (variant < 0 || variant > 3 || reps < 1) return fail(c, FEA_EINVAL, "variant must be 0..3 and reps >= 1");
+  if (c->opt.inner_loop != 0) return fail(c, FEA_EINVAL, "ablations are of the per-match inner loop (inner_loop = 0)");
+  if (variant == 1 && !(fea::kTiles[c->tile_cfg].threads == 256 && fea::kTiles[c->tile_cfg].steps == 2))
+    return fail(c, FEA_EINVAL, "variant 1 needs tile_matches = 2048");
+  if (c->n_items == 0) return fail(c, FEA_EINVAL, "no retained matches");
+  DeviceGuard g(c->device);
+  DBuf sums;
+  hipError_t e = dalloc(sums, (size_t)c->P * fea::kPartStride * sizeof(float));
+  if (e == hipSuccess) e = fea::run_ablation(c, variant, reps, ms_per_pass, sums.as<float>());
+  if (e == hipSuccess && pair_sums)
+    e = hipMemcpy(pair_sums, sums.p, (size_t)c->P * fea::kPartStride * sizeof(float), hipMemcpyDeviceToHost);
+  dfree(sums);
+  HIP_OR_FAIL(c, e);
   return FEA_OK;
 }
 
@@ -1526,9 +1644,12 @@ fea_status fea_mlp_features_dev(fea_ctx* c, float* feat_dev, int32_t* slot_pos_d
   HIP_OR_FAIL(c, hipMemsetAsync(feat_dev, 0, (size_t)c->layout_len * fea::kMlpFeat * sizeof(float), c->stream));
   HIP_OR_FAIL(c, fea::launch_mlp_weights(c, c->mlp.as<float>(), c->wlay.as<unsigned short>(),
                                          c->item_wsum.as<double>(), feat_dev));
-  if (slot_pos_dev)
+  if (slot_pos_dev) {
     HIP_OR_FAIL(c, hipMemcpyAsync(slot_pos_dev, c->lpos[c->cur].p, (size_t)c->layout_len * sizeof(int32_t),
                                   hipMemcpyDeviceToDevice, c->stream));
+    // quadratic form: the layout is whole; dropped matches are marked -1
+    if (c->opt.inner_loop == 1) HIP_OR_FAIL(c, fea::launch_mask_slots(c, slot_pos_dev));
+  }
   return FEA_OK;
 }
 
@@ -1541,13 +1662,16 @@ fea_status fea_get_learned_weights(fea_ctx* c, float* w) {
   HIP_OR_FAIL(c, download(c, pos, c->lpos[c->cur], c->layout_len));
   HIP_OR_FAIL(c, download(c, perm, c->perm, c->M));
   HIP_OR_FAIL(c, download(c, wl, c->wlay, c->layout_len));
+  std::vector<uint8_t> qm;
+  const bool masked = c->opt.inner_loop == 1;
+  if (masked) HIP_OR_FAIL(c, download(c, qm, c->qmask, c->layout_len));
   for (int64_t m = 0; m < c->M; ++m) w[m] = 0.f;
   for (int64_t n = 0; n < c->P; ++n) {
     const bool learned = c->scene_mode[c->pair_scene[n]] != 0;
     for (int64_t k = 0; k < c->cur_len[n]; ++k) {
       const int64_t slot = c->phys_off[n] + k;
       const int32_t p = pos[slot];
-      if (p < 0 || p >= c->M) continue;
+      if (p < 0 || p >= c->M || (masked && !qm[slot])) continue;
       float v = 1.f;
       if (learned) {
         const uint32_t u = (uint32_t)wl[slot] << 16;

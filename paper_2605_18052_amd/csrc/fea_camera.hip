@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_camgrad(
     gf_out[cam] = gf;
     loss_cam[cam] = L;
   }
-  if (!upd) return;
+  if (upd) {
   const int p = sc.p;
   const long long t_adam = sc.ctr->adam_t[p] + 1;
   const long long t_glob = sc.ctr->global_t[p] + 1;
@@ -228,6 +228,7 @@ __global__ __launch_bounds__(256) void k_camgrad(
 #pragma unroll
         for (int k = 0; k < 9; ++k) sc.logR[(slot * N + cam) * 9 + k] = Rnew[k];
     }
+  }
   }
 }
 
@@ -332,6 +333,26 @@ __global__ __launch_bounds__(256) void k_round_start(
   }
 }
 
+// Loss of every scene: the sum of its items' loss partials (a scene's items
+// are contiguous, since its cameras are), one workgroup per scene, fixed
+// order.
+__global__ __launch_bounds__(256) void k_scene_loss(const int32_t* __restrict__ scene_item_off,
+                                                    const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double s_red[256 / kWave];
+  const int sc = blockIdx.x, tid = threadIdx.x;
+  double L = 0.0;
+  for (int it = scene_item_off[sc] + tid; it < scene_item_off[sc + 1]; it += 256)
+    L += part[(int64_t)it * kPartStride + 9];
+  L = wave_sum_f64(L);
+  if ((tid & 63) == 0) s_red[tid >> 6] = L;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 256 / kWave; ++w) t += s_red[w];
+    out[sc] = t;
+  }
+}
+
 // Restores the round-snapshot parameters of flagged cameras (and their
 // intrinsics groups): used when the judge rejects a learned round.
 __global__ void k_restore(int N, const int32_t* __restrict__ flag, const int32_t* __restrict__ group,
@@ -354,6 +375,13 @@ __global__ void k_restore(int N, const int32_t* __restrict__ flag, const int32_t
 
 }  // namespace
 
+hipError_t launch_scene_loss(fea_ctx* c) {
+  if (c->S == 0) return hipSuccess;
+  k_scene_loss<<<(unsigned)c->S, 256, 0, c->stream>>>(c->d_scene_item_off.as<int32_t>(), c->part.as<double>(),
+                                                      c->scene_loss.as<double>());
+  return hipGetLastError();
+}
+
 hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero) {
   const int n = std::max(c->N, c->G);
   if (n == 0) return hipSuccess;
@@ -370,6 +398,7 @@ hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero) {
 
 hipError_t launch_restore(fea_ctx* c, const std::vector<int32_t>& flag) {
   hipError_t e = hipSuccess;
+  c->ptab_current = false;
   if (c->restore_flag.bytes < flag.size() * sizeof(int32_t)) {
     if (c->restore_flag.p) (void)hipFree(c->restore_flag.p);
     c->restore_flag.p = nullptr;

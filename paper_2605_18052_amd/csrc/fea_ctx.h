@@ -112,6 +112,7 @@ struct fea_ctx {
   std::vector<int32_t> pair_scene;  // [P]
   std::vector<int64_t> Zs;          // retained matches per scene
   std::vector<double> taus;         // threshold per scene, normalised units
+  std::vector<float> inv_zw_h;      // 1 / sum of retained learned weights per scene
 
   // poses
   bool have_poses = false;
@@ -137,14 +138,19 @@ struct fea_ctx {
   fea::DBuf swp;         // uint8 [M]
   fea::DBuf pair_item_off, item_keep, item_base;
   fea::DBuf item_rec;  // int4 per item: {pair, start, count, 0}
+  fea::DBuf d_scene_item_off;  // int32 [S+1]: items of each scene (contiguous)
+  fea::DBuf scene_loss;        // double [S]
+  bool scene_items_contiguous = true;  // each scene's items form one range
   fea::DBuf part;        // double [n_items * kPartStride]
   fea::DBuf d_pair_i, d_pair_j, d_cam_off, d_cam_ent, d_group, d_grp_off, d_grp_cams;
   fea::DBuf d_cx, d_cy;
   fea::DBuf d_pair_scene, d_inv_z, d_tau;  // int32 [P], float [S], double [S]
   fea::DBuf ptab;  // double [P * kPairRow], the pose table
+  bool ptab_current = false;  // the pose table's F is that of the current poses
   fea::DBuf stab;  // double [P * 40]: per-pair rows for the learned features
   fea::DBuf qpart;           // double [n_items * 45]: per-item sums of c w w^T (quadratic form)
   fea::DBuf qW;              // double [P * 45]: W_n of every pair for the round
+  fea::DBuf qmask;           // uint8 [full layout]: retained (the quadratic form keeps the full layout)
   fea::DBuf a6, tp, logf, m_a6, v_a6, m_t, v_t, m_f, v_f;
   fea::DBuf R[2], T[2], Fc[2];  // derived current/next R (N*9), t (N*3), f (N)
   fea::DBuf Rh, Th, Fh;         // round snapshot
@@ -159,7 +165,6 @@ struct fea_ctx {
   fea::DBuf d_fbar;                       // float [3*S]: median f per scene at the 3 snapshots
   fea::DBuf mlp;                          // float [kMlpParams]
   fea::DBuf wlay;                         // bf16 [layout] learned weight of each layout slot
-  fea::DBuf wlay_alt;                     // bf16 [layout] the compaction's destination for wlay
   fea::DBuf item_wsum;                    // double [n_items]
   fea::DBuf d_inv_zw;                     // float [S]: 1 / sum of learned weights per scene
   fea::DBuf d_scene_mode;                 // int32 [S]: 1 = learned weights this round, 0 = plain
@@ -203,16 +208,20 @@ hipError_t launch_resgrad_cfg(fea_ctx* c, int cfg);
 hipError_t launch_resgrad_at(fea_ctx* c, int cfg, const double* R, const double* T, const double* F,
                              bool loss_only, bool force_plain);
 hipError_t launch_filter_count(fea_ctx* c, const uint32_t* mask);
-hipError_t launch_filter_scatter(fea_ctx* c, int dst, const uint32_t* mask, bool weights);
+hipError_t launch_filter_scatter(fea_ctx* c, int dst, const uint32_t* mask);
 
 // --- per-camera epilogue (fea_camera.hip) ---
 hipError_t launch_camgrad(fea_ctx* c, int do_update, bool quad);
 hipError_t launch_quad_build(fea_ctx* c);
+hipError_t launch_mask_init(fea_ctx* c);
+hipError_t launch_mask_slots(fea_ctx* c, int32_t* slot_pos);
 hipError_t launch_quad_reduce(fea_ctx* c, const int32_t* pair_item_off_dev);
 hipError_t launch_focal_update(fea_ctx* c);
 hipError_t launch_loss_sum(fea_ctx* c);
 hipError_t launch_restore(fea_ctx* c, const std::vector<int32_t>& flag);
 hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero);
+hipError_t launch_scene_loss(fea_ctx* c);
+hipError_t run_ablation(fea_ctx* c, int variant, int reps, double* ms, float* pair_sum_dev);
 hipError_t launch_camgrad_at(fea_ctx* c, const double* R, const double* T, const double* F);
 
 // --- parameters given as device arrays (fea_autograd.hip) ---

@@ -26,7 +26,7 @@ namespace fea {
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef short s16x8 __attribute__((ext_vector_type(8)));  // bf16 bit patterns
+typedef __bf16 bf16x4h __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -46,6 +46,19 @@ __device__ __forceinline__ short to_bf16(float x) {
 
 __device__ __forceinline__ float sigmoidf_(float z) { return 1.f / (1.f + __expf(-z)); }
 
+// ReLU on the bit patterns: a negative float (or bf16) has its sign bit set,
+// so as a signed integer it is negative, and the integer max with 0 maps it
+// to +0 while leaving non-negative values unchanged (one integer max per
+// fp32 value, one packed 16-bit max per two bf16 values, no NaN handling).
+__device__ __forceinline__ float relu_f32(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ bf16x8 relu_bf16x8(bf16x8 v) {
+  const s16x8 b = __builtin_bit_cast(s16x8, v);
+  return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(b, (s16x8)0));
+}
+
 __device__ __forceinline__ double eps_at(const double* F, double x1, double y1, double x2, double y2) {
   const double l0 = fma(F[0], x1, fma(F[1], y1, F[2]));
   const double l1 = fma(F[3], x1, fma(F[4], y1, F[5]));
@@ -54,10 +67,11 @@ __device__ __forceinline__ double eps_at(const double* F, double x1, double y1, 
 }
 
 // Residual feature: log(1 + |eps| * fbar) / log(257), the residual in pixel
-// equivalents, log-compressed so that 256 px maps to 1 (fp32: the feature
-// enters the network in bf16).
+// equivalents, log-compressed so that 256 px maps to 1.  fp32 with the
+// hardware log2 (the feature enters the network in bf16): log2(1 + x) /
+// log2(257).
 __device__ __forceinline__ float res_feature(double e, float fbar) {
-  return log1pf((float)fabs(e) * fbar) * 0.18021021f;  // 1 / log(257)
+  return __log2f(1.f + (float)fabs(e) * fbar) * 0.124912178f;  // 1 / log2(257)
 }
 
 struct Snap3 {
@@ -139,31 +153,31 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
     const float* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ stab,
     const float* __restrict__ params, unsigned short* __restrict__ Wout, double* __restrict__ item_wsum,
     float* __restrict__ feat_out) {
-  __shared__ float s_w3[kNH];
   __shared__ float s_sum[kInferThreads / kWave];
   const int item = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int4 rec = items[item];
   const int n = rec.x, start = rec.y, cnt = rec.z;
   const double* row = stab + (int64_t)n * kSnapRow;
-  if (tid < kNH) s_w3[tid] = params[kOffW3 + tid];
   // weights in the A layout: row (lane%32) + 32*tile; layer 1 k = 4h + q;
   // layer 2 slice (t2, g) value j <-> hidden-in unit 32 t2 + 16 g + 8 (j/4) + 4 h + j%4
   const int r32 = lane & 31, h = lane >> 5;
   bf16x4 a1[2];
-  s16x8 a2[2][4];
-  f32x16 b1v[2], b2v[2];
+  bf16x8 a2[2][4];
+  f32x16 b1v[2], b2v[2], w3v[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int orow = r32 + 32 * t;
+    bf16x4h a1h;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a1[t][q] = to_bf16(params[orow * kNF + 4 * h + q]);
+    for (int q = 0; q < 4; ++q) a1h[q] = (__bf16)params[orow * kNF + 4 * h + q];
+    a1[t] = __builtin_bit_cast(bf16x4, a1h);
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl) {
       const int t2 = sl >> 1, g = sl & 1;
 #pragma unroll
       for (int jv = 0; jv < 8; ++jv) {
         const int unit = 32 * t2 + 16 * g + 8 * (jv >> 2) + 4 * h + (jv & 3);
-        a2[t][sl][jv] = to_bf16(params[kOffW2 + orow * kNH + unit]);
+        a2[t][sl][jv] = (__bf16)params[kOffW2 + orow * kNH + unit];
       }
     }
 #pragma unroll
@@ -171,6 +185,7 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
       const int u = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);  // hidden unit of accumulator r
       b1v[t][r] = params[kOffB1 + u];
       b2v[t][r] = params[kOffB2 + u];
+      w3v[t][r] = params[kOffW3 + u];
     }
   }
   const float b3 = params[kOffB3];
@@ -185,7 +200,6 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
   const float icxi = (float)row[kSnapInvC + 0], icyi = (float)row[kSnapInvC + 1];
   const float icxj = (float)row[kSnapInvC + 2], icyj = (float)row[kSnapInvC + 3];
   const float fb0 = (float)row[kSnapFbar + 0], fb1 = (float)row[kSnapFbar + 1], fb2 = (float)row[kSnapFbar + 2];
-  __syncthreads();
 
   constexpr int kStride = kInferThreads;  // matches per iteration of the workgroup
   float wsum = 0.f;
@@ -226,37 +240,34 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
     float zg[2];
 #pragma unroll
     for (int grp = 0; grp < 2; ++grp) {
-      bf16x4 bx;
+      bf16x4h bxh;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         // group A: h=0 own f[0..3], h=1 partner's f[4..7]; group B: h=0
         // partner's f[0..3], h=1 own f[4..7]
         const float v = (grp == 0) ? (h ? recv[q] : f[q]) : (h ? f[4 + q] : recv[q]);
-        bx[q] = to_bf16(v);
+        bxh[q] = (__bf16)v;
       }
+      const bf16x4 bx = __builtin_bit_cast(bf16x4, bxh);
       f32x16 acc1[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[t], bx, b1v[t], 0, 0, 0);
-      s16x8 hb[4];
+      bf16x8 hb[4];
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) {
         const int t2 = sl >> 1, g = sl & 1;
 #pragma unroll
-        for (int jv = 0; jv < 8; ++jv) hb[sl][jv] = to_bf16(fmaxf(acc1[t2][4 * (2 * g + (jv >> 2)) + (jv & 3)], 0.f));
+        for (int jv = 0; jv < 8; ++jv) hb[sl][jv] = (__bf16)acc1[t2][4 * (2 * g + (jv >> 2)) + (jv & 3)];
+        hb[sl] = relu_bf16x8(hb[sl]);
       }
       float z = 0.f;
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         f32x16 acc = b2v[t];
 #pragma unroll
-        for (int sl = 0; sl < 4; ++sl)
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a2[t][sl]),
-                                                        __builtin_bit_cast(bf16x8, hb[sl]), acc, 0, 0, 0);
+        for (int sl = 0; sl < 4; ++sl) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t][sl], hb[sl], acc, 0, 0, 0);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int u = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);
-          z = fmaf(s_w3[u], fmaxf(acc[r], 0.f), z);
-        }
+        for (int r = 0; r < 16; ++r) z = fmaf(w3v[t][r], relu_f32(acc[r]), z);
       }
       // lanes l and l^32 hold the two halves of the group's match l%32
       z += __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, __float_as_int(z)));
@@ -265,9 +276,9 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
     // lane l's own match is in group h
     const float w = sigmoidf_((h ? zg[1] : zg[0]) + b3);
     if (valid) {
-      const short wb = to_bf16(w);
-      Wout[cur] = (unsigned short)wb;
-      wsum += __uint_as_float((uint32_t)(unsigned short)wb << 16);  // the weight as stored
+      const __bf16 wb = (__bf16)w;
+      Wout[cur] = __builtin_bit_cast(unsigned short, wb);
+      wsum += (float)wb;  // the weight as stored
     }
   }
   wsum = wave_sum_f32(wsum);

@@ -36,7 +36,8 @@ __device__ __forceinline__ unsigned short v4w(const ushort4& q, int e) {
 }
 
 // One item of the round's pass: the threshold test at the snapshot
-// (|eps_hat| < tau, strict), the item's survivor count (and, with WEIGHTED,
+// (|eps_hat| < tau, strict) of the matches the mask still holds, the updated
+// mask, the item's survivor count (and, with WEIGHTED,
 // the sum of the survivors' learned weights), and the 45 sums of
 // c' w w^T over the survivors with c' = 1/max(|eps_hat|, delta) times the
 // learned weight on learned scenes -- the 1/Z normaliser, known only once
@@ -46,8 +47,8 @@ template <bool WEIGHTED>
 __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
     const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
     const float4* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ ptab,
-    const ushort4* __restrict__ Wl, double delta, double* __restrict__ qpart, int32_t* __restrict__ keep,
-    double* __restrict__ wkept) {
+    const ushort4* __restrict__ Wl, uchar4* __restrict__ mask, double delta, double* __restrict__ qpart,
+    int32_t* __restrict__ keep, double* __restrict__ wkept) {
   __shared__ double s_red[kQuadThreads / kWave][kQuad + 1];
   __shared__ int s_cnt[kQuadThreads / kWave];
   const int tid = threadIdx.x, item = blockIdx.x;
@@ -73,16 +74,19 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
   int v = tid;
   float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a, d = a;
   ushort4 wq = make_ushort4(0, 0, 0, 0);
+  uchar4 mq = make_uchar4(0, 0, 0, 0);
   if (v < nvec) {
     a = X1[v0 + v];
     b = Y1[v0 + v];
     c = X2[v0 + v];
     d = Y2[v0 + v];
     if (WEIGHTED) wq = Wl[v0 + v];
+    mq = mask[v0 + v];
   }
   for (; v < nvec; v += kQuadThreads) {
     const float4 ca = a, cb = b, cc = c, cd = d;
     const ushort4 cw4 = wq;
+    const uchar4 cm = mq;
     const int vn = v + kQuadThreads;
     if (vn < nvec) {
       a = X1[v0 + vn];
@@ -90,7 +94,9 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
       c = X2[v0 + vn];
       d = Y2[v0 + vn];
       if (WEIGHTED) wq = Wl[v0 + vn];
+      mq = mask[v0 + vn];
     }
+    unsigned char out[kVec] = {0, 0, 0, 0};
 #pragma unroll
     for (int e = 0; e < kVec; ++e) {
       const double x1 = v4q(ca, e), y1 = v4q(cb, e), x2 = v4q(cc, e), y2 = v4q(cd, e);
@@ -98,7 +104,9 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
       const double l1 = fma(Fh[3], x1, fma(Fh[4], y1, Fh[5]));
       const double l2 = fma(Fh[6], x1, fma(Fh[7], y1, Fh[8]));
       const double eph = fma(x2, l0, fma(y2, l1, l2));
-      if (!(v * kVec + e < cnt && fabs(eph) < tau)) continue;
+      const unsigned char was = e == 0 ? cm.x : (e == 1 ? cm.y : (e == 2 ? cm.z : cm.w));
+      if (!(was && v * kVec + e < cnt && fabs(eph) < tau)) continue;
+      out[e] = 1;
       ++kept;
       double cw = 1.0 / fmax(fabs(eph), delta);
       if (learned) {
@@ -121,6 +129,7 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
         for (int s = r; s < 9; ++s, ++k) acc[k] = fma(cr, w[s], acc[k]);
       }
     }
+    mask[v0 + v] = make_uchar4(out[0], out[1], out[2], out[3]);  // a dropped match stays dropped
   }
   wave_sum_f64_multi<kQuad>(acc);
   wsum = wave_sum_f64(wsum);
@@ -152,6 +161,18 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
   }
 }
 
+// Every valid slot of the layout retained (start of a solve).
+__global__ void k_mask_init(int64_t n, const int32_t* __restrict__ lpos, unsigned char* __restrict__ mask) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) mask[s] = lpos[s] >= 0 ? 1 : 0;
+}
+
+// slot_pos of dropped slots to -1.
+__global__ void k_mask_slots(int64_t n, const unsigned char* __restrict__ mask, int32_t* __restrict__ slot_pos) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n && !mask[s]) slot_pos[s] = -1;
+}
+
 // W_n = (1/Z of the pair's scene) * the sum of the pair's item partials in
 // item order; 1/Z is the pose table's (learned scenes: 1/sum of weights).
 __global__ __launch_bounds__(kQuadThreads) void k_quad_reduce(int32_t P, const int32_t* __restrict__ pair_item_off,
@@ -170,8 +191,9 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_reduce(int32_t P, const i
 
 }  // namespace
 
-// The round's pass over the current layout's items: threshold test at the
-// snapshot (pose table rows: F_hat, tau), survivor counts into item_keep,
+// The round's pass over the full layout's items: threshold test at the
+// snapshot (pose table rows: F_hat, tau) of the matches the retained mask
+// holds, the mask updated in place, survivor counts into item_keep,
 // the learned weights' survivor sums into item_wsum (learned scenes), and the
 // unnormalised per-item sums of the quadratic form.
 hipError_t launch_quad_build(fea_ctx* c) {
@@ -179,8 +201,8 @@ hipError_t launch_quad_build(fea_ctx* c) {
   const int b = c->cur;
 #define FEA_QUAD_BUILD_ARGS                                                                                 \
   c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(), \
-      c->item_rec.as<int4>(), c->ptab.as<double>(), c->wlay.as<ushort4>(), c->opt.delta, c->qpart.as<double>(), \
-      c->item_keep.as<int32_t>(), c->item_wsum.as<double>()
+      c->item_rec.as<int4>(), c->ptab.as<double>(), c->wlay.as<ushort4>(), c->qmask.as<uchar4>(), c->opt.delta,  \
+      c->qpart.as<double>(), c->item_keep.as<int32_t>(), c->item_wsum.as<double>()
   if (c->learned_any)
     k_quad_build<true><<<(unsigned)c->n_items, kQuadThreads, 0, c->stream>>>(FEA_QUAD_BUILD_ARGS);
   else
@@ -189,9 +211,23 @@ hipError_t launch_quad_build(fea_ctx* c) {
   return hipGetLastError();
 }
 
+hipError_t launch_mask_init(fea_ctx* c) {
+  const int64_t n = c->layout_len;
+  if (n == 0) return hipSuccess;
+  k_mask_init<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(n, c->lpos[0].as<int32_t>(),
+                                                                  c->qmask.as<unsigned char>());
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_slots(fea_ctx* c, int32_t* slot_pos) {
+  const int64_t n = c->layout_len;
+  if (n == 0) return hipSuccess;
+  k_mask_slots<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(n, c->qmask.as<unsigned char>(), slot_pos);
+  return hipGetLastError();
+}
+
 // W_n of every pair from the item sums of launch_quad_build; the pose
 // table's normalisers are refreshed first (they are set after the counts).
-// Uses the item partition of the pass, before the layout is compacted.
 hipError_t launch_quad_reduce(fea_ctx* c, const int32_t* pair_item_off_dev) {
   if (c->P == 0) return hipSuccess;
   hipError_t e = launch_pair_pose(c, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),

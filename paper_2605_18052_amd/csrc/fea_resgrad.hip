@@ -8,8 +8,9 @@
 // they act on raw pixel coordinates -- into a per-pair row of the pose table,
 // with the scene's 1/Z and the pair's principal points.
 //
-// k_resgrad: one workgroup per work item (<= 4096 matches of one camera pair,
-// contiguous in the pair-sorted SoA layout).  Every thread issues all of its
+// k_resgrad: one workgroup per work item (<= 8192 matches of one camera pair,
+// contiguous in the pair-sorted SoA layout; with the quadratic form the
+// layout stays whole and a per-match mask marks the retained matches).  Every thread issues all of its
 // 16-byte loads first; the pair's row is read with scalar loads (the item,
 // hence the pair, is uniform across the workgroup), so no wave waits on
 // another before streaming.  Per match: eps = q2^T F q1 and eps_hat in fp64
@@ -91,7 +92,7 @@ template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
 __global__ __launch_bounds__(THREADS) void k_resgrad(
     const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
     const float4* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ ptab, float delta,
-    double* __restrict__ part, const ushort4* __restrict__ Wl) {
+    double* __restrict__ part, const ushort4* __restrict__ Wl, const uchar4* __restrict__ qmask) {
   __shared__ float s_red[THREADS / kWave][kPartStride];
   const int tid = threadIdx.x;
   const int item = blockIdx.x;
@@ -103,15 +104,18 @@ __global__ __launch_bounds__(THREADS) void k_resgrad(
 
   float4 qa[STEPS], qb[STEPS], qc[STEPS], qd[STEPS];
   ushort4 qw[WEIGHTED ? STEPS : 1];
+  uchar4 qm[STEPS];
 #pragma unroll
   for (int s = 0; s < STEPS; ++s) {
     const int v = s * THREADS + tid;
+    qm[s] = make_uchar4(1, 1, 1, 1);
     if (v < nvec) {
       qa[s] = X1[v0 + v];
       qb[s] = Y1[v0 + v];
       qc[s] = X2[v0 + v];
       qd[s] = Y2[v0 + v];
       if (WEIGHTED) qw[s] = Wl[v0 + v];
+      if (qmask) qm[s] = qmask[v0 + v];
     } else {
       qa[s] = qb[s] = qc[s] = qd[s] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (WEIGHTED) qw[s] = make_ushort4(0, 0, 0, 0);
@@ -149,7 +153,8 @@ __global__ __launch_bounds__(THREADS) void k_resgrad(
         const unsigned short wb = e == 0 ? qw[s].x : (e == 1 ? qw[s].y : (e == 2 ? qw[s].z : qw[s].w));
         c *= __uint_as_float((uint32_t)wb << 16);
       }
-      c = (local < cnt) ? c : 0.f;  // alignment padding holds no weight
+      const unsigned char held = e == 0 ? qm[s].x : (e == 1 ? qm[s].y : (e == 2 ? qm[s].z : qm[s].w));
+      c = (local < cnt && held) ? c : 0.f;  // alignment padding and dropped matches hold no weight
       if (!LOSS_ONLY) {
         const float k2 = 2.f * c * ef;
         const float x1c = x1 - cxi, y1c = y1 - cyi, x2c = x2 - cxj, y2c = y2 - cyj;
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     const float4* __restrict__ Y2, const int4* __restrict__ POS, const int4* __restrict__ items,
     const double* __restrict__ ptab, const uint32_t* __restrict__ mask, const int32_t* __restrict__ base,
     float* __restrict__ ox1, float* __restrict__ oy1, float* __restrict__ ox2, float* __restrict__ oy2,
-    int32_t* __restrict__ opos, const ushort4* __restrict__ Wl, unsigned short* __restrict__ owl) {
+    int32_t* __restrict__ opos) {
   __shared__ int s_w[kFilterThreads / kWave];
   const int tid = threadIdx.x, item = blockIdx.x;
   const int4 rec = items[item];
@@ -260,16 +265,13 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     const int v = r * kFilterThreads + tid;
     float4 a = make_float4(0, 0, 0, 0), b = a, c = a, d = a;
     int4 p = make_int4(-1, -1, -1, -1);
-    ushort4 wq = make_ushort4(0, 0, 0, 0);
     if (v < nvec) {
       a = X1[v0 + v];
       b = Y1[v0 + v];
       c = X2[v0 + v];
       d = Y2[v0 + v];
       p = POS[v0 + v];
-      if (owl) wq = Wl[v0 + v];
     }
-    const unsigned short we[4] = {wq.x, wq.y, wq.z, wq.w};
     const int pe[4] = {p.x, p.y, p.z, p.w};
     int flags = 0, mine = 0;
 #pragma unroll
@@ -305,7 +307,6 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
         ox2[dst] = v4(c, e);
         oy2[dst] = v4(d, e);
         opos[dst] = pe[e];
-        if (owl) owl[dst] = we[e];
         ++dst;
       }
     }
@@ -317,6 +318,8 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
 
 hipError_t launch_pair_pose(fea_ctx* c, const double* R, const double* T, const double* F, bool snap) {
   if (c->P == 0) return hipSuccess;
+  c->ptab_current = R == c->R[c->pcur].as<double>() && T == c->T[c->pcur].as<double>() &&
+                    F == c->Fc[c->pcur].as<double>();
   const unsigned blocks = (unsigned)((c->P + kPairThreads - 1) / kPairThreads);
 #define FEA_PAIR_POSE_ARGS                                                                                   \
   (int32_t)c->P, c->d_pair_i.as<int32_t>(), c->d_pair_j.as<int32_t>(), R, T, F, c->Rh.as<double>(),          \
@@ -336,8 +339,8 @@ hipError_t launch_resgrad_t(fea_ctx* c) {
   const int b = c->cur;
   k_resgrad<THREADS, STEPS, LOSS_ONLY, WEIGHTED><<<(unsigned)c->n_items, THREADS, 0, c->stream>>>(
       c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(),
-      c->item_rec.as<int4>(), c->ptab.as<double>(),
-      (float)c->opt.delta, c->part.as<double>(), c->wlay.as<ushort4>());
+      c->item_rec.as<int4>(), c->ptab.as<double>(), (float)c->opt.delta, c->part.as<double>(),
+      c->wlay.as<ushort4>(), c->opt.inner_loop == 1 ? c->qmask.as<uchar4>() : nullptr);
   return hipGetLastError();
 }
 
@@ -380,13 +383,12 @@ hipError_t launch_resgrad_cfg(fea_ctx* c, int cfg) {
                            c->Fc[c->pcur].as<double>(), false, false);
 }
 
-// One step's per-match pass at the current poses; with kernel timing on, HIP
-// events bracket the per-match kernel alone.
+// One step's per-match pass at the current poses (the pose table must hold
+// them: the previous step's camera kernel, or launch_pair_pose, wrote it);
+// with kernel timing on, HIP events bracket the per-match kernel.
 hipError_t launch_resgrad(fea_ctx* c) {
   if (c->n_items == 0) return hipSuccess;
-  hipError_t err = launch_pair_pose(c, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
-                                    c->Fc[c->pcur].as<double>(), false);
-  if (err != hipSuccess) return err;
+  hipError_t err = hipSuccess;
   hipEvent_t ev1 = nullptr;
   if (c->timing) {
     while (c->ev_pool.size() < c->ev_used + 2) {
@@ -419,15 +421,14 @@ hipError_t launch_filter_count(fea_ctx* c, const uint32_t* mask) {
   return hipGetLastError();
 }
 
-hipError_t launch_filter_scatter(fea_ctx* c, int dst, const uint32_t* mask, bool weights) {
+hipError_t launch_filter_scatter(fea_ctx* c, int dst, const uint32_t* mask) {
   if (c->n_items == 0) return hipSuccess;
   const int b = c->cur;
 #define FEA_FILTER_SCATTER_ARGS                                                                               \
   c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(), \
       c->lpos[b].as<int4>(), c->item_rec.as<int4>(), c->ptab.as<double>(), mask, c->item_base.as<int32_t>(),  \
       c->lay[dst][0].as<float>(), c->lay[dst][1].as<float>(), c->lay[dst][2].as<float>(),                    \
-      c->lay[dst][3].as<float>(), c->lpos[dst].as<int32_t>(), c->wlay.as<ushort4>(),                       \
-      weights ? c->wlay_alt.as<unsigned short>() : nullptr
+      c->lay[dst][3].as<float>(), c->lpos[dst].as<int32_t>()
   if (mask)
     k_filter_scatter<true><<<(unsigned)c->n_items, kFilterThreads, 0, c->stream>>>(FEA_FILTER_SCATTER_ARGS);
   else

@@ -93,6 +93,7 @@ _SIGNATURES = {
     "fea_get_mask": ([_P, _P, _P], C.c_int),
     "fea_get_info": ([_P, _P], C.c_int),
     "fea_get_state": ([_P, _P, _P], C.c_int),
+    "fea_ablation": ([_P, C.c_int32, C.c_int32, _P, _P], C.c_int),
     "fea_set_state": ([_P, _P, C.c_size_t], C.c_int),
     "fea_synchronize": ([_P], C.c_int),
     "fea_get_rotation_log": ([_P, _P, _P], C.c_int),
@@ -394,6 +395,15 @@ class Context:
         z = C.c_int64(0)
         self._check(lib().fea_get_mask(self._h, mask.ctypes.data_as(_P), C.byref(z)))
         return mask[:M].astype(bool), z.value
+
+    def ablation(self, variant, reps=5):
+        """(mean ms per pass, per-pair sums [P, 10]) of ablation `variant`."""
+        P = self.info()["n_pairs"]
+        ms = C.c_double(0.0)
+        sums = np.zeros((max(P, 1), 10), np.float32)
+        self._check(lib().fea_ablation(self._h, int(variant), int(reps), C.byref(ms),
+                                       sums.ctypes.data_as(_P)))
+        return ms.value, sums[:P]
 
     def get_state(self):
         """Checkpoint of the solver state (bytes)."""

@@ -159,3 +159,28 @@ def test_quad_graph_replay_equals_eager():
         ctx.close()
     for a, b in zip(*res):
         assert np.array_equal(a, b)
+
+
+def test_quad_retained_mask_is_monotone_and_counted():
+    """The quadratic form keeps the whole layout and a per-match mask: a match
+    dropped in one round stays dropped, Z is the mask's count, and the
+    features' slot positions mark dropped matches."""
+    import torch
+    sc = SCENES["sphere20_m60k"]
+    ctx = make_context(sc, gauge=1, inner_loop=1)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    prev = np.ones(sc.n_matches, bool)
+    for r, tau in enumerate((128.0, 16.0, 4.0, 2.0)):
+        ctx.begin_round(tau)
+        mask, Z = ctx.get_mask()
+        assert Z == mask.sum() and not np.any(mask & ~prev), r
+        prev = mask
+        ctx.step(20)
+    assert prev.sum() < 0.95 * sc.n_matches  # the filter did drop matches
+    feat, pos = ctx.mlp_features()
+    pos = pos.cpu().numpy()
+    perm, _, _, _ = ctx.get_segments()
+    kept = np.zeros(sc.n_matches, bool)
+    kept[perm[pos[pos >= 0]]] = True
+    assert np.array_equal(kept, prev)
+    ctx.close()
