@@ -42,9 +42,12 @@ BYTES_PER_MATCH = 16  # x1, y1, x2, y2 as fp32: the algorithmic minimum per matc
 KERNEL_SOURCES = ("paper_2605_18052_amd/csrc/fea_resgrad.hip", "paper_2605_18052_amd/csrc/fea_device.h",
                   "paper_2605_18052_amd/csrc/fea_ctx.h")
 PMC_TRAFFIC = {
-    "sources_sha256": None,
+    "sources_sha256": "f6866b2ae461ae6f557126cbea34ed9180ab553dea3f987d61cb2b523ef119a9",
     "matches_per_launch": 17819274,
-    "bytes_per_launch": {},  # "matches x threads" -> fetched + written bytes
+    "bytes_per_launch": {  # "matches x threads" -> fetched + written bytes
+        "1024x128": 301053950, "1024x256": 301038527, "2048x128": 294116227, "2048x256": 294079235,
+        "4096x128": 290427785, "4096x256": 290352010, "4096x512": 290307019, "8192x512": 290315915,
+    },
 }
 
 

@@ -22,6 +22,8 @@
 // is deterministic.
 #include <hip/hip_runtime.h>
 
+#include <hip/hip_ext.h>
+
 #include "fea_ctx.h"
 #include "fea_device.h"
 
@@ -334,38 +336,57 @@ hipError_t launch_pair_pose(fea_ctx* c, const double* R, const double* T, const 
   return hipGetLastError();
 }
 
+// With ev0/ev1 set the dispatch itself records the two events at the
+// kernel's start and end (no separate marker packets around it).
 template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
-hipError_t launch_resgrad_t(fea_ctx* c) {
+hipError_t launch_resgrad_t(fea_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   const int b = c->cur;
-  k_resgrad<THREADS, STEPS, LOSS_ONLY, WEIGHTED><<<(unsigned)c->n_items, THREADS, 0, c->stream>>>(
-      c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(),
-      c->item_rec.as<int4>(), c->ptab.as<double>(), (float)c->opt.delta, c->part.as<double>(),
-      c->wlay.as<ushort4>(), c->opt.inner_loop == 1 ? c->qmask.as<uchar4>() : nullptr);
+  const dim3 grid((unsigned)c->n_items), block(THREADS);
+  const float4 *x1 = c->lay[b][0].as<float4>(), *y1 = c->lay[b][1].as<float4>(), *x2 = c->lay[b][2].as<float4>(),
+               *y2 = c->lay[b][3].as<float4>();
+  const int4* items = c->item_rec.as<int4>();
+  const double* ptab = c->ptab.as<double>();
+  const float delta = (float)c->opt.delta;
+  double* part = c->part.as<double>();
+  const ushort4* wl = c->wlay.as<ushort4>();
+  const uchar4* qm = c->opt.inner_loop == 1 ? c->qmask.as<uchar4>() : nullptr;
+  if (ev0)
+    hipExtLaunchKernelGGL(k_resgrad<THREADS, STEPS, LOSS_ONLY, WEIGHTED>, grid, block, 0, c->stream, ev0, ev1, 0,
+                          x1, y1, x2, y2, items, ptab, delta, part, wl, qm);
+  else
+    k_resgrad<THREADS, STEPS, LOSS_ONLY, WEIGHTED><<<grid, block, 0, c->stream>>>(x1, y1, x2, y2, items, ptab,
+                                                                                  delta, part, wl, qm);
   return hipGetLastError();
 }
 
 template <bool LOSS_ONLY, bool WEIGHTED>
-hipError_t launch_resgrad_sel(fea_ctx* c, int cfg) {
+hipError_t launch_resgrad_sel(fea_ctx* c, int cfg, hipEvent_t ev0, hipEvent_t ev1) {
   switch (cfg) {
-    case 0: return launch_resgrad_t<256, 4, LOSS_ONLY, WEIGHTED>(c);
-    case 1: return launch_resgrad_t<256, 2, LOSS_ONLY, WEIGHTED>(c);
-    case 2: return launch_resgrad_t<256, 1, LOSS_ONLY, WEIGHTED>(c);
-    case 3: return launch_resgrad_t<128, 8, LOSS_ONLY, WEIGHTED>(c);
-    case 4: return launch_resgrad_t<128, 4, LOSS_ONLY, WEIGHTED>(c);
-    case 5: return launch_resgrad_t<128, 2, LOSS_ONLY, WEIGHTED>(c);
-    case 6: return launch_resgrad_t<512, 2, LOSS_ONLY, WEIGHTED>(c);
-    case 7: return launch_resgrad_t<512, 4, LOSS_ONLY, WEIGHTED>(c);
+    case 0: return launch_resgrad_t<256, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
+    case 1: return launch_resgrad_t<256, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
+    case 2: return launch_resgrad_t<256, 1, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
+    case 3: return launch_resgrad_t<128, 8, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
+    case 4: return launch_resgrad_t<128, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
+    case 5: return launch_resgrad_t<128, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
+    case 6: return launch_resgrad_t<512, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
+    case 7: return launch_resgrad_t<512, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_resgrad_timed(fea_ctx* c, int cfg, bool loss_only, bool force_plain, hipEvent_t ev0,
+                                hipEvent_t ev1) {
+  if (c->n_items == 0) return hipSuccess;
+  const bool w = c->learned_any && !force_plain;
+  if (loss_only)
+    return w ? launch_resgrad_sel<true, true>(c, cfg, ev0, ev1) : launch_resgrad_sel<true, false>(c, cfg, ev0, ev1);
+  return w ? launch_resgrad_sel<false, true>(c, cfg, ev0, ev1) : launch_resgrad_sel<false, false>(c, cfg, ev0, ev1);
 }
 
 // The per-match kernel alone, with tile shape `cfg`, over the current items;
 // the pose table must hold F for the poses wanted.
 hipError_t launch_resgrad_kernel(fea_ctx* c, int cfg, bool loss_only, bool force_plain) {
-  if (c->n_items == 0) return hipSuccess;
-  const bool w = c->learned_any && !force_plain;
-  if (loss_only) return w ? launch_resgrad_sel<true, true>(c, cfg) : launch_resgrad_sel<true, false>(c, cfg);
-  return w ? launch_resgrad_sel<false, true>(c, cfg) : launch_resgrad_sel<false, false>(c, cfg);
+  return launch_resgrad_timed(c, cfg, loss_only, force_plain, nullptr, nullptr);
 }
 
 // Pose table at poses (R, T, F) (per camera, fp64), then the per-match kernel
@@ -384,27 +405,23 @@ hipError_t launch_resgrad_cfg(fea_ctx* c, int cfg) {
 }
 
 // One step's per-match pass at the current poses (the pose table must hold
-// them: the previous step's camera kernel, or launch_pair_pose, wrote it);
-// with kernel timing on, HIP events bracket the per-match kernel.
+// them: launch_pair_pose wrote it after the previous update); with kernel
+// timing on, the dispatch records a pair of HIP events at its start and end.
 hipError_t launch_resgrad(fea_ctx* c) {
   if (c->n_items == 0) return hipSuccess;
-  hipError_t err = hipSuccess;
-  hipEvent_t ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (c->timing) {
     while (c->ev_pool.size() < c->ev_used + 2) {
       hipEvent_t e;
-      err = hipEventCreate(&e);
+      const hipError_t err = hipEventCreate(&e);
       if (err != hipSuccess) return err;
       c->ev_pool.push_back(e);
     }
-    err = hipEventRecord(c->ev_pool[c->ev_used], c->stream);
-    if (err != hipSuccess) return err;
+    ev0 = c->ev_pool[c->ev_used];
     ev1 = c->ev_pool[c->ev_used + 1];
     c->ev_used += 2;
   }
-  err = launch_resgrad_kernel(c, c->tile_cfg, false, false);
-  if (err == hipSuccess && ev1) err = hipEventRecord(ev1, c->stream);
-  return err;
+  return launch_resgrad_timed(c, c->tile_cfg, false, false, ev0, ev1);
 }
 
 hipError_t launch_filter_count(fea_ctx* c, const uint32_t* mask) {
