@@ -5,7 +5,8 @@ first IRLS round: the fused residual / IRLS-weight / dL/dF kernel over every
 match, the per-camera adjoint and Adam update, and the focal/loss kernel.
 The workload is the 500-camera trajectory scene (200k points, 20 nearest
 neighbours, ~20M matches, sigma 1 px, 20% outliers, unknown focal lengths in
-[400, 1200] px), generated synthetically and resident in HBM before timing.
+[400, 1200] px), generated synthetically and resident in HBM before timing;
+`--workload traj3000_m100M` times the 3,000-camera, ~100M-match scene instead.
 
 Prints ONE JSON line on stdout (progress goes to stderr):
   value       retained matches processed per second (whole job = 1 GPU)
@@ -62,6 +63,14 @@ def measured_traffic(tile, Z):
     return PMC_TRAFFIC["bytes_per_launch"].get(tile)
 
 
+WORKLOADS = {
+    "traj500_m20M": ("500 cameras, 200k points, 20-NN pairs, ~20M matches, sigma 1 px, 20% outliers, "
+                     "f in [400,1200] px", "config2", 20_000_000),
+    "traj3000_m100M": ("3,000 cameras, 1M points, 30-NN pairs, ~100M matches, sigma 1 px, 25% outliers, "
+                       "f in [400,1200] px", "config3", 100_000_000),
+}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -71,7 +80,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--matches", type=int, default=20_000_000, help="target match count")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="traj500_m20M",
+                    help="scene the step is timed on (the 100M-match scene streams 1.6 GB per pass, "
+                         "far beyond the 256 MB Infinity Cache)")
+    ap.add_argument("--matches", type=int, default=0, help="target match count (0: the workload's own)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1-degree solve")
     ap.add_argument("--cpu-sample", type=int, default=6_000_000)
@@ -97,8 +109,14 @@ def cpu_baseline(sc, n_sample, iters):
     t0 = time.perf_counter()
     oracle.epipolar_adjust(pb, sc.R_init, sc.t_init, sc.f_init, options=opt)
     dt = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": pb.n_matches * iters / dt, "unit": "matches/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": oracle.num_threads(), "cpu_model": model, "kind": "oracle",
             "sample": f"{pb.n_matches} random matches of the same scene, 1 round x {iters} "
                       f"steps of the FP64 C oracle incl. its one-time segmenting, "
                       f"{dt:.1f} s wall"}
@@ -218,7 +236,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     t0 = time.perf_counter()
-    sc = synth.config2(target_matches=args.matches)
+    desc, gen, default_m = WORKLOADS[args.workload]
+    sc = getattr(synth, gen)(target_matches=args.matches or default_m)
     log(f"[bench] scene {sc.name}: {sc.n_cams} cams, {sc.n_matches} matches, "
         f"{len(sc.pairs())} pairs ({time.perf_counter() - t0:.1f} s)")
 
@@ -243,6 +262,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     k_ms, k_n = ctx.kernel_timing()
+    k_each = ctx.kernel_times()
     ctx.set_kernel_timing(False)
     ctx.close()
     ms_step = 1e3 * wall / args.steps
@@ -312,19 +332,21 @@ def main():
         cpu = cpu_baseline(sc, args.cpu_sample, args.cpu_iters)
         log(f"[bench] cpu: {cpu}")
 
+    traffic = measured_traffic(tile, Z)
     out = {
         "metric": METRIC, "value": value, "unit": "matches/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": "traj500_m20M: 500 cameras, 200k points, 20-NN pairs, "
-                               "~20M matches, sigma 1 px, 20% outliers, f in [400,1200] px",
+        "config": {"workload": f"{args.workload}: {desc}",
                    "matches_loaded": sc.n_matches, "matches_per_step": Z,
                    "pairs": info["n_pairs"], "items": info["n_items"], "round": 0,
                    "tau_px": opt.tau_px_init},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(tile, Z),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "achieved_on_traffic": None if traffic is None else traffic / k_avg_s / 1e9,
                      "kernel": "k_resgrad", "kernel_ms": 1e3 * k_avg_s,
+                     "kernel_ms_p10_p50_p90": [float(np.percentile(k_each, q)) for q in (10, 50, 90)],
                      "bytes_per_launch": BYTES_PER_MATCH * Z,
                      "measured_read_peak": read_peak, "frac_of_measured_read_peak": achieved / read_peak,
                      "tile": f"{info['tile_matches']} matches x {info['tile_threads']} threads",

@@ -371,12 +371,17 @@ fea_status fea_hbm_probe(int32_t device, int64_t bytes, int32_t reps, double *re
                          double *copy_gbps);
 
 /* Kernel timing for measurement.  While enabled, every launch of the
- * per-match residual/gradient kernel is bracketed by HIP events recorded on
- * the context's stream.  fea_set_kernel_timing(ctx, 1) clears earlier
- * records; fea_get_kernel_timing synchronises the stream and returns the
- * summed event time (ms) and the number of timed launches. */
+ * per-match residual/gradient kernel records a pair of HIP events at its
+ * own start and end on the context's stream (steps run without graph
+ * replay meanwhile).  fea_set_kernel_timing(ctx, 1) clears earlier records;
+ * fea_get_kernel_timing synchronises the stream and returns the summed
+ * event time (ms) and the number of timed launches.  fea_get_kernel_times
+ * writes the first min(cap, launches) per-launch durations (ms, launch
+ * order) into the caller's host array `ms` (NULL with cap 0 only counts)
+ * and the number of timed launches into *n. */
 fea_status fea_set_kernel_timing(fea_ctx *ctx, int32_t enable);
 fea_status fea_get_kernel_timing(fea_ctx *ctx, double *resgrad_ms, int64_t *resgrad_launches);
+fea_status fea_get_kernel_times(fea_ctx *ctx, float *ms, int64_t cap, int64_t *n);
 
 /* Rotation log kept by fea_epipolar_adjust when options.log_every > 0:
  * R_log [max_log * n_cams * 9] host, in the caller's frame; *n_logged

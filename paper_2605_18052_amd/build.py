@@ -24,9 +24,15 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-t
           "-Wno-unused-command-line-argument"]
 
 
+# Per-source code-generation options.  The MLP kernels keep their matrix-core
+# accumulators in ordinary VGPRs (the accumulation-register form would cost a
+# v_accvgpr_read per accumulator value before the next layer can use it).
+EXTRA = {"fea_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=true"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + COMMON + EXTRA.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     if src.endswith(".hip"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -1794,6 +1794,17 @@ fea_status fea_get_kernel_timing(fea_ctx* c, double* resgrad_ms, int64_t* resgra
   return FEA_OK;
 }
 
+fea_status fea_get_kernel_times(fea_ctx* c, float* ms, int64_t cap, int64_t* n) {
+  if (!c || cap < 0 || (cap > 0 && !ms)) return FEA_EINVAL;
+  DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  const int64_t launches = (int64_t)(c->ev_used / 2);
+  for (int64_t k = 0; k < std::min(cap, launches); ++k)
+    HIP_OR_FAIL(c, hipEventElapsedTime(&ms[k], c->ev_pool[2 * k], c->ev_pool[2 * k + 1]));
+  if (n) *n = launches;
+  return FEA_OK;
+}
+
 fea_status fea_get_rotation_log(fea_ctx* c, double* R_log, int32_t* n_logged) {
   if (!c) return FEA_EINVAL;
   if (n_logged) *n_logged = c->n_logged;

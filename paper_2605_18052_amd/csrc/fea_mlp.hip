@@ -7,11 +7,13 @@
 // Inference (k_mlp_weights) is a dense contraction, so it runs on the matrix
 // cores: each wave takes 32 matches at a time and evaluates
 //   H1^T = relu(W1 X^T + b1),  H2^T = relu(W2 H1^T + b2),  y = sigmoid(w3.H2 + b3)
-// with v_mfma_f32_32x32x8 bf16 (bf16 activations and weights, fp32
-// accumulation).  With the weights as the A operand and the activations as
-// the B operand, the accumulator of one layer is already laid out as the B
-// operand of the next (lane l holds match l%32 and hidden units
-// 8s + 4(l/32) + 0..3 of K-slice s), so no data moves between layers.
+// with bf16 MFMA (bf16 activations and weights, fp32 accumulation).  With
+// the weights as the A operand and the activations as the B operand, the
+// accumulator of one layer is already laid out as the B operand of the next
+// (lane l holds match l%32 and hidden units 8s + 4(l/32) + 0..3 of K-slice
+// s), so no data moves between layers; the output layer is one more MFMA
+// chain whose A operand repeats w3 in every row, so that every accumulator
+// register of lane l ends up holding the logit of match l%32.
 //
 // Training (k_mlp_fwd_bwd, k_mlp_grad_reduce, k_mlp_adam) runs on the vector
 // units in fp32: one thread per sample for the forward and backward passes,
@@ -46,17 +48,24 @@ __device__ __forceinline__ short to_bf16(float x) {
 
 __device__ __forceinline__ float sigmoidf_(float z) { return 1.f / (1.f + __expf(-z)); }
 
-// ReLU on the bit patterns: a negative float (or bf16) has its sign bit set,
-// so as a signed integer it is negative, and the integer max with 0 maps it
-// to +0 while leaving non-negative values unchanged (one integer max per
-// fp32 value, one packed 16-bit max per two bf16 values, no NaN handling).
-__device__ __forceinline__ float relu_f32(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-typedef short s16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ bf16x8 relu_bf16x8(bf16x8 v) {
-  const s16x8 b = __builtin_bit_cast(s16x8, v);
-  return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(b, (s16x8)0));
+// Accumulator registers first..first+7 as one bf16 B-operand slice of the
+// next layer, ReLU applied: each pair is one packed conversion (round to
+// nearest even) and one packed 16-bit integer max with 0 -- a negative bf16
+// has its sign bit set, so as a signed integer it is negative and maps to
+// +0, while non-negative values are unchanged (no NaN handling).
+__device__ __forceinline__ bf16x8 relu_slice(const f32x16& acc, int first) {
+  u32x4 w;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const bf16x2 p = __builtin_convertvector((f32x2){acc[first + 2 * k], acc[first + 2 * k + 1]}, bf16x2);
+    w[k] = __builtin_bit_cast(unsigned, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), (s16x2)0));
+  }
+  return __builtin_bit_cast(bf16x8, w);
 }
 
 __device__ __forceinline__ double eps_at(const double* F, double x1, double y1, double x2, double y2) {
@@ -130,11 +139,16 @@ __global__ __launch_bounds__(kPairThreads) void k_snap3(int32_t P, const int32_t
 
 constexpr int kInferThreads = 256;
 
-// Moves 4 floats from lane l^32 (ds_bpermute).
-__device__ __forceinline__ void swap_half(const float (&src)[4], float (&dst)[4]) {
-  const int addr = ((int)__lane_id() ^ 32) << 2;
+// Lanes l < 32 receive lo[] of lane l+32 and lanes l >= 32 receive hi[] of
+// lane l-32 (v_permlane32_swap trades the upper half of its first operand
+// with the lower half of its second).
+__device__ __forceinline__ void swap_half(const float (&lo)[4], const float (&hi)[4], bool upper,
+                                          float (&dst)[4]) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) dst[q] = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(src[q])));
+  for (int q = 0; q < 4; ++q) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo[q]), __float_as_uint(hi[q]), false, false);
+    dst[q] = __uint_as_float(upper ? r[0] : r[1]);
+  }
 }
 
 // Inference over one work item.  Each wave takes 64 matches per iteration,
@@ -162,8 +176,8 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
   // layer 2 slice (t2, g) value j <-> hidden-in unit 32 t2 + 16 g + 8 (j/4) + 4 h + j%4
   const int r32 = lane & 31, h = lane >> 5;
   bf16x4 a1[2];
-  bf16x8 a2[2][4];
-  f32x16 b1v[2], b2v[2], w3v[2];
+  bf16x8 a2[2][4], a3[4];
+  f32x16 b1v[2], b2v[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int orow = r32 + 32 * t;
@@ -185,8 +199,15 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
       const int u = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);  // hidden unit of accumulator r
       b1v[t][r] = params[kOffB1 + u];
       b2v[t][r] = params[kOffB2 + u];
-      w3v[t][r] = params[kOffW3 + u];
     }
+  }
+  // output layer: w3 in every row, contraction permuted as for layer 2
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    const int t2 = sl >> 1, g = sl & 1;
+#pragma unroll
+    for (int jv = 0; jv < 8; ++jv)
+      a3[sl][jv] = (__bf16)params[kOffW3 + 32 * t2 + 16 * g + 8 * (jv >> 2) + 4 * h + (jv & 3)];
   }
   const float b3 = params[kOffB3];
   double F0[9], F1[9], F2[9];
@@ -233,45 +254,45 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
     }
     // lanes l and l^32 trade halves: group A = matches of lanes 0..31,
     // group B = lanes 32..63
-    float send[4], recv[4];
+    float lo[4], hi[4], recv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) send[q] = h ? f[q] : f[4 + q];
-    swap_half(send, recv);
+    for (int q = 0; q < 4; ++q) {
+      lo[q] = f[q];
+      hi[q] = f[4 + q];
+    }
+    swap_half(lo, hi, h != 0, recv);
     float zg[2];
 #pragma unroll
     for (int grp = 0; grp < 2; ++grp) {
-      bf16x4h bxh;
+      // group A: h=0 own f[0..3], h=1 partner's f[4..7]; group B: h=0
+      // partner's f[0..3], h=1 own f[4..7]
+      float xv[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        // group A: h=0 own f[0..3], h=1 partner's f[4..7]; group B: h=0
-        // partner's f[0..3], h=1 own f[4..7]
-        const float v = (grp == 0) ? (h ? recv[q] : f[q]) : (h ? f[4 + q] : recv[q]);
-        bxh[q] = (__bf16)v;
-      }
-      const bf16x4 bx = __builtin_bit_cast(bf16x4, bxh);
+      for (int q = 0; q < 4; ++q) xv[q] = (grp == 0) ? (h ? recv[q] : f[q]) : (h ? f[4 + q] : recv[q]);
+      const bf16x2 x01 = __builtin_convertvector((f32x2){xv[0], xv[1]}, bf16x2);
+      const bf16x2 x23 = __builtin_convertvector((f32x2){xv[2], xv[3]}, bf16x2);
+      const bf16x4 bx = __builtin_bit_cast(
+          bf16x4, (f32x2){__builtin_bit_cast(float, x01), __builtin_bit_cast(float, x23)});
       f32x16 acc1[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[t], bx, b1v[t], 0, 0, 0);
       bf16x8 hb[4];
 #pragma unroll
-      for (int sl = 0; sl < 4; ++sl) {
-        const int t2 = sl >> 1, g = sl & 1;
-#pragma unroll
-        for (int jv = 0; jv < 8; ++jv) hb[sl][jv] = (__bf16)acc1[t2][4 * (2 * g + (jv >> 2)) + (jv & 3)];
-        hb[sl] = relu_bf16x8(hb[sl]);
-      }
-      float z = 0.f;
+      for (int sl = 0; sl < 4; ++sl) hb[sl] = relu_slice(acc1[sl >> 1], 8 * (sl & 1));
+      f32x16 acc2[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        f32x16 acc = b2v[t];
+        acc2[t] = b2v[t];
 #pragma unroll
-        for (int sl = 0; sl < 4; ++sl) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t][sl], hb[sl], acc, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) z = fmaf(w3v[t][r], relu_f32(acc[r]), z);
+        for (int sl = 0; sl < 4; ++sl)
+          acc2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t][sl], hb[sl], acc2[t], 0, 0, 0);
       }
-      // lanes l and l^32 hold the two halves of the group's match l%32
-      z += __int_as_float(__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, __float_as_int(z)));
-      zg[grp] = z;
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) hb[sl] = relu_slice(acc2[sl >> 1], 8 * (sl & 1));
+      f32x16 acc3 = {};
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[sl], hb[sl], acc3, 0, 0, 0);
+      zg[grp] = acc3[0];  // every row of the output tile is the logit
     }
     // lane l's own match is in group h
     const float w = sigmoidf_((h ? zg[1] : zg[0]) + b3);

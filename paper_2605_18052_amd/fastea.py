@@ -100,6 +100,7 @@ _SIGNATURES = {
     "fea_set_kernel_timing": ([_P, C.c_int32], C.c_int),
     "fea_hbm_probe": ([C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
     "fea_get_kernel_timing": ([_P, _P, _P], C.c_int),
+    "fea_get_kernel_times": ([_P, _P, C.c_int64, _P], C.c_int),
 }
 
 
@@ -426,6 +427,14 @@ class Context:
         n = C.c_int64(0)
         self._check(lib().fea_get_kernel_timing(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def kernel_times(self):
+        """Per-launch durations (ms, launch order) of the timed per-match kernel launches."""
+        n = C.c_int64(0)
+        self._check(lib().fea_get_kernel_times(self._h, None, 0, C.byref(n)))
+        out = np.zeros(max(n.value, 1), np.float32)
+        self._check(lib().fea_get_kernel_times(self._h, out.ctypes.data_as(_P), n.value, C.byref(n)))
+        return out[:n.value].astype(np.float64)
 
     def get_rotation_log(self, max_log):
         N = self.n_cams

@@ -82,9 +82,12 @@ def test_mfma_inference_matches_oracle():
     feat = oracle.mlp_features(oracle_problem(sc), [snaps[2], snaps[1], snaps[0]])
     ref = oracle.mlp_forward(feat, params.astype(np.float32).astype(np.float64))
     err = np.abs(w - ref)
-    # bf16 keeps 8 mantissa bits: ~0.4% per feature and weight, a few times
-    # that on the logit, at most 1/4 of it on the sigmoid
-    assert err.max() < 3e-2 and err.mean() < 5e-3, (err.max(), err.mean())
+    print(f"learned weight vs FP64 network: max |err| {err.max():.3g}, mean {err.mean():.3g}, "
+          f"max rel {(err / np.maximum(ref, 1e-3)).max():.3g}", flush=True)
+    # bf16 keeps 8 mantissa bits: ~0.4% per feature, weight and activation,
+    # a few times that on the logit, at most 1/4 of it on the sigmoid; the
+    # weight lies in [0, 1], so the bound is absolute
+    assert err.max() < 1e-2 and err.mean() < 2.5e-3, (err.max(), err.mean())
     assert ref.std() > 0.05  # the network is not constant on these inputs
 
 

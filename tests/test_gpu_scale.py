@@ -1,0 +1,72 @@
+"""Parity at the benchmark's own size: the ~20M-match, 500-camera trajectory
+scene in its first IRLS round at the default threshold, the per-match kernel
+in the tile the autotuner picks and in each fixed tile, every camera's
+gradient against the FP64 oracle evaluated over all matches."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_18052_amd import fastea, synth
+
+from gpu_helpers import make_context, per_camera_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bench_scene():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sc = synth.config2()
+    rng = np.random.default_rng(21)
+    dR = synth.rotation_from_axis_angle(rng.normal(size=(sc.n_cams, 3)), np.deg2rad(0.5) * np.ones(sc.n_cams))
+    R = dR @ sc.R_init
+    t = sc.t_init + rng.normal(scale=0.01, size=sc.t_init.shape)
+    f = sc.f_init * np.exp(rng.uniform(-0.01, 0.01, sc.n_cams))
+    pb = oracle.OracleProblem.from_scene(sc)
+    tau = fastea.default_options().tau_px_init / np.median(sc.f_init)
+    mask, Z = oracle.update_mask(pb, sc.R_init, sc.t_init, sc.f_init, tau, np.ones(sc.n_matches, bool))
+    eps = np.abs(oracle.residuals(pb, sc.R_init, sc.t_init, sc.f_init))
+    print(f"bench scene: {sc.n_matches} matches, {Z} retained at tau {tau:.4g}", flush=True)
+    return sc, pb, (R, t, f), tau, mask, Z, eps
+
+
+@pytest.mark.parametrize("tile", [0, 1024, 2048, 4096, 8192])
+def test_bench_workload_gradient_vs_oracle(bench_scene, tile):
+    sc, pb, (R, t, f), tau, mask_ref, Z_ref, eps = bench_scene
+    opt = fastea.default_options()
+    ctx = make_context(sc, gauge=0, tile_matches=tile)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    ctx.begin_round(opt.tau_px_init)
+    info = ctx.info()
+    assert tile == 0 or info["tile_matches"] == tile
+    ctx.set_poses(R, t, f)
+    loss, gR, gt, gf = ctx.residual_grad()
+    mask, Z = ctx.get_mask()
+    ctx.close()
+    # the retained set: identical except within rounding of the threshold
+    diff = np.flatnonzero(mask != mask_ref)
+    assert np.all(np.abs(eps[diff] - tau) <= 1e-9 * tau), diff[:10]
+    assert Z == int(mask.sum())
+    # both sides with the same retained set and Z
+    lr, gRr, gtr, gfr = (oracle.loss_grad(pb, R, t, f, sc.R_init, sc.t_init, sc.f_init, mask, delta=opt.delta)
+                         if len(diff) else bench_scene_ref(bench_scene, opt.delta))
+    l = float(loss.item())
+    assert abs(l - lr) <= 1e-5 * abs(lr), (l, lr)
+    for a, b in ((gR.cpu().numpy(), gRr), (gt.cpu().numpy(), gtr), (gf.cpu().numpy()[:, None], gfr[:, None])):
+        ok, worst = per_camera_close(a, b)
+        assert ok, (info["tile_matches"], worst)
+
+
+_REF = {}
+
+
+def bench_scene_ref(bench_scene, delta):
+    """The oracle's loss and gradient with its own retained set (computed once)."""
+    if "ref" not in _REF:
+        sc, pb, (R, t, f), tau, mask_ref, Z_ref, eps = bench_scene
+        _REF["ref"] = oracle.loss_grad(pb, R, t, f, sc.R_init, sc.t_init, sc.f_init, mask_ref, delta=delta)
+    return _REF["ref"]

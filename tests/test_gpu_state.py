@@ -147,3 +147,29 @@ def test_mismatched_states_are_rejected():
         m.set_state(ls)
     assert e.value.status == fastea.FEA_ESTATE
     m.close()
+
+
+def test_kernel_timing_leaves_results_unchanged():
+    """Steps timed with per-launch HIP events (no graph replay) give the same
+    poses bit for bit as untimed steps replayed from graphs; every timed
+    launch is reported and the per-launch durations add up to the total."""
+    sc = synth.config1()
+    out = []
+    for timed in (False, True):
+        ctx = make_context(sc)
+        ctx.init_poses(sc.R_init, sc.t_init)
+        ctx.begin_round(16.0)
+        ctx.set_kernel_timing(timed)
+        ctx.step(25)
+        if timed:
+            total, n = ctx.kernel_timing()
+            each = ctx.kernel_times()
+            assert n == 25 and len(each) == 25
+            assert np.all(each > 0)
+            assert abs(each.sum() - total) <= 1e-6 * total
+            ctx.set_kernel_timing(False)
+            assert ctx.kernel_timing() == (0.0, 0) and len(ctx.kernel_times()) == 0
+        out.append(ctx.get_poses())
+        ctx.close()
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(x, y)
