@@ -34,20 +34,27 @@ METRIC = "residual+grad matches/s and HBM GB/s vs peak; wall time to ≤1° mean
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_MATCH = 16  # x1, y1, x2, y2 as fp32: the algorithmic minimum per match
 
-# HBM bytes per launch of the per-match kernel at round 0 of this workload,
+# HBM bytes per launch of the per-match kernel at round 0 of each workload,
 # from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch
 # scaled by what the same counters read for a 1 GiB plain copy: x2.0, x1.0),
-# summarised in profiles/k_resgrad_traj500_m20M_hbm_traffic.md.  They hold
+# summarised in profiles/k_resgrad_<workload>_hbm_traffic.md.  They hold
 # only for the kernel source they were taken on (hashed below) and are keyed
-# by work-item shape, which the autotuner may pick differently per run.
+# by the retained-match count and the work-item shape, which the autotuner
+# may pick differently per run.
 KERNEL_SOURCES = ("paper_2605_18052_amd/csrc/fea_resgrad.hip", "paper_2605_18052_amd/csrc/fea_device.h",
                   "paper_2605_18052_amd/csrc/fea_ctx.h")
 PMC_TRAFFIC = {
     "sources_sha256": "f6866b2ae461ae6f557126cbea34ed9180ab553dea3f987d61cb2b523ef119a9",
-    "matches_per_launch": 17819274,
-    "bytes_per_launch": {  # "matches x threads" -> fetched + written bytes
-        "1024x128": 301053950, "1024x256": 301038527, "2048x128": 294116227, "2048x256": 294079235,
-        "4096x128": 290427785, "4096x256": 290352010, "4096x512": 290307019, "8192x512": 290315915,
+    # retained matches per launch -> "matches x threads" -> fetched + written bytes
+    "bytes_per_launch": {
+        17819274: {  # traj500_m20M, round 0
+            "1024x128": 301053950, "1024x256": 301038527, "2048x128": 294116227, "2048x256": 294079235,
+            "4096x128": 290427785, "4096x256": 290352010, "4096x512": 290307019, "8192x512": 290315915,
+        },
+        87275962: {  # traj3000_m100M, round 0
+            "1024x128": 1484899361, "1024x256": 1484887714, "2048x128": 1448140683, "2048x256": 1448100812,
+            "4096x128": 1446745384, "4096x256": 1446671466, "4096x512": 1446626411, "8192x512": 1446683113,
+        },
     },
 }
 
@@ -58,9 +65,9 @@ def measured_traffic(tile, Z):
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != PMC_TRAFFIC["sources_sha256"] or Z != PMC_TRAFFIC["matches_per_launch"]:
+    if h.hexdigest() != PMC_TRAFFIC["sources_sha256"]:
         return None
-    return PMC_TRAFFIC["bytes_per_launch"].get(tile)
+    return PMC_TRAFFIC["bytes_per_launch"].get(Z, {}).get(tile)
 
 
 WORKLOADS = {

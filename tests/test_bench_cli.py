@@ -22,14 +22,17 @@ def test_traffic_only_for_the_measured_kernel():
     import bench
     t = bench.PMC_TRAFFIC
     if t["sources_sha256"] is None:
-        assert bench.measured_traffic("2048x256", t["matches_per_launch"]) is None
+        assert bench.measured_traffic("2048x256", 17819274) is None
         return
-    tile = next(iter(t["bytes_per_launch"]))
-    assert bench.measured_traffic(tile, t["matches_per_launch"] + 1) is None
+    Z = next(iter(t["bytes_per_launch"]))
+    tile = next(iter(t["bytes_per_launch"][Z]))
+    assert bench.measured_traffic(tile, Z) == t["bytes_per_launch"][Z][tile]
+    assert bench.measured_traffic(tile, Z + 1) is None
+    assert bench.measured_traffic("3x5", Z) is None
     saved = t["sources_sha256"]
     try:
         t["sources_sha256"] = "0" * 64
-        assert bench.measured_traffic(tile, t["matches_per_launch"]) is None
+        assert bench.measured_traffic(tile, Z) is None
     finally:
         t["sources_sha256"] = saved
     json.dumps(t)
