@@ -514,7 +514,8 @@ fea_status run_steps(fea_ctx* c, int32_t n_steps) {
 }
 
 // Host -> device copy of the step counters: Adam count `t` and global count
-// `g` into the slots of the current parity.
+// `g` into the slots of the current parity, and the round's learning-rate
+// factor.
 hipError_t set_counters(fea_ctx* c, int64_t t, int64_t g) {
   fea::StepCounters h;
   std::memset(&h, 0, sizeof(h));
@@ -522,6 +523,7 @@ hipError_t set_counters(fea_ctx* c, int64_t t, int64_t g) {
   h.global_t[c->pcur] = g;
   h.b1t[c->pcur] = std::pow(c->opt.beta1, (double)t);
   h.b2t[c->pcur] = std::pow(c->opt.beta2, (double)t);
+  h.lr_scale = c->lr_scale;
   return stage_copy(c, c->counters.p, &h, sizeof(h));
 }
 
@@ -556,7 +558,8 @@ hipError_t compact_layout(fea_ctx* c, const uint32_t* mask) {
   if ((e = hipMemsetAsync(c->lpos[dst].p, 0xFF, span * sizeof(int32_t), c->stream)) != hipSuccess) return e;
   if ((e = upload(c, c->item_base, base.data(), c->n_items)) != hipSuccess) return e;
   if ((e = fea::launch_filter_scatter(c, dst, mask)) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  // no wait: later work on the stream sees the new layout in order, and the
+  // host builds the work items meanwhile
   c->cur = dst;
   c->cur_len = new_len;
   c->phys_off = new_off;
@@ -622,7 +625,10 @@ hipError_t round_weights(fea_ctx* c, bool choose_mode) {
   return upload(c, c->d_inv_zw, c->inv_zw_h.data(), c->S);
 }
 
-fea_status begin_round(fea_ctx* c, double tau_px) {
+// sync: wait for the round's set-up work before returning (the solver's own
+// rounds do not, so that graph capture and the host's item building overlap
+// the device's compaction).
+fea_status begin_round(fea_ctx* c, double tau_px, bool sync) {
   const size_t N = c->N;
   // snapshot and its history (learned features), round parameters for the
   // judge's restore, and (new objective) fresh Adam moments -- one kernel
@@ -658,6 +664,7 @@ fea_status begin_round(fea_ctx* c, double tau_px) {
     if (!c->tile_tuned) {
       HIP_OR_FAIL(c, choose_tile(c));
       HIP_OR_FAIL(c, build_items(c));
+      drop_graph(c);
     }
     if (c->round < 0) HIP_OR_FAIL(c, fea::launch_mask_init(c));
     HIP_OR_FAIL(c, round_weights(c, true));
@@ -672,8 +679,12 @@ fea_status begin_round(fea_ctx* c, double tau_px) {
     HIP_OR_FAIL(c, choose_tile(c));
     HIP_OR_FAIL(c, build_items(c));
   }
+  c->lr_scale = std::pow(c->opt.lr_decay, (double)(c->round + 1));
   HIP_OR_FAIL(c, set_counters(c, c->adam_t, c->global_step));
-  drop_graph(c);  // the layout or the weights changed: recapture on the next run of steps
+  // per match, the layout changed: recapture on the next run of steps.  The
+  // quadratic form's steps read only per-pair forms and device counters, so
+  // its captured graph stays valid across rounds.
+  if (!quad) drop_graph(c);
   if (!quad) {
     // learned weights of this round's retained matches, then the pose
     // table at the current poses with this round's normalisers
@@ -681,10 +692,9 @@ fea_status begin_round(fea_ctx* c, double tau_px) {
     HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
                                          c->Fc[c->pcur].as<double>(), false));
   }
-  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (sync) HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->round += 1;
   c->step = 0;
-  c->lr_scale = std::pow(c->opt.lr_decay, (double)c->round);
   return FEA_OK;
 }
 
@@ -858,6 +868,7 @@ void fea_destroy(fea_ctx* c) {
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   destroy_graph(c);
   if (c->stage) (void)hipHostFree(c->stage);
+  if (c->loss_log) (void)hipHostFree(c->loss_log);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1156,7 +1167,7 @@ fea_status fea_begin_round(fea_ctx* c, double tau_px) {
   if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
   if (std::isnan(tau_px) || !(tau_px > 0)) return fail(c, FEA_EINVAL, "tau_px must be > 0 (or INFINITY)");
   DeviceGuard g(c->device);
-  return begin_round(c, tau_px);
+  return begin_round(c, tau_px, true);
 }
 
 fea_status fea_residual_grad(fea_ctx* c, double* loss_dev, double* gR_dev, double* gt_dev, double* gf_dev) {
@@ -1266,7 +1277,7 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
   std::memset(&rep, 0, sizeof(rep));
   for (int r = 0; r < c->opt.rounds; ++r) {
     const double tau_px = std::max(c->opt.tau_px_init * std::pow(c->opt.tau_decay, (double)r), c->opt.tau_px_min);
-    fea_status s = begin_round(c, tau_px);
+    fea_status s = begin_round(c, tau_px, false);
     if (s != FEA_OK) return s;
     std::vector<double> l0, l1;
     if (c->learned_any) {
@@ -1294,15 +1305,18 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
       }
     }
     if (r < 64) {
+      // into pinned memory, so the copy is queued without waiting for the
+      // round's steps
       rep.inliers_per_round[r] = c->Z;
+      if (!c->loss_log) HIP_OR_FAIL(c, hipHostMalloc(&c->loss_log, 64 * sizeof(double), hipHostMallocDefault));
       HIP_OR_FAIL(c, fea::launch_loss_sum(c));
-      HIP_OR_FAIL(c, hipMemcpyAsync(&rep.loss_per_round[r], c->loss.p, sizeof(double), hipMemcpyDeviceToHost,
-                                    c->stream));
+      HIP_OR_FAIL(c, hipMemcpyAsync(c->loss_log + r, c->loss.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     }
     rep.rounds_run = r + 1;
     rep.iters_run += c->opt.iters_per_round;
   }
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  for (int r = 0; r < std::min(rep.rounds_run, 64); ++r) rep.loss_per_round[r] = c->loss_log[r];
   rep.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   rep.n_logged = c->n_logged;
   rep.fallbacks = c->fallbacks;

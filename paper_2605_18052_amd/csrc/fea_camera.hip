@@ -36,6 +36,7 @@ __device__ __forceinline__ void adam_step(double& p, double& m, double& v, doubl
   p -= lr * (m / bc1) / (sqrt(v / bc2) + eps);
 }
 
+// Base learning rates (scaled on the device by StepCounters::lr_scale).
 struct AdamArgs {
   double lr_rot, lr_t, lr_f, b1, b2, eps;
 };
@@ -194,6 +195,7 @@ __global__ __launch_bounds__(256) void k_camgrad(
     g_own = gf * Fc[cam];
     lr = optimize_focal ? ad.lr_f : 0.0;
   }
+  lr *= sc.ctr->lr_scale;
   const bool step_own = lane < 9 || optimize_focal;
   if (step_own) adam_step(p_own, m_own, v_own, g_own, lr, ad.b1, ad.b2, ad.eps, 1.0 - b1t, 1.0 - b2t);
   if (lane < 6) {
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(kFocalThreads) void k_focal_update(
     }
     // the camera kernel of this step has advanced the counters to slot pn
     double m = m_f[g], v = v_f[g];
-    adam_step(p, m, v, s, ad.lr_f, ad.b1, ad.b2, ad.eps, 1.0 - ctr->b1t[pn], 1.0 - ctr->b2t[pn]);
+    adam_step(p, m, v, s, ad.lr_f * ctr->lr_scale, ad.b1, ad.b2, ad.eps, 1.0 - ctr->b1t[pn], 1.0 - ctr->b2t[pn]);
     logf[g] = p;
     m_f[g] = m;
     v_f[g] = v;
@@ -280,9 +282,10 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_sum(int N, const double* 
   }
 }
 
+// Base learning rates; the kernels multiply them by the round's factor held
+// in the step counters, so a captured step graph stays valid across rounds.
 AdamArgs adam_args(const fea_ctx* c) {
-  return AdamArgs{c->opt.lr_rot * c->lr_scale, c->opt.lr_t * c->lr_scale, c->opt.lr_logf * c->lr_scale,
-                  c->opt.beta1, c->opt.beta2, c->opt.adam_eps};
+  return AdamArgs{c->opt.lr_rot, c->opt.lr_t, c->opt.lr_logf, c->opt.beta1, c->opt.beta2, c->opt.adam_eps};
 }
 
 StepCtl step_ctl(fea_ctx* c) {

@@ -58,6 +58,7 @@ struct StepCounters {
   long long global_t[2];
   double b1t[2];
   double b2t[2];
+  double lr_scale;  // learning-rate factor of the round (lr_decay^round)
 };
 
 // Thin owner of one device allocation.
@@ -184,6 +185,7 @@ struct fea_ctx {
   // pinned staging ring for small host-to-device copies
   void* stage = nullptr;
   size_t stage_used = 0;
+  double* loss_log = nullptr;  // pinned host: loss at the end of each solver round (64)
 
   // kernel timing (HIP events around each per-match pass)
   bool timing = false;
