@@ -7,8 +7,9 @@
 // (the same 16 bytes per match as the per-match kernel) and accumulates, per
 // lane in fp64, the 45 distinct entries of sum c w w^T with
 // w = vec(p2 p1^T) in centred pixel coordinates and c the round's IRLS weight
-// (times the learned weight on learned scenes).  The 45 sums are reduced over
-// the wave with DPP and over the waves in LDS into one fp64 partial per item;
+// (times the learned weight on learned scenes), one wavefront per work item.
+// The 45 sums are reduced over the wave (DPP, then LDS) into one fp64
+// partial per item;
 // k_quad_reduce adds a pair's item partials in item order into W_n.
 //
 // Every step, the camera kernel evaluates dL/dF = 2 W_n f and the loss
@@ -35,23 +36,33 @@ __device__ __forceinline__ unsigned short v4w(const ushort4& q, int e) {
   return e == 0 ? q.x : (e == 1 ? q.y : (e == 2 ? q.z : q.w));
 }
 
-// One item of the round's pass: the threshold test at the snapshot
-// (|eps_hat| < tau, strict) of the matches the mask still holds, the updated
-// mask, the item's survivor count (and, with WEIGHTED,
-// the sum of the survivors' learned weights), and the 45 sums of
-// c' w w^T over the survivors with c' = 1/max(|eps_hat|, delta) times the
-// learned weight on learned scenes -- the 1/Z normaliser, known only once
-// every item has been counted, is applied when the items are summed into
-// W_n.  The next 16-byte vectors are loaded before the current ones are used.
+// One item of the round's pass per wavefront (kBuildItems items per
+// workgroup, no block-level synchronisation): the threshold test at the
+// snapshot (|eps_hat| < tau, strict) of the matches the mask still holds,
+// the updated mask, the item's survivor count (and, with WEIGHTED, the sum
+// of the survivors' learned weights), and the 45 sums of c' w w^T over the
+// survivors with c' = 1/max(|eps_hat|, delta) times the learned weight on
+// learned scenes -- the 1/Z normaliser, known only once every item has been
+// counted, is applied when the items are summed into W_n.  The test is
+// branch-free: a dropped match gets c' = 0 and adds exactly zero.  The 45
+// per-lane sums are reduced over each group of 4 lanes with DPP, then the 16
+// group sums are transposed through LDS and added in group order by lanes
+// 0..44, which store the item's partial coalesced.  The next 16-byte
+// vectors are loaded before the current ones are used.
+constexpr int kBuildItems = kQuadThreads / kWave;
+constexpr int kBuildGroups = kWave / 4;
+
 template <bool WEIGHTED>
 __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
-    const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
+    int32_t n_items, const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
     const float4* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ ptab,
     const ushort4* __restrict__ Wl, uchar4* __restrict__ mask, double delta, double* __restrict__ qpart,
     int32_t* __restrict__ keep, double* __restrict__ wkept) {
-  __shared__ double s_red[kQuadThreads / kWave][kQuad + 1];
-  __shared__ int s_cnt[kQuadThreads / kWave];
-  const int tid = threadIdx.x, item = blockIdx.x;
+  __shared__ double s_t[kBuildItems][kBuildGroups][kQuad + 1];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int item = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kBuildItems + wid);
+  if (item >= n_items) return;  // the whole wave
   const int4 rec = items[item];
   const int n = rec.x;
   const int v0 = rec.y >> 2;
@@ -71,7 +82,7 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
   for (int k = 0; k < kQuad; ++k) acc[k] = 0.0;
   double wsum = 0.0;
   int kept = 0;
-  int v = tid;
+  int v = lane;
   float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a, d = a;
   ushort4 wq = make_ushort4(0, 0, 0, 0);
   uchar4 mq = make_uchar4(0, 0, 0, 0);
@@ -83,11 +94,11 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
     if (WEIGHTED) wq = Wl[v0 + v];
     mq = mask[v0 + v];
   }
-  for (; v < nvec; v += kQuadThreads) {
+  for (; v < nvec; v += kWave) {
     const float4 ca = a, cb = b, cc = c, cd = d;
     const ushort4 cw4 = wq;
     const uchar4 cm = mq;
-    const int vn = v + kQuadThreads;
+    const int vn = v + kWave;
     if (vn < nvec) {
       a = X1[v0 + vn];
       b = Y1[v0 + vn];
@@ -96,7 +107,7 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
       if (WEIGHTED) wq = Wl[v0 + vn];
       mq = mask[v0 + vn];
     }
-    unsigned char out[kVec] = {0, 0, 0, 0};
+    unsigned char out[kVec];
 #pragma unroll
     for (int e = 0; e < kVec; ++e) {
       const double x1 = v4q(ca, e), y1 = v4q(cb, e), x2 = v4q(cc, e), y2 = v4q(cd, e);
@@ -105,14 +116,14 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
       const double l2 = fma(Fh[6], x1, fma(Fh[7], y1, Fh[8]));
       const double eph = fma(x2, l0, fma(y2, l1, l2));
       const unsigned char was = e == 0 ? cm.x : (e == 1 ? cm.y : (e == 2 ? cm.z : cm.w));
-      if (!(was && v * kVec + e < cnt && fabs(eph) < tau)) continue;
-      out[e] = 1;
-      ++kept;
-      double cw = 1.0 / fmax(fabs(eph), delta);
+      const bool hold = was && v * kVec + e < cnt && fabs(eph) < tau;
+      out[e] = hold ? 1 : 0;
+      kept += hold ? 1 : 0;
+      double cw = hold ? 1.0 / fmax(fabs(eph), delta) : 0.0;
       if (learned) {
         const double wl = (double)__uint_as_float((uint32_t)v4w(cw4, e) << 16);
         cw *= wl;
-        wsum += wl;
+        wsum += hold ? wl : 0.0;
       }
       const double p1[3] = {x1 - cxi, y1 - cyi, 1.0};
       const double p2[3] = {x2 - cxj, y2 - cyj, 1.0};
@@ -120,44 +131,42 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int s = 0; s < 3; ++s) w[3 * r + s] = p2[r] * p1[s];
+        for (int q = 0; q < 3; ++q) w[3 * r + q] = p2[r] * p1[q];
       int k = 0;
 #pragma unroll
       for (int r = 0; r < 9; ++r) {
         const double cr = cw * w[r];
 #pragma unroll
-        for (int s = r; s < 9; ++s, ++k) acc[k] = fma(cr, w[s], acc[k]);
+        for (int q = r; q < 9; ++q, ++k) acc[k] = fma(cr, w[q], acc[k]);
       }
     }
     mask[v0 + v] = make_uchar4(out[0], out[1], out[2], out[3]);  // a dropped match stays dropped
   }
-  wave_sum_f64_multi<kQuad>(acc);
-  wsum = wave_sum_f64(wsum);
+  // groups of 4 lanes, then the 16 group sums through LDS in group order
+#pragma unroll
+  for (int k = 0; k < kQuad; ++k) acc[k] += dpp_f64<0xB1>(acc[k]);  // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int k = 0; k < kQuad; ++k) acc[k] += dpp_f64<0x4E>(acc[k]);  // quad_perm [2,3,0,1]
+  if ((lane & 3) == 0) {
+#pragma unroll
+    for (int k = 0; k < kQuad; ++k) s_t[wid][lane >> 2][k] = acc[k];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane < kQuad) {
+    double sum = 0.0;
+#pragma unroll
+    for (int g = 0; g < kBuildGroups; ++g) sum += s_t[wid][g][lane];
+    qpart[(int64_t)item * kQuad + lane] = sum;
+  }
   int kw = kept;
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) kw += __shfl_xor(kw, m);
-  const int wid = tid >> 6, lane = tid & 63;
+  if (WEIGHTED) wsum = wave_sum_f64(wsum);
   if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < kQuad; ++k) s_red[wid][k] = acc[k];
-    s_red[wid][kQuad] = wsum;
-    s_cnt[wid] = kw;
-  }
-  __syncthreads();
-  if (tid <= kQuad) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kQuadThreads / kWave; ++w) s += s_red[w][tid];
-    if (tid < kQuad)
-      qpart[(int64_t)item * kQuad + tid] = s;
-    else if (WEIGHTED)
-      wkept[item] = s;
-  }
-  if (tid == 0) {
-    int s = 0;
-#pragma unroll
-    for (int w = 0; w < kQuadThreads / kWave; ++w) s += s_cnt[w];
-    keep[item] = s;
+    keep[item] = kw;
+    if (WEIGHTED) wkept[item] = wsum;
   }
 }
 
@@ -203,10 +212,11 @@ hipError_t launch_quad_build(fea_ctx* c) {
   c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(), \
       c->item_rec.as<int4>(), c->ptab.as<double>(), c->wlay.as<ushort4>(), c->qmask.as<uchar4>(), c->opt.delta,  \
       c->qpart.as<double>(), c->item_keep.as<int32_t>(), c->item_wsum.as<double>()
+  const unsigned blocks = (unsigned)((c->n_items + kBuildItems - 1) / kBuildItems);
   if (c->learned_any)
-    k_quad_build<true><<<(unsigned)c->n_items, kQuadThreads, 0, c->stream>>>(FEA_QUAD_BUILD_ARGS);
+    k_quad_build<true><<<blocks, kQuadThreads, 0, c->stream>>>((int32_t)c->n_items, FEA_QUAD_BUILD_ARGS);
   else
-    k_quad_build<false><<<(unsigned)c->n_items, kQuadThreads, 0, c->stream>>>(FEA_QUAD_BUILD_ARGS);
+    k_quad_build<false><<<blocks, kQuadThreads, 0, c->stream>>>((int32_t)c->n_items, FEA_QUAD_BUILD_ARGS);
 #undef FEA_QUAD_BUILD_ARGS
   return hipGetLastError();
 }
