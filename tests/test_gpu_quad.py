@@ -184,3 +184,24 @@ def test_quad_retained_mask_is_monotone_and_counted():
     kept[perm[pos[pos >= 0]]] = True
     assert np.array_equal(kept, prev)
     ctx.close()
+
+
+@pytest.mark.parametrize("inner_loop", [0, 1])
+def test_solver_rounds_with_graphs_equal_eager(inner_loop):
+    """fea_epipolar_adjust over three rounds of an even number of steps, so
+    that the quadratic form's captured step graph is kept from round to round
+    (the round's learning-rate factor comes from the device counters) and the
+    per-match rounds return before their compaction has run: the poses equal
+    those of eager launches bit for bit."""
+    sc = SCENES["sphere20_m60k"]
+    res = []
+    for g in (0, 1):
+        ctx = make_context(sc, inner_loop=inner_loop, use_graphs=g, rounds=3, iters_per_round=20,
+                           lr_decay=0.5)
+        ctx.init_poses(sc.R_init, sc.t_init)
+        rep = ctx.epipolar_adjust()
+        res.append(ctx.get_poses() + (rep["loss"],))
+        ctx.close()
+    for a, b in zip(*res):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+    assert len(set(np.asarray(res[1][3]).tolist())) == 3  # a loss logged for every round
