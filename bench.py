@@ -44,16 +44,16 @@ BYTES_PER_MATCH = 16  # x1, y1, x2, y2 as fp32: the algorithmic minimum per matc
 KERNEL_SOURCES = ("paper_2605_18052_amd/csrc/fea_resgrad.hip", "paper_2605_18052_amd/csrc/fea_device.h",
                   "paper_2605_18052_amd/csrc/fea_ctx.h")
 PMC_TRAFFIC = {
-    "sources_sha256": "f6866b2ae461ae6f557126cbea34ed9180ab553dea3f987d61cb2b523ef119a9",
+    "sources_sha256": "1de3074fefdf6ec31ded877ac634540c3c4fd613ffbd5f602883db497f3f9109",
     # retained matches per launch -> "matches x threads" -> fetched + written bytes
     "bytes_per_launch": {
         17819274: {  # traj500_m20M, round 0
-            "1024x128": 301053950, "1024x256": 301038527, "2048x128": 294116227, "2048x256": 294079235,
-            "4096x128": 290427785, "4096x256": 290352010, "4096x512": 290307019, "8192x512": 290315915,
+            "1024x128": 301054135, "1024x256": 301038135, "2048x128": 294116413, "2048x256": 294079229,
+            "4096x128": 290427907, "4096x256": 290351877, "4096x512": 290307334, "8192x512": 290315846,
         },
         87275962: {  # traj3000_m100M, round 0
-            "1024x128": 1484899361, "1024x256": 1484887714, "2048x128": 1448140683, "2048x256": 1448100812,
-            "4096x128": 1446745384, "4096x256": 1446671466, "4096x512": 1446626411, "8192x512": 1446683113,
+            "1024x128": 1484899427, "1024x256": 1484886115, "2048x128": 1448136555, "2048x256": 1448099180,
+            "4096x128": 1446744009, "4096x256": 1446670091, "4096x512": 1446625036, "8192x512": 1446682506,
         },
     },
 }

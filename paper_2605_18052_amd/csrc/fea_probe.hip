@@ -72,9 +72,11 @@ extern "C" fea_status fea_hbm_probe(int32_t device, int64_t bytes, int32_t reps,
   hipEvent_t e0 = nullptr, e1 = nullptr;
   fea_status st = FEA_OK;
   hipDeviceProp_t prop;
+  // 32 workgroups per CU: fewer leave HBM bandwidth unused (8 per CU read
+  // ~6% less on a 1.4 GB stream)
   const int blocks = (hipGetDeviceProperties(&prop, device) == hipSuccess)
-                         ? prop.multiProcessorCount * 8
-                         : 2048;
+                         ? prop.multiProcessorCount * 32
+                         : 8192;
   if (hipMalloc(&a, n * 16) != hipSuccess || hipMalloc(&b, n * 16) != hipSuccess ||
       hipMalloc(&sink, blocks * sizeof(float)) != hipSuccess) {
     st = FEA_ENOMEM;
