@@ -119,7 +119,7 @@ std::vector<DBuf*> all_bufs(fea_ctx* c) {
                  &c->R[1], &c->T[0], &c->T[1], &c->Fc[0], &c->Fc[1], &c->Rh, &c->Th, &c->Fh, &c->gR,
                  &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag, &c->Re, &c->Te, &c->Fe, &c->d_pair_scene, &c->d_inv_z, &c->d_tau, &c->ptab, &c->qpart, &c->qW, &c->qmask, &c->stab, &c->counters,
                  &c->Rh1, &c->Th1, &c->Fh1, &c->Rh2, &c->Th2, &c->Fh2, &c->d_fbar, &c->mlp, &c->wlay,
-                 &c->item_wsum, &c->d_inv_zw, &c->d_scene_mode, &c->a6h, &c->tph, &c->logfh, &c->restore_flag};
+                 &c->item_wsum, &c->d_inv_zw, &c->d_scene_mode, &c->d_fbar_hist, &c->d_scene_cam_off, &c->d_scene_cams, &c->d_scene_z, &c->a6h, &c->tph, &c->logfh, &c->restore_flag};
   for (DBuf* b : one) v.push_back(b);
   return v;
 }
@@ -212,7 +212,7 @@ hipError_t build_items(fea_ctx* c) {
     return e;
   if ((e = dalloc(c->item_keep, std::max<int64_t>(c->n_items, 1) * sizeof(int32_t))) != hipSuccess) return e;
   if ((e = dalloc(c->item_wsum, std::max<int64_t>(c->n_items, 1) * sizeof(double))) != hipSuccess) return e;
-  return dalloc(c->item_base, std::max<int64_t>(c->n_items, 1) * sizeof(int32_t));
+  return dalloc(c->item_base, std::max<int64_t>(c->n_items, 1) * 2 * sizeof(int32_t));
 }
 
 // Per-scene device arrays sized by the number of scenes.
@@ -222,11 +222,57 @@ hipError_t alloc_scene_arrays(fea_ctx* c) {
   if ((e = dalloc(c->d_inv_zw, (size_t)c->S * sizeof(float))) != hipSuccess) return e;
   if ((e = dalloc(c->d_scene_mode, (size_t)c->S * sizeof(int32_t))) != hipSuccess) return e;
   if ((e = dalloc(c->d_fbar, 3 * (size_t)c->S * sizeof(float))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_fbar_hist, 3 * (size_t)c->S * sizeof(double))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_tau, (size_t)c->S * sizeof(double))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_scene_z, ((size_t)c->S + 1) * sizeof(int64_t))) != hipSuccess) return e;
+  // cameras of each scene, for the device round start
+  std::vector<int32_t> off(c->S + 1, 0), cams(c->N, 0);
+  for (int i = 0; i < c->N; ++i) off[c->cam_scene[i] + 1] += 1;
+  for (int s = 0; s < c->S; ++s) off[s + 1] += off[s];
+  c->max_scene_cams = 0;
+  for (int s = 0; s < c->S; ++s) c->max_scene_cams = std::max(c->max_scene_cams, off[s + 1] - off[s]);
+  {
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int i = 0; i < c->N; ++i) cams[fill[c->cam_scene[i]]++] = i;
+  }
+  if ((e = upload(c, c->d_scene_cam_off, off.data(), off.size())) != hipSuccess) return e;
+  if ((e = upload(c, c->d_scene_cams, cams.data(), cams.size())) != hipSuccess) return e;
+  c->host_tau_stale = c->host_z_stale = false;
   if ((e = hipMemsetAsync(c->d_inv_zw.p, 0, c->d_inv_zw.bytes, c->stream)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(c->d_scene_mode.p, 0, c->d_scene_mode.bytes, c->stream)) != hipSuccess) return e;
   c->scene_mode.assign(c->S, 0);
   c->scene_learned_ok.assign(c->S, 1);
   return hipSuccess;
+}
+
+// The round values computed on the device (thresholds and focal-length
+// medians at the round start; quadratic form: survivors per scene and the
+// learned normalisers) copied into the host's records when they are read.
+hipError_t refresh_round_host(fea_ctx* c) {
+  hipError_t e = hipSuccess;
+  if (c->host_tau_stale) {
+    if ((e = download(c, c->taus, c->d_tau, c->S)) != hipSuccess) return e;
+    if ((e = download(c, c->fbar_hist, c->d_fbar_hist, 3 * (size_t)c->S)) != hipSuccess) return e;
+    c->tau = c->taus.empty() ? 0.0 : c->taus[0];
+    c->host_tau_stale = false;
+  }
+  if (c->host_z_stale) {
+    std::vector<int64_t> z;
+    if ((e = download(c, z, c->d_scene_z, (size_t)c->S + 1)) != hipSuccess) return e;
+    c->Zs.assign(z.begin(), z.begin() + c->S);
+    c->Z = z[c->S];
+    if (c->learned_any && (e = download(c, c->inv_zw_h, c->d_inv_zw, c->S)) != hipSuccess) return e;
+    c->host_z_stale = false;
+  }
+  return e;
+}
+
+// The host's focal-length medians to both device copies.
+hipError_t upload_fbar(fea_ctx* c) {
+  std::vector<float> fb(c->fbar_hist.begin(), c->fbar_hist.end());
+  hipError_t e = upload(c, c->d_fbar, fb.data(), fb.size());
+  if (e != hipSuccess) return e;
+  return upload(c, c->d_fbar_hist, c->fbar_hist.data(), c->fbar_hist.size());
 }
 
 int tile_cfg_for(int32_t tile_matches) {
@@ -324,6 +370,7 @@ hipError_t upload_scene_z(fea_ctx* c) {
     c->Z += c->Zs[s];
     inv[s] = c->Zs[s] > 0 ? (float)(1.0 / (double)c->Zs[s]) : 0.f;
   }
+  c->host_z_stale = false;
   return upload(c, c->d_inv_z, inv.data(), c->S);
 }
 
@@ -348,6 +395,7 @@ void reset_round_state(fea_ctx* c) {
   c->global_step = 0;
   c->n_logged = 0;
   c->tau = std::numeric_limits<double>::infinity();
+  c->host_tau_stale = c->host_z_stale = false;
 }
 
 fea_status load_matches_common(fea_ctx* c, int64_t n, const float* x1, const float* y1, const float* x2,
@@ -536,9 +584,11 @@ hipError_t compact_layout(fea_ctx* c, const uint32_t* mask) {
   if (e != hipSuccess) return e;
   std::vector<int32_t> keep;
   if ((e = download(c, keep, c->item_keep, c->n_items)) != hipSuccess) return e;
-  // new per-pair lengths, aligned offsets and per-item destinations
+  // new per-pair lengths, aligned offsets and per-item destinations; the
+  // last item of each pair also gets the aligned end of the pair's run, up
+  // to which it clears the padding
   std::vector<int64_t> new_len(c->P, 0), new_off(c->P, 0);
-  std::vector<int32_t> base(c->n_items, 0);
+  std::vector<int32_t> base(2 * c->n_items, -1);
   for (int64_t n = 0; n < c->P; ++n)
     for (int32_t it = c->h_pair_item_off[n]; it < c->h_pair_item_off[n + 1]; ++it) new_len[n] += keep[it];
   int64_t off = 0;
@@ -546,17 +596,14 @@ hipError_t compact_layout(fea_ctx* c, const uint32_t* mask) {
     new_off[n] = off;
     int64_t run = off;
     for (int32_t it = c->h_pair_item_off[n]; it < c->h_pair_item_off[n + 1]; ++it) {
-      base[it] = (int32_t)run;
+      base[2 * it] = (int32_t)run;
       run += keep[it];
     }
     off += (new_len[n] + fea::kAlign - 1) / fea::kAlign * fea::kAlign;
+    if (c->h_pair_item_off[n + 1] > c->h_pair_item_off[n]) base[2 * (c->h_pair_item_off[n + 1] - 1) + 1] = (int32_t)off;
   }
   const int dst = (c->cur == 1) ? 2 : 1;
-  const size_t span = (size_t)std::max<int64_t>(off, 1);
-  for (int a = 0; a < 4; ++a)
-    if ((e = hipMemsetAsync(c->lay[dst][a].p, 0, span * sizeof(float), c->stream)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(c->lpos[dst].p, 0xFF, span * sizeof(int32_t), c->stream)) != hipSuccess) return e;
-  if ((e = upload(c, c->item_base, base.data(), c->n_items)) != hipSuccess) return e;
+  if ((e = upload(c, c->item_base, base.data(), base.size())) != hipSuccess) return e;
   if ((e = fea::launch_filter_scatter(c, dst, mask)) != hipSuccess) return e;
   // no wait: later work on the stream sees the new layout in order, and the
   // host builds the work items meanwhile
@@ -576,6 +623,12 @@ hipError_t compact_layout(fea_ctx* c, const uint32_t* mask) {
 hipError_t quad_round(fea_ctx* c) {
   hipError_t e = fea::launch_quad_build(c);
   if (e != hipSuccess) return e;
+  if (c->scene_items_contiguous) {
+    // per-scene counts and normalisers on the device: no host round trip
+    if ((e = fea::launch_scene_z(c)) != hipSuccess) return e;
+    c->host_z_stale = true;
+    return fea::launch_quad_reduce(c, c->pair_item_off.as<int32_t>());
+  }
   std::vector<int32_t> keep;
   if ((e = download(c, keep, c->item_keep, c->n_items)) != hipSuccess) return e;
   c->Zs.assign(c->S, 0);
@@ -596,6 +649,7 @@ hipError_t quad_round(fea_ctx* c) {
     for (int sc = 0; sc < c->S; ++sc) c->inv_zw_h[sc] = zw[sc] > 0 ? (float)(1.0 / zw[sc]) : 0.f;
     if ((e = upload(c, c->d_inv_zw, c->inv_zw_h.data(), c->S)) != hipSuccess) return e;
   }
+  c->host_z_stale = false;
   return fea::launch_quad_reduce(c, c->pair_item_off.as<int32_t>());
 }
 
@@ -611,11 +665,12 @@ hipError_t round_weights(fea_ctx* c, bool choose_mode) {
   }
   hipError_t e = upload(c, c->d_scene_mode, c->scene_mode.data(), c->S);
   if (e != hipSuccess || !c->learned_any) return e;
-  std::vector<float> fb(c->fbar_hist.begin(), c->fbar_hist.end());
-  if ((e = upload(c, c->d_fbar, fb.data(), fb.size())) != hipSuccess) return e;
+  // the feature table reads the medians the round start left on the device
   if ((e = fea::launch_mlp_weights(c, c->mlp.as<float>(), c->wlay.as<unsigned short>(),
                                    c->item_wsum.as<double>(), nullptr)) != hipSuccess)
     return e;
+  // quadratic form: the round's pass sums the survivors' weights itself
+  if (c->opt.inner_loop == 1) return hipSuccess;
   std::vector<double> ws;
   if ((e = download(c, ws, c->item_wsum, c->n_items)) != hipSuccess) return e;
   std::vector<double> zw(c->S, 0.0);
@@ -635,27 +690,35 @@ fea_status begin_round(fea_ctx* c, double tau_px, bool sync) {
   const bool zero = c->opt.reset_moments || c->round < 0;
   HIP_OR_FAIL(c, fea::launch_round_start(c, c->round >= 0, c->round < 0, zero));
   if (zero) c->adam_t = 0;
-  std::vector<double> fnow;
-  HIP_OR_FAIL(c, download(c, fnow, c->Fc[c->pcur], N));
-  // threshold per scene: tau_px over the scene's median focal length
-  std::vector<std::vector<double>> fs(c->S);
-  for (size_t i = 0; i < N; ++i) fs[c->cam_scene[i]].push_back(fnow[i]);
-  if (c->round < 0) {
-    c->fbar_hist.assign(3 * c->S, 0.0);
-    for (int sc = 0; sc < c->S; ++sc)
-      for (int k = 0; k < 3; ++k) c->fbar_hist[k * c->S + sc] = fs[sc].empty() ? 1.0 : median(fs[sc]);
+  if (c->max_scene_cams <= fea::kMaxSceneCams) {
+    // thresholds and focal-length medians on the device: no host round trip
+    HIP_OR_FAIL(c, fea::launch_scene_tau(c, tau_px, c->round < 0));
+    c->host_tau_stale = true;
   } else {
-    for (int sc = 0; sc < c->S; ++sc) {
-      c->fbar_hist[2 * c->S + sc] = c->fbar_hist[c->S + sc];
-      c->fbar_hist[c->S + sc] = c->fbar_hist[sc];
-      c->fbar_hist[sc] = fs[sc].empty() ? 1.0 : median(fs[sc]);
+    HIP_OR_FAIL(c, refresh_round_host(c));
+    std::vector<double> fnow;
+    HIP_OR_FAIL(c, download(c, fnow, c->Fc[c->pcur], N));
+    // threshold per scene: tau_px over the scene's median focal length
+    std::vector<std::vector<double>> fs(c->S);
+    for (size_t i = 0; i < N; ++i) fs[c->cam_scene[i]].push_back(fnow[i]);
+    if (c->round < 0) {
+      c->fbar_hist.assign(3 * c->S, 0.0);
+      for (int sc = 0; sc < c->S; ++sc)
+        for (int k = 0; k < 3; ++k) c->fbar_hist[k * c->S + sc] = fs[sc].empty() ? 1.0 : median(fs[sc]);
+    } else {
+      for (int sc = 0; sc < c->S; ++sc) {
+        c->fbar_hist[2 * c->S + sc] = c->fbar_hist[c->S + sc];
+        c->fbar_hist[c->S + sc] = c->fbar_hist[sc];
+        c->fbar_hist[sc] = fs[sc].empty() ? 1.0 : median(fs[sc]);
+      }
     }
+    c->taus.assign(c->S, std::numeric_limits<double>::infinity());
+    if (!std::isinf(tau_px))
+      for (int sc = 0; sc < c->S; ++sc) c->taus[sc] = tau_px / (fs[sc].empty() ? 1.0 : median(fs[sc]));
+    HIP_OR_FAIL(c, upload(c, c->d_tau, c->taus.data(), c->S));
+    HIP_OR_FAIL(c, upload_fbar(c));
+    c->tau = c->taus.empty() ? 0.0 : c->taus[0];
   }
-  c->taus.assign(c->S, std::numeric_limits<double>::infinity());
-  if (!std::isinf(tau_px))
-    for (int sc = 0; sc < c->S; ++sc) c->taus[sc] = tau_px / (fs[sc].empty() ? 1.0 : median(fs[sc]));
-  HIP_OR_FAIL(c, upload(c, c->d_tau, c->taus.data(), c->S));
-  c->tau = c->taus.empty() ? 0.0 : c->taus[0];
   const bool quad = c->opt.inner_loop == 1;
   if (quad) {
     // the full layout stays; a mask marks the retained matches.  The
@@ -869,6 +932,7 @@ void fea_destroy(fea_ctx* c) {
   destroy_graph(c);
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->loss_log) (void)hipHostFree(c->loss_log);
+  if (c->inl_log) (void)hipHostFree(c->inl_log);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -984,6 +1048,7 @@ fea_status fea_get_scene_stats(fea_ctx* c, double* loss, int64_t* retained, doub
   if (!c) return FEA_EINVAL;
   if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
   DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, refresh_round_host(c));
   if (loss) {
     std::vector<double> lc;
     HIP_OR_FAIL(c, download(c, lc, c->loss_cam, c->N));
@@ -1307,8 +1372,13 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
     if (r < 64) {
       // into pinned memory, so the copy is queued without waiting for the
       // round's steps
-      rep.inliers_per_round[r] = c->Z;
       if (!c->loss_log) HIP_OR_FAIL(c, hipHostMalloc(&c->loss_log, 64 * sizeof(double), hipHostMallocDefault));
+      if (!c->inl_log) HIP_OR_FAIL(c, hipHostMalloc(&c->inl_log, 64 * sizeof(int64_t), hipHostMallocDefault));
+      if (c->host_z_stale)
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->inl_log + r, c->d_scene_z.as<int64_t>() + c->S, sizeof(int64_t),
+                                      hipMemcpyDeviceToHost, c->stream));
+      else
+        c->inl_log[r] = c->Z;
       HIP_OR_FAIL(c, fea::launch_loss_sum(c));
       HIP_OR_FAIL(c, hipMemcpyAsync(c->loss_log + r, c->loss.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     }
@@ -1316,7 +1386,10 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
     rep.iters_run += c->opt.iters_per_round;
   }
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-  for (int r = 0; r < std::min(rep.rounds_run, 64); ++r) rep.loss_per_round[r] = c->loss_log[r];
+  for (int r = 0; r < std::min(rep.rounds_run, 64); ++r) {
+    rep.loss_per_round[r] = c->loss_log[r];
+    rep.inliers_per_round[r] = c->inl_log[r];
+  }
   rep.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   rep.n_logged = c->n_logged;
   rep.fallbacks = c->fallbacks;
@@ -1397,6 +1470,7 @@ fea_status fea_get_mask(fea_ctx* c, uint8_t* mask, int64_t* n_retained) {
   if (!c) return FEA_EINVAL;
   if (!c->have_matches) return fail(c, FEA_ESTATE, "load matches first");
   DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, refresh_round_host(c));
   if (n_retained) *n_retained = c->Z;
   if (!mask) return FEA_OK;
   std::vector<uint8_t> keep;
@@ -1420,6 +1494,7 @@ fea_status fea_get_state(fea_ctx* c, void* buf, size_t* len) {
     return fail(c, FEA_EINVAL, "buffer too small for the state (size written to *len)");
   }
   DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, refresh_round_host(c));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   StateHdr h;
   std::memset(&h, 0, sizeof(h));
@@ -1528,6 +1603,7 @@ fea_status fea_set_state(fea_ctx* c, const void* buf, size_t len) {
   take(r, bits.data(), bits.size());
   c->inv_zw_h.assign(S, 0.f);
   take(r, c->inv_zw_h.data(), S);
+  c->host_tau_stale = c->host_z_stale = false;
   c->round = h.round;
   c->step = h.step;
   c->n_logged = h.n_logged;
@@ -1576,6 +1652,7 @@ fea_status fea_set_state(fea_ctx* c, const void* buf, size_t len) {
       HIP_OR_FAIL(c, build_items(c));
     }
     HIP_OR_FAIL(c, upload(c, c->d_tau, c->taus.data(), S));
+    HIP_OR_FAIL(c, upload_fbar(c));
     const std::vector<float> izw_saved(c->inv_zw_h);
     HIP_OR_FAIL(c, round_weights(c, false));
     // the learned normalisers as they were (their sums ran over the
@@ -1610,6 +1687,10 @@ fea_status fea_ablation(fea_ctx* c, int32_t variant, int32_t reps, double* ms_pe
 
 fea_status fea_get_info(fea_ctx* c, fea_info* out) {
   if (!c || !out) return fail(c, FEA_EINVAL, "null argument");
+  if (c->host_tau_stale || c->host_z_stale) {
+    DeviceGuard g(c->device);
+    HIP_OR_FAIL(c, refresh_round_host(c));
+  }
   std::memset(out, 0, sizeof(*out));
   out->n_cams = c->N;
   out->n_groups = c->G;
@@ -1653,8 +1734,6 @@ fea_status fea_mlp_features_dev(fea_ctx* c, float* feat_dev, int32_t* slot_pos_d
   if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
   if (!feat_dev) return fail(c, FEA_EINVAL, "feat_dev is required");
   DeviceGuard g(c->device);
-  std::vector<float> fb(c->fbar_hist.begin(), c->fbar_hist.end());
-  HIP_OR_FAIL(c, upload(c, c->d_fbar, fb.data(), fb.size()));
   HIP_OR_FAIL(c, hipMemsetAsync(feat_dev, 0, (size_t)c->layout_len * fea::kMlpFeat * sizeof(float), c->stream));
   HIP_OR_FAIL(c, fea::launch_mlp_weights(c, c->mlp.as<float>(), c->wlay.as<unsigned short>(),
                                          c->item_wsum.as<double>(), feat_dev));

@@ -235,6 +235,7 @@ __global__ __launch_bounds__(256) void k_camgrad(
 }
 
 constexpr int kFocalThreads = 256;
+constexpr int kTauThreads = 256;
 
 // One thread per intrinsics group shared by several cameras.
 __global__ __launch_bounds__(kFocalThreads) void k_focal_update(
@@ -376,6 +377,101 @@ __global__ void k_restore(int N, const int32_t* __restrict__ flag, const int32_t
   logf[group[c]] = logfh[group[c]];  // identical value from every camera of the group
 }
 
+// Round start on the device, so that a round needs no host round trip:
+// one workgroup per scene sorts its cameras' focal lengths in LDS (bitonic,
+// padded with +inf to a power of two), takes the median the host would (the
+// middle value, or the mean of the two middle values for an even count; 1
+// for a scene without cameras), sets the threshold tau_px / median
+// (infinite stays infinite) and shifts the history of medians at the
+// snapshots r, r-1, r-2 (all three set at the first round), in fp64 and as
+// the fp32 copy the learned features read.
+__global__ __launch_bounds__(kTauThreads) void k_scene_tau(int S, const int32_t* __restrict__ scene_cam_off,
+                                                           const int32_t* __restrict__ scene_cams,
+                                                           const double* __restrict__ Fc, double tau_px, int first,
+                                                           double* __restrict__ fbar_hist, float* __restrict__ fbar,
+                                                           double* __restrict__ tau) {
+  __shared__ double v[kMaxSceneCams];
+  const int s = blockIdx.x;
+  const int b = scene_cam_off[s], n = scene_cam_off[s + 1] - b;
+  int p2 = 1;
+  while (p2 < n) p2 <<= 1;
+  for (int i = threadIdx.x; i < p2; i += kTauThreads) v[i] = i < n ? Fc[scene_cams[b + i]] : INFINITY;
+  __syncthreads();
+  for (int k = 2; k <= p2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < p2; i += kTauThreads) {
+        const int l = i ^ j;
+        if (l > i) {
+          const double a = v[i], c = v[l];
+          if (((i & k) == 0) ? (a > c) : (a < c)) {
+            v[i] = c;
+            v[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  if (threadIdx.x == 0) {
+    const double med = n == 0 ? 1.0 : ((n & 1) ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]));
+    if (first) {
+      for (int k = 0; k < 3; ++k) fbar_hist[k * S + s] = med;
+    } else {
+      fbar_hist[2 * S + s] = fbar_hist[S + s];
+      fbar_hist[S + s] = fbar_hist[s];
+      fbar_hist[s] = med;
+    }
+    for (int k = 0; k < 3; ++k) fbar[k * S + s] = (float)fbar_hist[k * S + s];
+    tau[s] = isinf(tau_px) ? tau_px : tau_px / med;
+  }
+}
+
+// Per-scene normalisers of a quadratic-form round on the device (each
+// scene's items contiguous): Z_s = survivors (exact, int64) and, on learned
+// rounds, Z_w = sum of the survivors' learned weights (per-thread sums over
+// contiguous item chunks, then a fixed-order tree: deterministic).  Writes
+// 1/Z and 1/Z_w as the pose table reads them and Z_s; k_total_z then puts
+// the total Z in zs[S].
+__global__ __launch_bounds__(kTauThreads) void k_scene_z(const int32_t* __restrict__ scene_item_off,
+                                                         const int32_t* __restrict__ keep,
+                                                         const double* __restrict__ wsum, int learned,
+                                                         int64_t* __restrict__ zs, float* __restrict__ inv_z,
+                                                         float* __restrict__ inv_zw) {
+  __shared__ long long s_z[kTauThreads];
+  __shared__ double s_w[kTauThreads];
+  const int s = blockIdx.x, t = threadIdx.x;
+  const int b = scene_item_off[s], e = scene_item_off[s + 1], n = e - b;
+  const int per = (n + kTauThreads - 1) / kTauThreads;
+  long long z = 0;
+  double w = 0.0;
+  const int lo = b + t * per, hi = min(e, b + (t + 1) * per);
+  for (int it = lo; it < hi; ++it) {
+    z += keep[it];
+    if (learned) w += wsum[it];
+  }
+  s_z[t] = z;
+  s_w[t] = w;
+  __syncthreads();
+  for (int h = kTauThreads / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      s_z[t] += s_z[t + h];
+      s_w[t] += s_w[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    zs[s] = s_z[0];
+    inv_z[s] = s_z[0] > 0 ? (float)(1.0 / (double)s_z[0]) : 0.f;
+    if (learned) inv_zw[s] = s_w[0] > 0 ? (float)(1.0 / s_w[0]) : 0.f;
+  }
+}
+
+// The total Z after k_scene_z (one thread; S is small).
+__global__ void k_total_z(int S, int64_t* __restrict__ zs) {
+  long long z = 0;
+  for (int s = 0; s < S; ++s) z += zs[s];
+  zs[S] = z;
+}
+
 }  // namespace
 
 hipError_t launch_scene_loss(fea_ctx* c) {
@@ -471,6 +567,24 @@ hipError_t launch_focal_update(fea_ctx* c) {
 
 hipError_t launch_loss_sum(fea_ctx* c) {
   k_loss_sum<<<1, kLossThreads, 0, c->stream>>>(c->N, c->loss_cam.as<double>(), c->loss.as<double>());
+  return hipGetLastError();
+}
+
+
+hipError_t launch_scene_tau(fea_ctx* c, double tau_px, bool first) {
+  if (c->S == 0) return hipSuccess;
+  k_scene_tau<<<(unsigned)c->S, kTauThreads, 0, c->stream>>>(
+      c->S, c->d_scene_cam_off.as<int32_t>(), c->d_scene_cams.as<int32_t>(), c->Fc[c->pcur].as<double>(), tau_px,
+      first ? 1 : 0, c->d_fbar_hist.as<double>(), c->d_fbar.as<float>(), c->d_tau.as<double>());
+  return hipGetLastError();
+}
+
+hipError_t launch_scene_z(fea_ctx* c) {
+  if (c->S == 0) return hipSuccess;
+  k_scene_z<<<(unsigned)c->S, kTauThreads, 0, c->stream>>>(
+      c->d_scene_item_off.as<int32_t>(), c->item_keep.as<int32_t>(), c->item_wsum.as<double>(),
+      c->learned_any ? 1 : 0, c->d_scene_z.as<int64_t>(), c->d_inv_z.as<float>(), c->d_inv_zw.as<float>());
+  k_total_z<<<1, 1, 0, c->stream>>>(c->S, c->d_scene_z.as<int64_t>());
   return hipGetLastError();
 }
 

@@ -31,6 +31,9 @@ constexpr int kRowF = 0, kRowFh = 9, kRowInvZ = 18, kRowInvZw = 19, kRowMode = 2
               kRowTau = 25;
 constexpr int kPairRow = 32;
 constexpr int kPairThreads = 256;
+// Scenes up to this many cameras take the device round start (median of
+// their focal lengths sorted in LDS); larger ones the host path.
+constexpr int kMaxSceneCams = 8192;
 
 // Work-item shapes of the per-match kernel: threads per workgroup and 16-byte
 // loads per thread per array; matches per item = threads * 4 * steps.
@@ -164,6 +167,13 @@ struct fea_ctx {
   // learned weights
   fea::DBuf Rh1, Th1, Fh1, Rh2, Th2, Fh2;  // snapshots of the two previous rounds
   fea::DBuf d_fbar;                       // float [3*S]: median f per scene at the 3 snapshots
+  fea::DBuf d_fbar_hist;                  // double [3*S]: the same medians in fp64 (device round start)
+  fea::DBuf d_scene_cam_off, d_scene_cams;  // int32 [S+1], [N]: cameras of each scene
+  fea::DBuf d_scene_z;                    // int64 [S+1]: survivors per scene, total last (quadratic form)
+  int32_t max_scene_cams = 0;             // largest scene, in cameras
+  bool host_tau_stale = false;            // taus, tau, fbar_hist live on the device until read back
+  bool host_z_stale = false;              // Zs, Z live on the device until read back
+  int64_t* inl_log = nullptr;             // pinned host: Z of each solver round (64)
   fea::DBuf mlp;                          // float [kMlpParams]
   fea::DBuf wlay;                         // bf16 [layout] learned weight of each layout slot
   fea::DBuf item_wsum;                    // double [n_items]
@@ -222,6 +232,8 @@ hipError_t launch_focal_update(fea_ctx* c);
 hipError_t launch_loss_sum(fea_ctx* c);
 hipError_t launch_restore(fea_ctx* c, const std::vector<int32_t>& flag);
 hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero);
+hipError_t launch_scene_tau(fea_ctx* c, double tau_px, bool first);
+hipError_t launch_scene_z(fea_ctx* c);
 hipError_t launch_scene_loss(fea_ctx* c);
 hipError_t run_ablation(fea_ctx* c, int variant, int reps, double* ms, float* pair_sum_dev);
 hipError_t launch_camgrad_at(fea_ctx* c, const double* R, const double* T, const double* F);

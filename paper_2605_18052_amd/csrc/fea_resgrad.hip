@@ -245,7 +245,7 @@ template <bool BY_MASK>
 __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
     const float4* __restrict__ Y2, const int4* __restrict__ POS, const int4* __restrict__ items,
-    const double* __restrict__ ptab, const uint32_t* __restrict__ mask, const int32_t* __restrict__ base,
+    const double* __restrict__ ptab, const uint32_t* __restrict__ mask, const int2* __restrict__ base,
     float* __restrict__ ox1, float* __restrict__ oy1, float* __restrict__ ox2, float* __restrict__ oy2,
     int32_t* __restrict__ opos) {
   __shared__ int s_w[kFilterThreads / kWave];
@@ -260,7 +260,8 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
 #pragma unroll
   for (int k = 0; k < 9; ++k) Fhat[k] = row[kRowFh + k];
   const double tau = row[kRowTau];
-  int run = base[item];
+  const int2 bp = base[item];  // {first destination slot, aligned end of the pair's run or -1}
+  int run = bp.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int rounds = (nvec + kFilterThreads - 1) / kFilterThreads;
   for (int r = 0; r < rounds; ++r) {
@@ -313,6 +314,15 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
       }
     }
     run += total;
+  }
+  // the pair's last item clears the alignment padding after the survivors
+  // (fewer than 32 slots), so the new layout needs no clearing beforehand
+  for (int sl = run + tid; sl < bp.y; sl += kFilterThreads) {
+    ox1[sl] = 0.f;
+    oy1[sl] = 0.f;
+    ox2[sl] = 0.f;
+    oy2[sl] = 0.f;
+    opos[sl] = -1;
   }
 }
 
@@ -443,7 +453,7 @@ hipError_t launch_filter_scatter(fea_ctx* c, int dst, const uint32_t* mask) {
   const int b = c->cur;
 #define FEA_FILTER_SCATTER_ARGS                                                                               \
   c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(), \
-      c->lpos[b].as<int4>(), c->item_rec.as<int4>(), c->ptab.as<double>(), mask, c->item_base.as<int32_t>(),  \
+      c->lpos[b].as<int4>(), c->item_rec.as<int4>(), c->ptab.as<double>(), mask, c->item_base.as<int2>(),       \
       c->lay[dst][0].as<float>(), c->lay[dst][1].as<float>(), c->lay[dst][2].as<float>(),                    \
       c->lay[dst][3].as<float>(), c->lpos[dst].as<int32_t>()
   if (mask)
