@@ -116,6 +116,19 @@ def cpu_baseline(sc, n_sample, iters):
     t0 = time.perf_counter()
     oracle.epipolar_adjust(pb, sc.R_init, sc.t_init, sc.f_init, options=opt)
     dt = time.perf_counter() - t0
+    # the same on one host thread, on a tenth of the sample and of the steps
+    threads = oracle.num_threads()
+    sel1 = sel[: max(len(sel) // 10, 1)]
+    pb1 = oracle.OracleProblem.from_scene(sc, sel1)
+    opt1 = oracle.default_options(rounds=1, iters_per_round=max(iters // 10, 1),
+                                  tau_px_init=oracle.default_options().tau_px_init)
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.epipolar_adjust(pb1, sc.R_init, sc.t_init, sc.f_init, options=opt1)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(threads)
     model = None
     try:
         with open("/proc/cpuinfo") as fh:
@@ -123,10 +136,12 @@ def cpu_baseline(sc, n_sample, iters):
     except OSError:
         pass
     return {"value": pb.n_matches * iters / dt, "unit": "matches/s",
-            "cores": oracle.num_threads(), "cpu_model": model, "kind": "oracle",
+            "cores": threads, "cpu_model": model, "kind": "oracle",
+            "value_1thread": pb1.n_matches * opt1.iters_per_round / dt1,
             "sample": f"{pb.n_matches} random matches of the same scene, 1 round x {iters} "
                       f"steps of the FP64 C oracle incl. its one-time segmenting, "
-                      f"{dt:.1f} s wall"}
+                      f"{dt:.1f} s wall on {threads} threads; value_1thread: "
+                      f"{pb1.n_matches} matches x {opt1.iters_per_round} steps on one thread, {dt1:.1f} s"}
 
 
 def time_to_one_degree(sc, fastea, metrics, every=10, **options):

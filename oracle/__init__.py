@@ -84,6 +84,7 @@ def lib():
         _lib.orc_mlp_bce_grad.argtypes = [C.c_int64, P, P, P, P]
         _lib.orc_mlp_bce_grad.restype = C.c_double
         _lib.orc_num_threads.restype = C.c_int
+        _lib.orc_set_threads.argtypes = [C.c_int]
     return _lib
 
 
@@ -280,6 +281,11 @@ def epipolar_adjust(pb: OracleProblem, R0, t0, f0, intr_group=None, options=None
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
 
 
 MLP_NFEAT = 8

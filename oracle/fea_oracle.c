@@ -22,6 +22,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads for the following parallel regions (per-pair partial sums are
+   added in a fixed order, so results do not depend on it). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 void orc_default_options(orc_options *o) {
   o->rounds = 20;
   o->iters_per_round = 50;

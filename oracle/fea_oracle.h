@@ -180,6 +180,7 @@ double orc_mlp_bce_grad(int64_t n, const double *feat, const double *target, con
 
 /* Number of OpenMP threads the oracle would use (1 without OpenMP). */
 int orc_num_threads(void);
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }
