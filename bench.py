@@ -44,16 +44,16 @@ BYTES_PER_MATCH = 16  # x1, y1, x2, y2 as fp32: the algorithmic minimum per matc
 KERNEL_SOURCES = ("paper_2605_18052_amd/csrc/fea_resgrad.hip", "paper_2605_18052_amd/csrc/fea_device.h",
                   "paper_2605_18052_amd/csrc/fea_ctx.h")
 PMC_TRAFFIC = {
-    "sources_sha256": "1de3074fefdf6ec31ded877ac634540c3c4fd613ffbd5f602883db497f3f9109",
+    "sources_sha256": "10fc816065221f5ecbd974c1d762a90e59f0451a201e2a6698cfa67a5887e534",
     # retained matches per launch -> "matches x threads" -> fetched + written bytes
     "bytes_per_launch": {
         17819274: {  # traj500_m20M, round 0
-            "1024x128": 301054135, "1024x256": 301038135, "2048x128": 294116413, "2048x256": 294079229,
-            "4096x128": 290427907, "4096x256": 290351877, "4096x512": 290307334, "8192x512": 290315846,
+            "1024x128": 301053751, "1024x256": 301038583, "2048x128": 294116285, "2048x256": 294079165,
+            "4096x128": 290428227, "4096x256": 290351749, "4096x512": 290307142, "8192x512": 290315846,
         },
         87275962: {  # traj3000_m100M, round 0
-            "1024x128": 1484899427, "1024x256": 1484886115, "2048x128": 1448136555, "2048x256": 1448099180,
-            "4096x128": 1446744009, "4096x256": 1446670091, "4096x512": 1446625036, "8192x512": 1446682506,
+            "1024x128": 1484902433, "1024x256": 1484885986, "2048x128": 1448137547, "2048x256": 1448101196,
+            "4096x128": 1446745448, "4096x256": 1446671466, "4096x512": 1446626411, "8192x512": 1446683369,
         },
     },
 }
@@ -116,11 +116,11 @@ def cpu_baseline(sc, n_sample, iters):
     t0 = time.perf_counter()
     oracle.epipolar_adjust(pb, sc.R_init, sc.t_init, sc.f_init, options=opt)
     dt = time.perf_counter() - t0
-    # the same on one host thread, on a tenth of the sample and of the steps
+    # the same on one host thread, on a tenth of the sample and a fifth of the steps
     threads = oracle.num_threads()
     sel1 = sel[: max(len(sel) // 10, 1)]
     pb1 = oracle.OracleProblem.from_scene(sc, sel1)
-    opt1 = oracle.default_options(rounds=1, iters_per_round=max(iters // 10, 1),
+    opt1 = oracle.default_options(rounds=1, iters_per_round=max(iters // 5, 1),
                                   tau_px_init=oracle.default_options().tau_px_init)
     oracle.set_threads(1)
     try:
