@@ -323,3 +323,28 @@ def test_graph_replay_matches_eager_launches():
     (R0, t0, f0, l0), (R1, t1, f1, l1) = out
     assert np.array_equal(R0, R1) and np.array_equal(t0, t1) and np.array_equal(f0, f1)
     assert len(l0) == len(l1) == 15 and np.array_equal(l0, l1)
+
+
+@pytest.mark.parametrize("n_cams", [20, 5])
+def test_round_threshold_uses_the_median_focal_length(n_cams):
+    """The round start computes each scene's threshold on the device: tau_px
+    over the median of the scene's current focal lengths (mean of the two
+    middle values for an even count), equal to numpy's median of the focal
+    lengths the library holds, exactly, at the first round and after steps
+    have moved them."""
+    sc = SCENES["sphere20_m60k"] if n_cams == 20 else synth.tiny_scene(n_cams=5, n_pts=60, seed=11)
+    f0 = sc.f_init * np.exp(np.linspace(-0.05, 0.05, sc.n_cams))
+    ctx = make_context(sc, f=f0)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    ctx.begin_round(64.0)
+    _, _, fc = ctx.get_poses()  # the library's f (held as log f) at the round start
+    np.testing.assert_allclose(fc, f0, rtol=1e-15)
+    assert ctx.info()["tau"] == 64.0 / np.median(fc)
+    ctx.step(7)
+    _, _, f1 = ctx.get_poses()
+    assert not np.array_equal(f1, f0)
+    ctx.begin_round(32.0)
+    assert ctx.info()["tau"] == 32.0 / np.median(f1)
+    ctx.begin_round(math.inf)
+    assert ctx.info()["tau"] == math.inf
+    ctx.close()
