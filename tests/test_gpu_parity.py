@@ -348,3 +348,33 @@ def test_round_threshold_uses_the_median_focal_length(n_cams):
     ctx.begin_round(math.inf)
     assert ctx.info()["tau"] == math.inf
     ctx.close()
+
+
+def test_round_threshold_host_path_for_large_scenes():
+    """A scene with more cameras than the device round start sorts in LDS
+    (9,000 here) takes the host path for its median focal length; the
+    threshold is the same expression, and steps run at that camera count."""
+    rng = np.random.default_rng(17)
+    N, per = 9000, 8
+    f = rng.uniform(400.0, 1200.0, N)
+    cx, cy = np.full(N, 320.0), np.full(N, 240.0)
+    R = np.tile(np.eye(3), (N, 1, 1))
+    t = rng.normal(size=(N, 3))
+    i = np.repeat(np.arange(N), per)
+    j = (i + 1) % N
+    M = len(i)
+    x1, x2 = (rng.uniform(0, 640, M).astype(np.float32) for _ in range(2))
+    y1, y2 = (rng.uniform(0, 480, M).astype(np.float32) for _ in range(2))
+    ctx = fastea.Context(0, fastea.default_options(gauge_normalize=0))
+    ctx.load_intrinsics(f, cx, cy)
+    ctx.load_matches(x1, y1, x2, y2, i.astype(np.int32), j.astype(np.int32))
+    ctx.init_poses(R, t)
+    ctx.begin_round(64.0)
+    _, _, fc = ctx.get_poses()
+    assert ctx.info()["tau"] == 64.0 / np.median(fc)
+    ctx.step(3)
+    _, _, f1 = ctx.get_poses()
+    ctx.begin_round(32.0)
+    assert ctx.info()["tau"] == 32.0 / np.median(f1)
+    assert np.all(np.isfinite(f1))
+    ctx.close()
