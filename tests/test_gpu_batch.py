@@ -27,12 +27,12 @@ def _scenes():
                                    name="d", calib_sample=5000)]
 
 
-def _opts():
-    return fastea.default_options(rounds=4, iters_per_round=15, tile_matches=2048)
+def _opts(inner_loop=0):
+    return fastea.default_options(rounds=4, iters_per_round=15, tile_matches=2048, inner_loop=inner_loop)
 
 
-def _solo(sc):
-    ctx = fastea.Context(0, _opts())
+def _solo(sc, inner_loop=0):
+    ctx = fastea.Context(0, _opts(inner_loop))
     ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
     ctx.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
     ctx.init_poses(sc.R_init, sc.t_init)
@@ -43,10 +43,14 @@ def _solo(sc):
     return R, t, f, mask, rep
 
 
-def test_batched_equals_individual():
+@pytest.mark.parametrize("inner_loop", [0, 1])
+def test_batched_equals_individual(inner_loop):
+    """Per match and with the quadratic form (whose per-scene counts and
+    normalisers are summed on the device): each scene of the batch ends as
+    it does when solved alone."""
     scenes = _scenes()
     cat, cam_scene, offs = synth.concat_scenes(scenes)
-    ctx = fastea.Context(0, _opts())
+    ctx = fastea.Context(0, _opts(inner_loop))
     ctx.load_intrinsics(cat["f_init"], cat["cx"], cat["cy"])
     ctx.set_scenes(cam_scene)
     ctx.load_matches(cat["x1"], cat["y1"], cat["x2"], cat["y2"], cat["cam1"], cat["cam2"])
@@ -59,7 +63,7 @@ def test_batched_equals_individual():
     ctx.close()
     m0 = 0
     for k, sc in enumerate(scenes):
-        Rs, ts, fs, ms, rep = _solo(sc)
+        Rs, ts, fs, ms, rep = _solo(sc, inner_loop)
         sl = slice(offs[k], offs[k + 1])
         np.testing.assert_allclose(R[sl], Rs, rtol=0, atol=1e-12)
         np.testing.assert_allclose(t[sl], ts, rtol=1e-12, atol=1e-12)
