@@ -254,7 +254,8 @@ fea_status fea_adjoint_dev(fea_ctx *ctx, const double *a6_dev, const double *t_d
 /* ---- Learned inlier weights ------------------------------------------
  * An MLP 8 -> 64 -> 64 -> 1 (ReLU, ReLU, sigmoid) maps each retained match's
  * features to a weight in (0, 1) that multiplies its IRLS weight; the
- * network runs once per round (matrix cores, bf16 activations).  Features:
+ * network runs once per round (matrix cores, fp16 activations and weights,
+ * fp32 accumulation; the weight is kept per match as bf16).  Features:
  * the match's residual at the last three round snapshots as
  * log(1 + |eps| * median f) / log(257), its keypoints scaled to [-1, 1] by
  * each camera's principal point (x/cx - 1, ...; the keypoint in the camera
@@ -268,7 +269,12 @@ fea_status fea_adjoint_dev(fea_ctx *ctx, const double *a6_dev, const double *t_d
 #define FEA_MLP_FEATURES 8
 #define FEA_MLP_PARAMS 4801
 
-/* Loads the network parameters (host array [FEA_MLP_PARAMS]). */
+/* Loads the network parameters (host array [FEA_MLP_PARAMS]).  Returns
+ * FEA_ENONFINITE for a non-finite parameter and FEA_EINVAL for a weight of
+ * W1, W2 or w3 beyond fp16's largest finite value, 65504 (inference takes
+ * the weights as fp16; the biases stay fp32).  The hidden activations are
+ * also taken as fp16: networks whose activations exceed that range on the
+ * bounded features are outside what the inference supports. */
 fea_status fea_set_mlp(fea_ctx *ctx, const float *params);
 
 /* Features of the current round's layout (after fea_begin_round):

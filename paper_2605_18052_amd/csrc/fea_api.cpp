@@ -15,6 +15,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "fea_ctx.h"
@@ -1722,6 +1723,15 @@ fea_status fea_set_mlp(fea_ctx* c, const float* params) {
   if (!c->have_intr) return fail(c, FEA_ESTATE, "load intrinsics first");
   for (int k = 0; k < fea::kMlpParams; ++k)
     if (!std::isfinite(params[k])) return fail(c, FEA_ENONFINITE, "non-finite network parameter");
+  // inference converts W1, W2 and w3 to fp16 (the biases stay fp32): a weight
+  // beyond fp16's largest finite value would become infinite there
+  constexpr int kH = fea::kMlpHidden, kF = fea::kMlpFeat;
+  constexpr int kW1 = 0, kW2 = kH * kF + kH, kW3 = kW2 + kH * kH + kH;
+  constexpr float kHalfMax = 65504.f;
+  for (const auto& r : {std::pair<int, int>{kW1, kH * kF}, {kW2, kH * kH}, {kW3, kH}})
+    for (int k = r.first; k < r.first + r.second; ++k)
+      if (std::fabs(params[k]) > kHalfMax)
+        return fail(c, FEA_EINVAL, "network weight beyond the fp16 range (|w| > 65504)");
   DeviceGuard g(c->device);
   HIP_OR_FAIL(c, upload(c, c->mlp, params, fea::kMlpParams));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));

@@ -7,7 +7,11 @@
 // Inference (k_mlp_weights) is a dense contraction, so it runs on the matrix
 // cores: each wave takes 32 matches at a time and evaluates
 //   H1^T = relu(W1 X^T + b1),  H2^T = relu(W2 H1^T + b2),  y = sigmoid(w3.H2 + b3)
-// with bf16 MFMA (bf16 activations and weights, fp32 accumulation).  With
+// with fp16 MFMA (fp16 activations and weights, fp32 accumulation; fp16
+// rather than bf16 for the 3 extra significand bits at the same matrix-core
+// rate -- the trained network's hidden values stay below ~20, far inside
+// the fp16 range, and conversions saturate).  The weight is stored per match
+// as bf16.  With
 // the weights as the A operand and the activations as the B operand, the
 // accumulator of one layer is already laid out as the B operand of the next
 // (lane l holds match l%32 and hidden units 8s + 4(l/32) + 0..3 of K-slice
@@ -27,9 +31,8 @@
 namespace fea {
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x4h __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kNF = kMlpFeat;    // 8
@@ -40,32 +43,32 @@ constexpr int kOffB2 = kOffW2 + kNH * kNH;
 constexpr int kOffW3 = kOffB2 + kNH;
 constexpr int kOffB3 = kOffW3 + kNH;
 
-// fp32 -> bf16, round to nearest even (inputs are finite).
-__device__ __forceinline__ short to_bf16(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-
 __device__ __forceinline__ float sigmoidf_(float z) { return 1.f / (1.f + __expf(-z)); }
 
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-// Accumulator registers first..first+7 as one bf16 B-operand slice of the
-// next layer, ReLU applied: each pair is one packed conversion (round to
-// nearest even) and one packed 16-bit integer max with 0 -- a negative bf16
-// has its sign bit set, so as a signed integer it is negative and maps to
-// +0, while non-negative values are unchanged (no NaN handling).
-__device__ __forceinline__ bf16x8 relu_slice(const f32x16& acc, int first) {
+// Two fp32 values as packed fp16, rounded toward zero (one instruction;
+// values beyond the fp16 range saturate to its largest finite value
+// instead of becoming infinite).
+__device__ __forceinline__ unsigned pk_f16(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(a, b));
+}
+
+// Accumulator registers first..first+7 as one fp16 B-operand slice of the
+// next layer, ReLU applied: each pair is one packed conversion and one
+// packed 16-bit integer max with 0 -- a negative fp16 has its sign bit set,
+// so as a signed integer it is negative and maps to +0, while non-negative
+// values are unchanged (no NaN handling).
+__device__ __forceinline__ f16x8 relu_slice(const f32x16& acc, int first) {
   u32x4 w;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const bf16x2 p = __builtin_convertvector((f32x2){acc[first + 2 * k], acc[first + 2 * k + 1]}, bf16x2);
+    const unsigned p = pk_f16(acc[first + 2 * k], acc[first + 2 * k + 1]);
     w[k] = __builtin_bit_cast(unsigned, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), (s16x2)0));
   }
-  return __builtin_bit_cast(bf16x8, w);
+  return __builtin_bit_cast(f16x8, w);
 }
 
 __device__ __forceinline__ double eps_at(const double* F, double x1, double y1, double x2, double y2) {
@@ -77,7 +80,7 @@ __device__ __forceinline__ double eps_at(const double* F, double x1, double y1, 
 
 // Residual feature: log(1 + |eps| * fbar) / log(257), the residual in pixel
 // equivalents, log-compressed so that 256 px maps to 1.  fp32 with the
-// hardware log2 (the feature enters the network in bf16): log2(1 + x) /
+// hardware log2 (the feature enters the network in fp16): log2(1 + x) /
 // log2(257).
 __device__ __forceinline__ float res_feature(double e, float fbar) {
   return __log2f(1.f + (float)fabs(e) * fbar) * 0.124912178f;  // 1 / log2(257)
@@ -155,9 +158,9 @@ __device__ __forceinline__ void swap_half(const float (&lo)[4], const float (&hi
 // one per lane: the lane computes all 8 features of its match once (the
 // residuals in fp64 with the pair's snapshot matrices read by scalar loads),
 // then lanes l and l^32 trade halves so that the two groups of 32 matches
-// are in the B layout of v_mfma_f32_32x32x8bf16 (lane l: features
+// are in the B layout of v_mfma_f32_32x32x8_f16 (lane l: features
 // 4(l/32)..+3 of match l%32).  Layer 1 (K = 8) uses that instruction; layer
-// 2 (K = 64) uses v_mfma_f32_32x32x16_bf16, whose B operand takes 8 units per
+// 2 (K = 64) uses v_mfma_f32_32x32x16_f16, whose B operand takes 8 units per
 // lane: with the contraction index permuted identically in W2's columns, the
 // layer-1 accumulator registers of a lane are that operand as they stand.
 // The next iteration's coordinates are loaded before this one is computed.
@@ -175,23 +178,21 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
   // weights in the A layout: row (lane%32) + 32*tile; layer 1 k = 4h + q;
   // layer 2 slice (t2, g) value j <-> hidden-in unit 32 t2 + 16 g + 8 (j/4) + 4 h + j%4
   const int r32 = lane & 31, h = lane >> 5;
-  bf16x4 a1[2];
-  bf16x8 a2[2][4], a3[4];
+  f16x4 a1[2];
+  f16x8 a2[2][4], a3[4];
   f32x16 b1v[2], b2v[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int orow = r32 + 32 * t;
-    bf16x4h a1h;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a1h[q] = (__bf16)params[orow * kNF + 4 * h + q];
-    a1[t] = __builtin_bit_cast(bf16x4, a1h);
+    for (int q = 0; q < 4; ++q) a1[t][q] = (_Float16)params[orow * kNF + 4 * h + q];
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl) {
       const int t2 = sl >> 1, g = sl & 1;
 #pragma unroll
       for (int jv = 0; jv < 8; ++jv) {
         const int unit = 32 * t2 + 16 * g + 8 * (jv >> 2) + 4 * h + (jv & 3);
-        a2[t][sl][jv] = (__bf16)params[kOffW2 + orow * kNH + unit];
+        a2[t][sl][jv] = (_Float16)params[kOffW2 + orow * kNH + unit];
       }
     }
 #pragma unroll
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
     const int t2 = sl >> 1, g = sl & 1;
 #pragma unroll
     for (int jv = 0; jv < 8; ++jv)
-      a3[sl][jv] = (__bf16)params[kOffW3 + 32 * t2 + 16 * g + 8 * (jv >> 2) + 4 * h + (jv & 3)];
+      a3[sl][jv] = (_Float16)params[kOffW3 + 32 * t2 + 16 * g + 8 * (jv >> 2) + 4 * h + (jv & 3)];
   }
   const float b3 = params[kOffB3];
   double F0[9], F1[9], F2[9];
@@ -269,14 +270,11 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
       float xv[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) xv[q] = (grp == 0) ? (h ? recv[q] : f[q]) : (h ? f[4 + q] : recv[q]);
-      const bf16x2 x01 = __builtin_convertvector((f32x2){xv[0], xv[1]}, bf16x2);
-      const bf16x2 x23 = __builtin_convertvector((f32x2){xv[2], xv[3]}, bf16x2);
-      const bf16x4 bx = __builtin_bit_cast(
-          bf16x4, (f32x2){__builtin_bit_cast(float, x01), __builtin_bit_cast(float, x23)});
+      const f16x4 bx = __builtin_bit_cast(f16x4, (u32x2){pk_f16(xv[0], xv[1]), pk_f16(xv[2], xv[3])});
       f32x16 acc1[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1[t], bx, b1v[t], 0, 0, 0);
-      bf16x8 hb[4];
+      for (int t = 0; t < 2; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x8f16(a1[t], bx, b1v[t], 0, 0, 0);
+      f16x8 hb[4];
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) hb[sl] = relu_slice(acc1[sl >> 1], 8 * (sl & 1));
       f32x16 acc2[2];
@@ -285,13 +283,13 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
         acc2[t] = b2v[t];
 #pragma unroll
         for (int sl = 0; sl < 4; ++sl)
-          acc2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[t][sl], hb[sl], acc2[t], 0, 0, 0);
+          acc2[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a2[t][sl], hb[sl], acc2[t], 0, 0, 0);
       }
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) hb[sl] = relu_slice(acc2[sl >> 1], 8 * (sl & 1));
       f32x16 acc3 = {};
 #pragma unroll
-      for (int sl = 0; sl < 4; ++sl) acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3[sl], hb[sl], acc3, 0, 0, 0);
+      for (int sl = 0; sl < 4; ++sl) acc3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(a3[sl], hb[sl], acc3, 0, 0, 0);
       zg[grp] = acc3[0];  // every row of the output tile is the logit
     }
     // lane l's own match is in group h

@@ -72,8 +72,8 @@ def test_features_match_oracle():
 
 
 def test_mfma_inference_matches_oracle():
-    """bf16 activations on the matrix cores vs the FP64 network: the weight
-    agrees to 1e-2 (bf16 keeps 8 bits of mantissa)."""
+    """fp16 activations on the matrix cores vs the FP64 network: the weight
+    agrees to 1e-2."""
     sc = synth.config1()
     params = _rand_mlp(2)
     ctx, snaps = _ctx_with_history(sc, params)
@@ -84,11 +84,33 @@ def test_mfma_inference_matches_oracle():
     err = np.abs(w - ref)
     print(f"learned weight vs FP64 network: max |err| {err.max():.3g}, mean {err.mean():.3g}, "
           f"max rel {(err / np.maximum(ref, 1e-3)).max():.3g}", flush=True)
-    # bf16 keeps 8 mantissa bits: ~0.4% per feature, weight and activation,
-    # a few times that on the logit, at most 1/4 of it on the sigmoid; the
-    # weight lies in [0, 1], so the bound is absolute
+    # fp16 keeps 11 significand bits (0.05% per feature, weight and
+    # activation), a few times that on the logit, at most 1/4 of it on the
+    # sigmoid, plus the bf16 storage of the weight (<= 0.004); the weight
+    # lies in [0, 1], so the bound is absolute
     assert err.max() < 1e-2 and err.mean() < 2.5e-3, (err.max(), err.mean())
     assert ref.std() > 0.05  # the network is not constant on these inputs
+
+
+def test_set_mlp_rejects_weights_beyond_fp16():
+    """Inference takes W1, W2 and w3 as fp16: a weight above 65504 would turn
+    infinite there, so the call refuses it; the fp32 biases may be larger."""
+    sc = synth.config1()
+    ctx = make_context(sc, gauge=0, weight_mode=1)
+    try:
+        base = _rand_mlp(7).astype(np.float32)
+        for off in (3, 576 + 100, 4736 + 5):  # one entry of W1, W2, w3
+            p = base.copy()
+            p[off] = 7e4
+            with pytest.raises(fastea.FeaError, match="fp16"):
+                ctx.set_mlp(p)
+        p = base.copy()
+        p[512] = 7e4  # b1
+        p[4800] = -7e4  # b3
+        p[576 + 7] = 65504.0  # the largest finite fp16 is accepted
+        ctx.set_mlp(p)
+    finally:
+        ctx.close()
 
 
 def test_training_gradient_matches_oracle():

@@ -70,3 +70,63 @@ def bench_scene_ref(bench_scene, delta):
         sc, pb, (R, t, f), tau, mask_ref, Z_ref, eps = bench_scene
         _REF["ref"] = oracle.loss_grad(pb, R, t, f, sc.R_init, sc.t_init, sc.f_init, mask_ref, delta=delta)
     return _REF["ref"]
+
+
+def test_bench_workload_quadratic_form_vs_oracle(bench_scene):
+    """The quadratic-form inner loop on the same scene and round (the forms
+    built once per round by one wavefront per 8192-match item): every
+    camera's gradient against the FP64 oracle's per-match sum."""
+    sc, pb, (R, t, f), tau, mask_ref, Z_ref, eps = bench_scene
+    opt = fastea.default_options()
+    ctx = make_context(sc, gauge=0, inner_loop=1)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    ctx.begin_round(opt.tau_px_init)
+    assert ctx.info()["tile_matches"] == 8192
+    ctx.set_poses(R, t, f)
+    loss, gR, gt, gf = ctx.residual_grad()
+    mask, Z = ctx.get_mask()
+    ctx.close()
+    diff = np.flatnonzero(mask != mask_ref)
+    assert np.all(np.abs(eps[diff] - tau) <= 1e-9 * tau), diff[:10]
+    lr, gRr, gtr, gfr = (oracle.loss_grad(pb, R, t, f, sc.R_init, sc.t_init, sc.f_init, mask, delta=opt.delta)
+                         if len(diff) else bench_scene_ref(bench_scene, opt.delta))
+    l = float(loss.item())
+    assert abs(l - lr) <= 1e-5 * abs(lr), (l, lr)
+    for a, b in ((gR.cpu().numpy(), gRr), (gt.cpu().numpy(), gtr), (gf.cpu().numpy()[:, None], gfr[:, None])):
+        ok, worst = per_camera_close(a, b)
+        assert ok, worst
+
+
+def test_bench_workload_learned_weights_vs_oracle(bench_scene):
+    """The shipped inlier network on the 20M-match scene after three round
+    snapshots: the weights of 100,000 sampled matches against the FP64
+    network on the oracle's features.  The bound follows from the
+    arithmetic: fp16 operands (relative rounding 2^-11) in 64-term dot
+    products whose terms reach ~15 for this network put up to ~0.06 on the
+    logit, at most a quarter of it on the sigmoid (0.015), plus the bf16
+    storage of the weight (up to 0.004): 2e-2 absolute."""
+    from paper_2605_18052_amd import learned
+    sc = bench_scene[0]
+    params = learned.load_weights()
+    rng = np.random.default_rng(23)
+    snaps = []
+    for k, deg in enumerate((0.0, 0.5, 1.0)):
+        Rk = synth.rotation_from_axis_angle(rng.normal(size=(sc.n_cams, 3)),
+                                            np.deg2rad(deg) * np.ones(sc.n_cams)) @ sc.R_init
+        snaps.append((Rk, sc.t_init + 0.01 * k, sc.f_init))
+    ctx = make_context(sc, gauge=0, weight_mode=1)
+    ctx.set_mlp(params.astype(np.float32))
+    ctx.init_poses(snaps[0][0], snaps[0][1])
+    ctx.begin_round(math.inf)
+    for Rk, tk, fk in snaps[1:]:
+        ctx.set_poses(Rk, tk, fk)
+        ctx.begin_round(math.inf)
+    w = ctx.learned_weights()
+    ctx.close()
+    sel = np.sort(rng.choice(sc.n_matches, size=100_000, replace=False))
+    feat = oracle.mlp_features(oracle.OracleProblem.from_scene(sc, sel), [snaps[2], snaps[1], snaps[0]])
+    ref = oracle.mlp_forward(feat, params.astype(np.float32).astype(np.float64))
+    err = np.abs(w[sel] - ref)
+    print(f"learned weights at full size: max |err| {err.max():.3g}, mean {err.mean():.3g}", flush=True)
+    assert err.max() < 2e-2 and err.mean() < 2.5e-3, (err.max(), err.mean())
+    assert ref.std() > 0.05
