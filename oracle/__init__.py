@@ -1,4 +1,6 @@
-"""FP64 CPU oracle for FastMap epipolar adjustment (ctypes binding).
+"""FP64 CPU oracle for FastMap epipolar adjustment and the Global
+Translation stages before it (relative-translation search, camera-centre
+alignment with multiple initialisations) (ctypes binding).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
 benchmark's CPU-baseline leg use it to check and time the GPU library.  The
@@ -83,6 +85,16 @@ def lib():
         _lib.orc_mlp_forward.argtypes = [C.c_int64, P, P, P]
         _lib.orc_mlp_bce_grad.argtypes = [C.c_int64, P, P, P, P]
         _lib.orc_mlp_bce_grad.restype = C.c_double
+        _lib.orc_rel_trans.argtypes = [P, P, P, C.c_int32, P, P, P, P, P, P, P]
+        _lib.orc_rel_trans.restype = C.c_int
+        _lib.orc_ta_targets.argtypes = [C.c_int32, C.c_int64, P, P, P, P, P]
+        _lib.orc_ta_targets.restype = C.c_int
+        _lib.orc_ta_loss_grad.argtypes = [C.c_int32, C.c_int64, P, P, P, P, P, P]
+        _lib.orc_ta_loss_grad.restype = C.c_double
+        _lib.orc_ta_default_options.argtypes = [P]
+        _lib.orc_ta_solve.argtypes = [C.c_int32, C.c_int64, P, P, P, C.c_int32, P, P, P, P, P,
+                                      P, P, P]
+        _lib.orc_ta_solve.restype = C.c_int
         _lib.orc_num_threads.restype = C.c_int
         _lib.orc_set_threads.argtypes = [C.c_int]
     return _lib
@@ -333,3 +345,89 @@ def mlp_bce_grad(feat, target, params):
     g = np.zeros(MLP_NPARAM)
     loss = lib().orc_mlp_bce_grad(len(feat), _p(feat), _p(target), _p(params), _p(g))
     return loss, g
+
+
+# ---- Global Translation -----------------------------------------------------
+
+class TaOptions(C.Structure):
+    _fields_ = [("iters_run", C.c_int32), ("iters_final", C.c_int32), ("lr", C.c_double),
+                ("lr_final", C.c_double), ("lr_end_frac", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("adam_eps", C.c_double)]
+
+
+def ta_default_options(**kw) -> TaOptions:
+    o = TaOptions()
+    lib().orc_ta_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def rel_trans(pb: OracleProblem, R, f, cand, scores=False):
+    """Relative-translation candidate search (see orc_rel_trans).  Returns a
+    dict with pair_cams [P,2], best [P], t_rel [P,3], vote [P] and, with
+    scores=True, the mean |eps| of every candidate [P, K]."""
+    _, _, pc, _ = segment(pb.cam1, pb.cam2, pb.n_cams)
+    P = len(pc)
+    cand = _f64(cand).reshape(-1, 3)
+    K = len(cand)
+    R = _f64(R).reshape(-1, 9)
+    f = _f64(f)
+    pair_cams = np.zeros((max(P, 1), 2), np.int32)
+    sc = np.zeros((max(P, 1), K)) if scores else None
+    best = np.zeros(max(P, 1), np.int32)
+    t_rel = np.zeros((max(P, 1), 3))
+    vote = np.zeros(max(P, 1), np.int64)
+    n_pairs = C.c_int64(0)
+    if lib().orc_rel_trans(pb.ref, _p(R), _p(f), K, _p(cand), C.byref(n_pairs), _p(pair_cams),
+                           _p(sc), _p(best), _p(t_rel), _p(vote)):
+        raise ValueError("oracle rel_trans rejected its input")
+    assert n_pairs.value == P
+    out = dict(pair_cams=pair_cams[:P], best=best[:P], t_rel=t_rel[:P], vote=vote[:P])
+    if scores:
+        out["scores"] = sc[:P]
+    return out
+
+
+def ta_targets(n_cams, pair_cams, R, t_rel):
+    pc = np.ascontiguousarray(pair_cams, np.int32).reshape(-1, 2)
+    pi, pj = np.ascontiguousarray(pc[:, 0]), np.ascontiguousarray(pc[:, 1])
+    t_rel = _f64(t_rel).reshape(-1, 3)
+    tg = np.zeros((max(len(pc), 1), 3))
+    if lib().orc_ta_targets(n_cams, len(pc), _p(pi), _p(pj), _p(_f64(R).reshape(-1, 9)),
+                            _p(t_rel), _p(tg)):
+        raise ValueError("oracle ta_targets rejected its input")
+    return tg[:len(pc)]
+
+
+def ta_loss_grad(pair_cams, target, o):
+    pc = np.ascontiguousarray(pair_cams, np.int32).reshape(-1, 2)
+    pi, pj = np.ascontiguousarray(pc[:, 0]), np.ascontiguousarray(pc[:, 1])
+    o = _f64(o).reshape(-1, 3)
+    g = np.zeros_like(o)
+    pl = np.zeros(max(len(pc), 1))
+    L = lib().orc_ta_loss_grad(len(o), len(pc), _p(pi), _p(pj), _p(_f64(target).reshape(-1, 3)),
+                               _p(o), _p(g), _p(pl))
+    return L, g, pl[:len(pc)]
+
+
+def ta_solve(pair_cams, target, o_init, options=None):
+    """Multiple-initialisation translation alignment (see orc_ta_solve).
+    o_init [runs, N, 3]."""
+    pc = np.ascontiguousarray(pair_cams, np.int32).reshape(-1, 2)
+    pi, pj = np.ascontiguousarray(pc[:, 0]), np.ascontiguousarray(pc[:, 1])
+    o_init = _f64(o_init)
+    runs, N = o_init.shape[0], o_init.shape[1]
+    opt = options if options is not None else ta_default_options()
+    o = np.zeros((N, 3))
+    run_o = np.zeros((runs, N, 3))
+    cam_loss = np.zeros((runs, N))
+    run_of_cam = np.zeros(N, np.int32)
+    run_loss = np.zeros(runs)
+    final = C.c_double(0.0)
+    if lib().orc_ta_solve(N, len(pc), _p(pi), _p(pj), _p(_f64(target).reshape(-1, 3)), runs,
+                          _p(o_init), C.byref(opt), _p(o), _p(run_o), _p(cam_loss),
+                          _p(run_of_cam), _p(run_loss), C.byref(final)):
+        raise ValueError("oracle ta_solve failed")
+    return dict(o=o, run_o=run_o, cam_loss=cam_loss, run_of_cam=run_of_cam, run_loss=run_loss,
+                final_loss=final.value)

@@ -815,3 +815,243 @@ double orc_mlp_bce_grad(int64_t n, const double *feat, const double *target, con
   }
   return loss / (double)(n > 0 ? n : 1);
 }
+
+/* ---- relative translations (Global Translation > Relative translation) --- */
+
+/* Depth signs of the two-view triangulation of one match for a relative
+ * translation t (camera j frame): the depths (l1, l2) minimising
+ * |l1 a - l2 b + t|^2 with a = R_ij x~1, b = x~2 solve the 2x2 normal
+ * equations [a.a, -a.b; -a.b, b.b] (l1, l2) = (-a.t, b.t).  Returns +1 when
+ * both depths are positive, -1 when both are negative, 0 otherwise (also
+ * when the rays are parallel and the depths undefined). */
+static int cheirality_vote(const double a[3], const double b[3], const double t[3]) {
+  const double aa = dot3(a, a), bb = dot3(b, b), ab = dot3(a, b);
+  const double at = dot3(a, t), bt = dot3(b, t);
+  const double det = aa * bb - ab * ab;
+  if (!(det > 0.0)) return 0;
+  const double l1 = (-at * bb + ab * bt) / det;
+  const double l2 = (aa * bt - ab * at) / det;
+  if (l1 > 0.0 && l2 > 0.0) return 1;
+  if (l1 < 0.0 && l2 < 0.0) return -1;
+  return 0;
+}
+
+int orc_rel_trans(const orc_problem *pb, const double *R, const double *f, int32_t n_cand,
+                  const double *cand, int64_t *n_pairs_out, int32_t *pair_cams, double *scores,
+                  int32_t *best, double *t_rel, int64_t *vote) {
+  if (check_problem(pb) || n_cand < 1) return -1;
+  seg_result s;
+  if (segment_problem(pb, &s)) {
+    free_segments(&s);
+    return -1;
+  }
+  const int64_t P = s.n_pairs;
+  *n_pairs_out = P;
+  int rc = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t n = 0; n < P; ++n) {
+    const int32_t i = s.pair_cams[2 * n], j = s.pair_cams[2 * n + 1];
+    pair_cams[2 * n] = i;
+    pair_cams[2 * n + 1] = j;
+    double Rij[9];
+    mat_mul_bt(R + 9 * j, R + 9 * i, Rij);
+    const int64_t b0 = s.seg_off[n], b1 = s.seg_off[n + 1];
+    double best_score = 0.0;
+    int32_t best_k = -1;
+    for (int32_t k = 0; k < n_cand; ++k) {
+      /* E = [u]x R_ij for the candidate direction u; eps = x~2^T E x~1 */
+      double S[9], E[9];
+      skew(cand + 3 * k, S);
+      mat_mul(S, Rij, E);
+      double sum = 0.0;
+      for (int64_t p = b0; p < b1; ++p) {
+        int32_t ci, cj;
+        double ax, ay, bx, by;
+        canonical_match(pb, s.perm[p], &ci, &cj, &ax, &ay, &bx, &by);
+        const double x1[3] = {ax / f[i], ay / f[i], 1.0}, x2[3] = {bx / f[j], by / f[j], 1.0};
+        double Ex1[3];
+        mat_vec(E, x1, Ex1);
+        sum += fabs(dot3(x2, Ex1));
+      }
+      const double mean = sum / (double)(b1 - b0);
+      if (scores) scores[n * n_cand + k] = mean;
+      if (best_k < 0 || mean < best_score) {
+        best_score = mean;
+        best_k = k;
+      }
+    }
+    best[n] = best_k;
+    const double *u = cand + 3 * best_k;
+    int64_t v = 0;
+    for (int64_t p = b0; p < b1; ++p) {
+      int32_t ci, cj;
+      double ax, ay, bx, by;
+      canonical_match(pb, s.perm[p], &ci, &cj, &ax, &ay, &bx, &by);
+      const double x1[3] = {ax / f[i], ay / f[i], 1.0}, x2[3] = {bx / f[j], by / f[j], 1.0};
+      double a[3];
+      mat_vec(Rij, x1, a);
+      v += cheirality_vote(a, x2, u);
+    }
+    vote[n] = v;
+    const double sg = v >= 0 ? 1.0 : -1.0;
+    for (int k = 0; k < 3; ++k) t_rel[3 * n + k] = sg * u[k];
+  }
+  free_segments(&s);
+  return rc;
+}
+
+/* ---- global translation alignment (Global Translation) ------------------ */
+
+int orc_ta_targets(int32_t n_cams, int64_t n_pairs, const int32_t *pair_i,
+                   const int32_t *pair_j, const double *R, const double *t_rel, double *target) {
+  for (int64_t p = 0; p < n_pairs; ++p) {
+    const int32_t i = pair_i[p], j = pair_j[p];
+    if (i < 0 || j < 0 || i >= n_cams || j >= n_cams || i == j) return -1;
+    const double nt = sqrt(dot3(t_rel + 3 * p, t_rel + 3 * p));
+    if (!(nt > 0.0)) return -2;
+    double u[3] = {t_rel[3 * p] / nt, t_rel[3 * p + 1] / nt, t_rel[3 * p + 2] / nt}, o[3];
+    mat_t_vec(R + 9 * j, u, o); /* R_j^T u */
+    for (int k = 0; k < 3; ++k) target[3 * p + k] = -o[k];
+  }
+  return 0;
+}
+
+static double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+double orc_ta_loss_grad(int32_t n_cams, int64_t n_pairs, const int32_t *pair_i,
+                        const int32_t *pair_j, const double *target, const double *o,
+                        double *grad, double *pair_loss) {
+  if (grad)
+    for (int64_t k = 0; k < 3 * (int64_t)n_cams; ++k) grad[k] = 0.0;
+  double L = 0.0;
+  for (int64_t p = 0; p < n_pairs; ++p) {
+    const int32_t i = pair_i[p], j = pair_j[p];
+    double d[3];
+    for (int k = 0; k < 3; ++k) d[k] = o[3 * j + k] - o[3 * i + k];
+    const double nd = sqrt(dot3(d, d));
+    double lp = 0.0;
+    if (nd > 0.0) {
+      double n[3], r[3], s[3];
+      for (int k = 0; k < 3; ++k) {
+        n[k] = d[k] / nd;
+        r[k] = n[k] - target[3 * p + k];
+        lp += fabs(r[k]);
+        s[k] = sgn(r[k]) / (double)n_pairs; /* dL/dn */
+      }
+      if (grad) {
+        /* n = d/|d|: dn/dd = (I - n n^T)/|d| */
+        const double ns = dot3(n, s);
+        for (int k = 0; k < 3; ++k) {
+          const double gd = (s[k] - n[k] * ns) / nd;
+          grad[3 * j + k] += gd;
+          grad[3 * i + k] -= gd;
+        }
+      }
+    }
+    if (pair_loss) pair_loss[p] = lp;
+    L += lp;
+  }
+  return n_pairs > 0 ? L / (double)n_pairs : 0.0;
+}
+
+/* Centre at the origin and rescale to unit mean norm (the alignment of the
+ * multiple-initialisation merge). */
+static int ta_align(int32_t N, double *o) {
+  double c[3] = {0, 0, 0};
+  for (int32_t i = 0; i < N; ++i)
+    for (int k = 0; k < 3; ++k) c[k] += o[3 * i + k];
+  for (int k = 0; k < 3; ++k) c[k] /= (double)N;
+  double s = 0.0;
+  for (int32_t i = 0; i < N; ++i) {
+    double d[3] = {o[3 * i] - c[0], o[3 * i + 1] - c[1], o[3 * i + 2] - c[2]};
+    s += sqrt(dot3(d, d));
+  }
+  s /= (double)N;
+  if (!(s > 0.0)) return -1;
+  for (int32_t i = 0; i < N; ++i)
+    for (int k = 0; k < 3; ++k) o[3 * i + k] = (o[3 * i + k] - c[k]) / s;
+  return 0;
+}
+
+/* Adam on the camera centres: iters steps, learning rate decayed
+ * geometrically from lr to lr * end_frac over the run (step k uses
+ * lr * end_frac^(k / iters)). */
+static void ta_adam_run(int32_t N, int64_t P, const int32_t *pi, const int32_t *pj,
+                        const double *target, double *o, int32_t iters, double lr,
+                        const orc_ta_options *opt) {
+  const size_t n3 = 3 * (size_t)N;
+  double *g = (double *)calloc(n3, sizeof(double));
+  double *m = (double *)calloc(n3, sizeof(double));
+  double *v = (double *)calloc(n3, sizeof(double));
+  for (int32_t k = 0; k < iters; ++k) {
+    orc_ta_loss_grad(N, P, pi, pj, target, o, g, NULL);
+    const double lr_k = lr * pow(opt->lr_end_frac, (double)k / (double)iters);
+    orc_adam((int64_t)n3, o, m, v, g, k + 1, lr_k, opt->beta1, opt->beta2, opt->adam_eps);
+  }
+  free(g);
+  free(m);
+  free(v);
+}
+
+void orc_ta_default_options(orc_ta_options *o) {
+  o->iters_run = 1500;
+  o->iters_final = 500;
+  o->lr = 2e-2;
+  o->lr_final = 2e-3;
+  o->lr_end_frac = 1e-3;
+  o->beta1 = 0.9;
+  o->beta2 = 0.999;
+  o->adam_eps = 1e-12;
+}
+
+int orc_ta_solve(int32_t N, int64_t P, const int32_t *pi, const int32_t *pj, const double *target,
+                 int32_t n_runs, const double *o_init, const orc_ta_options *opt, double *o_out,
+                 double *run_o, double *cam_loss, int32_t *run_of_cam, double *run_loss,
+                 double *final_loss) {
+  if (N < 1 || n_runs < 1) return -1;
+  const size_t n3 = 3 * (size_t)N;
+  double *ro = (double *)malloc(sizeof(double) * n3 * (size_t)n_runs);
+  double *cl = (double *)calloc((size_t)N * (size_t)n_runs, sizeof(double));
+  double *pl = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
+  int32_t *deg = (int32_t *)calloc((size_t)N, sizeof(int32_t));
+  int rc = 0;
+  for (int64_t p = 0; p < P; ++p) {
+    deg[pi[p]]++;
+    deg[pj[p]]++;
+  }
+  for (int32_t r = 0; r < n_runs && !rc; ++r) {
+    double *o = ro + n3 * (size_t)r;
+    memcpy(o, o_init + n3 * (size_t)r, sizeof(double) * n3);
+    ta_adam_run(N, P, pi, pj, target, o, opt->iters_run, opt->lr, opt);
+    if (ta_align(N, o)) rc = -2;
+    const double L = orc_ta_loss_grad(N, P, pi, pj, target, o, NULL, pl);
+    if (run_loss) run_loss[r] = L;
+    /* mean loss of each camera over its pairs */
+    double *c = cl + (size_t)N * (size_t)r;
+    for (int64_t p = 0; p < P; ++p) {
+      c[pi[p]] += pl[p];
+      c[pj[p]] += pl[p];
+    }
+    for (int32_t i = 0; i < N; ++i) c[i] = deg[i] ? c[i] / (double)deg[i] : 0.0;
+  }
+  if (!rc) {
+    for (int32_t i = 0; i < N; ++i) {
+      int32_t b = 0;
+      for (int32_t r = 1; r < n_runs; ++r)
+        if (cl[(size_t)N * r + i] < cl[(size_t)N * b + i]) b = r;
+      run_of_cam[i] = b;
+      for (int k = 0; k < 3; ++k) o_out[3 * i + k] = ro[n3 * (size_t)b + 3 * i + k];
+    }
+    ta_adam_run(N, P, pi, pj, target, o_out, opt->iters_final, opt->lr_final, opt);
+    if (ta_align(N, o_out)) rc = -2;
+    const double L = orc_ta_loss_grad(N, P, pi, pj, target, o_out, NULL, NULL);
+    if (final_loss) *final_loss = L;
+  }
+  if (run_o) memcpy(run_o, ro, sizeof(double) * n3 * (size_t)n_runs);
+  if (cam_loss) memcpy(cam_loss, cl, sizeof(double) * (size_t)N * (size_t)n_runs);
+  free(ro);
+  free(cl);
+  free(pl);
+  free(deg);
+  return rc;
+}

@@ -178,6 +178,60 @@ void orc_mlp_forward(int64_t n, const double *feat, const double *params, double
 double orc_mlp_bce_grad(int64_t n, const double *feat, const double *target, const double *params,
                         double *grad);
 
+/* ---- Global Translation: relative translations ---------------------------
+ * Method > Global Translation > Relative translation: with the global
+ * rotations fixed, each pair's unit relative translation is re-estimated by
+ * scoring candidate directions on the unit sphere by their mean epipolar
+ * error and keeping the best.  For every canonical pair (i < j, in the
+ * lexicographic order of orc_segment) and candidate u (cand[3k..3k+2]):
+ *   score(u) = mean over the pair's matches of |x~2^T [u]x R_ij x~1|,
+ * x~ = ((x - cx)/f, (y - cy)/f, 1), R_ij = R_j R_i^T (the EA residual with the
+ * relative translation set to u).  best = the lowest score (ties: the lower
+ * index).  The score does not change under u -> -u, so the sign is taken by
+ * cheirality (reading; the paper does not say): every match votes +1 when
+ * both depths of its two-view triangulation with t_ij = u are positive, -1
+ * when both are negative, 0 otherwise; t_rel = u if the vote sum is >= 0,
+ * else -u.  Outputs, caller-allocated for P pairs (P <= n_matches):
+ * pair_cams [2P], scores [P * n_cand] (nullable), best [P], t_rel [3P],
+ * vote [P].  Returns 0, or -1 for invalid matches or n_cand < 1. */
+int orc_rel_trans(const orc_problem *pb, const double *R, const double *f, int32_t n_cand,
+                  const double *cand, int64_t *n_pairs, int32_t *pair_cams, double *scores,
+                  int32_t *best, double *t_rel, int64_t *vote);
+
+/* ---- Global Translation: camera centres ------------------------------------
+ * Eq. fastmap-global-translation-objective and the text around it: targets
+ * o^{i->j} = -R_j^T t^{i->j} (t^{i->j} normalised to unit length); the loss
+ *   L_t = (1/|P|) sum_{(i,j)} | (o_j - o_i)/|o_j - o_i| - o^{i->j} |_1
+ * over the camera centres o; its gradient uses sign(0) = 0 and a pair whose
+ * two centres coincide contributes nothing. */
+int orc_ta_targets(int32_t n_cams, int64_t n_pairs, const int32_t *pair_i,
+                   const int32_t *pair_j, const double *R, const double *t_rel, double *target);
+double orc_ta_loss_grad(int32_t n_cams, int64_t n_pairs, const int32_t *pair_i,
+                        const int32_t *pair_j, const double *target, const double *o,
+                        double *grad, double *pair_loss);
+
+/* Multiple initialisations and merge (Global Translation > Multiple
+ * initializations): each run optimises the centres from its own initial
+ * values with Adam (readings: Adam with bias correction; the learning rate of
+ * step k of a run of T steps is lr * lr_end_frac^(k/T)); each run's result is
+ * centred at the origin and rescaled to unit mean norm; every camera takes its
+ * centre from the run with the lowest mean loss over that camera's pairs
+ * (ties: the lower run; a camera without pairs scores 0); the merged centres
+ * are optimised iters_final more steps from lr_final and aligned again.
+ * o_init [n_runs * N * 3]; outputs o_out [N*3], run_o [n_runs*N*3] (aligned
+ * run results, nullable), cam_loss [n_runs*N] (nullable), run_of_cam [N],
+ * run_loss [n_runs] (nullable), final_loss (nullable). */
+typedef struct {
+  int32_t iters_run, iters_final;
+  double lr, lr_final, lr_end_frac;
+  double beta1, beta2, adam_eps;
+} orc_ta_options;
+void orc_ta_default_options(orc_ta_options *o);
+int orc_ta_solve(int32_t n_cams, int64_t n_pairs, const int32_t *pair_i, const int32_t *pair_j,
+                 const double *target, int32_t n_runs, const double *o_init,
+                 const orc_ta_options *opt, double *o_out, double *run_o, double *cam_loss,
+                 int32_t *run_of_cam, double *run_loss, double *final_loss);
+
 /* Number of OpenMP threads the oracle would use (1 without OpenMP). */
 int orc_num_threads(void);
 void orc_set_threads(int n);

@@ -255,9 +255,11 @@ def _detect(seed, R, t, f, cx, cy, width, height, X, p_det, sigma):
 def sphere_scene(n_cams=20, n_pts=2000, radius=4.0, focal=500.0, width=640.0,
                  height=480.0, p_det=0.4, sigma=0.5, outlier_frac=0.1, seed=1,
                  extent=1.0, rot_sigma_deg=3.0, rot_min_deg=2.0, center_frac=0.05,
-                 name="sphere") -> Scene:
+                 name="sphere", pair_angle_deg=None) -> Scene:
     """Cameras at seeded uniform directions on a sphere, looking at the origin,
-    points uniform in a cube of side `extent`, all camera pairs matched."""
+    points uniform in a cube of side `extent`; all camera pairs matched, or
+    with pair_angle_deg only the pairs whose viewing directions are less than
+    that angle apart (an object-centric capture's pair graph)."""
     rng = np.random.default_rng(seed)
     dirs = rng.normal(size=(n_cams, 3))
     dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
@@ -269,7 +271,11 @@ def sphere_scene(n_cams=20, n_pts=2000, radius=4.0, focal=500.0, width=640.0,
     W = np.full(n_cams, float(width))
     H = np.full(n_cams, float(height))
     det = _detect(seed, R, t, f, W / 2, H / 2, W, H, X, p_det, sigma)
-    pair_list = [(i, j) for i in range(n_cams) for j in range(i + 1, n_cams)]
+    if pair_angle_deg is None:
+        pair_list = [(i, j) for i in range(n_cams) for j in range(i + 1, n_cams)]
+    else:
+        ii, jj = np.nonzero(np.triu(dirs @ dirs.T > np.cos(np.deg2rad(pair_angle_deg)), 1))
+        pair_list = list(zip(ii.tolist(), jj.tolist()))
     x1, y1, x2, y2, c1, c2, inl = _emit_matches(seed, pair_list, *det, n_cams, W, H,
                                                 outlier_frac, rng)
     R0, t0 = _perturb_init(rng, R, t, rot_sigma_deg, rot_min_deg, center_frac,
@@ -425,3 +431,30 @@ def concat_scenes(scenes: list):
                R_gt=cat("R_gt"))
     cam_scene = np.concatenate([np.full(s.n_cams, k, np.int32) for k, s in enumerate(scenes)])
     return out, cam_scene, offs
+
+
+def sphere_candidates(n: int) -> np.ndarray:
+    """n unit directions spread evenly over the upper hemisphere (z > 0): a
+    Fibonacci lattice, z_k = 1 - (k + 1/2)/n, azimuth k times the golden
+    angle.  Candidate relative-translation directions; a direction and its
+    opposite score the same, so one hemisphere suffices.  float64 [n, 3]."""
+    k = np.arange(n, dtype=np.float64)
+    z = 1.0 - (k + 0.5) / n
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = k * np.pi * (3.0 - np.sqrt(5.0))
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
+
+
+def random_centres(seed: int, n_runs: int, n_cams: int) -> np.ndarray:
+    """Independent random initial camera centres for translation alignment:
+    standard normal per coordinate, float64 [n_runs, n_cams, 3]."""
+    return np.random.default_rng(seed).normal(size=(n_runs, n_cams, 3))
+
+
+def relative_translations_gt(sc: "Scene", pair_cams: np.ndarray) -> np.ndarray:
+    """Ground-truth unit relative translations t^{i->j} (camera j frame) of the
+    given pairs, from the scene's true poses.  float64 [P, 3]."""
+    i, j = pair_cams[:, 0], pair_cams[:, 1]
+    Rij = np.einsum("pab,pcb->pac", sc.R_gt[j], sc.R_gt[i])
+    t = sc.t_gt[j] - np.einsum("pab,pb->pa", Rij, sc.t_gt[i])
+    return t / np.linalg.norm(t, axis=1, keepdims=True)
