@@ -395,6 +395,75 @@ fea_status fea_get_kernel_times(fea_ctx *ctx, float *ms, int64_t cap, int64_t *n
  * (k+1)*log_every, counting steps across rounds. */
 fea_status fea_get_rotation_log(fea_ctx *ctx, double *R_log, int32_t *n_logged);
 
+/* ---- Global Translation (the stages before epipolar adjustment) ---------
+ * Relative translations (Method > Global Translation > Relative
+ * translation): with the global rotations fixed, every image pair of the
+ * loaded matches gets a unit relative translation chosen among candidate
+ * directions by its mean epipolar error.  For pair n = (i, j) (the pair order
+ * of fea_get_segments) and candidate u:
+ *   score(u) = mean over the pair's matches of |x~2^T [u]x R_ij x~1|,
+ * x~ = ((x - cx)/f, (y - cy)/f, 1), R_ij = R_j R_i^T: the epipolar-adjustment
+ * residual with the relative translation set to u.  The lowest score wins
+ * (ties: the lower candidate index).  A direction and its opposite score the
+ * same, so the sign is decided by cheirality: each match votes +1 when both
+ * depths of its least-squares two-view triangulation with translation u are
+ * positive, -1 when both are negative, 0 otherwise; the result is u for a
+ * vote sum >= 0, else -u.  Scores are fp32 on the matrix cores; the vote is
+ * fp64.  Inputs (host, copied): R [n_cams*9] world-to-camera rotations,
+ * f [n_cams] focal lengths (NULL = the loaded intrinsics), cand [n_cand*3]
+ * unit vectors (one hemisphere suffices).  Outputs (host, caller-allocated,
+ * n_pairs = fea_get_info's n_pairs): t_rel [n_pairs*3], best [n_pairs]
+ * (nullable), vote [n_pairs] (nullable), score_best [n_pairs] (nullable),
+ * scores [n_pairs*n_cand] (nullable: every candidate's mean score),
+ * score_ms (nullable: duration of the scoring kernel, HIP events).
+ * Requires loaded matches (FEA_ESTATE otherwise); FEA_EINVAL for
+ * n_cand outside [1, 2^22], candidates that are not unit vectors (1e-6) or
+ * focal lengths <= 0; FEA_ENONFINITE for non-finite input.  Device scratch
+ * (n_cand rounded up to 1024, times the number of 2048-match work items, in
+ * fp32) is allocated and freed by the call. */
+fea_status fea_relative_translations(fea_ctx *ctx, const double *R, const double *f, int32_t n_cand,
+                                     const double *cand, double *t_rel, int32_t *best, int32_t *vote,
+                                     double *score_best, float *scores, float *score_ms);
+
+/* Camera centres (Eq. fastmap-global-translation-objective, Multiple
+ * initializations): targets o^{i->j} = -R_j^T t^{i->j} / |t^{i->j}|; the loss
+ *   L_t = (1/|P|) sum over pairs of | (o_j - o_i)/|o_j - o_i| - o^{i->j} |_1
+ * over the centres o is minimised with Adam (bias-corrected; the learning
+ * rate of step k of a phase of T steps is lr * lr_end_frac^(k/T); sign(0) = 0;
+ * a pair whose two centres coincide contributes nothing), n_runs times side by
+ * side from the caller's initial centres o_init [n_runs*n_cams*3] (the random
+ * numbers of the method are inputs).  Each run's result is centred at the
+ * origin and scaled to unit mean norm; each camera then takes its centre from
+ * the run with the lowest mean loss over that camera's pairs (ties: the lower
+ * run; a camera without pairs scores 0); the merged centres are optimised
+ * iters_final more steps from lr_final and aligned again.  Pairs are given
+ * explicitly (pair_i, pair_j [n_pairs], cameras in [0, n_cams), i != j;
+ * t_rel [n_pairs*3] in camera j's frame, any non-zero length; R
+ * [n_cams*9]); the context only supplies device, stream and error message
+ * (no intrinsics or matches needed).  Outputs (host): o_out [n_cams*3]
+ * (aligned), run_of_cam [n_cams], run_loss [n_runs], final_loss, run_o
+ * [n_runs*n_cams*3] (aligned run results), cam_loss [n_runs*n_cams], ms
+ * (device time of the whole call, HIP events); all but o_out nullable.
+ * FEA_EINVAL for invalid sizes, pairs or options (n_runs in [1, 64]),
+ * FEA_ENONFINITE for non-finite input, FEA_EDEGENERATE for a zero relative
+ * translation or a run whose centres all coincide.  Device scratch of
+ * O(n_runs * (n_cams + n_pairs)) is allocated and freed by the call. */
+typedef struct {
+  int32_t iters_run;   /* Adam steps of every run (default 1500) */
+  int32_t iters_final; /* Adam steps on the merged centres (500) */
+  double lr;           /* first learning rate of a run (2e-2) */
+  double lr_final;     /* first learning rate of the final loop (2e-3) */
+  double lr_end_frac;  /* learning rate at the end of a phase / at its start (1e-3) */
+  double beta1, beta2, adam_eps; /* 0.9, 0.999, 1e-12 */
+} fea_ta_options;
+
+fea_status fea_ta_default_options(fea_ta_options *out);
+fea_status fea_translation_align(fea_ctx *ctx, int32_t n_cams, int64_t n_pairs, const int32_t *pair_i,
+                                 const int32_t *pair_j, const double *R, const double *t_rel, int32_t n_runs,
+                                 const double *o_init, const fea_ta_options *opt, double *o_out,
+                                 int32_t *run_of_cam, double *run_loss, double *final_loss, double *run_o,
+                                 double *cam_loss, float *ms);
+
 #ifdef __cplusplus
 }
 #endif

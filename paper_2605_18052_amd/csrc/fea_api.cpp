@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "fea_ctx.h"
+#include "fea_trans.h"
 
 using fea::DBuf;
 
@@ -1916,6 +1917,338 @@ fea_status fea_get_rotation_log(fea_ctx* c, double* R_log, int32_t* n_logged) {
   HIP_OR_FAIL(c, hipMemcpyAsync(R_log, c->logR.p, sizeof(double) * 9 * c->N * c->n_logged,
                                 hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return FEA_OK;
+}
+
+}  // extern "C"
+
+// ---- Global Translation ---------------------------------------------------------
+
+namespace {
+
+// Device memory owned by one call: freed (after the stream has drained) when
+// the call returns, on every path.
+struct CallScratch {
+  hipStream_t st;
+  std::vector<void*> ptrs;
+  explicit CallScratch(hipStream_t s) : st(s) {}
+  ~CallScratch() {
+    (void)hipStreamSynchronize(st);
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  hipError_t alloc(T*& p, size_t n) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(n * sizeof(T), 16));
+    if (e == hipSuccess) {
+      ptrs.push_back(q);
+      p = static_cast<T*>(q);
+    }
+    return e;
+  }
+  template <class T>
+  hipError_t put(T*& p, const T* src, size_t n) {
+    hipError_t e = alloc(p, n);
+    if (e != hipSuccess || n == 0) return e;
+    return hipMemcpyAsync(p, src, n * sizeof(T), hipMemcpyHostToDevice, st);
+  }
+};
+
+template <class T>
+hipError_t fetch(hipStream_t st, T* dst, const T* src, size_t n) {
+  if (!dst || n == 0) return hipSuccess;
+  return hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, st);
+}
+
+bool all_finite(const double* a, size_t n) {
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(a[k])) return false;
+  return true;
+}
+
+// Camera -> (2 * pair + side) entries in pair order; side 1 = the pair's
+// second camera.
+void camera_entries(int32_t n_cams, int64_t n_pairs, const int32_t* pi, const int32_t* pj,
+                    std::vector<int32_t>& off, std::vector<int32_t>& ent) {
+  off.assign((size_t)n_cams + 1, 0);
+  for (int64_t p = 0; p < n_pairs; ++p) {
+    off[pi[p] + 1]++;
+    off[pj[p] + 1]++;
+  }
+  for (int32_t i = 0; i < n_cams; ++i) off[i + 1] += off[i];
+  ent.assign((size_t)2 * n_pairs, 0);
+  std::vector<int32_t> fill(off.begin(), off.end() - 1);
+  for (int64_t p = 0; p < n_pairs; ++p) {
+    ent[fill[pi[p]]++] = (int32_t)(2 * p);
+    ent[fill[pj[p]]++] = (int32_t)(2 * p + 1);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+fea_status fea_relative_translations(fea_ctx* c, const double* R, const double* f, int32_t n_cand,
+                                     const double* cand, double* t_rel, int32_t* best, int32_t* vote,
+                                     double* score_best, float* scores, float* score_ms) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_matches) return fail(c, FEA_ESTATE, "load matches first");
+  if (!R || !cand || !t_rel) return fail(c, FEA_EINVAL, "R, cand and t_rel are required");
+  if (n_cand < 1 || n_cand > (1 << 22)) return fail(c, FEA_EINVAL, "n_cand must be in [1, 2^22]");
+  const int32_t N = c->N;
+  if (!all_finite(R, (size_t)9 * N)) return fail(c, FEA_ENONFINITE, "non-finite rotation");
+  std::vector<double> fv(f ? f : c->f_in.data(), (f ? f : c->f_in.data()) + N);
+  for (double x : fv)
+    if (!std::isfinite(x) || !(x > 0.0)) return fail(c, FEA_EINVAL, "focal lengths must be finite and > 0");
+  for (int32_t k = 0; k < n_cand; ++k) {
+    const double* u = cand + 3 * (size_t)k;
+    if (!all_finite(u, 3)) return fail(c, FEA_ENONFINITE, "non-finite candidate");
+    if (std::fabs(std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - 1.0) > 1e-6)
+      return fail(c, FEA_EINVAL, "candidates must be unit vectors");
+  }
+  const int64_t P = c->P;
+  if (P == 0) return FEA_OK;
+  // work items over the full layout (each pair's run aligned as when loaded)
+  std::vector<int4> items;
+  std::vector<int32_t> pio((size_t)P + 1);
+  int64_t off = 0;
+  for (int64_t n = 0; n < P; ++n) {
+    const int64_t cnt = c->seg_off[n + 1] - c->seg_off[n];
+    pio[n] = (int32_t)items.size();
+    for (int64_t s = 0; s < cnt; s += fea::kRtItem) {
+      if (off + s > INT32_MAX) return fail(c, FEA_EINVAL, "layout too large for the candidate search");
+      items.push_back(make_int4((int)n, (int)(off + s), (int)std::min<int64_t>(fea::kRtItem, cnt - s), 0));
+    }
+    off += (cnt + fea::kAlign - 1) / fea::kAlign * fea::kAlign;
+  }
+  pio[P] = (int32_t)items.size();
+  const int64_t n_items = (int64_t)items.size();
+  const int groups = (n_cand + fea::kRtGroup - 1) / fea::kRtGroup;
+  const int kp = groups * fea::kRtGroup;
+  std::vector<float> cs((size_t)3 * kp, 0.f);  // structure of arrays, zero-padded
+  for (int32_t k = 0; k < n_cand; ++k)
+    for (int a = 0; a < 3; ++a) cs[(size_t)a * kp + k] = (float)cand[3 * (size_t)k + a];
+
+  DeviceGuard g(c->device);
+  CallScratch sc(c->stream);
+  double *dR, *df, *rowd, *dt, *dsb;
+  float *dcand, *rowf, *part, *dscores = nullptr;
+  int4* ditems;
+  int32_t *dpio, *dbest, *dvote;
+  HIP_OR_FAIL(c, sc.put(dR, R, (size_t)9 * N));
+  HIP_OR_FAIL(c, sc.put(df, fv.data(), (size_t)N));
+  HIP_OR_FAIL(c, sc.put(dcand, cs.data(), cs.size()));
+  HIP_OR_FAIL(c, sc.put(ditems, items.data(), items.size()));
+  HIP_OR_FAIL(c, sc.put(dpio, pio.data(), pio.size()));
+  HIP_OR_FAIL(c, sc.alloc(rowf, (size_t)fea::kRtRow * P));
+  HIP_OR_FAIL(c, sc.alloc(rowd, (size_t)fea::kRtRow * P));
+  HIP_OR_FAIL(c, sc.alloc(part, (size_t)n_items * kp));
+  HIP_OR_FAIL(c, sc.alloc(dbest, (size_t)P));
+  HIP_OR_FAIL(c, sc.alloc(dvote, (size_t)P));
+  HIP_OR_FAIL(c, sc.alloc(dt, (size_t)3 * P));
+  HIP_OR_FAIL(c, sc.alloc(dsb, (size_t)P));
+  if (scores) HIP_OR_FAIL(c, sc.alloc(dscores, (size_t)P * n_cand));
+  const float *x1 = c->lay[0][0].as<float>(), *y1 = c->lay[0][1].as<float>(), *x2 = c->lay[0][2].as<float>(),
+              *y2 = c->lay[0][3].as<float>();
+  HIP_OR_FAIL(c, fea::launch_rt_pairs(c->stream, P, c->d_pair_i.as<int32_t>(), c->d_pair_j.as<int32_t>(), dR, df,
+                                      c->d_cx.as<double>(), c->d_cy.as<double>(), rowf, rowd));
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (score_ms) {
+    HIP_OR_FAIL(c, hipEventCreate(&ev[0]));
+    HIP_OR_FAIL(c, hipEventCreate(&ev[1]));
+  }
+  hipError_t e = fea::launch_rt_score(c->stream, n_items, groups, ditems, rowf, x1, y1, x2, y2, dcand, kp, part,
+                                      ev[0], ev[1]);
+  if (e == hipSuccess)
+    e = fea::launch_rt_select(c->stream, P, n_cand, kp, dpio, ditems, part, dcand, rowd, x1, y1, x2, y2, dscores,
+                              dbest, dvote, dt, dsb);
+  if (e == hipSuccess) e = fetch(c->stream, t_rel, dt, (size_t)3 * P);
+  if (e == hipSuccess) e = fetch(c->stream, best, dbest, (size_t)P);
+  if (e == hipSuccess) e = fetch(c->stream, vote, dvote, (size_t)P);
+  if (e == hipSuccess) e = fetch(c->stream, score_best, dsb, (size_t)P);
+  if (e == hipSuccess) e = fetch(c->stream, scores, dscores, (size_t)P * n_cand);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && score_ms) e = hipEventElapsedTime(score_ms, ev[0], ev[1]);
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  HIP_OR_FAIL(c, e);
+  return FEA_OK;
+}
+
+fea_status fea_ta_default_options(fea_ta_options* o) {
+  if (!o) return FEA_EINVAL;
+  o->iters_run = 1500;
+  o->iters_final = 500;
+  o->lr = 2e-2;
+  o->lr_final = 2e-3;
+  o->lr_end_frac = 1e-3;
+  o->beta1 = 0.9;
+  o->beta2 = 0.999;
+  o->adam_eps = 1e-12;
+  return FEA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Steps of one alignment phase: a captured graph of an even number of steps
+// (the parity, and so the buffer roles, are the same at its end as at its
+// start) replayed, then the remainder launched directly.
+struct TaPhase {
+  fea_ctx* c;
+  int runs, N;
+  int64_t P;
+  const int32_t *off, *ent, *pi, *pj;
+  const double* tg;
+  double* o[2];
+  double *m, *v;
+  fea::TaCounters* ctr;
+  double b1, b2, eps, decay;
+  int parity = 0;
+
+  hipError_t step() {
+    hipError_t e = fea::launch_ta_step(c->stream, runs, N, P, off, ent, pi, pj, tg, o[parity], o[parity ^ 1], m, v,
+                                       ctr, parity, b1, b2, eps, decay);
+    parity ^= 1;
+    return e;
+  }
+  hipError_t run(int iters) {
+    constexpr int kChunk = 64;
+    int done = 0;
+    if (iters >= 2 * kChunk) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t x = nullptr;
+      hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return e;
+      hipError_t le = hipSuccess;
+      const int p0 = parity;
+      for (int k = 0; k < kChunk && le == hipSuccess; ++k) le = step();
+      e = hipStreamEndCapture(c->stream, &g);
+      parity = p0;
+      if (le != hipSuccess) e = le;
+      if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      for (; e == hipSuccess && done + kChunk <= iters; done += kChunk) e = hipGraphLaunch(x, c->stream);
+      if (x) (void)hipGraphExecDestroy(x);
+      if (e != hipSuccess) return e;
+    }
+    for (; done < iters; ++done) {
+      hipError_t e = step();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+fea_status fea_translation_align(fea_ctx* c, int32_t n_cams, int64_t n_pairs, const int32_t* pair_i,
+                                 const int32_t* pair_j, const double* R, const double* t_rel, int32_t n_runs,
+                                 const double* o_init, const fea_ta_options* opt, double* o_out,
+                                 int32_t* run_of_cam, double* run_loss, double* final_loss, double* run_o,
+                                 double* cam_loss, float* ms) {
+  if (!c) return FEA_EINVAL;
+  if (!pair_i || !pair_j || !R || !t_rel || !o_init || !o_out)
+    return fail(c, FEA_EINVAL, "pair_i, pair_j, R, t_rel, o_init and o_out are required");
+  if (n_cams < 2 || n_pairs < 1 || n_pairs > INT32_MAX / 2)
+    return fail(c, FEA_EINVAL, "need n_cams >= 2 and 1 <= n_pairs < 2^30");
+  if (n_runs < 1 || n_runs > 64) return fail(c, FEA_EINVAL, "n_runs must be in [1, 64]");
+  fea_ta_options o;
+  fea_ta_default_options(&o);
+  if (opt) o = *opt;
+  if (o.iters_run < 0 || o.iters_final < 0 || !(o.lr > 0) || !(o.lr_final > 0) || !(o.lr_end_frac > 0) ||
+      !(o.lr_end_frac <= 1) || !(o.beta1 >= 0 && o.beta1 < 1) || !(o.beta2 >= 0 && o.beta2 < 1) ||
+      !(o.adam_eps >= 0))
+    return fail(c, FEA_EINVAL, "invalid alignment options");
+  for (int64_t p = 0; p < n_pairs; ++p) {
+    const int32_t i = pair_i[p], j = pair_j[p];
+    if (i < 0 || j < 0 || i >= n_cams || j >= n_cams || i == j) return fail(c, FEA_EINVAL, "invalid camera pair");
+    const double* t = t_rel + 3 * p;
+    if (!all_finite(t, 3)) return fail(c, FEA_ENONFINITE, "non-finite relative translation");
+    if (!(t[0] * t[0] + t[1] * t[1] + t[2] * t[2] > 0.0))
+      return fail(c, FEA_EDEGENERATE, "zero relative translation");
+  }
+  if (!all_finite(R, (size_t)9 * n_cams)) return fail(c, FEA_ENONFINITE, "non-finite rotation");
+  const size_t n3 = (size_t)3 * n_cams, r3 = n3 * (size_t)n_runs;
+  if (!all_finite(o_init, r3)) return fail(c, FEA_ENONFINITE, "non-finite initial centre");
+  std::vector<int32_t> off, ent;
+  camera_entries(n_cams, n_pairs, pair_i, pair_j, off, ent);
+
+  DeviceGuard g(c->device);
+  CallScratch sc(c->stream);
+  int32_t *dpi, *dpj, *doff, *dent, *derr, *drun;
+  double *dR, *dt, *tg, *o0, *o1, *m, *v, *pl, *cl, *rl, *om0, *om1, *fl;
+  fea::TaCounters* ctr;
+  HIP_OR_FAIL(c, sc.put(dpi, pair_i, (size_t)n_pairs));
+  HIP_OR_FAIL(c, sc.put(dpj, pair_j, (size_t)n_pairs));
+  HIP_OR_FAIL(c, sc.put(doff, off.data(), off.size()));
+  HIP_OR_FAIL(c, sc.put(dent, ent.data(), ent.size()));
+  HIP_OR_FAIL(c, sc.put(dR, R, (size_t)9 * n_cams));
+  HIP_OR_FAIL(c, sc.put(dt, t_rel, (size_t)3 * n_pairs));
+  HIP_OR_FAIL(c, sc.put(o0, o_init, r3));
+  HIP_OR_FAIL(c, sc.alloc(tg, (size_t)3 * n_pairs));
+  HIP_OR_FAIL(c, sc.alloc(o1, r3));
+  HIP_OR_FAIL(c, sc.alloc(m, r3));
+  HIP_OR_FAIL(c, sc.alloc(v, r3));
+  HIP_OR_FAIL(c, sc.alloc(pl, (size_t)n_pairs * n_runs));
+  HIP_OR_FAIL(c, sc.alloc(cl, (size_t)n_cams * n_runs));
+  HIP_OR_FAIL(c, sc.alloc(rl, (size_t)n_runs));
+  HIP_OR_FAIL(c, sc.alloc(om0, n3));
+  HIP_OR_FAIL(c, sc.alloc(om1, n3));
+  HIP_OR_FAIL(c, sc.alloc(fl, 1));
+  HIP_OR_FAIL(c, sc.alloc(drun, (size_t)n_cams));
+  HIP_OR_FAIL(c, sc.alloc(derr, 1));
+  HIP_OR_FAIL(c, sc.alloc(ctr, 1));
+  HIP_OR_FAIL(c, hipMemsetAsync(m, 0, r3 * sizeof(double), c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(v, 0, r3 * sizeof(double), c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(derr, 0, sizeof(int32_t), c->stream));
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (ms) {
+    HIP_OR_FAIL(c, hipEventCreate(&ev[0]));
+    HIP_OR_FAIL(c, hipEventCreate(&ev[1]));
+  }
+  hipError_t e = hipSuccess;
+  if (ev[0]) e = hipEventRecord(ev[0], c->stream);
+  if (e == hipSuccess) e = fea::launch_ta_targets(c->stream, n_pairs, dpj, dR, dt, tg);
+  // the runs, side by side
+  TaPhase ph{c, n_runs, n_cams, n_pairs, doff, dent, dpi, dpj, tg, {o0, o1}, m, v, ctr,
+             o.beta1, o.beta2, o.adam_eps, o.iters_run > 0 ? std::pow(o.lr_end_frac, 1.0 / o.iters_run) : 1.0};
+  if (e == hipSuccess) e = fea::launch_ta_counters(c->stream, ctr, o.lr);
+  if (e == hipSuccess) e = ph.run(o.iters_run);
+  double* ro = ph.o[ph.parity];
+  if (e == hipSuccess) e = fea::launch_ta_align(c->stream, n_runs, n_cams, ro, derr);
+  if (e == hipSuccess) e = fea::launch_ta_losses(c->stream, n_runs, n_cams, n_pairs, doff, dent, dpi, dpj, tg, ro, pl, cl, rl);
+  if (e == hipSuccess) e = fea::launch_ta_merge(c->stream, n_runs, n_cams, ro, cl, om0, drun);
+  // the merged centres, one more loop
+  if (e == hipSuccess) e = hipMemsetAsync(m, 0, n3 * sizeof(double), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(v, 0, n3 * sizeof(double), c->stream);
+  TaPhase fin{c, 1, n_cams, n_pairs, doff, dent, dpi, dpj, tg, {om0, om1}, m, v, ctr,
+              o.beta1, o.beta2, o.adam_eps, o.iters_final > 0 ? std::pow(o.lr_end_frac, 1.0 / o.iters_final) : 1.0};
+  if (e == hipSuccess) e = fea::launch_ta_counters(c->stream, ctr, o.lr_final);
+  if (e == hipSuccess) e = fin.run(o.iters_final);
+  double* fo = fin.o[fin.parity];
+  if (e == hipSuccess) e = fea::launch_ta_align(c->stream, 1, n_cams, fo, derr);
+  if (e == hipSuccess) e = fea::launch_ta_losses(c->stream, 1, n_cams, n_pairs, doff, dent, dpi, dpj, tg, fo, pl, nullptr, fl);
+  if (e == hipSuccess && ev[1]) e = hipEventRecord(ev[1], c->stream);
+  int32_t herr = 0;
+  double hfl = 0.0;
+  if (e == hipSuccess) e = fetch(c->stream, o_out, fo, n3);
+  if (e == hipSuccess) e = fetch(c->stream, run_of_cam, drun, (size_t)n_cams);
+  if (e == hipSuccess) e = fetch(c->stream, run_loss, rl, (size_t)n_runs);
+  if (e == hipSuccess) e = fetch(c->stream, run_o, ro, r3);
+  if (e == hipSuccess) e = fetch(c->stream, cam_loss, cl, (size_t)n_cams * n_runs);
+  if (e == hipSuccess) e = fetch(c->stream, &hfl, fl, 1);
+  if (e == hipSuccess) e = fetch(c->stream, &herr, derr, 1);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && ms) e = hipEventElapsedTime(ms, ev[0], ev[1]);
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  HIP_OR_FAIL(c, e);
+  if (herr) return fail(c, FEA_EDEGENERATE, "all camera centres coincide");
+  if (final_loss) *final_loss = hfl;
   return FEA_OK;
 }
 

@@ -101,7 +101,17 @@ _SIGNATURES = {
     "fea_hbm_probe": ([C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
     "fea_get_kernel_timing": ([_P, _P, _P], C.c_int),
     "fea_get_kernel_times": ([_P, _P, C.c_int64, _P], C.c_int),
+    "fea_relative_translations": ([_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P], C.c_int),
+    "fea_ta_default_options": ([_P], C.c_int),
+    "fea_translation_align": ([_P, C.c_int32, C.c_int64, _P, _P, _P, _P, C.c_int32, _P, _P, _P, _P, _P,
+                               _P, _P, _P, _P], C.c_int),
 }
+
+
+class fea_ta_options(C.Structure):
+    _fields_ = [("iters_run", C.c_int32), ("iters_final", C.c_int32), ("lr", C.c_double),
+                ("lr_final", C.c_double), ("lr_end_frac", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("adam_eps", C.c_double)]
 
 
 def lib():
@@ -168,6 +178,16 @@ def mlp_grad(feat, target, params, device=0):
     if rc != FEA_OK:
         raise FeaError(rc, lib().fea_status_string(rc).decode())
     return loss.value, grad
+
+
+def ta_default_options(**kw) -> fea_ta_options:
+    o = fea_ta_options()
+    lib().fea_ta_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
 
 
 def default_options(**kw) -> fea_options:
@@ -372,6 +392,63 @@ class Context:
         self._check(lib().fea_get_poses(self._h, R.ctypes.data_as(_P), t.ctypes.data_as(_P),
                                         f.ctypes.data_as(_P)))
         return R, t, f
+
+    def relative_translations(self, R, cand, f=None, scores=False, timing=False):
+        """Relative-translation candidate search over the loaded matches (see
+        fea_relative_translations).  R [N,3,3], cand [K,3] unit vectors.
+        Returns t_rel [P,3], best [P], vote [P], score_best [P], optionally
+        scores [P,K] (float32) and score_ms."""
+        R, pR = _host(np.asarray(R).reshape(-1, 9), np.float64)
+        cand, pc = _host(np.asarray(cand).reshape(-1, 3), np.float64)
+        pf = None
+        if f is not None:
+            f, pf = _host(f, np.float64)
+        P = self.info()["n_pairs"]
+        t_rel = np.zeros((max(P, 1), 3))
+        best = np.zeros(max(P, 1), np.int32)
+        vote = np.zeros(max(P, 1), np.int32)
+        sb = np.zeros(max(P, 1))
+        sc = np.zeros((max(P, 1), len(cand)), np.float32) if scores else None
+        ms = C.c_float(0.0)
+        self._check(lib().fea_relative_translations(
+            self._h, pR, pf, len(cand), pc, t_rel.ctypes.data_as(_P), best.ctypes.data_as(_P),
+            vote.ctypes.data_as(_P), sb.ctypes.data_as(_P),
+            sc.ctypes.data_as(_P) if scores else None, C.byref(ms) if timing else None))
+        out = dict(t_rel=t_rel[:P], best=best[:P], vote=vote[:P], score_best=sb[:P])
+        if scores:
+            out["scores"] = sc[:P]
+        if timing:
+            out["score_ms"] = ms.value
+        return out
+
+    def translation_align(self, pair_cams, R, t_rel, o_init, options=None, details=False):
+        """Camera centres from unit relative translations with multiple random
+        initialisations (see fea_translation_align).  pair_cams [P,2],
+        R [N,3,3], t_rel [P,3], o_init [runs,N,3]."""
+        pc = np.ascontiguousarray(np.asarray(pair_cams).reshape(-1, 2), np.int32)
+        pi, ppi = _host(pc[:, 0], np.int32)
+        pj, ppj = _host(pc[:, 1], np.int32)
+        R, pR = _host(np.asarray(R).reshape(-1, 9), np.float64)
+        t_rel, pt = _host(np.asarray(t_rel).reshape(-1, 3), np.float64)
+        o_init, po = _host(o_init, np.float64)
+        runs, N = o_init.shape[0], o_init.shape[1]
+        opt = options if options is not None else ta_default_options()
+        o = np.zeros((N, 3))
+        run_of_cam = np.zeros(N, np.int32)
+        run_loss = np.zeros(runs)
+        final = C.c_double(0.0)
+        run_o = np.zeros((runs, N, 3)) if details else None
+        cam_loss = np.zeros((runs, N)) if details else None
+        ms = C.c_float(0.0)
+        self._check(lib().fea_translation_align(
+            self._h, N, len(pc), ppi, ppj, pR, pt, runs, po, C.byref(opt), o.ctypes.data_as(_P),
+            run_of_cam.ctypes.data_as(_P), run_loss.ctypes.data_as(_P), C.byref(final),
+            run_o.ctypes.data_as(_P) if details else None,
+            cam_loss.ctypes.data_as(_P) if details else None, C.byref(ms)))
+        out = dict(o=o, run_of_cam=run_of_cam, run_loss=run_loss, final_loss=final.value, ms=ms.value)
+        if details:
+            out.update(run_o=run_o, cam_loss=cam_loss)
+        return out
 
     def info(self) -> dict:
         i = fea_info()
