@@ -85,7 +85,7 @@ def lib():
         _lib.orc_mlp_forward.argtypes = [C.c_int64, P, P, P]
         _lib.orc_mlp_bce_grad.argtypes = [C.c_int64, P, P, P, P]
         _lib.orc_mlp_bce_grad.restype = C.c_double
-        _lib.orc_rel_trans.argtypes = [P, P, P, C.c_int32, P, P, P, P, P, P, P]
+        _lib.orc_rel_trans.argtypes = [P, P, P, C.c_int32, P, C.c_double, P, P, P, P, P, P]
         _lib.orc_rel_trans.restype = C.c_int
         _lib.orc_ta_targets.argtypes = [C.c_int32, C.c_int64, P, P, P, P, P]
         _lib.orc_ta_targets.restype = C.c_int
@@ -363,10 +363,11 @@ def ta_default_options(**kw) -> TaOptions:
     return o
 
 
-def rel_trans(pb: OracleProblem, R, f, cand, scores=False):
-    """Relative-translation candidate search (see orc_rel_trans).  Returns a
+def rel_trans(pb: OracleProblem, R, f, cand, scores=False, tau=np.inf):
+    """Relative-translation candidate search (see orc_rel_trans); tau caps
+    each match's |eps| (normalised units; inf: the plain mean).  Returns a
     dict with pair_cams [P,2], best [P], t_rel [P,3], vote [P] and, with
-    scores=True, the mean |eps| of every candidate [P, K]."""
+    scores=True, the mean capped |eps| of every candidate [P, K]."""
     _, _, pc, _ = segment(pb.cam1, pb.cam2, pb.n_cams)
     P = len(pc)
     cand = _f64(cand).reshape(-1, 3)
@@ -379,7 +380,7 @@ def rel_trans(pb: OracleProblem, R, f, cand, scores=False):
     t_rel = np.zeros((max(P, 1), 3))
     vote = np.zeros(max(P, 1), np.int64)
     n_pairs = C.c_int64(0)
-    if lib().orc_rel_trans(pb.ref, _p(R), _p(f), K, _p(cand), C.byref(n_pairs), _p(pair_cams),
+    if lib().orc_rel_trans(pb.ref, _p(R), _p(f), K, _p(cand), float(tau), C.byref(n_pairs), _p(pair_cams),
                            _p(sc), _p(best), _p(t_rel), _p(vote)):
         raise ValueError("oracle rel_trans rejected its input")
     assert n_pairs.value == P

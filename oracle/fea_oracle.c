@@ -837,8 +837,8 @@ static int cheirality_vote(const double a[3], const double b[3], const double t[
 }
 
 int orc_rel_trans(const orc_problem *pb, const double *R, const double *f, int32_t n_cand,
-                  const double *cand, int64_t *n_pairs_out, int32_t *pair_cams, double *scores,
-                  int32_t *best, double *t_rel, int64_t *vote) {
+                  const double *cand, double tau, int64_t *n_pairs_out, int32_t *pair_cams,
+                  double *scores, int32_t *best, double *t_rel, int64_t *vote) {
   if (check_problem(pb) || n_cand < 1) return -1;
   seg_result s;
   if (segment_problem(pb, &s)) {
@@ -871,7 +871,8 @@ int orc_rel_trans(const orc_problem *pb, const double *R, const double *f, int32
         const double x1[3] = {ax / f[i], ay / f[i], 1.0}, x2[3] = {bx / f[j], by / f[j], 1.0};
         double Ex1[3];
         mat_vec(E, x1, Ex1);
-        sum += fabs(dot3(x2, Ex1));
+        const double e = fabs(dot3(x2, Ex1));
+        sum += e < tau ? e : tau;
       }
       const double mean = sum / (double)(b1 - b0);
       if (scores) scores[n * n_cand + k] = mean;
@@ -882,13 +883,18 @@ int orc_rel_trans(const orc_problem *pb, const double *R, const double *f, int32
     }
     best[n] = best_k;
     const double *u = cand + 3 * best_k;
+    double S[9], E[9];
+    skew(u, S);
+    mat_mul(S, Rij, E);
     int64_t v = 0;
     for (int64_t p = b0; p < b1; ++p) {
       int32_t ci, cj;
       double ax, ay, bx, by;
       canonical_match(pb, s.perm[p], &ci, &cj, &ax, &ay, &bx, &by);
       const double x1[3] = {ax / f[i], ay / f[i], 1.0}, x2[3] = {bx / f[j], by / f[j], 1.0};
-      double a[3];
+      double a[3], Ex1[3];
+      mat_vec(E, x1, Ex1);
+      if (!(fabs(dot3(x2, Ex1)) < tau)) continue; /* only matches the chosen direction explains */
       mat_vec(Rij, x1, a);
       v += cheirality_vote(a, x2, u);
     }

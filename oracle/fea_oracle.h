@@ -184,19 +184,23 @@ double orc_mlp_bce_grad(int64_t n, const double *feat, const double *target, con
  * scoring candidate directions on the unit sphere by their mean epipolar
  * error and keeping the best.  For every canonical pair (i < j, in the
  * lexicographic order of orc_segment) and candidate u (cand[3k..3k+2]):
- *   score(u) = mean over the pair's matches of |x~2^T [u]x R_ij x~1|,
+ *   score(u) = mean over the pair's matches of min(|x~2^T [u]x R_ij x~1|, tau),
  * x~ = ((x - cx)/f, (y - cy)/f, 1), R_ij = R_j R_i^T (the EA residual with the
- * relative translation set to u).  best = the lowest score (ties: the lower
+ * relative translation set to u).  tau = INFINITY is the paper's plain mean;
+ * a finite tau (normalised units, reading: the paper scores two-view inliers,
+ * and the truncation keeps the outliers among the matches from steering the
+ * choice) caps each match's term.  best = the lowest score (ties: the lower
  * index).  The score does not change under u -> -u, so the sign is taken by
- * cheirality (reading; the paper does not say): every match votes +1 when
- * both depths of its two-view triangulation with t_ij = u are positive, -1
- * when both are negative, 0 otherwise; t_rel = u if the vote sum is >= 0,
- * else -u.  Outputs, caller-allocated for P pairs (P <= n_matches):
+ * cheirality (reading; the paper does not say): every match with
+ * |eps(u)| < tau votes +1 when both depths of its two-view triangulation
+ * with t_ij = u are positive, -1 when both are negative, 0 otherwise;
+ * t_rel = u if the vote sum is >= 0, else -u.  Outputs, caller-allocated for
+ * P pairs (P <= n_matches):
  * pair_cams [2P], scores [P * n_cand] (nullable), best [P], t_rel [3P],
  * vote [P].  Returns 0, or -1 for invalid matches or n_cand < 1. */
 int orc_rel_trans(const orc_problem *pb, const double *R, const double *f, int32_t n_cand,
-                  const double *cand, int64_t *n_pairs, int32_t *pair_cams, double *scores,
-                  int32_t *best, double *t_rel, int64_t *vote);
+                  const double *cand, double tau, int64_t *n_pairs, int32_t *pair_cams,
+                  double *scores, int32_t *best, double *t_rel, int64_t *vote);
 
 /* ---- Global Translation: camera centres ------------------------------------
  * Eq. fastmap-global-translation-objective and the text around it: targets
