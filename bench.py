@@ -15,6 +15,11 @@ Prints ONE JSON line on stdout (progress goes to stderr):
   cpu_baseline the FP64 oracle timed on the host on a 6M-match sample
   solve       wall time until the mean rotation error first drops to <= 1 deg,
               with the per-match inner loop and with the pairs' quadratic forms
+  translation the Global Translation stages before the adjustment: the
+              relative-translation candidate search over the same scene's
+              matches (its scoring kernel against the fp32 matrix-core peak)
+              and the multi-start camera-centre alignment on a 500-camera
+              object-centric pair graph, each with the oracle timed beside it
 """
 from __future__ import annotations
 
@@ -32,6 +37,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "residual+grad matches/s and HBM GB/s vs peak; wall time to ≤1° mean rot error"
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3  # dense fp32 matrix-core peak of the MI355X
+# VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 BYTES_PER_MATCH = 16  # x1, y1, x2, y2 as fp32: the algorithmic minimum per match
 
 # HBM bytes per launch of the per-match kernel at round 0 of each workload,
@@ -93,6 +101,14 @@ def parse():
     ap.add_argument("--matches", type=int, default=0, help="target match count (0: the workload's own)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1-degree solve")
+    ap.add_argument("--no-translation", action="store_true",
+                    help="skip the relative-translation search and camera-centre alignment")
+    ap.add_argument("--candidates", type=int, default=2048,
+                    help="candidate directions of the relative-translation search")
+    ap.add_argument("--search-cap-px", type=float, default=32.0,
+                    help="cap of each match's error in the search, pixels (inf: the plain mean)")
+    ap.add_argument("--search-cpu-pairs", type=int, default=400,
+                    help="pairs of the scene the CPU oracle searches for its baseline")
     ap.add_argument("--cpu-sample", type=int, default=6_000_000)
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--ablation", action="store_true",
@@ -244,6 +260,106 @@ def batched_vs_sequential(fastea, metrics, synth, **options):
             "options": ({**options, "weight_mode": "learned"} if mlp is not None else options) or "defaults"}
 
 
+def translation_stages(sc, fastea, synth, n_cand, with_cpu, cap_px=32.0, cpu_pairs=400, reps=5):
+    """Relative-translation search over the scene's matches (the true
+    rotations and focal lengths stand in for the outputs of global rotation
+    alignment and focal estimation, which are not built here; each match's
+    error capped at cap_px) and
+    camera-centre alignment (2 random starts, default schedule) on a
+    500-camera object graph (pairs within 60 degrees, true directions with 2
+    degrees of noise)."""
+    cand = synth.sphere_candidates(n_cand)
+    ctx = fastea.Context(0)
+    ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+    ctx.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+    ctx.relative_translations(sc.R_gt, cand, f=sc.f_gt, tau_px=cap_px)
+    ms, walls = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = ctx.relative_translations(sc.R_gt, cand, f=sc.f_gt, tau_px=cap_px, timing=True)
+        walls.append(time.perf_counter() - t0)
+        ms.append(r["score_ms"])
+    _, _, pc, _ = ctx.get_segments()
+    ctx.close()
+    gt = synth.relative_translations_gt(sc, pc)
+    ang = np.degrees(np.arccos(np.clip(np.sum(r["t_rel"] * gt, axis=1), -1.0, 1.0)))
+    k_ms = float(np.mean(ms))
+    flop = 6.0 * sc.n_matches * n_cand  # 3 multiply-adds per (candidate, match)
+    achieved = flop / (k_ms / 1e3) / 1e12
+    cm_rate = sc.n_matches * n_cand / (k_ms / 1e3)
+    mfma = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None, "flop_per_launch": flop,
+            "note": "6 flop per (candidate, match); the fp32 16x16x4 matrix instruction spends a fourth "
+                    "depth slot on zero padding, so the reachable fraction is 0.75"}
+    if math.isfinite(cap_px):
+        # capped score: per (candidate, match) one v_min_f32 and one v_add_f32 lane operation
+        peak_cm = VALU_LANE_OPS_PER_S / 2
+        roof = {"bound": "alu", "achieved": cm_rate / 1e12, "peak": peak_cm / 1e12,
+                "unit": "T candidate-matches/s", "frac": cm_rate / peak_cm, "traffic": None,
+                "note": "two VALU lane operations per (candidate, match), the cap and the sum, against "
+                        "256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz; the matrix-core products run beside them",
+                "mfma": mfma}
+    else:
+        roof = mfma
+    search = {
+        "candidates": n_cand, "pairs": int(len(pc)), "matches": sc.n_matches,
+        "cap_px": cap_px if math.isfinite(cap_px) else None,
+        "kernel": "k_rt_score", "kernel_ms": k_ms, "kernel_ms_all": [round(x, 4) for x in ms],
+        "call_ms": 1e3 * float(np.median(walls)),
+        "candidate_matches_per_s": cm_rate,
+        "roofline": roof,
+        "direction_error_deg_median": float(np.median(ang)),
+        "sign_correct": float(np.mean(ang < 90.0)),
+    }
+    pcg, R, tij, c = synth.object_pair_graph(500, 60.0, 0)
+    rng = np.random.default_rng(1)
+    tn = tij + np.deg2rad(2.0) * rng.normal(size=tij.shape) / np.sqrt(3.0)
+    init = synth.random_centres(7, 2, len(c))
+    actx = fastea.Context(0)
+    actx.translation_align(pcg, R, tn, init)
+    a_ms = []
+    for _ in range(reps):
+        a = actx.translation_align(pcg, R, tn, init)
+        a_ms.append(a["ms"])
+    actx.close()
+    truth = c - c.mean(0)
+    truth /= np.linalg.norm(truth, axis=1).mean()
+    opts = fastea.ta_default_options()
+    steps = opts.iters_run + opts.iters_final
+    align = {"cameras": len(c), "pairs": int(len(pcg)), "runs": 2, "steps_per_run": opts.iters_run,
+             "final_steps": opts.iters_final, "ms": float(np.median(a_ms)),
+             "us_per_step": 1e3 * float(np.median(a_ms)) / steps, "final_loss": a["final_loss"],
+             "centre_error_median": float(np.median(np.linalg.norm(a["o"] - truth, axis=1))),
+             "bound": "latency: O(runs x pairs) fp64 work per step, one wave per (run, camera)"}
+    out = {"relative_translations": search, "alignment": align}
+    if with_cpu:
+        import oracle
+        oracle.build(force=False)
+        sel_pairs = np.random.default_rng(5).choice(len(pc), size=min(cpu_pairs, len(pc)), replace=False)
+        i = np.minimum(sc.cam1, sc.cam2)
+        j = np.maximum(sc.cam1, sc.cam2)
+        key = i.astype(np.int64) * sc.n_cams + j
+        want = pc[sel_pairs, 0].astype(np.int64) * sc.n_cams + pc[sel_pairs, 1]
+        sel = np.nonzero(np.isin(key, want))[0]
+        pb = oracle.OracleProblem.from_scene(sc, sel)
+        t0 = time.perf_counter()
+        oracle.rel_trans(pb, sc.R_gt, sc.f_gt, cand, tau=cap_px / np.median(sc.f_gt))
+        dt = time.perf_counter() - t0
+        tg = oracle.ta_targets(len(c), pcg, R, tn)
+        t1 = time.perf_counter()
+        oracle.ta_solve(pcg, tg, init)
+        dt1 = time.perf_counter() - t1
+        search["cpu_baseline"] = {
+            "value": len(sel) * n_cand / dt, "unit": "candidate-matches/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{len(sel_pairs)} random pairs ({len(sel)} matches) x {n_cand} candidates, FP64 C "
+                      f"oracle (OpenMP over pairs), {dt:.1f} s wall"}
+        align["cpu_baseline"] = {"value": 1e3 * dt1, "unit": "ms", "cores": 1, "kind": "oracle",
+                                 "sample": "the same alignment (2 runs, default schedule) in the FP64 C "
+                                           f"oracle, one thread, {dt1:.1f} s wall"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -348,6 +464,18 @@ def main():
             log(f"[bench] batch {name}: batched {batch[name]['batched_s']} s, sequential "
                 f"{batch[name]['sequential_s']} s, {batch[name]['scenes_at_or_below_1deg']} scenes <= 1 deg")
 
+    translation = None
+    if not args.no_translation:
+        log("[bench] relative-translation search and camera-centre alignment ...")
+        translation = translation_stages(sc, fastea, synth, args.candidates, not args.no_cpu,
+                                         args.search_cap_px, args.search_cpu_pairs)
+        rt, al = translation["relative_translations"], translation["alignment"]
+        log(f"[bench] search: k_rt_score {rt['kernel_ms']:.3f} ms = {rt['roofline']['achieved']:.2f} "
+            f"{rt['roofline']['unit']} ({rt['roofline']['frac']:.3f} of the {rt['roofline']['bound']} peak), "
+            f"median direction error "
+            f"{rt['direction_error_deg_median']:.2f} deg; alignment {al['ms']:.2f} ms "
+            f"({al['us_per_step']:.2f} us/step)")
+
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
@@ -376,6 +504,7 @@ def main():
                                        "copy (null if the kernel changed since they were taken)"},
         "cpu_baseline": cpu,
         "solve": solve,
+        "translation": translation,
     }
     if batch is not None:
         out["batch"] = batch

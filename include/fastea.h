@@ -403,25 +403,29 @@ fea_status fea_get_rotation_log(fea_ctx *ctx, double *R_log, int32_t *n_logged);
  * of fea_get_segments) and candidate u:
  *   score(u) = mean over the pair's matches of |x~2^T [u]x R_ij x~1|,
  * x~ = ((x - cx)/f, (y - cy)/f, 1), R_ij = R_j R_i^T: the epipolar-adjustment
- * residual with the relative translation set to u.  The lowest score wins
- * (ties: the lower candidate index).  A direction and its opposite score the
- * same, so the sign is decided by cheirality: each match votes +1 when both
- * depths of its least-squares two-view triangulation with translation u are
- * positive, -1 when both are negative, 0 otherwise; the result is u for a
- * vote sum >= 0, else -u.  Scores are fp32 on the matrix cores; the vote is
- * fp64.  Inputs (host, copied): R [n_cams*9] world-to-camera rotations,
- * f [n_cams] focal lengths (NULL = the loaded intrinsics), cand [n_cand*3]
- * unit vectors (one hemisphere suffices).  Outputs (host, caller-allocated,
+ * residual with the relative translation set to u.  With a finite tau_px
+ * every match's term is capped, min(|eps|, tau) with tau = tau_px / median f:
+ * the paper scores two-view inliers, and the cap keeps outliers among the
+ * matches from steering the choice (tau_px = INFINITY: the plain mean).  The
+ * lowest score wins (ties: the lower candidate index).  A direction and its
+ * opposite score the same, so the sign is decided by cheirality: each match
+ * with |eps| < tau at the chosen direction votes +1 when both depths of its
+ * least-squares two-view triangulation with translation u are positive, -1
+ * when both are negative, 0 otherwise; the result is u for a vote sum >= 0,
+ * else -u.  Scores are fp32 on the matrix cores; the vote is fp64.  Inputs
+ * (host, copied): R [n_cams*9] world-to-camera rotations, f [n_cams] focal
+ * lengths (NULL = the loaded intrinsics), tau_px > 0, cand [n_cand*3] unit
+ * vectors (one hemisphere suffices).  Outputs (host, caller-allocated,
  * n_pairs = fea_get_info's n_pairs): t_rel [n_pairs*3], best [n_pairs]
  * (nullable), vote [n_pairs] (nullable), score_best [n_pairs] (nullable),
  * scores [n_pairs*n_cand] (nullable: every candidate's mean score),
  * score_ms (nullable: duration of the scoring kernel, HIP events).
  * Requires loaded matches (FEA_ESTATE otherwise); FEA_EINVAL for
  * n_cand outside [1, 2^22], candidates that are not unit vectors (1e-6) or
- * focal lengths <= 0; FEA_ENONFINITE for non-finite input.  Device scratch
+ * focal lengths <= 0 or tau_px <= 0; FEA_ENONFINITE for non-finite input.  Device scratch
  * (n_cand rounded up to 1024, times the number of 2048-match work items, in
  * fp32) is allocated and freed by the call. */
-fea_status fea_relative_translations(fea_ctx *ctx, const double *R, const double *f, int32_t n_cand,
+fea_status fea_relative_translations(fea_ctx *ctx, const double *R, const double *f, double tau_px, int32_t n_cand,
                                      const double *cand, double *t_rel, int32_t *best, int32_t *vote,
                                      double *score_best, float *scores, float *score_ms);
 

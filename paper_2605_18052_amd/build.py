@@ -24,10 +24,11 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-t
           "-Wno-unused-command-line-argument"]
 
 
-# Per-source code-generation options.  The MLP kernels keep their matrix-core
-# accumulators in ordinary VGPRs (the accumulation-register form would cost a
-# v_accvgpr_read per accumulator value before the next layer can use it).
-EXTRA = {"fea_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=true"]}
+# Per-source code-generation options.  The MLP and candidate-scoring kernels
+# keep their matrix-core results in ordinary VGPRs (the accumulation-register
+# form would cost a v_accvgpr_read per value before the VALU can use it).
+EXTRA = {"fea_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=true"],
+         "fea_trans.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=true"]}
 
 
 def _compile(src: str) -> str:

@@ -1988,7 +1988,7 @@ void camera_entries(int32_t n_cams, int64_t n_pairs, const int32_t* pi, const in
 
 extern "C" {
 
-fea_status fea_relative_translations(fea_ctx* c, const double* R, const double* f, int32_t n_cand,
+fea_status fea_relative_translations(fea_ctx* c, const double* R, const double* f, double tau_px, int32_t n_cand,
                                      const double* cand, double* t_rel, int32_t* best, int32_t* vote,
                                      double* score_best, float* scores, float* score_ms) {
   if (!c) return FEA_EINVAL;
@@ -2000,6 +2000,15 @@ fea_status fea_relative_translations(fea_ctx* c, const double* R, const double* 
   std::vector<double> fv(f ? f : c->f_in.data(), (f ? f : c->f_in.data()) + N);
   for (double x : fv)
     if (!std::isfinite(x) || !(x > 0.0)) return fail(c, FEA_EINVAL, "focal lengths must be finite and > 0");
+  if (std::isnan(tau_px) || !(tau_px > 0.0)) return fail(c, FEA_EINVAL, "tau_px must be > 0 (inf: no cap)");
+  // the cap in normalised units: pixels over the median focal length
+  double tau = tau_px;
+  if (std::isfinite(tau_px)) {
+    std::vector<double> fs(fv);
+    std::sort(fs.begin(), fs.end());
+    const size_t n = fs.size();
+    tau = tau_px / ((n & 1) ? fs[n / 2] : 0.5 * (fs[n / 2 - 1] + fs[n / 2]));
+  }
   for (int32_t k = 0; k < n_cand; ++k) {
     const double* u = cand + 3 * (size_t)k;
     if (!all_finite(u, 3)) return fail(c, FEA_ENONFINITE, "non-finite candidate");
@@ -2057,11 +2066,11 @@ fea_status fea_relative_translations(fea_ctx* c, const double* R, const double* 
     HIP_OR_FAIL(c, hipEventCreate(&ev[0]));
     HIP_OR_FAIL(c, hipEventCreate(&ev[1]));
   }
-  hipError_t e = fea::launch_rt_score(c->stream, n_items, groups, ditems, rowf, x1, y1, x2, y2, dcand, kp, part,
-                                      ev[0], ev[1]);
+  hipError_t e = fea::launch_rt_score(c->stream, n_items, groups, ditems, rowf, x1, y1, x2, y2, dcand, kp, tau,
+                                      part, ev[0], ev[1]);
   if (e == hipSuccess)
-    e = fea::launch_rt_select(c->stream, P, n_cand, kp, dpio, ditems, part, dcand, rowd, x1, y1, x2, y2, dscores,
-                              dbest, dvote, dt, dsb);
+    e = fea::launch_rt_select(c->stream, P, n_cand, kp, tau, dpio, ditems, part, dcand, rowd, x1, y1, x2, y2,
+                              dscores, dbest, dvote, dt, dsb);
   if (e == hipSuccess) e = fetch(c->stream, t_rel, dt, (size_t)3 * P);
   if (e == hipSuccess) e = fetch(c->stream, best, dbest, (size_t)P);
   if (e == hipSuccess) e = fetch(c->stream, vote, dvote, (size_t)P);

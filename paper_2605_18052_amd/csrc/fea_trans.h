@@ -10,10 +10,11 @@
 namespace fea {
 
 // Candidate search: one scoring workgroup covers one work item (a run of at
-// most kRtItem matches of one pair) and kRtGroup candidates (4 waves x 16
-// blocks of 16 candidates).
+// most kRtItem matches of one pair) and kRtGroup candidates (4 waves x
+// kRtBlocks blocks of 16 candidates).
 constexpr int kRtItem = 2048;
-constexpr int kRtGroup = 1024;
+constexpr int kRtBlocks = 16;
+constexpr int kRtGroup = 4 * kRtBlocks * 16;
 constexpr int kRtRow = 16;  // per-pair row: R_ij (9), 1/f_i, 1/f_j, cx_i, cy_i, cx_j, cy_j, pad
 
 // Adam state shared by all cameras of one alignment phase, one slot per step
@@ -29,8 +30,8 @@ hipError_t launch_rt_pairs(hipStream_t st, int64_t n_pairs, const int32_t* pair_
                            double* rowd);
 hipError_t launch_rt_score(hipStream_t st, int64_t n_items, int n_groups, const int4* items, const float* rowf,
                            const float* x1, const float* y1, const float* x2, const float* y2, const float* cand,
-                           int kp, float* partial, hipEvent_t ev0, hipEvent_t ev1);
-hipError_t launch_rt_select(hipStream_t st, int64_t n_pairs, int k, int kp, const int32_t* pair_item_off,
+                           int kp, double tau, float* partial, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_rt_select(hipStream_t st, int64_t n_pairs, int k, int kp, double tau, const int32_t* pair_item_off,
                             const int4* items, const float* partial, const float* cand, const double* rowd,
                             const float* x1, const float* y1, const float* x2, const float* y2, float* scores,
                             int32_t* best, int32_t* vote, double* t_rel, double* score_best);

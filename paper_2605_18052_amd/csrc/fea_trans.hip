@@ -13,9 +13,9 @@
 //
 // Camera centres.  The L1 direction loss of
 // Eq. fastmap-global-translation-objective is minimised with Adam, one thread
-// per (run, camera): each thread sums its camera's pair terms in pair order
-// (no atomics, the same order at every step and as a plain serial loop), then
-// takes the Adam step.  Several runs from independent random initial centres
+// per (run, camera) wave: the lanes split the camera's pair terms and a fixed
+// wave sum adds them (no atomics: the same order at every step), then the
+// Adam step.  Several runs from independent random initial centres
 // share each launch; they are aligned (centred, unit mean norm) and merged per
 // camera by its mean pair loss (Multiple initializations), then the merged
 // centres get a final loop.  Everything here is fp64: the work is O(pairs)
@@ -23,6 +23,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "fea_trans.h"
@@ -33,7 +34,6 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRtThreads = 256;
-constexpr int kRtBlocks = 16;                     // 16-candidate blocks per wave
 constexpr int kRtLds = kRtItem + 16;              // LDS row stride (floats): rows land 16 banks apart
 constexpr int kTaThreads = 256;
 
@@ -73,11 +73,14 @@ __global__ void k_rt_pairs(int64_t n_pairs, const int32_t* __restrict__ pair_i, 
 // lane l supplies A[l%16][l/16] = component l/16 of match l%16 of the block
 // and B[l/16][l%16] = component l/16 of candidate l%16; it receives D[4(l/16)+r][l%16]
 // for r = 0..3, i.e. four matches of candidate l%16.  Component 3 is zero.
+// With CAP every product enters as min(|d|, tau) (one v_min_f32 with an abs
+// source each), else as |d| (folded into the adds).
+template <bool CAP>
 __global__ __launch_bounds__(kRtThreads) void k_rt_score(const int4* __restrict__ items, int n_groups,
                                                          const float* __restrict__ rowf,
                                                          const float* __restrict__ x1, const float* __restrict__ y1,
                                                          const float* __restrict__ x2, const float* __restrict__ y2,
-                                                         const float* __restrict__ cand, int kp,
+                                                         const float* __restrict__ cand, int kp, float tau,
                                                          float* __restrict__ partial) {
   __shared__ float sn[3][kRtLds];
   const int it = blockIdx.x / n_groups;
@@ -115,32 +118,40 @@ __global__ __launch_bounds__(kRtThreads) void k_rt_score(const int4* __restrict_
   float bop[kRtBlocks];
 #pragma unroll
   for (int q = 0; q < kRtBlocks; ++q) bop[q] = kq < 3 ? cand[(int64_t)kq * kp + cbase + 16 * q + col] : 0.f;
-  float accf[kRtBlocks];
-  double accd[kRtBlocks];
+  float accf[kRtBlocks], acc2[kRtBlocks];
 #pragma unroll
   for (int q = 0; q < kRtBlocks; ++q) {
     accf[q] = 0.f;
-    accd[q] = 0.0;
+    acc2[q] = 0.f;
   }
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  // the row of the next block is read while this one's products run (the
+  // read past the last block stays inside the LDS row: nblk * 16 < kRtLds)
+  const float* srow = sn[kq < 3 ? kq : 0];
+  float a_next = srow[col];
   for (int mb = 0; mb < nblk; ++mb) {
-    const float a = kq < 3 ? sn[kq][(mb << 4) + col] : 0.f;
+    const float a = kq < 3 ? a_next : 0.f;
+    a_next = srow[((mb + 1) << 4) + col];
 #pragma unroll
     for (int q = 0; q < kRtBlocks; ++q) {
       const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bop[q], zero, 0, 0, 0);
-      accf[q] += (__builtin_fabsf(d[0]) + __builtin_fabsf(d[1])) + (__builtin_fabsf(d[2]) + __builtin_fabsf(d[3]));
+      if constexpr (CAP)
+        accf[q] += (__builtin_fminf(__builtin_fabsf(d[0]), tau) + __builtin_fminf(__builtin_fabsf(d[1]), tau)) +
+                   (__builtin_fminf(__builtin_fabsf(d[2]), tau) + __builtin_fminf(__builtin_fabsf(d[3]), tau));
+      else
+        accf[q] += (__builtin_fabsf(d[0]) + __builtin_fabsf(d[1])) + (__builtin_fabsf(d[2]) + __builtin_fabsf(d[3]));
     }
-    if ((mb & 31) == 31) {  // fp32 sums of at most 128 terms, then fp64
+    if ((mb & 31) == 31) {  // lane sums of at most 128 terms, then at most 4 of those
 #pragma unroll
       for (int q = 0; q < kRtBlocks; ++q) {
-        accd[q] += (double)accf[q];
+        acc2[q] += accf[q];
         accf[q] = 0.f;
       }
     }
   }
 #pragma unroll
   for (int q = 0; q < kRtBlocks; ++q) {
-    double s = accd[q] + (double)accf[q];
+    double s = (double)acc2[q] + (double)accf[q];
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
     if (kq == 0) partial[(int64_t)it * kp + cbase + 16 * q + col] = (float)s;
@@ -152,12 +163,16 @@ __global__ __launch_bounds__(kRtThreads) void k_rt_score(const int4* __restrict_
 // l2 x~2 = l1 R_ij x~1 + u have the signs of -(a.u)(b.b) + (a.b)(b.u) and
 // (a.a)(b.u) - (a.b)(a.u), a = R_ij x~1, b = x~2 (the determinant
 // |a x b|^2 is positive unless the rays are parallel).
-__device__ int cheirality_vote(const double* row, float fx1, float fy1, float fx2, float fy2, const double u[3]) {
+__device__ int cheirality_vote(const double* row, float fx1, float fy1, float fx2, float fy2, const double u[3],
+                               double tau) {
   const double ax = ((double)fx1 - row[11]) / row[9], ay = ((double)fy1 - row[12]) / row[9];
   const double bx = ((double)fx2 - row[13]) / row[10], by = ((double)fy2 - row[14]) / row[10];
   const double a0 = row[0] * ax + row[1] * ay + row[2];
   const double a1 = row[3] * ax + row[4] * ay + row[5];
   const double a2 = row[6] * ax + row[7] * ay + row[8];
+  // eps(u) = u . (a x b): only matches the chosen direction explains vote
+  const double e = u[0] * (a1 - a2 * by) + u[1] * (a2 * bx - a0) + u[2] * (a0 * by - a1 * bx);
+  if (!(fabs(e) < tau)) return 0;
   const double aa = a0 * a0 + a1 * a1 + a2 * a2, bb = bx * bx + by * by + 1.0;
   const double ab = a0 * bx + a1 * by + a2;
   const double au = a0 * u[0] + a1 * u[1] + a2 * u[2], bu = bx * u[0] + by * u[1] + u[2];
@@ -170,8 +185,10 @@ __device__ int cheirality_vote(const double* row, float fx1, float fy1, float fx
 }
 
 // Per pair: mean score of every candidate (sum of the item partials over the
-// pair's match count), the lowest (ties: lower index), then the vote.
-__global__ __launch_bounds__(kRtThreads) void k_rt_select(int k_cand, int kp, const int32_t* __restrict__ pair_item_off,
+// pair's match count), the lowest (ties: lower index), then the vote of the
+// matches with |eps| < tau at that direction.
+__global__ __launch_bounds__(kRtThreads) void k_rt_select(int k_cand, int kp, double tau,
+                                                          const int32_t* __restrict__ pair_item_off,
                                                           const int4* __restrict__ items,
                                                           const float* __restrict__ partial,
                                                           const float* __restrict__ cand,
@@ -223,7 +240,7 @@ __global__ __launch_bounds__(kRtThreads) void k_rt_select(int k_cand, int kp, co
     const int4 rec = items[it];
     for (int m = threadIdx.x; m < rec.z; m += kRtThreads) {
       const int64_t s = (int64_t)rec.y + m;
-      v += cheirality_vote(row, x1[s], y1[s], x2[s], y2[s], u);
+      v += cheirality_vote(row, x1[s], y1[s], x2[s], y2[s], u, tau);
     }
   }
   __syncthreads();
@@ -244,15 +261,12 @@ __global__ __launch_bounds__(kRtThreads) void k_rt_select(int k_cand, int kp, co
 }
 
 // ---- camera centres -------------------------------------------------------------
-// The arithmetic below is written without fused multiply-adds so that every
-// step rounds like a plain serial evaluation of the same expressions.
 
 __device__ __forceinline__ double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
 // o^{i->j} = -R_j^T t^{i->j} / |t^{i->j}|
 __global__ void k_ta_targets(int64_t n_pairs, const int32_t* __restrict__ pair_j, const double* __restrict__ R,
                              const double* __restrict__ t_rel, double* __restrict__ target) {
-#pragma clang fp contract(off)
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_pairs) return;
   const double* t = t_rel + 3 * p;
@@ -268,38 +282,10 @@ __global__ void k_ta_counters(TaCounters* ctr, double lr) {
   ctr->b2t[0] = ctr->b2t[1] = 1.0;
 }
 
-// Gradient of camera c's terms: (s - n (n.s)) / |d| per pair with
-// s = sign(n - o^{i->j}) / |P|, added for j and subtracted for i.
-__device__ void ta_cam_grad(int c, const double* __restrict__ o, int64_t n_pairs, const int32_t* __restrict__ cam_off,
-                            const int32_t* __restrict__ cam_ent, const int32_t* __restrict__ pair_i,
-                            const int32_t* __restrict__ pair_j, const double* __restrict__ target, double g[3]) {
-#pragma clang fp contract(off)
-  g[0] = g[1] = g[2] = 0.0;
-  const double np = (double)n_pairs;
-  for (int e = cam_off[c]; e < cam_off[c + 1]; ++e) {
-    const int ent = cam_ent[e];
-    const int64_t q = ent >> 1;
-    const int i = pair_i[q], j = pair_j[q];
-    const double d0 = o[3 * j] - o[3 * i], d1 = o[3 * j + 1] - o[3 * i + 1], d2 = o[3 * j + 2] - o[3 * i + 2];
-    const double nd = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    if (!(nd > 0.0)) continue;
-    const double n0 = d0 / nd, n1 = d1 / nd, n2 = d2 / nd;
-    const double s0 = sgn(n0 - target[3 * q]) / np, s1 = sgn(n1 - target[3 * q + 1]) / np,
-                 s2 = sgn(n2 - target[3 * q + 2]) / np;
-    const double ns = n0 * s0 + n1 * s1 + n2 * s2;
-    const double g0 = (s0 - n0 * ns) / nd, g1 = (s1 - n1 * ns) / nd, g2 = (s2 - n2 * ns) / nd;
-    if (ent & 1) {
-      g[0] += g0;
-      g[1] += g1;
-      g[2] += g2;
-    } else {
-      g[0] -= g0;
-      g[1] -= g1;
-      g[2] -= g2;
-    }
-  }
-}
-
+// One wave per (run, camera): the lanes split the camera's pair terms
+// (s - n (n.s)) / |d| with s = sign(n - o^{i->j}) / |P|, added for j and
+// subtracted for i; a fixed-order wave sum; lanes 0-2 take the Adam step of
+// x, y, z.
 __global__ __launch_bounds__(kTaThreads) void k_ta_step(int runs, int n_cams, int64_t n_pairs,
                                                         const int32_t* __restrict__ cam_off,
                                                         const int32_t* __restrict__ cam_ent,
@@ -310,28 +296,51 @@ __global__ __launch_bounds__(kTaThreads) void k_ta_step(int runs, int n_cams, in
                                                         double* __restrict__ m, double* __restrict__ v,
                                                         TaCounters* ctr, int p, double beta1, double beta2,
                                                         double eps, double decay) {
-#pragma clang fp contract(off)
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)blockIdx.x * (kTaThreads / 64) + (threadIdx.x >> 6);
   const double lr = ctr->lr[p];
   const double b1t = ctr->b1t[p] * beta1, b2t = ctr->b2t[p] * beta2;
-  if (idx == 0) {  // the other parity's slot: read by the next step only
+  if (w == 0 && lane == 0) {  // the other parity's slot: read by the next step only
     ctr->lr[p ^ 1] = lr * decay;
     ctr->b1t[p ^ 1] = b1t;
     ctr->b2t[p ^ 1] = b2t;
   }
-  if (idx >= (int64_t)runs * n_cams) return;
-  const int r = (int)(idx / n_cams), c = (int)(idx - (int64_t)r * n_cams);
+  if (w >= (int64_t)runs * n_cams) return;
+  const int r = (int)(w / n_cams), c = (int)(w - (int64_t)r * n_cams);
   const int64_t base = (int64_t)r * n_cams * 3;
-  double g[3];
-  ta_cam_grad(c, o_in + base, n_pairs, cam_off, cam_ent, pair_i, pair_j, target, g);
-  const double bc1 = 1.0 - b1t, bc2 = 1.0 - b2t;
-  for (int k = 0; k < 3; ++k) {
-    const int64_t a = base + 3 * c + k;
-    const double mk = beta1 * m[a] + (1.0 - beta1) * g[k];
-    const double vk = beta2 * v[a] + (1.0 - beta2) * g[k] * g[k];
+  const double* o = o_in + base;
+  const double inv_np = 1.0 / (double)n_pairs;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int e = cam_off[c] + lane; e < cam_off[c + 1]; e += 64) {
+    const int ent = cam_ent[e];
+    const int64_t q = ent >> 1;
+    const int i = pair_i[q], j = pair_j[q];
+    const double d0 = o[3 * j] - o[3 * i], d1 = o[3 * j + 1] - o[3 * i + 1], d2 = o[3 * j + 2] - o[3 * i + 2];
+    const double nd = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    if (!(nd > 0.0)) continue;
+    const double inv = 1.0 / nd;
+    const double n0 = d0 * inv, n1 = d1 * inv, n2 = d2 * inv;
+    const double s0 = sgn(n0 - target[3 * q]) * inv_np, s1 = sgn(n1 - target[3 * q + 1]) * inv_np,
+                 s2 = sgn(n2 - target[3 * q + 2]) * inv_np;
+    const double ns = n0 * s0 + n1 * s1 + n2 * s2;
+    const double sd = (ent & 1) ? inv : -inv;
+    g0 += (s0 - n0 * ns) * sd;
+    g1 += (s1 - n1 * ns) * sd;
+    g2 += (s2 - n2 * ns) * sd;
+  }
+  for (int k = 32; k > 0; k >>= 1) {
+    g0 += __shfl_xor(g0, k);
+    g1 += __shfl_xor(g1, k);
+    g2 += __shfl_xor(g2, k);
+  }
+  if (lane < 3) {
+    const double gk = lane == 0 ? g0 : (lane == 1 ? g1 : g2);
+    const int64_t a = base + 3 * c + lane;
+    const double mk = beta1 * m[a] + (1.0 - beta1) * gk;
+    const double vk = beta2 * v[a] + (1.0 - beta2) * gk * gk;
     m[a] = mk;
     v[a] = vk;
-    const double mh = mk / bc1, vh = vk / bc2;
+    const double mh = mk / (1.0 - b1t), vh = vk / (1.0 - b2t);
     o_out[a] = o_in[a] - lr * mh / (sqrt(vh) + eps);
   }
 }
@@ -339,7 +348,6 @@ __global__ __launch_bounds__(kTaThreads) void k_ta_step(int runs, int n_cams, in
 // One workgroup per run: centre at the origin, rescale to unit mean norm.
 __global__ __launch_bounds__(kTaThreads) void k_ta_align(int n_cams, double* __restrict__ o_all,
                                                          int32_t* __restrict__ err) {
-#pragma clang fp contract(off)
   __shared__ double red[3][kTaThreads];
   double* o = o_all + (int64_t)blockIdx.x * n_cams * 3;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -386,7 +394,6 @@ __global__ __launch_bounds__(kTaThreads) void k_ta_align(int n_cams, double* __r
 __global__ void k_ta_pair_loss(int runs, int n_cams, int64_t n_pairs, const int32_t* __restrict__ pair_i,
                                const int32_t* __restrict__ pair_j, const double* __restrict__ target,
                                const double* __restrict__ o_all, double* __restrict__ pair_loss) {
-#pragma clang fp contract(off)
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)runs * n_pairs) return;
   const int64_t r = idx / n_pairs, q = idx - r * n_pairs;
@@ -458,25 +465,36 @@ hipError_t launch_rt_pairs(hipStream_t st, int64_t n_pairs, const int32_t* pair_
   return hipGetLastError();
 }
 
-hipError_t launch_rt_score(hipStream_t st, int64_t n_items, int n_groups, const int4* items, const float* rowf,
-                           const float* x1, const float* y1, const float* x2, const float* y2, const float* cand,
-                           int kp, float* partial, hipEvent_t ev0, hipEvent_t ev1) {
-  if (n_items == 0) return hipSuccess;
+template <bool CAP>
+hipError_t launch_rt_score_t(hipStream_t st, int64_t n_items, int n_groups, const int4* items, const float* rowf,
+                             const float* x1, const float* y1, const float* x2, const float* y2, const float* cand,
+                             int kp, float tau, float* partial, hipEvent_t ev0, hipEvent_t ev1) {
   const dim3 grid((unsigned)(n_items * n_groups)), block(kRtThreads);
   if (ev0)
-    hipExtLaunchKernelGGL(k_rt_score, grid, block, 0, st, ev0, ev1, 0, items, n_groups, rowf, x1, y1, x2, y2, cand,
-                          kp, partial);
+    hipExtLaunchKernelGGL(k_rt_score<CAP>, grid, block, 0, st, ev0, ev1, 0, items, n_groups, rowf, x1, y1, x2, y2,
+                          cand, kp, tau, partial);
   else
-    k_rt_score<<<grid, block, 0, st>>>(items, n_groups, rowf, x1, y1, x2, y2, cand, kp, partial);
+    k_rt_score<CAP><<<grid, block, 0, st>>>(items, n_groups, rowf, x1, y1, x2, y2, cand, kp, tau, partial);
   return hipGetLastError();
 }
 
-hipError_t launch_rt_select(hipStream_t st, int64_t n_pairs, int k, int kp, const int32_t* pair_item_off,
+hipError_t launch_rt_score(hipStream_t st, int64_t n_items, int n_groups, const int4* items, const float* rowf,
+                           const float* x1, const float* y1, const float* x2, const float* y2, const float* cand,
+                           int kp, double tau, float* partial, hipEvent_t ev0, hipEvent_t ev1) {
+  if (n_items == 0) return hipSuccess;
+  if (std::isinf(tau))
+    return launch_rt_score_t<false>(st, n_items, n_groups, items, rowf, x1, y1, x2, y2, cand, kp, 0.f, partial, ev0,
+                                    ev1);
+  return launch_rt_score_t<true>(st, n_items, n_groups, items, rowf, x1, y1, x2, y2, cand, kp, (float)tau, partial,
+                                 ev0, ev1);
+}
+
+hipError_t launch_rt_select(hipStream_t st, int64_t n_pairs, int k, int kp, double tau, const int32_t* pair_item_off,
                             const int4* items, const float* partial, const float* cand, const double* rowd,
                             const float* x1, const float* y1, const float* x2, const float* y2, float* scores,
                             int32_t* best, int32_t* vote, double* t_rel, double* score_best) {
   if (n_pairs == 0) return hipSuccess;
-  k_rt_select<<<(unsigned)n_pairs, kRtThreads, 0, st>>>(k, kp, pair_item_off, items, partial, cand, rowd, x1, y1,
+  k_rt_select<<<(unsigned)n_pairs, kRtThreads, 0, st>>>(k, kp, tau, pair_item_off, items, partial, cand, rowd, x1, y1,
                                                         x2, y2, scores, best, vote, t_rel, score_best);
   return hipGetLastError();
 }
@@ -497,7 +515,7 @@ hipError_t launch_ta_step(hipStream_t st, int runs, int n_cams, int64_t n_pairs,
                           const int32_t* cam_ent, const int32_t* pair_i, const int32_t* pair_j,
                           const double* target, const double* o_in, double* o_out, double* m, double* v,
                           TaCounters* ctr, int parity, double beta1, double beta2, double eps, double decay) {
-  k_ta_step<<<blocks_for((int64_t)runs * n_cams, kTaThreads), kTaThreads, 0, st>>>(
+  k_ta_step<<<blocks_for((int64_t)runs * n_cams, kTaThreads / 64), kTaThreads, 0, st>>>(
       runs, n_cams, n_pairs, cam_off, cam_ent, pair_i, pair_j, target, o_in, o_out, m, v, ctr, parity, beta1, beta2,
       eps, decay);
   return hipGetLastError();

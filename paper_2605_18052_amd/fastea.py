@@ -101,7 +101,7 @@ _SIGNATURES = {
     "fea_hbm_probe": ([C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
     "fea_get_kernel_timing": ([_P, _P, _P], C.c_int),
     "fea_get_kernel_times": ([_P, _P, C.c_int64, _P], C.c_int),
-    "fea_relative_translations": ([_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P], C.c_int),
+    "fea_relative_translations": ([_P, _P, _P, C.c_double, C.c_int32, _P, _P, _P, _P, _P, _P, _P], C.c_int),
     "fea_ta_default_options": ([_P], C.c_int),
     "fea_translation_align": ([_P, C.c_int32, C.c_int64, _P, _P, _P, _P, C.c_int32, _P, _P, _P, _P, _P,
                                _P, _P, _P, _P], C.c_int),
@@ -393,9 +393,10 @@ class Context:
                                         f.ctypes.data_as(_P)))
         return R, t, f
 
-    def relative_translations(self, R, cand, f=None, scores=False, timing=False):
+    def relative_translations(self, R, cand, f=None, tau_px=math.inf, scores=False, timing=False):
         """Relative-translation candidate search over the loaded matches (see
-        fea_relative_translations).  R [N,3,3], cand [K,3] unit vectors.
+        fea_relative_translations).  R [N,3,3], cand [K,3] unit vectors,
+        tau_px the cap of each match's error in pixels (inf: plain mean).
         Returns t_rel [P,3], best [P], vote [P], score_best [P], optionally
         scores [P,K] (float32) and score_ms."""
         R, pR = _host(np.asarray(R).reshape(-1, 9), np.float64)
@@ -411,7 +412,7 @@ class Context:
         sc = np.zeros((max(P, 1), len(cand)), np.float32) if scores else None
         ms = C.c_float(0.0)
         self._check(lib().fea_relative_translations(
-            self._h, pR, pf, len(cand), pc, t_rel.ctypes.data_as(_P), best.ctypes.data_as(_P),
+            self._h, pR, pf, float(tau_px), len(cand), pc, t_rel.ctypes.data_as(_P), best.ctypes.data_as(_P),
             vote.ctypes.data_as(_P), sb.ctypes.data_as(_P),
             sc.ctypes.data_as(_P) if scores else None, C.byref(ms) if timing else None))
         out = dict(t_rel=t_rel[:P], best=best[:P], vote=vote[:P], score_best=sb[:P])

@@ -458,3 +458,24 @@ def relative_translations_gt(sc: "Scene", pair_cams: np.ndarray) -> np.ndarray:
     Rij = np.einsum("pab,pcb->pac", sc.R_gt[j], sc.R_gt[i])
     t = sc.t_gt[j] - np.einsum("pab,pb->pa", Rij, sc.t_gt[i])
     return t / np.linalg.norm(t, axis=1, keepdims=True)
+
+
+def object_pair_graph(n_cams: int = 500, angle_deg: float = 60.0, seed: int = 0, radius: float = 4.0):
+    """An object-centric capture's pair graph without matches: cameras at
+    seeded uniform directions on a sphere looking at the origin, pairs whose
+    viewing directions are less than angle_deg apart.  Returns pair_cams
+    int32 [P, 2] (i < j), world-to-camera rotations [N, 3, 3], the true unit
+    relative translations t^{i->j} [P, 3] (camera j frame) and the camera
+    centres [N, 3]."""
+    rng = np.random.default_rng(seed)
+    dirs = rng.normal(size=(n_cams, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    ii, jj = np.nonzero(np.triu(dirs @ dirs.T > np.cos(np.deg2rad(angle_deg)), 1))
+    pc = np.stack([ii, jj], 1).astype(np.int32)
+    c = radius * dirs
+    R = look_at(c, np.zeros(3))
+    t = -np.einsum("nij,nj->ni", R, c)
+    i, j = pc[:, 0], pc[:, 1]
+    Rij = np.einsum("pab,pcb->pac", R[j], R[i])
+    tij = t[j] - np.einsum("pab,pb->pa", Rij, t[i])
+    return pc, R, tij / np.linalg.norm(tij, axis=1, keepdims=True), c
