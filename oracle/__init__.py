@@ -1,6 +1,7 @@
-"""FP64 CPU oracle for FastMap epipolar adjustment and the Global
-Translation stages before it (relative-translation search, camera-centre
-alignment with multiple initialisations) (ctypes binding).
+"""FP64 CPU oracle for FastMap epipolar adjustment and the stages before it
+(focal-length vote, relative-translation search, camera-centre alignment
+with multiple initialisations).  The C parts go through ctypes; the focal
+vote is plain numpy (its singular values from numpy's SVD).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
 benchmark's CPU-baseline leg use it to check and time the GPU library.  The
@@ -432,3 +433,44 @@ def ta_solve(pair_cams, target, o_init, options=None):
         raise ValueError("oracle ta_solve failed")
     return dict(o=o, run_o=run_o, cam_loss=cam_loss, run_of_cam=run_of_cam, run_loss=run_loss,
                 final_loss=final.value)
+
+
+# ---- Focal Length Estimation ---------------------------------------------------
+
+def focal_vote(pair_cams, F, group, f_cur, cand_f, tau):
+    """Focal-length vote (Method > Focal Length Estimation,
+    Eq. fastmap-focal-vote), plain numpy.  For intrinsics group g and
+    candidate f: v_g(f) = sum over the pairs touching g of
+    exp((1 - s1/s2) / tau), s1 >= s2 the two largest singular values of
+    E = K_j^T F K_i with K = diag(f, f, 1) in centred pixel coordinates; the
+    cameras of group g take the candidate, the others their group's f_cur
+    (reading: with one group for all cameras this is the paper's
+    shared-intrinsics vote).  F [P, 3, 3] maps camera i's centred point to a
+    line of camera j (p_j^T F p_i = 0).  Returns votes [G, K] and the best
+    candidate per group (highest vote, ties: the lower index)."""
+    pc = np.asarray(pair_cams).reshape(-1, 2)
+    F = np.asarray(F, dtype=np.float64).reshape(-1, 3, 3)
+    group = np.asarray(group)
+    cand_f = np.asarray(cand_f, dtype=np.float64)
+    f_cur = np.asarray(f_cur, dtype=np.float64)
+    G = int(group.max()) + 1
+    votes = np.zeros((G, len(cand_f)))
+    gi, gj = group[pc[:, 0]], group[pc[:, 1]]
+    for g in range(G):
+        sel = np.nonzero((gi == g) | (gj == g))[0]
+        if len(sel) == 0:
+            continue
+        for k, f in enumerate(cand_f):
+            fi = np.where(gi[sel] == g, f, f_cur[gi[sel]])
+            fj = np.where(gj[sel] == g, f, f_cur[gj[sel]])
+            Ki = np.zeros((len(sel), 3, 3))
+            Kj = np.zeros((len(sel), 3, 3))
+            Ki[:, 0, 0] = Ki[:, 1, 1] = fi
+            Kj[:, 0, 0] = Kj[:, 1, 1] = fj
+            Ki[:, 2, 2] = Kj[:, 2, 2] = 1.0
+            E = np.transpose(Kj, (0, 2, 1)) @ F[sel] @ Ki
+            s = np.linalg.svd(E, compute_uv=False)
+            ratio = np.where(s[:, 1] > 0, s[:, 0] / np.where(s[:, 1] > 0, s[:, 1], 1.0), np.inf)
+            votes[g, k] = np.sum(np.exp((1.0 - ratio) / tau))
+    best = cand_f[np.argmax(votes, axis=1)]  # argmax takes the first of equal maxima
+    return votes, best

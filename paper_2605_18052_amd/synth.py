@@ -479,3 +479,35 @@ def object_pair_graph(n_cams: int = 500, angle_deg: float = 60.0, seed: int = 0,
     Rij = np.einsum("pab,pcb->pac", R[j], R[i])
     tij = t[j] - np.einsum("pab,pb->pa", Rij, t[i])
     return pc, R, tij / np.linalg.norm(tij, axis=1, keepdims=True), c
+
+
+def fundamental_matrices(sc: "Scene", pair_cams: np.ndarray, noise: float = 0.0, seed: int = 0) -> np.ndarray:
+    """Fundamental matrices of the given pairs from the scene's true poses and
+    focal lengths, in centred pixel coordinates (p_j^T F p_i = 0 with
+    p = (x - cx, y - cy, 1)), each scaled to unit Frobenius norm.  With noise,
+    the essential matrix (unit Frobenius norm, calibrated coordinates, where
+    all entries have comparable scale) gets seeded Gaussian noise of that
+    size on every entry and is projected back to rank 2 before the focal
+    lengths are applied.  float64 [P, 3, 3]."""
+    i, j = pair_cams[:, 0], pair_cams[:, 1]
+    Rij = np.einsum("pab,pcb->pac", sc.R_gt[j], sc.R_gt[i])
+    t = sc.t_gt[j] - np.einsum("pab,pb->pa", Rij, sc.t_gt[i])
+    tx = np.zeros((len(t), 3, 3))
+    tx[:, 0, 1], tx[:, 0, 2], tx[:, 1, 2] = -t[:, 2], t[:, 1], -t[:, 0]
+    tx[:, 1, 0], tx[:, 2, 0], tx[:, 2, 1] = t[:, 2], -t[:, 1], t[:, 0]
+    E = tx @ Rij
+    E /= np.linalg.norm(E, axis=(1, 2), keepdims=True)
+    if noise > 0:
+        E = E + noise * np.random.default_rng(seed).normal(size=E.shape)
+        U, s, Vt = np.linalg.svd(E)
+        s[:, 2] = 0.0
+        E = U @ (s[:, :, None] * Vt)
+    di = np.stack([1 / sc.f_gt[i], 1 / sc.f_gt[i], np.ones(len(i))], 1)
+    dj = np.stack([1 / sc.f_gt[j], 1 / sc.f_gt[j], np.ones(len(j))], 1)
+    F = dj[:, :, None] * E * di[:, None, :]
+    return F / np.linalg.norm(F, axis=(1, 2), keepdims=True)
+
+
+def focal_candidates(n: int, lo: float = 100.0, hi: float = 5000.0) -> np.ndarray:
+    """n focal lengths spaced evenly in log between lo and hi (pixels)."""
+    return np.exp(np.linspace(np.log(lo), np.log(hi), n))
