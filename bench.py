@@ -15,11 +15,12 @@ Prints ONE JSON line on stdout (progress goes to stderr):
   cpu_baseline the FP64 oracle timed on the host on a 6M-match sample
   solve       wall time until the mean rotation error first drops to <= 1 deg,
               with the per-match inner loop and with the pairs' quadratic forms
-  translation the Global Translation stages before the adjustment: the
-              relative-translation candidate search over the same scene's
-              matches (its scoring kernel against the fp32 matrix-core peak)
-              and the multi-start camera-centre alignment on a 500-camera
-              object-centric pair graph, each with the oracle timed beside it
+  translation the stages before the adjustment: the focal-length vote on the
+              scene's pair graph, the relative-translation candidate search
+              over the same scene's matches (its scoring kernel against its
+              roofline) and the multi-start camera-centre alignment on a
+              500-camera object-centric pair graph, each with the oracle
+              timed beside it
 """
 from __future__ import annotations
 
@@ -331,7 +332,28 @@ def translation_stages(sc, fastea, synth, n_cand, with_cpu, cap_px=32.0, cpu_pai
              "us_per_step": 1e3 * float(np.median(a_ms)) / steps, "final_loss": a["final_loss"],
              "centre_error_median": float(np.median(np.linalg.norm(a["o"] - truth, axis=1))),
              "bound": "latency: O(runs x pairs) fp64 work per step, one wave per (run, camera)"}
-    out = {"relative_translations": search, "alignment": align}
+    # focal-length vote on the same scene's pair graph: one group per camera,
+    # the others at their initial focal lengths, 1% noise on the true
+    # essential matrices, 1,024 candidates from 200 to 3,000 px
+    fF = synth.fundamental_matrices(sc, pc, noise=1e-2, seed=1)
+    fcand = synth.focal_candidates(1024, 200.0, 3000.0)
+    groups = np.arange(sc.n_cams, dtype=np.int32)
+    fctx = fastea.Context(0)
+    fctx.focal_vote(sc.n_cams, pc, fF, fcand, 0.05, group=groups, f_cur=sc.f_init)
+    f_ms = []
+    for _ in range(reps):
+        fv = fctx.focal_vote(sc.n_cams, pc, fF, fcand, 0.05, group=groups, f_cur=sc.f_init)
+        f_ms.append(fv["ms"])
+    fctx.close()
+    n_eval = 2 * len(pc) * len(fcand)  # each pair votes for both of its cameras' groups
+    ratio = fv["f_best"] / sc.f_gt
+    focal = {"cameras": sc.n_cams, "pairs": int(len(pc)), "candidates": len(fcand), "tau": 0.05,
+             "kernel": "k_fv_vote", "kernel_ms": float(np.median(f_ms)),
+             "matrices_per_s": n_eval / (float(np.median(f_ms)) / 1e3),
+             "bound": "latency: one wave per (camera, candidate) over ~20 pairs, fp64 closed-form 3x3",
+             "f_best_over_true_median": float(np.median(ratio)),
+             "within_5pct": float(np.mean(np.abs(ratio - 1) < 0.05))}
+    out = {"relative_translations": search, "alignment": align, "focal_vote": focal}
     if with_cpu:
         import oracle
         oracle.build(force=False)
@@ -354,6 +376,15 @@ def translation_stages(sc, fastea, synth, n_cand, with_cpu, cap_px=32.0, cpu_pai
             "kind": "oracle",
             "sample": f"{len(sel_pairs)} random pairs ({len(sel)} matches) x {n_cand} candidates, FP64 C "
                       f"oracle (OpenMP over pairs), {dt:.1f} s wall"}
+        keep = (pc[:, 0] < 50) & (pc[:, 1] < 50)  # the pairs among the first 50 cameras
+        t2 = time.perf_counter()
+        oracle.focal_vote(pc[keep], fF[keep], groups, sc.f_init, fcand, 0.05)
+        dt2 = time.perf_counter() - t2
+        focal["cpu_baseline"] = {"value": 2 * int(keep.sum()) * len(fcand) / dt2, "unit": "matrices/s", "cores": 1,
+                                 "kind": "oracle",
+                                 "sample": f"the per-camera votes over the {int(keep.sum())} pairs among 50 "
+                                           f"cameras x {len(fcand)} candidates in the numpy oracle, "
+                                           f"{dt2:.1f} s wall"}
         align["cpu_baseline"] = {"value": 1e3 * dt1, "unit": "ms", "cores": 1, "kind": "oracle",
                                  "sample": "the same alignment (2 runs, default schedule) in the FP64 C "
                                            f"oracle, one thread, {dt1:.1f} s wall"}
@@ -470,6 +501,9 @@ def main():
         translation = translation_stages(sc, fastea, synth, args.candidates, not args.no_cpu,
                                          args.search_cap_px, args.search_cpu_pairs)
         rt, al = translation["relative_translations"], translation["alignment"]
+        fv = translation["focal_vote"]
+        log(f"[bench] focal vote: {fv['kernel_ms']:.3f} ms for {fv['cameras']} cameras x {fv['candidates']} "
+            f"candidates, {fv['within_5pct']:.2f} of the cameras within 5%")
         log(f"[bench] search: k_rt_score {rt['kernel_ms']:.3f} ms = {rt['roofline']['achieved']:.2f} "
             f"{rt['roofline']['unit']} ({rt['roofline']['frac']:.3f} of the {rt['roofline']['bound']} peak), "
             f"median direction error "

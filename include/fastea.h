@@ -395,6 +395,32 @@ fea_status fea_get_kernel_times(fea_ctx *ctx, float *ms, int64_t cap, int64_t *n
  * (k+1)*log_every, counting steps across rounds. */
 fea_status fea_get_rotation_log(fea_ctx *ctx, double *R_log, int32_t *n_logged);
 
+/* ---- Focal-length vote (Method > Focal Length Estimation) ---------------
+ * Eq. fastmap-focal-vote: a 3x3 matrix is essential exactly when its two
+ * non-zero singular values are equal, so a candidate focal length f scores
+ *   v(f) = sum over pairs of exp((1 - s1/s2) / tau),
+ * s1 >= s2 the two largest singular values of E = K_j^T F K_i with
+ * K = diag(f, f, 1) in centred pixel coordinates.  Per intrinsics group g
+ * (group [n_cams], NULL = one group for every camera, the paper's shared
+ * intrinsics): the pairs with a camera in g vote; g's cameras take the
+ * candidate, every other camera keeps its group's f_cur (one sweep of
+ * per-camera votes when every camera is its own group).  The best candidate
+ * per group has the highest vote (ties: the lower index).  Inputs (host,
+ * copied): pair_i, pair_j [n_pairs] (cameras in [0, n_cams), i != j),
+ * F [n_pairs*9] row-major with p_j^T F p_i = 0 for centred pixel coordinates
+ * p = (x - cx, y - cy, 1) (any scale or sign), f_cur [n_groups] (required
+ * with more than one group), cand_f [n_cand] > 0, tau > 0.  Outputs (host):
+ * f_best [n_groups], k_best [n_groups] (nullable), votes
+ * [n_groups*n_cand] (nullable), ms (nullable: the vote kernel's HIP-event
+ * time).  fp64 throughout; the singular-value ratio comes from the closed-form
+ * eigenvalues of E^T E, which fix it to ~1.5e-8 near equal values.  The
+ * context only supplies device, stream and error message.  FEA_EINVAL for
+ * invalid sizes, pairs, groups or values; FEA_ENONFINITE for a non-finite F. */
+fea_status fea_focal_vote(fea_ctx *ctx, int32_t n_cams, int64_t n_pairs, const int32_t *pair_i,
+                          const int32_t *pair_j, const double *F, const int32_t *group, const double *f_cur,
+                          int32_t n_cand, const double *cand_f, double tau, double *f_best, int32_t *k_best,
+                          double *votes, float *ms);
+
 /* ---- Global Translation (the stages before epipolar adjustment) ---------
  * Relative translations (Method > Global Translation > Relative
  * translation): with the global rotations fixed, every image pair of the

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "fea_ctx.h"
+#include "fea_focal.h"
 #include "fea_trans.h"
 
 using fea::DBuf;
@@ -2258,6 +2259,85 @@ fea_status fea_translation_align(fea_ctx* c, int32_t n_cams, int64_t n_pairs, co
   HIP_OR_FAIL(c, e);
   if (herr) return fail(c, FEA_EDEGENERATE, "all camera centres coincide");
   if (final_loss) *final_loss = hfl;
+  return FEA_OK;
+}
+
+fea_status fea_focal_vote(fea_ctx* c, int32_t n_cams, int64_t n_pairs, const int32_t* pair_i,
+                          const int32_t* pair_j, const double* F, const int32_t* group, const double* f_cur,
+                          int32_t n_cand, const double* cand_f, double tau, double* f_best, int32_t* k_best,
+                          double* votes, float* ms) {
+  if (!c) return FEA_EINVAL;
+  if (!pair_i || !pair_j || !F || !cand_f || !f_best)
+    return fail(c, FEA_EINVAL, "pair_i, pair_j, F, cand_f and f_best are required");
+  if (n_cams < 2 || n_pairs < 1 || n_pairs > INT32_MAX) return fail(c, FEA_EINVAL, "need n_cams >= 2 and n_pairs >= 1");
+  if (n_cand < 1 || n_cand > (1 << 20)) return fail(c, FEA_EINVAL, "n_cand must be in [1, 2^20]");
+  if (!std::isfinite(tau) || !(tau > 0.0)) return fail(c, FEA_EINVAL, "tau must be finite and > 0");
+  std::vector<int32_t> grp(group ? group : nullptr, group ? group + n_cams : nullptr);
+  if (!group) grp.assign((size_t)n_cams, 0);
+  int32_t G = 0;
+  for (int32_t g : grp) {
+    if (g < 0 || g >= n_cams) return fail(c, FEA_EINVAL, "group ids must be in [0, n_cams)");
+    G = std::max(G, g + 1);
+  }
+  std::vector<double> fc((size_t)G, 1.0);
+  if (G > 1) {
+    if (!f_cur) return fail(c, FEA_EINVAL, "f_cur is required with more than one group");
+    for (int32_t g = 0; g < G; ++g) {
+      if (!std::isfinite(f_cur[g]) || !(f_cur[g] > 0.0)) return fail(c, FEA_EINVAL, "f_cur must be finite and > 0");
+      fc[g] = f_cur[g];
+    }
+  }
+  for (int32_t k = 0; k < n_cand; ++k)
+    if (!std::isfinite(cand_f[k]) || !(cand_f[k] > 0.0))
+      return fail(c, FEA_EINVAL, "candidate focal lengths must be finite and > 0");
+  if (!all_finite(F, (size_t)9 * n_pairs)) return fail(c, FEA_ENONFINITE, "non-finite fundamental matrix");
+  // group -> its pairs, in pair order (a pair within one group is listed once)
+  std::vector<int32_t> off((size_t)G + 1, 0), lst;
+  for (int64_t p = 0; p < n_pairs; ++p) {
+    const int32_t i = pair_i[p], j = pair_j[p];
+    if (i < 0 || j < 0 || i >= n_cams || j >= n_cams || i == j) return fail(c, FEA_EINVAL, "invalid camera pair");
+    off[grp[i] + 1]++;
+    if (grp[j] != grp[i]) off[grp[j] + 1]++;
+  }
+  for (int32_t g = 0; g < G; ++g) off[g + 1] += off[g];
+  lst.assign((size_t)off[G], 0);
+  std::vector<int32_t> fill(off.begin(), off.end() - 1);
+  for (int64_t p = 0; p < n_pairs; ++p) {
+    const int32_t gi = grp[pair_i[p]], gj = grp[pair_j[p]];
+    lst[fill[gi]++] = (int32_t)p;
+    if (gj != gi) lst[fill[gj]++] = (int32_t)p;
+  }
+  DeviceGuard dg(c->device);
+  CallScratch sc(c->stream);
+  int32_t *dpi, *dpj, *dgrp, *doff, *dlst, *dkb;
+  double *dF, *dfc, *dcand, *dvotes, *dfb;
+  HIP_OR_FAIL(c, sc.put(dpi, pair_i, (size_t)n_pairs));
+  HIP_OR_FAIL(c, sc.put(dpj, pair_j, (size_t)n_pairs));
+  HIP_OR_FAIL(c, sc.put(dgrp, grp.data(), grp.size()));
+  HIP_OR_FAIL(c, sc.put(doff, off.data(), off.size()));
+  HIP_OR_FAIL(c, sc.put(dlst, lst.data(), lst.size()));
+  HIP_OR_FAIL(c, sc.put(dF, F, (size_t)9 * n_pairs));
+  HIP_OR_FAIL(c, sc.put(dfc, fc.data(), fc.size()));
+  HIP_OR_FAIL(c, sc.put(dcand, cand_f, (size_t)n_cand));
+  HIP_OR_FAIL(c, sc.alloc(dvotes, (size_t)G * n_cand));
+  HIP_OR_FAIL(c, sc.alloc(dfb, (size_t)G));
+  HIP_OR_FAIL(c, sc.alloc(dkb, (size_t)G));
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (ms) {
+    HIP_OR_FAIL(c, hipEventCreate(&ev[0]));
+    HIP_OR_FAIL(c, hipEventCreate(&ev[1]));
+  }
+  hipError_t e = fea::launch_fv_vote(c->stream, G, n_cand, doff, dlst, dpi, dpj, dgrp, dF, dfc, dcand, tau, dvotes,
+                                     ev[0], ev[1]);
+  if (e == hipSuccess) e = fea::launch_fv_best(c->stream, G, n_cand, dvotes, dcand, dfb, dkb);
+  if (e == hipSuccess) e = fetch(c->stream, f_best, dfb, (size_t)G);
+  if (e == hipSuccess) e = fetch(c->stream, k_best, dkb, (size_t)G);
+  if (e == hipSuccess) e = fetch(c->stream, votes, dvotes, (size_t)G * n_cand);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && ms) e = hipEventElapsedTime(ms, ev[0], ev[1]);
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  HIP_OR_FAIL(c, e);
   return FEA_OK;
 }
 

@@ -103,6 +103,8 @@ _SIGNATURES = {
     "fea_get_kernel_times": ([_P, _P, C.c_int64, _P], C.c_int),
     "fea_relative_translations": ([_P, _P, _P, C.c_double, C.c_int32, _P, _P, _P, _P, _P, _P, _P], C.c_int),
     "fea_ta_default_options": ([_P], C.c_int),
+    "fea_focal_vote": ([_P, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32, _P, C.c_double, _P, _P, _P,
+                        _P], C.c_int),
     "fea_translation_align": ([_P, C.c_int32, C.c_int64, _P, _P, _P, _P, C.c_int32, _P, _P, _P, _P, _P,
                                _P, _P, _P, _P], C.c_int),
 }
@@ -449,6 +451,35 @@ class Context:
         out = dict(o=o, run_of_cam=run_of_cam, run_loss=run_loss, final_loss=final.value, ms=ms.value)
         if details:
             out.update(run_o=run_o, cam_loss=cam_loss)
+        return out
+
+    def focal_vote(self, n_cams, pair_cams, F, cand_f, tau, group=None, f_cur=None, votes=False):
+        """Focal-length vote (see fea_focal_vote).  pair_cams [P,2], F [P,3,3]
+        in centred pixel coordinates, cand_f [K]; group [N] (None: one group),
+        f_cur [G].  Returns f_best [G], k_best [G], optionally votes [G,K], and
+        the vote kernel's ms."""
+        pc = np.ascontiguousarray(np.asarray(pair_cams).reshape(-1, 2), np.int32)
+        pi, ppi = _host(pc[:, 0], np.int32)
+        pj, ppj = _host(pc[:, 1], np.int32)
+        F, pF = _host(np.asarray(F).reshape(-1, 9), np.float64)
+        cand, pc_ = _host(cand_f, np.float64)
+        pg = pfc = None
+        G = 1
+        if group is not None:
+            group, pg = _host(group, np.int32)
+            G = int(group.max()) + 1
+        if f_cur is not None:
+            f_cur, pfc = _host(f_cur, np.float64)
+        fb = np.zeros(G)
+        kb = np.zeros(G, np.int32)
+        v = np.zeros((G, len(cand))) if votes else None
+        ms = C.c_float(0.0)
+        self._check(lib().fea_focal_vote(self._h, int(n_cams), len(pc), ppi, ppj, pF, pg, pfc, len(cand), pc_,
+                                         float(tau), fb.ctypes.data_as(_P), kb.ctypes.data_as(_P),
+                                         v.ctypes.data_as(_P) if votes else None, C.byref(ms)))
+        out = dict(f_best=fb, k_best=kb, ms=ms.value)
+        if votes:
+            out["votes"] = v
         return out
 
     def info(self) -> dict:
