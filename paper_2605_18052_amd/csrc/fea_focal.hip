@@ -7,8 +7,10 @@
 // K = diag(f, f, 1) in centred pixel coordinates.  Per intrinsics group g the
 // group's cameras take the candidate and every other camera keeps its
 // group's current focal length; with one group this is the shared-intrinsics
-// vote.  One wave per (group, candidate): the lanes take the group's pairs in
-// pair order, a fixed-order wave sum adds them (no atomics).  The singular
+// vote.  One wave per (group, 64 candidates): each lane holds one candidate
+// and walks the group's pairs in pair order with the rest of the wave (the
+// pair's data is the same for every lane), so every lane works and the sum
+// of each candidate is a plain serial one (no atomics).  The singular
 // values come from the eigenvalues of the symmetric E^T E in closed form
 // (the trigonometric solution of its characteristic cubic), all in fp64:
 // the work is tiny (pairs x candidates 3x3 problems) and latency-bound.
@@ -63,12 +65,13 @@ __global__ __launch_bounds__(kFvThreads) void k_fv_vote(int n_groups, int n_cand
                                                         const double* __restrict__ cand, double inv_tau,
                                                         double* __restrict__ votes) {
   const int lane = threadIdx.x & 63;
+  const int nb = (n_cand + 63) >> 6;
   const int64_t w = (int64_t)blockIdx.x * (kFvThreads / 64) + (threadIdx.x >> 6);
-  if (w >= (int64_t)n_groups * n_cand) return;
-  const int g = (int)(w / n_cand), k = (int)(w - (int64_t)g * n_cand);
-  const double f = cand[k];
+  if (w >= (int64_t)n_groups * nb) return;
+  const int g = (int)(w / nb), k = (int)(w - (int64_t)g * nb) * 64 + lane;
+  const double f = cand[k < n_cand ? k : n_cand - 1];
   double s = 0.0;
-  for (int e = grp_off[g] + lane; e < grp_off[g + 1]; e += 64) {
+  for (int e = grp_off[g]; e < grp_off[g + 1]; ++e) {  // the pair is the same for the whole wave
     const int p = grp_pairs[e];
     const int i = pair_i[p], j = pair_j[p];
     const int gi = group[i], gj = group[j];
@@ -81,8 +84,7 @@ __global__ __launch_bounds__(kFvThreads) void k_fv_vote(int n_groups, int n_cand
       for (int cc = 0; cc < 3; ++cc) E[3 * r + cc] = sj[r] * Fp[3 * r + cc] * si[cc];
     s += exp((1.0 - sv_ratio(E)) * inv_tau);
   }
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) votes[w] = s;
+  if (k < n_cand) votes[(int64_t)g * n_cand + k] = s;
 }
 
 // Per group: the candidate with the highest vote (ties: the lower index).
@@ -125,7 +127,7 @@ hipError_t launch_fv_vote(hipStream_t st, int n_groups, int n_cand, const int32_
                           const int32_t* pair_i, const int32_t* pair_j, const int32_t* group, const double* F,
                           const double* f_cur, const double* cand, double tau, double* votes, hipEvent_t ev0,
                           hipEvent_t ev1) {
-  const int64_t waves = (int64_t)n_groups * n_cand;
+  const int64_t waves = (int64_t)n_groups * ((n_cand + 63) / 64);
   const dim3 grid((unsigned)((waves + kFvThreads / 64 - 1) / (kFvThreads / 64))), block(kFvThreads);
   if (ev0)
     hipExtLaunchKernelGGL(k_fv_vote, grid, block, 0, st, ev0, ev1, 0, n_groups, n_cand, grp_off, grp_pairs, pair_i,
