@@ -1,7 +1,8 @@
 """FP64 CPU oracle for FastMap epipolar adjustment and the stages before it
-(focal-length vote, relative-translation search, camera-centre alignment
-with multiple initialisations).  The C parts go through ctypes; the focal
-vote is plain numpy (its singular values from numpy's SVD).
+(focal-length vote, global rotation, relative-translation search,
+camera-centre alignment with multiple initialisations).  The C parts go
+through ctypes; the focal vote and the global rotation are plain numpy
+(singular values from numpy's SVD, eigenvectors from its eigh).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
 benchmark's CPU-baseline leg use it to check and time the GPU library.  The
@@ -474,3 +475,84 @@ def focal_vote(pair_cams, F, group, f_cur, cand_f, tau):
             votes[g, k] = np.sum(np.exp((1.0 - ratio) / tau))
     best = cand_f[np.argmax(votes, axis=1)]  # argmax takes the first of equal maxima
     return votes, best
+
+
+# ---- Global Rotation -----------------------------------------------------------
+
+def geodesic(Ra, Rb):
+    """d(Ra, Rb) = arccos((tr(Ra^T Rb) - 1) / 2), the argument clamped to
+    [-1, 1] (Global Rotation; reading: clamp)."""
+    x = (np.einsum("...ab,...ab->...", Ra, Rb) - 1.0) / 2.0
+    return np.arccos(np.clip(x, -1.0, 1.0))
+
+
+def ra_loss_grad(pair_cams, R_rel, a6):
+    """Eq. fastmap-rotation-objective: L_R = (1/|P|) sum d(R_j, R^{i->j} R_i)
+    over the pairs, R_i from the 6D parameters a6 [N, 6] (columns a1, a2;
+    Gram-Schmidt).  Returns L_R and dL_R/da6 [N, 6].  The derivative of
+    arccos is taken where its argument lies strictly inside (-1, 1) and is
+    zero elsewhere (a pair already at distance 0 or pi)."""
+    pc = np.asarray(pair_cams).reshape(-1, 2)
+    a6 = _f64(a6).reshape(-1, 6)
+    N, P = len(a6), len(pc)
+    R = np.stack([rot6d_to_R(a6[k]) for k in range(N)])
+    Rr = _f64(R_rel).reshape(-1, 3, 3)
+    i, j = pc[:, 0], pc[:, 1]
+    Ri_t = Rr @ R[i]  # the prediction of R_j
+    x = (np.einsum("pab,pab->p", R[j], Ri_t) - 1.0) / 2.0
+    L = np.sum(np.arccos(np.clip(x, -1.0, 1.0))) / P
+    inside = np.abs(x) < 1.0
+    dx = np.where(inside, -1.0 / np.sqrt(np.where(inside, 1.0 - x * x, 1.0)), 0.0) / P
+    # tr(R_j^T R_rel R_i): d/dR_j = R_rel R_i, d/dR_i = R_rel^T R_j; x = (tr - 1)/2
+    gR = np.zeros((N, 3, 3))
+    np.add.at(gR, j, 0.5 * dx[:, None, None] * Ri_t)
+    np.add.at(gR, i, 0.5 * dx[:, None, None] * (np.transpose(Rr, (0, 2, 1)) @ R[j]))
+    g6 = np.stack([rot6d_backward(a6[k], gR[k].ravel()) for k in range(N)])
+    return L, g6
+
+
+def ra_init(pair_cams, R_rel, n_cams):
+    """Initialisation (Global Rotation > Initialization details, after
+    Martinec and Pajdla): the first columns c1 minimise
+    sum |c1_j - R^{i->j} c1_i|^2 over unit-norm stacked vectors (the smallest
+    eigenvector of the 3N x 3N normal matrix, numpy's eigh), each then
+    normalised; the second columns minimise the same over the pairs / |P|
+    plus sum (c1_i^T c2_i)^2 / |I|, then are normalised and made orthogonal
+    to c1 (Gram-Schmidt); the third column is c1 x c2.  Returns a6 [N, 6]
+    (c1, c2) and R [N, 3, 3]."""
+    pc = np.asarray(pair_cams).reshape(-1, 2)
+    Rr = _f64(R_rel).reshape(-1, 3, 3)
+    N, P = n_cams, len(pc)
+    M = np.zeros((3 * N, 3 * N))
+    for p, (i, j) in enumerate(pc):
+        A = np.zeros((3, 3 * N))
+        A[:, 3 * j:3 * j + 3] = np.eye(3)
+        A[:, 3 * i:3 * i + 3] = -Rr[p]
+        M += A.T @ A
+    _, V = np.linalg.eigh(M)
+    c1 = V[:, 0].reshape(N, 3)
+    c1 /= np.linalg.norm(c1, axis=1, keepdims=True)
+    B = np.zeros((3 * N, 3 * N))
+    for k in range(N):
+        B[3 * k:3 * k + 3, 3 * k:3 * k + 3] = np.outer(c1[k], c1[k])
+    _, V2 = np.linalg.eigh(M / P + B / N)
+    c2 = V2[:, 0].reshape(N, 3)
+    c2 -= np.sum(c1 * c2, axis=1, keepdims=True) * c1
+    c2 /= np.linalg.norm(c2, axis=1, keepdims=True)
+    a6 = np.concatenate([c1, c2], axis=1)
+    return a6, np.stack([rot6d_to_R(a6[k]) for k in range(N)])
+
+
+def ra_solve(pair_cams, R_rel, a6_0, iters=1000, lr=1e-2, lr_end_frac=1e-2, beta1=0.9, beta2=0.999,
+             eps=1e-12):
+    """Adam on the 6D parameters of L_R from a6_0 (reading: the learning rate
+    of step k is lr * lr_end_frac^(k/iters)).  Returns a6, R and the loss."""
+    a6 = _f64(a6_0).reshape(-1, 6).copy()
+    m = np.zeros(a6.size)
+    v = np.zeros(a6.size)
+    for k in range(iters):
+        _, g = ra_loss_grad(pair_cams, R_rel, a6)
+        p, m, v = adam(a6.ravel(), m, v, g.ravel(), k + 1, lr * lr_end_frac ** (k / iters), beta1, beta2, eps)
+        a6 = p.reshape(-1, 6)
+    L, _ = ra_loss_grad(pair_cams, R_rel, a6)
+    return a6, np.stack([rot6d_to_R(a6[k]) for k in range(len(a6))]), L
