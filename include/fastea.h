@@ -395,6 +395,45 @@ fea_status fea_get_kernel_times(fea_ctx *ctx, float *ms, int64_t cap, int64_t *n
  * (k+1)*log_every, counting steps across rounds. */
 fea_status fea_get_rotation_log(fea_ctx *ctx, double *R_log, int32_t *n_logged);
 
+/* ---- Global rotation (Method > Global Rotation) --------------------------
+ * Eq. fastmap-rotation-objective: world-to-camera rotations R_i minimising
+ *   L_R = (1/|P|) sum over pairs of d(R_j, R^{i->j} R_i),
+ * d(R, R') = arccos((tr(R^T R') - 1)/2) (argument clamped to [-1, 1]), by
+ * Adam on the 6D parameterisation (bias-corrected; the learning rate of step
+ * k of T is lr * lr_end_frac^(k/T); the arccos derivative is taken where its
+ * argument is strictly inside (-1, 1), zero elsewhere).  Initialisation
+ * (after Martinec and Pajdla, as the paper modifies it): the first columns
+ * minimise sum |c_j - R^{i->j} c_i|^2 over unit-norm stacked vectors, the
+ * second columns the same over |P| plus sum (c1_i . c2_i)^2 / |I|, each by
+ * init_iters power iterations from the caller's random start vectors v0
+ * [2 * n_cams * 3] (any vector in the near-null space of the first problem
+ * is a valid first column: the rotations are fixed up to one global
+ * rotation), normalised per camera, the second made orthogonal to the
+ * first; the third column is their cross product.  With a6_init
+ * [n_cams * 6] (nullable) the initialisation is skipped and the
+ * optimisation starts there.  Inputs (host, copied): pair_i, pair_j
+ * [n_pairs] (cameras in [0, n_cams), i != j), R_rel [n_pairs*9] row-major
+ * with R_j ~ R_rel R_i.  Outputs (host): R_out [n_cams*9], R_init [n_cams*9]
+ * (nullable: the rotations the optimisation starts from), loss [2]
+ * (nullable: L_R at the start and the end), ms (nullable: device time of the
+ * call, HIP events).  FEA_EINVAL for invalid sizes, pairs or options;
+ * FEA_ENONFINITE for non-finite input; FEA_EDEGENERATE if a camera's column
+ * vanishes in the initialisation (a camera without pairs).  Device scratch of
+ * O(n_cams + n_pairs) is allocated and freed by the call. */
+typedef struct {
+  int32_t init_iters; /* power iterations per column (default 5000) */
+  int32_t iters;      /* Adam steps (1000) */
+  double lr;          /* first learning rate (1e-2) */
+  double lr_end_frac; /* last over first learning rate (1e-2) */
+  double beta1, beta2, adam_eps; /* 0.9, 0.999, 1e-12 */
+} fea_ra_options;
+
+fea_status fea_ra_default_options(fea_ra_options *out);
+fea_status fea_rotation_averaging(fea_ctx *ctx, int32_t n_cams, int64_t n_pairs, const int32_t *pair_i,
+                                  const int32_t *pair_j, const double *R_rel, const double *v0,
+                                  const double *a6_init, const fea_ra_options *opt, double *R_out,
+                                  double *R_init, double *loss, float *ms);
+
 /* ---- Focal-length vote (Method > Focal Length Estimation) ---------------
  * Eq. fastmap-focal-vote: a 3x3 matrix is essential exactly when its two
  * non-zero singular values are equal, so a candidate focal length f scores

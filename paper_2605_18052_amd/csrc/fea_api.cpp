@@ -20,6 +20,7 @@
 
 #include "fea_ctx.h"
 #include "fea_focal.h"
+#include "fea_rotation.h"
 #include "fea_trans.h"
 
 using fea::DBuf;
@@ -2338,6 +2339,180 @@ fea_status fea_focal_vote(fea_ctx* c, int32_t n_cams, int64_t n_pairs, const int
   for (hipEvent_t x : ev)
     if (x) (void)hipEventDestroy(x);
   HIP_OR_FAIL(c, e);
+  return FEA_OK;
+}
+
+fea_status fea_ra_default_options(fea_ra_options* o) {
+  if (!o) return FEA_EINVAL;
+  o->init_iters = 5000;
+  o->iters = 1000;
+  o->lr = 1e-2;
+  o->lr_end_frac = 1e-2;
+  o->beta1 = 0.9;
+  o->beta2 = 0.999;
+  o->adam_eps = 1e-12;
+  return FEA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Runs `iters` iterations of `step` (which flips `parity`), an even number
+// at a time from a captured graph, the rest launched directly.
+template <class Step>
+hipError_t run_captured(hipStream_t st, int iters, int& parity, Step step) {
+  constexpr int kChunk = 64;
+  int done = 0;
+  if (iters >= 2 * kChunk) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    const int p0 = parity;
+    for (int k = 0; k < kChunk && le == hipSuccess; ++k) le = step();
+    e = hipStreamEndCapture(st, &g);
+    parity = p0;
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    for (; e == hipSuccess && done + kChunk <= iters; done += kChunk) e = hipGraphLaunch(x, st);
+    if (x) (void)hipGraphExecDestroy(x);
+    if (e != hipSuccess) return e;
+  }
+  for (; done < iters; ++done) {
+    hipError_t e = step();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+fea_status fea_rotation_averaging(fea_ctx* c, int32_t n_cams, int64_t n_pairs, const int32_t* pair_i,
+                                  const int32_t* pair_j, const double* R_rel, const double* v0,
+                                  const double* a6_init, const fea_ra_options* opt, double* R_out, double* R_init,
+                                  double* loss, float* ms) {
+  if (!c) return FEA_EINVAL;
+  if (!pair_i || !pair_j || !R_rel || !R_out || (!v0 && !a6_init))
+    return fail(c, FEA_EINVAL, "pair_i, pair_j, R_rel, R_out and v0 (or a6_init) are required");
+  if (n_cams < 2 || n_pairs < 1 || n_pairs > INT32_MAX / 2)
+    return fail(c, FEA_EINVAL, "need n_cams >= 2 and 1 <= n_pairs < 2^30");
+  fea_ra_options o;
+  fea_ra_default_options(&o);
+  if (opt) o = *opt;
+  if (o.init_iters < 0 || o.iters < 0 || !(o.lr > 0) || !(o.lr_end_frac > 0) || !(o.lr_end_frac <= 1) ||
+      !(o.beta1 >= 0 && o.beta1 < 1) || !(o.beta2 >= 0 && o.beta2 < 1) || !(o.adam_eps >= 0))
+    return fail(c, FEA_EINVAL, "invalid rotation options");
+  for (int64_t p = 0; p < n_pairs; ++p) {
+    const int32_t i = pair_i[p], j = pair_j[p];
+    if (i < 0 || j < 0 || i >= n_cams || j >= n_cams || i == j) return fail(c, FEA_EINVAL, "invalid camera pair");
+  }
+  if (!all_finite(R_rel, (size_t)9 * n_pairs)) return fail(c, FEA_ENONFINITE, "non-finite relative rotation");
+  if (v0 && !all_finite(v0, (size_t)6 * n_cams)) return fail(c, FEA_ENONFINITE, "non-finite start vector");
+  if (a6_init && !all_finite(a6_init, (size_t)6 * n_cams)) return fail(c, FEA_ENONFINITE, "non-finite a6_init");
+  std::vector<int32_t> off, ent;
+  camera_entries(n_cams, n_pairs, pair_i, pair_j, off, ent);
+  int32_t max_deg = 0;
+  for (int32_t i = 0; i < n_cams; ++i) max_deg = std::max(max_deg, off[i + 1] - off[i]);
+  const size_t N3 = (size_t)3 * n_cams, N6 = (size_t)6 * n_cams;
+
+  DeviceGuard g(c->device);
+  CallScratch sc(c->stream);
+  int32_t *dpi, *dpj, *doff, *dent, *derr;
+  double *dR, *cbuf[2], *c1, *sq, *scale, *a6[2], *m, *v, *dloss;
+  fea::TaCounters* ctr;
+  HIP_OR_FAIL(c, sc.put(dpi, pair_i, (size_t)n_pairs));
+  HIP_OR_FAIL(c, sc.put(dpj, pair_j, (size_t)n_pairs));
+  HIP_OR_FAIL(c, sc.put(doff, off.data(), off.size()));
+  HIP_OR_FAIL(c, sc.put(dent, ent.data(), ent.size()));
+  HIP_OR_FAIL(c, sc.put(dR, R_rel, (size_t)9 * n_pairs));
+  HIP_OR_FAIL(c, sc.alloc(cbuf[0], N6));  // both start vectors, then ping-pong
+  HIP_OR_FAIL(c, sc.alloc(cbuf[1], N3));
+  HIP_OR_FAIL(c, sc.alloc(c1, N3));
+  HIP_OR_FAIL(c, sc.alloc(sq, (size_t)n_cams));
+  HIP_OR_FAIL(c, sc.alloc(scale, 1));
+  HIP_OR_FAIL(c, sc.alloc(a6[0], N6));
+  HIP_OR_FAIL(c, sc.alloc(a6[1], N6));
+  HIP_OR_FAIL(c, sc.alloc(m, N6));
+  HIP_OR_FAIL(c, sc.alloc(v, N6));
+  HIP_OR_FAIL(c, sc.alloc(dloss, 2));
+  HIP_OR_FAIL(c, sc.alloc(derr, 1));
+  HIP_OR_FAIL(c, sc.alloc(ctr, 1));
+  HIP_OR_FAIL(c, hipMemsetAsync(derr, 0, sizeof(int32_t), c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(m, 0, N6 * sizeof(double), c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(v, 0, N6 * sizeof(double), c->stream));
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (ms) {
+    HIP_OR_FAIL(c, hipEventCreate(&ev[0]));
+    HIP_OR_FAIL(c, hipEventCreate(&ev[1]));
+  }
+  hipError_t e = hipSuccess;
+  if (ev[0]) e = hipEventRecord(ev[0], c->stream);
+  if (a6_init) {
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(a6[0], a6_init, N6 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  } else {
+    // both start vectors into cbuf[0]: column 1 iterates between its first
+    // half and cbuf[1], column 2 between its second half and cbuf[1]
+    if (e == hipSuccess) e = hipMemcpyAsync(cbuf[0], v0, N6 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    // column 1: smallest eigenvector of M; column 2: of M/|P| + B/|I|.  sigma
+    // just above half the Gershgorin bound (2 max_deg; 2 max_deg/|P| + 1/|I|)
+    const double sig1 = 1.01 * max_deg, sig2 = 1.01 * (max_deg / (double)n_pairs + 0.5 / n_cams);
+    for (int col = 0; col < 2 && e == hipSuccess; ++col) {
+      double* buf[2] = {col == 0 ? cbuf[0] : cbuf[0] + N3, cbuf[1]};
+      // the start vector's own scale first
+      std::vector<double> ones(1, 1.0);
+      e = hipMemcpyAsync(scale, ones.data(), sizeof(double), hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      int par = 0;
+      auto step = [&]() {
+        hipError_t r = fea::launch_ra_apply(c->stream, n_cams, doff, dent, dpi, dpj, dR, buf[par], scale,
+                                            col == 0 ? nullptr : c1, col == 0 ? sig1 : sig2,
+                                            col == 0 ? 1.0 : 1.0 / n_pairs, 1.0 / n_cams, buf[par ^ 1], sq, scale);
+        par ^= 1;
+        return r;
+      };
+      if (e == hipSuccess) e = run_captured(c->stream, o.init_iters, par, step);
+      if (e == hipSuccess)
+        e = fea::launch_ra_columns(c->stream, n_cams, buf[par], col == 0 ? nullptr : c1, col == 0 ? c1 : a6[0], derr);
+    }
+  }
+  if (e == hipSuccess) e = fea::launch_ra_loss(c->stream, n_pairs, dpi, dpj, dR, a6[0], dloss);
+  double* dRinit = nullptr;
+  if (e == hipSuccess && R_init) {
+    e = sc.alloc(dRinit, (size_t)9 * n_cams);
+    if (e == hipSuccess) e = fea::launch_ra_to_R(c->stream, n_cams, a6[0], dRinit);
+  }
+  int par = 0;
+  const double decay = o.iters > 0 ? std::pow(o.lr_end_frac, 1.0 / o.iters) : 1.0;
+  if (e == hipSuccess) e = fea::launch_ta_counters(c->stream, ctr, o.lr);
+  auto ostep = [&]() {
+    hipError_t r = fea::launch_ra_step(c->stream, n_cams, n_pairs, doff, dent, dpi, dpj, dR, a6[par], a6[par ^ 1], m,
+                                       v, ctr, par, o.beta1, o.beta2, o.adam_eps, decay);
+    par ^= 1;
+    return r;
+  };
+  if (e == hipSuccess) e = run_captured(c->stream, o.iters, par, ostep);
+  if (e == hipSuccess) e = fea::launch_ra_loss(c->stream, n_pairs, dpi, dpj, dR, a6[par], dloss + 1);
+  double* dRout = nullptr;
+  if (e == hipSuccess) e = sc.alloc(dRout, (size_t)9 * n_cams);
+  if (e == hipSuccess) e = fea::launch_ra_to_R(c->stream, n_cams, a6[par], dRout);
+  if (e == hipSuccess && ev[1]) e = hipEventRecord(ev[1], c->stream);
+  int32_t herr = 0;
+  if (e == hipSuccess) e = fetch(c->stream, R_out, dRout, (size_t)9 * n_cams);
+  if (e == hipSuccess && R_init) e = fetch(c->stream, R_init, dRinit, (size_t)9 * n_cams);
+  if (e == hipSuccess) e = fetch(c->stream, loss, dloss, 2);
+  if (e == hipSuccess) e = fetch(c->stream, &herr, derr, 1);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && ms) e = hipEventElapsedTime(ms, ev[0], ev[1]);
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  HIP_OR_FAIL(c, e);
+  if (herr) return fail(c, FEA_EDEGENERATE, "a camera's column vanished in the initialisation (unconnected camera?)");
   return FEA_OK;
 }
 

@@ -103,6 +103,8 @@ _SIGNATURES = {
     "fea_get_kernel_times": ([_P, _P, C.c_int64, _P], C.c_int),
     "fea_relative_translations": ([_P, _P, _P, C.c_double, C.c_int32, _P, _P, _P, _P, _P, _P, _P], C.c_int),
     "fea_ta_default_options": ([_P], C.c_int),
+    "fea_ra_default_options": ([_P], C.c_int),
+    "fea_rotation_averaging": ([_P, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], C.c_int),
     "fea_focal_vote": ([_P, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, C.c_int32, _P, C.c_double, _P, _P, _P,
                         _P], C.c_int),
     "fea_translation_align": ([_P, C.c_int32, C.c_int64, _P, _P, _P, _P, C.c_int32, _P, _P, _P, _P, _P,
@@ -180,6 +182,22 @@ def mlp_grad(feat, target, params, device=0):
     if rc != FEA_OK:
         raise FeaError(rc, lib().fea_status_string(rc).decode())
     return loss.value, grad
+
+
+class fea_ra_options(C.Structure):
+    _fields_ = [("init_iters", C.c_int32), ("iters", C.c_int32), ("lr", C.c_double),
+                ("lr_end_frac", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("adam_eps", C.c_double)]
+
+
+def ra_default_options(**kw) -> fea_ra_options:
+    o = fea_ra_options()
+    lib().fea_ra_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
 
 
 def ta_default_options(**kw) -> fea_ta_options:
@@ -452,6 +470,30 @@ class Context:
         if details:
             out.update(run_o=run_o, cam_loss=cam_loss)
         return out
+
+    def rotation_averaging(self, n_cams, pair_cams, R_rel, v0=None, a6_init=None, options=None):
+        """Global rotations from relative rotations (see
+        fea_rotation_averaging).  pair_cams [P,2], R_rel [P,3,3] with
+        R_j ~ R_rel R_i, v0 [2,N,3] random start vectors of the
+        initialisation, or a6_init [N,6] to start the optimisation there."""
+        pc = np.ascontiguousarray(np.asarray(pair_cams).reshape(-1, 2), np.int32)
+        pi, ppi = _host(pc[:, 0], np.int32)
+        pj, ppj = _host(pc[:, 1], np.int32)
+        Rr, pR = _host(np.asarray(R_rel).reshape(-1, 9), np.float64)
+        pv = pa = None
+        if v0 is not None:
+            v0, pv = _host(np.asarray(v0).reshape(-1), np.float64)
+        if a6_init is not None:
+            a6_init, pa = _host(np.asarray(a6_init).reshape(-1), np.float64)
+        opt = options if options is not None else ra_default_options()
+        R = np.zeros((n_cams, 3, 3))
+        R0 = np.zeros((n_cams, 3, 3))
+        loss = np.zeros(2)
+        ms = C.c_float(0.0)
+        self._check(lib().fea_rotation_averaging(self._h, int(n_cams), len(pc), ppi, ppj, pR, pv, pa, C.byref(opt),
+                                                 R.ctypes.data_as(_P), R0.ctypes.data_as(_P),
+                                                 loss.ctypes.data_as(_P), C.byref(ms)))
+        return dict(R=R, R_init=R0, loss_init=loss[0], loss=loss[1], ms=ms.value)
 
     def focal_vote(self, n_cams, pair_cams, F, cand_f, tau, group=None, f_cur=None, votes=False):
         """Focal-length vote (see fea_focal_vote).  pair_cams [P,2], F [P,3,3]
