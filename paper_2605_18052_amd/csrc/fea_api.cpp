@@ -2468,11 +2468,18 @@ fea_status fea_rotation_averaging(fea_ctx* c, int32_t n_cams, int64_t n_pairs, c
       std::vector<double> ones(1, 1.0);
       e = hipMemcpyAsync(scale, ones.data(), sizeof(double), hipMemcpyHostToDevice, c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-      int par = 0;
+      int par = 0, it = 0;
+      // renormalised every 8th step (and at the last): growth between two is
+      // at most sigma^8, far inside the fp64 range
       auto step = [&]() {
-        hipError_t r = fea::launch_ra_apply(c->stream, n_cams, doff, dent, dpi, dpj, dR, buf[par], scale,
+        ++it;
+        const bool renorm = (it % 8) == 0 || it == o.init_iters;
+        const bool rescale = (it % 8) == 1;  // the step after a renormalisation (or the first)
+        hipError_t r = fea::launch_ra_apply(c->stream, n_cams, doff, dent, dpi, dpj, dR, buf[par],
+                                            rescale ? scale : nullptr,
                                             col == 0 ? nullptr : c1, col == 0 ? sig1 : sig2,
-                                            col == 0 ? 1.0 : 1.0 / n_pairs, 1.0 / n_cams, buf[par ^ 1], sq, scale);
+                                            col == 0 ? 1.0 : 1.0 / n_pairs, 1.0 / n_cams, buf[par ^ 1], sq, scale,
+                                            renorm);
         par ^= 1;
         return r;
       };

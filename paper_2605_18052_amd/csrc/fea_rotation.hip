@@ -7,7 +7,7 @@
 // penalty diag(c1_i c1_i^T)).  Both by power iteration on sigma I - A with
 // sigma just above half of A's Gershgorin bound (so the smallest eigenvalues
 // of A dominate): one wave per camera applies A over the camera's pairs
-// (no atomics), one workgroup normalises.  Without noise the smallest
+// (no atomics); one workgroup renormalises every 8th step.  Without noise the smallest
 // eigenvalue of M has the three columns of the true rotations (times any
 // fixed vector) as eigenvectors, a three-dimensional space; any vector in it
 // is a valid first column.
@@ -32,7 +32,8 @@ constexpr int kRaWaves = kRaThreads / 64;
 
 // y_w = s (sigma c_w - wm (M c)_w - wp c1_w (c1_w . c_w)) for camera w, with
 // (M c)_w = sum over its pairs of r (as camera j) or -R^T r (as camera i),
-// r = c_j - R^{i->j} c_i; s = 1/|c| of the input (kept unnormalised).
+// r = c_j - R^{i->j} c_i; s = the last renormalisation's 1/|c| on the step
+// right after it, 1 on the others (scale == nullptr).
 template <bool PEN>
 __global__ __launch_bounds__(kRaThreads) void k_ra_apply(int n_cams, const int32_t* __restrict__ cam_off,
                                                          const int32_t* __restrict__ cam_ent,
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(kRaThreads) void k_ra_apply(int n_cams, const int32
   }
   wave_sum_f64_multi(acc);
   if (lane != 0) return;
-  const double s = *scale;
+  const double s = scale ? *scale : 1.0;
   const double cw[3] = {c_in[3 * w], c_in[3 * w + 1], c_in[3 * w + 2]};
   double y[3];
   for (int a = 0; a < 3; ++a) y[a] = s * (sigma * cw[a] - wm * acc[a]);
@@ -217,14 +218,14 @@ unsigned wave_blocks(int n) { return (unsigned)((n + kRaWaves - 1) / kRaWaves); 
 hipError_t launch_ra_apply(hipStream_t st, int n_cams, const int32_t* cam_off, const int32_t* cam_ent,
                            const int32_t* pair_i, const int32_t* pair_j, const double* Rrel, const double* c_in,
                            const double* scale, const double* c1, double sigma, double wm, double wp, double* c_out,
-                           double* sq, double* scale_out) {
+                           double* sq, double* scale_out, bool renorm) {
   if (c1)
     k_ra_apply<true><<<wave_blocks(n_cams), kRaThreads, 0, st>>>(n_cams, cam_off, cam_ent, pair_i, pair_j, Rrel, c_in,
                                                                  scale, c1, sigma, wm, wp, c_out, sq);
   else
     k_ra_apply<false><<<wave_blocks(n_cams), kRaThreads, 0, st>>>(n_cams, cam_off, cam_ent, pair_i, pair_j, Rrel,
                                                                   c_in, scale, nullptr, sigma, wm, wp, c_out, sq);
-  k_ra_norm<<<1, kRaThreads, 0, st>>>(n_cams, sq, scale_out);
+  if (renorm) k_ra_norm<<<1, kRaThreads, 0, st>>>(n_cams, sq, scale_out);
   return hipGetLastError();
 }
 
