@@ -15,8 +15,9 @@ Prints ONE JSON line on stdout (progress goes to stderr):
   cpu_baseline the FP64 oracle timed on the host on a 6M-match sample
   solve       wall time until the mean rotation error first drops to <= 1 deg,
               with the per-match inner loop and with the pairs' quadratic forms
-  translation the stages before the adjustment: the focal-length vote on the
-              scene's pair graph, the relative-translation candidate search
+  translation the stages before the adjustment: the focal-length vote and
+              global rotation on the scene's pair graph, the
+              relative-translation candidate search
               over the same scene's matches (its scoring kernel against its
               roofline) and the multi-start camera-centre alignment on a
               500-camera object-centric pair graph, each with the oracle
