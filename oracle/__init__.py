@@ -511,7 +511,7 @@ def ra_loss_grad(pair_cams, R_rel, a6):
     return L, g6
 
 
-def ra_init(pair_cams, R_rel, n_cams):
+def ra_init(pair_cams, R_rel, n_cams, details=False):
     """Initialisation (Global Rotation > Initialization details, after
     Martinec and Pajdla): the first columns c1 minimise
     sum |c1_j - R^{i->j} c1_i|^2 over unit-norm stacked vectors (the smallest
@@ -519,7 +519,8 @@ def ra_init(pair_cams, R_rel, n_cams):
     normalised; the second columns minimise the same over the pairs / |P|
     plus sum (c1_i^T c2_i)^2 / |I|, then are normalised and made orthogonal
     to c1 (Gram-Schmidt); the third column is c1 x c2.  Returns a6 [N, 6]
-    (c1, c2) and R [N, 3, 3]."""
+    (c1, c2) and R [N, 3, 3]; with details also the second problem's raw
+    solution [N, 3] (before the per-camera steps)."""
     pc = np.asarray(pair_cams).reshape(-1, 2)
     Rr = _f64(R_rel).reshape(-1, 3, 3)
     N, P = n_cams, len(pc)
@@ -536,11 +537,13 @@ def ra_init(pair_cams, R_rel, n_cams):
     for k in range(N):
         B[3 * k:3 * k + 3, 3 * k:3 * k + 3] = np.outer(c1[k], c1[k])
     _, V2 = np.linalg.eigh(M / P + B / N)
-    c2 = V2[:, 0].reshape(N, 3)
+    raw2 = V2[:, 0].reshape(N, 3).copy()
+    c2 = raw2.copy()
     c2 -= np.sum(c1 * c2, axis=1, keepdims=True) * c1
     c2 /= np.linalg.norm(c2, axis=1, keepdims=True)
     a6 = np.concatenate([c1, c2], axis=1)
-    return a6, np.stack([rot6d_to_R(a6[k]) for k in range(N)])
+    R = np.stack([rot6d_to_R(a6[k]) for k in range(N)])
+    return (a6, R, raw2) if details else (a6, R)
 
 
 def ra_solve(pair_cams, R_rel, a6_0, iters=1000, lr=1e-2, lr_end_frac=1e-2, beta1=0.9, beta2=0.999,

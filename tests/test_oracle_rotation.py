@@ -67,6 +67,23 @@ def test_initialisation_recovers_noiseless_rotations_up_to_one_rotation():
     np.testing.assert_allclose(np.linalg.det(Ri), 1.0, atol=1e-12)
 
 
+def test_initialisation_with_noise_lands_near_the_truth():
+    """With 3 degrees of noise per pair the column-wise initialisation is
+    already within a degree.  Without the orthogonality penalty the second
+    column problem has the first column's own solution, and Gram-Schmidt
+    would leave rounding noise."""
+    pc, R, _, _ = synth.object_pair_graph(120, 70.0, 0)
+    rng = np.random.default_rng(1)
+    Q = synth.rotation_from_axis_angle(rng.normal(size=(len(pc), 3)),
+                                       np.deg2rad(3.0) * np.abs(rng.normal(size=len(pc))))
+    a6, Ri, raw2 = oracle.ra_init(pc, Q @ _rel(R, pc), len(R), details=True)
+    assert metrics.mean_rotation_error_deg(Ri, R) < 1.0
+    # the penalty makes the second problem's own solution nearly orthogonal to
+    # the first column in every camera, before any Gram-Schmidt step
+    cosines = np.abs(np.sum(a6[:, :3] * raw2, axis=1)) / np.linalg.norm(raw2, axis=1)
+    assert cosines.max() < 0.05, cosines.max()
+
+
 def test_optimisation_lowers_loss_and_error_from_the_initialisation():
     pc, R, _, _ = synth.object_pair_graph(120, 70.0, 0)
     rng = np.random.default_rng(1)
