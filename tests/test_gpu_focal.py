@@ -6,6 +6,8 @@ import pytest
 import oracle
 from paper_2605_18052_amd import fastea, synth
 
+from gpu_helpers import vote_tol
+
 pytestmark = pytest.mark.gpu
 
 
@@ -14,14 +16,6 @@ def _need_gpu():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-
-
-def vote_tol(ref, tau, n_pairs):
-    """The closed-form eigenvalues fix s1/s2 to ~1.5e-8 (sqrt of the fp64
-    epsilon: the gap of two nearly equal eigenvalues from the cubic's
-    invariants), so each term exp((1 - s1/s2)/tau) to ~1.5e-8/tau relative;
-    a factor 10 of margin, plus an absolute floor for terms near zero."""
-    return 10 * 1.5e-8 / tau * np.abs(ref) + 1e-12 * n_pairs
 
 
 def check(got, ref_votes, ref_best, cand, tau, n_pairs):

@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_2605_18052_amd import fastea, synth
 
-from gpu_helpers import make_context, per_camera_close
+from gpu_helpers import check_search, make_context, per_camera_close, vote_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -130,3 +130,70 @@ def test_bench_workload_learned_weights_vs_oracle(bench_scene):
     print(f"learned weights at full size: max |err| {err.max():.3g}, mean {err.mean():.3g}", flush=True)
     assert err.max() < 2e-2 and err.mean() < 2.5e-3, (err.max(), err.mean())
     assert ref.std() > 0.05
+
+
+def test_bench_workload_relative_translations_vs_oracle(bench_scene):
+    """The relative-translation search in bench.py's configuration (the
+    20M-match scene, true rotations and focal lengths, 2,048 candidates, the
+    32 px cap, 2,048-match work items) against the FP64 oracle on 16 sampled
+    pairs: scores within the fp32 bound, the choice where separated, vote
+    and signed direction where the choice agrees."""
+    sc = bench_scene[0]
+    cand = synth.sphere_candidates(2048).astype(np.float32).astype(np.float64)
+    ctx = make_context(sc)
+    got = ctx.relative_translations(sc.R_gt, cand, f=sc.f_gt, tau_px=32.0, scores=True)
+    _, _, pc, _ = ctx.get_segments()
+    ctx.close()
+    pick = np.sort(np.random.default_rng(31).choice(len(pc), 16, replace=False))
+    i = np.minimum(sc.cam1, sc.cam2).astype(np.int64)
+    j = np.maximum(sc.cam1, sc.cam2).astype(np.int64)
+    sel = np.nonzero(np.isin(i * sc.n_cams + j, pc[pick, 0].astype(np.int64) * sc.n_cams + pc[pick, 1]))[0]
+    ref = oracle.rel_trans(oracle.OracleProblem.from_scene(sc, sel), sc.R_gt, sc.f_gt, cand, scores=True,
+                           tau=32.0 / np.median(sc.f_gt))
+    np.testing.assert_array_equal(ref["pair_cams"], pc[pick])
+    sub = {k: got[k][pick] for k in ("scores", "best", "vote", "t_rel", "score_best")}
+    agree, _ = check_search(sub, ref, 2048)
+    print(f"search at full size: choice agrees on {agree:.3f} of 16 sampled pairs", flush=True)
+
+
+def test_bench_workload_focal_vote_vs_oracle(bench_scene):
+    """The focal vote in bench.py's configuration (one group per camera of the
+    20M-match scene, the others at their initial focal lengths, 1% noise on
+    the essential matrices, 1,024 candidates) against the oracle on 25
+    sampled cameras (all of their pairs)."""
+    sc = bench_scene[0]
+    pc = sc.pairs().astype(np.int32)
+    F = synth.fundamental_matrices(sc, pc, noise=1e-2, seed=1)
+    cand = synth.focal_candidates(1024, 200.0, 3000.0)
+    groups = np.arange(sc.n_cams, dtype=np.int32)
+    ctx = fastea.Context(0)
+    got = ctx.focal_vote(sc.n_cams, pc, F, cand, 0.05, group=groups, f_cur=sc.f_init, votes=True)
+    ctx.close()
+    cams = np.sort(np.random.default_rng(32).choice(sc.n_cams, 25, replace=False))
+    keep = np.isin(pc[:, 0], cams) | np.isin(pc[:, 1], cams)
+    ref_v, _ = oracle.focal_vote(pc[keep], F[keep], groups, sc.f_init, cand, 0.05)
+    v = got["votes"][cams]
+    r = ref_v[cams]
+    assert np.all(np.abs(v - r) <= vote_tol(r, 0.05, len(pc)))
+    srt = np.sort(r, axis=1)
+    sep = srt[:, -1] - srt[:, -2] > 2 * vote_tol(srt[:, -1], 0.05, len(pc))
+    np.testing.assert_array_equal(got["f_best"][cams][sep], cand[np.argmax(r, axis=1)][sep])
+
+
+def test_bench_workload_rotation_steps_vs_oracle(bench_scene):
+    """Global rotation on bench.py's pair graph and noise (500 cameras, 5,181
+    pairs, |N(0, 2 deg)| per pair): twenty Adam steps from the oracle's
+    initialisation, the same rotations to 1e-9."""
+    sc = bench_scene[0]
+    pc = sc.pairs().astype(np.int32)
+    rng = np.random.default_rng(3)
+    Q = synth.rotation_from_axis_angle(rng.normal(size=(len(pc), 3)),
+                                       np.deg2rad(2.0) * np.abs(rng.normal(size=len(pc))))
+    Rrel = Q @ np.einsum("pab,pcb->pac", sc.R_gt[pc[:, 1]], sc.R_gt[pc[:, 0]])
+    a6, _ = oracle.ra_init(pc, Rrel, sc.n_cams)
+    ctx = fastea.Context(0)
+    got = ctx.rotation_averaging(sc.n_cams, pc, Rrel, a6_init=a6, options=fastea.ra_default_options(iters=20))
+    ctx.close()
+    _, Rref, Lref = oracle.ra_solve(pc, Rrel, a6, iters=20)
+    np.testing.assert_allclose(got["R"], Rref, atol=1e-9)
+    assert got["loss"] == pytest.approx(Lref, rel=1e-9)

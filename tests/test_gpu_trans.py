@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_2605_18052_amd import fastea, metrics, synth
 
-from gpu_helpers import make_context, oracle_problem
+from gpu_helpers import check_search, make_context, oracle_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -26,38 +26,6 @@ def _need_gpu():
 def _cand32(k):
     """Candidates rounded to fp32 and given to both sides in that form."""
     return synth.sphere_candidates(k).astype(np.float32).astype(np.float64)
-
-
-def score_tol(ref):
-    """Bound on |fp32 score - fp64 score|: the per-match n = (R x1) x x2 in fp32
-    from fp32 inputs carries <= ~1e-6 absolute (normalised coordinates below
-    ~1.5, a few roundings of 2^-24 each), the matrix-core dot products a few
-    ulps more; lane sums of <= 128 terms in fp32 add <= 128 * 2^-24 = 8e-6
-    relative before the fp64 accumulation."""
-    return 1e-6 + 1e-5 * np.abs(ref)
-
-
-def check_search(got, ref, K):
-    """Scores to the bound; the choice equal where the oracle's best is
-    separated from its runner-up by more than the bound, else a valid
-    near-tie; vote and signed direction equal where the choice agrees."""
-    sg, sr = got["scores"].astype(np.float64), ref["scores"]
-    tol = score_tol(sr)
-    bad = np.abs(sg - sr) > tol
-    assert not bad.any(), (np.argwhere(bad)[:5], np.abs(sg - sr)[bad][:5], sr[bad][:5])
-    P = len(sr)
-    order = np.sort(sr, axis=1)
-    sep = order[:, 1] - order[:, 0] > 2 * score_tol(order[:, 0]) if K > 1 else np.ones(P, bool)
-    assert np.array_equal(got["best"][sep], ref["best"][sep])
-    chosen = sr[np.arange(P), got["best"]]
-    assert np.all(chosen <= order[:, 0] + 2 * score_tol(order[:, 0]))
-    same = got["best"] == ref["best"]
-    assert np.all(np.abs(got["vote"][same] - ref["vote"][same]) <= 2)
-    sgn = np.sign(got["vote"]) == np.sign(ref["vote"])
-    m = same & (sgn | (np.abs(ref["vote"]) > 2))
-    np.testing.assert_array_equal(got["t_rel"][same & sgn], ref["t_rel"][same & sgn])
-    np.testing.assert_allclose(got["score_best"], chosen, rtol=1e-5, atol=1e-6)
-    return same.mean(), m.mean()
 
 
 @pytest.mark.parametrize("K,tau_px", [(1, math.inf), (700, 32.0), (2048, math.inf), (3000, 32.0)])
