@@ -436,6 +436,8 @@ fea_status load_matches_common(fea_ctx* c, int64_t n, const float* x1, const flo
   c->ptab_current = false;
   HIP_OR_FAIL(c, dalloc(c->stab, (size_t)std::max<int64_t>(c->P, 1) * 40 * sizeof(double)));
   HIP_OR_FAIL(c, dalloc(c->wlay, std::max<int64_t>(c->layout_len, 4) * sizeof(uint16_t)));
+  // padding slots never get a weight from the network: keep them zero
+  HIP_OR_FAIL(c, hipMemsetAsync(c->wlay.p, 0, c->wlay.bytes, c->stream));
   // camera -> incident (pair, side) entries, in pair order
   const int N = c->N;
   c->cam_off.assign(N + 1, 0);

@@ -121,8 +121,10 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
       kept += hold ? 1 : 0;
       double cw = hold ? 1.0 / fmax(fabs(eph), delta) : 0.0;
       if (learned) {
+        // the network writes only the slots of real matches: the weight of a
+        // padding slot is never read into the arithmetic (0 * NaN is NaN)
         const double wl = (double)__uint_as_float((uint32_t)v4w(cw4, e) << 16);
-        cw *= wl;
+        cw = hold ? cw * wl : 0.0;
         wsum += hold ? wl : 0.0;
       }
       const double p1[3] = {x1 - cxi, y1 - cyi, 1.0};
