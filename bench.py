@@ -370,15 +370,13 @@ def translation_stages(sc, fastea, synth, n_cand, with_cpu, cap_px=32.0, cpu_pai
         r_ms.append(ra["ms"])
     rctx.close()
     ropt = fastea.ra_default_options()
-    rotation = {"cameras": sc.n_cams, "pairs": int(len(pc)), "init_iters": ropt.init_iters, "iters": ropt.iters,
-                "ms": float(np.median(r_ms)),
-                # launches: per column one per power iteration plus a renormalisation every 8th; one per step
-                "us_per_launch": 1e3 * float(np.median(r_ms)) / (2 * ropt.init_iters * 9 / 8 + ropt.iters),
+    rotation = {"cameras": sc.n_cams, "pairs": int(len(pc)), "init_iters_cap": ropt.init_iters,
+                "iters": ropt.iters, "ms": float(np.median(r_ms)),
                 "error_init_deg": metrics.mean_rotation_error_deg(ra["R_init"], sc.R_gt),
                 "error_deg": metrics.mean_rotation_error_deg(ra["R"], sc.R_gt),
                 "loss_init": ra["loss_init"], "loss": ra["loss"],
-                "bound": "latency: one launch per power iteration (a renormalisation every 8th) and one per "
-                         "Adam step, O(pairs) fp64 each"}
+                "bound": "latency: one launch per power iteration (a renormalisation every 8th, run until "
+                         "the Rayleigh quotient settles) and one per Adam step, O(pairs) fp64 each"}
     out = {"relative_translations": search, "alignment": align, "focal_vote": focal, "rotation": rotation}
     if with_cpu:
         import oracle

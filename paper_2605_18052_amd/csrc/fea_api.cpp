@@ -2346,7 +2346,7 @@ fea_status fea_focal_vote(fea_ctx* c, int32_t n_cams, int64_t n_pairs, const int
 
 fea_status fea_ra_default_options(fea_ra_options* o) {
   if (!o) return FEA_EINVAL;
-  o->init_iters = 5000;
+  o->init_iters = 200000;
   o->iters = 1000;
   o->lr = 1e-2;
   o->lr_end_frac = 1e-2;
@@ -2425,7 +2425,7 @@ fea_status fea_rotation_averaging(fea_ctx* c, int32_t n_cams, int64_t n_pairs, c
   DeviceGuard g(c->device);
   CallScratch sc(c->stream);
   int32_t *dpi, *dpj, *doff, *dent, *derr;
-  double *dR, *cbuf[2], *c1, *sq, *scale, *a6[2], *m, *v, *dloss;
+  double *dR, *cbuf[2], *c1, *sq, *scale, *rho, *a6[2], *m, *v, *dloss;
   fea::TaCounters* ctr;
   HIP_OR_FAIL(c, sc.put(dpi, pair_i, (size_t)n_pairs));
   HIP_OR_FAIL(c, sc.put(dpj, pair_j, (size_t)n_pairs));
@@ -2435,8 +2435,9 @@ fea_status fea_rotation_averaging(fea_ctx* c, int32_t n_cams, int64_t n_pairs, c
   HIP_OR_FAIL(c, sc.alloc(cbuf[0], N6));  // both start vectors, then ping-pong
   HIP_OR_FAIL(c, sc.alloc(cbuf[1], N3));
   HIP_OR_FAIL(c, sc.alloc(c1, N3));
-  HIP_OR_FAIL(c, sc.alloc(sq, (size_t)n_cams));
+  HIP_OR_FAIL(c, sc.alloc(sq, (size_t)3 * n_cams));
   HIP_OR_FAIL(c, sc.alloc(scale, 1));
+  HIP_OR_FAIL(c, sc.alloc(rho, 1));
   HIP_OR_FAIL(c, sc.alloc(a6[0], N6));
   HIP_OR_FAIL(c, sc.alloc(a6[1], N6));
   HIP_OR_FAIL(c, sc.alloc(m, N6));
@@ -2471,21 +2472,50 @@ fea_status fea_rotation_averaging(fea_ctx* c, int32_t n_cams, int64_t n_pairs, c
       e = hipMemcpyAsync(scale, ones.data(), sizeof(double), hipMemcpyHostToDevice, c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       int par = 0, it = 0;
-      // renormalised every 8th step (and at the last): growth between two is
-      // at most sigma^8, far inside the fp64 range
+      const double sig = col == 0 ? sig1 : sig2;
+      // renormalised every 8th step: growth between two is at most sigma^8,
+      // far inside the fp64 range; the renormalisation also gives the
+      // Rayleigh quotient of the step's input
       auto step = [&]() {
         ++it;
-        const bool renorm = (it % 8) == 0 || it == o.init_iters;
+        const bool renorm = (it % 8) == 0;
         const bool rescale = (it % 8) == 1;  // the step after a renormalisation (or the first)
         hipError_t r = fea::launch_ra_apply(c->stream, n_cams, doff, dent, dpi, dpj, dR, buf[par],
-                                            rescale ? scale : nullptr,
-                                            col == 0 ? nullptr : c1, col == 0 ? sig1 : sig2,
+                                            rescale ? scale : nullptr, col == 0 ? nullptr : c1, sig,
                                             col == 0 ? 1.0 : 1.0 / n_pairs, 1.0 / n_cams, buf[par ^ 1], sq, scale,
-                                            renorm);
+                                            renorm, rho);
         par ^= 1;
         return r;
       };
-      if (e == hipSuccess) e = run_captured(c->stream, o.init_iters, par, step);
+      // 64 steps captured once (an even count: the buffer roles return), run
+      // 256 at a time until the Rayleigh quotient settles (its change over
+      // 256 steps below 3e-5 of itself, or 1e-12 sigma near zero) or
+      // init_iters steps have run.  Inside the near-null cluster (split by
+      // noise) the iterate keeps drifting towards the single smallest
+      // eigenvector at a rate set by the tiny split; any vector of the
+      // cluster is a valid column, so the test only has to see it arrive.
+      hipGraph_t gph = nullptr;
+      hipGraphExec_t gx = nullptr;
+      if (e == hipSuccess) e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t le = hipSuccess;
+        for (int k = 0; k < 64 && le == hipSuccess; ++k) le = step();
+        e = hipStreamEndCapture(c->stream, &gph);
+        if (le != hipSuccess) e = le;
+      }
+      par = 0;
+      if (e == hipSuccess) e = hipGraphInstantiate(&gx, gph, nullptr, nullptr, 0);
+      if (gph) (void)hipGraphDestroy(gph);
+      double rho_prev = 0.0;
+      for (int done = 0; e == hipSuccess && done < o.init_iters; done += 256) {
+        for (int r = 0; r < 4 && e == hipSuccess; ++r) e = hipGraphLaunch(gx, c->stream);
+        double rh = 0.0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&rh, rho, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess && done > 0 && std::fabs(rh - rho_prev) <= 3e-5 * std::fabs(rh) + 1e-12 * sig) break;
+        rho_prev = rh;
+      }
+      if (gx) (void)hipGraphExecDestroy(gx);
       if (e == hipSuccess)
         e = fea::launch_ra_columns(c->stream, n_cams, buf[par], col == 0 ? nullptr : c1, col == 0 ? c1 : a6[0], derr);
     }

@@ -12,14 +12,14 @@ namespace fea {
 
 // One power-iteration step: c_out = s (sigma c_in - wm M c_in - wp P c_in)
 // with s = *scale (1 when scale is null: pass it only on the step after a
-// renormalisation); with renorm also scale_out = 1/|c_out|.  Between
+// renormalisation); with renorm also scale_out = 1/|c_out| and *rho = the
+// Rayleigh quotient of A at c_in (sq holds 3 n_cams doubles).  Between
 // renormalisations the vector grows by at most sigma per step (the scale
 // only keeps it inside the fp64 range; the direction is the result).
 hipError_t launch_ra_apply(hipStream_t st, int n_cams, const int32_t* cam_off, const int32_t* cam_ent,
                            const int32_t* pair_i, const int32_t* pair_j, const double* Rrel, const double* c_in,
                            const double* scale, const double* c1, double sigma, double wm, double wp, double* c_out,
-                           double* sq, double* scale_out, bool renorm);
-hipError_t launch_ra_norm(hipStream_t st, int n, const double* sq, double* scale);
+                           double* sq, double* scale_out, bool renorm, double* rho);
 hipError_t launch_ra_columns(hipStream_t st, int n_cams, const double* c, const double* c1, double* out,
                              int32_t* err);
 hipError_t launch_ra_step(hipStream_t st, int n_cams, int64_t n_pairs, const int32_t* cam_off, const int32_t* cam_ent,

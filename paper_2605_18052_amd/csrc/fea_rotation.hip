@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kRaThreads) void k_ra_apply(int n_cams, const int32
                                                          const double* __restrict__ scale,
                                                          const double* __restrict__ c1, double sigma, double wm,
                                                          double wp, double* __restrict__ c_out,
-                                                         double* __restrict__ sq) {
+                                                         double* __restrict__ sq) {  // [3 n_cams]: y.y, c.y, c.c
   const int lane = threadIdx.x & 63;
   const int w = blockIdx.x * kRaWaves + (threadIdx.x >> 6);
   if (w >= n_cams) return;
@@ -76,20 +76,37 @@ __global__ __launch_bounds__(kRaThreads) void k_ra_apply(int n_cams, const int32
   }
   for (int a = 0; a < 3; ++a) c_out[3 * w + a] = y[a];
   sq[w] = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+  sq[n_cams + w] = cw[0] * y[0] + cw[1] * y[1] + cw[2] * y[2];
+  sq[2 * n_cams + w] = cw[0] * cw[0] + cw[1] * cw[1] + cw[2] * cw[2];
 }
 
-// scale = 1 / sqrt(sum of sq) (fixed-order block sum); 0 marks a zero vector.
-__global__ __launch_bounds__(kRaThreads) void k_ra_norm(int n, const double* __restrict__ sq, double* __restrict__ scale) {
-  __shared__ double red[kRaThreads];
-  double s = 0.0;
-  for (int k = threadIdx.x; k < n; k += kRaThreads) s += sq[k];
-  red[threadIdx.x] = s;
+// scale = 1 / sqrt(sum of y.y) (fixed-order block sums; 0 marks a zero
+// vector) and the Rayleigh quotient of A at the step's input c:
+// c.Ac / c.c = sigma - (c.y) / (s c.c), y = s (sigma c - A c), s the step's
+// input scale; written to rho[0].
+__global__ __launch_bounds__(kRaThreads) void k_ra_norm(int n, const double* __restrict__ sq, double sigma,
+                                                        double s_in, double* __restrict__ scale,
+                                                        double* __restrict__ rho) {
+  __shared__ double red[3][kRaThreads];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int k = threadIdx.x; k < n; k += kRaThreads) {
+    a += sq[k];
+    b += sq[n + k];
+    c += sq[2 * n + k];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  red[2][threadIdx.x] = c;
   __syncthreads();
   for (int o = kRaThreads / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if (threadIdx.x < o)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *scale = red[0] > 0.0 ? 1.0 / sqrt(red[0]) : 0.0;
+  if (threadIdx.x == 0) {
+    *scale = red[0][0] > 0.0 ? 1.0 / sqrt(red[0][0]) : 0.0;
+    if (rho) *rho = red[2][0] > 0.0 ? sigma - red[1][0] / (s_in * red[2][0]) : 0.0;
+  }
 }
 
 // Per camera: c1 = c/|c|; or, with c1 given, the second column: c minus its
@@ -218,19 +235,15 @@ unsigned wave_blocks(int n) { return (unsigned)((n + kRaWaves - 1) / kRaWaves); 
 hipError_t launch_ra_apply(hipStream_t st, int n_cams, const int32_t* cam_off, const int32_t* cam_ent,
                            const int32_t* pair_i, const int32_t* pair_j, const double* Rrel, const double* c_in,
                            const double* scale, const double* c1, double sigma, double wm, double wp, double* c_out,
-                           double* sq, double* scale_out, bool renorm) {
+                           double* sq, double* scale_out, bool renorm, double* rho) {
   if (c1)
     k_ra_apply<true><<<wave_blocks(n_cams), kRaThreads, 0, st>>>(n_cams, cam_off, cam_ent, pair_i, pair_j, Rrel, c_in,
                                                                  scale, c1, sigma, wm, wp, c_out, sq);
   else
     k_ra_apply<false><<<wave_blocks(n_cams), kRaThreads, 0, st>>>(n_cams, cam_off, cam_ent, pair_i, pair_j, Rrel,
                                                                   c_in, scale, nullptr, sigma, wm, wp, c_out, sq);
-  if (renorm) k_ra_norm<<<1, kRaThreads, 0, st>>>(n_cams, sq, scale_out);
-  return hipGetLastError();
-}
-
-hipError_t launch_ra_norm(hipStream_t st, int n, const double* sq, double* scale) {
-  k_ra_norm<<<1, kRaThreads, 0, st>>>(n, sq, scale);
+  // the input scale of a renormalising step is 1 (it never follows one)
+  if (renorm) k_ra_norm<<<1, kRaThreads, 0, st>>>(n_cams, sq, sigma, 1.0, scale_out, rho);
   return hipGetLastError();
 }
 
