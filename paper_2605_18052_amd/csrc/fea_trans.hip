@@ -125,6 +125,7 @@ __global__ __launch_bounds__(kRtThreads) void k_rt_score(const int4* __restrict_
     acc2[q] = 0.f;
   }
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  const float ntau = -tau;
   // the row of the next block is read while this one's products run (the
   // read past the last block stays inside the LDS row: nblk * 16 < kRtLds)
   const float* srow = sn[kq < 3 ? kq : 0];
@@ -135,10 +136,14 @@ __global__ __launch_bounds__(kRtThreads) void k_rt_score(const int4* __restrict_
 #pragma unroll
     for (int q = 0; q < kRtBlocks; ++q) {
       const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bop[q], zero, 0, 0, 0);
-      if constexpr (CAP)
-        accf[q] += (__builtin_fminf(__builtin_fabsf(d[0]), tau) + __builtin_fminf(__builtin_fabsf(d[1]), tau)) +
-                   (__builtin_fminf(__builtin_fabsf(d[2]), tau) + __builtin_fminf(__builtin_fabsf(d[3]), tau));
-      else
+      if constexpr (CAP) {
+        // |clamp(e, -tau, tau)| = min(|e|, tau): one v_med3 per product, the
+        // absolute value rides on the add as a source modifier (fminf would
+        // add a canonicalising max before every min)
+        const float c0 = __builtin_amdgcn_fmed3f(d[0], ntau, tau), c1 = __builtin_amdgcn_fmed3f(d[1], ntau, tau);
+        const float c2 = __builtin_amdgcn_fmed3f(d[2], ntau, tau), c3 = __builtin_amdgcn_fmed3f(d[3], ntau, tau);
+        accf[q] += (__builtin_fabsf(c0) + __builtin_fabsf(c1)) + (__builtin_fabsf(c2) + __builtin_fabsf(c3));
+      } else
         accf[q] += (__builtin_fabsf(d[0]) + __builtin_fabsf(d[1])) + (__builtin_fabsf(d[2]) + __builtin_fabsf(d[3]));
     }
     if ((mb & 31) == 31) {  // lane sums of at most 128 terms, then at most 4 of those
