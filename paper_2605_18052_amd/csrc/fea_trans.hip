@@ -73,8 +73,8 @@ __global__ void k_rt_pairs(int64_t n_pairs, const int32_t* __restrict__ pair_i, 
 // lane l supplies A[l%16][l/16] = component l/16 of match l%16 of the block
 // and B[l/16][l%16] = component l/16 of candidate l%16; it receives D[4(l/16)+r][l%16]
 // for r = 0..3, i.e. four matches of candidate l%16.  Component 3 is zero.
-// With CAP every product enters as min(|d|, tau) (one v_min_f32 with an abs
-// source each), else as |d| (folded into the adds).
+// With CAP every product enters as min(|d|, tau) (one v_med3_f32 clamp each,
+// the absolute value folded into the adds), else as |d| (folded into the adds).
 template <bool CAP>
 __global__ __launch_bounds__(kRtThreads) void k_rt_score(const int4* __restrict__ items, int n_groups,
                                                          const float* __restrict__ rowf,
