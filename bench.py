@@ -557,7 +557,7 @@ def main():
         "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}",
                    "matches_loaded": sc.n_matches, "matches_per_step": Z,
-                   "pairs": info["n_pairs"], "items": info["n_items"], "round": 0,
+                   "pairs": info["n_pairs"], "items": info["n_items"], "irls_round": 0,
                    "tau_px": opt.tau_px_init},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
