@@ -2112,7 +2112,7 @@ struct TaPhase {
   fea_ctx* c;
   int runs, N;
   int64_t P;
-  const int32_t *off, *ent, *pi, *pj;
+  const int32_t *off, *ent, *oth;
   const double* tg;
   double* o[2];
   double *m, *v;
@@ -2121,7 +2121,7 @@ struct TaPhase {
   int parity = 0;
 
   hipError_t step() {
-    hipError_t e = fea::launch_ta_step(c->stream, runs, N, P, off, ent, pi, pj, tg, o[parity], o[parity ^ 1], m, v,
+    hipError_t e = fea::launch_ta_step(c->stream, runs, N, P, off, ent, oth, tg, o[parity], o[parity ^ 1], m, v,
                                        ctr, parity, b1, b2, eps, decay);
     parity ^= 1;
     return e;
@@ -2189,16 +2189,20 @@ fea_status fea_translation_align(fea_ctx* c, int32_t n_cams, int64_t n_pairs, co
   if (!all_finite(o_init, r3)) return fail(c, FEA_ENONFINITE, "non-finite initial centre");
   std::vector<int32_t> off, ent;
   camera_entries(n_cams, n_pairs, pair_i, pair_j, off, ent);
+  // the other camera of each entry, so that a step reads it without the pair
+  std::vector<int32_t> oth(ent.size());
+  for (size_t e = 0; e < ent.size(); ++e) oth[e] = (ent[e] & 1) ? pair_i[ent[e] >> 1] : pair_j[ent[e] >> 1];
 
   DeviceGuard g(c->device);
   CallScratch sc(c->stream);
-  int32_t *dpi, *dpj, *doff, *dent, *derr, *drun;
+  int32_t *dpi, *dpj, *doff, *dent, *doth, *derr, *drun;
   double *dR, *dt, *tg, *o0, *o1, *m, *v, *pl, *cl, *rl, *om0, *om1, *fl;
   fea::TaCounters* ctr;
   HIP_OR_FAIL(c, sc.put(dpi, pair_i, (size_t)n_pairs));
   HIP_OR_FAIL(c, sc.put(dpj, pair_j, (size_t)n_pairs));
   HIP_OR_FAIL(c, sc.put(doff, off.data(), off.size()));
   HIP_OR_FAIL(c, sc.put(dent, ent.data(), ent.size()));
+  HIP_OR_FAIL(c, sc.put(doth, oth.data(), oth.size()));
   HIP_OR_FAIL(c, sc.put(dR, R, (size_t)9 * n_cams));
   HIP_OR_FAIL(c, sc.put(dt, t_rel, (size_t)3 * n_pairs));
   HIP_OR_FAIL(c, sc.put(o0, o_init, r3));
@@ -2227,7 +2231,7 @@ fea_status fea_translation_align(fea_ctx* c, int32_t n_cams, int64_t n_pairs, co
   if (ev[0]) e = hipEventRecord(ev[0], c->stream);
   if (e == hipSuccess) e = fea::launch_ta_targets(c->stream, n_pairs, dpj, dR, dt, tg);
   // the runs, side by side
-  TaPhase ph{c, n_runs, n_cams, n_pairs, doff, dent, dpi, dpj, tg, {o0, o1}, m, v, ctr,
+  TaPhase ph{c, n_runs, n_cams, n_pairs, doff, dent, doth, tg, {o0, o1}, m, v, ctr,
              o.beta1, o.beta2, o.adam_eps, o.iters_run > 0 ? std::pow(o.lr_end_frac, 1.0 / o.iters_run) : 1.0};
   if (e == hipSuccess) e = fea::launch_ta_counters(c->stream, ctr, o.lr);
   if (e == hipSuccess) e = ph.run(o.iters_run);
@@ -2238,7 +2242,7 @@ fea_status fea_translation_align(fea_ctx* c, int32_t n_cams, int64_t n_pairs, co
   // the merged centres, one more loop
   if (e == hipSuccess) e = hipMemsetAsync(m, 0, n3 * sizeof(double), c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(v, 0, n3 * sizeof(double), c->stream);
-  TaPhase fin{c, 1, n_cams, n_pairs, doff, dent, dpi, dpj, tg, {om0, om1}, m, v, ctr,
+  TaPhase fin{c, 1, n_cams, n_pairs, doff, dent, doth, tg, {om0, om1}, m, v, ctr,
               o.beta1, o.beta2, o.adam_eps, o.iters_final > 0 ? std::pow(o.lr_end_frac, 1.0 / o.iters_final) : 1.0};
   if (e == hipSuccess) e = fea::launch_ta_counters(c->stream, ctr, o.lr_final);
   if (e == hipSuccess) e = fin.run(o.iters_final);

@@ -40,8 +40,7 @@ hipError_t launch_ta_targets(hipStream_t st, int64_t n_pairs, const int32_t* pai
                              const double* t_rel, double* target);
 hipError_t launch_ta_counters(hipStream_t st, TaCounters* ctr, double lr);
 hipError_t launch_ta_step(hipStream_t st, int runs, int n_cams, int64_t n_pairs, const int32_t* cam_off,
-                          const int32_t* cam_ent, const int32_t* pair_i, const int32_t* pair_j,
-                          const double* target, const double* o_in, double* o_out, double* m, double* v,
+                          const int32_t* cam_ent, const int32_t* ent_other, const double* target, const double* o_in, double* o_out, double* m, double* v,
                           TaCounters* ctr, int parity, double beta1, double beta2, double eps, double decay);
 hipError_t launch_ta_align(hipStream_t st, int runs, int n_cams, double* o, int32_t* err);
 hipError_t launch_ta_losses(hipStream_t st, int runs, int n_cams, int64_t n_pairs, const int32_t* cam_off,

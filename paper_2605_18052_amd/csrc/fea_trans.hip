@@ -294,8 +294,7 @@ __global__ void k_ta_counters(TaCounters* ctr, double lr) {
 __global__ __launch_bounds__(kTaThreads) void k_ta_step(int runs, int n_cams, int64_t n_pairs,
                                                         const int32_t* __restrict__ cam_off,
                                                         const int32_t* __restrict__ cam_ent,
-                                                        const int32_t* __restrict__ pair_i,
-                                                        const int32_t* __restrict__ pair_j,
+                                                        const int32_t* __restrict__ ent_other,
                                                         const double* __restrict__ target,
                                                         const double* __restrict__ o_in, double* __restrict__ o_out,
                                                         double* __restrict__ m, double* __restrict__ v,
@@ -316,11 +315,15 @@ __global__ __launch_bounds__(kTaThreads) void k_ta_step(int runs, int n_cams, in
   const double* o = o_in + base;
   const double inv_np = 1.0 / (double)n_pairs;
   double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  const double oc0 = o[3 * c], oc1 = o[3 * c + 1], oc2 = o[3 * c + 2];
   for (int e = cam_off[c] + lane; e < cam_off[c + 1]; e += 64) {
-    const int ent = cam_ent[e];
+    // the entry and its other camera load side by side (no pair lookup)
+    const int ent = cam_ent[e], oc = ent_other[e];
     const int64_t q = ent >> 1;
-    const int i = pair_i[q], j = pair_j[q];
-    const double d0 = o[3 * j] - o[3 * i], d1 = o[3 * j + 1] - o[3 * i + 1], d2 = o[3 * j + 2] - o[3 * i + 2];
+    const double x0 = o[3 * oc], x1 = o[3 * oc + 1], x2 = o[3 * oc + 2];
+    // d = o_j - o_i; this camera is j of the pair when the entry is odd
+    const bool cj = ent & 1;
+    const double d0 = cj ? oc0 - x0 : x0 - oc0, d1 = cj ? oc1 - x1 : x1 - oc1, d2 = cj ? oc2 - x2 : x2 - oc2;
     const double nd = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
     if (!(nd > 0.0)) continue;
     const double inv = 1.0 / nd;
@@ -517,12 +520,12 @@ hipError_t launch_ta_counters(hipStream_t st, TaCounters* ctr, double lr) {
 }
 
 hipError_t launch_ta_step(hipStream_t st, int runs, int n_cams, int64_t n_pairs, const int32_t* cam_off,
-                          const int32_t* cam_ent, const int32_t* pair_i, const int32_t* pair_j,
-                          const double* target, const double* o_in, double* o_out, double* m, double* v,
-                          TaCounters* ctr, int parity, double beta1, double beta2, double eps, double decay) {
+                          const int32_t* cam_ent, const int32_t* ent_other, const double* target, const double* o_in,
+                          double* o_out, double* m, double* v, TaCounters* ctr, int parity, double beta1,
+                          double beta2, double eps, double decay) {
   k_ta_step<<<blocks_for((int64_t)runs * n_cams, kTaThreads / 64), kTaThreads, 0, st>>>(
-      runs, n_cams, n_pairs, cam_off, cam_ent, pair_i, pair_j, target, o_in, o_out, m, v, ctr, parity, beta1, beta2,
-      eps, decay);
+      runs, n_cams, n_pairs, cam_off, cam_ent, ent_other, target, o_in, o_out, m, v, ctr, parity, beta1, beta2, eps,
+      decay);
   return hipGetLastError();
 }
 
