@@ -134,6 +134,14 @@ int32_t fea_version(void);
 /* Human-readable name of a status code (static string). */
 const char *fea_status_string(fea_status s);
 
+/* Checks options without a context or a GPU: FEA_OK when fea_create and
+ * fea_set_options would accept them, else FEA_EINVAL with the reason written
+ * to why (NUL-terminated, at most why_len bytes; why may be NULL).  Besides
+ * the ranges documented at each field, learned weights (weight_mode = 1)
+ * with the quadratic form (inner_loop = 1) accept tile_matches 0 or 8192
+ * only. */
+fea_status fea_check_options(const fea_options *opt, char *why, size_t why_len);
+
 /* Fills *out with the default options.  FEA_EINVAL if out is NULL. */
 fea_status fea_default_options(fea_options *out);
 

@@ -191,6 +191,7 @@ struct fea_ctx {
   // captured step graph (kGraphSteps steps of the current round)
   hipGraphExec_t graph = nullptr;
   int graph_pcur = -1;
+  uint64_t graph_gen = 0;  // device-buffer generation the graph was captured at
 
   // pinned staging ring for small host-to-device copies
   void* stage = nullptr;

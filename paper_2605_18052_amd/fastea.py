@@ -64,6 +64,7 @@ _SIGNATURES = {
     "fea_version": ([], C.c_int32),
     "fea_status_string": ([C.c_int], C.c_char_p),
     "fea_default_options": ([_P], C.c_int),
+    "fea_check_options": ([_P, _P, C.c_size_t], C.c_int),
     "fea_create": ([_P, C.c_int32, _P, _P], C.c_int),
     "fea_destroy": ([_P], None),
     "fea_last_error": ([_P], C.c_char_p),
@@ -218,6 +219,14 @@ def default_options(**kw) -> fea_options:
             raise AttributeError(k)
         setattr(o, k, v)
     return o
+
+
+def check_options(opt: fea_options):
+    """(status, reason) of fea_check_options: whether a context would accept
+    these options (needs no GPU)."""
+    buf = C.create_string_buffer(256)
+    rc = lib().fea_check_options(C.byref(opt), buf, len(buf))
+    return rc, buf.value.decode()
 
 
 def _host(a, dtype):

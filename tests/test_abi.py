@@ -62,3 +62,28 @@ def test_null_handles_are_rejected(so):
     assert L.fea_begin_round(None, 1.0) == fastea.FEA_EINVAL
     assert L.fea_get_poses(None, None, None, None) == fastea.FEA_EINVAL
     L.fea_destroy(None)
+
+
+def test_check_options_without_a_gpu(so):
+    from paper_2605_18052_amd import fastea
+    ok, why = fastea.check_options(fastea.default_options())
+    assert ok == fastea.FEA_OK and why == ""
+    bad, why = fastea.check_options(fastea.default_options(tile_matches=3000))
+    assert bad == fastea.FEA_EINVAL and "tile_matches" in why
+    assert fastea.lib().fea_check_options(None, None, 0) == fastea.FEA_EINVAL
+
+
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+def test_learned_quadratic_form_with_small_items_is_refused(so, tile):
+    """Learned weights with the quadratic form accept only the default
+    (8192-match) work items; smaller ones are refused before any GPU work."""
+    from paper_2605_18052_amd import fastea
+    o = fastea.default_options(weight_mode=1, inner_loop=1, tile_matches=tile)
+    rc, why = fastea.check_options(o)
+    assert rc == fastea.FEA_EINVAL and "tile_matches 0 or 8192" in why
+    for t in (0, 8192):
+        assert fastea.check_options(fastea.default_options(weight_mode=1, inner_loop=1,
+                                                           tile_matches=t))[0] == fastea.FEA_OK
+    # each alone stays accepted with small items
+    assert fastea.check_options(fastea.default_options(inner_loop=1, tile_matches=tile))[0] == fastea.FEA_OK
+    assert fastea.check_options(fastea.default_options(weight_mode=1, tile_matches=tile))[0] == fastea.FEA_OK

@@ -112,7 +112,8 @@ def test_learned_weights_gradient_vs_oracle():
     sc = SCENES["sphere20_m60k"]
     p = _soft_inlier_mlp()
     R, t, f = _perturbed(sc, seed=5)
-    quad = _gpu_grad(sc, R, t, f, math.inf, 1, mlp=p.astype(np.float32))
+    # the quadratic form with learned weights takes its default (8192-match) items
+    quad = _gpu_grad(sc, R, t, f, math.inf, 1, mlp=p.astype(np.float32), tile=0)
     plain = _gpu_grad(sc, R, t, f, math.inf, 0, mlp=p.astype(np.float32))
     _close(quad, plain[:4], 1e-5)
     pb = oracle_problem(sc)
