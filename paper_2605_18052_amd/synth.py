@@ -19,6 +19,8 @@ comes from a counter-based hash of (seed, stream, a, b); the bulk layout
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -33,6 +35,36 @@ def _splitmix64(x: np.ndarray) -> np.ndarray:
         z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
         z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
         return z ^ (z >> np.uint64(31))
+
+
+def _workers() -> int:
+    """Host threads for scene generation (numpy releases the GIL in the bulk
+    array work; every result is assembled in a fixed order, so the scene does
+    not depend on the thread count)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _pmap(fn, items):
+    """fn over items on the generation threads, results in item order."""
+    items = list(items)
+    if len(items) <= 1 or _workers() == 1:
+        return [fn(x) for x in items]
+    # one BLAS thread per worker: the small products here gain nothing from
+    # BLAS's own threads, which would contend with the workers
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1, user_api="blas"), ThreadPoolExecutor(max_workers=_workers()) as ex:
+        return list(ex.map(fn, items))
+
+
+def _ranges(n: int, parts: int):
+    """Contiguous [lo, hi) ranges splitting range(n) into about `parts` pieces."""
+    parts = max(1, min(parts, n))
+    cuts = np.linspace(0, n, parts + 1).astype(np.int64)
+    return [(int(cuts[k]), int(cuts[k + 1])) for k in range(parts) if cuts[k + 1] > cuts[k]]
 
 
 def hash_u01(seed: int, stream: int, a, b) -> np.ndarray:
@@ -185,24 +217,38 @@ def _emit_matches(seed, pair_list, det_ids, det_u, det_v, n_cams, width, height,
     all_u = np.concatenate(det_u) if n_pts else np.zeros(0)
     all_v = np.concatenate(det_v) if n_pts else np.zeros(0)
     # visit pairs grouped by their second camera, with a dense point -> slot
-    # map of that camera
-    pos = np.full(max(n_pts, 1), -1, dtype=np.int64)
-    a_parts, b_parts, k_parts = [], [], []
-    cur = -1
-    for k in np.argsort(pairs[:, 1], kind="stable"):
-        i, j = int(pairs[k, 0]), int(pairs[k, 1])
-        if j != cur:
-            if cur >= 0:
-                pos[det_ids[cur]] = -1
+    # map of that camera; runs of whole groups go to the threads and their
+    # parts are joined in visiting order
+    order = np.argsort(pairs[:, 1], kind="stable")
+    heads = np.flatnonzero(np.diff(pairs[order, 1], prepend=-1)) if len(order) else np.zeros(0, np.int64)
+    bounds = np.append(heads, len(order))
+
+    def visit(span):
+        g0, g1 = span
+        pos = np.full(max(n_pts, 1), -1, dtype=np.int64)
+        a_parts, b_parts, k_parts = [], [], []
+        for g in range(g0, g1):
+            ks = order[bounds[g]:bounds[g + 1]]
+            j = int(pairs[ks[0], 1])
             pos[det_ids[j]] = np.arange(len(det_ids[j]))
-            cur = j
-        h = pos[det_ids[i]]
-        hit = np.flatnonzero(h >= 0)
-        if len(hit) == 0:
-            continue
-        a_parts.append(offs[i] + hit)
-        b_parts.append(offs[j] + h[hit])
-        k_parts.append(np.full(len(hit), k, dtype=np.int64))
+            for k in ks:
+                i = int(pairs[k, 0])
+                h = pos[det_ids[i]]
+                hit = np.flatnonzero(h >= 0)
+                if len(hit) == 0:
+                    continue
+                a_parts.append(offs[i] + hit)
+                b_parts.append(offs[j] + h[hit])
+                k_parts.append(np.full(len(hit), k, dtype=np.int64))
+            pos[det_ids[j]] = -1
+        return a_parts, b_parts, k_parts
+
+    spans = _ranges(len(heads), 8 * _workers())
+    a_parts, b_parts, k_parts = [], [], []
+    for a, b, k in _pmap(visit, spans):
+        a_parts += a
+        b_parts += b
+        k_parts += k
     if not a_parts:
         e = np.zeros(0, np.float32)
         ei = np.zeros(0, np.int32)
@@ -210,31 +256,53 @@ def _emit_matches(seed, pair_list, det_ids, det_u, det_v, n_cams, width, height,
     A = np.concatenate(a_parts)
     B = np.concatenate(b_parts)
     K = np.concatenate(k_parts)
-    ci, cj = pairs[K, 0], pairs[K, 1]
-    pts = all_ids[A]
-    x1, y1 = all_u[A], all_v[A]
-    x2, y2 = all_u[B].copy(), all_v[B].copy()
-    key = ci.astype(np.uint64) * np.uint64(n_cams) + cj.astype(np.uint64)
-    out = hash_u01(seed, 40, key, pts) < outlier_frac
-    x2[out] = hash_u01(seed, 41, key[out], pts[out]) * width[cj[out]]
-    y2[out] = hash_u01(seed, 42, key[out], pts[out]) * height[cj[out]]
-    flip = hash_u01(seed, 43, key, pts) < 0.5
-    c1 = np.where(flip, cj, ci).astype(np.int32)
-    c2 = np.where(flip, ci, cj).astype(np.int32)
-    ax, ay = np.where(flip, x2, x1), np.where(flip, y2, y1)
-    bx, by = np.where(flip, x1, x2), np.where(flip, y1, y2)
-    perm = rng.permutation(len(A))
-    return (ax[perm].astype(np.float32), ay[perm].astype(np.float32),
-            bx[perm].astype(np.float32), by[perm].astype(np.float32),
-            c1[perm], c2[perm], ~out[perm])
+    del a_parts, b_parts, k_parts
+    n = len(A)
+    ax, ay, bx, by = (np.empty(n) for _ in range(4))
+    c1 = np.empty(n, np.int32)
+    c2 = np.empty(n, np.int32)
+    inl = np.empty(n, bool)
+
+    def emit(span):
+        lo, hi = span
+        Ak, Bk, Kk = A[lo:hi], B[lo:hi], K[lo:hi]
+        ci, cj = pairs[Kk, 0], pairs[Kk, 1]
+        pts = all_ids[Ak]
+        x1, y1 = all_u[Ak], all_v[Ak]
+        x2, y2 = all_u[Bk], all_v[Bk]
+        key = ci.astype(np.uint64) * np.uint64(n_cams) + cj.astype(np.uint64)
+        out = hash_u01(seed, 40, key, pts) < outlier_frac
+        x2[out] = hash_u01(seed, 41, key[out], pts[out]) * width[cj[out]]
+        y2[out] = hash_u01(seed, 42, key[out], pts[out]) * height[cj[out]]
+        flip = hash_u01(seed, 43, key, pts) < 0.5
+        c1[lo:hi] = np.where(flip, cj, ci)
+        c2[lo:hi] = np.where(flip, ci, cj)
+        ax[lo:hi], ay[lo:hi] = np.where(flip, x2, x1), np.where(flip, y2, y1)
+        bx[lo:hi], by[lo:hi] = np.where(flip, x1, x2), np.where(flip, y1, y2)
+        inl[lo:hi] = ~out
+
+    _pmap(emit, _ranges(n, 4 * _workers()))
+    del A, B, K
+    perm = rng.permutation(n)
+    res = (np.empty(n, np.float32), np.empty(n, np.float32), np.empty(n, np.float32),
+           np.empty(n, np.float32), np.empty(n, np.int32), np.empty(n, np.int32), np.empty(n, bool))
+
+    def gather(span):
+        lo, hi = span
+        pk = perm[lo:hi]
+        for dst, src in zip(res, (ax, ay, bx, by, c1, c2, inl)):
+            dst[lo:hi] = src[pk]
+
+    _pmap(gather, _ranges(n, 4 * _workers()))
+    return res
 
 
 def _detect(seed, R, t, f, cx, cy, width, height, X, p_det, sigma):
     """Per camera: sorted detected point ids and their noisy pixels."""
     n = len(R)
     ids_all = np.arange(len(X), dtype=np.int64)
-    det_ids, det_u, det_v = [], [], []
-    for c in range(n):
+
+    def one(c):
         u, v, z = _observe(R[c], t[c], f[c], cx[c], cy[c], X)
         vis = _visible(u, v, z, width[c], height[c])
         ids = ids_all[vis]
@@ -246,10 +314,10 @@ def _detect(seed, R, t, f, cx, cy, width, height, X, p_det, sigma):
         if sigma > 0:
             uu = uu + sigma * hash_normal(seed, 11, c, ids)
             vv = vv + sigma * hash_normal(seed, 12, c, ids)
-        det_ids.append(ids)
-        det_u.append(uu)
-        det_v.append(vv)
-    return det_ids, det_u, det_v
+        return ids, uu, vv
+
+    res = _pmap(one, range(n))
+    return [r[0] for r in res], [r[1] for r in res], [r[2] for r in res]
 
 
 def sphere_scene(n_cams=20, n_pts=2000, radius=4.0, focal=500.0, width=640.0,
@@ -330,10 +398,13 @@ def trajectory_scene(n_cams=500, n_pts=200_000, radius=6.0, height_wave=1.0,
     # Calibrate the detection probability on a point sample: the expected
     # number of matches is p^2 * sum over pairs of co-visible points.
     samp = rng.choice(n_pts, size=min(calib_sample, n_pts), replace=False)
-    vis = np.zeros((n_cams, len(samp)), dtype=bool)
-    for c in range(n_cams):
-        u, v, z = _observe(R[c], t[c], f[c], W[c] / 2, H[c] / 2, X[samp])
-        vis[c] = _visible(u, v, z, W[c], H[c])
+    Xs = X[samp]
+
+    def seen(c):
+        u, v, z = _observe(R[c], t[c], f[c], W[c] / 2, H[c] / 2, Xs)
+        return _visible(u, v, z, W[c], H[c])
+
+    vis = np.stack(_pmap(seen, range(n_cams))) if n_cams else np.zeros((0, len(samp)), bool)
     packed = np.packbits(vis, axis=1)
     covis = 0
     for s in range(0, len(pair_arr), 4096):
