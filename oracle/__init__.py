@@ -50,7 +50,8 @@ class Options(C.Structure):
                 ("lr_rot", C.c_double), ("lr_t", C.c_double), ("lr_logf", C.c_double),
                 ("beta1", C.c_double), ("beta2", C.c_double), ("adam_eps", C.c_double),
                 ("optimize_focal", C.c_int32), ("gauge_normalize", C.c_int32),
-                ("lr_decay", C.c_double), ("reset_moments", C.c_int32)]
+                ("lr_decay", C.c_double), ("reset_moments", C.c_int32),
+                ("converge_deg", C.c_double)]
 
 
 def lib():
@@ -286,8 +287,9 @@ def epipolar_adjust(pb: OracleProblem, R0, t0, f0, intr_group=None, options=None
                                    max_log, _p(logR), C.byref(nlog), _p(mask))
     if rc:
         raise ValueError(f"oracle epipolar_adjust failed ({rc})")
-    out = dict(R=R.reshape(N, 3, 3), t=t.reshape(N, 3), f=f, loss=losses[:opt.rounds],
-               inliers=inl[:opt.rounds], mask=mask[:pb.n_matches].astype(bool))
+    run = int(np.sum(inl[:opt.rounds] >= 0))  # rounds before an early exit
+    out = dict(R=R.reshape(N, 3, 3), t=t.reshape(N, 3), f=f, loss=losses[:run],
+               inliers=inl[:run], mask=mask[:pb.n_matches].astype(bool), rounds_run=run)
     if logR is not None:
         out["log_R"] = logR[:nlog.value].reshape(-1, N, 3, 3)
     return out

@@ -49,6 +49,7 @@ void orc_default_options(orc_options *o) {
   o->gauge_normalize = 1;
   o->lr_decay = 0.9;
   o->reset_moments = 1;
+  o->converge_deg = 0.0;
 }
 
 /* ---- small 3x3 helpers (row-major) ------------------------------------ */
@@ -611,13 +612,35 @@ int orc_epipolar_adjust(const orc_problem *pb, const orc_options *opt, const dou
   int64_t it_global = 0;
   int64_t adam_step = 0;
 
+  for (int32_t r = 0; r < opt->rounds; ++r) {
+    loss_per_round[r] = NAN;
+    inliers[r] = -1;
+  }
+  double prev_tau_px = -1.0;
   for (int32_t r = 0; r < opt->rounds && rc == 0; ++r) {
+    double tau_px = opt->tau_px_init * pow(opt->tau_decay, (double)r);
+    if (tau_px < opt->tau_px_min) tau_px = opt->tau_px_min;
+    if (opt->converge_deg > 0.0 && r > 0 && tau_px == prev_tau_px) {
+      /* early exit (a batching addition; the paper runs a fixed schedule):
+       * Rh, fh still hold the previous round's snapshot */
+      double mean_rot = 0.0, mean_f = 0.0;
+      for (int32_t c = 0; c < N; ++c) {
+        double tr = 0.0;
+        for (int k = 0; k < 9; ++k) tr += Rh[9 * c + k] * R[9 * c + k]; /* tr(Rh^T R) */
+        double ca = 0.5 * (tr - 1.0);
+        if (ca > 1.0) ca = 1.0;
+        if (ca < -1.0) ca = -1.0;
+        mean_rot += acos(ca) / N;
+        mean_f += fabs(log(f[c] / fh[c])) / N;
+      }
+      const double to_deg = 57.29577951308232; /* 180 / pi */
+      if (mean_rot * to_deg < opt->converge_deg && mean_f * to_deg < opt->converge_deg) break;
+    }
+    prev_tau_px = tau_px;
     /* snapshot and filter (Method > Epipolar Adjustment, re-weighting rounds) */
     memcpy(Rh, R, sizeof(double) * 9 * (size_t)N);
     memcpy(thh, t, sizeof(double) * 3 * (size_t)N);
     memcpy(fh, f, sizeof(double) * (size_t)N);
-    double tau_px = opt->tau_px_init * pow(opt->tau_decay, (double)r);
-    if (tau_px < opt->tau_px_min) tau_px = opt->tau_px_min;
     double tau = tau_px / median_of(fh, N);
     if (orc_residuals(pb, Rh, thh, fh, eps)) {
       rc = -2;

@@ -64,6 +64,12 @@ typedef struct {
   int32_t gauge_normalize; /* 0 none, 1 centre + median-baseline scale at start */
   double lr_decay;         /* learning rates of round r: lr * lr_decay^r */
   int32_t reset_moments;   /* 1: Adam moments (and step count) restart every round */
+  double converge_deg;     /* early exit, 0 = off: the solve stops at the start of a
+                              round whose threshold equals the previous round's when
+                              the cameras' mean rotation over that round (geodesic
+                              distance) is below converge_deg degrees and their mean
+                              |log f change| below converge_deg pi/180; the rounds
+                              not run report loss NaN and inliers -1 */
 } orc_options;
 
 void orc_default_options(orc_options *o);
