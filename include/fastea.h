@@ -94,6 +94,17 @@ typedef struct {
                               f^T W_n f with W_n summed over its matches once
                               per round, so that a step costs O(pairs) */
   int32_t reserved[3];     /* must be zero */
+  double converge_deg;     /* per-scene early exit (0 = off, default): at the
+                              start of a round whose threshold equals the
+                              previous round's (the schedule at its floor), a
+                              scene whose cameras rotated by less than
+                              converge_deg degrees on average over the
+                              previous round (geodesic distance), and whose
+                              mean |log f| change is below
+                              converge_deg * pi/180, is
+                              converged: it takes no further steps and its
+                              poses and optimiser state stay as they are;
+                              the solve ends once every scene has converged */
 } fea_options;
 
 /* What fea_epipolar_adjust did. */
@@ -105,7 +116,8 @@ typedef struct {
   double ms_total;               /* wall time of the call, milliseconds */
   int32_t n_logged;              /* pose snapshots kept (log_every > 0) */
   int32_t fallbacks;             /* learned rounds rejected by the judge (all scenes) */
-  int32_t reserved[6];
+  int32_t scenes_converged;      /* scenes the early exit stopped (converge_deg > 0) */
+  int32_t reserved[5];
 } fea_report;
 
 /* Sizes and state of a context. */
@@ -188,6 +200,15 @@ fea_status fea_set_scenes(fea_ctx *ctx, int32_t n_scenes, const int32_t *cam_sce
 fea_status fea_get_scene_stats(fea_ctx *ctx, double *loss, int64_t *retained,
                                double *gauge_center, double *gauge_scale, int32_t *learned);
 
+/* Per-scene convergence (options.converge_deg): converged_round [n_scenes]
+ * receives the round at whose start each scene was found converged (it took
+ * no steps from that round on), or -1; change_deg [n_scenes] the mean
+ * rotation of the scene's cameras over the last completed round, in
+ * degrees, as measured at the latest round start (measured only with
+ * converge_deg > 0; 0 before the second round).  Host arrays; either may be
+ * NULL. */
+fea_status fea_get_scene_convergence(fea_ctx *ctx, int32_t *converged_round, double *change_deg);
+
 /* Keypoint matches (Method > Epipolar Adjustment: point pairs Q_n of the
  * image pairs P).  Match m relates pixel (x1[m], y1[m]) of camera cam1[m] to
  * (x2[m], y2[m]) of camera cam2[m].  Host arrays of length n, copied.
@@ -205,8 +226,10 @@ fea_status fea_load_matches_device(fea_ctx *ctx, int64_t n, const float *x1_dev,
                                    const float *y2_dev, const int32_t *cam1_dev,
                                    const int32_t *cam2_dev);
 
-/* Initial poses: R [n_cams*9] row-major world-to-camera rotations, t
- * [n_cams*3]; host arrays.  Rotations must be proper (det > 0) and finite.
+/* Initial poses (Method > Optimization Formulations > Epipolar Adjustment:
+ * the adjustment starts from the global rotations and translations of the
+ * earlier stages and optimises world-to-camera poses): R [n_cams*9]
+ * row-major world-to-camera rotations, t [n_cams*3]; host arrays.  Rotations must be proper (det > 0) and finite.
  * Applies the gauge normalisation if enabled and resets the round state.
  * FEA_EDEGENERATE if two matched cameras share a centre. */
 fea_status fea_init_poses(fea_ctx *ctx, const double *R, const double *t);
@@ -227,7 +250,13 @@ fea_status fea_begin_round(fea_ctx *ctx, double tau_px);
 
 /* One pass of the residual, IRLS weight and gradient at the current poses,
  * with the current round's weights (no parameter update), by the inner loop
- * the options select (per match, or the pairs' quadratic forms).  Outputs are
+ * the options select (per match, or the pairs' quadratic forms).  The
+ * objective is the re-weighted one that follows
+ * Eq. fastmap-epipolar-objective-l2 (the L1 objective of
+ * Eq. fastmap-epipolar-objective approximated by squared residuals over the
+ * snapshot's |eps_hat|), with Z the round's retained matches and
+ * 1/max(|eps_hat|, delta) as the weight; the gradient is the one the fused
+ * kernel of Method > Kernel Fusion computes, taken per match.  Outputs are
  * device arrays, caller-allocated, any of which may be NULL:
  *   loss_dev [1]; gR_dev [n_cams*9] dL/dR (R as an unconstrained 3x3);
  *   gt_dev [n_cams*3] dL/dt; gf_dev [n_cams] dL/df.
@@ -247,11 +276,15 @@ fea_status fea_residual_grad(fea_ctx *ctx, double *loss_dev, double *gR_dev, dou
  * (any pointer may be NULL). */
 fea_status fea_get_params_dev(fea_ctx *ctx, double *a6_dev, double *t_dev, double *logf_dev);
 
-/* Forward: loss_dev [1] = L(a6, t, logf). */
+/* Forward: loss_dev [1] = L(a6, t, logf), the round's re-weighted epipolar
+ * objective (the IRLS form after Eq. fastmap-epipolar-objective-l2) at the
+ * caller's parameters. */
 fea_status fea_loss_dev(fea_ctx *ctx, const double *a6_dev, const double *t_dev,
                         const double *logf_dev, double *loss_dev);
 
-/* Backward (hand-written adjoint, forward recomputed, no per-match state kept):
+/* Backward of the same objective (Method > Kernel Fusion: forward and
+ * backward fused, here as a hand-written adjoint with the forward recomputed
+ * and no per-match state kept):
  * ga6_dev [n_cams*6], gt_dev [n_cams*3], glogf_dev [n_groups] receive
  * gout * dL/d(parameter), gout_dev [1] the upstream gradient (NULL = 1).
  * Output pointers may be NULL. */
@@ -310,12 +343,19 @@ fea_status fea_mlp_train(int32_t device, const float *feat_dev, const float *tar
 fea_status fea_mlp_grad(int32_t device, const float *feat_dev, const float *target_dev, int64_t n,
                         const float *params_dev, float *grad_dev, double *loss);
 
-/* n_steps Adam steps of the current round (each: residual, weight, gradient,
- * per-camera chain rule and update). */
+/* n_steps first-order steps of the current round (Method > First-order
+ * Optimization; Adam as the optimiser the paper cites), each a residual,
+ * weight and gradient pass over the round's objective, the per-camera chain
+ * rule through the 6D rotation (Method > Optimization Formulations > Global
+ * Rotation) and log f, and the update.  Needs a round (FEA_ESTATE). */
 fea_status fea_step(fea_ctx *ctx, int32_t n_steps);
 
-/* The whole solve: options.rounds rounds of fea_begin_round with the
- * threshold schedule max(tau_px_init * tau_decay^r, tau_px_min) followed by
+/* The whole solve (Method > Optimization Formulations > Epipolar
+ * Adjustment: the weights are recomputed and another optimisation loop run
+ * after each round, with outliers filtered by a threshold that starts large
+ * and decreases to a minimum; focal lengths folded into the essential
+ * matrices): options.rounds rounds of fea_begin_round with the threshold
+ * schedule max(tau_px_init * tau_decay^r, tau_px_min), each followed by
  * options.iters_per_round steps.  out may be NULL. */
 fea_status fea_epipolar_adjust(fea_ctx *ctx, fea_report *out);
 

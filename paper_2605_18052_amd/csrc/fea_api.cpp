@@ -167,6 +167,7 @@ bool options_valid(const fea_options* o, std::string* why) {
     return bad("learned weights with the quadratic form support tile_matches 0 or 8192 only");
   for (int k = 0; k < 3; ++k)
     if (o->reserved[k] != 0) return bad("reserved option fields must be zero");
+  if (!(o->converge_deg >= 0) || !std::isfinite(o->converge_deg)) return bad("converge_deg must be finite and >= 0");
   return true;
 }
 
@@ -180,6 +181,18 @@ double median(std::vector<double> v) {
 // Work items of the current layout: runs of <= tile matches of one pair
 // (pairs with no retained match get none), and each camera's int4 entries
 // {2n+side, first item, end item, other camera} for the epilogue.
+// No scene converged (start of a solve, new scenes).
+hipError_t clear_convergence(fea_ctx* c) {
+  c->n_done = 0;
+  c->prev_tau_px = -1.0;
+  c->scene_done_h.assign(c->S, 0);
+  hipError_t e = hipSuccess;
+  if (c->d_scene_done.p && (e = hipMemsetAsync(c->d_scene_done.p, 0, c->d_scene_done.bytes, c->stream)) != hipSuccess)
+    return e;
+  if (c->d_scene_change.p) e = hipMemsetAsync(c->d_scene_change.p, 0, c->d_scene_change.bytes, c->stream);
+  return e;
+}
+
 hipError_t build_items(fea_ctx* c) {
   const int64_t tile = fea::tile_matches_of(c->tile_cfg);
   c->h_item_pair.clear();
@@ -197,10 +210,13 @@ hipError_t build_items(fea_ctx* c) {
   c->h_pair_item_off[c->P] = (int32_t)c->h_item_pair.size();
   c->n_items = (int64_t)c->h_item_pair.size();
   c->h_item_rec.assign(4 * c->n_items, 0);
+  const bool flags = c->n_done > 0 && (int)c->scene_done_h.size() == c->S;
   for (int64_t it = 0; it < c->n_items; ++it) {
     c->h_item_rec[4 * it] = c->h_item_pair[it];
     c->h_item_rec[4 * it + 1] = c->h_item_start[it];
     c->h_item_rec[4 * it + 2] = c->h_item_count[it];
+    // items of converged scenes are skipped by the steps
+    c->h_item_rec[4 * it + 3] = flags && c->scene_done_h[c->pair_scene[c->h_item_pair[it]]] != 0 ? 1 : 0;
   }
   c->h_cam_ent4.assign(4 * 2 * c->P, 0);
   for (size_t e = 0; e < c->cam_ent.size(); ++e) {
@@ -244,6 +260,9 @@ hipError_t alloc_scene_arrays(fea_ctx* c) {
   if ((e = dalloc(c->d_fbar_hist, 3 * (size_t)c->S * sizeof(double))) != hipSuccess) return e;
   if ((e = dalloc(c->d_tau, (size_t)c->S * sizeof(double))) != hipSuccess) return e;
   if ((e = dalloc(c->d_scene_z, ((size_t)c->S + 1) * sizeof(int64_t))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_scene_done, (size_t)c->S * sizeof(int32_t))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_scene_change, (size_t)c->S * sizeof(double))) != hipSuccess) return e;
+  if ((e = upload(c, c->d_cam_scene, c->cam_scene.data(), c->cam_scene.size())) != hipSuccess) return e;
   // cameras of each scene, for the device round start
   std::vector<int32_t> off(c->S + 1, 0), cams(c->N, 0);
   for (int i = 0; i < c->N; ++i) off[c->cam_scene[i] + 1] += 1;
@@ -259,6 +278,7 @@ hipError_t alloc_scene_arrays(fea_ctx* c) {
   c->host_tau_stale = c->host_z_stale = false;
   if ((e = hipMemsetAsync(c->d_inv_zw.p, 0, c->d_inv_zw.bytes, c->stream)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(c->d_scene_mode.p, 0, c->d_scene_mode.bytes, c->stream)) != hipSuccess) return e;
+  if ((e = clear_convergence(c)) != hipSuccess) return e;
   c->scene_mode.assign(c->S, 0);
   c->scene_learned_ok.assign(c->S, 1);
   return hipSuccess;
@@ -510,7 +530,7 @@ hipError_t issue_step(fea_ctx* c) {
   // Per match: the pose table holds F at the current poses; after the
   // update it is rebuilt at the new ones for the next step.
   const bool quad = c->opt.inner_loop == 1;
-  hipError_t e = quad ? hipSuccess : fea::launch_resgrad(c);
+  hipError_t e = quad ? hipSuccess : fea::launch_resgrad(c, true);
   if (e == hipSuccess) e = fea::launch_camgrad(c, 1, quad);
   if (e == hipSuccess && !c->all_single) e = fea::launch_focal_update(c);
   const int nx = c->pcur ^ 1;
@@ -654,8 +674,14 @@ hipError_t quad_round(fea_ctx* c) {
   }
   std::vector<int32_t> keep;
   if ((e = download(c, keep, c->item_keep, c->n_items)) != hipSuccess) return e;
-  c->Zs.assign(c->S, 0);
-  for (int64_t it = 0; it < c->n_items; ++it) c->Zs[c->pair_scene[c->h_item_pair[it]]] += keep[it];
+  // a converged scene keeps its count (its items were not passed over)
+  const bool frozen = c->opt.converge_deg > 0 && c->n_done > 0 && (int)c->Zs.size() == c->S &&
+                      (int)c->scene_done_h.size() == c->S;
+  std::vector<int64_t> zs(c->S, 0);
+  for (int64_t it = 0; it < c->n_items; ++it) zs[c->pair_scene[c->h_item_pair[it]]] += keep[it];
+  if ((int)c->Zs.size() != c->S) c->Zs.assign(c->S, 0);
+  for (int sc = 0; sc < c->S; ++sc)
+    if (!(frozen && c->scene_done_h[sc] != 0)) c->Zs[sc] = zs[sc];
   c->Z = 0;
   std::vector<float> inv(c->S, 0.f);
   for (int sc = 0; sc < c->S; ++sc) {
@@ -668,8 +694,9 @@ hipError_t quad_round(fea_ctx* c) {
     if ((e = download(c, ws, c->item_wsum, c->n_items)) != hipSuccess) return e;
     std::vector<double> zw(c->S, 0.0);
     for (int64_t it = 0; it < c->n_items; ++it) zw[c->pair_scene[c->h_item_pair[it]]] += ws[it];
-    c->inv_zw_h.assign(c->S, 0.f);
-    for (int sc = 0; sc < c->S; ++sc) c->inv_zw_h[sc] = zw[sc] > 0 ? (float)(1.0 / zw[sc]) : 0.f;
+    if ((int)c->inv_zw_h.size() != c->S) c->inv_zw_h.assign(c->S, 0.f);
+    for (int sc = 0; sc < c->S; ++sc)
+      if (!(frozen && c->scene_done_h[sc] != 0)) c->inv_zw_h[sc] = zw[sc] > 0 ? (float)(1.0 / zw[sc]) : 0.f;
     if ((e = upload(c, c->d_inv_zw, c->inv_zw_h.data(), c->S)) != hipSuccess) return e;
   }
   c->host_z_stale = false;
@@ -708,6 +735,16 @@ hipError_t round_weights(fea_ctx* c, bool choose_mode) {
 // the device's compaction).
 fea_status begin_round(fea_ctx* c, double tau_px, bool sync) {
   const size_t N = c->N;
+  if (c->opt.converge_deg > 0 && c->round >= 0) {
+    // per-scene convergence over the round that just ended (before its
+    // snapshot is replaced); a scene can converge only while the threshold
+    // schedule stays put
+    HIP_OR_FAIL(c, fea::launch_scene_converge(c, tau_px == c->prev_tau_px, c->round + 1));
+    HIP_OR_FAIL(c, download(c, c->scene_done_h, c->d_scene_done, (size_t)c->S));
+    c->n_done = 0;
+    for (int sc = 0; sc < c->S; ++sc) c->n_done += c->scene_done_h[sc] != 0 ? 1 : 0;
+  }
+  c->prev_tau_px = tau_px;
   // snapshot and its history (learned features), round parameters for the
   // judge's restore, and (new objective) fresh Adam moments -- one kernel
   const bool zero = c->opt.reset_moments || c->round < 0;
@@ -786,7 +823,7 @@ fea_status begin_round(fea_ctx* c, double tau_px, bool sync) {
 
 
 constexpr char kStateMagic[8] = {'F', 'E', 'A', 'S', 'T', 'A', 'T', 'E'};
-constexpr int32_t kStateVersion = 1;
+constexpr int32_t kStateVersion = 2;
 
 // Fixed header of a checkpoint; the sections listed in state_sections and
 // the retained-match bit mask follow it.
@@ -799,6 +836,7 @@ struct StateHdr {
   int32_t round, step, n_logged, fallbacks, tile_cfg, pcur, learned_any, have_mlp;
   int64_t adam_t, global_step;
   double tau, lr_scale;
+  double prev_tau_px;  // threshold of the last round begun (early exit)
 };
 
 uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
@@ -838,7 +876,8 @@ std::vector<std::pair<DBuf*, size_t>> state_sections(fea_ctx* c) {
           {&c->Rh, 9 * N * d},   {&c->Th, 3 * N * d},   {&c->Fh, N * d},      {&c->Rh1, 9 * N * d},
           {&c->Th1, 3 * N * d},  {&c->Fh1, N * d},      {&c->Rh2, 9 * N * d}, {&c->Th2, 3 * N * d},
           {&c->Fh2, N * d},      {&c->a6h, 6 * N * d},  {&c->tph, 3 * N * d}, {&c->logfh, G * d},
-          {&c->counters, sizeof(fea::StepCounters)}, {&c->qW, (size_t)c->P * 45 * d}};
+          {&c->counters, sizeof(fea::StepCounters)}, {&c->qW, (size_t)c->P * 45 * d},
+          {&c->d_scene_done, (size_t)c->S * sizeof(int32_t)}};
 }
 
 size_t state_bytes(fea_ctx* c) {
@@ -1244,6 +1283,7 @@ fea_status fea_init_poses(fea_ctx* c, const double* R, const double* t) {
     HIP_OR_FAIL(c, dalloc(c->logR, (size_t)c->opt.max_log * 9 * c->N * sizeof(double)));
   drop_graph(c);
   reset_round_state(c);
+  HIP_OR_FAIL(c, clear_convergence(c));
   c->adam_t = 0;
   HIP_OR_FAIL(c, set_counters(c, 0, 0));
   c->scene_learned_ok.assign(c->S, 1);
@@ -1379,6 +1419,7 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
     const double tau_px = std::max(c->opt.tau_px_init * std::pow(c->opt.tau_decay, (double)r), c->opt.tau_px_min);
     fea_status s = begin_round(c, tau_px, false);
     if (s != FEA_OK) return s;
+    if (c->opt.converge_deg > 0 && c->n_done == c->S) break;  // every scene converged
     std::vector<double> l0, l1;
     if (c->learned_any) {
       s = plain_loss_per_scene(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), l0);
@@ -1428,7 +1469,23 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
   rep.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   rep.n_logged = c->n_logged;
   rep.fallbacks = c->fallbacks;
+  rep.scenes_converged = c->n_done;
   if (out) *out = rep;
+  return FEA_OK;
+}
+
+fea_status fea_get_scene_convergence(fea_ctx* c, int32_t* converged_round, double* change_deg) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
+  DeviceGuard g(c->device);
+  std::vector<int32_t> done;
+  std::vector<double> ch;
+  HIP_OR_FAIL(c, download(c, done, c->d_scene_done, (size_t)c->S));
+  HIP_OR_FAIL(c, download(c, ch, c->d_scene_change, (size_t)c->S));
+  for (int s = 0; s < c->S; ++s) {
+    if (converged_round) converged_round[s] = done[s] - 1;
+    if (change_deg) change_deg[s] = ch[s];
+  }
   return FEA_OK;
 }
 
@@ -1554,6 +1611,7 @@ fea_status fea_get_state(fea_ctx* c, void* buf, size_t* len) {
   h.global_step = c->global_step;
   h.tau = c->tau;
   h.lr_scale = c->lr_scale;
+  h.prev_tau_px = c->prev_tau_px;
   uint8_t* w = static_cast<uint8_t*>(buf);
   put(w, &h, 1);
   for (auto& sec : state_sections(c)) {
@@ -1647,8 +1705,13 @@ fea_status fea_set_state(fea_ctx* c, const void* buf, size_t len) {
   c->global_step = h.global_step;
   c->tau = h.tau;
   c->lr_scale = h.lr_scale;
+  c->prev_tau_px = h.prev_tau_px;
   c->have_poses = true;
   drop_graph(c);
+  // converged scenes (their flags came with the sections)
+  HIP_OR_FAIL(c, download(c, c->scene_done_h, c->d_scene_done, S));
+  c->n_done = 0;
+  for (size_t sc = 0; sc < S; ++sc) c->n_done += c->scene_done_h[sc] != 0 ? 1 : 0;
   // rebuild the live layout: the full one, then the saved retained set
   c->tile_cfg = h.tile_cfg;
   c->tile_tuned = true;
@@ -1677,6 +1740,10 @@ fea_status fea_set_state(fea_ctx* c, const void* buf, size_t len) {
         inv[sc] = c->Zs[sc] > 0 ? (float)(1.0 / (double)c->Zs[sc]) : 0.f;
       }
       HIP_OR_FAIL(c, upload(c, c->d_inv_z, inv.data(), S));
+      // the device's per-scene counts (converged scenes keep theirs)
+      std::vector<int64_t> zd(c->Zs);
+      zd.push_back(c->Z);
+      HIP_OR_FAIL(c, upload(c, c->d_scene_z, zd.data(), zd.size()));
     } else {
       DBuf d_bits;
       hipError_t e = upload(c, d_bits, bits.data(), bits.size());

@@ -89,10 +89,35 @@ __global__ __launch_bounds__(256) void k_camgrad(
     int focal_inline, int optimize_focal, const int32_t* __restrict__ group, double* __restrict__ a6,
     double* __restrict__ tp, double* __restrict__ logf, double* __restrict__ m_a6, double* __restrict__ v_a6,
     double* __restrict__ m_t, double* __restrict__ v_t, double* __restrict__ m_f, double* __restrict__ v_f,
-    AdamArgs ad, StepCtl sc, double* __restrict__ Rn, double* __restrict__ Tn, double* __restrict__ Fn) {
+    AdamArgs ad, StepCtl sc, double* __restrict__ Rn, double* __restrict__ Tn, double* __restrict__ Fn,
+    const int32_t* __restrict__ cam_scene, const int32_t* __restrict__ scene_done) {
   const int cam = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (cam >= N) return;  // uniform per wave
+  if (do_update && scene_done != nullptr && scene_done[cam_scene[cam]] != 0) {
+    // a converged scene takes no step: its poses carry over to the next
+    // parity unchanged (the rotation log still records them) and its
+    // gradient, loss and optimiser state are left as they are
+    const int p = sc.p;
+    const long long t_glob = sc.ctr->global_t[p] + 1;
+    if (cam == 0 && lane == 0) {
+      sc.ctr->adam_t[p ^ 1] = sc.ctr->adam_t[p] + 1;
+      sc.ctr->global_t[p ^ 1] = t_glob;
+      sc.ctr->b1t[p ^ 1] = sc.ctr->b1t[p] * ad.b1;
+      sc.ctr->b2t[p ^ 1] = sc.ctr->b2t[p] * ad.b2;
+    }
+    if (lane < 9) {
+      const double r = R[9 * cam + lane];
+      Rn[9 * cam + lane] = r;
+      if (sc.log_every > 0 && t_glob % sc.log_every == 0) {
+        const long long slot = t_glob / sc.log_every - 1;
+        if (slot < sc.max_log) sc.logR[(slot * N + cam) * 9 + lane] = r;
+      }
+    }
+    if (lane < 3) Tn[3 * cam + lane] = T[3 * cam + lane];
+    if (lane == 0 && focal_inline) Fn[cam] = Fc[cam];
+    return;
+  }
   // optimiser state, fetched before the pair loop: lane k < 6 owns 6D
   // coordinate k, lanes 6..8 the translation, lane 9 log f (single-camera
   // intrinsics groups); every update lane also needs the whole 6D vector
@@ -242,13 +267,15 @@ __global__ __launch_bounds__(kFocalThreads) void k_focal_update(
     int G, const int32_t* __restrict__ grp_off, const int32_t* __restrict__ grp_cams,
     const double* __restrict__ gf, const double* __restrict__ Fc, int optimize_focal, double* __restrict__ logf,
     double* __restrict__ m_f, double* __restrict__ v_f, AdamArgs ad, const StepCounters* __restrict__ ctr, int pn,
-    double* __restrict__ Fn) {
+    double* __restrict__ Fn, const int32_t* __restrict__ cam_scene, const int32_t* __restrict__ scene_done) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   const int b = grp_off[g], e = grp_off[g + 1];
   if (b == e) return;
   double p = logf[g];
-  if (optimize_focal) {
+  // a group lies in one scene; a converged scene's focal length stays
+  const bool frozen = scene_done != nullptr && scene_done[cam_scene[grp_cams[b]]] != 0;
+  if (optimize_focal && !frozen) {
     double s = 0.0;
     for (int k = b; k < e; ++k) {
       const int c = grp_cams[k];
@@ -425,6 +452,61 @@ __global__ __launch_bounds__(kTauThreads) void k_scene_tau(int S, const int32_t*
   }
 }
 
+// Per-scene convergence test at a round start (before the snapshot is
+// replaced): one workgroup per scene takes the mean over its cameras of the
+// rotation between the previous round's snapshot and the current poses,
+// 2 asin(|R - R_hat|_F / (2 sqrt 2)) (the geodesic angle, written for
+// accuracy at small angles), and the mean |log(f / f_hat)|, both in
+// degrees (per-thread sums, a fixed-order wave and workgroup sum).  With
+// `check` (this round's threshold equals the previous round's) a scene
+// still active whose two figures are below tol_deg is marked converged at
+// `round` (stored as round + 1).
+constexpr int kConvThreads = 256;
+
+__global__ __launch_bounds__(kConvThreads) void k_scene_converge(
+    const int32_t* __restrict__ scene_cam_off, const int32_t* __restrict__ scene_cams,
+    const double* __restrict__ Rh, const double* __restrict__ Fh, const double* __restrict__ R,
+    const double* __restrict__ F, int check, int round, double tol_deg, int32_t* __restrict__ done,
+    double* __restrict__ change) {
+  __shared__ double s_rot[kConvThreads / kWave], s_foc[kConvThreads / kWave];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int b = scene_cam_off[s], e = scene_cam_off[s + 1];
+  double rot = 0.0, foc = 0.0;
+  for (int k = b + tid; k < e; k += kConvThreads) {
+    const int c = scene_cams[k];
+    double d2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const double d = R[9 * c + q] - Rh[9 * c + q];
+      d2 = fma(d, d, d2);
+    }
+    const double half = fmin(1.0, sqrt(d2) / (2.0 * 1.4142135623730951));
+    rot += 2.0 * asin(half);
+    foc += fabs(log(F[c] / Fh[c]));
+  }
+  rot = wave_sum_f64(rot);
+  foc = wave_sum_f64(foc);
+  if ((tid & 63) == 0) {
+    s_rot[tid >> 6] = rot;
+    s_foc[tid >> 6] = foc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    rot = 0.0;
+    foc = 0.0;
+    for (int w = 0; w < kConvThreads / kWave; ++w) {
+      rot += s_rot[w];
+      foc += s_foc[w];
+    }
+    const double to_deg = 57.29577951308232;
+    const double n = (double)max(e - b, 1);
+    rot = rot / n * to_deg;
+    foc = foc / n * to_deg;
+    change[s] = rot;
+    if (check && done[s] == 0 && rot < tol_deg && foc < tol_deg) done[s] = round + 1;
+  }
+}
+
 // Per-scene normalisers of a quadratic-form round on the device (each
 // scene's items contiguous): Z_s = survivors (exact, int64) and, on learned
 // rounds, Z_w = sum of the survivors' learned weights (per-thread sums over
@@ -435,10 +517,12 @@ __global__ __launch_bounds__(kTauThreads) void k_scene_z(const int32_t* __restri
                                                          const int32_t* __restrict__ keep,
                                                          const double* __restrict__ wsum, int learned,
                                                          int64_t* __restrict__ zs, float* __restrict__ inv_z,
-                                                         float* __restrict__ inv_zw) {
+                                                         float* __restrict__ inv_zw,
+                                                         const int32_t* __restrict__ scene_done) {
   __shared__ long long s_z[kTauThreads];
   __shared__ double s_w[kTauThreads];
   const int s = blockIdx.x, t = threadIdx.x;
+  if (scene_done != nullptr && scene_done[s] != 0) return;  // a converged scene keeps its counts
   const int b = scene_item_off[s], e = scene_item_off[s + 1], n = e - b;
   const int per = (n + kTauThreads - 1) / kTauThreads;
   long long z = 0;
@@ -533,7 +617,8 @@ hipError_t launch_camgrad(fea_ctx* c, int do_update, bool quad) {
       c->opt.optimize_focal, c->d_group.as<int32_t>(), c->a6.as<double>(), c->tp.as<double>(),                 \
       c->logf.as<double>(), c->m_a6.as<double>(), c->v_a6.as<double>(), c->m_t.as<double>(),                   \
       c->v_t.as<double>(), c->m_f.as<double>(), c->v_f.as<double>(), adam_args(c), step_ctl(c),                \
-      c->R[nx].as<double>(), c->T[nx].as<double>(), c->Fc[nx].as<double>()
+      c->R[nx].as<double>(), c->T[nx].as<double>(), c->Fc[nx].as<double>(), c->d_cam_scene.as<int32_t>(),     \
+      c->opt.converge_deg > 0 ? c->d_scene_done.as<int32_t>() : nullptr
   if (quad)
     k_camgrad<true><<<blocks, 256, 0, c->stream>>>(FEA_CAMGRAD_ARGS);
   else
@@ -551,7 +636,7 @@ hipError_t launch_camgrad_at(fea_ctx* c, const double* R, const double* T, const
       c->N, c->d_cam_off.as<int32_t>(), c->d_cam_ent.as<int4>(), c->part.as<double>(), nullptr, R, T, F,
       c->gR.as<double>(), c->gt.as<double>(), c->gf.as<double>(), c->loss_cam.as<double>(), 0, 0, 0,
       c->d_group.as<int32_t>(), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-      adam_args(c), step_ctl(c), nullptr, nullptr, nullptr);
+      adam_args(c), step_ctl(c), nullptr, nullptr, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -561,7 +646,8 @@ hipError_t launch_focal_update(fea_ctx* c) {
   k_focal_update<<<(unsigned)((c->G + kFocalThreads - 1) / kFocalThreads), kFocalThreads, 0, c->stream>>>(
       c->G, c->d_grp_off.as<int32_t>(), c->d_grp_cams.as<int32_t>(), c->gf.as<double>(),
       c->Fc[c->pcur].as<double>(), c->opt.optimize_focal, c->logf.as<double>(), c->m_f.as<double>(),
-      c->v_f.as<double>(), adam_args(c), c->counters.as<StepCounters>(), c->pcur ^ 1, c->Fc[nx].as<double>());
+      c->v_f.as<double>(), adam_args(c), c->counters.as<StepCounters>(), c->pcur ^ 1, c->Fc[nx].as<double>(),
+      c->d_cam_scene.as<int32_t>(), c->opt.converge_deg > 0 ? c->d_scene_done.as<int32_t>() : nullptr);
   return hipGetLastError();
 }
 
@@ -579,11 +665,22 @@ hipError_t launch_scene_tau(fea_ctx* c, double tau_px, bool first) {
   return hipGetLastError();
 }
 
+hipError_t launch_scene_converge(fea_ctx* c, bool check, int32_t round) {
+  if (c->S == 0) return hipSuccess;
+  const int p = c->pcur;
+  k_scene_converge<<<(unsigned)c->S, kConvThreads, 0, c->stream>>>(
+      c->d_scene_cam_off.as<int32_t>(), c->d_scene_cams.as<int32_t>(), c->Rh.as<double>(), c->Fh.as<double>(),
+      c->R[p].as<double>(), c->Fc[p].as<double>(), check ? 1 : 0, round, c->opt.converge_deg,
+      c->d_scene_done.as<int32_t>(), c->d_scene_change.as<double>());
+  return hipGetLastError();
+}
+
 hipError_t launch_scene_z(fea_ctx* c) {
   if (c->S == 0) return hipSuccess;
   k_scene_z<<<(unsigned)c->S, kTauThreads, 0, c->stream>>>(
       c->d_scene_item_off.as<int32_t>(), c->item_keep.as<int32_t>(), c->item_wsum.as<double>(),
-      c->learned_any ? 1 : 0, c->d_scene_z.as<int64_t>(), c->d_inv_z.as<float>(), c->d_inv_zw.as<float>());
+      c->learned_any ? 1 : 0, c->d_scene_z.as<int64_t>(), c->d_inv_z.as<float>(), c->d_inv_zw.as<float>(),
+      c->opt.converge_deg > 0 ? c->d_scene_done.as<int32_t>() : nullptr);
   k_total_z<<<1, 1, 0, c->stream>>>(c->S, c->d_scene_z.as<int64_t>());
   return hipGetLastError();
 }

@@ -181,6 +181,14 @@ struct fea_ctx {
   fea::DBuf d_scene_mode;                 // int32 [S]: 1 = learned weights this round, 0 = plain
   fea::DBuf a6h, tph, logfh;              // parameters at the round snapshot (judge fallback)
   fea::DBuf restore_flag;                 // int32 [N] cameras to restore
+
+  // per-scene early exit (options.converge_deg > 0)
+  fea::DBuf d_cam_scene;                  // int32 [N]: scene of each camera
+  fea::DBuf d_scene_done;                 // int32 [S]: 0 active, r + 1 once converged at round r
+  fea::DBuf d_scene_change;               // double [S]: largest camera rotation over the last round, degrees
+  std::vector<int32_t> scene_done_h;      // host copy of d_scene_done (read at every round start)
+  int32_t n_done = 0;                     // converged scenes
+  double prev_tau_px = -1.0;              // threshold of the previous round, pixels (-1: none yet)
   bool have_mlp = false;
   bool learned_any = false;               // some scene uses learned weights this round
   std::vector<int32_t> scene_mode;        // host copy of d_scene_mode
@@ -216,7 +224,7 @@ hipError_t segment_matches(fea_ctx* c, const float* x1, const float* y1, const f
 // --- per-match pass (fea_resgrad.hip) ---
 hipError_t launch_pair_pose(fea_ctx* c, const double* R, const double* T, const double* F, bool snap);
 hipError_t launch_resgrad_kernel(fea_ctx* c, int cfg, bool loss_only, bool force_plain);
-hipError_t launch_resgrad(fea_ctx* c);
+hipError_t launch_resgrad(fea_ctx* c, bool step = false);
 hipError_t launch_resgrad_cfg(fea_ctx* c, int cfg);
 hipError_t launch_resgrad_at(fea_ctx* c, int cfg, const double* R, const double* T, const double* F,
                              bool loss_only, bool force_plain);
@@ -236,6 +244,7 @@ hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero);
 hipError_t launch_scene_tau(fea_ctx* c, double tau_px, bool first);
 hipError_t launch_scene_z(fea_ctx* c);
 hipError_t launch_scene_loss(fea_ctx* c);
+hipError_t launch_scene_converge(fea_ctx* c, bool check, int32_t round);
 hipError_t run_ablation(fea_ctx* c, int variant, int reps, double* ms, float* pair_sum_dev);
 hipError_t launch_camgrad_at(fea_ctx* c, const double* R, const double* T, const double* F);
 

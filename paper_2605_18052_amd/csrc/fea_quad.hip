@@ -57,7 +57,8 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
     int32_t n_items, const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
     const float4* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ ptab,
     const ushort4* __restrict__ Wl, uchar4* __restrict__ mask, double delta, double* __restrict__ qpart,
-    int32_t* __restrict__ keep, double* __restrict__ wkept) {
+    int32_t* __restrict__ keep, double* __restrict__ wkept, const int32_t* __restrict__ pair_scene,
+    const int32_t* __restrict__ scene_done) {
   __shared__ double s_t[kBuildItems][kBuildGroups][kQuad + 1];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
@@ -65,6 +66,8 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
   if (item >= n_items) return;  // the whole wave
   const int4 rec = items[item];
   const int n = rec.x;
+  // a converged scene keeps its mask, counts and sums from its last round
+  if (scene_done != nullptr && scene_done[pair_scene[n]] != 0) return;
   const int v0 = rec.y >> 2;
   const int cnt = rec.z;
   const int nvec = (cnt + kVec - 1) / kVec;
@@ -189,10 +192,13 @@ __global__ void k_mask_slots(int64_t n, const unsigned char* __restrict__ mask, 
 __global__ __launch_bounds__(kQuadThreads) void k_quad_reduce(int32_t P, const int32_t* __restrict__ pair_item_off,
                                                               const double* __restrict__ ptab,
                                                               const double* __restrict__ qpart,
-                                                              double* __restrict__ qW) {
+                                                              double* __restrict__ qW,
+                                                              const int32_t* __restrict__ pair_scene,
+                                                              const int32_t* __restrict__ scene_done) {
   const int64_t t = (int64_t)blockIdx.x * kQuadThreads + threadIdx.x;
   if (t >= (int64_t)P * kQuad) return;
   const int n = (int)(t / kQuad), k = (int)(t % kQuad);
+  if (scene_done != nullptr && scene_done[pair_scene[n]] != 0) return;  // keeps its last round's form
   const double* row = ptab + (int64_t)n * kPairRow;
   const double inv_z = row[kRowMode] != 0.0 ? row[kRowInvZw] : row[kRowInvZ];
   double s = 0.0;
@@ -213,7 +219,8 @@ hipError_t launch_quad_build(fea_ctx* c) {
 #define FEA_QUAD_BUILD_ARGS                                                                                 \
   c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(), \
       c->item_rec.as<int4>(), c->ptab.as<double>(), c->wlay.as<ushort4>(), c->qmask.as<uchar4>(), c->opt.delta,  \
-      c->qpart.as<double>(), c->item_keep.as<int32_t>(), c->item_wsum.as<double>()
+      c->qpart.as<double>(), c->item_keep.as<int32_t>(), c->item_wsum.as<double>(),                          \
+      c->d_pair_scene.as<int32_t>(), c->opt.converge_deg > 0 ? c->d_scene_done.as<int32_t>() : nullptr
   const unsigned blocks = (unsigned)((c->n_items + kBuildItems - 1) / kBuildItems);
   if (c->learned_any)
     k_quad_build<true><<<blocks, kQuadThreads, 0, c->stream>>>((int32_t)c->n_items, FEA_QUAD_BUILD_ARGS);
@@ -247,7 +254,8 @@ hipError_t launch_quad_reduce(fea_ctx* c, const int32_t* pair_item_off_dev) {
   if (e != hipSuccess) return e;
   const int64_t t = c->P * kQuad;
   k_quad_reduce<<<(unsigned)((t + kQuadThreads - 1) / kQuadThreads), kQuadThreads, 0, c->stream>>>(
-      (int32_t)c->P, pair_item_off_dev, c->ptab.as<double>(), c->qpart.as<double>(), c->qW.as<double>());
+      (int32_t)c->P, pair_item_off_dev, c->ptab.as<double>(), c->qpart.as<double>(), c->qW.as<double>(),
+      c->d_pair_scene.as<int32_t>(), c->opt.converge_deg > 0 ? c->d_scene_done.as<int32_t>() : nullptr);
   return hipGetLastError();
 }
 

@@ -94,11 +94,15 @@ template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
 __global__ __launch_bounds__(THREADS) void k_resgrad(
     const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
     const float4* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ ptab, float delta,
-    double* __restrict__ part, const ushort4* __restrict__ Wl, const uchar4* __restrict__ qmask) {
+    double* __restrict__ part, const ushort4* __restrict__ Wl, const uchar4* __restrict__ qmask,
+    int skip_flagged) {
   __shared__ float s_red[THREADS / kWave][kPartStride];
   const int tid = threadIdx.x;
   const int item = blockIdx.x;
   const int4 rec = items[item];
+  // a step skips the items of converged scenes (flag in the record's last
+  // field); their partials are not read by the update
+  if (skip_flagged && rec.w != 0) return;
   const int n = rec.x;
   const int v0 = rec.y >> 2;
   const int cnt = rec.z;
@@ -349,7 +353,7 @@ hipError_t launch_pair_pose(fea_ctx* c, const double* R, const double* T, const 
 // With ev0/ev1 set the dispatch itself records the two events at the
 // kernel's start and end (no separate marker packets around it).
 template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
-hipError_t launch_resgrad_t(fea_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_resgrad_t(fea_ctx* c, hipEvent_t ev0, hipEvent_t ev1, int skip) {
   const int b = c->cur;
   const dim3 grid((unsigned)c->n_items), block(THREADS);
   const float4 *x1 = c->lay[b][0].as<float4>(), *y1 = c->lay[b][1].as<float4>(), *x2 = c->lay[b][2].as<float4>(),
@@ -362,35 +366,37 @@ hipError_t launch_resgrad_t(fea_ctx* c, hipEvent_t ev0, hipEvent_t ev1) {
   const uchar4* qm = c->opt.inner_loop == 1 ? c->qmask.as<uchar4>() : nullptr;
   if (ev0)
     hipExtLaunchKernelGGL(k_resgrad<THREADS, STEPS, LOSS_ONLY, WEIGHTED>, grid, block, 0, c->stream, ev0, ev1, 0,
-                          x1, y1, x2, y2, items, ptab, delta, part, wl, qm);
+                          x1, y1, x2, y2, items, ptab, delta, part, wl, qm, skip);
   else
     k_resgrad<THREADS, STEPS, LOSS_ONLY, WEIGHTED><<<grid, block, 0, c->stream>>>(x1, y1, x2, y2, items, ptab,
-                                                                                  delta, part, wl, qm);
+                                                                                  delta, part, wl, qm, skip);
   return hipGetLastError();
 }
 
 template <bool LOSS_ONLY, bool WEIGHTED>
-hipError_t launch_resgrad_sel(fea_ctx* c, int cfg, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_resgrad_sel(fea_ctx* c, int cfg, hipEvent_t ev0, hipEvent_t ev1, int skip) {
   switch (cfg) {
-    case 0: return launch_resgrad_t<256, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
-    case 1: return launch_resgrad_t<256, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
-    case 2: return launch_resgrad_t<256, 1, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
-    case 3: return launch_resgrad_t<128, 8, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
-    case 4: return launch_resgrad_t<128, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
-    case 5: return launch_resgrad_t<128, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
-    case 6: return launch_resgrad_t<512, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
-    case 7: return launch_resgrad_t<512, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1);
+    case 0: return launch_resgrad_t<256, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
+    case 1: return launch_resgrad_t<256, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
+    case 2: return launch_resgrad_t<256, 1, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
+    case 3: return launch_resgrad_t<128, 8, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
+    case 4: return launch_resgrad_t<128, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
+    case 5: return launch_resgrad_t<128, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
+    case 6: return launch_resgrad_t<512, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
+    case 7: return launch_resgrad_t<512, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_resgrad_timed(fea_ctx* c, int cfg, bool loss_only, bool force_plain, hipEvent_t ev0,
-                                hipEvent_t ev1) {
+                                hipEvent_t ev1, int skip = 0) {
   if (c->n_items == 0) return hipSuccess;
   const bool w = c->learned_any && !force_plain;
   if (loss_only)
-    return w ? launch_resgrad_sel<true, true>(c, cfg, ev0, ev1) : launch_resgrad_sel<true, false>(c, cfg, ev0, ev1);
-  return w ? launch_resgrad_sel<false, true>(c, cfg, ev0, ev1) : launch_resgrad_sel<false, false>(c, cfg, ev0, ev1);
+    return w ? launch_resgrad_sel<true, true>(c, cfg, ev0, ev1, skip)
+             : launch_resgrad_sel<true, false>(c, cfg, ev0, ev1, skip);
+  return w ? launch_resgrad_sel<false, true>(c, cfg, ev0, ev1, skip)
+           : launch_resgrad_sel<false, false>(c, cfg, ev0, ev1, skip);
 }
 
 // The per-match kernel alone, with tile shape `cfg`, over the current items;
@@ -414,10 +420,11 @@ hipError_t launch_resgrad_cfg(fea_ctx* c, int cfg) {
                            c->Fc[c->pcur].as<double>(), false, false);
 }
 
-// One step's per-match pass at the current poses (the pose table must hold
-// them: launch_pair_pose wrote it after the previous update); with kernel
-// timing on, the dispatch records a pair of HIP events at its start and end.
-hipError_t launch_resgrad(fea_ctx* c) {
+// One per-match pass at the current poses (the pose table must hold them:
+// launch_pair_pose wrote it after the previous update); with kernel timing
+// on, the dispatch records a pair of HIP events at its start and end.  A
+// step (step = true) skips the items of converged scenes.
+hipError_t launch_resgrad(fea_ctx* c, bool step) {
   if (c->n_items == 0) return hipSuccess;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (c->timing) {
@@ -431,7 +438,7 @@ hipError_t launch_resgrad(fea_ctx* c) {
     ev1 = c->ev_pool[c->ev_used + 1];
     c->ev_used += 2;
   }
-  return launch_resgrad_timed(c, c->tile_cfg, false, false, ev0, ev1);
+  return launch_resgrad_timed(c, c->tile_cfg, false, false, ev0, ev1, step && c->opt.converge_deg > 0 ? 1 : 0);
 }
 
 hipError_t launch_filter_count(fea_ctx* c, const uint32_t* mask) {

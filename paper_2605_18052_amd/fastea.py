@@ -32,14 +32,14 @@ class fea_options(C.Structure):
                 ("lr_decay", C.c_double), ("reset_moments", C.c_int32),
                 ("tile_matches", C.c_int32), ("use_graphs", C.c_int32),
                 ("weight_mode", C.c_int32), ("inner_loop", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("reserved", C.c_int32 * 3), ("converge_deg", C.c_double)]
 
 
 class fea_report(C.Structure):
     _fields_ = [("rounds_run", C.c_int32), ("iters_run", C.c_int32),
                 ("inliers_per_round", C.c_int64 * 64), ("loss_per_round", C.c_double * 64),
                 ("ms_total", C.c_double), ("n_logged", C.c_int32), ("fallbacks", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("scenes_converged", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class fea_info(C.Structure):
@@ -72,6 +72,7 @@ _SIGNATURES = {
     "fea_load_intrinsics": ([_P, C.c_int32, _P, _P, _P, _P], C.c_int),
     "fea_set_scenes": ([_P, C.c_int32, _P], C.c_int),
     "fea_get_scene_stats": ([_P, _P, _P, _P, _P, _P], C.c_int),
+    "fea_get_scene_convergence": ([_P, _P, _P], C.c_int),
     "fea_set_mlp": ([_P, _P], C.c_int),
     "fea_mlp_features_dev": ([_P, _P, _P], C.c_int),
     "fea_get_learned_weights": ([_P, _P], C.c_int),
@@ -301,6 +302,15 @@ class Context:
                                               lm.ctypes.data_as(_P)))
         return dict(loss=loss, retained=ret, gauge_center=gc, gauge_scale=gs, learned=lm)
 
+    def scene_convergence(self):
+        """(round each scene converged at or -1 [S], mean camera rotation over
+        the last round in degrees [S])."""
+        S = self.info()["n_scenes"]
+        rd = np.zeros(S, np.int32)
+        ch = np.zeros(S)
+        self._check(lib().fea_get_scene_convergence(self._h, rd.ctypes.data_as(_P), ch.ctypes.data_as(_P)))
+        return rd, ch
+
     # -- learned inlier weights --
     def set_mlp(self, params):
         params, p = _host(params, np.float32)
@@ -411,7 +421,8 @@ class Context:
         return dict(rounds_run=r, iters_run=rep.iters_run,
                     inliers=np.array(rep.inliers_per_round[:min(r, 64)]),
                     loss=np.array(rep.loss_per_round[:min(r, 64)]), ms_total=rep.ms_total,
-                    n_logged=rep.n_logged, fallbacks=rep.fallbacks)
+                    n_logged=rep.n_logged, fallbacks=rep.fallbacks,
+                    scenes_converged=rep.scenes_converged)
 
     def get_poses(self):
         N = self.n_cams

@@ -47,12 +47,31 @@ def test_version_and_defaults(so):
     assert fastea.lib().fea_status_string(fastea.FEA_ESTATE) == b"call out of order"
 
 
-def test_struct_sizes_match_c_layout():
+def test_struct_sizes_match_c_layout(tmp_path):
+    """The ctypes structures have the sizes and field offsets a C compiler
+    gives the header's structures."""
+    import subprocess
     from paper_2605_18052_amd import fastea
-    # int32 x2 + double x10 + int32 x4 + double + int32 x2 + int32 x6
-    assert ctypes.sizeof(fastea.fea_options) == 8 + 80 + 16 + 8 + 8 + 24
-    assert ctypes.sizeof(fastea.fea_report) == 8 + 512 + 512 + 8 + 4 + 4 + 24
-    assert ctypes.sizeof(fastea.fea_info) == 8 + 40 + 8 + 24 + 8 + 8 + 32
+    structs = {"fea_options": fastea.fea_options, "fea_report": fastea.fea_report,
+               "fea_info": fastea.fea_info, "fea_ra_options": fastea.fea_ra_options,
+               "fea_ta_options": fastea.fea_ta_options}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fastea.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(ln.split() for ln in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                    text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, (name, fname)
 
 
 def test_null_handles_are_rejected(so):
