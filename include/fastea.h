@@ -359,6 +359,31 @@ fea_status fea_step(fea_ctx *ctx, int32_t n_steps);
  * options.iters_per_round steps.  out may be NULL. */
 fea_status fea_epipolar_adjust(fea_ctx *ctx, fea_report *out);
 
+/* Batched solve of independent problems (the batching of Method > Kernel
+ * Fusion's launch-bound small scenes, Table fastmap-kernel_fusion: every
+ * kernel launch covers all scenes): scenes [n_scenes] are contexts that
+ * each hold one scene (fea_set_scenes not used) with intrinsics, matches and
+ * initial poses loaded, all on one device; each is solved as
+ * fea_epipolar_adjust would solve it alone, with options opt (NULL = the
+ * first context's options; learned weights take the first context's
+ * network), the scenes' early exit included.  The library builds one
+ * working context holding every scene (the matches are exported in sorted
+ * order on the device and segmented again: O(total matches) of set-up work
+ * and device memory), solves it, and frees it.  Afterwards each context
+ * holds its solved poses as if fea_init_poses and fea_set_poses had been
+ * called with them (round state reset).  out [n_scenes] (nullable) receives
+ * each scene's report: its rounds (up to its convergence round), steps,
+ * per-round loss and retained matches of that scene, fallbacks 1 if the judge
+ * rejected its learned weights, scenes_converged 1 if it converged, and
+ * ms_total the batched solve's wall time (set-up excluded).  Errors:
+ * FEA_EINVAL for n_scenes < 1, a NULL or repeated context, contexts on
+ * several devices or holding several scenes, more than 65535 cameras or 2^31
+ * matches in all, invalid options; FEA_ESTATE for a context without poses
+ * (or learned weights without a network); the message goes to the first
+ * context.  On an error the contexts keep their state unless the write-back
+ * of results had begun. */
+fea_status fea_batch_solve(int32_t n_scenes, fea_ctx *const *scenes, const fea_options *opt, fea_report *out);
+
 /* Current poses in the caller's frame: R [n_cams*9], t [n_cams*3], f
  * [n_cams] (host arrays, caller-allocated; any may be NULL). */
 fea_status fea_get_poses(fea_ctx *ctx, double *R, double *t, double *f);

@@ -1415,6 +1415,9 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
   const auto t0 = std::chrono::steady_clock::now();
   fea_report rep;
   std::memset(&rep, 0, sizeof(rep));
+  // per-scene logs of the rounds (loss, retained matches), kept on the device
+  HIP_OR_FAIL(c, dalloc(c->d_scene_loss_log, 64 * (size_t)c->S * sizeof(double)));
+  HIP_OR_FAIL(c, dalloc(c->d_scene_z_log, 64 * (size_t)c->S * sizeof(int64_t)));
   for (int r = 0; r < c->opt.rounds; ++r) {
     const double tau_px = std::max(c->opt.tau_px_init * std::pow(c->opt.tau_decay, (double)r), c->opt.tau_px_min);
     fea_status s = begin_round(c, tau_px, false);
@@ -1457,6 +1460,13 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
         c->inl_log[r] = c->Z;
       HIP_OR_FAIL(c, fea::launch_loss_sum(c));
       HIP_OR_FAIL(c, hipMemcpyAsync(c->loss_log + r, c->loss.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIP_OR_FAIL(c, fea::launch_scene_loss_log(c, r));
+      int64_t* zrow = c->d_scene_z_log.as<int64_t>() + (size_t)r * c->S;
+      if (c->host_z_stale)
+        HIP_OR_FAIL(c, hipMemcpyAsync(zrow, c->d_scene_z.p, (size_t)c->S * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                                      c->stream));
+      else
+        HIP_OR_FAIL(c, stage_copy(c, zrow, c->Zs.data(), (size_t)c->S * sizeof(int64_t)));
     }
     rep.rounds_run = r + 1;
     rep.iters_run += c->opt.iters_per_round;
@@ -1471,6 +1481,131 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
   rep.fallbacks = c->fallbacks;
   rep.scenes_converged = c->n_done;
   if (out) *out = rep;
+  return FEA_OK;
+}
+
+namespace {
+
+// Frees the working context and the export buffers of fea_batch_solve.
+struct BatchScratch {
+  fea_ctx* work = nullptr;
+  DBuf x1, y1, x2, y2, c1, c2, seg;
+  ~BatchScratch() {
+    DBuf* bs[] = {&x1, &y1, &x2, &y2, &c1, &c2, &seg};
+    for (DBuf* b : bs) dfree(*b);
+    fea_destroy(work);
+  }
+};
+
+}  // namespace
+
+fea_status fea_batch_solve(int32_t n_scenes, fea_ctx* const* scenes, const fea_options* opt, fea_report* out) {
+  if (n_scenes < 1 || !scenes) return FEA_EINVAL;
+  for (int k = 0; k < n_scenes; ++k)
+    if (!scenes[k]) return FEA_EINVAL;
+  fea_ctx* c0 = scenes[0];
+  int64_t N = 0, M = 0;
+  for (int k = 0; k < n_scenes; ++k) {
+    fea_ctx* c = scenes[k];
+    if (!c->have_poses) return fail(c, FEA_ESTATE, "fea_batch_solve: initialise poses first");
+    if (c->S != 1) return fail(c, FEA_EINVAL, "fea_batch_solve: each context must hold one scene");
+    if (c->device != c0->device) return fail(c, FEA_EINVAL, "fea_batch_solve: every context on one device");
+    for (int j = 0; j < k; ++j)
+      if (scenes[j] == c) return fail(c, FEA_EINVAL, "fea_batch_solve: a context is listed twice");
+    N += c->N;
+    M += c->M;
+  }
+  if (N > 65535) return fail(c0, FEA_EINVAL, "fea_batch_solve: more than 65535 cameras in all");
+  if (M >= (int64_t(1) << 31)) return fail(c0, FEA_EINVAL, "fea_batch_solve: 2^31 matches or more in all");
+  fea_options o = opt ? *opt : c0->opt;
+  std::string why;
+  if (!options_valid(&o, &why)) return fail(c0, FEA_EINVAL, "fea_batch_solve: " + why);
+  if (o.weight_mode == 1 && !c0->have_mlp) return fail(c0, FEA_ESTATE, "fea_batch_solve: load the network first");
+  DeviceGuard g(c0->device);
+  // each scene's current poses (caller's frame) and intrinsics, one problem
+  std::vector<double> R(9 * N), t(3 * N), f(N), cx(N), cy(N);
+  std::vector<int32_t> grp(N), cam_scene(N);
+  std::vector<int64_t> cam_off(n_scenes + 1, 0);
+  for (int k = 0; k < n_scenes; ++k) {
+    fea_ctx* c = scenes[k];
+    const int64_t b = cam_off[k];
+    cam_off[k + 1] = b + c->N;
+    fea_status st = fea_get_poses(c, &R[9 * b], &t[3 * b], &f[b]);
+    if (st != FEA_OK) return st;
+    int32_t gbase = 0;
+    for (int j = 0; j < k; ++j) gbase += scenes[j]->G;
+    for (int i = 0; i < c->N; ++i) {
+      cx[b + i] = c->cx[i];
+      cy[b + i] = c->cy[i];
+      grp[b + i] = gbase + c->group[i];
+      cam_scene[b + i] = k;
+    }
+  }
+  BatchScratch w;
+  // the sorted matches of every scene, exported on the device
+  if (dalloc(w.x1, M * sizeof(float)) != hipSuccess || dalloc(w.y1, M * sizeof(float)) != hipSuccess ||
+      dalloc(w.x2, M * sizeof(float)) != hipSuccess || dalloc(w.y2, M * sizeof(float)) != hipSuccess ||
+      dalloc(w.c1, M * sizeof(int32_t)) != hipSuccess || dalloc(w.c2, M * sizeof(int32_t)) != hipSuccess)
+    return fail(c0, FEA_ENOMEM, "fea_batch_solve: no device memory for the exported matches");
+  int64_t m0 = 0;
+  for (int k = 0; k < n_scenes; ++k) {
+    fea_ctx* c = scenes[k];
+    HIP_OR_FAIL(c, upload(c, w.seg, c->seg_off.data(), c->seg_off.size()));
+    HIP_OR_FAIL(c, fea::export_sorted(c, (int32_t)cam_off[k], w.seg.as<int64_t>(), w.x1.as<float>() + m0,
+                                      w.y1.as<float>() + m0, w.x2.as<float>() + m0, w.y2.as<float>() + m0,
+                                      w.c1.as<int32_t>() + m0, w.c2.as<int32_t>() + m0));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));  // w.seg is reused by the next scene
+    m0 += c->M;
+  }
+  // the working context: every scene at once
+  fea_status st = fea_create(&w.work, c0->device, &o, nullptr);
+  if (st != FEA_OK) return fail(c0, st, "fea_batch_solve: could not create the working context");
+  fea_ctx* b = w.work;
+  auto pass = [&](fea_status s) -> fea_status {
+    if (s != FEA_OK) c0->err = "fea_batch_solve: " + b->err;
+    return s;
+  };
+  if ((st = pass(fea_load_intrinsics(b, (int32_t)N, f.data(), cx.data(), cy.data(), grp.data()))) != FEA_OK) return st;
+  if ((st = pass(fea_set_scenes(b, n_scenes, cam_scene.data()))) != FEA_OK) return st;
+  if (o.weight_mode == 1) {
+    std::vector<float> params;
+    HIP_OR_FAIL(c0, download(c0, params, c0->mlp, fea::kMlpParams));
+    if ((st = pass(fea_set_mlp(b, params.data()))) != FEA_OK) return st;
+  }
+  if ((st = pass(fea_load_matches_device(b, M, w.x1.as<float>(), w.y1.as<float>(), w.x2.as<float>(),
+                                         w.y2.as<float>(), w.c1.as<int32_t>(), w.c2.as<int32_t>()))) != FEA_OK)
+    return st;
+  if ((st = pass(fea_init_poses(b, R.data(), t.data()))) != FEA_OK) return st;
+  if ((st = pass(fea_set_poses(b, R.data(), t.data(), f.data()))) != FEA_OK) return st;
+  fea_report rep;
+  if ((st = pass(fea_epipolar_adjust(b, &rep))) != FEA_OK) return st;
+  // results back into each scene's context
+  std::vector<double> Rb(9 * N), tb(3 * N), fb(N);
+  if ((st = pass(fea_get_poses(b, Rb.data(), tb.data(), fb.data()))) != FEA_OK) return st;
+  std::vector<int32_t> done;
+  std::vector<double> slog;
+  std::vector<int64_t> zlog;
+  HIP_OR_FAIL(c0, download(b, done, b->d_scene_done, (size_t)n_scenes));
+  HIP_OR_FAIL(c0, download(b, slog, b->d_scene_loss_log, 64 * (size_t)n_scenes));
+  HIP_OR_FAIL(c0, download(b, zlog, b->d_scene_z_log, 64 * (size_t)n_scenes));
+  for (int k = 0; k < n_scenes; ++k) {
+    fea_ctx* c = scenes[k];
+    const int64_t q = cam_off[k];
+    if ((st = fea_init_poses(c, &Rb[9 * q], &tb[3 * q])) != FEA_OK) return st;
+    if ((st = fea_set_poses(c, &Rb[9 * q], &tb[3 * q], &fb[q])) != FEA_OK) return st;
+    if (!out) continue;
+    fea_report& r = out[k];
+    std::memset(&r, 0, sizeof(r));
+    r.rounds_run = done[k] > 0 ? std::min(done[k] - 1, rep.rounds_run) : rep.rounds_run;
+    r.iters_run = r.rounds_run * o.iters_per_round;
+    for (int j = 0; j < std::min(r.rounds_run, 64); ++j) {
+      r.loss_per_round[j] = slog[(size_t)j * n_scenes + k];
+      r.inliers_per_round[j] = zlog[(size_t)j * n_scenes + k];
+    }
+    r.fallbacks = (o.weight_mode == 1 && !b->scene_learned_ok[k]) ? 1 : 0;
+    r.scenes_converged = done[k] > 0 ? 1 : 0;
+    r.ms_total = rep.ms_total;
+  }
   return FEA_OK;
 }
 

@@ -507,6 +507,26 @@ __global__ __launch_bounds__(kConvThreads) void k_scene_converge(
   }
 }
 
+// Each scene's loss from its cameras' shares (the share of a pair sits with
+// its lower camera), summed in camera order, into row `round` of the log.
+__global__ __launch_bounds__(kConvThreads) void k_scene_loss_log(int S, const int32_t* __restrict__ scene_cam_off,
+                                                                 const int32_t* __restrict__ scene_cams,
+                                                                 const double* __restrict__ loss_cam, int round,
+                                                                 double* __restrict__ log) {
+  __shared__ double s_red[kConvThreads / kWave];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  double L = 0.0;
+  for (int k = scene_cam_off[s] + tid; k < scene_cam_off[s + 1]; k += kConvThreads) L += loss_cam[scene_cams[k]];
+  L = wave_sum_f64(L);
+  if ((tid & 63) == 0) s_red[tid >> 6] = L;
+  __syncthreads();
+  if (tid == 0) {
+    L = 0.0;
+    for (int w = 0; w < kConvThreads / kWave; ++w) L += s_red[w];
+    log[(int64_t)round * S + s] = L;
+  }
+}
+
 // Per-scene normalisers of a quadratic-form round on the device (each
 // scene's items contiguous): Z_s = survivors (exact, int64) and, on learned
 // rounds, Z_w = sum of the survivors' learned weights (per-thread sums over
@@ -672,6 +692,14 @@ hipError_t launch_scene_converge(fea_ctx* c, bool check, int32_t round) {
       c->d_scene_cam_off.as<int32_t>(), c->d_scene_cams.as<int32_t>(), c->Rh.as<double>(), c->Fh.as<double>(),
       c->R[p].as<double>(), c->Fc[p].as<double>(), check ? 1 : 0, round, c->opt.converge_deg,
       c->d_scene_done.as<int32_t>(), c->d_scene_change.as<double>());
+  return hipGetLastError();
+}
+
+hipError_t launch_scene_loss_log(fea_ctx* c, int32_t round) {
+  if (c->S == 0) return hipSuccess;
+  k_scene_loss_log<<<(unsigned)c->S, kConvThreads, 0, c->stream>>>(
+      c->S, c->d_scene_cam_off.as<int32_t>(), c->d_scene_cams.as<int32_t>(), c->loss_cam.as<double>(), round,
+      c->d_scene_loss_log.as<double>());
   return hipGetLastError();
 }
 

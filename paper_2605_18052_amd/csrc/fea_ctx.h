@@ -189,6 +189,8 @@ struct fea_ctx {
   std::vector<int32_t> scene_done_h;      // host copy of d_scene_done (read at every round start)
   int32_t n_done = 0;                     // converged scenes
   double prev_tau_px = -1.0;              // threshold of the previous round, pixels (-1: none yet)
+  fea::DBuf d_scene_loss_log;             // double [64 * S]: each scene's loss at the end of each round
+  fea::DBuf d_scene_z_log;                // int64 [64 * S]: each scene's retained matches in each round
   bool have_mlp = false;
   bool learned_any = false;               // some scene uses learned weights this round
   std::vector<int32_t> scene_mode;        // host copy of d_scene_mode
@@ -220,6 +222,8 @@ namespace fea {
 // *bad_bits to the validation error bits.
 hipError_t segment_matches(fea_ctx* c, const float* x1, const float* y1, const float* x2, const float* y2,
                            const int32_t* cam1, const int32_t* cam2, int* bad_bits);
+hipError_t export_sorted(fea_ctx* c, int32_t cam_base, const int64_t* seg_off_dev, float* x1, float* y1,
+                         float* x2, float* y2, int32_t* cam1, int32_t* cam2);
 
 // --- per-match pass (fea_resgrad.hip) ---
 hipError_t launch_pair_pose(fea_ctx* c, const double* R, const double* T, const double* F, bool snap);
@@ -245,6 +249,7 @@ hipError_t launch_scene_tau(fea_ctx* c, double tau_px, bool first);
 hipError_t launch_scene_z(fea_ctx* c);
 hipError_t launch_scene_loss(fea_ctx* c);
 hipError_t launch_scene_converge(fea_ctx* c, bool check, int32_t round);
+hipError_t launch_scene_loss_log(fea_ctx* c, int32_t round);
 hipError_t run_ablation(fea_ctx* c, int variant, int reps, double* ms, float* pair_sum_dev);
 hipError_t launch_camgrad_at(fea_ctx* c, const double* R, const double* T, const double* F);
 

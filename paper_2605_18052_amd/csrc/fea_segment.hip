@@ -274,7 +274,55 @@ hipError_t alloc_dbuf(DBuf& b, size_t bytes) {
   return hipSuccess;
 }
 
+// Export, pass 1: the coordinates of every real slot of the full layout to
+// its sorted position (padding slots hold lpos = -1).
+__global__ void k_export_coords(int64_t n_slots, const int32_t* __restrict__ lpos, const float* __restrict__ x1,
+                                const float* __restrict__ y1, const float* __restrict__ x2,
+                                const float* __restrict__ y2, float* __restrict__ ox1, float* __restrict__ oy1,
+                                float* __restrict__ ox2, float* __restrict__ oy2) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_slots) return;
+  const int32_t q = lpos[s];
+  if (q < 0) return;
+  ox1[q] = x1[s];
+  oy1[q] = y1[s];
+  ox2[q] = x2[s];
+  oy2[q] = y2[s];
+}
+
+// Export, pass 2: one workgroup per pair writes the pair's camera ids
+// (offset by cam_base) over its sorted range.
+__global__ void k_export_cams(const int64_t* __restrict__ seg_off, const int32_t* __restrict__ pair_i,
+                              const int32_t* __restrict__ pair_j, int32_t cam_base, int32_t* __restrict__ c1,
+                              int32_t* __restrict__ c2) {
+  const int n = blockIdx.x;
+  const int32_t a = pair_i[n] + cam_base, b = pair_j[n] + cam_base;
+  for (int64_t q = seg_off[n] + threadIdx.x; q < seg_off[n + 1]; q += blockDim.x) {
+    c1[q] = a;
+    c2[q] = b;
+  }
+}
+
 }  // namespace
+
+// The loaded matches in sorted order (each canonical, lower camera first),
+// into device arrays [n_matches] of the context's device: coordinates as
+// loaded, camera ids offset by cam_base.  seg_off_dev: the pair ranges
+// [P + 1] on the device (caller-provided scratch).
+hipError_t export_sorted(fea_ctx* c, int32_t cam_base, const int64_t* seg_off_dev, float* x1, float* y1,
+                         float* x2, float* y2, int32_t* cam1, int32_t* cam2) {
+  int64_t slots = 0;
+  for (int64_t n = 0; n < c->P; ++n)
+    slots += (c->seg_off[n + 1] - c->seg_off[n] + kAlign - 1) / kAlign * kAlign;
+  if (slots > 0)
+    k_export_coords<<<(unsigned)((slots + 255) / 256), 256, 0, c->stream>>>(
+        slots, c->lpos[0].as<int32_t>(), c->lay[0][0].as<float>(), c->lay[0][1].as<float>(),
+        c->lay[0][2].as<float>(), c->lay[0][3].as<float>(), x1, y1, x2, y2);
+  if (c->P > 0)
+    k_export_cams<<<(unsigned)c->P, 256, 0, c->stream>>>(seg_off_dev, c->d_pair_i.as<int32_t>(),
+                                                       c->d_pair_j.as<int32_t>(), cam_base, cam1, cam2);
+  return hipGetLastError();
+}
 
 hipError_t segment_matches(fea_ctx* c, const float* x1, const float* y1, const float* x2, const float* y2,
                            const int32_t* cam1, const int32_t* cam2, int* bad_bits) {

@@ -73,6 +73,7 @@ _SIGNATURES = {
     "fea_set_scenes": ([_P, C.c_int32, _P], C.c_int),
     "fea_get_scene_stats": ([_P, _P, _P, _P, _P, _P], C.c_int),
     "fea_get_scene_convergence": ([_P, _P, _P], C.c_int),
+    "fea_batch_solve": ([C.c_int32, _P, _P, _P], C.c_int),
     "fea_set_mlp": ([_P, _P], C.c_int),
     "fea_mlp_features_dev": ([_P, _P, _P], C.c_int),
     "fea_get_learned_weights": ([_P, _P], C.c_int),
@@ -220,6 +221,30 @@ def default_options(**kw) -> fea_options:
             raise AttributeError(k)
         setattr(o, k, v)
     return o
+
+
+def _report(rep):
+    r = rep.rounds_run
+    return dict(rounds_run=r, iters_run=rep.iters_run,
+                inliers=np.array(rep.inliers_per_round[:min(r, 64)]),
+                loss=np.array(rep.loss_per_round[:min(r, 64)]), ms_total=rep.ms_total,
+                n_logged=rep.n_logged, fallbacks=rep.fallbacks,
+                scenes_converged=rep.scenes_converged)
+
+
+def batch_solve(contexts, options: fea_options | None = None):
+    """fea_batch_solve over Context objects (each with one scene, poses
+    initialised, all on one device): one batched solve, each context's poses
+    then hold its result.  Returns one report dict per context."""
+    n = len(contexts)
+    arr = (C.c_void_p * n)(*[c._h.value for c in contexts])
+    reps = (fea_report * n)()
+    popt = C.byref(options) if options is not None else None
+    rc = lib().fea_batch_solve(n, arr, popt, reps)
+    if rc != FEA_OK:
+        msg = lib().fea_last_error(contexts[0]._h).decode() if n else ""
+        raise FeaError(rc, msg)
+    return [_report(r) for r in reps]
 
 
 def check_options(opt: fea_options):
@@ -417,12 +442,7 @@ class Context:
     def epipolar_adjust(self):
         rep = fea_report()
         self._check(lib().fea_epipolar_adjust(self._h, C.byref(rep)))
-        r = rep.rounds_run
-        return dict(rounds_run=r, iters_run=rep.iters_run,
-                    inliers=np.array(rep.inliers_per_round[:min(r, 64)]),
-                    loss=np.array(rep.loss_per_round[:min(r, 64)]), ms_total=rep.ms_total,
-                    n_logged=rep.n_logged, fallbacks=rep.fallbacks,
-                    scenes_converged=rep.scenes_converged)
+        return _report(rep)
 
     def get_poses(self):
         N = self.n_cams

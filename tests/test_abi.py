@@ -77,6 +77,9 @@ def test_struct_sizes_match_c_layout(tmp_path):
 def test_null_handles_are_rejected(so):
     from paper_2605_18052_amd import fastea
     L = fastea.lib()
+    assert L.fea_batch_solve(0, None, None, None) == fastea.FEA_EINVAL
+    assert L.fea_batch_solve(1, None, None, None) == fastea.FEA_EINVAL
+    assert L.fea_get_scene_convergence(None, None, None) == fastea.FEA_EINVAL
     assert L.fea_step(None, 1) == fastea.FEA_EINVAL
     assert L.fea_begin_round(None, 1.0) == fastea.FEA_EINVAL
     assert L.fea_get_poses(None, None, None, None) == fastea.FEA_EINVAL

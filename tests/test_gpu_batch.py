@@ -109,3 +109,48 @@ def test_autotuner_choice_is_reused_in_process():
         picks.append((info["tile_matches"], info["tile_threads"]))
         ctx.close()
     assert picks[0] == picks[1] and picks[0][0] in (1024, 2048, 4096, 8192)
+
+
+@pytest.mark.parametrize("inner_loop", [0, 1])
+def test_batch_solve_equals_solo_solves(inner_loop):
+    """fea_batch_solve over separately loaded contexts: each context ends
+    with the poses its solo solve reaches, and its report holds that solve's
+    per-round loss and retained matches."""
+    scenes = _scenes()
+    ctxs, solo = [], []
+    for sc in scenes:
+        c = fastea.Context(0, _opts(inner_loop))
+        c.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+        c.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+        c.init_poses(sc.R_init, sc.t_init)
+        ctxs.append(c)
+        solo.append(_solo(sc, inner_loop))
+    reps = fastea.batch_solve(ctxs)
+    for c, (Rs, ts, fs, _, rep_s), rep in zip(ctxs, solo, reps):
+        R, t, f = c.get_poses()
+        np.testing.assert_allclose(R, Rs, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(t, ts, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(f, fs, rtol=1e-12)
+        assert rep["rounds_run"] == rep_s["rounds_run"] and rep["iters_run"] == rep_s["iters_run"]
+        np.testing.assert_array_equal(rep["inliers"], rep_s["inliers"])
+        np.testing.assert_allclose(rep["loss"], rep_s["loss"], rtol=1e-10)
+        assert rep["scenes_converged"] == 0
+        c.close()
+
+
+def test_batch_solve_rejects_bad_arguments():
+    sc = _scenes()[0]
+    c = fastea.Context(0, _opts())
+    c.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+    c.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+    with pytest.raises(fastea.FeaError) as e:
+        fastea.batch_solve([c])  # no poses yet
+    assert e.value.status == fastea.FEA_ESTATE
+    c.init_poses(sc.R_init, sc.t_init)
+    with pytest.raises(fastea.FeaError) as e:
+        fastea.batch_solve([c, c])
+    assert e.value.status == fastea.FEA_EINVAL
+    with pytest.raises(fastea.FeaError) as e:
+        fastea.batch_solve([c], fastea.default_options(tile_matches=3000))
+    assert e.value.status == fastea.FEA_EINVAL
+    c.close()
