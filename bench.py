@@ -2,26 +2,34 @@
 
 A step is one pass of the whole hot path over the retained matches of the
 first IRLS round: the fused residual / IRLS-weight / dL/dF kernel over every
-match, the per-camera adjoint and Adam update, and the focal/loss kernel.
-The workload is the 500-camera trajectory scene (200k points, 20 nearest
-neighbours, ~20M matches, sigma 1 px, 20% outliers, unknown focal lengths in
-[400, 1200] px), generated synthetically and resident in HBM before timing;
-`--workload traj3000_m100M` times the 3,000-camera, ~100M-match scene instead.
+match, the per-camera adjoint and Adam update, and the pose table of the next
+step.  The default workload is the 3,000-camera trajectory scene (1M points,
+30 nearest neighbours, ~100M matches, sigma 1 px, 25% outliers, unknown focal
+lengths in [400, 1200] px): 1.4 GB of retained coordinates per pass, 5.5x the
+256 MB Infinity Cache, so the pass streams from HBM.  It is generated
+synthetically and resident in HBM before timing; `--workload traj500_m20M`
+times the 500-camera, ~20M-match scene instead.
 
 Prints ONE JSON line on stdout (progress goes to stderr):
-  value       retained matches processed per second (whole job = 1 GPU)
+  value       retained matches processed per second (whole job = 1 GPU), from
+              the timed steps as the library runs them (runs of 10 steps
+              replayed as HIP graphs)
   roofline    the per-match kernel: algorithmic bytes (16 B/match) / its
-              mean HIP-event duration, against the 8 TB/s HBM peak
+              mean HIP-event duration over a second, per-dispatch-timed run of
+              the same steps, against the 8 TB/s HBM peak
   cpu_baseline the FP64 oracle timed on the host on a 6M-match sample
-  solve       wall time until the mean rotation error first drops to <= 1 deg,
-              with the per-match inner loop and with the pairs' quadratic forms
-  translation the stages before the adjustment: the focal-length vote and
-              global rotation on the scene's pair graph, the
-              relative-translation candidate search
-              over the same scene's matches (its scoring kernel against its
-              roofline) and the multi-start camera-centre alignment on a
-              500-camera object-centric pair graph, each with the oracle
-              timed beside it
+  solve       wall time until the mean rotation error first drops to <= 1 deg
+              on the held-out learned-weight scenes (1,000 cameras, ~30M
+              matches, 30% outliers): the per-match inner loop, the pairs'
+              quadratic forms, and learned weights with the quadratic forms
+  batch       64 uneven scenes (~120M matches) solved in one context against
+              one after another, with per-scene early exit and convergence
+  translation the stages before the adjustment on the first held-out scene:
+              the focal-length vote and global rotation on its pair graph,
+              the relative-translation candidate search over its matches (the
+              scoring kernel against its roofline) and the multi-start
+              camera-centre alignment on a 500-camera object-centric pair
+              graph, each with the oracle timed beside it
 """
 from __future__ import annotations
 
@@ -43,6 +51,10 @@ FP32_MFMA_PEAK_TFLOPS = 157.3  # dense fp32 matrix-core peak of the MI355X
 # VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 BYTES_PER_MATCH = 16  # x1, y1, x2, y2 as fp32: the algorithmic minimum per match
+# per-scene early exit of the batched solves: a scene whose cameras rotate by
+# less than this many degrees on average over a round at the threshold floor
+# stops
+BATCH_CONVERGE_DEG = 0.01
 
 # HBM bytes per launch of the per-match kernel at round 0 of each workload,
 # from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch
@@ -97,12 +109,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="traj500_m20M",
-                    help="scene the step is timed on (the 100M-match scene streams 1.6 GB per pass, "
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="traj3000_m100M",
+                    help="scene the step is timed on (the 100M-match scene streams 1.4 GB per pass, "
                          "far beyond the 256 MB Infinity Cache)")
     ap.add_argument("--matches", type=int, default=0, help="target match count (0: the workload's own)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1-degree solve")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1-degree solves")
+    ap.add_argument("--solve-seeds", default="5100,5101,5102",
+                    help="seeds of the held-out learned-weight scenes the solves run on")
+    ap.add_argument("--solve-per-match-seeds", type=int, default=1,
+                    help="how many of those scenes also run the per-match inner loop")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-scene batch (batched against one after another)")
     ap.add_argument("--no-translation", action="store_true",
                     help="skip the relative-translation search and camera-centre alignment")
     ap.add_argument("--candidates", type=int, default=2048,
@@ -115,8 +133,6 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--ablation", action="store_true",
                     help="also time the per-match pass with each design choice taken back")
-    ap.add_argument("--batch", action="store_true",
-                    help="also solve 64 uneven scenes (~120M matches) batched and one by one")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -213,15 +229,13 @@ def time_to_one_degree(sc, fastea, metrics, every=10, **options):
     return out
 
 
-def batched_vs_sequential(fastea, metrics, synth, **options):
-    """64 independent scenes of uneven size solved in one context (every
-    kernel launch covers all scenes, steps replayed as HIP graphs) against
-    the same scenes solved one after another.  Setup (loading, segmenting)
-    is outside the timed regions; per-scene convergence is reported."""
-    t0 = time.perf_counter()
-    scenes = synth.config4()
-    log(f"[bench] batch: {len(scenes)} scenes, {sum(s.n_matches for s in scenes)} matches "
-        f"({time.perf_counter() - t0:.1f} s)")
+def batched_vs_sequential(scenes, fastea, metrics, synth, sequential=True, **options):
+    """Independent scenes of uneven size solved in one context (every kernel
+    launch covers all scenes, steps replayed as HIP graphs, a scene that has
+    converged takes no further steps) against the same scenes solved one
+    after another with the same options.  Loading and segmenting are outside
+    the timed regions; per-scene convergence and final rotation error are
+    reported."""
     cat, cam_scene, offs = synth.concat_scenes(scenes)
     mlp = options.pop("mlp", None)
     ctx = fastea.Context(0, fastea.default_options(**options))
@@ -237,14 +251,17 @@ def batched_vs_sequential(fastea, metrics, synth, **options):
     ctx.synchronize()
     batched = time.perf_counter() - t1
     R, _, _ = ctx.get_poses()
-    learned_scenes = int(sum(ctx.scene_stats()["learned"])) if mlp is not None else 0
+    done, _ = ctx.scene_convergence()
+    learned_scenes = int(sum(ctx.scene_stats()["learned"])) if mlp is not None else None
     ctx.close()
     per_scene = [metrics.mean_rotation_error_deg(R[offs[k]:offs[k + 1]], sc.R_gt)
                  for k, sc in enumerate(scenes)]
-    seq = None if mlp is not None else 0.0
-    for sc in ([] if mlp is not None else scenes):
+    seq, seq_err = (0.0, []) if sequential else (None, None)
+    for sc in (scenes if sequential else []):
         c = fastea.Context(0, fastea.default_options(**options))
         c.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+        if mlp is not None:
+            c.set_mlp(mlp)
         c.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
         c.init_poses(sc.R_init, sc.t_init)
         c.synchronize()
@@ -252,13 +269,20 @@ def batched_vs_sequential(fastea, metrics, synth, **options):
         c.epipolar_adjust()
         c.synchronize()
         seq += time.perf_counter() - t1
+        Rs, _, _ = c.get_poses()
+        seq_err.append(metrics.mean_rotation_error_deg(Rs, sc.R_gt))
         c.close()
+    rounds = fastea.default_options(**options).rounds
     return {"scenes": len(scenes), "matches": int(sum(s.n_matches for s in scenes)),
             "batched_s": round(batched, 4), "sequential_s": None if seq is None else round(seq, 4),
-            "learned_scenes_at_end": learned_scenes if mlp is not None else None,
+            "speedup": None if not seq else round(seq / batched, 2),
+            "rounds_run": rep["rounds_run"], "scenes_converged": rep["scenes_converged"],
+            "per_scene_rounds": [int(d) if d >= 0 else rounds for d in done],
+            "learned_scenes_at_end": learned_scenes,
             "judge_fallbacks": rep["fallbacks"] if mlp is not None else None,
             "per_scene_final_rot_err_deg": [round(e, 3) for e in per_scene],
             "scenes_at_or_below_1deg": int(sum(e <= 1.0 for e in per_scene)),
+            "sequential_scenes_at_or_below_1deg": None if seq_err is None else int(sum(e <= 1.0 for e in seq_err)),
             "options": ({**options, "weight_mode": "learned"} if mlp is not None else options) or "defaults"}
 
 
@@ -414,8 +438,9 @@ def translation_stages(sc, fastea, synth, n_cand, with_cpu, cap_px=32.0, cpu_pai
         oracle.ra_solve(pc, Rrel, a6o, iters=100)
         dt3 = time.perf_counter() - t3
         rotation["cpu_baseline"] = {"value": 1e3 * dt3, "unit": "ms", "cores": 1, "kind": "oracle",
-                                    "sample": "the numpy oracle's initialisation (dense eigh of the 1,500 x 1,500 "
-                                              f"normal matrices) and 100 of the 1,000 Adam steps, {dt3:.1f} s wall"}
+                                    "sample": f"the numpy oracle's initialisation (dense eigh of the {3 * sc.n_cams:,} x "
+                                              f"{3 * sc.n_cams:,} normal matrices) and 100 of the "
+                                              f"{ropt.iters:,} Adam steps, {dt3:.1f} s wall"}
         align["cpu_baseline"] = {"value": 1e3 * dt1, "unit": "ms", "cores": 1, "kind": "oracle",
                                  "sample": "the same alignment (2 runs, default schedule) in the FP64 C "
                                            f"oracle, one thread, {dt1:.1f} s wall"}
@@ -444,32 +469,44 @@ def main():
     opt = fastea.default_options()
     ctx = fastea.Context(0, opt)
     ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
+    t1 = time.perf_counter()
     ctx.load_matches(sc.x1, sc.y1, sc.x2, sc.y2, sc.cam1, sc.cam2)
+    ctx.synchronize()
+    seg_s = time.perf_counter() - t1
     ctx.init_poses(sc.R_init, sc.t_init)
     ctx.begin_round(opt.tau_px_init)
     info = ctx.info()
     Z = info["n_retained"]
     tile = f"{info['tile_matches']}x{info['tile_threads']}"
-    log(f"[bench] round 0: {Z} of {sc.n_matches} matches retained, {info['n_items']} items")
+    log(f"[bench] loaded and segmented in {seg_s:.2f} s; round 0: {Z} of {sc.n_matches} matches retained, "
+        f"{info['n_items']} items of {tile}")
+    # timed region: the steps as the library issues them (runs of 10 steps
+    # replayed as HIP graphs), nothing read back until the end
     ctx.step(args.warmup)
     ctx.synchronize()
-    torch.cuda.synchronize()
-    ctx.set_kernel_timing(True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     ctx.step(args.steps)
     ctx.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    ms_step = 1e3 * wall / args.steps
+    value = Z * args.steps / wall
+    # second pass over the same steps, issued one by one, each dispatch of the
+    # per-match kernel bracketed by a pair of HIP events on the library's stream
+    ctx.set_kernel_timing(True)
+    t_k = time.perf_counter()
+    ctx.step(args.steps)
+    ctx.synchronize()
+    eager_ms = 1e3 * (time.perf_counter() - t_k) / args.steps
     k_ms, k_n = ctx.kernel_timing()
     k_each = ctx.kernel_times()
     ctx.set_kernel_timing(False)
     ctx.close()
-    ms_step = 1e3 * wall / args.steps
-    value = Z * args.steps / wall
     k_avg_s = k_ms / 1e3 / max(k_n, 1)
     achieved = BYTES_PER_MATCH * Z / k_avg_s / 1e9
-    log(f"[bench] {args.steps} steps in {wall:.4f} s ({ms_step:.4f} ms/step); "
+    log(f"[bench] {args.steps} steps in {wall:.4f} s ({ms_step:.4f} ms/step, graph replay; "
+        f"{eager_ms:.4f} ms/step issued one by one with kernel timing); "
         f"k_resgrad {1e3 * k_avg_s:.4f} ms avg over {k_n} launches = {achieved:.1f} GB/s")
 
     read_peak, copy_peak = fastea.hbm_probe(0, 1 << 30, 5)
@@ -483,17 +520,6 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {args.calib_copy_mib} MiB read + written, 3 launches")
-
-    solve = None
-    if not args.no_solve:
-        solve = {}
-        from paper_2605_18052_amd import learned
-        mlp = learned.load_weights()
-        for name, o in (("per_match", {}), ("quadratic_form", {"inner_loop": 1}),
-                        ("learned_quadratic_form", {"inner_loop": 1, "weight_mode": 1, "mlp": mlp})):
-            log(f"[bench] solve to <= 1 deg, {name} inner loop ...")
-            solve[name] = time_to_one_degree(sc, fastea, metrics, **o)
-            log(f"[bench] solve {name}: {solve[name]}")
 
     ablation = None
     if args.ablation:
@@ -515,39 +541,73 @@ def main():
             log(f"[bench] ablation {v}: {ms:.4f} ms ({name})")
         actx.close()
 
-    batch = None
-    if args.batch:
-        batch = {}
-        from paper_2605_18052_amd import learned
-        mlp = learned.load_weights()
-        for name, o in (("per_match", {}), ("quadratic_form", {"inner_loop": 1}),
-                        ("learned_quadratic_form", {"inner_loop": 1, "weight_mode": 1, "mlp": mlp})):
-            batch[name] = batched_vs_sequential(fastea, metrics, synth, **o)
-            log(f"[bench] batch {name}: batched {batch[name]['batched_s']} s, sequential "
-                f"{batch[name]['sequential_s']} s, {batch[name]['scenes_at_or_below_1deg']} scenes <= 1 deg")
-
-    translation = None
-    if not args.no_translation:
-        log("[bench] relative-translation search and camera-centre alignment ...")
-        translation = translation_stages(sc, fastea, synth, args.candidates, not args.no_cpu,
-                                         args.search_cap_px, args.search_cpu_pairs)
-        rt, al = translation["relative_translations"], translation["alignment"]
-        ro = translation["rotation"]
-        log(f"[bench] rotation: {ro['ms']:.1f} ms, error {ro['error_init_deg']:.3f} -> {ro['error_deg']:.3f} deg")
-        fv = translation["focal_vote"]
-        log(f"[bench] focal vote: {fv['kernel_ms']:.3f} ms for {fv['cameras']} cameras x {fv['candidates']} "
-            f"candidates, {fv['within_5pct']:.2f} of the cameras within 5%")
-        log(f"[bench] search: k_rt_score {rt['kernel_ms']:.3f} ms = {rt['roofline']['achieved']:.2f} "
-            f"{rt['roofline']['unit']} ({rt['roofline']['frac']:.3f} of the {rt['roofline']['bound']} peak), "
-            f"median direction error "
-            f"{rt['direction_error_deg_median']:.2f} deg; alignment {al['ms']:.2f} ms "
-            f"({al['us_per_step']:.2f} us/step)")
-
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         cpu = cpu_baseline(sc, args.cpu_sample, args.cpu_iters)
         log(f"[bench] cpu: {cpu}")
+    del sc
+
+    # held-out learned-weight scenes: the solves and the stages before them
+    solve, translation, held = None, None, None
+    if not (args.no_solve and args.no_translation):
+        seeds = [int(x) for x in args.solve_seeds.split(",") if x.strip()] or [5100]
+        from paper_2605_18052_amd import learned
+        mlp = learned.load_weights()
+        solve = {"scenes": [], "variants": {}} if not args.no_solve else None
+        for k, seed in enumerate(seeds if not args.no_solve else seeds[:1]):
+            t0 = time.perf_counter()
+            held = synth.config5(seed=seed)
+            log(f"[bench] held-out scene {held.name}: {held.n_cams} cams, {held.n_matches} matches "
+                f"({time.perf_counter() - t0:.1f} s)")
+            if solve is not None:
+                solve["scenes"].append(held.name)
+                variants = [("quadratic_form", {"inner_loop": 1}),
+                            ("learned_quadratic_form", {"inner_loop": 1, "weight_mode": 1, "mlp": mlp})]
+                if k < args.solve_per_match_seeds:
+                    variants.insert(0, ("per_match", {}))
+                for name, o in variants:
+                    r = time_to_one_degree(held, fastea, metrics, **dict(o))
+                    solve["variants"].setdefault(name, []).append(r)
+                    log(f"[bench] solve {held.name} {name}: {r}")
+            if k == 0 and not args.no_translation:
+                log("[bench] stages before the adjustment on the first held-out scene ...")
+                translation = translation_stages(held, fastea, synth, args.candidates, not args.no_cpu,
+                                                 args.search_cap_px, args.search_cpu_pairs)
+                translation["scene"] = held.name
+                rt, al = translation["relative_translations"], translation["alignment"]
+                ro, fv = translation["rotation"], translation["focal_vote"]
+                log(f"[bench] rotation: {ro['ms']:.1f} ms, error {ro['error_init_deg']:.3f} -> "
+                    f"{ro['error_deg']:.3f} deg; focal vote: {fv['kernel_ms']:.3f} ms, {fv['within_5pct']:.2f} "
+                    f"within 5%; search: k_rt_score {rt['kernel_ms']:.3f} ms, median direction error "
+                    f"{rt['direction_error_deg_median']:.2f} deg; alignment {al['ms']:.2f} ms")
+            del held
+        if solve is not None:
+            summary = {}
+            for name, rs in solve["variants"].items():
+                w = [r["wall_to_1deg_s"] for r in rs]
+                summary[name] = {"wall_to_1deg_s": w, "reached_1deg": int(sum(x is not None for x in w)),
+                                 "total_s_if_all_reached": (round(sum(w), 4) if all(x is not None for x in w)
+                                                            else None)}
+            solve["summary"] = summary
+
+    batch = None
+    if not args.no_batch:
+        t0 = time.perf_counter()
+        scenes = synth.config4()
+        log(f"[bench] batch: {len(scenes)} scenes, {sum(s.n_matches for s in scenes)} matches "
+            f"({time.perf_counter() - t0:.1f} s)")
+        from paper_2605_18052_amd import learned
+        mlp = learned.load_weights()
+        batch = {"early_exit_deg": BATCH_CONVERGE_DEG}
+        for name, o, seq in (("per_match", {}, True), ("quadratic_form", {"inner_loop": 1}, True),
+                             ("learned_quadratic_form", {"inner_loop": 1, "weight_mode": 1, "mlp": mlp}, False)):
+            batch[name] = batched_vs_sequential(scenes, fastea, metrics, synth, sequential=seq,
+                                                converge_deg=BATCH_CONVERGE_DEG, **o)
+            log(f"[bench] batch {name}: batched {batch[name]['batched_s']} s, sequential "
+                f"{batch[name]['sequential_s']} s, {batch[name]['scenes_converged']} scenes converged, "
+                f"{batch[name]['scenes_at_or_below_1deg']} scenes <= 1 deg")
+        del scenes
 
     traffic = measured_traffic(tile, Z)
     out = {
@@ -556,9 +616,11 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}",
-                   "matches_loaded": sc.n_matches, "matches_per_step": Z,
+                   "matches_loaded": info["n_matches"], "matches_per_step": Z,
                    "pairs": info["n_pairs"], "items": info["n_items"], "irls_round": 0,
-                   "tau_px": opt.tau_px_init},
+                   "tau_px": opt.tau_px_init, "segmenting_s": round(seg_s, 3),
+                   "step_timing": "runs of 10 steps replayed as HIP graphs, host clock around the K steps",
+                   "ms_per_step_issued_one_by_one": eager_ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "achieved_on_traffic": None if traffic is None else traffic / k_avg_s / 1e9,
@@ -571,10 +633,9 @@ def main():
                                        "copy (null if the kernel changed since they were taken)"},
         "cpu_baseline": cpu,
         "solve": solve,
+        "batch": batch,
         "translation": translation,
     }
-    if batch is not None:
-        out["batch"] = batch
     if ablation is not None:
         out["ablation"] = ablation
     print(json.dumps(out), flush=True)

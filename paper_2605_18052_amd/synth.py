@@ -448,6 +448,16 @@ def config3(seed: int = 3, target_matches: int = 100_000_000) -> Scene:
                             seed=seed, name="traj3000_m100M")
 
 
+def config5(seed: int = 5100, target_matches: int = 30_000_000) -> Scene:
+    """Held-out scene of the learned-weight workload: 1,000 cameras on the
+    noisy loop, 400k points, 20 nearest neighbours, ~30M matches, sigma
+    1 px, 30% outliers, f in [400,1200] px.  The network is trained on the
+    500-camera, 20%-outlier scenes of seeds 5000-5003 and validated on 5004;
+    the test scenes are seeds 5100-5102."""
+    return trajectory_scene(n_cams=1000, n_pts=400_000, knn=20, target_matches=target_matches,
+                            outlier_frac=0.3, seed=seed, name=f"traj1000_m30M_s{seed}")
+
+
 def tiny_scene(n_cams=4, n_pts=40, seed=7, sigma=0.0, outlier_frac=0.0,
                p_det=1.0, focal=500.0, distinct_focals=True) -> Scene:
     """Small sphere scene for brute-force checks; optional distinct focals."""
