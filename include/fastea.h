@@ -117,7 +117,8 @@ typedef struct {
   int32_t n_logged;              /* pose snapshots kept (log_every > 0) */
   int32_t fallbacks;             /* learned rounds rejected by the judge (all scenes) */
   int32_t scenes_converged;      /* scenes the early exit stopped (converge_deg > 0) */
-  int32_t reserved[5];
+  int32_t scenes_nonfinite;      /* scenes the non-finite guard stopped (see fea_epipolar_adjust) */
+  int32_t reserved[4];
 } fea_report;
 
 /* Sizes and state of a context. */
@@ -209,6 +210,13 @@ fea_status fea_get_scene_stats(fea_ctx *ctx, double *loss, int64_t *retained,
  * NULL. */
 fea_status fea_get_scene_convergence(fea_ctx *ctx, int32_t *converged_round, double *change_deg);
 
+/* Scenes stopped by the non-finite guard (see fea_epipolar_adjust):
+ * stopped_round [n_scenes] (host, not NULL) receives the round at whose start
+ * the scene was found non-finite (options.rounds or the rounds run if at the
+ * end of the solve), or -1.  Its poses are those of the snapshot taken at
+ * the start of the round before. */
+fea_status fea_get_scene_nonfinite(fea_ctx *ctx, int32_t *stopped_round);
+
 /* Keypoint matches (Method > Epipolar Adjustment: point pairs Q_n of the
  * image pairs P).  Match m relates pixel (x1[m], y1[m]) of camera cam1[m] to
  * (x2[m], y2[m]) of camera cam2[m].  Host arrays of length n, copied.
@@ -275,6 +283,16 @@ fea_status fea_residual_grad(fea_ctx *ctx, double *loss_dev, double *gR_dev, dou
  * fea_get_params_dev: the context's current parameters into such arrays
  * (any pointer may be NULL). */
 fea_status fea_get_params_dev(fea_ctx *ctx, double *a6_dev, double *t_dev, double *logf_dev);
+
+/* fea_set_params_dev: replaces the context's current parameters with such
+ * arrays (device pointers, read on the context's stream before the call's
+ * work completes; none may be NULL) and derives the poses from them, e.g.
+ * after a caller's own optimiser step.  The Adam moments and the round's
+ * snapshot are kept.  The values are not inspected on the host: a
+ * non-finite value is caught by the non-finite guard at the next round
+ * boundary (fea_begin_round, fea_epipolar_adjust).  FEA_ESTATE before
+ * fea_init_poses. */
+fea_status fea_set_params_dev(fea_ctx *ctx, const double *a6_dev, const double *t_dev, const double *logf_dev);
 
 /* Forward: loss_dev [1] = L(a6, t, logf), the round's re-weighted epipolar
  * objective (the IRLS form after Eq. fastmap-epipolar-objective-l2) at the
@@ -356,7 +374,15 @@ fea_status fea_step(fea_ctx *ctx, int32_t n_steps);
  * and decreases to a minimum; focal lengths folded into the essential
  * matrices): options.rounds rounds of fea_begin_round with the threshold
  * schedule max(tau_px_init * tau_decay^r, tau_px_min), each followed by
- * options.iters_per_round steps.  out may be NULL. */
+ * options.iters_per_round steps.  out may be NULL.
+ * Non-finite guard: at every round boundary (and once more after the last
+ * round) each scene's parameters, poses and last-step loss are checked on
+ * the device; a scene holding a non-finite value gets back the parameters
+ * and poses of the snapshot its last round started from (the last values
+ * found finite) and takes no further steps, while the other scenes go on.
+ * The call then returns FEA_ENONFINITE after filling out (scenes_nonfinite
+ * counts such scenes; fea_get_scene_nonfinite names them).  fea_begin_round
+ * runs the same check and returns FEA_ENONFINITE when it stops a scene. */
 fea_status fea_epipolar_adjust(fea_ctx *ctx, fea_report *out);
 
 /* Batched solve of independent problems (the batching of Method > Kernel
@@ -374,8 +400,11 @@ fea_status fea_epipolar_adjust(fea_ctx *ctx, fea_report *out);
  * called with them (round state reset).  out [n_scenes] (nullable) receives
  * each scene's report: its rounds (up to its convergence round), steps,
  * per-round loss and retained matches of that scene, fallbacks 1 if the judge
- * rejected its learned weights, scenes_converged 1 if it converged, and
- * ms_total the batched solve's wall time (set-up excluded).  Errors:
+ * rejected its learned weights, scenes_converged 1 if it converged,
+ * scenes_nonfinite 1 if the non-finite guard stopped it, and ms_total the
+ * batched solve's wall time (set-up excluded).  If the guard stopped a
+ * scene the results are still written back and the call returns
+ * FEA_ENONFINITE.  Errors:
  * FEA_EINVAL for n_scenes < 1, a NULL or repeated context, contexts on
  * several devices or holding several scenes, more than 65535 cameras or 2^31
  * matches in all, invalid options; FEA_ESTATE for a context without poses
@@ -440,6 +469,14 @@ fea_status fea_get_info(fea_ctx *ctx, fea_info *out);
 
 /* Blocks until all work issued on the context's stream has finished. */
 fea_status fea_synchronize(fea_ctx *ctx);
+
+/* The HIP stream (hipStream_t) every call on this context issues its work on:
+ * the one given to fea_create, or the context's own.  Callers that produce or
+ * consume the *_dev arrays on another stream order the two with events on
+ * this handle instead of synchronising the host.  The context keeps
+ * ownership; the handle is valid until fea_destroy.  FEA_EINVAL if either
+ * pointer is NULL. */
+fea_status fea_get_stream(fea_ctx *ctx, void **stream);
 
 /* STREAM-style HBM probe on GPU `device`: a read-only kernel and a copy
  * kernel over `bytes` bytes (rounded down to 16-byte vectors), best of

@@ -5,14 +5,39 @@ round at those parameters; backward runs the library's hand-written adjoint
 (the forward is recomputed; no per-match tensor is kept), so a torch
 optimiser can drive the solve.  Parameters are float64 CUDA tensors in the
 context's gauge: a6 [N,6] 6D rotations, t [N,3] translations, logf [G] log
-focal length per intrinsics group.  The torch stream is synchronised with the
-library's stream around each call.
+focal length per intrinsics group.
+
+Ordering: the library's work is queued behind everything already issued on
+torch's current stream, and torch's current stream waits for the library's
+work, both through device-side events; the host never waits.  The tensors
+the library reads or writes are marked as used on the library's stream, so
+torch's allocator does not hand their memory out again before that work is
+done.
 """
 from __future__ import annotations
 
 import torch
 
 from . import fastea
+
+
+def _enter(fctx: fastea.Context, device):
+    """(library stream, torch's current stream, whether they differ); the
+    library's stream waits for torch's current one."""
+    cur = torch.cuda.current_stream(device)
+    lib = fctx.torch_stream()
+    other = lib.cuda_stream != cur.cuda_stream
+    if other:
+        lib.wait_stream(cur)
+    return lib, cur, other
+
+
+def _leave(lib, cur, other, tensors):
+    if other:
+        cur.wait_stream(lib)
+        for x in tensors:
+            if x is not None:
+                x.record_stream(lib)
 
 
 class EpipolarLoss(torch.autograd.Function):
@@ -22,9 +47,9 @@ class EpipolarLoss(torch.autograd.Function):
             if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
                 raise ValueError("parameters must be contiguous float64 CUDA tensors")
         out = torch.empty(1, dtype=torch.float64, device=a6.device)
-        torch.cuda.current_stream().synchronize()
+        lib, cur, other = _enter(fctx, a6.device)
         fctx.loss_dev(a6, t, logf, out)
-        fctx.synchronize()
+        _leave(lib, cur, other, (a6, t, logf, out))
         ctx.save_for_backward(a6, t, logf)
         ctx.fctx = fctx
         return out[0]
@@ -37,9 +62,9 @@ class EpipolarLoss(torch.autograd.Function):
         ga6 = torch.empty_like(a6) if ctx.needs_input_grad[0] else None
         gt = torch.empty_like(t) if ctx.needs_input_grad[1] else None
         glogf = torch.empty_like(logf) if ctx.needs_input_grad[2] else None
-        torch.cuda.current_stream().synchronize()
+        lib, cur, other = _enter(fctx, a6.device)
         fctx.adjoint_dev(a6, t, logf, g, ga6, gt, glogf)
-        fctx.synchronize()
+        _leave(lib, cur, other, (a6, t, logf, g, ga6, gt, glogf))
         return ga6, gt, glogf, None
 
 

@@ -131,7 +131,7 @@ std::vector<DBuf*> all_bufs(fea_ctx* c) {
                  &c->R[1], &c->T[0], &c->T[1], &c->Fc[0], &c->Fc[1], &c->Rh, &c->Th, &c->Fh, &c->gR,
                  &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag, &c->Re, &c->Te, &c->Fe, &c->d_pair_scene, &c->d_inv_z, &c->d_tau, &c->ptab, &c->qpart, &c->qW, &c->qmask, &c->stab, &c->counters,
                  &c->Rh1, &c->Th1, &c->Fh1, &c->Rh2, &c->Th2, &c->Fh2, &c->d_fbar, &c->mlp, &c->wlay,
-                 &c->item_wsum, &c->d_inv_zw, &c->d_scene_mode, &c->d_fbar_hist, &c->d_scene_cam_off, &c->d_scene_cams, &c->d_scene_z, &c->a6h, &c->tph, &c->logfh, &c->restore_flag};
+                 &c->item_wsum, &c->d_inv_zw, &c->d_scene_mode, &c->d_fbar_hist, &c->d_scene_cam_off, &c->d_scene_cams, &c->d_scene_z, &c->a6h, &c->tph, &c->logfh, &c->d_learned_ok, &c->d_fallbacks, &c->d_judge_l0, &c->d_judge_l1};
   for (DBuf* b : one) v.push_back(b);
   return v;
 }
@@ -171,6 +171,32 @@ bool options_valid(const fea_options* o, std::string* why) {
   return true;
 }
 
+// Scenes the non-finite guard has stopped (waits for the stream): the counts
+// of converged and stopped scenes, and FEA_ENONFINITE if more are stopped
+// than at the previous check.
+fea_status check_nonfinite(fea_ctx* c, int32_t* converged = nullptr, int32_t* stopped = nullptr) {
+  std::vector<int32_t> done;
+  HIP_OR_FAIL(c, download(c, done, c->d_scene_done, (size_t)c->S));
+  int32_t nc = 0, nb = 0;
+  std::string which;
+  for (int s = 0; s < c->S; ++s) {
+    nc += done[s] > 0 ? 1 : 0;
+    if (done[s] < 0) {
+      ++nb;
+      if (which.size() < 120) which += " " + std::to_string(s);
+    }
+  }
+  if (converged) *converged = nc;
+  if (stopped) *stopped = nb;
+  const int32_t before = c->n_nonfinite;
+  c->n_nonfinite = nb;
+  if (nb > before)
+    return fail(c, FEA_ENONFINITE,
+                "non-finite parameters, poses or loss in scene(s)" + which +
+                    ": their poses are the last finite round snapshot and they take no further steps");
+  return FEA_OK;
+}
+
 double median(std::vector<double> v) {
   if (v.empty()) return 1.0;
   std::sort(v.begin(), v.end());
@@ -184,6 +210,7 @@ double median(std::vector<double> v) {
 // No scene converged (start of a solve, new scenes).
 hipError_t clear_convergence(fea_ctx* c) {
   c->n_done = 0;
+  c->n_nonfinite = 0;
   c->prev_tau_px = -1.0;
   c->scene_done_h.assign(c->S, 0);
   hipError_t e = hipSuccess;
@@ -250,6 +277,32 @@ hipError_t build_items(fea_ctx* c) {
   return dalloc(c->item_base, std::max<int64_t>(c->n_items, 1) * 2 * sizeof(int32_t));
 }
 
+// Every scene may use learned weights again, no rejection counted.
+hipError_t reset_judge(fea_ctx* c) {
+  c->scene_learned_ok.assign(c->S, 1);
+  c->fallbacks = 0;
+  c->fallbacks_base = 0;
+  c->judge_pending = false;
+  hipError_t e = upload(c, c->d_learned_ok, c->scene_learned_ok.data(), c->S);
+  if (e != hipSuccess || c->S == 0) return e;
+  return hipMemsetAsync(c->d_fallbacks.p, 0, (size_t)c->S * sizeof(int32_t), c->stream);
+}
+
+// The judge's per-scene verdicts and weighting modes as the device holds
+// them, into the host's records (waits for the stream).
+hipError_t refresh_learned_host(fea_ctx* c) {
+  if (c->S == 0) return hipSuccess;
+  std::vector<int32_t> fb;
+  hipError_t e;
+  if ((e = download(c, c->scene_learned_ok, c->d_learned_ok, c->S)) != hipSuccess) return e;
+  if ((e = download(c, c->scene_mode, c->d_scene_mode, c->S)) != hipSuccess) return e;
+  if ((e = download(c, fb, c->d_fallbacks, c->S)) != hipSuccess) return e;
+  c->fallbacks = c->fallbacks_base;
+  for (int32_t v : fb) c->fallbacks += v;
+  c->judge_pending = false;
+  return hipSuccess;
+}
+
 // Per-scene device arrays sized by the number of scenes.
 hipError_t alloc_scene_arrays(fea_ctx* c) {
   hipError_t e;
@@ -262,6 +315,10 @@ hipError_t alloc_scene_arrays(fea_ctx* c) {
   if ((e = dalloc(c->d_scene_z, ((size_t)c->S + 1) * sizeof(int64_t))) != hipSuccess) return e;
   if ((e = dalloc(c->d_scene_done, (size_t)c->S * sizeof(int32_t))) != hipSuccess) return e;
   if ((e = dalloc(c->d_scene_change, (size_t)c->S * sizeof(double))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_learned_ok, (size_t)c->S * sizeof(int32_t))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_fallbacks, (size_t)c->S * sizeof(int32_t))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_judge_l0, (size_t)c->S * sizeof(double))) != hipSuccess) return e;
+  if ((e = dalloc(c->d_judge_l1, (size_t)c->S * sizeof(double))) != hipSuccess) return e;
   if ((e = upload(c, c->d_cam_scene, c->cam_scene.data(), c->cam_scene.size())) != hipSuccess) return e;
   // cameras of each scene, for the device round start
   std::vector<int32_t> off(c->S + 1, 0), cams(c->N, 0);
@@ -280,8 +337,7 @@ hipError_t alloc_scene_arrays(fea_ctx* c) {
   if ((e = hipMemsetAsync(c->d_scene_mode.p, 0, c->d_scene_mode.bytes, c->stream)) != hipSuccess) return e;
   if ((e = clear_convergence(c)) != hipSuccess) return e;
   c->scene_mode.assign(c->S, 0);
-  c->scene_learned_ok.assign(c->S, 1);
-  return hipSuccess;
+  return reset_judge(c);
 }
 
 // The round values computed on the device (thresholds and focal-length
@@ -707,13 +763,28 @@ hipError_t quad_round(fea_ctx* c) {
 // from a checkpoint) and, for scenes on learned weights, the network's weight
 // of every retained match and 1 / (sum of weights).
 hipError_t round_weights(fea_ctx* c, bool choose_mode) {
-  c->learned_any = false;
-  for (int sc = 0; sc < c->S; ++sc) {
-    if (choose_mode)
-      c->scene_mode[sc] = (c->opt.weight_mode == 1 && c->have_mlp && c->scene_learned_ok[sc]) ? 1 : 0;
-    c->learned_any = c->learned_any || c->scene_mode[sc];
+  hipError_t e = hipSuccess;
+  if (choose_mode) {
+    // the device holds the judge's verdicts; the host reads its copy of
+    // them only once the copy has landed (no wait), so it may run the
+    // network one round longer than needed -- the modes themselves come
+    // from the device's flags
+    if (c->judge_pending && hipEventQuery(c->judge_ev) == hipSuccess) {
+      c->scene_learned_ok.assign(c->judge_ok_h, c->judge_ok_h + c->S);
+      c->judge_pending = false;
+    }
+    const bool enabled = c->opt.weight_mode == 1 && c->have_mlp;
+    c->learned_any = false;
+    for (int sc = 0; sc < c->S; ++sc) {
+      c->scene_mode[sc] = (enabled && c->scene_learned_ok[sc]) ? 1 : 0;
+      c->learned_any = c->learned_any || c->scene_mode[sc];
+    }
+    e = fea::launch_choose_mode(c, enabled);
+  } else {
+    c->learned_any = false;
+    for (int sc = 0; sc < c->S; ++sc) c->learned_any = c->learned_any || c->scene_mode[sc];
+    e = upload(c, c->d_scene_mode, c->scene_mode.data(), c->S);
   }
-  hipError_t e = upload(c, c->d_scene_mode, c->scene_mode.data(), c->S);
   if (e != hipSuccess || !c->learned_any) return e;
   // the feature table reads the medians the round start left on the device
   if ((e = fea::launch_mlp_weights(c, c->mlp.as<float>(), c->wlay.as<unsigned short>(),
@@ -735,6 +806,9 @@ hipError_t round_weights(fea_ctx* c, bool choose_mode) {
 // the device's compaction).
 fea_status begin_round(fea_ctx* c, double tau_px, bool sync) {
   const size_t N = c->N;
+  // a scene whose parameters, poses or loss went non-finite in the round
+  // that just ended gets its snapshot back and stops
+  if (c->round >= 0) HIP_OR_FAIL(c, fea::launch_guard(c, c->round + 1));
   if (c->opt.converge_deg > 0 && c->round >= 0) {
     // per-scene convergence over the round that just ended (before its
     // snapshot is replaced); a scene can converge only while the threshold
@@ -1007,6 +1081,8 @@ void fea_destroy(fea_ctx* c) {
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->loss_log) (void)hipHostFree(c->loss_log);
   if (c->inl_log) (void)hipHostFree(c->inl_log);
+  if (c->judge_ok_h) (void)hipHostFree(c->judge_ok_h);
+  if (c->judge_ev) (void)hipEventDestroy(c->judge_ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1123,6 +1199,7 @@ fea_status fea_get_scene_stats(fea_ctx* c, double* loss, int64_t* retained, doub
   if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
   DeviceGuard g(c->device);
   HIP_OR_FAIL(c, refresh_round_host(c));
+  HIP_OR_FAIL(c, refresh_learned_host(c));
   if (loss) {
     std::vector<double> lc;
     HIP_OR_FAIL(c, download(c, lc, c->loss_cam, c->N));
@@ -1279,6 +1356,9 @@ fea_status fea_init_poses(fea_ctx* c, const double* R, const double* t) {
   fea_status s = put_poses(c, R, t, c->f_in.data(), true);
   if (s != FEA_OK) return s;
   HIP_OR_FAIL(c, reset_layout(c));
+  // the per-camera loss shares are read by the non-finite guard before any
+  // step may have written them
+  HIP_OR_FAIL(c, hipMemsetAsync(c->loss_cam.p, 0, c->loss_cam.bytes, c->stream));
   if (c->opt.log_every > 0 && c->opt.max_log > 0)
     HIP_OR_FAIL(c, dalloc(c->logR, (size_t)c->opt.max_log * 9 * c->N * sizeof(double)));
   drop_graph(c);
@@ -1286,10 +1366,9 @@ fea_status fea_init_poses(fea_ctx* c, const double* R, const double* t) {
   HIP_OR_FAIL(c, clear_convergence(c));
   c->adam_t = 0;
   HIP_OR_FAIL(c, set_counters(c, 0, 0));
-  c->scene_learned_ok.assign(c->S, 1);
   c->scene_mode.assign(c->S, 0);
   c->learned_any = false;
-  c->fallbacks = 0;
+  HIP_OR_FAIL(c, reset_judge(c));
   c->have_poses = true;
   return FEA_OK;
 }
@@ -1307,7 +1386,9 @@ fea_status fea_begin_round(fea_ctx* c, double tau_px) {
   if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
   if (std::isnan(tau_px) || !(tau_px > 0)) return fail(c, FEA_EINVAL, "tau_px must be > 0 (or INFINITY)");
   DeviceGuard g(c->device);
-  return begin_round(c, tau_px, true);
+  fea_status s = begin_round(c, tau_px, true);
+  if (s != FEA_OK) return s;
+  return check_nonfinite(c);
 }
 
 fea_status fea_residual_grad(fea_ctx* c, double* loss_dev, double* gR_dev, double* gt_dev, double* gf_dev) {
@@ -1350,6 +1431,24 @@ fea_status fea_get_params_dev(fea_ctx* c, double* a6_dev, double* t_dev, double*
   return FEA_OK;
 }
 
+fea_status fea_set_params_dev(fea_ctx* c, const double* a6_dev, const double* t_dev, const double* logf_dev) {
+  if (!c) return FEA_EINVAL;
+  if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
+  if (!a6_dev || !t_dev || !logf_dev) return fail(c, FEA_EINVAL, "null device array");
+  DeviceGuard g(c->device);
+  const size_t N = c->N, d = sizeof(double);
+  const int p = c->pcur;
+  HIP_OR_FAIL(c, fea::launch_params_to_pose(c, a6_dev, t_dev, logf_dev));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->a6.p, a6_dev, 6 * N * d, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->tp.p, t_dev, 3 * N * d, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->logf.p, logf_dev, (size_t)c->G * d, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->R[p].p, c->Re.p, 9 * N * d, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->T[p].p, c->Te.p, 3 * N * d, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->Fc[p].p, c->Fe.p, N * d, hipMemcpyDeviceToDevice, c->stream));
+  c->ptab_current = false;
+  return FEA_OK;
+}
+
 fea_status fea_loss_dev(fea_ctx* c, const double* a6_dev, const double* t_dev, const double* logf_dev,
                         double* loss_dev) {
   if (!c) return FEA_EINVAL;
@@ -1388,21 +1487,40 @@ fea_status fea_step(fea_ctx* c, int32_t n_steps) {
 namespace {
 
 // Plain IRLS objective per scene at poses (R, T, F) with this round's
-// snapshot weights (loss-only pass, learned weights ignored).
-fea_status plain_loss_per_scene(fea_ctx* c, const double* R, const double* T, const double* F,
-                                std::vector<double>& out) {
+// snapshot weights (loss-only pass, learned weights ignored) into the
+// device array out [S]; no host wait unless the scenes' items interleave.
+fea_status plain_loss_per_scene(fea_ctx* c, const double* R, const double* T, const double* F, DBuf& out) {
   HIP_OR_FAIL(c, fea::launch_resgrad_at(c, c->tile_cfg, R, T, F, true, true));
   if (c->scene_items_contiguous) {
-    HIP_OR_FAIL(c, fea::launch_scene_loss(c));
-    HIP_OR_FAIL(c, download(c, out, c->scene_loss, (size_t)c->S));
+    HIP_OR_FAIL(c, fea::launch_scene_loss(c, out.as<double>()));
     return FEA_OK;
   }
   // scenes with interleaved camera ids: sum the item losses on the host
-  std::vector<double> part;
+  std::vector<double> part, sum(c->S, 0.0);
   HIP_OR_FAIL(c, download(c, part, c->part, (size_t)c->n_items * fea::kPartStride));
-  out.assign(c->S, 0.0);
   for (int64_t it = 0; it < c->n_items; ++it)
-    out[c->pair_scene[c->h_item_pair[it]]] += part[it * fea::kPartStride + 9];
+    sum[c->pair_scene[c->h_item_pair[it]]] += part[it * fea::kPartStride + 9];
+  HIP_OR_FAIL(c, upload(c, out, sum.data(), (size_t)c->S));
+  return FEA_OK;
+}
+
+// After a learned round: the judge on the device, then its verdicts copied
+// to pinned memory for the host to pick up later without waiting.
+fea_status judge_round(fea_ctx* c) {
+  HIP_OR_FAIL(c, fea::launch_judge(c));
+  if (c->judge_ok_cap < c->S) {
+    if (c->judge_ok_h) HIP_OR_FAIL(c, hipHostFree(c->judge_ok_h));
+    c->judge_ok_h = nullptr;
+    c->judge_ok_cap = 0;
+    HIP_OR_FAIL(c, hipHostMalloc(reinterpret_cast<void**>(&c->judge_ok_h), (size_t)c->S * sizeof(int32_t),
+                                 hipHostMallocDefault));
+    c->judge_ok_cap = c->S;
+  }
+  if (!c->judge_ev) HIP_OR_FAIL(c, hipEventCreateWithFlags(&c->judge_ev, hipEventDisableTiming));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->judge_ok_h, c->d_learned_ok.p, (size_t)c->S * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipEventRecord(c->judge_ev, c->stream));
+  c->judge_pending = true;
   return FEA_OK;
 }
 
@@ -1423,30 +1541,19 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
     fea_status s = begin_round(c, tau_px, false);
     if (s != FEA_OK) return s;
     if (c->opt.converge_deg > 0 && c->n_done == c->S) break;  // every scene converged
-    std::vector<double> l0, l1;
-    if (c->learned_any) {
-      s = plain_loss_per_scene(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), l0);
+    const bool judge = c->learned_any;
+    if (judge) {
+      s = plain_loss_per_scene(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), c->d_judge_l0);
       if (s != FEA_OK) return s;
     }
     s = run_steps(c, c->opt.iters_per_round);
     if (s != FEA_OK) return s;
-    if (c->learned_any) {
+    if (judge) {
       // judge: a learned round must lower the plain objective of its scene
       s = plain_loss_per_scene(c, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
-                               c->Fc[c->pcur].as<double>(), l1);
+                               c->Fc[c->pcur].as<double>(), c->d_judge_l1);
       if (s != FEA_OK) return s;
-      std::vector<int32_t> reject(c->N, 0);
-      bool any = false;
-      for (int sc = 0; sc < c->S; ++sc)
-        if (c->scene_mode[sc] && !(l1[sc] <= l0[sc])) {
-          c->scene_learned_ok[sc] = 0;
-          c->fallbacks += 1;
-          any = true;
-        }
-      if (any) {
-        for (int i = 0; i < c->N; ++i) reject[i] = c->scene_mode[c->cam_scene[i]] && !c->scene_learned_ok[c->cam_scene[i]];
-        HIP_OR_FAIL(c, fea::launch_restore(c, reject));
-      }
+      if ((s = judge_round(c)) != FEA_OK) return s;
     }
     if (r < 64) {
       // into pinned memory, so the copy is queued without waiting for the
@@ -1471,6 +1578,8 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
     rep.rounds_run = r + 1;
     rep.iters_run += c->opt.iters_per_round;
   }
+  // the last round's end is checked as every round's is
+  if (rep.rounds_run > 0) HIP_OR_FAIL(c, fea::launch_guard(c, c->round + 1));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   for (int r = 0; r < std::min(rep.rounds_run, 64); ++r) {
     rep.loss_per_round[r] = c->loss_log[r];
@@ -1478,10 +1587,11 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
   }
   rep.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   rep.n_logged = c->n_logged;
+  HIP_OR_FAIL(c, refresh_learned_host(c));
   rep.fallbacks = c->fallbacks;
-  rep.scenes_converged = c->n_done;
+  const fea_status guard = check_nonfinite(c, &rep.scenes_converged, &rep.scenes_nonfinite);
   if (out) *out = rep;
-  return FEA_OK;
+  return guard;
 }
 
 namespace {
@@ -1578,7 +1688,8 @@ fea_status fea_batch_solve(int32_t n_scenes, fea_ctx* const* scenes, const fea_o
   if ((st = pass(fea_init_poses(b, R.data(), t.data()))) != FEA_OK) return st;
   if ((st = pass(fea_set_poses(b, R.data(), t.data(), f.data()))) != FEA_OK) return st;
   fea_report rep;
-  if ((st = pass(fea_epipolar_adjust(b, &rep))) != FEA_OK) return st;
+  const fea_status solved = pass(fea_epipolar_adjust(b, &rep));
+  if (solved != FEA_OK && solved != FEA_ENONFINITE) return solved;
   // results back into each scene's context
   std::vector<double> Rb(9 * N), tb(3 * N), fb(N);
   if ((st = pass(fea_get_poses(b, Rb.data(), tb.data(), fb.data()))) != FEA_OK) return st;
@@ -1596,7 +1707,8 @@ fea_status fea_batch_solve(int32_t n_scenes, fea_ctx* const* scenes, const fea_o
     if (!out) continue;
     fea_report& r = out[k];
     std::memset(&r, 0, sizeof(r));
-    r.rounds_run = done[k] > 0 ? std::min(done[k] - 1, rep.rounds_run) : rep.rounds_run;
+    const int32_t ended = done[k] > 0 ? done[k] - 1 : (done[k] < 0 ? -done[k] - 1 : rep.rounds_run);
+    r.rounds_run = std::min(ended, rep.rounds_run);
     r.iters_run = r.rounds_run * o.iters_per_round;
     for (int j = 0; j < std::min(r.rounds_run, 64); ++j) {
       r.loss_per_round[j] = slog[(size_t)j * n_scenes + k];
@@ -1604,9 +1716,10 @@ fea_status fea_batch_solve(int32_t n_scenes, fea_ctx* const* scenes, const fea_o
     }
     r.fallbacks = (o.weight_mode == 1 && !b->scene_learned_ok[k]) ? 1 : 0;
     r.scenes_converged = done[k] > 0 ? 1 : 0;
+    r.scenes_nonfinite = done[k] < 0 ? 1 : 0;
     r.ms_total = rep.ms_total;
   }
-  return FEA_OK;
+  return solved;
 }
 
 fea_status fea_get_scene_convergence(fea_ctx* c, int32_t* converged_round, double* change_deg) {
@@ -1618,9 +1731,19 @@ fea_status fea_get_scene_convergence(fea_ctx* c, int32_t* converged_round, doubl
   HIP_OR_FAIL(c, download(c, done, c->d_scene_done, (size_t)c->S));
   HIP_OR_FAIL(c, download(c, ch, c->d_scene_change, (size_t)c->S));
   for (int s = 0; s < c->S; ++s) {
-    if (converged_round) converged_round[s] = done[s] - 1;
+    if (converged_round) converged_round[s] = done[s] > 0 ? done[s] - 1 : -1;
     if (change_deg) change_deg[s] = ch[s];
   }
+  return FEA_OK;
+}
+
+fea_status fea_get_scene_nonfinite(fea_ctx* c, int32_t* stopped_round) {
+  if (!c || !stopped_round) return FEA_EINVAL;
+  if (!c->have_poses) return fail(c, FEA_ESTATE, "initialise poses first");
+  DeviceGuard g(c->device);
+  std::vector<int32_t> done;
+  HIP_OR_FAIL(c, download(c, done, c->d_scene_done, (size_t)c->S));
+  for (int s = 0; s < c->S; ++s) stopped_round[s] = done[s] < 0 ? -done[s] - 1 : -1;
   return FEA_OK;
 }
 
@@ -1722,6 +1845,7 @@ fea_status fea_get_state(fea_ctx* c, void* buf, size_t* len) {
   }
   DeviceGuard g(c->device);
   HIP_OR_FAIL(c, refresh_round_host(c));
+  HIP_OR_FAIL(c, refresh_learned_host(c));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   StateHdr h;
   std::memset(&h, 0, sizeof(h));
@@ -1835,7 +1959,14 @@ fea_status fea_set_state(fea_ctx* c, const void* buf, size_t len) {
   c->round = h.round;
   c->step = h.step;
   c->n_logged = h.n_logged;
+  // the judge's verdicts back onto the device; earlier rejections are
+  // counted on the host
   c->fallbacks = h.fallbacks;
+  c->fallbacks_base = h.fallbacks;
+  c->judge_pending = false;
+  HIP_OR_FAIL(c, upload(c, c->d_learned_ok, c->scene_learned_ok.data(), S));
+  HIP_OR_FAIL(c, upload(c, c->d_scene_mode, c->scene_mode.data(), S));
+  HIP_OR_FAIL(c, hipMemsetAsync(c->d_fallbacks.p, 0, S * sizeof(int32_t), c->stream));
   c->adam_t = h.adam_t;
   c->global_step = h.global_step;
   c->tau = h.tau;
@@ -1954,6 +2085,12 @@ fea_status fea_synchronize(fea_ctx* c) {
   return FEA_OK;
 }
 
+fea_status fea_get_stream(fea_ctx* c, void** stream) {
+  if (!c || !stream) return FEA_EINVAL;
+  *stream = static_cast<void*>(c->stream);
+  return FEA_OK;
+}
+
 fea_status fea_set_mlp(fea_ctx* c, const float* params) {
   if (!c || !params) return fail(c, FEA_EINVAL, "null argument");
   if (!c->have_intr) return fail(c, FEA_ESTATE, "load intrinsics first");
@@ -1996,6 +2133,7 @@ fea_status fea_get_learned_weights(fea_ctx* c, float* w) {
   if (!c || !w) return fail(c, FEA_EINVAL, "null argument");
   if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
   DeviceGuard g(c->device);
+  HIP_OR_FAIL(c, refresh_learned_host(c));
   std::vector<int32_t> pos, perm;
   std::vector<uint16_t> wl;
   HIP_OR_FAIL(c, download(c, pos, c->lpos[c->cur], c->layout_len));

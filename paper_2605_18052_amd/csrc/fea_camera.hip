@@ -384,24 +384,98 @@ __global__ __launch_bounds__(256) void k_scene_loss(const int32_t* __restrict__ 
   }
 }
 
-// Restores the round-snapshot parameters of flagged cameras (and their
-// intrinsics groups): used when the judge rejects a learned round.
-__global__ void k_restore(int N, const int32_t* __restrict__ flag, const int32_t* __restrict__ group,
-                          const double* __restrict__ a6h, const double* __restrict__ tph,
-                          const double* __restrict__ logfh, const double* __restrict__ Rh,
-                          const double* __restrict__ Th, const double* __restrict__ Fh, double* __restrict__ a6,
-                          double* __restrict__ tp, double* __restrict__ logf, double* __restrict__ R,
-                          double* __restrict__ T, double* __restrict__ F) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N || !flag[c]) return;
-  for (int k = 0; k < 6; ++k) a6[6 * c + k] = a6h[6 * c + k];
-  for (int k = 0; k < 3; ++k) {
-    tp[3 * c + k] = tph[3 * c + k];
-    T[3 * c + k] = Th[3 * c + k];
+// Snapshot of a round start (parameters and the poses derived from them),
+// for the restores below.
+struct SnapView {
+  const double *a6, *tp, *logf, *R, *T, *F;
+};
+struct PoseView {
+  double *a6, *tp, *logf, *R, *T, *F;
+};
+
+// Every camera of a scene (cameras scene_cams[b, e)) gets the snapshot's
+// parameters and poses back, the workgroup's threads over the cameras.
+__device__ void restore_scene(int b, int e, const int32_t* __restrict__ scene_cams,
+                              const int32_t* __restrict__ group, const SnapView& h, const PoseView& p, int nthreads) {
+  for (int k = b + (int)threadIdx.x; k < e; k += nthreads) {
+    const int c = scene_cams[k];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) p.a6[6 * c + q] = h.a6[6 * c + q];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      p.tp[3 * c + q] = h.tp[3 * c + q];
+      p.T[3 * c + q] = h.T[3 * c + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) p.R[9 * c + q] = h.R[9 * c + q];
+    p.F[c] = h.F[c];
+    p.logf[group[c]] = h.logf[group[c]];  // the same value from every camera of the group
   }
-  for (int k = 0; k < 9; ++k) R[9 * c + k] = Rh[9 * c + k];
-  F[c] = Fh[c];
-  logf[group[c]] = logfh[group[c]];  // identical value from every camera of the group
+}
+
+// Non-finite guard at a round boundary, one workgroup per scene: if any of
+// the scene's cameras holds a non-finite parameter (6D rotation,
+// translation, log focal length of its group), pose (R, t, f) or loss share
+// of the last step, every camera of the scene gets the parameters and poses
+// of the snapshot the finished round started from (checked finite when it
+// was taken) and the scene is stopped: done[s] = -(round + 1), which every
+// step kernel honours as it honours a converged scene.  A scene already
+// stopped or converged is left alone.
+constexpr int kGuardThreads = 1024;
+
+__global__ __launch_bounds__(kGuardThreads) void k_guard(const int32_t* __restrict__ scene_cam_off,
+                                                         const int32_t* __restrict__ scene_cams,
+                                                         const int32_t* __restrict__ group, SnapView h, PoseView p,
+                                                         const double* __restrict__ loss_cam, int32_t round,
+                                                         int32_t* __restrict__ done) {
+  const int s = blockIdx.x, tid = threadIdx.x;
+  if (done[s] != 0) return;  // uniform over the workgroup
+  const int b = scene_cam_off[s], e = scene_cam_off[s + 1];
+  int bad = 0;
+  for (int k = b + tid; k < e; k += kGuardThreads) {
+    const int c = scene_cams[k];
+    double acc = p.logf[group[c]] + p.F[c] + loss_cam[c];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc += p.a6[6 * c + q];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc += p.tp[3 * c + q] + p.T[3 * c + q];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc += p.R[9 * c + q];
+    // a sum of finite values can overflow to inf only if the values are
+    // huge, which is as much a failure as a non-finite one
+    bad |= !isfinite(acc);
+  }
+  if (!__syncthreads_or(bad)) return;
+  restore_scene(b, e, scene_cams, group, h, p, kGuardThreads);
+  if (tid == 0) done[s] = -(round + 1);
+}
+
+// The learned-weight judge after a round, on the device: a scene that ran
+// the round on learned weights and whose plain IRLS objective (this round's
+// plain weights) did not go down from the snapshot (l0) to the round's end
+// (l1) -- or is not a number -- gets the snapshot back and plain weights
+// from the next round on (ok[s] = 0; fallbacks[s] counts the rejections).
+__global__ __launch_bounds__(kGuardThreads) void k_judge(const int32_t* __restrict__ scene_cam_off,
+                                                         const int32_t* __restrict__ scene_cams,
+                                                         const int32_t* __restrict__ group, SnapView h, PoseView p,
+                                                         const int32_t* __restrict__ mode,
+                                                         const double* __restrict__ l0,
+                                                         const double* __restrict__ l1, int32_t* __restrict__ ok,
+                                                         int32_t* __restrict__ fallbacks) {
+  const int s = blockIdx.x;
+  if (mode[s] == 0 || l1[s] <= l0[s]) return;  // uniform over the workgroup
+  restore_scene(scene_cam_off[s], scene_cam_off[s + 1], scene_cams, group, h, p, kGuardThreads);
+  if (threadIdx.x == 0) {
+    ok[s] = 0;
+    fallbacks[s] += 1;
+  }
+}
+
+// Weighting mode of each scene for the round: learned while enabled and not
+// rejected by the judge.
+__global__ void k_choose_mode(int S, int enabled, const int32_t* __restrict__ ok, int32_t* __restrict__ mode) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S) mode[s] = (enabled && ok[s] != 0) ? 1 : 0;
 }
 
 // Round start on the device, so that a round needs no host round trip:
@@ -578,10 +652,10 @@ __global__ void k_total_z(int S, int64_t* __restrict__ zs) {
 
 }  // namespace
 
-hipError_t launch_scene_loss(fea_ctx* c) {
+hipError_t launch_scene_loss(fea_ctx* c, double* out) {
   if (c->S == 0) return hipSuccess;
   k_scene_loss<<<(unsigned)c->S, 256, 0, c->stream>>>(c->d_scene_item_off.as<int32_t>(), c->part.as<double>(),
-                                                      c->scene_loss.as<double>());
+                                                      out ? out : c->scene_loss.as<double>());
   return hipGetLastError();
 }
 
@@ -599,30 +673,6 @@ hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero) {
   return hipGetLastError();
 }
 
-hipError_t launch_restore(fea_ctx* c, const std::vector<int32_t>& flag) {
-  hipError_t e = hipSuccess;
-  c->ptab_current = false;
-  if (c->restore_flag.bytes < flag.size() * sizeof(int32_t)) {
-    if (c->restore_flag.p) (void)hipFree(c->restore_flag.p);
-    c->restore_flag.p = nullptr;
-    c->restore_flag.bytes = 0;
-    e = hipMalloc(&c->restore_flag.p, std::max<size_t>(flag.size(), 1) * sizeof(int32_t));
-    if (e != hipSuccess) return e;
-    c->restore_flag.bytes = std::max<size_t>(flag.size(), 1) * sizeof(int32_t);
-  }
-  e = hipMemcpyAsync(c->restore_flag.p, flag.data(), flag.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                     c->stream);
-  if (e != hipSuccess) return e;
-  k_restore<<<(unsigned)((c->N + 255) / 256), 256, 0, c->stream>>>(
-      c->N, c->restore_flag.as<int32_t>(), c->d_group.as<int32_t>(), c->a6h.as<double>(), c->tph.as<double>(),
-      c->logfh.as<double>(), c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), c->a6.as<double>(),
-      c->tp.as<double>(), c->logf.as<double>(), c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
-      c->Fc[c->pcur].as<double>());
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return hipStreamSynchronize(c->stream);
-}
-
 // quad: dL/dF of each pair from its quadratic form W_n (built for the round)
 // instead of the per-match kernel's item partials.
 hipError_t launch_camgrad(fea_ctx* c, int do_update, bool quad) {
@@ -638,7 +688,7 @@ hipError_t launch_camgrad(fea_ctx* c, int do_update, bool quad) {
       c->logf.as<double>(), c->m_a6.as<double>(), c->v_a6.as<double>(), c->m_t.as<double>(),                   \
       c->v_t.as<double>(), c->m_f.as<double>(), c->v_f.as<double>(), adam_args(c), step_ctl(c),                \
       c->R[nx].as<double>(), c->T[nx].as<double>(), c->Fc[nx].as<double>(), c->d_cam_scene.as<int32_t>(),     \
-      c->opt.converge_deg > 0 ? c->d_scene_done.as<int32_t>() : nullptr
+      c->d_scene_done.as<int32_t>()
   if (quad)
     k_camgrad<true><<<blocks, 256, 0, c->stream>>>(FEA_CAMGRAD_ARGS);
   else
@@ -667,7 +717,7 @@ hipError_t launch_focal_update(fea_ctx* c) {
       c->G, c->d_grp_off.as<int32_t>(), c->d_grp_cams.as<int32_t>(), c->gf.as<double>(),
       c->Fc[c->pcur].as<double>(), c->opt.optimize_focal, c->logf.as<double>(), c->m_f.as<double>(),
       c->v_f.as<double>(), adam_args(c), c->counters.as<StepCounters>(), c->pcur ^ 1, c->Fc[nx].as<double>(),
-      c->d_cam_scene.as<int32_t>(), c->opt.converge_deg > 0 ? c->d_scene_done.as<int32_t>() : nullptr);
+      c->d_cam_scene.as<int32_t>(), c->d_scene_done.as<int32_t>());
   return hipGetLastError();
 }
 
@@ -682,6 +732,45 @@ hipError_t launch_scene_tau(fea_ctx* c, double tau_px, bool first) {
   k_scene_tau<<<(unsigned)c->S, kTauThreads, 0, c->stream>>>(
       c->S, c->d_scene_cam_off.as<int32_t>(), c->d_scene_cams.as<int32_t>(), c->Fc[c->pcur].as<double>(), tau_px,
       first ? 1 : 0, c->d_fbar_hist.as<double>(), c->d_fbar.as<float>(), c->d_tau.as<double>());
+  return hipGetLastError();
+}
+
+namespace {
+SnapView snap_view(fea_ctx* c) {
+  return SnapView{c->a6h.as<double>(), c->tph.as<double>(), c->logfh.as<double>(),
+                  c->Rh.as<double>(),  c->Th.as<double>(),  c->Fh.as<double>()};
+}
+PoseView pose_view(fea_ctx* c) {
+  const int p = c->pcur;
+  return PoseView{c->a6.as<double>(),   c->tp.as<double>(),   c->logf.as<double>(),
+                  c->R[p].as<double>(), c->T[p].as<double>(), c->Fc[p].as<double>()};
+}
+}  // namespace
+
+hipError_t launch_guard(fea_ctx* c, int32_t round) {
+  if (c->S == 0 || c->N == 0) return hipSuccess;
+  k_guard<<<(unsigned)c->S, kGuardThreads, 0, c->stream>>>(c->d_scene_cam_off.as<int32_t>(),
+                                                           c->d_scene_cams.as<int32_t>(), c->d_group.as<int32_t>(),
+                                                           snap_view(c), pose_view(c), c->loss_cam.as<double>(),
+                                                           round, c->d_scene_done.as<int32_t>());
+  c->ptab_current = false;
+  return hipGetLastError();
+}
+
+hipError_t launch_judge(fea_ctx* c) {
+  if (c->S == 0 || c->N == 0) return hipSuccess;
+  k_judge<<<(unsigned)c->S, kGuardThreads, 0, c->stream>>>(
+      c->d_scene_cam_off.as<int32_t>(), c->d_scene_cams.as<int32_t>(), c->d_group.as<int32_t>(), snap_view(c),
+      pose_view(c), c->d_scene_mode.as<int32_t>(), c->d_judge_l0.as<double>(), c->d_judge_l1.as<double>(),
+      c->d_learned_ok.as<int32_t>(), c->d_fallbacks.as<int32_t>());
+  c->ptab_current = false;
+  return hipGetLastError();
+}
+
+hipError_t launch_choose_mode(fea_ctx* c, bool enabled) {
+  if (c->S == 0) return hipSuccess;
+  k_choose_mode<<<(unsigned)((c->S + 255) / 256), 256, 0, c->stream>>>(
+      c->S, enabled ? 1 : 0, c->d_learned_ok.as<int32_t>(), c->d_scene_mode.as<int32_t>());
   return hipGetLastError();
 }
 
@@ -708,7 +797,7 @@ hipError_t launch_scene_z(fea_ctx* c) {
   k_scene_z<<<(unsigned)c->S, kTauThreads, 0, c->stream>>>(
       c->d_scene_item_off.as<int32_t>(), c->item_keep.as<int32_t>(), c->item_wsum.as<double>(),
       c->learned_any ? 1 : 0, c->d_scene_z.as<int64_t>(), c->d_inv_z.as<float>(), c->d_inv_zw.as<float>(),
-      c->opt.converge_deg > 0 ? c->d_scene_done.as<int32_t>() : nullptr);
+      c->d_scene_done.as<int32_t>());
   k_total_z<<<1, 1, 0, c->stream>>>(c->S, c->d_scene_z.as<int64_t>());
   return hipGetLastError();
 }

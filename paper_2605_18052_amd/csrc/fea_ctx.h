@@ -180,14 +180,23 @@ struct fea_ctx {
   fea::DBuf d_inv_zw;                     // float [S]: 1 / sum of learned weights per scene
   fea::DBuf d_scene_mode;                 // int32 [S]: 1 = learned weights this round, 0 = plain
   fea::DBuf a6h, tph, logfh;              // parameters at the round snapshot (judge fallback)
-  fea::DBuf restore_flag;                 // int32 [N] cameras to restore
+  fea::DBuf d_learned_ok;                 // int32 [S]: 0 once the judge rejected the scene's learned weights
+  fea::DBuf d_fallbacks;                  // int32 [S]: the judge's rejections per scene
+  fea::DBuf d_judge_l0, d_judge_l1;       // double [S]: plain objective at a learned round's start and end
+  int32_t fallbacks_base = 0;             // rejections restored from a checkpoint (added to d_fallbacks)
+  hipEvent_t judge_ev = nullptr;          // recorded after the judge's flags are copied to judge_ok_h
+  int32_t* judge_ok_h = nullptr;          // pinned [S]: d_learned_ok as of the last judge
+  int32_t judge_ok_cap = 0;               // capacity of judge_ok_h
+  bool judge_pending = false;             // judge_ok_h not yet read since judge_ev was recorded
 
   // per-scene early exit (options.converge_deg > 0)
   fea::DBuf d_cam_scene;                  // int32 [N]: scene of each camera
-  fea::DBuf d_scene_done;                 // int32 [S]: 0 active, r + 1 once converged at round r
+  fea::DBuf d_scene_done;                 // int32 [S]: 0 active, r + 1 once converged at round r,
+                                          // -(r + 1) once stopped by the non-finite guard at round r
   fea::DBuf d_scene_change;               // double [S]: largest camera rotation over the last round, degrees
   std::vector<int32_t> scene_done_h;      // host copy of d_scene_done (read at every round start)
-  int32_t n_done = 0;                     // converged scenes
+  int32_t n_done = 0;                     // converged or stopped scenes (read at round starts with converge_deg)
+  int32_t n_nonfinite = 0;                // scenes the non-finite guard had stopped at the last check
   double prev_tau_px = -1.0;              // threshold of the previous round, pixels (-1: none yet)
   fea::DBuf d_scene_loss_log;             // double [64 * S]: each scene's loss at the end of each round
   fea::DBuf d_scene_z_log;                // int64 [64 * S]: each scene's retained matches in each round
@@ -243,12 +252,14 @@ hipError_t launch_mask_slots(fea_ctx* c, int32_t* slot_pos);
 hipError_t launch_quad_reduce(fea_ctx* c, const int32_t* pair_item_off_dev);
 hipError_t launch_focal_update(fea_ctx* c);
 hipError_t launch_loss_sum(fea_ctx* c);
-hipError_t launch_restore(fea_ctx* c, const std::vector<int32_t>& flag);
+hipError_t launch_judge(fea_ctx* c);
+hipError_t launch_choose_mode(fea_ctx* c, bool enabled);
 hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero);
 hipError_t launch_scene_tau(fea_ctx* c, double tau_px, bool first);
 hipError_t launch_scene_z(fea_ctx* c);
-hipError_t launch_scene_loss(fea_ctx* c);
+hipError_t launch_scene_loss(fea_ctx* c, double* out = nullptr);
 hipError_t launch_scene_converge(fea_ctx* c, bool check, int32_t round);
+hipError_t launch_guard(fea_ctx* c, int32_t round);
 hipError_t launch_scene_loss_log(fea_ctx* c, int32_t round);
 hipError_t run_ablation(fea_ctx* c, int variant, int reps, double* ms, float* pair_sum_dev);
 hipError_t launch_camgrad_at(fea_ctx* c, const double* R, const double* T, const double* F);

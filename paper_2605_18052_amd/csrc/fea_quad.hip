@@ -220,7 +220,7 @@ hipError_t launch_quad_build(fea_ctx* c) {
   c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(), \
       c->item_rec.as<int4>(), c->ptab.as<double>(), c->wlay.as<ushort4>(), c->qmask.as<uchar4>(), c->opt.delta,  \
       c->qpart.as<double>(), c->item_keep.as<int32_t>(), c->item_wsum.as<double>(),                          \
-      c->d_pair_scene.as<int32_t>(), c->opt.converge_deg > 0 ? c->d_scene_done.as<int32_t>() : nullptr
+      c->d_pair_scene.as<int32_t>(), c->d_scene_done.as<int32_t>()
   const unsigned blocks = (unsigned)((c->n_items + kBuildItems - 1) / kBuildItems);
   if (c->learned_any)
     k_quad_build<true><<<blocks, kQuadThreads, 0, c->stream>>>((int32_t)c->n_items, FEA_QUAD_BUILD_ARGS);
@@ -255,7 +255,7 @@ hipError_t launch_quad_reduce(fea_ctx* c, const int32_t* pair_item_off_dev) {
   const int64_t t = c->P * kQuad;
   k_quad_reduce<<<(unsigned)((t + kQuadThreads - 1) / kQuadThreads), kQuadThreads, 0, c->stream>>>(
       (int32_t)c->P, pair_item_off_dev, c->ptab.as<double>(), c->qpart.as<double>(), c->qW.as<double>(),
-      c->d_pair_scene.as<int32_t>(), c->opt.converge_deg > 0 ? c->d_scene_done.as<int32_t>() : nullptr);
+      c->d_pair_scene.as<int32_t>(), c->d_scene_done.as<int32_t>());
   return hipGetLastError();
 }
 

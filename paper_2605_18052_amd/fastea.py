@@ -39,7 +39,8 @@ class fea_report(C.Structure):
     _fields_ = [("rounds_run", C.c_int32), ("iters_run", C.c_int32),
                 ("inliers_per_round", C.c_int64 * 64), ("loss_per_round", C.c_double * 64),
                 ("ms_total", C.c_double), ("n_logged", C.c_int32), ("fallbacks", C.c_int32),
-                ("scenes_converged", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("scenes_converged", C.c_int32), ("scenes_nonfinite", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class fea_info(C.Structure):
@@ -73,6 +74,8 @@ _SIGNATURES = {
     "fea_set_scenes": ([_P, C.c_int32, _P], C.c_int),
     "fea_get_scene_stats": ([_P, _P, _P, _P, _P, _P], C.c_int),
     "fea_get_scene_convergence": ([_P, _P, _P], C.c_int),
+    "fea_get_scene_nonfinite": ([_P, _P], C.c_int),
+    "fea_set_params_dev": ([_P, _P, _P, _P], C.c_int),
     "fea_batch_solve": ([C.c_int32, _P, _P, _P], C.c_int),
     "fea_set_mlp": ([_P, _P], C.c_int),
     "fea_mlp_features_dev": ([_P, _P, _P], C.c_int),
@@ -99,6 +102,7 @@ _SIGNATURES = {
     "fea_ablation": ([_P, C.c_int32, C.c_int32, _P, _P], C.c_int),
     "fea_set_state": ([_P, _P, C.c_size_t], C.c_int),
     "fea_synchronize": ([_P], C.c_int),
+    "fea_get_stream": ([_P, _P], C.c_int),
     "fea_get_rotation_log": ([_P, _P, _P], C.c_int),
     "fea_set_kernel_timing": ([_P, C.c_int32], C.c_int),
     "fea_hbm_probe": ([C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
@@ -229,7 +233,7 @@ def _report(rep):
                 inliers=np.array(rep.inliers_per_round[:min(r, 64)]),
                 loss=np.array(rep.loss_per_round[:min(r, 64)]), ms_total=rep.ms_total,
                 n_logged=rep.n_logged, fallbacks=rep.fallbacks,
-                scenes_converged=rep.scenes_converged)
+                scenes_converged=rep.scenes_converged, scenes_nonfinite=rep.scenes_nonfinite)
 
 
 def batch_solve(contexts, options: fea_options | None = None):
@@ -326,6 +330,29 @@ class Context:
                                               gc.ctypes.data_as(_P), gs.ctypes.data_as(_P),
                                               lm.ctypes.data_as(_P)))
         return dict(loss=loss, retained=ret, gauge_center=gc, gauge_scale=gs, learned=lm)
+
+    def scene_nonfinite(self):
+        """Per scene: the round at whose start the non-finite guard stopped
+        it (the number of rounds run if at the end of the solve), or -1."""
+        S = self.info()["n_scenes"]
+        out = np.zeros(S, dtype=np.int32)
+        self._check(lib().fea_get_scene_nonfinite(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_params_dev(self, a6, t, logf):
+        """Replaces the parameters with float64 device tensors (a6 [N,6], t
+        [N,3], logf [G]) in the context's gauge; ordered after torch's
+        current stream, no host wait."""
+        import torch
+        cur = torch.cuda.current_stream(a6.device)
+        ls = self.torch_stream()
+        if ls.cuda_stream != cur.cuda_stream:
+            ls.wait_stream(cur)
+        self._check(lib().fea_set_params_dev(self._h, self._dev(a6), self._dev(t), self._dev(logf)))
+        if ls.cuda_stream != cur.cuda_stream:
+            cur.wait_stream(ls)
+            for x in (a6, t, logf):
+                x.record_stream(ls)
 
     def scene_convergence(self):
         """(round each scene converged at or -1 [S], mean camera rotation over
@@ -439,9 +466,32 @@ class Context:
     def synchronize(self):
         self._check(lib().fea_synchronize(self._h))
 
+    def stream_handle(self) -> int:
+        """The context's hipStream_t as an integer."""
+        h = C.c_void_p()
+        self._check(lib().fea_get_stream(self._h, C.byref(h)))
+        return int(h.value or 0)
+
+    def torch_stream(self):
+        """The context's stream as a torch stream object (for event ordering
+        against torch's streams); the context keeps ownership."""
+        import torch
+        if getattr(self, "_tstream", None) is None:
+            self._tstream = torch.cuda.ExternalStream(self.stream_handle(),
+                                                      device=torch.device("cuda", self.device))
+        return self._tstream
+
     def epipolar_adjust(self):
+        """Runs the solve; returns its report.  If the non-finite guard
+        stopped a scene, raises FeaError(FEA_ENONFINITE) whose `report`
+        attribute holds the report (the other scenes ran to the end)."""
         rep = fea_report()
-        self._check(lib().fea_epipolar_adjust(self._h, C.byref(rep)))
+        rc = lib().fea_epipolar_adjust(self._h, C.byref(rep))
+        if rc == FEA_ENONFINITE:
+            err = FeaError(rc, lib().fea_last_error(self._h).decode())
+            err.report = _report(rep)
+            raise err
+        self._check(rc)
         return _report(rep)
 
     def get_poses(self):

@@ -82,6 +82,45 @@ def test_epipolar_loss_matches_oracle(name):
     ctx.close()
 
 
+def test_epipolar_loss_orders_on_the_callers_stream():
+    """Parameters produced by torch work still queued on a side stream (no
+    host synchronisation in between) give bit-identical loss and gradients
+    to a fully synchronised call: the library's stream waits for torch's
+    current stream and torch's waits for the library's, through events."""
+    import torch
+
+    from paper_2605_18052_amd.autograd import EpipolarLoss
+    sc = synth.config1()
+    ctx = _setup(sc)
+    a6, t, logf = ctx.get_params()
+    a6p, tp, lp = _perturb_params(a6, t, logf)
+    ref = []
+    for x in (a6p, tp, lp):
+        x.requires_grad_(True)
+    loss = EpipolarLoss.apply(a6p, tp, lp, ctx)
+    loss.backward()
+    torch.cuda.synchronize()
+    ref = [loss.detach().cpu(), a6p.grad.cpu(), tp.grad.cpu(), lp.grad.cpu()]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        # a few milliseconds of queued work that the parameters depend on
+        big = torch.randn(4096, 4096, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+        for _ in range(12):
+            big = torch.tanh(big @ big)
+        z = (big.sum() * 0.0).double()
+        a6s = (a6p.detach() + z).contiguous().requires_grad_(True)
+        ts = (tp.detach() + z).contiguous().requires_grad_(True)
+        ls = (lp.detach() + z).contiguous().requires_grad_(True)
+        loss2 = EpipolarLoss.apply(a6s, ts, ls, ctx)
+        loss2.backward()
+        got = [loss2.detach().clone(), a6s.grad.clone(), ts.grad.clone(), ls.grad.clone()]
+    torch.cuda.synchronize()
+    ctx.close()
+    for a, b in zip(got, ref):
+        assert torch.equal(a.cpu(), b)
+
+
 def test_epipolar_loss_finite_differences():
     """Central differences of the forward agree with the adjoint (loose: the
     forward accumulates in fp32)."""
