@@ -9,10 +9,11 @@ focal length per intrinsics group.
 
 Ordering: the library's work is queued behind everything already issued on
 torch's current stream, and torch's current stream waits for the library's
-work, both through device-side events; the host never waits.  The tensors
-the library reads or writes are marked as used on the library's stream, so
-torch's allocator does not hand their memory out again before that work is
-done.
+work, both through device-side events; the host never waits.  Since torch's
+stream waits right after each call, memory that torch later frees and hands
+out again (on that stream) is reused only after the library's work: the
+tensors are not marked as used on the library's stream, whose lifetime is
+the context's and may end before theirs.
 """
 from __future__ import annotations
 
@@ -32,12 +33,9 @@ def _enter(fctx: fastea.Context, device):
     return lib, cur, other
 
 
-def _leave(lib, cur, other, tensors):
+def _leave(lib, cur, other):
     if other:
         cur.wait_stream(lib)
-        for x in tensors:
-            if x is not None:
-                x.record_stream(lib)
 
 
 class EpipolarLoss(torch.autograd.Function):
@@ -49,7 +47,7 @@ class EpipolarLoss(torch.autograd.Function):
         out = torch.empty(1, dtype=torch.float64, device=a6.device)
         lib, cur, other = _enter(fctx, a6.device)
         fctx.loss_dev(a6, t, logf, out)
-        _leave(lib, cur, other, (a6, t, logf, out))
+        _leave(lib, cur, other)
         ctx.save_for_backward(a6, t, logf)
         ctx.fctx = fctx
         return out[0]
@@ -64,7 +62,7 @@ class EpipolarLoss(torch.autograd.Function):
         glogf = torch.empty_like(logf) if ctx.needs_input_grad[2] else None
         lib, cur, other = _enter(fctx, a6.device)
         fctx.adjoint_dev(a6, t, logf, g, ga6, gt, glogf)
-        _leave(lib, cur, other, (a6, t, logf, g, ga6, gt, glogf))
+        _leave(lib, cur, other)
         return ga6, gt, glogf, None
 
 

@@ -1686,7 +1686,34 @@ fea_status fea_batch_solve(int32_t n_scenes, fea_ctx* const* scenes, const fea_o
                                          w.y2.as<float>(), w.c1.as<int32_t>(), w.c2.as<int32_t>()))) != FEA_OK)
     return st;
   if ((st = pass(fea_init_poses(b, R.data(), t.data()))) != FEA_OK) return st;
-  if ((st = pass(fea_set_poses(b, R.data(), t.data(), f.data()))) != FEA_OK) return st;
+  // each scene's own parameters, poses and gauge, bit for bit: the
+  // caller-frame poses above only set the working context up (their round
+  // trip through the caller's frame is exact only to rounding)
+  {
+    const size_t d = sizeof(double);
+    int32_t gbase = 0;
+    for (int k = 0; k < n_scenes; ++k) {
+      fea_ctx* c = scenes[k];
+      const size_t q = (size_t)cam_off[k], n = (size_t)c->N;
+      HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+      const std::pair<void*, const void*> cp[] = {
+          {b->a6.as<double>() + 6 * q, c->a6.p},
+          {b->tp.as<double>() + 3 * q, c->tp.p},
+          {b->R[b->pcur].as<double>() + 9 * q, c->R[c->pcur].p},
+          {b->T[b->pcur].as<double>() + 3 * q, c->T[c->pcur].p},
+          {b->Fc[b->pcur].as<double>() + q, c->Fc[c->pcur].p}};
+      const size_t len[] = {6 * n * d, 3 * n * d, 9 * n * d, 3 * n * d, n * d};
+      for (int a = 0; a < 5; ++a)
+        HIP_OR_FAIL(c0, hipMemcpyAsync(cp[a].first, cp[a].second, len[a], hipMemcpyDeviceToDevice, b->stream));
+      HIP_OR_FAIL(c0, hipMemcpyAsync(b->logf.as<double>() + gbase, c->logf.p, (size_t)c->G * d,
+                                     hipMemcpyDeviceToDevice, b->stream));
+      for (int a = 0; a < 3; ++a) b->gauge_c[3 * k + a] = c->gauge_c[a];
+      b->gauge_s[k] = c->gauge_s[0];
+      gbase += c->G;
+    }
+    HIP_OR_FAIL(c0, hipStreamSynchronize(b->stream));
+    b->ptab_current = false;
+  }
   fea_report rep;
   const fea_status solved = pass(fea_epipolar_adjust(b, &rep));
   if (solved != FEA_OK && solved != FEA_ENONFINITE) return solved;

@@ -289,6 +289,7 @@ class Context:
         if self._h:
             lib().fea_destroy(self._h)
             self._h = C.c_void_p()
+        self._tstream = None
 
     def __del__(self):
         try:
@@ -351,8 +352,6 @@ class Context:
         self._check(lib().fea_set_params_dev(self._h, self._dev(a6), self._dev(t), self._dev(logf)))
         if ls.cuda_stream != cur.cuda_stream:
             cur.wait_stream(ls)
-            for x in (a6, t, logf):
-                x.record_stream(ls)
 
     def scene_convergence(self):
         """(round each scene converged at or -1 [S], mean camera rotation over
