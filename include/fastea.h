@@ -361,6 +361,23 @@ fea_status fea_mlp_train(int32_t device, const float *feat_dev, const float *tar
 fea_status fea_mlp_grad(int32_t device, const float *feat_dev, const float *target_dev, int64_t n,
                         const float *params_dev, float *grad_dev, double *loss);
 
+/* fea_mlp_grad without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving or training loops,
+ * harnesses that forbid hipMalloc): the same kernels, with the per-workgroup
+ * partials in a fixed workspace the library holds on each GPU it runs on
+ * (about 19.7 MB, kept until the process ends).  Queued on hip_stream
+ * (a hipStream_t; NULL = the null stream) on GPU `device`, which becomes
+ * current for the call only; nothing is allocated, freed or waited for.
+ * n in [1, FEA_MLP_NOALLOC_MAX_SAMPLES]; grad_dev [FEA_MLP_PARAMS] receives
+ * the gradient of the mean BCE loss and loss_dev [1] (device, nullable) the
+ * mean loss.  Calls that overlap on one GPU share the workspace and race:
+ * order them on one stream.  FEA_EINVAL for a NULL array, n outside the
+ * range or an unknown device; FEA_EDEVICE if a launch fails. */
+#define FEA_MLP_NOALLOC_MAX_SAMPLES 65536
+fea_status fea_mlp_grad_noalloc(int32_t device, void *hip_stream, const float *feat_dev,
+                                const float *target_dev, int64_t n, const float *params_dev,
+                                float *grad_dev, double *loss_dev);
+
 /* n_steps first-order steps of the current round (Method > First-order
  * Optimization; Adam as the optimiser the paper cites), each a residual,
  * weight and gradient pass over the round's objective, the per-camera chain

@@ -51,6 +51,9 @@ constexpr int kMlpFeat = 8;
 constexpr int kMlpHidden = 64;
 constexpr int kMlpParams = kMlpHidden * kMlpFeat + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
                            kMlpHidden + 1;
+// Largest sample count of fea_mlp_grad_noalloc (its workspace holds one
+// gradient partial per 64 samples: 1,024 x 4,801 floats, about 19.7 MB).
+constexpr int64_t kMlpNoAllocMaxSamples = FEA_MLP_NOALLOC_MAX_SAMPLES;
 constexpr int tile_matches_of(int cfg) { return kTiles[cfg].threads * kVec * kTiles[cfg].steps; }
 
 // Device-side step counters, one slot per pose parity p (see the camera

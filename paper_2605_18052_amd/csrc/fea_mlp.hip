@@ -25,6 +25,8 @@
 // activations, per-workgroup partials summed in a fixed order, then Adam.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "fea_ctx.h"
 #include "fea_device.h"
 
@@ -430,9 +432,11 @@ __global__ __launch_bounds__(kTrainThreads) void k_mlp_fwd_bwd(
   }
 }
 
-// grad[p] = sum over workgroups of their partial (fixed order).
+// grad[p] = sum over workgroups of their partial (fixed order); the loss
+// sum times `scale` is added to loss_acc[0] (accumulate) or stored there.
 __global__ void k_mlp_grad_reduce(int n_parts, const float* __restrict__ gpart, float* __restrict__ grad,
-                                  const double* __restrict__ lpart, double* __restrict__ loss_acc) {
+                                  const double* __restrict__ lpart, double* __restrict__ loss_acc, int accumulate,
+                                  double scale) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < kMlpParams) {
     float s = 0.f;
@@ -442,7 +446,7 @@ __global__ void k_mlp_grad_reduce(int n_parts, const float* __restrict__ gpart, 
   if (p == 0) {
     double L = 0.0;
     for (int w = 0; w < n_parts; ++w) L += lpart[w];
-    loss_acc[0] += L;
+    loss_acc[0] = accumulate ? loss_acc[0] + L * scale : L * scale;
   }
 }
 
@@ -493,7 +497,7 @@ hipError_t mlp_train_step(hipStream_t st, const float* feat, const float* target
                                                  1.f / (float)batch, gpart, lpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_mlp_grad_reduce<<<(kMlpParams + 255) / 256, 256, 0, st>>>(parts, gpart, grad, lpart, loss_acc);
+  k_mlp_grad_reduce<<<(kMlpParams + 255) / 256, 256, 0, st>>>(parts, gpart, grad, lpart, loss_acc, 1, 1.0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const float b1 = 0.9f, b2 = 0.999f;
@@ -511,10 +515,80 @@ hipError_t mlp_grad_once(hipStream_t st, const float* feat, const float* target,
                                                  lpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_mlp_grad_reduce<<<(kMlpParams + 255) / 256, 256, 0, st>>>(parts, gpart, grad, lpart, loss_acc);
+  k_mlp_grad_reduce<<<(kMlpParams + 255) / 256, 256, 0, st>>>(parts, gpart, grad, lpart, loss_acc, 1, 1.0);
   return hipGetLastError();
 }
 
 int mlp_train_threads() { return kTrainThreads; }
 
+// ---- gradient without allocation ------------------------------------------
+// Workspace of fea_mlp_grad_noalloc: the per-workgroup loss partials
+// (double [kNoAllocParts]) then the gradient partials (float [kNoAllocParts *
+// kMlpParams]), one copy per GPU for the life of the process.  Host code uses
+// it only through the device address hipGetSymbolAddress returns for the
+// current device (the array's own name is a host-side stand-in).
+constexpr int64_t kNoAllocParts = kMlpNoAllocMaxSamples / kTrainThreads;
+constexpr size_t kScratchLpartBytes = (size_t)kNoAllocParts * sizeof(double);
+constexpr size_t kScratchBytes = kScratchLpartBytes + (size_t)kNoAllocParts * kMlpParams * sizeof(float);
+static_assert(kMlpNoAllocMaxSamples % kTrainThreads == 0, "whole workgroups");
+static_assert(kScratchLpartBytes % 256 == 0, "gradient partials start 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// The device address of this GPU's workspace (looked up once per device,
+// with that device current).
+hipError_t mlp_scratch(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[device]);
+  return hipSuccess;
+}
+
 }  // namespace fea
+
+extern "C" fea_status fea_mlp_grad_noalloc(int32_t device, void* hip_stream, const float* feat_dev,
+                                           const float* target_dev, int64_t n, const float* params_dev,
+                                           float* grad_dev, double* loss_dev) {
+  using namespace fea;
+  if (!feat_dev || !target_dev || !params_dev || !grad_dev) return FEA_EINVAL;
+  if (n < 1 || n > kMlpNoAllocMaxSamples) return FEA_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FEA_EINVAL;
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) return FEA_EDEVICE;
+  if (prev != device && hipSetDevice(device) != hipSuccess) return FEA_EDEVICE;
+  fea_status st = FEA_OK;
+  unsigned char* ws = nullptr;
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (mlp_scratch(device, &ws) != hipSuccess) {
+    st = FEA_EDEVICE;
+  } else {
+    double* lpart = reinterpret_cast<double*>(ws);
+    float* gpart = reinterpret_cast<float*>(ws + kScratchLpartBytes);
+    const int parts = (int)((n + kTrainThreads - 1) / kTrainThreads);
+    k_mlp_fwd_bwd<<<parts, kTrainThreads, 0, s>>>(feat_dev, target_dev, n, 0, n, 1, 0, params_dev,
+                                                  1.f / (float)n, gpart, lpart);
+    if (hipGetLastError() != hipSuccess) st = FEA_EDEVICE;
+    if (st == FEA_OK) {
+      // loss_dev may be NULL: the loss then goes to the workspace's first slot
+      k_mlp_grad_reduce<<<(kMlpParams + 255) / 256, 256, 0, s>>>(parts, gpart, grad_dev, lpart,
+                                                                  loss_dev ? loss_dev : lpart, 0, 1.0 / (double)n);
+      if (hipGetLastError() != hipSuccess) st = FEA_EDEVICE;
+    }
+  }
+  if (prev != device) (void)hipSetDevice(prev);
+  return st;
+}

@@ -83,6 +83,7 @@ _SIGNATURES = {
     "fea_mlp_train": ([C.c_int32, _P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_double, C.c_uint64, _P,
                        _P], C.c_int),
     "fea_mlp_grad": ([C.c_int32, _P, _P, C.c_int64, _P, _P, _P], C.c_int),
+    "fea_mlp_grad_noalloc": ([C.c_int32, _P, _P, _P, C.c_int64, _P, _P, _P], C.c_int),
     "fea_load_matches": ([_P, C.c_int64, _P, _P, _P, _P, _P, _P], C.c_int),
     "fea_load_matches_device": ([_P, C.c_int64, _P, _P, _P, _P, _P, _P], C.c_int),
     "fea_init_poses": ([_P, _P, _P], C.c_int),
