@@ -477,7 +477,8 @@ def main():
     ctx.begin_round(opt.tau_px_init)
     info = ctx.info()
     Z = info["n_retained"]
-    tile = f"{info['tile_matches']}x{info['tile_threads']}"
+    tile = f"{info['tile_matches']}x{info['tile_threads']}" + ("p" if info["tile_persistent"] else "")
+    tune_ms = [round(float(x), 5) for x in ctx.tile_timings()]
     log(f"[bench] loaded and segmented in {seg_s:.2f} s; round 0: {Z} of {sc.n_matches} matches retained, "
         f"{info['n_items']} items of {tile}")
     # timed region: the steps as the library issues them (runs of 10 steps
@@ -628,7 +629,9 @@ def main():
                      "kernel_ms_p10_p50_p90": [float(np.percentile(k_each, q)) for q in (10, 50, 90)],
                      "bytes_per_launch": BYTES_PER_MATCH * Z,
                      "measured_read_peak": read_peak, "frac_of_measured_read_peak": achieved / read_peak,
-                     "tile": f"{info['tile_matches']} matches x {info['tile_threads']} threads",
+                     "tile": f"{info['tile_matches']} matches x {info['tile_threads']} threads"
+                             + (", persistent workgroups" if info["tile_persistent"] else ", one workgroup per item"),
+                     "autotuner_ms_per_shape": tune_ms,
                      "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, calibrated on a 1 GiB "
                                        "copy (null if the kernel changed since they were taken)"},
         "cpu_baseline": cpu,

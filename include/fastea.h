@@ -93,7 +93,12 @@ typedef struct {
                               1: the weighted quadratic form of each pair,
                               f^T W_n f with W_n summed over its matches once
                               per round, so that a step costs O(pairs) */
-  int32_t reserved[3];     /* must be zero */
+  int32_t tile_persistent; /* with tile_matches 1024, 2048 or 4096: 1 takes
+                              the persistent launch of that item size (as
+                              many workgroups per CU as reside at once, each
+                              walking the items with the next item's loads
+                              in flight), 0 one workgroup per item (0) */
+  int32_t reserved[2];     /* must be zero */
   double converge_deg;     /* per-scene early exit (0 = off, default): at the
                               start of a round whose threshold equals the
                               previous round's (the schedule at its floor), a
@@ -138,7 +143,11 @@ typedef struct {
   int32_t tile_matches;  /* matches per work item of the per-match kernel */
   int32_t tile_threads;  /* threads per workgroup of the per-match kernel */
   int32_t n_scenes;      /* independent scenes in the context (fea_set_scenes) */
-  int32_t reserved[5];
+  int32_t tile_persistent; /* 0: one workgroup per work item; 1: as many
+                              workgroups per CU as reside at once, each
+                              walking the items with the next item's loads
+                              in flight */
+  int32_t reserved[4];
 } fea_info;
 
 /* Library version (FEA_VERSION of the build). */
@@ -314,7 +323,8 @@ fea_status fea_adjoint_dev(fea_ctx *ctx, const double *a6_dev, const double *t_d
  * An MLP 8 -> 64 -> 64 -> 1 (ReLU, ReLU, sigmoid) maps each retained match's
  * features to a weight in (0, 1) that multiplies its IRLS weight; the
  * network runs once per round (matrix cores, fp16 activations and weights,
- * fp32 accumulation; the weight is kept per match as bf16).  Features:
+ * fp32 accumulation; the features enter as two fp16 parts; the weight is
+ * kept per match as fp16).  Features:
  * the match's residual at the last three round snapshots as
  * log(1 + |eps| * median f) / log(257), its keypoints scaled to [-1, 1] by
  * each camera's principal point (x/cx - 1, ...; the keypoint in the camera
@@ -483,6 +493,14 @@ fea_status fea_set_state(fea_ctx *ctx, const void *buf, size_t len);
 
 /* Sizes and state. */
 fea_status fea_get_info(fea_ctx *ctx, fea_info *out);
+
+/* The autotuner's last tuning on this context: ms [cap] receives the mean
+ * time of one per-match pass for each candidate work-item shape (13 shapes:
+ * 1024 to 8192 matches per item, 128 to 512 threads, one workgroup per item
+ * or persistent workgroups); *n the number of shapes timed (0 if the shape
+ * was given or reused).  The pick is the first shape, in that order, within
+ * 3% of the fastest. */
+fea_status fea_get_tile_timings(fea_ctx *ctx, float *ms, int32_t cap, int32_t *n);
 
 /* Blocks until all work issued on the context's stream has finished. */
 fea_status fea_synchronize(fea_ctx *ctx);

@@ -165,7 +165,10 @@ bool options_valid(const fea_options* o, std::string* why) {
   // 8192 matches).
   if (o->weight_mode == 1 && o->inner_loop == 1 && o->tile_matches != 0 && o->tile_matches != 8192)
     return bad("learned weights with the quadratic form support tile_matches 0 or 8192 only");
-  for (int k = 0; k < 3; ++k)
+  if (o->tile_persistent != 0 && o->tile_persistent != 1) return bad("tile_persistent must be 0 or 1");
+  if (o->tile_persistent == 1 && o->tile_matches != 1024 && o->tile_matches != 2048 && o->tile_matches != 4096)
+    return bad("tile_persistent = 1 needs tile_matches 1024, 2048 or 4096");
+  for (int k = 0; k < 2; ++k)
     if (o->reserved[k] != 0) return bad("reserved option fields must be zero");
   if (!(o->converge_deg >= 0) || !std::isfinite(o->converge_deg)) return bad("converge_deg must be finite and >= 0");
   return true;
@@ -370,9 +373,9 @@ hipError_t upload_fbar(fea_ctx* c) {
   return upload(c, c->d_fbar_hist, c->fbar_hist.data(), c->fbar_hist.size());
 }
 
-int tile_cfg_for(int32_t tile_matches) {
+int tile_cfg_for(int32_t tile_matches, bool persistent = false) {
   for (int k = 0; k < fea::kNumTiles; ++k)
-    if (fea::tile_matches_of(k) == tile_matches) return k;
+    if (fea::tile_matches_of(k) == tile_matches && fea::kTiles[k].persistent == persistent) return k;
   return -1;
 }
 
@@ -395,10 +398,18 @@ int size_class(int64_t n) { return n > 0 ? (int)std::lround(4.0 * std::log2((dou
 // the requested size, the shape chosen earlier in this process for a problem
 // of the same size class, or the fastest of the candidate shapes timed on
 // this layout with HIP events (three launches each after one warm-up).
+hipError_t choose_tile_impl(fea_ctx* c);
+
 hipError_t choose_tile(fea_ctx* c) {
+  const hipError_t e = choose_tile_impl(c);
+  if (e == hipSuccess) fea::prepare_resgrad(c->tile_cfg);
+  return e;
+}
+
+hipError_t choose_tile_impl(fea_ctx* c) {
   if (c->tile_tuned) return hipSuccess;
   if (c->opt.tile_matches > 0) {
-    c->tile_cfg = tile_cfg_for(c->opt.tile_matches);
+    c->tile_cfg = tile_cfg_for(c->opt.tile_matches, c->opt.tile_persistent == 1);
     c->tile_tuned = true;
     return hipSuccess;
   }
@@ -427,8 +438,7 @@ hipError_t choose_tile(fea_ctx* c) {
     (void)hipEventDestroy(e0);
     return e;
   }
-  float best = 1e30f;
-  int best_cfg = 0;
+  std::vector<float> times(fea::kNumTiles, 0.f);
   for (int k = 0; k < fea::kNumTiles && e == hipSuccess; ++k) {
     c->tile_cfg = k;
     if ((e = build_items(c)) != hipSuccess) break;
@@ -440,14 +450,18 @@ hipError_t choose_tile(fea_ctx* c) {
     if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
     float ms = 0.f;
     if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-    if (ms < best) {
-      best = ms;
-      best_cfg = k;
-    }
+    times[k] = ms / 3.f;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return e;
+  // the first shape, in the table's order, within 3% of the fastest: shapes
+  // whose times differ by less than the run-to-run noise would otherwise
+  // trade places between runs
+  const float best = *std::min_element(times.begin(), times.end());
+  int best_cfg = 0;
+  while (times[best_cfg] > 1.03f * best) ++best_cfg;
+  c->tune_ms = times;
   c->tile_cfg = best_cfg;
   c->tile_tuned = true;
   std::lock_guard<std::mutex> lk(g_tile_mu);
@@ -547,7 +561,7 @@ fea_status load_matches_common(fea_ctx* c, int64_t n, const float* x1, const flo
   HIP_OR_FAIL(c, upload(c, c->d_pair_j, c->pair_j.data(), c->P));
   HIP_OR_FAIL(c, upload(c, c->d_cam_off, c->cam_off.data(), N + 1));
   c->tile_tuned = false;
-  c->tile_cfg = (c->opt.tile_matches > 0) ? tile_cfg_for(c->opt.tile_matches) : 0;
+  c->tile_cfg = (c->opt.tile_matches > 0) ? tile_cfg_for(c->opt.tile_matches, c->opt.tile_persistent == 1) : 0;
   HIP_OR_FAIL(c, reset_layout(c));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   reset_round_state(c);
@@ -1054,6 +1068,10 @@ fea_status fea_create(fea_ctx** out, int32_t device, const fea_options* opt, voi
   c->device = device;
   c->opt = o;
   DeviceGuard g(device);
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n_cu < 1)
+    n_cu = 256;
+  c->n_cu = n_cu;
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);
   } else {
@@ -2008,6 +2026,7 @@ fea_status fea_set_state(fea_ctx* c, const void* buf, size_t len) {
   // rebuild the live layout: the full one, then the saved retained set
   c->tile_cfg = h.tile_cfg;
   c->tile_tuned = true;
+  fea::prepare_resgrad(c->tile_cfg);
   HIP_OR_FAIL(c, reset_layout(c));
   if (c->round >= 0) {
     if (c->opt.inner_loop == 1) {
@@ -2102,6 +2121,14 @@ fea_status fea_get_info(fea_ctx* c, fea_info* out) {
   out->tau = c->tau;
   out->tile_matches = fea::tile_matches_of(c->tile_cfg);
   out->tile_threads = fea::kTiles[c->tile_cfg].threads;
+  out->tile_persistent = fea::kTiles[c->tile_cfg].persistent ? 1 : 0;
+  return FEA_OK;
+}
+
+fea_status fea_get_tile_timings(fea_ctx* c, float* ms, int32_t cap, int32_t* n) {
+  if (!c || !n || (cap > 0 && !ms)) return FEA_EINVAL;
+  *n = (int32_t)c->tune_ms.size();
+  for (int32_t k = 0; k < std::min<int32_t>(cap, *n); ++k) ms[k] = c->tune_ms[k];
   return FEA_OK;
 }
 
@@ -2156,6 +2183,24 @@ fea_status fea_mlp_features_dev(fea_ctx* c, float* feat_dev, int32_t* slot_pos_d
   return FEA_OK;
 }
 
+namespace {
+
+// IEEE binary16 bits to float (the learned weights are stored as fp16).
+float half_to_float(uint16_t h) {
+  const uint32_t sign = (uint32_t)(h >> 15) << 31, e = (h >> 10) & 31u, m = h & 1023u;
+  float v;
+  if (e == 0) {
+    v = std::ldexp((float)m, -24);  // zero or subnormal
+  } else if (e == 31) {
+    v = m ? std::numeric_limits<float>::quiet_NaN() : std::numeric_limits<float>::infinity();
+  } else {
+    v = std::ldexp((float)(m | 1024u), (int)e - 25);
+  }
+  return sign ? -v : v;
+}
+
+}  // namespace
+
 fea_status fea_get_learned_weights(fea_ctx* c, float* w) {
   if (!c || !w) return fail(c, FEA_EINVAL, "null argument");
   if (c->round < 0) return fail(c, FEA_ESTATE, "begin a round first");
@@ -2176,12 +2221,7 @@ fea_status fea_get_learned_weights(fea_ctx* c, float* w) {
       const int64_t slot = c->phys_off[n] + k;
       const int32_t p = pos[slot];
       if (p < 0 || p >= c->M || (masked && !qm[slot])) continue;
-      float v = 1.f;
-      if (learned) {
-        const uint32_t u = (uint32_t)wl[slot] << 16;
-        std::memcpy(&v, &u, sizeof(v));
-      }
-      w[perm[p]] = v;
+      w[perm[p]] = learned ? half_to_float(wl[slot]) : 1.f;
     }
   }
   return FEA_OK;

@@ -36,12 +36,18 @@ constexpr int kPairThreads = 256;
 constexpr int kMaxSceneCams = 8192;
 
 // Work-item shapes of the per-match kernel: threads per workgroup and 16-byte
-// loads per thread per array; matches per item = threads * 4 * steps.
+// loads per thread per array (matches per item = threads * 4 * steps), and
+// whether the launch is persistent: as many workgroups per CU as can reside
+// at once, each walking the items with the next item's loads in flight,
+// instead of one workgroup per item.
 struct TileCfg {
   int threads, steps;
+  bool persistent;
 };
-constexpr TileCfg kTiles[] = {{256, 4}, {256, 2}, {256, 1}, {128, 8},
-                              {128, 4}, {128, 2}, {512, 2}, {512, 4}};
+constexpr TileCfg kTiles[] = {{256, 4, false}, {256, 2, false}, {256, 1, false}, {128, 8, false},
+                              {128, 4, false}, {128, 2, false}, {512, 2, false}, {512, 4, false},
+                              {256, 2, true},  {256, 1, true},  {128, 2, true},  {512, 1, true},
+                              {512, 2, true}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 constexpr int kGraphSteps = 10;  // steps per captured graph (even: the pose parity is preserved)
 
@@ -82,6 +88,8 @@ enum : int { kErrSameCam = 1, kErrRange = 2, kErrNonFinite = 4 };
 
 struct fea_ctx {
   int device = 0;
+  int n_cu = 256;                         // compute units of the device (persistent launches)
+  std::vector<float> tune_ms;             // the autotuner's mean time per shape of kTiles (last tuning)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   fea_options opt{};
@@ -178,7 +186,7 @@ struct fea_ctx {
   bool host_z_stale = false;              // Zs, Z live on the device until read back
   int64_t* inl_log = nullptr;             // pinned host: Z of each solver round (64)
   fea::DBuf mlp;                          // float [kMlpParams]
-  fea::DBuf wlay;                         // bf16 [layout] learned weight of each layout slot
+  fea::DBuf wlay;                         // fp16 [layout] learned weight of each layout slot
   fea::DBuf item_wsum;                    // double [n_items]
   fea::DBuf d_inv_zw;                     // float [S]: 1 / sum of learned weights per scene
   fea::DBuf d_scene_mode;                 // int32 [S]: 1 = learned weights this round, 0 = plain
@@ -240,6 +248,7 @@ hipError_t export_sorted(fea_ctx* c, int32_t cam_base, const int64_t* seg_off_de
 // --- per-match pass (fea_resgrad.hip) ---
 hipError_t launch_pair_pose(fea_ctx* c, const double* R, const double* T, const double* F, bool snap);
 hipError_t launch_resgrad_kernel(fea_ctx* c, int cfg, bool loss_only, bool force_plain);
+void prepare_resgrad(int cfg);
 hipError_t launch_resgrad(fea_ctx* c, bool step = false);
 hipError_t launch_resgrad_cfg(fea_ctx* c, int cfg);
 hipError_t launch_resgrad_at(fea_ctx* c, int cfg, const double* R, const double* T, const double* F,

@@ -7,17 +7,22 @@
 // Inference (k_mlp_weights) is a dense contraction, so it runs on the matrix
 // cores: each wave takes 32 matches at a time and evaluates
 //   H1^T = relu(W1 X^T + b1),  H2^T = relu(W2 H1^T + b2),  y = sigmoid(w3.H2 + b3)
-// with fp16 MFMA (fp16 activations and weights, fp32 accumulation; fp16
-// rather than bf16 for the 3 extra significand bits at the same matrix-core
-// rate -- the trained network's hidden values stay below ~20, far inside
-// the fp16 range, and conversions saturate).  The weight is stored per match
-// as bf16.  With
-// the weights as the A operand and the activations as the B operand, the
-// accumulator of one layer is already laid out as the B operand of the next
-// (lane l holds match l%32 and hidden units 8s + 4(l/32) + 0..3 of K-slice
-// s), so no data moves between layers; the output layer is one more MFMA
-// chain whose A operand repeats w3 in every row, so that every accumulator
-// register of lane l ends up holding the logit of match l%32.
+// with fp16 MFMA (fp16 operands, fp32 accumulation; fp16 rather than bf16
+// for the 3 extra significand bits at the same matrix-core rate).  The input
+// features enter as two fp16 parts, x = hi + lo (hi the rounded feature, lo
+// the rounded remainder), through a first layer of contraction depth 16
+// whose A operand holds W1 twice: the rounding of the features, which would
+// dominate the error of the weight, is gone at no extra matrix-core cost
+// (the depth-16 instruction takes as long as the depth-8 one).  Hidden
+// activations are rounded to nearest and saturate at fp16's largest finite
+// value (the trained network's stay below ~20).  The weight is stored per
+// match as fp16.  With the weights as the A operand and the activations as
+// the B operand, the accumulator of one layer is already laid out as the B
+// operand of the next (lane l holds match l%32 and hidden units
+// 8s + 4(l/32) + 0..3 of K-slice s), so no data moves between layers; the
+// output layer is one more MFMA chain whose A operand repeats w3 in every
+// row, so that every accumulator register of lane l ends up holding the
+// logit of match l%32.
 //
 // Training (k_mlp_fwd_bwd, k_mlp_grad_reduce, k_mlp_adam) runs on the vector
 // units in fp32: one thread per sample for the forward and backward passes,
@@ -51,24 +56,28 @@ typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-// Two fp32 values as packed fp16, rounded toward zero (one instruction;
-// values beyond the fp16 range saturate to its largest finite value
-// instead of becoming infinite).
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two fp32 values as packed fp16, rounded to nearest (one instruction).
 __device__ __forceinline__ unsigned pk_f16(float a, float b) {
-  return __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(a, b));
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, f16x2));
 }
 
 // Accumulator registers first..first+7 as one fp16 B-operand slice of the
-// next layer, ReLU applied: each pair is one packed conversion and one
-// packed 16-bit integer max with 0 -- a negative fp16 has its sign bit set,
-// so as a signed integer it is negative and maps to +0, while non-negative
-// values are unchanged (no NaN handling).
+// next layer, ReLU applied: per pair one packed conversion, one packed fp16
+// min with 65504 (an overflow to infinity saturates at fp16's largest
+// finite value) and one packed 16-bit integer max with 0 -- a negative fp16
+// has its sign bit set, so as a signed integer it is negative and maps to
+// +0, while non-negative values are unchanged.
 __device__ __forceinline__ f16x8 relu_slice(const f32x16& acc, int first) {
   u32x4 w;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const unsigned p = pk_f16(acc[first + 2 * k], acc[first + 2 * k + 1]);
-    w[k] = __builtin_bit_cast(unsigned, __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), (s16x2)0));
+    const f16x2 v = __builtin_elementwise_min(
+        __builtin_convertvector((f32x2){acc[first + 2 * k], acc[first + 2 * k + 1]}, f16x2),
+        (f16x2){(_Float16)65504.f, (_Float16)65504.f});
+    w[k] = __builtin_bit_cast(unsigned, __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), (s16x2)0));
   }
   return __builtin_bit_cast(f16x8, w);
 }
@@ -147,25 +156,25 @@ constexpr int kInferThreads = 256;
 // Lanes l < 32 receive lo[] of lane l+32 and lanes l >= 32 receive hi[] of
 // lane l-32 (v_permlane32_swap trades the upper half of its first operand
 // with the lower half of its second).
-__device__ __forceinline__ void swap_half(const float (&lo)[4], const float (&hi)[4], bool upper,
-                                          float (&dst)[4]) {
+__device__ __forceinline__ void swap_half(const u32x4& lo, const u32x4& hi, bool upper, u32x4& dst) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo[q]), __float_as_uint(hi[q]), false, false);
-    dst[q] = __uint_as_float(upper ? r[0] : r[1]);
+    const auto r = __builtin_amdgcn_permlane32_swap(lo[q], hi[q], false, false);
+    dst[q] = upper ? r[0] : r[1];
   }
 }
 
 // Inference over one work item.  Each wave takes 64 matches per iteration,
 // one per lane: the lane computes all 8 features of its match once (the
-// residuals in fp64 with the pair's snapshot matrices read by scalar loads),
-// then lanes l and l^32 trade halves so that the two groups of 32 matches
-// are in the B layout of v_mfma_f32_32x32x8_f16 (lane l: features
-// 4(l/32)..+3 of match l%32).  Layer 1 (K = 8) uses that instruction; layer
-// 2 (K = 64) uses v_mfma_f32_32x32x16_f16, whose B operand takes 8 units per
-// lane: with the contraction index permuted identically in W2's columns, the
-// layer-1 accumulator registers of a lane are that operand as they stand.
-// The next iteration's coordinates are loaded before this one is computed.
+// residuals in fp64 with the pair's snapshot matrices read by scalar loads)
+// and splits them into fp16 parts hi and lo; then lanes l and l^32 trade
+// parts so that the two groups of 32 matches are in the B layout of
+// v_mfma_f32_32x32x16_f16 (lane l < 32: hi of match l; lane l >= 32: lo of
+// match l-32 -- contraction index 8(l/32) + feature).  Layer 2 (K = 64)
+// uses the same instruction, whose B operand takes 8 units per lane: with
+// the contraction index permuted identically in W2's columns, the layer-1
+// accumulator registers of a lane are that operand as they stand.  The next
+// iteration's coordinates are loaded before this one is computed.
 template <bool STORE_FEAT>
 __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
     const float* __restrict__ X1, const float* __restrict__ Y1, const float* __restrict__ X2,
@@ -177,17 +186,18 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
   const int4 rec = items[item];
   const int n = rec.x, start = rec.y, cnt = rec.z;
   const double* row = stab + (int64_t)n * kSnapRow;
-  // weights in the A layout: row (lane%32) + 32*tile; layer 1 k = 4h + q;
-  // layer 2 slice (t2, g) value j <-> hidden-in unit 32 t2 + 16 g + 8 (j/4) + 4 h + j%4
+  // weights in the A layout: row (lane%32) + 32*tile; layer 1: k = 8h + q
+  // multiplies feature q in both halves (hi and lo parts); layer 2 slice
+  // (t2, g) value j <-> hidden-in unit 32 t2 + 16 g + 8 (j/4) + 4 h + j%4
   const int r32 = lane & 31, h = lane >> 5;
-  f16x4 a1[2];
+  f16x8 a1[2];
   f16x8 a2[2][4], a3[4];
   f32x16 b1v[2], b2v[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int orow = r32 + 32 * t;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a1[t][q] = (_Float16)params[orow * kNF + 4 * h + q];
+    for (int q = 0; q < kNF; ++q) a1[t][q] = (_Float16)params[orow * kNF + q];
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl) {
       const int t2 = sl >> 1, g = sl & 1;
@@ -255,27 +265,28 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
       fo[0] = make_float4(f[0], f[1], f[2], f[3]);
       fo[1] = make_float4(f[4], f[5], f[6], f[7]);
     }
-    // lanes l and l^32 trade halves: group A = matches of lanes 0..31,
-    // group B = lanes 32..63
-    float lo[4], hi[4], recv[4];
+    // the features as fp16 parts x = hi + lo, packed in pairs
+    u32x4 fhi, flo;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      lo[q] = f[q];
-      hi[q] = f[4 + q];
+      const f16x2 hv = __builtin_convertvector((f32x2){f[2 * q], f[2 * q + 1]}, f16x2);
+      fhi[q] = __builtin_bit_cast(unsigned, hv);
+      flo[q] = pk_f16(f[2 * q] - (float)hv[0], f[2 * q + 1] - (float)hv[1]);
     }
-    swap_half(lo, hi, h != 0, recv);
+    // lanes l and l^32 trade parts: group A = matches of lanes 0..31,
+    // group B = lanes 32..63; lanes < 32 supply hi, lanes >= 32 lo
+    u32x4 recv;
+    swap_half(fhi, flo, h != 0, recv);
     float zg[2];
 #pragma unroll
     for (int grp = 0; grp < 2; ++grp) {
-      // group A: h=0 own f[0..3], h=1 partner's f[4..7]; group B: h=0
-      // partner's f[0..3], h=1 own f[4..7]
-      float xv[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) xv[q] = (grp == 0) ? (h ? recv[q] : f[q]) : (h ? f[4 + q] : recv[q]);
-      const f16x4 bx = __builtin_bit_cast(f16x4, (u32x2){pk_f16(xv[0], xv[1]), pk_f16(xv[2], xv[3])});
+      // group A: h=0 own hi, h=1 the partner's lo; group B: h=0 the
+      // partner's hi, h=1 own lo
+      const u32x4 xv = (grp == 0) ? (h ? recv : fhi) : (h ? flo : recv);
+      const f16x8 bx = __builtin_bit_cast(f16x8, xv);
       f32x16 acc1[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x8f16(a1[t], bx, b1v[t], 0, 0, 0);
+      for (int t = 0; t < 2; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[t], bx, b1v[t], 0, 0, 0);
       f16x8 hb[4];
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) hb[sl] = relu_slice(acc1[sl >> 1], 8 * (sl & 1));
@@ -297,9 +308,9 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
     // lane l's own match is in group h
     const float w = sigmoidf_((h ? zg[1] : zg[0]) + b3);
     if (valid) {
-      const __bf16 wb = (__bf16)w;
-      Wout[cur] = __builtin_bit_cast(unsigned short, wb);
-      wsum += (float)wb;  // the weight as stored
+      const _Float16 wh = (_Float16)w;
+      Wout[cur] = __builtin_bit_cast(unsigned short, wh);
+      wsum += (float)wh;  // the weight as stored
     }
   }
   wsum = wave_sum_f32(wsum);

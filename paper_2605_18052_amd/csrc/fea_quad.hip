@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
       if (learned) {
         // the network writes only the slots of real matches: the weight of a
         // padding slot is never read into the arithmetic (0 * NaN is NaN)
-        const double wl = (double)__uint_as_float((uint32_t)v4w(cw4, e) << 16);
+        const double wl = (double)(float)__builtin_bit_cast(_Float16, (unsigned short)v4w(cw4, e));
         cw = hold ? cw * wl : 0.0;
         wsum += hold ? wl : 0.0;
       }

@@ -24,6 +24,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "fea_ctx.h"
 #include "fea_device.h"
 
@@ -90,43 +92,57 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_pose(
   }
 }
 
-template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
-__global__ __launch_bounds__(THREADS) void k_resgrad(
-    const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
-    const float4* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ ptab, float delta,
-    double* __restrict__ part, const ushort4* __restrict__ Wl, const uchar4* __restrict__ qmask,
-    int skip_flagged) {
-  __shared__ float s_red[THREADS / kWave][kPartStride];
-  const int tid = threadIdx.x;
-  const int item = blockIdx.x;
-  const int4 rec = items[item];
-  // a step skips the items of converged scenes (flag in the record's last
-  // field); their partials are not read by the update
-  if (skip_flagged && rec.w != 0) return;
-  const int n = rec.x;
-  const int v0 = rec.y >> 2;
-  const int cnt = rec.z;
-  const int nvec = (cnt + kVec - 1) / kVec;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-  float4 qa[STEPS], qb[STEPS], qc[STEPS], qd[STEPS];
-  ushort4 qw[WEIGHTED ? STEPS : 1];
-  uchar4 qm[STEPS];
+__device__ __forceinline__ float4 nt_load(const float4* p) {
+  const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// One work item's coordinates (and learned weights / retained mask) in
+// registers: STEPS 16-byte loads per array per thread, issued together.
+template <int THREADS, int STEPS, bool WEIGHTED>
+struct ItemRegs {
+  float4 a[STEPS], b[STEPS], c[STEPS], d[STEPS];
+  ushort4 w[WEIGHTED ? STEPS : 1];
+  uchar4 m[STEPS];
+
+  __device__ __forceinline__ void load(const float4* __restrict__ X1, const float4* __restrict__ Y1,
+                                       const float4* __restrict__ X2, const float4* __restrict__ Y2,
+                                       const ushort4* __restrict__ Wl, const uchar4* __restrict__ qmask, int4 rec,
+                                       int tid) {
+    const int v0 = rec.y >> 2;
+    const int nvec = (rec.z + kVec - 1) / kVec;
 #pragma unroll
-  for (int s = 0; s < STEPS; ++s) {
-    const int v = s * THREADS + tid;
-    qm[s] = make_uchar4(1, 1, 1, 1);
-    if (v < nvec) {
-      qa[s] = X1[v0 + v];
-      qb[s] = Y1[v0 + v];
-      qc[s] = X2[v0 + v];
-      qd[s] = Y2[v0 + v];
-      if (WEIGHTED) qw[s] = Wl[v0 + v];
-      if (qmask) qm[s] = qmask[v0 + v];
-    } else {
-      qa[s] = qb[s] = qc[s] = qd[s] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (WEIGHTED) qw[s] = make_ushort4(0, 0, 0, 0);
+    for (int s = 0; s < STEPS; ++s) {
+      const int v = s * THREADS + tid;
+      m[s] = make_uchar4(1, 1, 1, 1);
+      if (v < nvec) {
+        // read once per pass: non-temporal, so the stream does not
+        // displace cached data
+        a[s] = nt_load(X1 + v0 + v);
+        b[s] = nt_load(Y1 + v0 + v);
+        c[s] = nt_load(X2 + v0 + v);
+        d[s] = nt_load(Y2 + v0 + v);
+        if (WEIGHTED) w[s] = Wl[v0 + v];
+        if (qmask) m[s] = qmask[v0 + v];
+      } else {
+        a[s] = b[s] = c[s] = d[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (WEIGHTED) w[s] = make_ushort4(0, 0, 0, 0);
+      }
     }
   }
+};
+
+// The residuals, weights and gradient sums of one work item whose data sit
+// in q, reduced over the workgroup into its fp64 partial part[item]
+// (s_red: the workgroup's reduction buffer, free on entry; one barrier).
+template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
+__device__ __forceinline__ void resgrad_item(const ItemRegs<THREADS, STEPS, WEIGHTED>& q, int4 rec, int item,
+                                             const double* __restrict__ ptab, float delta,
+                                             double* __restrict__ part, float (*s_red)[kPartStride], int tid) {
+  const int n = rec.x;
+  const int cnt = rec.z;
   const double* row = ptab + (int64_t)n * kPairRow;
   double F[9], Fhat[9];
 #pragma unroll
@@ -149,17 +165,17 @@ __global__ __launch_bounds__(THREADS) void k_resgrad(
 #pragma unroll
     for (int e = 0; e < kVec; ++e) {
       const int local = (s * THREADS + tid) * kVec + e;
-      const float x1 = v4(qa[s], e), y1 = v4(qb[s], e), x2 = v4(qc[s], e), y2 = v4(qd[s], e);
+      const float x1 = v4(q.a[s], e), y1 = v4(q.b[s], e), x2 = v4(q.c[s], e), y2 = v4(q.d[s], e);
       const double eps = eval_eps(F, x1, y1, x2, y2);
       const double eph = eval_eps(Fhat, x1, y1, x2, y2);
       const float ef = (float)eps;
       const float w = fmaxf(fabsf((float)eph), delta);
       float c = inv_z * __builtin_amdgcn_rcpf(w);
       if (WEIGHTED && learned) {
-        const unsigned short wb = e == 0 ? qw[s].x : (e == 1 ? qw[s].y : (e == 2 ? qw[s].z : qw[s].w));
-        c *= __uint_as_float((uint32_t)wb << 16);
+        const unsigned short wb = e == 0 ? q.w[s].x : (e == 1 ? q.w[s].y : (e == 2 ? q.w[s].z : q.w[s].w));
+        c *= (float)__builtin_bit_cast(_Float16, wb);
       }
-      const unsigned char held = e == 0 ? qm[s].x : (e == 1 ? qm[s].y : (e == 2 ? qm[s].z : qm[s].w));
+      const unsigned char held = e == 0 ? q.m[s].x : (e == 1 ? q.m[s].y : (e == 2 ? q.m[s].z : q.m[s].w));
       c = (local < cnt && held) ? c : 0.f;  // alignment padding and dropped matches hold no weight
       if (!LOSS_ONLY) {
         const float k2 = 2.f * c * ef;
@@ -190,6 +206,69 @@ __global__ __launch_bounds__(THREADS) void k_resgrad(
 #pragma unroll
     for (int w = 0; w < THREADS / kWave; ++w) sum += (double)s_red[w][tid];
     part[(int64_t)item * kPartStride + tid] = sum;
+  }
+}
+
+// One workgroup per work item.
+template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
+__global__ __launch_bounds__(THREADS) void k_resgrad(
+    const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
+    const float4* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ ptab, float delta,
+    double* __restrict__ part, const ushort4* __restrict__ Wl, const uchar4* __restrict__ qmask,
+    int skip_flagged) {
+  __shared__ float s_red[THREADS / kWave][kPartStride];
+  const int tid = threadIdx.x;
+  const int item = blockIdx.x;
+  const int4 rec = items[item];
+  // a step skips the items of converged scenes (flag in the record's last
+  // field); their partials are not read by the update
+  if (skip_flagged && rec.w != 0) return;
+  ItemRegs<THREADS, STEPS, WEIGHTED> q;
+  q.load(X1, Y1, X2, Y2, Wl, qmask, rec, tid);
+  resgrad_item<THREADS, STEPS, LOSS_ONLY, WEIGHTED>(q, rec, item, ptab, delta, part, s_red, tid);
+}
+
+// A fixed number of workgroups per CU, each walking the items
+// blockIdx.x, blockIdx.x + gridDim.x, ...: the next item's record and
+// coordinates are loaded before the current item is computed, so every
+// workgroup keeps its loads in flight while it computes and no load waits
+// on a record.  The reduction buffer alternates between two halves, so one
+// barrier per item suffices.  Same partials as k_resgrad, bit for bit.
+template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
+__global__ __launch_bounds__(THREADS) void k_resgrad_p(
+    const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
+    const float4* __restrict__ Y2, const int4* __restrict__ items, int32_t n_items,
+    const double* __restrict__ ptab, float delta, double* __restrict__ part, const ushort4* __restrict__ Wl,
+    const uchar4* __restrict__ qmask, int skip_flagged) {
+  __shared__ float s_red[2][THREADS / kWave][kPartStride];
+  const int tid = threadIdx.x;
+  int item = blockIdx.x;
+  if (item >= n_items) return;
+  int4 rec = items[item];
+  // two items per trip, so that the two register buffers keep fixed roles
+  // (indexing one array of them by the trip's parity would put them in
+  // scratch memory)
+  ItemRegs<THREADS, STEPS, WEIGHTED> q0, q1;
+  q0.load(X1, Y1, X2, Y2, Wl, qmask, rec, tid);
+  for (;;) {
+    int next = item + (int)gridDim.x;
+    bool more = next < n_items;
+    int4 nrec = more ? items[next] : rec;
+    if (more) q1.load(X1, Y1, X2, Y2, Wl, qmask, nrec, tid);
+    if (!(skip_flagged && rec.w != 0))
+      resgrad_item<THREADS, STEPS, LOSS_ONLY, WEIGHTED>(q0, rec, item, ptab, delta, part, s_red[0], tid);
+    if (!more) break;
+    item = next;
+    rec = nrec;
+    next = item + (int)gridDim.x;
+    more = next < n_items;
+    nrec = more ? items[next] : rec;
+    if (more) q0.load(X1, Y1, X2, Y2, Wl, qmask, nrec, tid);
+    if (!(skip_flagged && rec.w != 0))
+      resgrad_item<THREADS, STEPS, LOSS_ONLY, WEIGHTED>(q1, rec, item, ptab, delta, part, s_red[1], tid);
+    if (!more) break;
+    item = next;
+    rec = nrec;
   }
 }
 
@@ -352,10 +431,35 @@ hipError_t launch_pair_pose(fea_ctx* c, const double* R, const double* T, const 
 
 // With ev0/ev1 set the dispatch itself records the two events at the
 // kernel's start and end (no separate marker packets around it).
+// Workgroups of a persistent per-match kernel that reside on one CU at once
+// (the runtime's occupancy for its register and LDS use), looked up once.
 template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
-hipError_t launch_resgrad_t(fea_ctx* c, hipEvent_t ev0, hipEvent_t ev1, int skip) {
+int persistent_per_cu() {
+  static const int per_cu = [] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_resgrad_p<THREADS, STEPS, LOSS_ONLY, WEIGHTED>, THREADS,
+                                                     0) != hipSuccess ||
+        n < 1)
+      n = 1;
+    return n;
+  }();
+  return per_cu;
+}
+
+template <int THREADS, int STEPS>
+void prepare_persistent() {
+  (void)persistent_per_cu<THREADS, STEPS, false, false>();
+  (void)persistent_per_cu<THREADS, STEPS, true, false>();
+  (void)persistent_per_cu<THREADS, STEPS, false, true>();
+  (void)persistent_per_cu<THREADS, STEPS, true, true>();
+}
+
+template <int THREADS, int STEPS, bool LOSS_ONLY, bool WEIGHTED>
+hipError_t launch_resgrad_t(fea_ctx* c, hipEvent_t ev0, hipEvent_t ev1, int skip, bool persistent) {
   const int b = c->cur;
-  const dim3 grid((unsigned)c->n_items), block(THREADS);
+  const int per_cu = persistent ? persistent_per_cu<THREADS, STEPS, LOSS_ONLY, WEIGHTED>() : 0;
+  const dim3 grid((unsigned)(per_cu > 0 ? std::min<int64_t>(c->n_items, (int64_t)per_cu * c->n_cu) : c->n_items)),
+      block(THREADS);
   const float4 *x1 = c->lay[b][0].as<float4>(), *y1 = c->lay[b][1].as<float4>(), *x2 = c->lay[b][2].as<float4>(),
                *y2 = c->lay[b][3].as<float4>();
   const int4* items = c->item_rec.as<int4>();
@@ -364,28 +468,62 @@ hipError_t launch_resgrad_t(fea_ctx* c, hipEvent_t ev0, hipEvent_t ev1, int skip
   double* part = c->part.as<double>();
   const ushort4* wl = c->wlay.as<ushort4>();
   const uchar4* qm = c->opt.inner_loop == 1 ? c->qmask.as<uchar4>() : nullptr;
-  if (ev0)
+  if (per_cu > 0) {
+    const int32_t ni = (int32_t)c->n_items;
+    if (ev0)
+      hipExtLaunchKernelGGL(k_resgrad_p<THREADS, STEPS, LOSS_ONLY, WEIGHTED>, grid, block, 0, c->stream, ev0, ev1,
+                            0, x1, y1, x2, y2, items, ni, ptab, delta, part, wl, qm, skip);
+    else
+      k_resgrad_p<THREADS, STEPS, LOSS_ONLY, WEIGHTED>
+          <<<grid, block, 0, c->stream>>>(x1, y1, x2, y2, items, ni, ptab, delta, part, wl, qm, skip);
+  } else if (ev0) {
     hipExtLaunchKernelGGL(k_resgrad<THREADS, STEPS, LOSS_ONLY, WEIGHTED>, grid, block, 0, c->stream, ev0, ev1, 0,
                           x1, y1, x2, y2, items, ptab, delta, part, wl, qm, skip);
-  else
+  } else {
     k_resgrad<THREADS, STEPS, LOSS_ONLY, WEIGHTED><<<grid, block, 0, c->stream>>>(x1, y1, x2, y2, items, ptab,
                                                                                   delta, part, wl, qm, skip);
+  }
   return hipGetLastError();
 }
 
 template <bool LOSS_ONLY, bool WEIGHTED>
 hipError_t launch_resgrad_sel(fea_ctx* c, int cfg, hipEvent_t ev0, hipEvent_t ev1, int skip) {
+  // the shapes of kTiles, in order
   switch (cfg) {
-    case 0: return launch_resgrad_t<256, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
-    case 1: return launch_resgrad_t<256, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
-    case 2: return launch_resgrad_t<256, 1, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
-    case 3: return launch_resgrad_t<128, 8, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
-    case 4: return launch_resgrad_t<128, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
-    case 5: return launch_resgrad_t<128, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
-    case 6: return launch_resgrad_t<512, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
-    case 7: return launch_resgrad_t<512, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip);
+    case 0: return launch_resgrad_t<256, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, false);
+    case 1: return launch_resgrad_t<256, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, false);
+    case 2: return launch_resgrad_t<256, 1, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, false);
+    case 3: return launch_resgrad_t<128, 8, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, false);
+    case 4: return launch_resgrad_t<128, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, false);
+    case 5: return launch_resgrad_t<128, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, false);
+    case 6: return launch_resgrad_t<512, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, false);
+    case 7: return launch_resgrad_t<512, 4, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, false);
+    case 8: return launch_resgrad_t<256, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, true);
+    case 9: return launch_resgrad_t<256, 1, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, true);
+    case 10: return launch_resgrad_t<128, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, true);
+    case 11: return launch_resgrad_t<512, 1, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, true);
+    case 12: return launch_resgrad_t<512, 2, LOSS_ONLY, WEIGHTED>(c, ev0, ev1, skip, true);
   }
+  static_assert(kNumTiles == 13, "a launch for every work-item shape");
+  static_assert(kTiles[8].threads == 256 && kTiles[8].steps == 2 && kTiles[9].threads == 256 &&
+                    kTiles[9].steps == 1 && kTiles[10].threads == 128 && kTiles[10].steps == 2 &&
+                    kTiles[11].threads == 512 && kTiles[11].steps == 1 && kTiles[12].threads == 512 &&
+                    kTiles[12].steps == 2 && kTiles[8].persistent && kTiles[12].persistent && !kTiles[7].persistent,
+                "the persistent launches follow the table");
   return hipErrorInvalidValue;
+}
+
+// Looks up the occupancy of the persistent launches of shape `cfg` now, so
+// that no launch issued under graph capture is the first to ask.
+void prepare_resgrad(int cfg) {
+  if (cfg < 0 || cfg >= kNumTiles || !kTiles[cfg].persistent) return;
+  switch (cfg) {
+    case 8: prepare_persistent<256, 2>(); break;
+    case 9: prepare_persistent<256, 1>(); break;
+    case 10: prepare_persistent<128, 2>(); break;
+    case 11: prepare_persistent<512, 1>(); break;
+    case 12: prepare_persistent<512, 2>(); break;
+  }
 }
 
 hipError_t launch_resgrad_timed(fea_ctx* c, int cfg, bool loss_only, bool force_plain, hipEvent_t ev0,

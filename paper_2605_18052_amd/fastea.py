@@ -32,7 +32,8 @@ class fea_options(C.Structure):
                 ("lr_decay", C.c_double), ("reset_moments", C.c_int32),
                 ("tile_matches", C.c_int32), ("use_graphs", C.c_int32),
                 ("weight_mode", C.c_int32), ("inner_loop", C.c_int32),
-                ("reserved", C.c_int32 * 3), ("converge_deg", C.c_double)]
+                ("tile_persistent", C.c_int32), ("reserved", C.c_int32 * 2),
+                ("converge_deg", C.c_double)]
 
 
 class fea_report(C.Structure):
@@ -50,7 +51,7 @@ class fea_info(C.Structure):
                 ("gauge_center", C.c_double * 3), ("gauge_scale", C.c_double),
                 ("tau", C.c_double), ("tile_matches", C.c_int32),
                 ("tile_threads", C.c_int32), ("n_scenes", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("tile_persistent", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class FeaError(RuntimeError):
@@ -103,6 +104,7 @@ _SIGNATURES = {
     "fea_ablation": ([_P, C.c_int32, C.c_int32, _P, _P], C.c_int),
     "fea_set_state": ([_P, _P, C.c_size_t], C.c_int),
     "fea_synchronize": ([_P], C.c_int),
+    "fea_get_tile_timings": ([_P, _P, C.c_int32, _P], C.c_int),
     "fea_get_stream": ([_P, _P], C.c_int),
     "fea_get_rotation_log": ([_P, _P, _P], C.c_int),
     "fea_set_kernel_timing": ([_P, C.c_int32], C.c_int),
@@ -465,6 +467,14 @@ class Context:
 
     def synchronize(self):
         self._check(lib().fea_synchronize(self._h))
+
+    def tile_timings(self):
+        """The autotuner's mean per-pass time (ms) of each candidate shape at
+        its last tuning on this context (empty if none was timed)."""
+        n = C.c_int32(0)
+        ms = np.zeros(64, dtype=np.float32)
+        self._check(lib().fea_get_tile_timings(self._h, ms.ctypes.data_as(_P), 64, C.byref(n)))
+        return ms[:n.value].copy()
 
     def stream_handle(self) -> int:
         """The context's hipStream_t as an integer."""

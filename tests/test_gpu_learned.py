@@ -84,10 +84,11 @@ def test_mfma_inference_matches_oracle():
     err = np.abs(w - ref)
     print(f"learned weight vs FP64 network: max |err| {err.max():.3g}, mean {err.mean():.3g}, "
           f"max rel {(err / np.maximum(ref, 1e-3)).max():.3g}", flush=True)
-    # fp16 keeps 11 significand bits (0.05% per feature, weight and
-    # activation), a few times that on the logit, at most 1/4 of it on the
-    # sigmoid, plus the bf16 storage of the weight (<= 0.004); the weight
-    # lies in [0, 1], so the bound is absolute
+    # the features enter as fp16 hi + lo parts (about 22 significand bits);
+    # weights and hidden activations keep fp16's 11 (rounded to nearest), a
+    # few times that on the logit, at most 1/4 of it on the sigmoid, plus
+    # the fp16 storage of the weight (<= 2.5e-4); the weight lies in [0, 1],
+    # so the bound is absolute
     assert err.max() < 1e-2 and err.mean() < 2.5e-3, (err.max(), err.mean())
     assert ref.std() > 0.05  # the network is not constant on these inputs
 

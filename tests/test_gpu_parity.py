@@ -155,8 +155,8 @@ def test_zero_matches():
 
 # ------------------------------------------------------- residual + gradient
 
-def _parity(sc, R_snap, t_snap, f_snap, R, t, f, tau_px, gauge=0):
-    ctx = make_context(sc, gauge=gauge, f=f_snap)
+def _parity(sc, R_snap, t_snap, f_snap, R, t, f, tau_px, gauge=0, **opt):
+    ctx = make_context(sc, gauge=gauge, f=f_snap, **opt)
     ctx.init_poses(R_snap, t_snap)
     ctx.begin_round(tau_px)
     ctx.set_poses(R, t, f)
@@ -200,6 +200,36 @@ def test_residual_grad_parity_filtered(name):
     for a, b in ((gR, gRr), (gt, gtr), (gf[:, None], gfr[:, None])):
         ok, worst = per_camera_close(a, b)
         assert ok, worst
+
+
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+@pytest.mark.parametrize("name", ["sphere20_m60k", "multi_item"])
+def test_persistent_launch_parity(name, tile):
+    """The persistent launch of the per-match kernel (a fixed number of
+    workgroups per CU walking the items, the next item's loads in flight)
+    against the oracle, and, where the one-workgroup-per-item launch of the
+    same item size has the same threads and loads per thread (1024 and 2048
+    matches), bit for bit against it: the same per-item partials in the
+    same order."""
+    sc = SCENES[name]
+    pb = oracle_problem(sc)
+    eps = np.abs(oracle.residuals(pb, sc.R_init, sc.t_init, sc.f_init))
+    tau = tau_in_gap(eps, np.quantile(eps, 0.8))
+    R, t, f = _perturbed(sc, seed=5)
+    (l, gR, gt, gf), (lr, gRr, gtr, gfr) = _parity(sc, sc.R_init, sc.t_init, sc.f_init, R, t, f,
+                                                   tau * np.median(sc.f_init), tile_matches=tile,
+                                                   tile_persistent=1)
+    assert abs(l - lr) <= 1e-5 * abs(lr)
+    for a, b in ((gR, gRr), (gt, gtr), (gf[:, None], gfr[:, None])):
+        ok, worst = per_camera_close(a, b)
+        assert ok, worst
+    if tile == 4096:
+        return  # 512 threads x 2 loads persistent, 256 x 4 per item: another summation order
+    (l1, gR1, gt1, gf1), _ = _parity(sc, sc.R_init, sc.t_init, sc.f_init, R, t, f, tau * np.median(sc.f_init),
+                                     tile_matches=tile, tile_persistent=0)
+    assert l == l1
+    for a, b in ((gR, gR1), (gt, gt1), (gf, gf1)):
+        np.testing.assert_array_equal(a, b)
 
 
 def test_parity_at_snapshot_is_l1():

@@ -106,9 +106,9 @@ def _soft_inlier_mlp():
 def test_learned_weights_gradient_vs_oracle():
     """Learned weights in both inner loops against the oracle's weighted loss
     with the weights of its own FP64 network on its own features.  The GPU's
-    network runs with bf16 activations (weights agree to ~1e-2), so the bound
-    against the oracle is 2e-2; the two GPU inner loops use the same weights
-    and agree to 1e-5."""
+    network runs on fp16 operands (its weights agree to 1e-2 absolute), so
+    the bound against the oracle is 1e-2, the reduced-precision mode's; the
+    two GPU inner loops use the same weights and agree to 1e-5."""
     sc = SCENES["sphere20_m60k"]
     p = _soft_inlier_mlp()
     R, t, f = _perturbed(sc, seed=5)
@@ -123,7 +123,7 @@ def test_learned_weights_gradient_vs_oracle():
                            p.astype(np.float32).astype(np.float64))
     assert w.std() > 0.05
     ref = oracle.loss_grad(pb, R, t, f, *snap, delta=fastea.default_options().delta, weights=w)
-    _close(quad, ref, 2e-2)
+    _close(quad, ref, 1e-2)
     # and the weights matter: the unweighted gradient is further away
     unw = oracle.loss_grad(pb, R, t, f, *snap, delta=fastea.default_options().delta)
     err = lambda g: np.linalg.norm(g - ref[2]) / np.linalg.norm(ref[2])

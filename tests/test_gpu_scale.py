@@ -34,15 +34,16 @@ def bench_scene():
     return sc, pb, (R, t, f), tau, mask, Z, eps
 
 
-@pytest.mark.parametrize("tile", [0, 1024, 2048, 4096, 8192])
-def test_bench_workload_gradient_vs_oracle(bench_scene, tile):
+@pytest.mark.parametrize("tile,persistent", [(0, 0), (1024, 0), (2048, 0), (4096, 0), (8192, 0), (1024, 1),
+                                             (2048, 1), (4096, 1)])
+def test_bench_workload_gradient_vs_oracle(bench_scene, tile, persistent):
     sc, pb, (R, t, f), tau, mask_ref, Z_ref, eps = bench_scene
     opt = fastea.default_options()
-    ctx = make_context(sc, gauge=0, tile_matches=tile)
+    ctx = make_context(sc, gauge=0, tile_matches=tile, tile_persistent=persistent)
     ctx.init_poses(sc.R_init, sc.t_init)
     ctx.begin_round(opt.tau_px_init)
     info = ctx.info()
-    assert tile == 0 or info["tile_matches"] == tile
+    assert tile == 0 or (info["tile_matches"] == tile and info["tile_persistent"] == persistent)
     ctx.set_poses(R, t, f)
     loss, gR, gt, gf = ctx.residual_grad()
     mask, Z = ctx.get_mask()
@@ -100,11 +101,14 @@ def test_bench_workload_quadratic_form_vs_oracle(bench_scene):
 def test_bench_workload_learned_weights_vs_oracle(bench_scene):
     """The shipped inlier network on the 20M-match scene after three round
     snapshots: the weights of 100,000 sampled matches against the FP64
-    network on the oracle's features.  The bound follows from the
-    arithmetic: fp16 operands (relative rounding 2^-11) in 64-term dot
-    products whose terms reach ~15 for this network put up to ~0.06 on the
-    logit, at most a quarter of it on the sigmoid (0.015), plus the bf16
-    storage of the weight (up to 0.004): 2e-2 absolute."""
+    network on the oracle's features, to 1e-2 absolute (the bound for the
+    reduced-precision mode).  The arithmetic: the features enter as fp16
+    hi + lo parts (about 2^-22 relative), the weights and the two hidden
+    layers' activations are fp16 rounded to nearest (2^-12 relative) in
+    64-term dot products; on this network that puts at most ~0.02 on the
+    logit and a quarter of it on the weight (an fp64 emulation of exactly
+    these roundings gives 4.9e-3 at most over 200,000 feature vectors), and
+    the fp16 storage of the weight adds at most 2.5e-4."""
     from paper_2605_18052_amd import learned
     sc = bench_scene[0]
     params = learned.load_weights()
@@ -128,7 +132,7 @@ def test_bench_workload_learned_weights_vs_oracle(bench_scene):
     ref = oracle.mlp_forward(feat, params.astype(np.float32).astype(np.float64))
     err = np.abs(w[sel] - ref)
     print(f"learned weights at full size: max |err| {err.max():.3g}, mean {err.mean():.3g}", flush=True)
-    assert err.max() < 2e-2 and err.mean() < 2.5e-3, (err.max(), err.mean())
+    assert err.max() < 1e-2 and err.mean() < 1e-3, (err.max(), err.mean())
     assert ref.std() > 0.05
 
 
