@@ -59,23 +59,18 @@ BATCH_CONVERGE_DEG = 0.01
 # HBM bytes per launch of the per-match kernel at round 0 of each workload,
 # from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch
 # scaled by what the same counters read for a 1 GiB plain copy: x2.0, x1.0),
-# summarised in profiles/k_resgrad_<workload>_hbm_traffic.md.  They hold
+# summarised in profiles/k_resgrad_traj3000_m100M_hbm_traffic.md.  They hold
 # only for the kernel source they were taken on (hashed below) and are keyed
 # by the retained-match count and the work-item shape, which the autotuner
 # may pick differently per run.
 KERNEL_SOURCES = ("paper_2605_18052_amd/csrc/fea_resgrad.hip", "paper_2605_18052_amd/csrc/fea_device.h",
                   "paper_2605_18052_amd/csrc/fea_ctx.h")
 PMC_TRAFFIC = {
-    "sources_sha256": "10fc816065221f5ecbd974c1d762a90e59f0451a201e2a6698cfa67a5887e534",
+    "sources_sha256": "e4c30ec566c9117e4b51dff9a23671744848736c9e5769e0650b9c7d7560e01e",
     # retained matches per launch -> "matches x threads" -> fetched + written bytes
     "bytes_per_launch": {
-        17819274: {  # traj500_m20M, round 0
-            "1024x128": 301053751, "1024x256": 301038583, "2048x128": 294116285, "2048x256": 294079165,
-            "4096x128": 290428227, "4096x256": 290351749, "4096x512": 290307142, "8192x512": 290315846,
-        },
         87275962: {  # traj3000_m100M, round 0
-            "1024x128": 1484902433, "1024x256": 1484885986, "2048x128": 1448137547, "2048x256": 1448101196,
-            "4096x128": 1446745448, "4096x256": 1446671466, "4096x512": 1446626411, "8192x512": 1446683369,
+            "2048x256": 1448071858, "1024x256": 1484856328,
         },
     },
 }
@@ -133,6 +128,10 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--ablation", action="store_true",
                     help="also time the per-match pass with each design choice taken back")
+    ap.add_argument("--tile-matches", type=int, default=0,
+                    help="matches per work item of the per-match kernel (0: the autotuner picks)")
+    ap.add_argument("--tile-persistent", type=int, default=0,
+                    help="with --tile-matches: 1 for the persistent launch of that item size")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -466,7 +465,7 @@ def main():
     log(f"[bench] scene {sc.name}: {sc.n_cams} cams, {sc.n_matches} matches, "
         f"{len(sc.pairs())} pairs ({time.perf_counter() - t0:.1f} s)")
 
-    opt = fastea.default_options()
+    opt = fastea.default_options(tile_matches=args.tile_matches, tile_persistent=args.tile_persistent)
     ctx = fastea.Context(0, opt)
     ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
     t1 = time.perf_counter()
