@@ -120,7 +120,7 @@ def parse():
                     help="skip the relative-translation search and camera-centre alignment")
     ap.add_argument("--candidates", type=int, default=2048,
                     help="candidate directions of the relative-translation search")
-    ap.add_argument("--search-cap-px", type=float, default=32.0,
+    ap.add_argument("--search-cap-px", type=float, default=8.0,
                     help="cap of each match's error in the search, pixels (inf: the plain mean)")
     ap.add_argument("--search-cpu-pairs", type=int, default=400,
                     help="pairs of the scene the CPU oracle searches for its baseline")
@@ -285,7 +285,7 @@ def batched_vs_sequential(scenes, fastea, metrics, synth, sequential=True, **opt
             "options": ({**options, "weight_mode": "learned"} if mlp is not None else options) or "defaults"}
 
 
-def translation_stages(sc, fastea, synth, n_cand, with_cpu, cap_px=32.0, cpu_pairs=400, reps=5):
+def translation_stages(sc, fastea, synth, n_cand, with_cpu, cap_px=8.0, cpu_pairs=400, reps=5):
     from paper_2605_18052_amd import metrics
     """Relative-translation search over the scene's matches (the true
     rotations and focal lengths stand in for the outputs of global rotation
