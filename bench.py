@@ -398,8 +398,9 @@ def translation_stages(sc, fastea, synth, n_cand, with_cpu, cap_px=8.0, cpu_pair
                 "error_init_deg": metrics.mean_rotation_error_deg(ra["R_init"], sc.R_gt),
                 "error_deg": metrics.mean_rotation_error_deg(ra["R"], sc.R_gt),
                 "loss_init": ra["loss_init"], "loss": ra["loss"],
-                "bound": "latency: one launch per power iteration (a renormalisation every 8th, run until "
-                         "the Rayleigh quotient settles) and one per Adam step, O(pairs) fp64 each"}
+                "bound": "latency: six launches per Lanczos step (operator, two projection and two "
+                         "subtraction passes, normalisation; host check every 16 steps) and one per Adam step, "
+                         "O(pairs) fp64 each"}
     out = {"relative_translations": search, "alignment": align, "focal_vote": focal, "rotation": rotation}
     if with_cpu:
         import oracle

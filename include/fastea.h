@@ -549,10 +549,12 @@ fea_status fea_get_rotation_log(fea_ctx *ctx, double *R_log, int32_t *n_logged);
  * argument is strictly inside (-1, 1), zero elsewhere).  Initialisation
  * (after Martinec and Pajdla, as the paper modifies it): the first columns
  * minimise sum |c_j - R^{i->j} c_i|^2 over unit-norm stacked vectors, the
- * second columns the same over |P| plus sum (c1_i . c2_i)^2 / |I|, each by
- * power iterations from the caller's random start vectors v0 (run 256 at a
- * time until the Rayleigh quotient changes by less than 3e-5 of itself, at
- * most init_iters rounded up to 256)
+ * second columns the same over |P| plus sum (c1_i . c2_i)^2 / |I|, each the
+ * Ritz vector of the smallest eigenvalue of the problem's 3N x 3N normal
+ * matrix by the Lanczos method with full reorthogonalisation from the
+ * caller's random start vectors v0 (until the smallest Ritz value changes
+ * by less than 3e-5 of itself over 16 steps; restarted from the Ritz vector
+ * every 256 steps; at most init_iters products with the matrix)
  * [2 * n_cams * 3] (any vector in the near-null space of the first problem
  * is a valid first column: the rotations are fixed up to one global
  * rotation), normalised per camera, the second made orthogonal to the
@@ -566,9 +568,9 @@ fea_status fea_get_rotation_log(fea_ctx *ctx, double *R_log, int32_t *n_logged);
  * call, HIP events).  FEA_EINVAL for invalid sizes, pairs or options;
  * FEA_ENONFINITE for non-finite input; FEA_EDEGENERATE if a camera's column
  * vanishes in the initialisation (a camera without pairs).  Device scratch of
- * O(n_cams + n_pairs) is allocated and freed by the call. */
+ * O(n_pairs + 257 * 3 n_cams) doubles is allocated and freed by the call. */
 typedef struct {
-  int32_t init_iters; /* at most this many power iterations per column (default 200000) */
+  int32_t init_iters; /* at most this many Lanczos steps per column (default 200000) */
   int32_t iters;      /* Adam steps (1000) */
   double lr;          /* first learning rate (1e-2) */
   double lr_end_frac; /* last over first learning rate (1e-2) */

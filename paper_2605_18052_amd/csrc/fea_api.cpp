@@ -2834,6 +2834,164 @@ hipError_t run_captured(hipStream_t st, int iters, int& parity, Step step) {
 
 extern "C" {
 
+namespace {
+
+// Lanczos scratch (device arrays): basis V [(kmax+1) x n], the step's vector
+// w [n], the apply kernel's per-camera side output sq [n], both passes'
+// projections h1, h2, the tridiagonal alpha, beta, the Ritz coefficients s
+// [kmax+1] and the norm partials.
+struct LzScratch {
+  int64_t n = 0;
+  int kmax = 0;
+  double *V = nullptr, *w = nullptr, *sq = nullptr, *h1 = nullptr, *h2 = nullptr, *alpha = nullptr,
+         *beta = nullptr, *s = nullptr, *part = nullptr;
+};
+
+// A = wm M + wp diag(c1 c1^T) over the pair graph (device arrays).
+struct LzOperator {
+  int n_cams;
+  const int32_t *cam_off, *cam_ent, *pair_i, *pair_j;
+  const double* Rrel;
+  const double* c1;
+  double wm, wp;
+};
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal a[0..m) and off-diagonal b[0..m-1) (the signs of the pivots of
+// its LDL^T factorisation, Sylvester's law of inertia).
+int sturm_below(const std::vector<double>& a, const std::vector<double>& b, int m, double x) {
+  int count = 0;
+  double q = 1.0;
+  for (int i = 0; i < m; ++i) {
+    q = (a[i] - x) - (i > 0 ? b[i - 1] * b[i - 1] / q : 0.0);
+    if (q == 0.0) q = -1e-300;  // a zero pivot: x is an eigenvalue; count it below
+    if (q < 0.0) ++count;
+  }
+  return count;
+}
+
+// The smallest eigenvalue of that matrix by bisection between Gershgorin
+// bounds, to the last bits.
+double tridiag_smallest(const std::vector<double>& a, const std::vector<double>& b, int m) {
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_below(a, b, m, mid) >= 1)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// A unit eigenvector of that matrix for eigenvalue theta: two steps of
+// inverse iteration, (T - theta I) x_new = x, by Gaussian elimination with
+// partial pivoting on the dense m x m matrix (m <= a few hundred).
+std::vector<double> tridiag_eigvec(const std::vector<double>& a, const std::vector<double>& b, int m, double theta) {
+  std::vector<double> x(m, 1.0 / std::sqrt((double)m));
+  const double scale = std::max(1e-300, std::fabs(theta) + std::fabs(a[0]));
+  for (int rep = 0; rep < 2; ++rep) {
+    std::vector<double> M((size_t)m * m, 0.0), r(x);
+    for (int i = 0; i < m; ++i) {
+      M[(size_t)i * m + i] = a[i] - theta;
+      if (i + 1 < m) M[(size_t)i * m + i + 1] = M[(size_t)(i + 1) * m + i] = b[i];
+    }
+    for (int col = 0; col < m; ++col) {
+      int piv = col;
+      for (int i = col + 1; i < m; ++i)
+        if (std::fabs(M[(size_t)i * m + col]) > std::fabs(M[(size_t)piv * m + col])) piv = i;
+      if (piv != col) {
+        for (int k = 0; k < m; ++k) std::swap(M[(size_t)col * m + k], M[(size_t)piv * m + k]);
+        std::swap(r[col], r[piv]);
+      }
+      double d = M[(size_t)col * m + col];
+      if (std::fabs(d) < 1e-15 * scale) d = M[(size_t)col * m + col] = (d < 0 ? -1e-15 : 1e-15) * scale;
+      for (int i = col + 1; i < m; ++i) {
+        const double l = M[(size_t)i * m + col] / d;
+        if (l == 0.0) continue;
+        for (int k = col; k < m; ++k) M[(size_t)i * m + k] -= l * M[(size_t)col * m + k];
+        r[i] -= l * r[col];
+      }
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      double t = r[i];
+      for (int k = i + 1; k < m; ++k) t -= M[(size_t)i * m + k] * x[k];
+      x[i] = t / M[(size_t)i * m + i];
+    }
+    double nrm = 0.0;
+    for (double v : x) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return std::vector<double>(m, 0.0);
+    for (double& v : x) v /= nrm;
+  }
+  return x;
+}
+
+// The Ritz vector of A's smallest eigenvalue into y (device [n]): Lanczos
+// from the start vector v0 (host [n]), at most kmax steps between restarts
+// (a restart starts again from the current Ritz vector), until the smallest
+// Ritz value changes by at most 3e-5 of itself (or 1e-12 sigma) over 16
+// steps, the Krylov space is exhausted, or max_apply products with A have
+// run.  Inside the near-null cluster (split by noise) any vector is a valid
+// column, so the test only has to see the bottom of the spectrum arrive.
+hipError_t lanczos_bottom(hipStream_t st, const LzOperator& A, double sigma, const double* v0, int max_apply,
+                          LzScratch& z, double* y) {
+  const int64_t n = z.n;
+  std::vector<double> v(v0, v0 + n);
+  double nrm = 0.0;
+  for (double t : v) nrm += t * t;
+  nrm = std::sqrt(nrm);
+  if (!(nrm > 0.0)) return hipErrorInvalidValue;
+  for (double& t : v) t /= nrm;
+  hipError_t e = hipMemcpyAsync(z.V, v.data(), n * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  int applied = 0;
+  double theta_prev = std::numeric_limits<double>::quiet_NaN();
+  std::vector<double> a, b;
+  for (;;) {
+    int m = 0;
+    bool done = false;
+    double theta = 0.0;
+    for (int j = 0; j < z.kmax; ++j) {
+      e = fea::launch_lz_step(st, A.n_cams, A.cam_off, A.cam_ent, A.pair_i, A.pair_j, A.Rrel, A.c1, A.wm, A.wp, z.V,
+                              j, z.w, z.sq, z.h1, z.h2, z.part, z.alpha, z.beta);
+      if (e != hipSuccess) return e;
+      ++applied;
+      m = j + 1;
+      if (m % 16 != 0 && m != z.kmax && applied < max_apply) continue;
+      a.assign(m, 0.0);
+      b.assign(m, 0.0);
+      if ((e = hipMemcpyAsync(a.data(), z.alpha, m * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+          (e = hipMemcpyAsync(b.data(), z.beta, m * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+          (e = hipStreamSynchronize(st)) != hipSuccess)
+        return e;
+      theta = tridiag_smallest(a, b, m);
+      const bool exhausted = !(b[m - 1] > 1e-14 * sigma);
+      const bool settled = std::fabs(theta - theta_prev) <= 3e-5 * std::fabs(theta) + 1e-12 * sigma;
+      theta_prev = theta;
+      if (exhausted || settled || applied >= max_apply) {
+        done = true;
+        break;
+      }
+    }
+    // the Ritz vector of the basis built so far
+    const std::vector<double> sv = tridiag_eigvec(a, b, m, theta);
+    if ((e = hipMemcpyAsync(z.s, sv.data(), m * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    if ((e = fea::launch_lz_combine(st, n, m, z.V, z.s, done ? y : z.w)) != hipSuccess) return e;
+    if (done) return hipStreamSynchronize(st);
+    // restart from it (a unit vector: the basis is orthonormal)
+    if ((e = hipMemcpyAsync(z.V, z.w, n * sizeof(double), hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+  }
+}
+
+}  // namespace
+
 fea_status fea_rotation_averaging(fea_ctx* c, int32_t n_cams, int64_t n_pairs, const int32_t* pair_i,
                                   const int32_t* pair_j, const double* R_rel, const double* v0,
                                   const double* a6_init, const fea_ra_options* opt, double* R_out, double* R_init,
@@ -2865,19 +3023,15 @@ fea_status fea_rotation_averaging(fea_ctx* c, int32_t n_cams, int64_t n_pairs, c
   DeviceGuard g(c->device);
   CallScratch sc(c->stream);
   int32_t *dpi, *dpj, *doff, *dent, *derr;
-  double *dR, *cbuf[2], *c1, *sq, *scale, *rho, *a6[2], *m, *v, *dloss;
+  double *dR, *col, *c1, *a6[2], *m, *v, *dloss;
   fea::TaCounters* ctr;
   HIP_OR_FAIL(c, sc.put(dpi, pair_i, (size_t)n_pairs));
   HIP_OR_FAIL(c, sc.put(dpj, pair_j, (size_t)n_pairs));
   HIP_OR_FAIL(c, sc.put(doff, off.data(), off.size()));
   HIP_OR_FAIL(c, sc.put(dent, ent.data(), ent.size()));
   HIP_OR_FAIL(c, sc.put(dR, R_rel, (size_t)9 * n_pairs));
-  HIP_OR_FAIL(c, sc.alloc(cbuf[0], N6));  // both start vectors, then ping-pong
-  HIP_OR_FAIL(c, sc.alloc(cbuf[1], N3));
+  HIP_OR_FAIL(c, sc.alloc(col, N3));  // the column being solved for
   HIP_OR_FAIL(c, sc.alloc(c1, N3));
-  HIP_OR_FAIL(c, sc.alloc(sq, (size_t)3 * n_cams));
-  HIP_OR_FAIL(c, sc.alloc(scale, 1));
-  HIP_OR_FAIL(c, sc.alloc(rho, 1));
   HIP_OR_FAIL(c, sc.alloc(a6[0], N6));
   HIP_OR_FAIL(c, sc.alloc(a6[1], N6));
   HIP_OR_FAIL(c, sc.alloc(m, N6));
@@ -2899,65 +3053,28 @@ fea_status fea_rotation_averaging(fea_ctx* c, int32_t n_cams, int64_t n_pairs, c
     if (e == hipSuccess)
       e = hipMemcpyAsync(a6[0], a6_init, N6 * sizeof(double), hipMemcpyHostToDevice, c->stream);
   } else {
-    // both start vectors into cbuf[0]: column 1 iterates between its first
-    // half and cbuf[1], column 2 between its second half and cbuf[1]
-    if (e == hipSuccess) e = hipMemcpyAsync(cbuf[0], v0, N6 * sizeof(double), hipMemcpyHostToDevice, c->stream);
-    // column 1: smallest eigenvector of M; column 2: of M/|P| + B/|I|.  sigma
-    // just above half the Gershgorin bound (2 max_deg; 2 max_deg/|P| + 1/|I|)
-    const double sig1 = 1.01 * max_deg, sig2 = 1.01 * (max_deg / (double)n_pairs + 0.5 / n_cams);
-    for (int col = 0; col < 2 && e == hipSuccess; ++col) {
-      double* buf[2] = {col == 0 ? cbuf[0] : cbuf[0] + N3, cbuf[1]};
-      // the start vector's own scale first
-      std::vector<double> ones(1, 1.0);
-      e = hipMemcpyAsync(scale, ones.data(), sizeof(double), hipMemcpyHostToDevice, c->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-      int par = 0, it = 0;
-      const double sig = col == 0 ? sig1 : sig2;
-      // renormalised every 8th step: growth between two is at most sigma^8,
-      // far inside the fp64 range; the renormalisation also gives the
-      // Rayleigh quotient of the step's input
-      auto step = [&]() {
-        ++it;
-        const bool renorm = (it % 8) == 0;
-        const bool rescale = (it % 8) == 1;  // the step after a renormalisation (or the first)
-        hipError_t r = fea::launch_ra_apply(c->stream, n_cams, doff, dent, dpi, dpj, dR, buf[par],
-                                            rescale ? scale : nullptr, col == 0 ? nullptr : c1, sig,
-                                            col == 0 ? 1.0 : 1.0 / n_pairs, 1.0 / n_cams, buf[par ^ 1], sq, scale,
-                                            renorm, rho);
-        par ^= 1;
-        return r;
-      };
-      // 64 steps captured once (an even count: the buffer roles return), run
-      // 256 at a time until the Rayleigh quotient settles (its change over
-      // 256 steps below 3e-5 of itself, or 1e-12 sigma near zero) or
-      // init_iters steps have run.  Inside the near-null cluster (split by
-      // noise) the iterate keeps drifting towards the single smallest
-      // eigenvector at a rate set by the tiny split; any vector of the
-      // cluster is a valid column, so the test only has to see it arrive.
-      hipGraph_t gph = nullptr;
-      hipGraphExec_t gx = nullptr;
-      if (e == hipSuccess) e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
-      if (e == hipSuccess) {
-        hipError_t le = hipSuccess;
-        for (int k = 0; k < 64 && le == hipSuccess; ++k) le = step();
-        e = hipStreamEndCapture(c->stream, &gph);
-        if (le != hipSuccess) e = le;
-      }
-      par = 0;
-      if (e == hipSuccess) e = hipGraphInstantiate(&gx, gph, nullptr, nullptr, 0);
-      if (gph) (void)hipGraphDestroy(gph);
-      double rho_prev = 0.0;
-      for (int done = 0; e == hipSuccess && done < o.init_iters; done += 256) {
-        for (int r = 0; r < 4 && e == hipSuccess; ++r) e = hipGraphLaunch(gx, c->stream);
-        double rh = 0.0;
-        if (e == hipSuccess) e = hipMemcpyAsync(&rh, rho, sizeof(double), hipMemcpyDeviceToHost, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (e == hipSuccess && done > 0 && std::fabs(rh - rho_prev) <= 3e-5 * std::fabs(rh) + 1e-12 * sig) break;
-        rho_prev = rh;
-      }
-      if (gx) (void)hipGraphExecDestroy(gx);
+    // column 1: smallest eigenvector of M; column 2: of M/|P| + B/|I|, each
+    // by Lanczos from its start vector; the spectrum's scale (the Gershgorin
+    // bound) sets the stopping test's absolute term
+    const double sig1 = 2.0 * max_deg, sig2 = 2.0 * (max_deg / (double)n_pairs + 0.5 / n_cams);
+    LzScratch z;
+    z.n = (int64_t)N3;
+    z.kmax = (int)std::min<int64_t>({256, z.n, std::max<int64_t>(o.init_iters, 1)});
+    if (e == hipSuccess) e = sc.alloc(z.V, (size_t)(z.kmax + 1) * N3);
+    if (e == hipSuccess) e = sc.alloc(z.w, N3);
+    if (e == hipSuccess) e = sc.alloc(z.sq, N3);
+    if (e == hipSuccess) e = sc.alloc(z.h1, (size_t)z.kmax + 1);
+    if (e == hipSuccess) e = sc.alloc(z.h2, (size_t)z.kmax + 1);
+    if (e == hipSuccess) e = sc.alloc(z.alpha, (size_t)z.kmax + 1);
+    if (e == hipSuccess) e = sc.alloc(z.beta, (size_t)z.kmax + 1);
+    if (e == hipSuccess) e = sc.alloc(z.s, (size_t)z.kmax + 1);
+    if (e == hipSuccess) e = sc.alloc(z.part, (size_t)fea::lz_orth_blocks(z.n));
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+      const LzOperator A{n_cams, doff, dent, dpi, dpj, dR, k == 0 ? nullptr : c1, k == 0 ? 1.0 : 1.0 / n_pairs,
+                         1.0 / n_cams};
+      e = lanczos_bottom(c->stream, A, k == 0 ? sig1 : sig2, v0 + (size_t)k * N3, o.init_iters, z, col);
       if (e == hipSuccess)
-        e = fea::launch_ra_columns(c->stream, n_cams, buf[par], col == 0 ? nullptr : c1, col == 0 ? c1 : a6[0], derr);
+        e = fea::launch_ra_columns(c->stream, n_cams, col, k == 0 ? nullptr : c1, k == 0 ? c1 : a6[0], derr);
     }
   }
   if (e == hipSuccess) e = fea::launch_ra_loss(c->stream, n_pairs, dpi, dpj, dR, a6[0], dloss);

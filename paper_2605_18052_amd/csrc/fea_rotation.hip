@@ -4,13 +4,18 @@
 // first columns c1 minimise sum |c1_j - R^{i->j} c1_i|^2 over unit-norm
 // stacked vectors, i.e. the smallest eigenvector of the 3N x 3N normal matrix
 // M; the second columns do the same for M/|P| + B/|I| (B the orthogonality
-// penalty diag(c1_i c1_i^T)).  Both by power iteration on sigma I - A with
-// sigma just above half of A's Gershgorin bound (so the smallest eigenvalues
-// of A dominate): one wave per camera applies A over the camera's pairs
-// (no atomics); one workgroup renormalises every 8th step.  Without noise the smallest
-// eigenvalue of M has the three columns of the true rotations (times any
-// fixed vector) as eigenvectors, a three-dimensional space; any vector in it
-// is a valid first column.
+// penalty diag(c1_i c1_i^T)).  Both by the Lanczos method with full
+// reorthogonalisation (classical Gram-Schmidt, twice) from the caller's
+// start vector, in fp64: one wave per camera applies A over the camera's
+// pairs (no atomics), one workgroup per basis vector forms the projections,
+// one thread per coordinate subtracts them; the host takes the smallest
+// eigenvalue of the small tridiagonal matrix (bisection on Sturm counts)
+// every 16 steps, stops once it settles, and the Ritz vector is formed on
+// the device.  The Krylov space converges to the bottom of the spectrum in
+// about the square root of the steps power iteration needs.  Without noise
+// the smallest eigenvalue of M has the three columns of the true rotations
+// (times any fixed vector) as eigenvectors, a three-dimensional space; any
+// vector in it is a valid first column.
 //
 // Optimisation: Adam on the 6D parameters of the mean geodesic distance
 // d(R_j, R^{i->j} R_i) = arccos((tr(R_j^T R^{i->j} R_i) - 1)/2); one wave per
@@ -32,8 +37,8 @@ constexpr int kRaWaves = kRaThreads / 64;
 
 // y_w = s (sigma c_w - wm (M c)_w - wp c1_w (c1_w . c_w)) for camera w, with
 // (M c)_w = sum over its pairs of r (as camera j) or -R^T r (as camera i),
-// r = c_j - R^{i->j} c_i; s = the last renormalisation's 1/|c| on the step
-// right after it, 1 on the others (scale == nullptr).
+// r = c_j - R^{i->j} c_i; s = *scale (1 when scale is null); sq receives the
+// per-camera y.y, c.y and c.c.
 template <bool PEN>
 __global__ __launch_bounds__(kRaThreads) void k_ra_apply(int n_cams, const int32_t* __restrict__ cam_off,
                                                          const int32_t* __restrict__ cam_ent,
@@ -78,35 +83,6 @@ __global__ __launch_bounds__(kRaThreads) void k_ra_apply(int n_cams, const int32
   sq[w] = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
   sq[n_cams + w] = cw[0] * y[0] + cw[1] * y[1] + cw[2] * y[2];
   sq[2 * n_cams + w] = cw[0] * cw[0] + cw[1] * cw[1] + cw[2] * cw[2];
-}
-
-// scale = 1 / sqrt(sum of y.y) (fixed-order block sums; 0 marks a zero
-// vector) and the Rayleigh quotient of A at the step's input c:
-// c.Ac / c.c = sigma - (c.y) / (s c.c), y = s (sigma c - A c), s the step's
-// input scale; written to rho[0].
-__global__ __launch_bounds__(kRaThreads) void k_ra_norm(int n, const double* __restrict__ sq, double sigma,
-                                                        double s_in, double* __restrict__ scale,
-                                                        double* __restrict__ rho) {
-  __shared__ double red[3][kRaThreads];
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int k = threadIdx.x; k < n; k += kRaThreads) {
-    a += sq[k];
-    b += sq[n + k];
-    c += sq[2 * n + k];
-  }
-  red[0][threadIdx.x] = a;
-  red[1][threadIdx.x] = b;
-  red[2][threadIdx.x] = c;
-  __syncthreads();
-  for (int o = kRaThreads / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o)
-      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    *scale = red[0][0] > 0.0 ? 1.0 / sqrt(red[0][0]) : 0.0;
-    if (rho) *rho = red[2][0] > 0.0 ? sigma - red[1][0] / (s_in * red[2][0]) : 0.0;
-  }
 }
 
 // Per camera: c1 = c/|c|; or, with c1 given, the second column: c minus its
@@ -228,22 +204,112 @@ __global__ void k_ra_to_R(int n_cams, const double* __restrict__ a6, double* __r
   if (w < n_cams) rot6d_forward(a6 + 6 * (int64_t)w, R + 9 * (int64_t)w);
 }
 
+// ---- Lanczos with full reorthogonalisation ---------------------------------
+// The basis V is row-major [m][n]: row i is the i-th Lanczos vector in the
+// camera-major layout (3 entries per camera).
+constexpr int kLzThreads = 256;
+constexpr int kLzOrthThreads = 64;  // small workgroups spread one pass over many CUs
+
+// h[i] = V_i . w, one workgroup per basis vector (fixed-order sums).
+__global__ __launch_bounds__(kLzThreads) void k_lz_dots(int64_t n, const double* __restrict__ V,
+                                                        const double* __restrict__ w, double* __restrict__ h) {
+  __shared__ double red[kLzThreads];
+  const double* v = V + (int64_t)blockIdx.x * n;
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += kLzThreads) s = fma(v[k], w[k], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kLzThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) h[blockIdx.x] = red[0];
+}
+
+// w -= sum over i < m of h[i] V_i, one thread per coordinate; part[block]
+// = the block's sum of w^2 after the subtraction.
+__global__ __launch_bounds__(kLzOrthThreads) void k_lz_orth(int64_t n, int m, const double* __restrict__ V,
+                                                            const double* __restrict__ h, double* __restrict__ w,
+                                                            double* __restrict__ part) {
+  __shared__ double red[kLzOrthThreads];
+  const int64_t k = (int64_t)blockIdx.x * kLzOrthThreads + threadIdx.x;
+  double x = 0.0;
+  if (k < n) {
+    x = w[k];
+    for (int i = 0; i < m; ++i) x = fma(-h[i], V[(int64_t)i * n + k], x);
+    w[k] = x;
+  }
+  red[threadIdx.x] = x * x;
+  __syncthreads();
+  for (int o = kLzOrthThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// beta[j] = |w| (the parts summed in order), alpha[j] = h1[j] + h2[j] (the
+// coefficient of V_j over both passes), V_{j+1} = w / beta[j] (zero when
+// the Krylov space is exhausted).
+__global__ __launch_bounds__(1024) void k_lz_next(int64_t n, int nparts, const double* __restrict__ part,
+                                                  const double* __restrict__ h1, const double* __restrict__ h2, int j,
+                                                  const double* __restrict__ w, double* __restrict__ vnext,
+                                                  double* __restrict__ alpha, double* __restrict__ beta) {
+  __shared__ double s_beta;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < nparts; ++q) t += part[q];
+    const double b = sqrt(t);
+    s_beta = b;
+    beta[j] = b;
+    alpha[j] = h1[j] + h2[j];
+  }
+  __syncthreads();
+  const double inv = s_beta > 0.0 ? 1.0 / s_beta : 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 1024) vnext[k] = w[k] * inv;
+}
+
+// y = sum over i < m of s[i] V_i (the Ritz vector), one thread per coordinate.
+__global__ void k_lz_combine(int64_t n, int m, const double* __restrict__ V, const double* __restrict__ s,
+                             double* __restrict__ y) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double x = 0.0;
+  for (int i = 0; i < m; ++i) x = fma(s[i], V[(int64_t)i * n + k], x);
+  y[k] = x;
+}
+
 unsigned wave_blocks(int n) { return (unsigned)((n + kRaWaves - 1) / kRaWaves); }
 
 }  // namespace
 
-hipError_t launch_ra_apply(hipStream_t st, int n_cams, const int32_t* cam_off, const int32_t* cam_ent,
-                           const int32_t* pair_i, const int32_t* pair_j, const double* Rrel, const double* c_in,
-                           const double* scale, const double* c1, double sigma, double wm, double wp, double* c_out,
-                           double* sq, double* scale_out, bool renorm, double* rho) {
+int lz_orth_blocks(int64_t n) { return (int)((n + kLzOrthThreads - 1) / kLzOrthThreads); }
+
+hipError_t launch_lz_step(hipStream_t st, int n_cams, const int32_t* cam_off, const int32_t* cam_ent,
+                          const int32_t* pair_i, const int32_t* pair_j, const double* Rrel, const double* c1, double wm,
+                          double wp, double* V, int j, double* w, double* sq, double* h1, double* h2, double* part,
+                          double* alpha, double* beta) {
+  const int64_t n = (int64_t)3 * n_cams;
+  const double* vj = V + (int64_t)j * n;
+  // w = A v_j: the operator kernel with sigma = 0 and negated weights
   if (c1)
-    k_ra_apply<true><<<wave_blocks(n_cams), kRaThreads, 0, st>>>(n_cams, cam_off, cam_ent, pair_i, pair_j, Rrel, c_in,
-                                                                 scale, c1, sigma, wm, wp, c_out, sq);
+    k_ra_apply<true><<<wave_blocks(n_cams), kRaThreads, 0, st>>>(n_cams, cam_off, cam_ent, pair_i, pair_j, Rrel, vj,
+                                                                 nullptr, c1, 0.0, -wm, -wp, w, sq);
   else
     k_ra_apply<false><<<wave_blocks(n_cams), kRaThreads, 0, st>>>(n_cams, cam_off, cam_ent, pair_i, pair_j, Rrel,
-                                                                  c_in, scale, nullptr, sigma, wm, wp, c_out, sq);
-  // the input scale of a renormalising step is 1 (it never follows one)
-  if (renorm) k_ra_norm<<<1, kRaThreads, 0, st>>>(n_cams, sq, sigma, 1.0, scale_out, rho);
+                                                                  vj, nullptr, nullptr, 0.0, -wm, -wp, w, sq);
+  const int m = j + 1;
+  const int nb = lz_orth_blocks(n);
+  k_lz_dots<<<m, kLzThreads, 0, st>>>(n, V, w, h1);
+  k_lz_orth<<<nb, kLzOrthThreads, 0, st>>>(n, m, V, h1, w, part);
+  k_lz_dots<<<m, kLzThreads, 0, st>>>(n, V, w, h2);
+  k_lz_orth<<<nb, kLzOrthThreads, 0, st>>>(n, m, V, h2, w, part);
+  k_lz_next<<<1, 1024, 0, st>>>(n, nb, part, h1, h2, j, w, V + (int64_t)m * n, alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_lz_combine(hipStream_t st, int64_t n, int m, const double* V, const double* s, double* y) {
+  k_lz_combine<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, m, V, s, y);
   return hipGetLastError();
 }
 
