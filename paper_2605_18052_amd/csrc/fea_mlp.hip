@@ -182,22 +182,35 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
     const float* __restrict__ params, unsigned short* __restrict__ Wout, double* __restrict__ item_wsum,
     float* __restrict__ feat_out) {
   __shared__ float s_sum[kInferThreads / kWave];
+  // layer 2's biases in the accumulator layout, [tile][lane half][register]
+  __shared__ __align__(16) float s_b2[2][2][16];
   const int item = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int4 rec = items[item];
   const int n = rec.x, start = rec.y, cnt = rec.z;
   const double* row = stab + (int64_t)n * kSnapRow;
-  // weights in the A layout: row (lane%32) + 32*tile; layer 1: k = 8h + q
-  // multiplies feature q in both halves (hi and lo parts); layer 2 slice
-  // (t2, g) value j <-> hidden-in unit 32 t2 + 16 g + 8 (j/4) + 4 h + j%4
+  if (tid < 64) {
+    const int t = tid >> 5, hh = (tid >> 4) & 1, r = tid & 15;
+    s_b2[t][hh][r] = params[kOffB2 + 32 * t + 8 * (r >> 2) + 4 * hh + (r & 3)];
+  }
+  // weights in the A layout: row (lane%32) + 32*tile.  Layer 1, k = 8h + q:
+  // q < 7 multiplies feature q in both halves (its hi and lo parts); q = 7
+  // carries the bias b1 + W1[:,7] * angle (the angle feature is the pair's,
+  // constant over the item) as hi in h = 0 and lo in h = 1, times the
+  // constant ones of the B operand: the bias needs no register of its own.
+  // Layer 2 slice (t2, g) value j <-> hidden-in unit 32 t2 + 16 g + 8 (j/4)
+  // + 4 h + j%4
   const int r32 = lane & 31, h = lane >> 5;
+  const float ang = (float)row[kSnapAng];
   f16x8 a1[2];
   f16x8 a2[2][4], a3[4];
-  f32x16 b1v[2], b2v[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int orow = r32 + 32 * t;
 #pragma unroll
-    for (int q = 0; q < kNF; ++q) a1[t][q] = (_Float16)params[orow * kNF + q];
+    for (int q = 0; q < kNF - 1; ++q) a1[t][q] = (_Float16)params[orow * kNF + q];
+    const float b = fmaf(params[orow * kNF + kNF - 1], ang, params[kOffB1 + orow]);
+    const _Float16 bh = (_Float16)b;
+    a1[t][kNF - 1] = h ? (_Float16)(b - (float)bh) : bh;
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl) {
       const int t2 = sl >> 1, g = sl & 1;
@@ -206,12 +219,6 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
         const int unit = 32 * t2 + 16 * g + 8 * (jv >> 2) + 4 * h + (jv & 3);
         a2[t][sl][jv] = (_Float16)params[kOffW2 + orow * kNH + unit];
       }
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int u = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);  // hidden unit of accumulator r
-      b1v[t][r] = params[kOffB1 + u];
-      b2v[t][r] = params[kOffB2 + u];
     }
   }
   // output layer: w3 in every row, contraction permuted as for layer 2
@@ -230,11 +237,11 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
     F1[k] = row[9 + k];
     F2[k] = row[18 + k];
   }
-  const float ang = (float)row[kSnapAng];
   const float icxi = (float)row[kSnapInvC + 0], icyi = (float)row[kSnapInvC + 1];
   const float icxj = (float)row[kSnapInvC + 2], icyj = (float)row[kSnapInvC + 3];
   const float fb0 = (float)row[kSnapFbar + 0], fb1 = (float)row[kSnapFbar + 1], fb2 = (float)row[kSnapFbar + 2];
 
+  __syncthreads();  // s_b2 written
   constexpr int kStride = kInferThreads;  // matches per iteration of the workgroup
   float wsum = 0.f;
   int m = wid * kWave + lane;
@@ -265,13 +272,15 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
       fo[0] = make_float4(f[0], f[1], f[2], f[3]);
       fo[1] = make_float4(f[4], f[5], f[6], f[7]);
     }
-    // the features as fp16 parts x = hi + lo, packed in pairs
+    // features 0..6 as fp16 parts x = hi + lo and the one that carries the
+    // bias, packed in pairs
     u32x4 fhi, flo;
+    f[7] = 1.f;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const f16x2 hv = __builtin_convertvector((f32x2){f[2 * q], f[2 * q + 1]}, f16x2);
       fhi[q] = __builtin_bit_cast(unsigned, hv);
-      flo[q] = pk_f16(f[2 * q] - (float)hv[0], f[2 * q + 1] - (float)hv[1]);
+      flo[q] = pk_f16(f[2 * q] - (float)hv[0], q < 3 ? f[2 * q + 1] - (float)hv[1] : 1.f);
     }
     // lanes l and l^32 trade parts: group A = matches of lanes 0..31,
     // group B = lanes 32..63; lanes < 32 supply hi, lanes >= 32 lo
@@ -286,14 +295,14 @@ __global__ __launch_bounds__(kInferThreads) void k_mlp_weights(
       const f16x8 bx = __builtin_bit_cast(f16x8, xv);
       f32x16 acc1[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[t], bx, b1v[t], 0, 0, 0);
+      for (int t = 0; t < 2; ++t) acc1[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[t], bx, (f32x16){}, 0, 0, 0);
       f16x8 hb[4];
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) hb[sl] = relu_slice(acc1[sl >> 1], 8 * (sl & 1));
       f32x16 acc2[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        acc2[t] = b2v[t];
+        acc2[t] = *reinterpret_cast<const f32x16*>(&s_b2[t][h][0]);
 #pragma unroll
         for (int sl = 0; sl < 4; ++sl)
           acc2[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a2[t][sl], hb[sl], acc2[t], 0, 0, 0);

@@ -198,13 +198,21 @@ def test_search_alignment_and_adjustment_compose():
     within 70 degrees, 0.5 px noise, no outliers) from rotations 2-5 degrees
     off and no translations: candidate search, alignment with two random
     starts, then epipolar adjustment from those centres reaches <= 1 degree
-    mean rotation error and recovers the centres."""
+    mean rotation error and recovers the centres.  The oracle runs the same
+    three stages from the same scene, candidates and starts; the adjustment's
+    fixed schedule leaves the centres short of their optimum by an amount that
+    is the method's, not the library's (0.022 of the mean centre distance in
+    the oracle's chain), so the library's centre error is bounded by the
+    oracle's: the two chains part only where fp32 scoring breaks a near-tie
+    between candidates differently."""
     sc = synth.sphere_scene(n_cams=60, n_pts=3000, p_det=0.35, sigma=0.5, outlier_frac=0.0, seed=41,
                             pair_angle_deg=70.0, name="object60")
+    cand = _cand32(4096)
+    starts = synth.random_centres(3, 2, sc.n_cams)
     ctx = make_context(sc, gauge=1)
-    rt = ctx.relative_translations(sc.R_init, _cand32(4096), tau_px=32.0)
+    rt = ctx.relative_translations(sc.R_init, cand, tau_px=32.0)
     _, _, pc, _ = ctx.get_segments()
-    al = ctx.translation_align(pc, sc.R_init, rt["t_rel"], synth.random_centres(3, 2, sc.n_cams))
+    al = ctx.translation_align(pc, sc.R_init, rt["t_rel"], starts)
     o = al["o"]
     t0 = -np.einsum("nab,nb->na", sc.R_init, o)
     ctx.init_poses(sc.R_init, t0)
@@ -216,9 +224,19 @@ def test_search_alignment_and_adjustment_compose():
     truth = _aligned(-np.einsum("nba,nb->na", sc.R_gt, sc.t_gt))
     c_ta = np.linalg.norm(o - truth, axis=1)
     c_ea = np.linalg.norm(_aligned(-np.einsum("nba,nb->na", R, t)) - truth, axis=1)
-    print(f"pipeline: rotation error {err0:.2f} -> {err1:.3f} deg; centre error after alignment "
-          f"{np.median(c_ta):.3f} (median), after adjustment {np.median(c_ea):.4f}", flush=True)
+    # the oracle's chain
+    pb = oracle_problem(sc)
+    ort = oracle.rel_trans(pb, sc.R_init, sc.f_init, cand, tau=32.0 / np.median(sc.f_init))
+    tg = oracle.ta_targets(sc.n_cams, ort["pair_cams"], sc.R_init, ort["t_rel"])
+    oo = oracle.ta_solve(ort["pair_cams"], tg, starts)["o"]
+    out = oracle.epipolar_adjust(pb, sc.R_init, -np.einsum("nab,nb->na", sc.R_init, oo), sc.f_init,
+                                 options=oracle.default_options(gauge_normalize=1))
+    c_ta_ref = np.linalg.norm(oo - truth, axis=1)
+    c_ea_ref = np.linalg.norm(_aligned(-np.einsum("nba,nb->na", out["R"], out["t"])) - truth, axis=1)
+    print(f"pipeline: rotation error {err0:.2f} -> {err1:.3f} deg (oracle "
+          f"{metrics.mean_rotation_error_deg(out['R'], sc.R_gt):.3f}); median centre error after "
+          f"alignment {np.median(c_ta):.4f} (oracle {np.median(c_ta_ref):.4f}), after adjustment "
+          f"{np.median(c_ea):.4f} (oracle {np.median(c_ea_ref):.4f})", flush=True)
     assert err1 <= 1.0 < err0
-    # the adjustment improves the centres (its schedule stops on the rotation
-    # error, before the centres have fully settled: 0.018-0.021 here)
-    assert np.median(c_ea) < np.median(c_ta) and np.median(c_ea) < 0.04
+    assert np.median(c_ea) < np.median(c_ta)
+    assert np.median(c_ea) <= 1.1 * np.median(c_ea_ref)
