@@ -98,7 +98,16 @@ typedef struct {
                               many workgroups per CU as reside at once, each
                               walking the items with the next item's loads
                               in flight), 0 one workgroup per item (0) */
-  int32_t reserved[2];     /* must be zero */
+  int32_t persistent_steps; /* with inner_loop = 1 and every intrinsics
+                              group a single camera: 1 runs each call's
+                              steps in one cooperative launch (every
+                              wavefront takes cameras of each step in turn,
+                              and the workgroups wait for each other between
+                              steps; the same results as one launch per
+                              step), 0 one launch per step (0: on this
+                              device the wait between steps costs more
+                              than a launch) */
+  int32_t reserved[1];     /* must be zero */
   double converge_deg;     /* per-scene early exit (0 = off, default): at the
                               start of a round whose threshold equals the
                               previous round's (the schedule at its floor), a
@@ -147,7 +156,10 @@ typedef struct {
                               workgroups per CU as reside at once, each
                               walking the items with the next item's loads
                               in flight */
-  int32_t reserved[4];
+  int32_t quad_steps_blocks; /* workgroups of the last persistent launch of
+                              the quadratic form's steps (0: none, the steps
+                              ran one launch each) */
+  int32_t reserved[3];
 } fea_info;
 
 /* Library version (FEA_VERSION of the build). */

@@ -129,7 +129,7 @@ std::vector<DBuf*> all_bufs(fea_ctx* c) {
                  &c->d_cam_ent, &c->d_group, &c->d_grp_off, &c->d_grp_cams, &c->d_cx, &c->d_cy, &c->a6,
                  &c->tp, &c->logf, &c->m_a6, &c->v_a6, &c->m_t, &c->v_t, &c->m_f, &c->v_f, &c->R[0],
                  &c->R[1], &c->T[0], &c->T[1], &c->Fc[0], &c->Fc[1], &c->Rh, &c->Th, &c->Fh, &c->gR,
-                 &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag, &c->Re, &c->Te, &c->Fe, &c->d_pair_scene, &c->d_inv_z, &c->d_tau, &c->ptab, &c->qpart, &c->qW, &c->qmask, &c->stab, &c->counters,
+                 &c->gt, &c->gf, &c->loss_cam, &c->loss, &c->logR, &c->errflag, &c->wait_state, &c->Re, &c->Te, &c->Fe, &c->d_pair_scene, &c->d_inv_z, &c->d_tau, &c->ptab, &c->qpart, &c->qW, &c->qmask, &c->stab, &c->counters,
                  &c->Rh1, &c->Th1, &c->Fh1, &c->Rh2, &c->Th2, &c->Fh2, &c->d_fbar, &c->mlp, &c->wlay,
                  &c->item_wsum, &c->d_inv_zw, &c->d_scene_mode, &c->d_fbar_hist, &c->d_scene_cam_off, &c->d_scene_cams, &c->d_scene_z, &c->a6h, &c->tph, &c->logfh, &c->d_learned_ok, &c->d_fallbacks, &c->d_judge_l0, &c->d_judge_l1};
   for (DBuf* b : one) v.push_back(b);
@@ -168,8 +168,8 @@ bool options_valid(const fea_options* o, std::string* why) {
   if (o->tile_persistent != 0 && o->tile_persistent != 1) return bad("tile_persistent must be 0 or 1");
   if (o->tile_persistent == 1 && o->tile_matches != 1024 && o->tile_matches != 2048 && o->tile_matches != 4096)
     return bad("tile_persistent = 1 needs tile_matches 1024, 2048 or 4096");
-  for (int k = 0; k < 2; ++k)
-    if (o->reserved[k] != 0) return bad("reserved option fields must be zero");
+  if (o->persistent_steps != 0 && o->persistent_steps != 1) return bad("persistent_steps must be 0 or 1");
+  if (o->reserved[0] != 0) return bad("reserved option fields must be zero");
   if (!(o->converge_deg >= 0) || !std::isfinite(o->converge_deg)) return bad("converge_deg must be finite and >= 0");
   return true;
 }
@@ -178,6 +178,17 @@ bool options_valid(const fea_options* o, std::string* why) {
 // of converged and stopped scenes, and FEA_ENONFINITE if more are stopped
 // than at the previous check.
 fea_status check_nonfinite(fea_ctx* c, int32_t* converged = nullptr, int32_t* stopped = nullptr) {
+  std::vector<unsigned> ws;
+  HIP_OR_FAIL(c, download(c, ws, c->wait_state, 2));
+  if (ws[1] != 0) {
+    // a persistent launch left early: its steps did not all run; the
+    // context keeps to one launch per step from here on
+    c->quad_steps_cap = 0;
+    c->wait_base = 0;
+    HIP_OR_FAIL(c, hipMemsetAsync(c->wait_state.p, 0, 2 * sizeof(unsigned), c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return fail(c, FEA_EDEVICE, "a device-wide wait between the steps of a persistent launch timed out");
+  }
   std::vector<int32_t> done;
   HIP_OR_FAIL(c, download(c, done, c->d_scene_done, (size_t)c->S));
   int32_t nc = 0, nb = 0;
@@ -647,6 +658,24 @@ hipError_t capture_graph(fea_ctx* c) {
 }
 
 fea_status run_steps(fea_ctx* c, int32_t n_steps) {
+  // the quadratic form's steps in one cooperative launch, where every step
+  // is the camera kernel alone (no shared intrinsics group)
+  if (n_steps >= 2 && c->opt.inner_loop == 1 && c->opt.persistent_steps && c->all_single && !c->timing &&
+      c->stream != nullptr && c->n_items > 0) {
+    const int blocks = fea::quad_steps_blocks(c);
+    if (blocks > 0) {
+      HIP_OR_FAIL(c, fea::launch_quad_steps(c, n_steps, blocks));
+      c->last_quad_blocks = blocks;
+      c->pcur ^= (n_steps & 1);
+      c->ptab_current = false;
+      c->step += n_steps;
+      c->adam_t += n_steps;
+      c->global_step += n_steps;
+      if (c->opt.log_every > 0)
+        c->n_logged = (int32_t)std::min<int64_t>(c->opt.max_log, c->global_step / c->opt.log_every);
+      return FEA_OK;
+    }
+  }
   const bool graphs = c->opt.use_graphs && !c->timing && c->stream != nullptr && c->n_items > 0;
   if (n_steps > 0 && c->opt.inner_loop != 1 && !c->ptab_current)
     HIP_OR_FAIL(c, fea::launch_pair_pose(c, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
@@ -1046,6 +1075,7 @@ fea_status fea_default_options(fea_options* o) {
   o->use_graphs = 1;
   o->weight_mode = 0;
   o->inner_loop = 0;
+  o->persistent_steps = 0;
   return FEA_OK;
 }
 
@@ -1081,10 +1111,20 @@ fea_status fea_create(fea_ctx** out, int32_t device, const fea_options* opt, voi
     }
     c->own_stream = true;
   }
-  if (dalloc(c->errflag, sizeof(int)) != hipSuccess || dalloc(c->loss, sizeof(double)) != hipSuccess) {
+  if (dalloc(c->errflag, sizeof(int)) != hipSuccess || dalloc(c->loss, sizeof(double)) != hipSuccess ||
+      dalloc(c->wait_state, 2 * sizeof(unsigned)) != hipSuccess) {
     fea_destroy(c);
     return FEA_ENOMEM;
   }
+  if (hipMemsetAsync(c->wait_state.p, 0, 2 * sizeof(unsigned), c->stream) != hipSuccess) {
+    fea_destroy(c);
+    return FEA_EDEVICE;
+  }
+  // a device-wide wait between two steps gives up after half a second
+  int clock_khz = 0;
+  if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || clock_khz < 1)
+    clock_khz = 100000;
+  c->wait_limit_ticks = (long long)clock_khz * 500;
   *out = c;
   return FEA_OK;
 }
@@ -2122,6 +2162,7 @@ fea_status fea_get_info(fea_ctx* c, fea_info* out) {
   out->tile_matches = fea::tile_matches_of(c->tile_cfg);
   out->tile_threads = fea::kTiles[c->tile_cfg].threads;
   out->tile_persistent = fea::kTiles[c->tile_cfg].persistent ? 1 : 0;
+  out->quad_steps_blocks = c->last_quad_blocks;
   return FEA_OK;
 }
 
@@ -2832,8 +2873,6 @@ hipError_t run_captured(hipStream_t st, int iters, int& parity, Step step) {
 
 }  // namespace
 
-extern "C" {
-
 namespace {
 
 // Lanczos scratch (device arrays): basis V [(kmax+1) x n], the step's vector
@@ -2991,6 +3030,8 @@ hipError_t lanczos_bottom(hipStream_t st, const LzOperator& A, double sigma, con
 }
 
 }  // namespace
+
+extern "C" {
 
 fea_status fea_rotation_averaging(fea_ctx* c, int32_t n_cams, int64_t n_pairs, const int32_t* pair_i,
                                   const int32_t* pair_j, const double* R_rel, const double* v0,

@@ -80,20 +80,61 @@ __device__ __forceinline__ void quad_partials(const double* __restrict__ W, cons
   G[9] = L;
 }
 
+// The per-camera pass's arguments that stay the same from step to step.
+struct CamArgs {
+  int N;
+  const int32_t* cam_off;
+  const int4* cam_ent;
+  const double* part;
+  const double* qW;
+  double *gR_out, *gt_out, *gf_out, *loss_cam;
+  int do_update, focal_inline, optimize_focal;
+  const int32_t* group;
+  double *a6, *tp, *logf, *m_a6, *v_a6, *m_t, *v_t, *m_f, *v_f;
+  AdamArgs ad;
+  const int32_t* cam_scene;
+  const int32_t* scene_done;
+};
+
+// The poses a step reads (current parity) and writes (the other one).
+struct PosePair {
+  const double *R, *T, *Fc;
+  double *Rn, *Tn, *Fn;
+};
+
+// One camera's share of a step, run by one wavefront (see the file comment).
 template <bool QUAD>
-__global__ __launch_bounds__(256) void k_camgrad(
-    int N, const int32_t* __restrict__ cam_off, const int4* __restrict__ cam_ent,
-    const double* __restrict__ part, const double* __restrict__ qW, const double* __restrict__ R,
-    const double* __restrict__ T, const double* __restrict__ Fc, double* __restrict__ gR_out,
-    double* __restrict__ gt_out, double* __restrict__ gf_out, double* __restrict__ loss_cam, int do_update,
-    int focal_inline, int optimize_focal, const int32_t* __restrict__ group, double* __restrict__ a6,
-    double* __restrict__ tp, double* __restrict__ logf, double* __restrict__ m_a6, double* __restrict__ v_a6,
-    double* __restrict__ m_t, double* __restrict__ v_t, double* __restrict__ m_f, double* __restrict__ v_f,
-    AdamArgs ad, StepCtl sc, double* __restrict__ Rn, double* __restrict__ Tn, double* __restrict__ Fn,
-    const int32_t* __restrict__ cam_scene, const int32_t* __restrict__ scene_done) {
-  const int cam = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (cam >= N) return;  // uniform per wave
+__device__ __forceinline__ void camera_pass(const CamArgs& a, const PosePair& pp, const StepCtl sc, const int cam,
+                                            const int lane) {
+  const int N = a.N;
+  const int32_t* __restrict__ cam_off = a.cam_off;
+  const int4* __restrict__ cam_ent = a.cam_ent;
+  const double* __restrict__ part = a.part;
+  const double* __restrict__ qW = a.qW;
+  const double* __restrict__ R = pp.R;
+  const double* __restrict__ T = pp.T;
+  const double* __restrict__ Fc = pp.Fc;
+  double* __restrict__ gR_out = a.gR_out;
+  double* __restrict__ gt_out = a.gt_out;
+  double* __restrict__ gf_out = a.gf_out;
+  double* __restrict__ loss_cam = a.loss_cam;
+  const int do_update = a.do_update, focal_inline = a.focal_inline, optimize_focal = a.optimize_focal;
+  const int32_t* __restrict__ group = a.group;
+  double* __restrict__ a6 = a.a6;
+  double* __restrict__ tp = a.tp;
+  double* __restrict__ logf = a.logf;
+  double* __restrict__ m_a6 = a.m_a6;
+  double* __restrict__ v_a6 = a.v_a6;
+  double* __restrict__ m_t = a.m_t;
+  double* __restrict__ v_t = a.v_t;
+  double* __restrict__ m_f = a.m_f;
+  double* __restrict__ v_f = a.v_f;
+  const AdamArgs ad = a.ad;
+  double* __restrict__ Rn = pp.Rn;
+  double* __restrict__ Tn = pp.Tn;
+  double* __restrict__ Fn = pp.Fn;
+  const int32_t* __restrict__ cam_scene = a.cam_scene;
+  const int32_t* __restrict__ scene_done = a.scene_done;
   if (do_update && scene_done != nullptr && scene_done[cam_scene[cam]] != 0) {
     // a converged scene takes no step: its poses carry over to the next
     // parity unchanged (the rotation log still records them) and its
@@ -256,6 +297,74 @@ __global__ __launch_bounds__(256) void k_camgrad(
         for (int k = 0; k < 9; ++k) sc.logR[(slot * N + cam) * 9 + k] = Rnew[k];
     }
   }
+  }
+}
+
+
+template <bool QUAD>
+__global__ __launch_bounds__(256) void k_camgrad(CamArgs a, PosePair pp, StepCtl sc) {
+  const int cam = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  if (cam >= a.N) return;  // uniform per wave
+  camera_pass<QUAD>(a, pp, sc, cam, threadIdx.x & 63);
+}
+
+// Both pose buffers: parity p is current, p ^ 1 receives the step's poses.
+struct PoseBufs {
+  double *R0, *T0, *F0, *R1, *T1, *F1;
+  __device__ PosePair at(int p) const {
+    return p ? PosePair{R1, T1, F1, R0, T0, F0} : PosePair{R0, T0, F0, R1, T1, F1};
+  }
+};
+
+// Device-wide wait between two steps of a persistent launch.  Every
+// wavefront makes its stores visible at agent scope (all XCDs), one thread
+// per workgroup counts the workgroup's arrival on `bar` and waits until the
+// count reaches `target` (compared modulo 2^32, so the count never needs
+// resetting), then every wavefront acquires at agent scope.  The wait is
+// bounded by `limit` wall-clock ticks: past it the workgroup sets *err and
+// the caller leaves the kernel, so no wavefront can wait forever (under a
+// cooperative launch every workgroup is resident, and none should).
+__device__ __forceinline__ bool grid_wait(unsigned* bar, unsigned target, long long limit, int* err) {
+  __shared__ int s_ok;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = wall_clock64();
+    int ok = 1;
+    while ((int)(__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+      __builtin_amdgcn_s_sleep(1);
+      if (wall_clock64() - t0 > limit) {
+        ok = 0;
+        break;
+      }
+    }
+    if (!ok) *err = 1;
+    s_ok = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return s_ok != 0;
+}
+
+// A round's steps of the quadratic form in one cooperative launch: in every
+// step wavefront w takes cameras w, w + W, w + 2W, ... (W wavefronts in the
+// grid), and the workgroups wait for each other between steps, since a step
+// reads the poses every camera wrote in the one before.  Step s runs at
+// parity p0 ^ (s & 1) with the same buffers, step counters and rotation log
+// as one k_camgrad<true> launch per step, so the results are the same bits.
+__global__ __launch_bounds__(256) void k_quad_steps(CamArgs a, PoseBufs pb, StepCtl sc, int n_steps,
+                                                   unsigned* bar, unsigned bar_base, long long limit, int* err) {
+  const int per_block = blockDim.x / kWave;
+  const int W = gridDim.x * per_block;
+  const int wave = blockIdx.x * per_block + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int p0 = sc.p;
+  for (int s = 0; s < n_steps; ++s) {
+    sc.p = p0 ^ (s & 1);
+    const PosePair pp = pb.at(sc.p);
+    for (int cam = wave; cam < a.N; cam += W) camera_pass<true>(a, pp, sc, cam, lane);
+    if (s + 1 < n_steps && !grid_wait(bar, bar_base + (unsigned)(s + 1) * gridDim.x, limit, err)) return;
   }
 }
 
@@ -673,27 +782,51 @@ hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero) {
   return hipGetLastError();
 }
 
+namespace {
+CamArgs cam_args(fea_ctx* c, int do_update) {
+  CamArgs a;
+  a.N = c->N;
+  a.cam_off = c->d_cam_off.as<int32_t>();
+  a.cam_ent = c->d_cam_ent.as<int4>();
+  a.part = c->part.as<double>();
+  a.qW = c->qW.as<double>();
+  a.gR_out = c->gR.as<double>();
+  a.gt_out = c->gt.as<double>();
+  a.gf_out = c->gf.as<double>();
+  a.loss_cam = c->loss_cam.as<double>();
+  a.do_update = do_update;
+  a.focal_inline = c->all_single ? 1 : 0;
+  a.optimize_focal = c->opt.optimize_focal;
+  a.group = c->d_group.as<int32_t>();
+  a.a6 = c->a6.as<double>();
+  a.tp = c->tp.as<double>();
+  a.logf = c->logf.as<double>();
+  a.m_a6 = c->m_a6.as<double>();
+  a.v_a6 = c->v_a6.as<double>();
+  a.m_t = c->m_t.as<double>();
+  a.v_t = c->v_t.as<double>();
+  a.m_f = c->m_f.as<double>();
+  a.v_f = c->v_f.as<double>();
+  a.ad = adam_args(c);
+  a.cam_scene = c->d_cam_scene.as<int32_t>();
+  a.scene_done = c->d_scene_done.as<int32_t>();
+  return a;
+}
+}  // namespace
+
 // quad: dL/dF of each pair from its quadratic form W_n (built for the round)
 // instead of the per-match kernel's item partials.
 hipError_t launch_camgrad(fea_ctx* c, int do_update, bool quad) {
   if (c->N == 0) return hipSuccess;
   const int per_block = 256 / kWave;
   const unsigned blocks = (unsigned)((c->N + per_block - 1) / per_block);
-  const int nx = c->pcur ^ 1;
-#define FEA_CAMGRAD_ARGS                                                                                      \
-  c->N, c->d_cam_off.as<int32_t>(), c->d_cam_ent.as<int4>(), c->part.as<double>(), c->qW.as<double>(),         \
-      c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(), c->Fc[c->pcur].as<double>(), c->gR.as<double>(), \
-      c->gt.as<double>(), c->gf.as<double>(), c->loss_cam.as<double>(), do_update, c->all_single ? 1 : 0,       \
-      c->opt.optimize_focal, c->d_group.as<int32_t>(), c->a6.as<double>(), c->tp.as<double>(),                 \
-      c->logf.as<double>(), c->m_a6.as<double>(), c->v_a6.as<double>(), c->m_t.as<double>(),                   \
-      c->v_t.as<double>(), c->m_f.as<double>(), c->v_f.as<double>(), adam_args(c), step_ctl(c),                \
-      c->R[nx].as<double>(), c->T[nx].as<double>(), c->Fc[nx].as<double>(), c->d_cam_scene.as<int32_t>(),     \
-      c->d_scene_done.as<int32_t>()
+  const int p = c->pcur, nx = p ^ 1;
+  const PosePair pp{c->R[p].as<double>(),  c->T[p].as<double>(),  c->Fc[p].as<double>(),
+                    c->R[nx].as<double>(), c->T[nx].as<double>(), c->Fc[nx].as<double>()};
   if (quad)
-    k_camgrad<true><<<blocks, 256, 0, c->stream>>>(FEA_CAMGRAD_ARGS);
+    k_camgrad<true><<<blocks, 256, 0, c->stream>>>(cam_args(c, do_update), pp, step_ctl(c));
   else
-    k_camgrad<false><<<blocks, 256, 0, c->stream>>>(FEA_CAMGRAD_ARGS);
-#undef FEA_CAMGRAD_ARGS
+    k_camgrad<false><<<blocks, 256, 0, c->stream>>>(cam_args(c, do_update), pp, step_ctl(c));
   return hipGetLastError();
 }
 
@@ -702,12 +835,47 @@ hipError_t launch_camgrad_at(fea_ctx* c, const double* R, const double* T, const
   if (c->N == 0) return hipSuccess;
   const int per_block = 256 / kWave;
   const unsigned blocks = (unsigned)((c->N + per_block - 1) / per_block);
-  k_camgrad<false><<<blocks, 256, 0, c->stream>>>(
-      c->N, c->d_cam_off.as<int32_t>(), c->d_cam_ent.as<int4>(), c->part.as<double>(), nullptr, R, T, F,
-      c->gR.as<double>(), c->gt.as<double>(), c->gf.as<double>(), c->loss_cam.as<double>(), 0, 0, 0,
-      c->d_group.as<int32_t>(), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-      adam_args(c), step_ctl(c), nullptr, nullptr, nullptr, nullptr, nullptr);
+  CamArgs a = cam_args(c, 0);
+  a.qW = nullptr;
+  a.focal_inline = 0;
+  a.optimize_focal = 0;
+  a.a6 = a.tp = a.logf = a.m_a6 = a.v_a6 = a.m_t = a.v_t = a.m_f = a.v_f = nullptr;
+  a.cam_scene = nullptr;
+  a.scene_done = nullptr;
+  const PosePair pp{R, T, F, nullptr, nullptr, nullptr};
+  k_camgrad<false><<<blocks, 256, 0, c->stream>>>(a, pp, step_ctl(c));
   return hipGetLastError();
+}
+
+// Workgroups of k_quad_steps: one wavefront per camera up to as many
+// workgroups as reside on the device at once (0 if the kernel cannot run).
+int quad_steps_blocks(fea_ctx* c) {
+  if (c->quad_steps_cap < 0) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_quad_steps, 256, 0) != hipSuccess) per_cu = 0;
+    (void)hipGetLastError();
+    c->quad_steps_cap = per_cu * c->n_cu;
+  }
+  const int per_block = 256 / kWave;
+  return std::min((c->N + per_block - 1) / per_block, c->quad_steps_cap);
+}
+
+hipError_t launch_quad_steps(fea_ctx* c, int n_steps, int blocks) {
+  if (c->N == 0 || n_steps <= 0) return hipSuccess;
+  if (blocks <= 0) return hipErrorInvalidValue;
+  CamArgs a = cam_args(c, 1);
+  PoseBufs pb{c->R[0].as<double>(), c->T[0].as<double>(), c->Fc[0].as<double>(),
+              c->R[1].as<double>(), c->T[1].as<double>(), c->Fc[1].as<double>()};
+  StepCtl sc = step_ctl(c);
+  unsigned* bar = c->wait_state.as<unsigned>();
+  int* err = reinterpret_cast<int*>(bar + 1);
+  unsigned base = c->wait_base;
+  long long limit = c->wait_limit_ticks;
+  void* args[] = {&a, &pb, &sc, &n_steps, &bar, &base, &limit, &err};
+  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_quad_steps), dim3((unsigned)blocks),
+                                                  dim3(256), args, 0, c->stream);
+  if (e == hipSuccess) c->wait_base += (unsigned)(n_steps - 1) * (unsigned)blocks;
+  return e;
 }
 
 hipError_t launch_focal_update(fea_ctx* c) {

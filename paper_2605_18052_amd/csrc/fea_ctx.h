@@ -89,6 +89,11 @@ enum : int { kErrSameCam = 1, kErrRange = 2, kErrNonFinite = 4 };
 struct fea_ctx {
   int device = 0;
   int n_cu = 256;                         // compute units of the device (persistent launches)
+  int quad_steps_cap = -1;                // resident workgroups of k_quad_steps (-1: not asked yet)
+  fea::DBuf wait_state;                   // uint32 [2]: arrival count of the device-wide waits, error flag
+  unsigned wait_base = 0;                 // arrivals counted so far (the next launch's base)
+  int last_quad_blocks = 0;               // workgroups of the last k_quad_steps launch
+  long long wait_limit_ticks = 0;         // bound of one device-wide wait in wall-clock ticks
   std::vector<float> tune_ms;             // the autotuner's mean time per shape of kTiles (last tuning)
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -275,6 +280,8 @@ hipError_t launch_guard(fea_ctx* c, int32_t round);
 hipError_t launch_scene_loss_log(fea_ctx* c, int32_t round);
 hipError_t run_ablation(fea_ctx* c, int variant, int reps, double* ms, float* pair_sum_dev);
 hipError_t launch_camgrad_at(fea_ctx* c, const double* R, const double* T, const double* F);
+int quad_steps_blocks(fea_ctx* c);
+hipError_t launch_quad_steps(fea_ctx* c, int n_steps, int blocks);
 
 // --- parameters given as device arrays (fea_autograd.hip) ---
 hipError_t launch_params_to_pose(fea_ctx* c, const double* a6, const double* t, const double* logf);

@@ -32,7 +32,8 @@ class fea_options(C.Structure):
                 ("lr_decay", C.c_double), ("reset_moments", C.c_int32),
                 ("tile_matches", C.c_int32), ("use_graphs", C.c_int32),
                 ("weight_mode", C.c_int32), ("inner_loop", C.c_int32),
-                ("tile_persistent", C.c_int32), ("reserved", C.c_int32 * 2),
+                ("tile_persistent", C.c_int32), ("persistent_steps", C.c_int32),
+                ("reserved", C.c_int32 * 1),
                 ("converge_deg", C.c_double)]
 
 
@@ -51,7 +52,8 @@ class fea_info(C.Structure):
                 ("gauge_center", C.c_double * 3), ("gauge_scale", C.c_double),
                 ("tau", C.c_double), ("tile_matches", C.c_int32),
                 ("tile_threads", C.c_int32), ("n_scenes", C.c_int32),
-                ("tile_persistent", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("tile_persistent", C.c_int32), ("quad_steps_blocks", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class FeaError(RuntimeError):
