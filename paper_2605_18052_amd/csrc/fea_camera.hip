@@ -135,33 +135,17 @@ __device__ __forceinline__ void camera_pass(const CamArgs& a, const PosePair& pp
   double* __restrict__ Fn = pp.Fn;
   const int32_t* __restrict__ cam_scene = a.cam_scene;
   const int32_t* __restrict__ scene_done = a.scene_done;
-  if (do_update && scene_done != nullptr && scene_done[cam_scene[cam]] != 0) {
-    // a converged scene takes no step: its poses carry over to the next
-    // parity unchanged (the rotation log still records them) and its
-    // gradient, loss and optimiser state are left as they are
-    const int p = sc.p;
-    const long long t_glob = sc.ctr->global_t[p] + 1;
-    if (cam == 0 && lane == 0) {
-      sc.ctr->adam_t[p ^ 1] = sc.ctr->adam_t[p] + 1;
-      sc.ctr->global_t[p ^ 1] = t_glob;
-      sc.ctr->b1t[p ^ 1] = sc.ctr->b1t[p] * ad.b1;
-      sc.ctr->b2t[p ^ 1] = sc.ctr->b2t[p] * ad.b2;
-    }
-    if (lane < 9) {
-      const double r = R[9 * cam + lane];
-      Rn[9 * cam + lane] = r;
-      if (sc.log_every > 0 && t_glob % sc.log_every == 0) {
-        const long long slot = t_glob / sc.log_every - 1;
-        if (slot < sc.max_log) sc.logR[(slot * N + cam) * 9 + lane] = r;
-      }
-    }
-    if (lane < 3) Tn[3 * cam + lane] = T[3 * cam + lane];
-    if (lane == 0 && focal_inline) Fn[cam] = Fc[cam];
-    return;
-  }
-  // optimiser state, fetched before the pair loop: lane k < 6 owns 6D
-  // coordinate k, lanes 6..8 the translation, lane 9 log f (single-camera
-  // intrinsics groups); every update lane also needs the whole 6D vector
+  // The loads go in the order of their chains, so that the chains overlap:
+  // the camera's entry range, its scene, the optimiser state, then the
+  // camera's first entries and the scene's stop flag (a stopped scene
+  // ignores the rest).
+  const int e_end = cam_off[cam + 1];
+  int e = cam_off[cam] + lane;
+  const bool may_stop = do_update && scene_done != nullptr;
+  const int scene = may_stop ? cam_scene[cam] : 0;
+  // optimiser state: lane k < 6 owns 6D coordinate k, lanes 6..8 the
+  // translation, lane 9 log f (single-camera intrinsics groups); every
+  // update lane also needs the whole 6D vector
   const bool upd = do_update && lane < (focal_inline ? 10 : 9);
   double a_cur[6], p_own = 0.0, m_own = 0.0, v_own = 0.0;
   int grp = 0;
@@ -185,13 +169,41 @@ __device__ __forceinline__ void camera_pass(const CamArgs& a, const PosePair& pp
       v_own = v_f[grp];
     }
   }
+  int4 en_next = make_int4(0, 0, 0, 0);
+  if (e < e_end) en_next = cam_ent[e];
+  const bool stopped = may_stop && scene_done[scene] != 0;
+  if (stopped) {
+    // a converged scene takes no step: its poses carry over to the next
+    // parity unchanged (the rotation log still records them) and its
+    // gradient, loss and optimiser state are left as they are
+    const int p = sc.p;
+    const long long t_glob = sc.ctr->global_t[p] + 1;
+    if (cam == 0 && lane == 0) {
+      sc.ctr->adam_t[p ^ 1] = sc.ctr->adam_t[p] + 1;
+      sc.ctr->global_t[p ^ 1] = t_glob;
+      sc.ctr->b1t[p ^ 1] = sc.ctr->b1t[p] * ad.b1;
+      sc.ctr->b2t[p ^ 1] = sc.ctr->b2t[p] * ad.b2;
+    }
+    if (lane < 9) {
+      const double r = R[9 * cam + lane];
+      Rn[9 * cam + lane] = r;
+      if (sc.log_every > 0 && t_glob % sc.log_every == 0) {
+        const long long slot = t_glob / sc.log_every - 1;
+        if (slot < sc.max_log) sc.logR[(slot * N + cam) * 9 + lane] = r;
+      }
+    }
+    if (lane < 3) Tn[3 * cam + lane] = T[3 * cam + lane];
+    if (lane == 0 && focal_inline) Fn[cam] = Fc[cam];
+    return;
+  }
   double gR[9], gt[3], gf = 0.0, L = 0.0;
 #pragma unroll
   for (int k = 0; k < 9; ++k) gR[k] = 0.0;
   gt[0] = gt[1] = gt[2] = 0.0;
-  const int e_end = cam_off[cam + 1];
-  for (int e = cam_off[cam] + lane; e < e_end; e += kWave) {
-    const int4 en = cam_ent[e];
+  while (e < e_end) {
+    const int4 en = en_next;
+    e += kWave;
+    if (e < e_end) en_next = cam_ent[e];  // the lane's next entry, in flight meanwhile
     const int side = en.x & 1;
     const int i = side ? en.w : cam;
     const int j = side ? cam : en.w;
@@ -218,7 +230,7 @@ __device__ __forceinline__ void camera_pass(const CamArgs& a, const PosePair& pp
   for (int k = 0; k < 3; ++k) red[9 + k] = gt[k];
   red[12] = gf;
   red[13] = L;
-  wave_sum_f64_multi<14>(red);
+  wave_sum_f64_scatter<14>(red);
 #pragma unroll
   for (int k = 0; k < 9; ++k) gR[k] = red[k];
 #pragma unroll

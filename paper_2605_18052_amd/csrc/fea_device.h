@@ -90,6 +90,59 @@ __device__ __forceinline__ void wave_sum_f64_multi(double (&v)[NV]) {
     v[k] = (readlane_f64(v[k], 0) + readlane_f64(v[k], 16)) + (readlane_f64(v[k], 32) + readlane_f64(v[k], 48));
 }
 
+// l <-> l^32 exchange of two fp64 values and their sum: lanes < 32 return
+// x(l) + x(l + 32), lanes >= 32 return y(l - 32) + y(l).  v_permlane32_swap
+// trades the upper 32 lanes of its first operand with the lower 32 of its
+// second.
+__device__ __forceinline__ double swap32_add(double x, double y) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// The same between the rows of 16 lanes: rows 0 and 2 return x summed with
+// the next row, rows 1 and 3 return y summed with the previous row
+// (v_permlane16_swap trades the odd rows of its first operand with the even
+// rows of its second).
+__device__ __forceinline__ double swap16_add(double x, double y) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// Wave sums of up to 16 fp64 values, every lane receiving the results, as a
+// reduce-scatter: each stage pairs the lanes across one bit of the lane
+// index and halves the values a lane carries (a lane keeps the half its
+// side owns, adding the partner's copy), so 16 sums cost about the
+// exchanges of two single butterflies.  Stages: l <-> l^32, neighbouring
+// rows, the row mirror (p <-> 15 - p), the half-row mirror (q <-> 7 - q),
+// then a butterfly inside each quad; sum k ends in the quad at lane
+// 32 (k>>3) + 16 ((k>>2)&1) + 8 ((k>>1)&1) + 4 (k&1) and is read from there.
+// The order of the additions is fixed, so the sums are reproducible.
+template <int NV>
+__device__ __forceinline__ void wave_sum_f64_scatter(double (&v)[NV]) {
+  static_assert(NV <= 16, "at most 16 values");
+  double a[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) a[k] = k < NV ? v[k] : 0.0;
+  double b[8], c[4], d[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) b[k] = swap32_add(a[k], a[k + 8]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c[k] = swap16_add(b[k], b[k + 4]);
+  const int lane = __lane_id();
+  const bool upper8 = (lane & 8) != 0, upper4 = (lane & 4) != 0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    d[k] = (upper8 ? c[k + 2] : c[k]) + dpp_f64<0x140>(upper8 ? c[k] : c[k + 2]);  // row_mirror
+  double e = (upper4 ? d[1] : d[0]) + dpp_f64<0x141>(upper4 ? d[0] : d[1]);     // row_half_mirror
+  e += dpp_f64<0x4E>(e);  // quad_perm [2,3,0,1]
+  e += dpp_f64<0xB1>(e);  // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    v[k] = readlane_f64(e, 32 * (k >> 3) + 16 * ((k >> 2) & 1) + 8 * ((k >> 1) & 1) + 4 * (k & 1));
+}
+
 __device__ __forceinline__ double readfirstlane_f64(double v) {
   const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
   const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
