@@ -208,7 +208,8 @@ __global__ void k_ra_to_R(int n_cams, const double* __restrict__ a6, double* __r
 // The basis V is row-major [m][n]: row i is the i-th Lanczos vector in the
 // camera-major layout (3 entries per camera).
 constexpr int kLzThreads = 256;
-constexpr int kLzOrthThreads = 64;  // small workgroups spread one pass over many CUs
+constexpr int kLzOrthThreads = 64;  // coordinates per workgroup of k_lz_orth (one per lane)
+constexpr int kLzOrthWaves = 16;    // wavefronts per workgroup, each a slice of the basis
 
 // h[i] = V_i . w, one workgroup per basis vector (fixed-order sums).
 __global__ __launch_bounds__(kLzThreads) void k_lz_dots(int64_t n, const double* __restrict__ V,
@@ -226,26 +227,36 @@ __global__ __launch_bounds__(kLzThreads) void k_lz_dots(int64_t n, const double*
   if (threadIdx.x == 0) h[blockIdx.x] = red[0];
 }
 
-// w -= sum over i < m of h[i] V_i, one thread per coordinate; part[block]
-// = the block's sum of w^2 after the subtraction.
-__global__ __launch_bounds__(kLzOrthThreads) void k_lz_orth(int64_t n, int m, const double* __restrict__ V,
-                                                            const double* __restrict__ h, double* __restrict__ w,
-                                                            double* __restrict__ part) {
-  __shared__ double red[kLzOrthThreads];
-  const int64_t k = (int64_t)blockIdx.x * kLzOrthThreads + threadIdx.x;
-  double x = 0.0;
-  if (k < n) {
-    x = w[k];
-    for (int i = 0; i < m; ++i) x = fma(-h[i], V[(int64_t)i * n + k], x);
-    w[k] = x;
-  }
-  red[threadIdx.x] = x * x;
+// w -= sum over i < m of h[i] V_i.  A workgroup takes 64 coordinates (one
+// per lane) and splits the basis over its 16 wavefronts (wavefront q sums
+// rows q, q + 16, ...), so a pass over an m x n basis runs on 16 n / 64
+// wavefronts instead of n / 64; the 16 partial sums are added in LDS in a
+// fixed order.  part[block] = the block's sum of w^2 after the subtraction.
+__global__ __launch_bounds__(kLzOrthThreads * kLzOrthWaves) void k_lz_orth(int64_t n, int m,
+                                                                          const double* __restrict__ V,
+                                                                          const double* __restrict__ h,
+                                                                          double* __restrict__ w,
+                                                                          double* __restrict__ part) {
+  __shared__ double s_acc[kLzOrthWaves][kLzOrthThreads];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t k = (int64_t)blockIdx.x * kLzOrthThreads + lane;
+  double acc = 0.0;
+  if (k < n)
+    for (int i = q; i < m; i += kLzOrthWaves) acc = fma(h[i], V[(int64_t)i * n + k], acc);
+  s_acc[q][lane] = acc;
   __syncthreads();
-  for (int o = kLzOrthThreads / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+  if (q == 0) {
+    double x = 0.0;
+    if (k < n) {
+      double sub = 0.0;
+#pragma unroll
+      for (int r = 0; r < kLzOrthWaves; ++r) sub += s_acc[r][lane];
+      x = w[k] - sub;
+      w[k] = x;
+    }
+    const double sq = wave_sum_f64(x * x);
+    if (lane == 0) part[blockIdx.x] = sq;
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 // beta[j] = |w| (the parts summed in order), alpha[j] = h1[j] + h2[j] (the
@@ -301,9 +312,9 @@ hipError_t launch_lz_step(hipStream_t st, int n_cams, const int32_t* cam_off, co
   const int m = j + 1;
   const int nb = lz_orth_blocks(n);
   k_lz_dots<<<m, kLzThreads, 0, st>>>(n, V, w, h1);
-  k_lz_orth<<<nb, kLzOrthThreads, 0, st>>>(n, m, V, h1, w, part);
+  k_lz_orth<<<nb, kLzOrthThreads * kLzOrthWaves, 0, st>>>(n, m, V, h1, w, part);
   k_lz_dots<<<m, kLzThreads, 0, st>>>(n, V, w, h2);
-  k_lz_orth<<<nb, kLzOrthThreads, 0, st>>>(n, m, V, h2, w, part);
+  k_lz_orth<<<nb, kLzOrthThreads * kLzOrthWaves, 0, st>>>(n, m, V, h2, w, part);
   k_lz_next<<<1, 1024, 0, st>>>(n, nb, part, h1, h2, j, w, V + (int64_t)m * n, alpha, beta);
   return hipGetLastError();
 }
