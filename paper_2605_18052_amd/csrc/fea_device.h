@@ -44,20 +44,6 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
   return (s0 + s1) + (s2 + s3);
 }
 
-__device__ __forceinline__ double shfl_xor_f64(double v, int mask) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int src = (__lane_id() ^ mask) << 2;
-  return __hiloint2double(__builtin_amdgcn_ds_bpermute(src, hi), __builtin_amdgcn_ds_bpermute(src, lo));
-}
-
-// Sum of v over all 64 lanes in fp64 (butterfly, fixed order, every lane
-// receives the same bits).
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_f64(v, m);
-  return v;
-}
-
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
@@ -69,25 +55,6 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
   return __hiloint2double(hi, lo);
-}
-
-// Wave sums of n fp64 values at once, every lane receiving the results.
-// Each DPP stage is applied to all n values before the next, so the n
-// reductions overlap instead of waiting on each other; the fixed order makes
-// the sums reproducible.
-template <int NV>
-__device__ __forceinline__ void wave_sum_f64_multi(double (&v)[NV]) {
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0xB1>(v[k]);  // quad_perm [1,0,3,2]
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0x4E>(v[k]);  // quad_perm [2,3,0,1]
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0x141>(v[k]);  // row_half_mirror
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] += dpp_f64<0x140>(v[k]);  // row_mirror
-#pragma unroll
-  for (int k = 0; k < NV; ++k)
-    v[k] = (readlane_f64(v[k], 0) + readlane_f64(v[k], 16)) + (readlane_f64(v[k], 32) + readlane_f64(v[k], 48));
 }
 
 // l <-> l^32 exchange of two fp64 values and their sum: lanes < 32 return
@@ -111,36 +78,78 @@ __device__ __forceinline__ double swap16_add(double x, double y) {
 }
 
 // Wave sums of up to 16 fp64 values, every lane receiving the results, as a
-// reduce-scatter: each stage pairs the lanes across one bit of the lane
-// index and halves the values a lane carries (a lane keeps the half its
-// side owns, adding the partner's copy), so 16 sums cost about the
-// exchanges of two single butterflies.  Stages: l <-> l^32, neighbouring
-// rows, the row mirror (p <-> 15 - p), the half-row mirror (q <-> 7 - q),
-// then a butterfly inside each quad; sum k ends in the quad at lane
-// 32 (k>>3) + 16 ((k>>2)&1) + 8 ((k>>1)&1) + 4 (k&1) and is read from there.
-// The order of the additions is fixed, so the sums are reproducible.
+// reduce-scatter over S slots (S the power of two >= NV, the values padded
+// with zeros).  Six stages pair the lanes across one bit of the lane index
+// each: l <-> l^32 (v_permlane32_swap), neighbouring rows of 16
+// (v_permlane16_swap), the row mirror (p <-> 15 - p), the half-row mirror
+// (q <-> 7 - q), then the two pairings inside a quad.  While a lane carries
+// more than one value a stage halves them -- the lane keeps the half its
+// side owns and adds the partner's copy -- and after that every stage is a
+// plain butterfly; so 16 sums cost about the exchanges of two single ones.
+// With S = 2^L, sum k ends in the lanes whose bits 5, 4, 3, 2 (the first L
+// of them) spell k from its top bit down, and is read from there.  The
+// order of the additions is fixed, so the sums are reproducible and every
+// lane receives the same bits.
 template <int NV>
 __device__ __forceinline__ void wave_sum_f64_scatter(double (&v)[NV]) {
-  static_assert(NV <= 16, "at most 16 values");
-  double a[16];
+  static_assert(NV >= 1 && NV <= 16, "1 to 16 values");
+  constexpr int S = NV <= 1 ? 1 : NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : 16;
+  constexpr int L = S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : S == 8 ? 3 : 4;
+  double x[S];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) a[k] = k < NV ? v[k] : 0.0;
-  double b[8], c[4], d[2];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) b[k] = swap32_add(a[k], a[k + 8]);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) c[k] = swap16_add(b[k], b[k + 4]);
+  for (int k = 0; k < S; ++k) x[k] = k < NV ? v[k] : 0.0;
   const int lane = __lane_id();
-  const bool upper8 = (lane & 8) != 0, upper4 = (lane & 4) != 0;
+  // stage 1: l <-> l^32
+  if constexpr (S >= 2) {
 #pragma unroll
-  for (int k = 0; k < 2; ++k)
-    d[k] = (upper8 ? c[k + 2] : c[k]) + dpp_f64<0x140>(upper8 ? c[k] : c[k + 2]);  // row_mirror
-  double e = (upper4 ? d[1] : d[0]) + dpp_f64<0x141>(upper4 ? d[0] : d[1]);     // row_half_mirror
-  e += dpp_f64<0x4E>(e);  // quad_perm [2,3,0,1]
-  e += dpp_f64<0xB1>(e);  // quad_perm [1,0,3,2]
+    for (int k = 0; k < S / 2; ++k) x[k] = swap32_add(x[k], x[k + S / 2]);
+  } else {
+    x[0] = swap32_add(x[0], x[0]);
+  }
+  // stage 2: neighbouring rows
+  if constexpr (S >= 4) {
 #pragma unroll
-  for (int k = 0; k < NV; ++k)
-    v[k] = readlane_f64(e, 32 * (k >> 3) + 16 * ((k >> 2) & 1) + 8 * ((k >> 1) & 1) + 4 * (k & 1));
+    for (int k = 0; k < S / 4; ++k) x[k] = swap16_add(x[k], x[k + S / 4]);
+  } else {
+    x[0] = swap16_add(x[0], x[0]);
+  }
+  // stage 3: row mirror
+  if constexpr (S >= 8) {
+    const bool up = (lane & 8) != 0;
+#pragma unroll
+    for (int k = 0; k < S / 8; ++k) {
+      const double keep = up ? x[k + S / 8] : x[k], send = up ? x[k] : x[k + S / 8];
+      x[k] = keep + dpp_f64<0x140>(send);
+    }
+  } else {
+    x[0] += dpp_f64<0x140>(x[0]);
+  }
+  // stage 4: half-row mirror
+  if constexpr (S >= 16) {
+    const bool up = (lane & 4) != 0;
+    const double keep = up ? x[1] : x[0], send = up ? x[0] : x[1];
+    x[0] = keep + dpp_f64<0x141>(send);
+  } else {
+    x[0] += dpp_f64<0x141>(x[0]);
+  }
+  x[0] += dpp_f64<0x4E>(x[0]);  // quad_perm [2,3,0,1]
+  x[0] += dpp_f64<0xB1>(x[0]);  // quad_perm [1,0,3,2]
+  constexpr int kBit[4] = {32, 16, 8, 4};
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    int src = 0;
+#pragma unroll
+    for (int t = 0; t < L; ++t) src += ((k >> (L - 1 - t)) & 1) ? kBit[t] : 0;
+    v[k] = readlane_f64(x[0], src);
+  }
+}
+
+// Sum of v over all 64 lanes in fp64 (fixed order, every lane receives the
+// same bits).
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  double a[1] = {v};
+  wave_sum_f64_scatter<1>(a);
+  return a[0];
 }
 
 __device__ __forceinline__ double readfirstlane_f64(double v) {

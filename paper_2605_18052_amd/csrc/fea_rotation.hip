@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kRaThreads) void k_ra_apply(int n_cams, const int32
       for (int a = 0; a < 3; ++a) acc[a] -= R[a] * r[0] + R[3 + a] * r[1] + R[6 + a] * r[2];
     }
   }
-  wave_sum_f64_multi(acc);
+  wave_sum_f64_scatter(acc);
   if (lane != 0) return;
   const double s = scale ? *scale : 1.0;
   const double cw[3] = {c_in[3 * w], c_in[3 * w + 1], c_in[3 * w + 2]};
@@ -132,6 +132,15 @@ __global__ __launch_bounds__(kRaThreads) void k_ra_step(int n_cams, int64_t n_pa
     ctr->b2t[p ^ 1] = b2t;
   }
   if (w >= n_cams) return;
+  // this camera's parameters and optimiser state (lanes 0..5), loaded
+  // before the pair loop so that they arrive meanwhile
+  const int64_t idx = 6 * (int64_t)w + (lane < 6 ? lane : 0);
+  double a_cur[6], m_old = 0.0, v_old = 0.0;
+  for (int k = 0; k < 6; ++k) a_cur[k] = a_in[6 * (int64_t)w + k];
+  if (lane < 6) {
+    m_old = m[idx];
+    v_old = v[idx];
+  }
   const double inv_np = 1.0 / (double)n_pairs;
   double G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int e = cam_off[w] + lane; e < cam_off[w + 1]; e += 64) {
@@ -155,19 +164,21 @@ __global__ __launch_bounds__(kRaThreads) void k_ra_step(int n_cams, int64_t n_pa
         for (int b = 0; b < 3; ++b) G[3 * a + b] += h * (R[a] * Rj[b] + R[3 + a] * Rj[3 + b] + R[6 + a] * Rj[6 + b]);
     }
   }
-  wave_sum_f64_multi(G);
+  wave_sum_f64_scatter(G);
   if (lane >= 6) return;
   double ga[6];
-  rot6d_vjp(a_in + 6 * (int64_t)w, G, ga);
-  double gk = ga[0];
+  rot6d_vjp(a_cur, G, ga);
+  double gk = ga[0], ak = a_cur[0];
   for (int k = 1; k < 6; ++k)
-    if (lane == k) gk = ga[k];
-  const int64_t idx = 6 * (int64_t)w + lane;
-  const double mk = beta1 * m[idx] + (1.0 - beta1) * gk;
-  const double vk = beta2 * v[idx] + (1.0 - beta2) * gk * gk;
+    if (lane == k) {
+      gk = ga[k];
+      ak = a_cur[k];
+    }
+  const double mk = beta1 * m_old + (1.0 - beta1) * gk;
+  const double vk = beta2 * v_old + (1.0 - beta2) * gk * gk;
   m[idx] = mk;
   v[idx] = vk;
-  a_out[idx] = a_in[idx] - lr * (mk / (1.0 - b1t)) / (sqrt(vk / (1.0 - b2t)) + eps);
+  a_out[idx] = ak - lr * (mk / (1.0 - b1t)) / (sqrt(vk / (1.0 - b2t)) + eps);
 }
 
 // Mean geodesic distance over the pairs (argument clamped to [-1, 1]).

@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "fea_device.h"
 #include "fea_trans.h"
 
 namespace fea {
@@ -316,6 +317,15 @@ __global__ __launch_bounds__(kTaThreads) void k_ta_step(int runs, int n_cams, in
   const double inv_np = 1.0 / (double)n_pairs;
   double g0 = 0.0, g1 = 0.0, g2 = 0.0;
   const double oc0 = o[3 * c], oc1 = o[3 * c + 1], oc2 = o[3 * c + 2];
+  // the optimiser state of this camera's coordinate (lanes 0..2), loaded
+  // before the pair loop so that it arrives meanwhile
+  const int64_t a = base + 3 * c + (lane < 3 ? lane : 0);
+  double m_old = 0.0, v_old = 0.0, o_old = 0.0;
+  if (lane < 3) {
+    m_old = m[a];
+    v_old = v[a];
+    o_old = o_in[a];
+  }
   for (int e = cam_off[c] + lane; e < cam_off[c + 1]; e += 64) {
     // the entry and its other camera load side by side (no pair lookup)
     const int ent = cam_ent[e], oc = ent_other[e];
@@ -336,20 +346,16 @@ __global__ __launch_bounds__(kTaThreads) void k_ta_step(int runs, int n_cams, in
     g1 += (s1 - n1 * ns) * sd;
     g2 += (s2 - n2 * ns) * sd;
   }
-  for (int k = 32; k > 0; k >>= 1) {
-    g0 += __shfl_xor(g0, k);
-    g1 += __shfl_xor(g1, k);
-    g2 += __shfl_xor(g2, k);
-  }
+  double g[3] = {g0, g1, g2};
+  wave_sum_f64_scatter(g);
   if (lane < 3) {
-    const double gk = lane == 0 ? g0 : (lane == 1 ? g1 : g2);
-    const int64_t a = base + 3 * c + lane;
-    const double mk = beta1 * m[a] + (1.0 - beta1) * gk;
-    const double vk = beta2 * v[a] + (1.0 - beta2) * gk * gk;
+    const double gk = lane == 0 ? g[0] : (lane == 1 ? g[1] : g[2]);
+    const double mk = beta1 * m_old + (1.0 - beta1) * gk;
+    const double vk = beta2 * v_old + (1.0 - beta2) * gk * gk;
     m[a] = mk;
     v[a] = vk;
     const double mh = mk / (1.0 - b1t), vh = vk / (1.0 - b2t);
-    o_out[a] = o_in[a] - lr * mh / (sqrt(vh) + eps);
+    o_out[a] = o_old - lr * mh / (sqrt(vh) + eps);
   }
 }
 
