@@ -34,6 +34,10 @@ def _scenes():
         "multi_item": synth.sphere_scene(n_cams=4, n_pts=13000, p_det=1.0, sigma=1.0,
                                          outlier_frac=0.15, seed=21, name="multi_item"),
         "tiny_focals": synth.tiny_scene(n_cams=6, n_pts=70, seed=5, sigma=1.0, outlier_frac=0.2),
+        # every camera in 89 pairs: more than one entry per lane of the
+        # camera's wavefront, so the camera pass takes a second turn
+        "dense90": synth.sphere_scene(n_cams=90, n_pts=150, p_det=1.0, sigma=0.5, outlier_frac=0.1, seed=23,
+                                      name="dense90"),
     }
 
 
@@ -175,11 +179,13 @@ def _parity(sc, R_snap, t_snap, f_snap, R, t, f, tau_px, gauge=0, **opt):
 
 
 @pytest.mark.parametrize("name", list(SCENES))
-def test_residual_grad_parity_no_filter(name):
+@pytest.mark.parametrize("inner_loop", [0, 1])
+def test_residual_grad_parity_no_filter(name, inner_loop):
     sc = SCENES[name]
     R, t, f = _perturbed(sc)
     (l, gR, gt, gf), (lr, gRr, gtr, gfr) = _parity(sc, sc.R_init, sc.t_init, sc.f_init,
-                                                   R, t, f, math.inf)
+                                                   R, t, f, math.inf, inner_loop=inner_loop,
+                                                   tile_matches=8192 if inner_loop else 0)
     assert abs(l - lr) <= 1e-5 * abs(lr)
     for a, b in ((gR, gRr), (gt, gtr), (gf[:, None], gfr[:, None])):
         ok, worst = per_camera_close(a, b)
