@@ -283,7 +283,7 @@ hipError_t build_items(fea_ctx* c) {
   if ((e = dalloc(c->scene_loss, (size_t)std::max(c->S, 1) * sizeof(double))) != hipSuccess) return e;
   if ((e = upload(c, c->pair_item_off, c->h_pair_item_off.data(), c->P + 1)) != hipSuccess) return e;
   if ((e = upload(c, c->d_cam_ent, c->h_cam_ent4.data(), c->h_cam_ent4.size())) != hipSuccess) return e;
-  if ((e = dalloc(c->qpart, std::max<int64_t>(c->n_items, 1) * 45 * sizeof(double))) != hipSuccess) return e;
+  if ((e = dalloc(c->qpart, std::max<int64_t>(c->n_items, 1) * 36 * sizeof(double))) != hipSuccess) return e;
   if ((e = dalloc(c->part, std::max<int64_t>(c->n_items, 1) * fea::kPartStride * sizeof(double))) != hipSuccess)
     return e;
   if ((e = dalloc(c->item_keep, std::max<int64_t>(c->n_items, 1) * sizeof(int32_t))) != hipSuccess) return e;

@@ -168,7 +168,7 @@ struct fea_ctx {
   fea::DBuf ptab;  // double [P * kPairRow], the pose table
   bool ptab_current = false;  // the pose table's F is that of the current poses
   fea::DBuf stab;  // double [P * 40]: per-pair rows for the learned features
-  fea::DBuf qpart;           // double [n_items * 45]: per-item sums of c w w^T (quadratic form)
+  fea::DBuf qpart;           // double [n_items * 36]: per-item sums of c P2_s P1_t (quadratic form)
   fea::DBuf qW;              // double [P * 45]: W_n of every pair for the round
   fea::DBuf qmask;           // uint8 [full layout]: retained (the quadratic form keeps the full layout)
   fea::DBuf a6, tp, logf, m_a6, v_a6, m_t, v_t, m_f, v_f;

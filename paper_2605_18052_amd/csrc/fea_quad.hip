@@ -5,12 +5,16 @@
 //
 // Once per round, k_quad_build streams the retained matches of each work item
 // (the same 16 bytes per match as the per-match kernel) and accumulates, per
-// lane in fp64, the 45 distinct entries of sum c w w^T with
-// w = vec(p2 p1^T) in centred pixel coordinates and c the round's IRLS weight
-// (times the learned weight on learned scenes), one wavefront per work item.
-// The 45 sums are reduced over the wave (DPP, then LDS) into one fp64
-// partial per item;
-// k_quad_reduce adds a pair's item partials in item order into W_n.
+// lane in fp64, sum c w w^T with w = vec(p2 p1^T) in centred pixel
+// coordinates and c the round's IRLS weight (times the learned weight on
+// learned scenes), one wavefront per work item.  With p = (u, v, 1) the
+// entry of w w^T at (3a + b, 3a' + b') is (p2_a p2_a') (p1_b p1_b'), and each
+// factor takes one of only 6 values (u^2, uv, u, v^2, v, 1), so the kernel
+// sums the 6 x 6 products c P2_s P1_t -- 36 multiply-adds per match
+// instead of the 45 of the form's distinct entries plus the 18 products
+// that build c w.  The 36 sums are reduced over the wave (DPP, then LDS)
+// into one fp64 partial per item; k_quad_reduce adds a pair's item partials
+// in item order and spreads the 36 sums over W_n's 45 entries.
 //
 // Every step, the camera kernel evaluates dL/dF = 2 W_n f and the loss
 // f^T W_n f of each incident pair at the current poses, so a step is one
@@ -26,7 +30,29 @@ namespace fea {
 namespace {
 
 constexpr int kQuad = 45;  // distinct entries of a symmetric 9x9 matrix
+constexpr int kMono = 36;  // products P2_s P1_t summed per match (6 x 6)
 constexpr int kQuadThreads = 256;
+
+// Index (0..5) of the product x_a x_b, a <= b, of a 3-vector's entries.
+__host__ __device__ constexpr int sym3(int a, int b) { return a == 0 ? b : (a == 1 ? 2 + b : 5); }
+
+// For entry k of the form's upper triangle (row-major: (0,0), (0,1), ...,
+// (0,8), (1,1), ...), the index 6 s + t of its sum: entry (i, j) with
+// i = 3a + b, j = 3a' + b' is P2_{sym(a, a')} P1_{sym(b, b')}.
+struct MonoTable {
+  int of[kQuad];
+  constexpr MonoTable() : of() {
+    int k = 0;
+    for (int i = 0; i < 9; ++i)
+      for (int j = i; j < 9; ++j, ++k) {
+        const int a = i / 3, b = i % 3, a2 = j / 3, b2 = j % 3;
+        const int s = a <= a2 ? sym3(a, a2) : sym3(a2, a);
+        const int t = b <= b2 ? sym3(b, b2) : sym3(b2, b);
+        of[k] = 6 * s + t;
+      }
+  }
+};
+__constant__ constexpr MonoTable kMonoOf{};
 
 __device__ __forceinline__ float v4q(const float4& q, int e) {
   return e == 0 ? q.x : (e == 1 ? q.y : (e == 2 ? q.z : q.w));
@@ -47,7 +73,7 @@ __device__ __forceinline__ unsigned short v4w(const ushort4& q, int e) {
 // branch-free: a dropped match gets c' = 0 and adds exactly zero.  The 45
 // per-lane sums are reduced over each group of 4 lanes with DPP, then the 16
 // group sums are transposed through LDS and added in group order by lanes
-// 0..44, which store the item's partial coalesced.  The next 16-byte
+// 0..35, which store the item's partial coalesced.  The next 16-byte
 // vectors are loaded before the current ones are used.
 constexpr int kBuildItems = kQuadThreads / kWave;
 constexpr int kBuildGroups = kWave / 4;
@@ -59,7 +85,7 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
     const ushort4* __restrict__ Wl, uchar4* __restrict__ mask, double delta, double* __restrict__ qpart,
     int32_t* __restrict__ keep, double* __restrict__ wkept, const int32_t* __restrict__ pair_scene,
     const int32_t* __restrict__ scene_done) {
-  __shared__ double s_t[kBuildItems][kBuildGroups][kQuad + 1];
+  __shared__ double s_t[kBuildItems][kBuildGroups][kMono + 1];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const int item = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kBuildItems + wid);
@@ -80,9 +106,9 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
   const double tau = row[kRowTau];
   const bool learned = WEIGHTED && row[kRowMode] != 0.0;
 
-  double acc[kQuad];
+  double acc[kMono];
 #pragma unroll
-  for (int k = 0; k < kQuad; ++k) acc[k] = 0.0;
+  for (int k = 0; k < kMono; ++k) acc[k] = 0.0;
   double wsum = 0.0;
   int kept = 0;
   int v = lane;
@@ -130,40 +156,34 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
         cw = hold ? cw * wl : 0.0;
         wsum += hold ? wl : 0.0;
       }
-      const double p1[3] = {x1 - cxi, y1 - cyi, 1.0};
-      const double p2[3] = {x2 - cxj, y2 - cyj, 1.0};
-      double w[9];
+      const double u1 = x1 - cxi, v1 = y1 - cyi, u2 = x2 - cxj, v2 = y2 - cyj;
+      // sym3 order: u^2, uv, u, v^2, v, 1
+      const double P1[6] = {u1 * u1, u1 * v1, u1, v1 * v1, v1, 1.0};
+      const double cP2[6] = {cw * (u2 * u2), cw * (u2 * v2), cw * u2, cw * (v2 * v2), cw * v2, cw};
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+      for (int s2 = 0; s2 < 6; ++s2)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) w[3 * r + q] = p2[r] * p1[q];
-      int k = 0;
-#pragma unroll
-      for (int r = 0; r < 9; ++r) {
-        const double cr = cw * w[r];
-#pragma unroll
-        for (int q = r; q < 9; ++q, ++k) acc[k] = fma(cr, w[q], acc[k]);
-      }
+        for (int t = 0; t < 6; ++t) acc[6 * s2 + t] = fma(cP2[s2], P1[t], acc[6 * s2 + t]);
     }
     mask[v0 + v] = make_uchar4(out[0], out[1], out[2], out[3]);  // a dropped match stays dropped
   }
   // groups of 4 lanes, then the 16 group sums through LDS in group order
 #pragma unroll
-  for (int k = 0; k < kQuad; ++k) acc[k] += dpp_f64<0xB1>(acc[k]);  // quad_perm [1,0,3,2]
+  for (int k = 0; k < kMono; ++k) acc[k] += dpp_f64<0xB1>(acc[k]);  // quad_perm [1,0,3,2]
 #pragma unroll
-  for (int k = 0; k < kQuad; ++k) acc[k] += dpp_f64<0x4E>(acc[k]);  // quad_perm [2,3,0,1]
+  for (int k = 0; k < kMono; ++k) acc[k] += dpp_f64<0x4E>(acc[k]);  // quad_perm [2,3,0,1]
   if ((lane & 3) == 0) {
 #pragma unroll
-    for (int k = 0; k < kQuad; ++k) s_t[wid][lane >> 2][k] = acc[k];
+    for (int k = 0; k < kMono; ++k) s_t[wid][lane >> 2][k] = acc[k];
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (lane < kQuad) {
+  if (lane < kMono) {
     double sum = 0.0;
 #pragma unroll
     for (int g = 0; g < kBuildGroups; ++g) sum += s_t[wid][g][lane];
-    qpart[(int64_t)item * kQuad + lane] = sum;
+    qpart[(int64_t)item * kMono + lane] = sum;
   }
   int kw = kept;
 #pragma unroll
@@ -188,7 +208,8 @@ __global__ void k_mask_slots(int64_t n, const unsigned char* __restrict__ mask, 
 }
 
 // W_n = (1/Z of the pair's scene) * the sum of the pair's item partials in
-// item order; 1/Z is the pose table's (learned scenes: 1/sum of weights).
+// item order, entry k taking sum kMonoOf.of[k]; 1/Z is the pose table's
+// (learned scenes: 1/sum of weights).
 __global__ __launch_bounds__(kQuadThreads) void k_quad_reduce(int32_t P, const int32_t* __restrict__ pair_item_off,
                                                               const double* __restrict__ ptab,
                                                               const double* __restrict__ qpart,
@@ -201,8 +222,9 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_reduce(int32_t P, const i
   if (scene_done != nullptr && scene_done[pair_scene[n]] != 0) return;  // keeps its last round's form
   const double* row = ptab + (int64_t)n * kPairRow;
   const double inv_z = row[kRowMode] != 0.0 ? row[kRowInvZw] : row[kRowInvZ];
+  const int mk = kMonoOf.of[k];
   double s = 0.0;
-  for (int it = pair_item_off[n]; it < pair_item_off[n + 1]; ++it) s += qpart[(int64_t)it * kQuad + k];
+  for (int it = pair_item_off[n]; it < pair_item_off[n + 1]; ++it) s += qpart[(int64_t)it * kMono + mk];
   qW[t] = inv_z * s;
 }
 
