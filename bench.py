@@ -67,11 +67,11 @@ BATCH_CONVERGE_DEG = 0.01
 KERNEL_SOURCES = ("paper_2605_18052_amd/csrc/fea_resgrad.hip", "paper_2605_18052_amd/csrc/fea_device.h",
                   "paper_2605_18052_amd/csrc/fea_ctx.h")
 PMC_TRAFFIC = {
-    "sources_sha256": "e4c30ec566c9117e4b51dff9a23671744848736c9e5769e0650b9c7d7560e01e",
+    "sources_sha256": "ed75a1cb2d260f19f3d80b00e1a4fbc2cb55cb4ea110737b456cd740ea289209",
     # retained matches per launch -> "matches x threads" -> fetched + written bytes
     "bytes_per_launch": {
         87275962: {  # traj3000_m100M, round 0
-            "2048x256": 1448071858, "1024x256": 1484856328,
+            "2048x256": 1448072246, "1024x256": 1484853562,
         },
     },
 }
