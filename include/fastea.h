@@ -107,7 +107,11 @@ typedef struct {
                               step), 0 one launch per step (0: on this
                               device the wait between steps costs more
                               than a launch) */
-  int32_t reserved[1];     /* must be zero */
+  int32_t wait_limit_us;   /* bound of one device-wide wait between the
+                              steps of a persistent launch, microseconds
+                              (0: 500,000); a wait that runs past it ends
+                              the launch, and the next round boundary
+                              reports FEA_EDEVICE (0) */
   double converge_deg;     /* per-scene early exit (0 = off, default): at the
                               start of a round whose threshold equals the
                               previous round's (the schedule at its floor), a

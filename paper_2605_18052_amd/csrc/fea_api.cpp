@@ -169,7 +169,7 @@ bool options_valid(const fea_options* o, std::string* why) {
   if (o->tile_persistent == 1 && o->tile_matches != 1024 && o->tile_matches != 2048 && o->tile_matches != 4096)
     return bad("tile_persistent = 1 needs tile_matches 1024, 2048 or 4096");
   if (o->persistent_steps != 0 && o->persistent_steps != 1) return bad("persistent_steps must be 0 or 1");
-  if (o->reserved[0] != 0) return bad("reserved option fields must be zero");
+  if (o->wait_limit_us < 0) return bad("wait_limit_us must be >= 0");
   if (!(o->converge_deg >= 0) || !std::isfinite(o->converge_deg)) return bad("converge_deg must be finite and >= 0");
   return true;
 }
@@ -1124,7 +1124,7 @@ fea_status fea_create(fea_ctx** out, int32_t device, const fea_options* opt, voi
   int clock_khz = 0;
   if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || clock_khz < 1)
     clock_khz = 100000;
-  c->wait_limit_ticks = (long long)clock_khz * 500;
+  c->wall_clock_khz = clock_khz;
   *out = c;
   return FEA_OK;
 }

@@ -882,7 +882,8 @@ hipError_t launch_quad_steps(fea_ctx* c, int n_steps, int blocks) {
   unsigned* bar = c->wait_state.as<unsigned>();
   int* err = reinterpret_cast<int*>(bar + 1);
   unsigned base = c->wait_base;
-  long long limit = c->wait_limit_ticks;
+  const long long limit_us = c->opt.wait_limit_us > 0 ? c->opt.wait_limit_us : 500000;
+  long long limit = limit_us * (long long)c->wall_clock_khz / 1000;
   void* args[] = {&a, &pb, &sc, &n_steps, &bar, &base, &limit, &err};
   const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_quad_steps), dim3((unsigned)blocks),
                                                   dim3(256), args, 0, c->stream);

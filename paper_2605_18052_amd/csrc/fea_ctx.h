@@ -93,7 +93,7 @@ struct fea_ctx {
   fea::DBuf wait_state;                   // uint32 [2]: arrival count of the device-wide waits, error flag
   unsigned wait_base = 0;                 // arrivals counted so far (the next launch's base)
   int last_quad_blocks = 0;               // workgroups of the last k_quad_steps launch
-  long long wait_limit_ticks = 0;         // bound of one device-wide wait in wall-clock ticks
+  int wall_clock_khz = 100000;            // rate of the device's wall clock (wall_clock64)
   std::vector<float> tune_ms;             // the autotuner's mean time per shape of kTiles (last tuning)
   hipStream_t stream = nullptr;
   bool own_stream = false;

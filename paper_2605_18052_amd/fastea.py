@@ -33,7 +33,7 @@ class fea_options(C.Structure):
                 ("tile_matches", C.c_int32), ("use_graphs", C.c_int32),
                 ("weight_mode", C.c_int32), ("inner_loop", C.c_int32),
                 ("tile_persistent", C.c_int32), ("persistent_steps", C.c_int32),
-                ("reserved", C.c_int32 * 1),
+                ("wait_limit_us", C.c_int32),
                 ("converge_deg", C.c_double)]
 
 

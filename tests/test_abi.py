@@ -92,6 +92,10 @@ def test_check_options_without_a_gpu(so):
     assert ok == fastea.FEA_OK and why == ""
     bad, why = fastea.check_options(fastea.default_options(tile_matches=3000))
     assert bad == fastea.FEA_EINVAL and "tile_matches" in why
+    for field, value in (("persistent_steps", 2), ("wait_limit_us", -1)):
+        bad, why = fastea.check_options(fastea.default_options(**{field: value}))
+        assert bad == fastea.FEA_EINVAL and field in why, (field, why)
+    assert fastea.check_options(fastea.default_options(persistent_steps=1, wait_limit_us=10))[0] == fastea.FEA_OK
     assert fastea.lib().fea_check_options(None, None, 0) == fastea.FEA_EINVAL
 
 

@@ -108,3 +108,25 @@ def test_persistent_steps_more_cameras_than_resident_waves():
     blocks = _both(run)
     print(f"persistent launch: {blocks} workgroups ({4 * blocks} wavefronts) for 3000 cameras", flush=True)
     assert 4 * blocks < 3000
+
+
+def test_a_wait_past_its_bound_ends_the_launch_and_is_reported():
+    """The device-wide wait between steps gives up after wait_limit_us: with
+    a bound of 1 us (a wait takes about 10 us) the workgroups leave the
+    launch early and set the flag, every wavefront exiting normally; the
+    next round boundary reports FEA_EDEVICE once, and the context goes on
+    with one launch per step."""
+    sc = synth.config1()
+    ctx = make_context(sc, inner_loop=1, persistent_steps=1, wait_limit_us=1)
+    ctx.init_poses(sc.R_init, sc.t_init)
+    ctx.begin_round(128.0)
+    ctx.step(20)
+    with pytest.raises(fastea.FeaError) as err:
+        ctx.begin_round(64.0)
+    assert err.value.status == fastea.FEA_EDEVICE and "wait" in str(err.value)
+    ctx.begin_round(64.0)  # reported once: the flag was cleared
+    ctx.step(20)
+    assert ctx.info()["quad_steps_blocks"] > 0  # the last persistent launch's size is kept
+    R, t, f = ctx.get_poses()
+    assert np.isfinite(R).all() and np.isfinite(t).all() and np.isfinite(f).all()
+    ctx.close()
