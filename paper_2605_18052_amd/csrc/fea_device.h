@@ -144,6 +144,70 @@ __device__ __forceinline__ void wave_sum_f64_scatter(double (&v)[NV]) {
   }
 }
 
+// The fp32 forms of the exchanges above, and the same reduce-scatter for up
+// to 16 fp32 values (one lane swap per exchange instead of two).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float swap32_add(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_add(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+template <int NV>
+__device__ __forceinline__ void wave_sum_f32_scatter(float (&v)[NV]) {
+  static_assert(NV >= 1 && NV <= 16, "1 to 16 values");
+  constexpr int S = NV <= 1 ? 1 : NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : 16;
+  constexpr int L = S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : S == 8 ? 3 : 4;
+  float x[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) x[k] = k < NV ? v[k] : 0.f;
+  const int lane = __lane_id();
+  if constexpr (S >= 2) {
+#pragma unroll
+    for (int k = 0; k < S / 2; ++k) x[k] = swap32_add(x[k], x[k + S / 2]);
+  } else {
+    x[0] = swap32_add(x[0], x[0]);
+  }
+  if constexpr (S >= 4) {
+#pragma unroll
+    for (int k = 0; k < S / 4; ++k) x[k] = swap16_add(x[k], x[k + S / 4]);
+  } else {
+    x[0] = swap16_add(x[0], x[0]);
+  }
+  if constexpr (S >= 8) {
+    const bool up = (lane & 8) != 0;
+#pragma unroll
+    for (int k = 0; k < S / 8; ++k) {
+      const float keep = up ? x[k + S / 8] : x[k], send = up ? x[k] : x[k + S / 8];
+      x[k] = keep + dpp_f32<0x140>(send);
+    }
+  } else {
+    x[0] += dpp_f32<0x140>(x[0]);
+  }
+  if constexpr (S >= 16) {
+    const bool up = (lane & 4) != 0;
+    const float keep = up ? x[1] : x[0], send = up ? x[0] : x[1];
+    x[0] = keep + dpp_f32<0x141>(send);
+  } else {
+    x[0] += dpp_f32<0x141>(x[0]);
+  }
+  x[0] += dpp_f32<0x4E>(x[0]);
+  x[0] += dpp_f32<0xB1>(x[0]);
+  constexpr int kBit[4] = {32, 16, 8, 4};
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    int src = 0;
+#pragma unroll
+    for (int t = 0; t < L; ++t) src += ((k >> (L - 1 - t)) & 1) ? kBit[t] : 0;
+    v[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[0]), src));
+  }
+}
+
 // Sum of v over all 64 lanes in fp64 (fixed order, every lane receives the
 // same bits).
 __device__ __forceinline__ double wave_sum_f64(double v) {

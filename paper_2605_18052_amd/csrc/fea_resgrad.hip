@@ -17,9 +17,9 @@
 // (the residual of an inlier is ~1e-3 of its terms, so fp32 would lose ~4
 // digits), weight c = 1/(Z max(|eps_hat|, delta)), then the contribution
 // 2 c eps p2 p1^T to dL/dF and c eps^2 to L accumulate per lane in fp32.
-// The 10 sums are reduced across each wave with DPP, across the waves in
-// LDS, and written as one fp64 partial per item -- no atomics, so the result
-// is deterministic.
+// The 10 sums are reduced across each wave (a reduce-scatter of lane swaps
+// and DPP), across the waves in LDS, and written as one fp64 partial per
+// item -- no atomics, so the result is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <hip/hip_ext.h>
@@ -195,10 +195,10 @@ __device__ __forceinline__ void resgrad_item(const ItemRegs<THREADS, STEPS, WEIG
     }
   }
   const int wid = tid >> 6, lane = tid & 63;
+  wave_sum_f32_scatter(acc);
+  if (lane == 0) {
 #pragma unroll
-  for (int k = 0; k < kPartStride; ++k) {
-    const float w = wave_sum_f32(acc[k]);
-    if (lane == 0) s_red[wid][k] = w;
+    for (int k = 0; k < kPartStride; ++k) s_red[wid][k] = acc[k];
   }
   __syncthreads();
   if (tid < kPartStride) {
