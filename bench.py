@@ -69,11 +69,11 @@ BATCH_CONVERGE_DEG = 0.01
 KERNEL_SOURCES = ("paper_2605_18052_amd/csrc/fea_resgrad.hip", "paper_2605_18052_amd/csrc/fea_device.h",
                   "paper_2605_18052_amd/csrc/fea_layout.h")
 PMC_TRAFFIC = {
-    "sources_sha256": "3186603211d4143530d7d0e193db9a0cfc7ad9fac0d88fde75bcf2130e20f87c",
+    "sources_sha256": "ae4ae9335ad5bcd2b9618202a94debe76a69ae78142e19155b69f6cba3e7c4e8",
     # retained matches per launch -> "matches x threads" -> fetched + written bytes
     "bytes_per_launch": {
         87275962: {  # traj3000_m100M, round 0
-            "2048x256": 1448072246, "1024x256": 1484853562,
+            "2048x256": 1448063047, "1024x256": 1484844646,
         },
     },
 }
