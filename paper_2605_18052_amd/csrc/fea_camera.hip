@@ -441,11 +441,13 @@ StepCtl step_ctl(fea_ctx* c) {
   return StepCtl{c->counters.as<StepCounters>(), c->pcur, c->opt.log_every, c->opt.max_log, c->logR.as<double>()};
 }
 
-// Round start on the device, one thread per camera (and per intrinsics
-// group): the snapshot history for the learned features (r-2 <- r-1 <- r
-// with `shift`; on the first round all three become the current poses), the
-// snapshot of the current poses and parameters, and with `zero` fresh Adam
-// moments.
+// Round start on the device, one thread per value (the N x 9 rotation
+// entries, N x 3 translations, N focal lengths, N x 6 rotation and N x 3
+// translation parameters, G log focal lengths), so that no thread walks a
+// camera's values one after another: the snapshot history for the learned
+// features (r-2 <- r-1 <- r with `shift`; on the first round all three
+// become the current poses), the snapshot of the current poses and
+// parameters, and with `zero` fresh Adam moments.
 __global__ __launch_bounds__(256) void k_round_start(
     int N, int G, int shift, int first, int zero, const double* __restrict__ R, const double* __restrict__ T,
     const double* __restrict__ F, const double* __restrict__ a6, const double* __restrict__ tp,
@@ -454,53 +456,73 @@ __global__ __launch_bounds__(256) void k_round_start(
     double* __restrict__ Th2, double* __restrict__ Fh2, double* __restrict__ a6h, double* __restrict__ tph,
     double* __restrict__ logfh, double* __restrict__ m_a6, double* __restrict__ v_a6, double* __restrict__ m_t,
     double* __restrict__ v_t, double* __restrict__ m_f, double* __restrict__ v_f) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < N) {
-    auto snap = [&](double* h0, double* h1, double* h2, const double* cur, int k) {
-      const double now = cur[k];
-      if (first) {
-        h1[k] = now;
-        h2[k] = now;
-      } else if (shift) {
-        h2[k] = h1[k];
-        h1[k] = h0[k];
-      }
-      h0[k] = now;
-    };
-    for (int k = 9 * c; k < 9 * c + 9; ++k) snap(Rh, Rh1, Rh2, R, k);
-    for (int k = 3 * c; k < 3 * c + 3; ++k) snap(Th, Th1, Th2, T, k);
-    snap(Fh, Fh1, Fh2, F, c);
-    for (int k = 6 * c; k < 6 * c + 6; ++k) {
-      a6h[k] = a6[k];
-      if (zero) m_a6[k] = v_a6[k] = 0.0;
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  auto snap = [&](double* h0, double* h1, double* h2, const double* cur, int64_t k) {
+    const double now = cur[k];
+    if (first) {
+      h1[k] = now;
+      h2[k] = now;
+    } else if (shift) {
+      h2[k] = h1[k];
+      h1[k] = h0[k];
     }
-    for (int k = 3 * c; k < 3 * c + 3; ++k) {
-      tph[k] = tp[k];
-      if (zero) m_t[k] = v_t[k] = 0.0;
-    }
+    h0[k] = now;
+  };
+  const int64_t n = N;
+  if (q < 9 * n) return snap(Rh, Rh1, Rh2, R, q);
+  q -= 9 * n;
+  if (q < 3 * n) return snap(Th, Th1, Th2, T, q);
+  q -= 3 * n;
+  if (q < n) return snap(Fh, Fh1, Fh2, F, q);
+  q -= n;
+  if (q < 6 * n) {
+    a6h[q] = a6[q];
+    if (zero) m_a6[q] = v_a6[q] = 0.0;
+    return;
   }
-  if (c < G) {
-    logfh[c] = logf[c];
-    if (zero) m_f[c] = v_f[c] = 0.0;
+  q -= 6 * n;
+  if (q < 3 * n) {
+    tph[q] = tp[q];
+    if (zero) m_t[q] = v_t[q] = 0.0;
+    return;
+  }
+  q -= 3 * n;
+  if (q < G) {
+    logfh[q] = logf[q];
+    if (zero) m_f[q] = v_f[q] = 0.0;
   }
 }
+constexpr int kRoundStartValues = 22;  // per camera: 9 + 3 + 1 + 6 + 3
+
+// Per-scene sums over a scene's contiguous items: 1,024 threads, each
+// adding the items tid, tid + 1024, ... in that order (four independent
+// loads per trip), then the wave sums and the 16 wave totals in wave order:
+// a fixed order, the same for a scene alone or in a batch.
+constexpr int kSceneSumThreads = 1024;
 
 // Loss of every scene: the sum of its items' loss partials (a scene's items
-// are contiguous, since its cameras are), one workgroup per scene, fixed
-// order.
-__global__ __launch_bounds__(256) void k_scene_loss(const int32_t* __restrict__ scene_item_off,
-                                                    const double* __restrict__ part, double* __restrict__ out) {
-  __shared__ double s_red[256 / kWave];
+// are contiguous, since its cameras are), one workgroup per scene.
+__global__ __launch_bounds__(kSceneSumThreads) void k_scene_loss(const int32_t* __restrict__ scene_item_off,
+                                                                 const double* __restrict__ part,
+                                                                 double* __restrict__ out) {
+  __shared__ double s_red[kSceneSumThreads / kWave];
+  constexpr int T = kSceneSumThreads;
   const int sc = blockIdx.x, tid = threadIdx.x;
+  const int e = scene_item_off[sc + 1];
   double L = 0.0;
-  for (int it = scene_item_off[sc] + tid; it < scene_item_off[sc + 1]; it += 256)
-    L += part[(int64_t)it * kPartStride + 9];
+  for (int it = scene_item_off[sc] + tid; it < e; it += 4 * T) {
+    double x[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = it + r * T < e ? part[(int64_t)(it + r * T) * kPartStride + 9] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) L += x[r];
+  }
   L = wave_sum_f64(L);
   if ((tid & 63) == 0) s_red[tid >> 6] = L;
   __syncthreads();
   if (tid == 0) {
     double t = 0.0;
-    for (int w = 0; w < 256 / kWave; ++w) t += s_red[w];
+    for (int w = 0; w < T / kWave; ++w) t += s_red[w];
     out[sc] = t;
   }
 }
@@ -607,28 +629,32 @@ __global__ void k_choose_mode(int S, int enabled, const int32_t* __restrict__ ok
 // (infinite stays infinite) and shifts the history of medians at the
 // snapshots r, r-1, r-2 (all three set at the first round), in fp64 and as
 // the fp32 copy the learned features read.
-__global__ __launch_bounds__(kTauThreads) void k_scene_tau(int S, const int32_t* __restrict__ scene_cam_off,
-                                                           const int32_t* __restrict__ scene_cams,
-                                                           const double* __restrict__ Fc, double tau_px, int first,
-                                                           double* __restrict__ fbar_hist, float* __restrict__ fbar,
-                                                           double* __restrict__ tau) {
+constexpr int kTauSortThreads = 1024;
+
+__global__ __launch_bounds__(kTauSortThreads) void k_scene_tau(int S, const int32_t* __restrict__ scene_cam_off,
+                                                               const int32_t* __restrict__ scene_cams,
+                                                               const double* __restrict__ Fc, double tau_px,
+                                                               int first, double* __restrict__ fbar_hist,
+                                                               float* __restrict__ fbar, double* __restrict__ tau) {
   __shared__ double v[kMaxSceneCams];
   const int s = blockIdx.x;
   const int b = scene_cam_off[s], n = scene_cam_off[s + 1] - b;
   int p2 = 1;
   while (p2 < n) p2 <<= 1;
-  for (int i = threadIdx.x; i < p2; i += kTauThreads) v[i] = i < n ? Fc[scene_cams[b + i]] : INFINITY;
+  for (int i = threadIdx.x; i < p2; i += kTauSortThreads) v[i] = i < n ? Fc[scene_cams[b + i]] : INFINITY;
   __syncthreads();
+  // stage (k, j) compares the p2 / 2 pairs (i, i + j), i with bit j clear:
+  // pair q's i is q with a zero bit inserted at bit j, so every thread
+  // takes one pair per stage up to 2,048 cameras
   for (int k = 2; k <= p2; k <<= 1)
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < p2; i += kTauThreads) {
-        const int l = i ^ j;
-        if (l > i) {
-          const double a = v[i], c = v[l];
-          if (((i & k) == 0) ? (a > c) : (a < c)) {
-            v[i] = c;
-            v[l] = a;
-          }
+      for (int q = threadIdx.x; q < (p2 >> 1); q += kTauSortThreads) {
+        const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+        const int l = i | j;
+        const double a = v[i], c = v[l];
+        if (((i & k) == 0) ? (a > c) : (a < c)) {
+          v[i] = c;
+          v[l] = a;
         }
       }
       __syncthreads();
@@ -724,43 +750,57 @@ __global__ __launch_bounds__(kConvThreads) void k_scene_loss_log(int S, const in
 
 // Per-scene normalisers of a quadratic-form round on the device (each
 // scene's items contiguous): Z_s = survivors (exact, int64) and, on learned
-// rounds, Z_w = sum of the survivors' learned weights (per-thread sums over
-// contiguous item chunks, then a fixed-order tree: deterministic).  Writes
+// rounds, Z_w = sum of the survivors' learned weights (in the fixed order of
+// the per-scene sums above: deterministic).  Writes
 // 1/Z and 1/Z_w as the pose table reads them and Z_s; k_total_z then puts
 // the total Z in zs[S].
-__global__ __launch_bounds__(kTauThreads) void k_scene_z(const int32_t* __restrict__ scene_item_off,
-                                                         const int32_t* __restrict__ keep,
-                                                         const double* __restrict__ wsum, int learned,
-                                                         int64_t* __restrict__ zs, float* __restrict__ inv_z,
-                                                         float* __restrict__ inv_zw,
-                                                         const int32_t* __restrict__ scene_done) {
-  __shared__ long long s_z[kTauThreads];
-  __shared__ double s_w[kTauThreads];
+__global__ __launch_bounds__(kSceneSumThreads) void k_scene_z(const int32_t* __restrict__ scene_item_off,
+                                                              const int32_t* __restrict__ keep,
+                                                              const double* __restrict__ wsum, int learned,
+                                                              int64_t* __restrict__ zs, float* __restrict__ inv_z,
+                                                              float* __restrict__ inv_zw,
+                                                              const int32_t* __restrict__ scene_done) {
+  __shared__ long long s_z[kSceneSumThreads / kWave];
+  __shared__ double s_w[kSceneSumThreads / kWave];
+  constexpr int T = kSceneSumThreads;
   const int s = blockIdx.x, t = threadIdx.x;
   if (scene_done != nullptr && scene_done[s] != 0) return;  // a converged scene keeps its counts
-  const int b = scene_item_off[s], e = scene_item_off[s + 1], n = e - b;
-  const int per = (n + kTauThreads - 1) / kTauThreads;
+  const int e = scene_item_off[s + 1];
   long long z = 0;
   double w = 0.0;
-  const int lo = b + t * per, hi = min(e, b + (t + 1) * per);
-  for (int it = lo; it < hi; ++it) {
-    z += keep[it];
-    if (learned) w += wsum[it];
-  }
-  s_z[t] = z;
-  s_w[t] = w;
-  __syncthreads();
-  for (int h = kTauThreads / 2; h > 0; h >>= 1) {
-    if (t < h) {
-      s_z[t] += s_z[t + h];
-      s_w[t] += s_w[t + h];
+  for (int it = scene_item_off[s] + t; it < e; it += 4 * T) {
+    int k[4];
+    double x[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool in = it + r * T < e;
+      k[r] = in ? keep[it + r * T] : 0;
+      x[r] = (learned && in) ? wsum[it + r * T] : 0.0;
     }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      z += k[r];
+      w += x[r];
+    }
   }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) z += __shfl_xor(z, m);
+  w = wave_sum_f64(w);
+  if ((t & 63) == 0) {
+    s_z[t >> 6] = z;
+    s_w[t >> 6] = w;
+  }
+  __syncthreads();
   if (t == 0) {
-    zs[s] = s_z[0];
-    inv_z[s] = s_z[0] > 0 ? (float)(1.0 / (double)s_z[0]) : 0.f;
-    if (learned) inv_zw[s] = s_w[0] > 0 ? (float)(1.0 / s_w[0]) : 0.f;
+    z = 0;
+    w = 0.0;
+    for (int q = 0; q < T / kWave; ++q) {
+      z += s_z[q];
+      w += s_w[q];
+    }
+    zs[s] = z;
+    inv_z[s] = z > 0 ? (float)(1.0 / (double)z) : 0.f;
+    if (learned) inv_zw[s] = w > 0 ? (float)(1.0 / w) : 0.f;
   }
 }
 
@@ -775,13 +815,13 @@ __global__ void k_total_z(int S, int64_t* __restrict__ zs) {
 
 hipError_t launch_scene_loss(fea_ctx* c, double* out) {
   if (c->S == 0) return hipSuccess;
-  k_scene_loss<<<(unsigned)c->S, 256, 0, c->stream>>>(c->d_scene_item_off.as<int32_t>(), c->part.as<double>(),
+  k_scene_loss<<<(unsigned)c->S, kSceneSumThreads, 0, c->stream>>>(c->d_scene_item_off.as<int32_t>(), c->part.as<double>(),
                                                       out ? out : c->scene_loss.as<double>());
   return hipGetLastError();
 }
 
 hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero) {
-  const int n = std::max(c->N, c->G);
+  const int64_t n = (int64_t)kRoundStartValues * c->N + c->G;
   if (n == 0) return hipSuccess;
   const int p = c->pcur;
   k_round_start<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
@@ -910,7 +950,7 @@ hipError_t launch_loss_sum(fea_ctx* c) {
 
 hipError_t launch_scene_tau(fea_ctx* c, double tau_px, bool first) {
   if (c->S == 0) return hipSuccess;
-  k_scene_tau<<<(unsigned)c->S, kTauThreads, 0, c->stream>>>(
+  k_scene_tau<<<(unsigned)c->S, kTauSortThreads, 0, c->stream>>>(
       c->S, c->d_scene_cam_off.as<int32_t>(), c->d_scene_cams.as<int32_t>(), c->Fc[c->pcur].as<double>(), tau_px,
       first ? 1 : 0, c->d_fbar_hist.as<double>(), c->d_fbar.as<float>(), c->d_tau.as<double>());
   return hipGetLastError();
@@ -975,7 +1015,7 @@ hipError_t launch_scene_loss_log(fea_ctx* c, int32_t round) {
 
 hipError_t launch_scene_z(fea_ctx* c) {
   if (c->S == 0) return hipSuccess;
-  k_scene_z<<<(unsigned)c->S, kTauThreads, 0, c->stream>>>(
+  k_scene_z<<<(unsigned)c->S, kSceneSumThreads, 0, c->stream>>>(
       c->d_scene_item_off.as<int32_t>(), c->item_keep.as<int32_t>(), c->item_wsum.as<double>(),
       c->learned_any ? 1 : 0, c->d_scene_z.as<int64_t>(), c->d_inv_z.as<float>(), c->d_inv_zw.as<float>(),
       c->d_scene_done.as<int32_t>());

@@ -77,27 +77,14 @@ __device__ __forceinline__ double swap16_add(double x, double y) {
   return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
 }
 
-// Wave sums of up to 16 fp64 values, every lane receiving the results, as a
-// reduce-scatter over S slots (S the power of two >= NV, the values padded
-// with zeros).  Six stages pair the lanes across one bit of the lane index
-// each: l <-> l^32 (v_permlane32_swap), neighbouring rows of 16
-// (v_permlane16_swap), the row mirror (p <-> 15 - p), the half-row mirror
-// (q <-> 7 - q), then the two pairings inside a quad.  While a lane carries
-// more than one value a stage halves them -- the lane keeps the half its
-// side owns and adds the partner's copy -- and after that every stage is a
-// plain butterfly; so 16 sums cost about the exchanges of two single ones.
-// With S = 2^L, sum k ends in the lanes whose bits 5, 4, 3, 2 (the first L
-// of them) spell k from its top bit down, and is read from there.  The
-// order of the additions is fixed, so the sums are reproducible and every
-// lane receives the same bits.
-template <int NV>
-__device__ __forceinline__ void wave_sum_f64_scatter(double (&v)[NV]) {
-  static_assert(NV >= 1 && NV <= 16, "1 to 16 values");
-  constexpr int S = NV <= 1 ? 1 : NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : 16;
-  constexpr int L = S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : S == 8 ? 3 : 4;
-  double x[S];
-#pragma unroll
-  for (int k = 0; k < S; ++k) x[k] = k < NV ? v[k] : 0.0;
+// The six stages of the fp64 reduce-scatter below over S = 2^L slots
+// (1 <= S <= 16), in place: on return x[0] of a lane holds the wave sum of
+// x[k], k the lane's bits 5, 4, 3, 2 (the first L of them) read from the
+// top bit down -- for S = 16, k = (lane >> 2) & 15; for S = 4,
+// k = (lane >> 4) & 3.
+template <int S>
+__device__ __forceinline__ void wave_scatter_stages_f64(double (&x)[S]) {
+  static_assert(S == 1 || S == 2 || S == 4 || S == 8 || S == 16, "a power of two up to 16");
   const int lane = __lane_id();
   // stage 1: l <-> l^32
   if constexpr (S >= 2) {
@@ -134,6 +121,30 @@ __device__ __forceinline__ void wave_sum_f64_scatter(double (&v)[NV]) {
   }
   x[0] += dpp_f64<0x4E>(x[0]);  // quad_perm [2,3,0,1]
   x[0] += dpp_f64<0xB1>(x[0]);  // quad_perm [1,0,3,2]
+}
+
+// Wave sums of up to 16 fp64 values, every lane receiving the results, as a
+// reduce-scatter over S slots (S the power of two >= NV, the values padded
+// with zeros).  Six stages pair the lanes across one bit of the lane index
+// each: l <-> l^32 (v_permlane32_swap), neighbouring rows of 16
+// (v_permlane16_swap), the row mirror (p <-> 15 - p), the half-row mirror
+// (q <-> 7 - q), then the two pairings inside a quad.  While a lane carries
+// more than one value a stage halves them -- the lane keeps the half its
+// side owns and adds the partner's copy -- and after that every stage is a
+// plain butterfly; so 16 sums cost about the exchanges of two single ones.
+// With S = 2^L, sum k ends in the lanes whose bits 5, 4, 3, 2 (the first L
+// of them) spell k from its top bit down, and is read from there.  The
+// order of the additions is fixed, so the sums are reproducible and every
+// lane receives the same bits.
+template <int NV>
+__device__ __forceinline__ void wave_sum_f64_scatter(double (&v)[NV]) {
+  static_assert(NV >= 1 && NV <= 16, "1 to 16 values");
+  constexpr int S = NV <= 1 ? 1 : NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : 16;
+  constexpr int L = S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : S == 8 ? 3 : 4;
+  double x[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) x[k] = k < NV ? v[k] : 0.0;
+  wave_scatter_stages_f64<S>(x);
   constexpr int kBit[4] = {32, 16, 8, 4};
 #pragma unroll
   for (int k = 0; k < NV; ++k) {

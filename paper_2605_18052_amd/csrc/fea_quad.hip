@@ -12,8 +12,8 @@
 // factor takes one of only 6 values (u^2, uv, u, v^2, v, 1), so the kernel
 // sums the 6 x 6 products c P2_s P1_t -- 36 multiply-adds per match
 // instead of the 45 of the form's distinct entries plus the 18 products
-// that build c w.  The 36 sums are reduced over the wave (DPP, then LDS)
-// into one fp64 partial per item; k_quad_reduce adds a pair's item partials
+// that build c w.  The 36 sums are reduced over the wave (lane swaps and
+// DPP) into one fp64 partial per item; k_quad_reduce adds a pair's item partials
 // in item order and spreads the 36 sums over W_n's 45 entries.
 //
 // Every step, the camera kernel evaluates dL/dF = 2 W_n f and the loss
@@ -54,14 +54,6 @@ struct MonoTable {
 };
 __constant__ constexpr MonoTable kMonoOf{};
 
-__device__ __forceinline__ float v4q(const float4& q, int e) {
-  return e == 0 ? q.x : (e == 1 ? q.y : (e == 2 ? q.z : q.w));
-}
-
-__device__ __forceinline__ unsigned short v4w(const ushort4& q, int e) {
-  return e == 0 ? q.x : (e == 1 ? q.y : (e == 2 ? q.z : q.w));
-}
-
 // One item of the round's pass per wavefront (kBuildItems items per
 // workgroup, no block-level synchronisation): the threshold test at the
 // snapshot (|eps_hat| < tau, strict) of the matches the mask still holds,
@@ -70,22 +62,21 @@ __device__ __forceinline__ unsigned short v4w(const ushort4& q, int e) {
 // survivors with c' = 1/max(|eps_hat|, delta) times the learned weight on
 // learned scenes -- the 1/Z normaliser, known only once every item has been
 // counted, is applied when the items are summed into W_n.  The test is
-// branch-free: a dropped match gets c' = 0 and adds exactly zero.  The 45
-// per-lane sums are reduced over each group of 4 lanes with DPP, then the 16
-// group sums are transposed through LDS and added in group order by lanes
-// 0..35, which store the item's partial coalesced.  The next 16-byte
-// vectors are loaded before the current ones are used.
+// branch-free: a dropped match gets c' = 0 and adds exactly zero.  Each lane
+// takes one match per trip, so only that match's products are live next to
+// the 36 per-lane sums (occupancy 4); the 36 sums are reduced over the wave
+// by three reduce-scatters (16, 16 and 4 sums), stored straight from the
+// lanes that hold them.  The next match is loaded before the current one is
+// used.
 constexpr int kBuildItems = kQuadThreads / kWave;
-constexpr int kBuildGroups = kWave / 4;
 
 template <bool WEIGHTED>
 __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
-    int32_t n_items, const float4* __restrict__ X1, const float4* __restrict__ Y1, const float4* __restrict__ X2,
-    const float4* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ ptab,
-    const ushort4* __restrict__ Wl, uchar4* __restrict__ mask, double delta, double* __restrict__ qpart,
-    int32_t* __restrict__ keep, double* __restrict__ wkept, const int32_t* __restrict__ pair_scene,
-    const int32_t* __restrict__ scene_done) {
-  __shared__ double s_t[kBuildItems][kBuildGroups][kMono + 1];
+    int32_t n_items, const float* __restrict__ X1, const float* __restrict__ Y1, const float* __restrict__ X2,
+    const float* __restrict__ Y2, const int4* __restrict__ items, const double* __restrict__ ptab,
+    const unsigned short* __restrict__ Wl, unsigned char* __restrict__ mask, double delta,
+    double* __restrict__ qpart, int32_t* __restrict__ keep, double* __restrict__ wkept,
+    const int32_t* __restrict__ pair_scene, const int32_t* __restrict__ scene_done) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const int item = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kBuildItems + wid);
@@ -94,9 +85,11 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
   const int n = rec.x;
   // a converged scene keeps its mask, counts and sums from its last round
   if (scene_done != nullptr && scene_done[pair_scene[n]] != 0) return;
-  const int v0 = rec.y >> 2;
+  const int64_t s0 = rec.y;  // first slot of the item
   const int cnt = rec.z;
-  const int nvec = (cnt + kVec - 1) / kVec;
+  // every slot of the item's last 16-byte vector is visited, so the padding
+  // slots of a pair's run are written as dropped, as in the vector layout
+  const int nslot = (cnt + kVec - 1) / kVec * kVec;
   const double* row = ptab + (int64_t)n * kPairRow;
   double Fh[9];
 #pragma unroll
@@ -111,79 +104,93 @@ __global__ __launch_bounds__(kQuadThreads) void k_quad_build(
   for (int k = 0; k < kMono; ++k) acc[k] = 0.0;
   double wsum = 0.0;
   int kept = 0;
-  int v = lane;
-  float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a, d = a;
-  ushort4 wq = make_ushort4(0, 0, 0, 0);
-  uchar4 mq = make_uchar4(0, 0, 0, 0);
-  if (v < nvec) {
-    a = X1[v0 + v];
-    b = Y1[v0 + v];
-    c = X2[v0 + v];
-    d = Y2[v0 + v];
-    if (WEIGHTED) wq = Wl[v0 + v];
-    mq = mask[v0 + v];
+  // one match per lane per trip (consecutive lanes read consecutive words),
+  // so that only one match's products are live next to the 36 sums; the
+  // next trip's match is loaded before the current one is used
+  const float *__restrict__ x1p = X1 + s0, *__restrict__ y1p = Y1 + s0;
+  const float *__restrict__ x2p = X2 + s0, *__restrict__ y2p = Y2 + s0;
+  const unsigned short* __restrict__ wp = Wl + s0;
+  unsigned char* __restrict__ mp = mask + s0;
+  const unsigned ns = (unsigned)nslot;
+  unsigned j = lane;
+  float x1 = 0.f, y1 = 0.f, x2 = 0.f, y2 = 0.f;
+  unsigned short wq = 0;
+  unsigned char mq = 0;
+  if (j < ns) {
+    x1 = x1p[j];
+    y1 = y1p[j];
+    x2 = x2p[j];
+    y2 = y2p[j];
+    if (WEIGHTED) wq = wp[j];
+    mq = mp[j];
   }
-  for (; v < nvec; v += kWave) {
-    const float4 ca = a, cb = b, cc = c, cd = d;
-    const ushort4 cw4 = wq;
-    const uchar4 cm = mq;
-    const int vn = v + kWave;
-    if (vn < nvec) {
-      a = X1[v0 + vn];
-      b = Y1[v0 + vn];
-      c = X2[v0 + vn];
-      d = Y2[v0 + vn];
-      if (WEIGHTED) wq = Wl[v0 + vn];
-      mq = mask[v0 + vn];
+  for (; j < ns; j += kWave) {
+    const double dx1 = x1, dy1 = y1, dx2 = x2, dy2 = y2;
+    const unsigned short cwq = wq;
+    const bool was = mq != 0;
+    const unsigned jn = j + kWave;
+    if (jn < ns) {
+      x1 = x1p[jn];
+      y1 = y1p[jn];
+      x2 = x2p[jn];
+      y2 = y2p[jn];
+      if (WEIGHTED) wq = wp[jn];
+      mq = mp[jn];
     }
-    unsigned char out[kVec];
-#pragma unroll
-    for (int e = 0; e < kVec; ++e) {
-      const double x1 = v4q(ca, e), y1 = v4q(cb, e), x2 = v4q(cc, e), y2 = v4q(cd, e);
-      const double l0 = fma(Fh[0], x1, fma(Fh[1], y1, Fh[2]));
-      const double l1 = fma(Fh[3], x1, fma(Fh[4], y1, Fh[5]));
-      const double l2 = fma(Fh[6], x1, fma(Fh[7], y1, Fh[8]));
-      const double eph = fma(x2, l0, fma(y2, l1, l2));
-      const unsigned char was = e == 0 ? cm.x : (e == 1 ? cm.y : (e == 2 ? cm.z : cm.w));
-      const bool hold = was && v * kVec + e < cnt && fabs(eph) < tau;
-      out[e] = hold ? 1 : 0;
-      kept += hold ? 1 : 0;
-      double cw = hold ? 1.0 / fmax(fabs(eph), delta) : 0.0;
-      if (learned) {
-        // the network writes only the slots of real matches: the weight of a
-        // padding slot is never read into the arithmetic (0 * NaN is NaN)
-        const double wl = (double)(float)__builtin_bit_cast(_Float16, (unsigned short)v4w(cw4, e));
-        cw = hold ? cw * wl : 0.0;
-        wsum += hold ? wl : 0.0;
-      }
-      const double u1 = x1 - cxi, v1 = y1 - cyi, u2 = x2 - cxj, v2 = y2 - cyj;
-      // sym3 order: u^2, uv, u, v^2, v, 1
-      const double P1[6] = {u1 * u1, u1 * v1, u1, v1 * v1, v1, 1.0};
-      const double cP2[6] = {cw * (u2 * u2), cw * (u2 * v2), cw * u2, cw * (v2 * v2), cw * v2, cw};
-#pragma unroll
-      for (int s2 = 0; s2 < 6; ++s2)
-#pragma unroll
-        for (int t = 0; t < 6; ++t) acc[6 * s2 + t] = fma(cP2[s2], P1[t], acc[6 * s2 + t]);
+    const double l0 = fma(Fh[0], dx1, fma(Fh[1], dy1, Fh[2]));
+    const double l1 = fma(Fh[3], dx1, fma(Fh[4], dy1, Fh[5]));
+    const double l2 = fma(Fh[6], dx1, fma(Fh[7], dy1, Fh[8]));
+    const double eph = fma(dx2, l0, fma(dy2, l1, l2));
+    const bool hold = was && j < (unsigned)cnt && fabs(eph) < tau;
+    mp[j] = hold ? 1 : 0;  // a dropped match stays dropped
+    kept += hold ? 1 : 0;
+    // 1 / max(|eps_hat|, delta): the hardware reciprocal refined by two
+    // Newton steps r <- r + r (1 - x r), within an ulp of the quotient
+    const double x = fmax(fabs(eph), delta);
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    double cw = hold ? r : 0.0;
+    if (learned) {
+      // the network writes only the slots of real matches: the weight of a
+      // padding slot is never read into the arithmetic (0 * NaN is NaN)
+      const double wl = (double)(float)__builtin_bit_cast(_Float16, cwq);
+      cw = hold ? cw * wl : 0.0;
+      wsum += hold ? wl : 0.0;
     }
-    mask[v0 + v] = make_uchar4(out[0], out[1], out[2], out[3]);  // a dropped match stays dropped
+    const double u1 = dx1 - cxi, v1 = dy1 - cyi, u2 = dx2 - cxj, v2 = dy2 - cyj;
+    const double cu2 = cw * u2, cv2 = cw * v2;
+    // sym3 order: u^2, uv, u, v^2, v, 1
+    const double P1[6] = {u1 * u1, u1 * v1, u1, v1 * v1, v1, 1.0};
+    const double cP2[6] = {cu2 * u2, cu2 * v2, cu2, cv2 * v2, cv2, cw};
+#pragma unroll
+    for (int s2 = 0; s2 < 6; ++s2)
+#pragma unroll
+      for (int t = 0; t < 6; ++t) acc[6 * s2 + t] = fma(cP2[s2], P1[t], acc[6 * s2 + t]);
   }
-  // groups of 4 lanes, then the 16 group sums through LDS in group order
+  // the wave is the item: the 36 sums as reduce-scatters of 16, 16 and 4,
+  // each stored by the lanes that end up holding it
+  double* out = qpart + (int64_t)item * kMono;
+  {
+    double x[16];
 #pragma unroll
-  for (int k = 0; k < kMono; ++k) acc[k] += dpp_f64<0xB1>(acc[k]);  // quad_perm [1,0,3,2]
-#pragma unroll
-  for (int k = 0; k < kMono; ++k) acc[k] += dpp_f64<0x4E>(acc[k]);  // quad_perm [2,3,0,1]
-  if ((lane & 3) == 0) {
-#pragma unroll
-    for (int k = 0; k < kMono; ++k) s_t[wid][lane >> 2][k] = acc[k];
+    for (int k = 0; k < 16; ++k) x[k] = acc[k];
+    wave_scatter_stages_f64<16>(x);
+    if ((lane & 3) == 0) out[(lane >> 2) & 15] = x[0];
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (lane < kMono) {
-    double sum = 0.0;
+  {
+    double x[16];
 #pragma unroll
-    for (int g = 0; g < kBuildGroups; ++g) sum += s_t[wid][g][lane];
-    qpart[(int64_t)item * kMono + lane] = sum;
+    for (int k = 0; k < 16; ++k) x[k] = acc[16 + k];
+    wave_scatter_stages_f64<16>(x);
+    if ((lane & 3) == 0) out[16 + ((lane >> 2) & 15)] = x[0];
+  }
+  {
+    double x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = acc[32 + k];
+    wave_scatter_stages_f64<4>(x);
+    if ((lane & 15) == 0) out[32 + ((lane >> 4) & 3)] = x[0];
   }
   int kw = kept;
 #pragma unroll
@@ -239,8 +246,9 @@ hipError_t launch_quad_build(fea_ctx* c) {
   if (c->n_items == 0) return hipSuccess;
   const int b = c->cur;
 #define FEA_QUAD_BUILD_ARGS                                                                                 \
-  c->lay[b][0].as<float4>(), c->lay[b][1].as<float4>(), c->lay[b][2].as<float4>(), c->lay[b][3].as<float4>(), \
-      c->item_rec.as<int4>(), c->ptab.as<double>(), c->wlay.as<ushort4>(), c->qmask.as<uchar4>(), c->opt.delta,  \
+  c->lay[b][0].as<float>(), c->lay[b][1].as<float>(), c->lay[b][2].as<float>(), c->lay[b][3].as<float>(),     \
+      c->item_rec.as<int4>(), c->ptab.as<double>(), c->wlay.as<unsigned short>(), c->qmask.as<unsigned char>(),  \
+      c->opt.delta,                                                                                          \
       c->qpart.as<double>(), c->item_keep.as<int32_t>(), c->item_wsum.as<double>(),                          \
       c->d_pair_scene.as<int32_t>(), c->d_scene_done.as<int32_t>()
   const unsigned blocks = (unsigned)((c->n_items + kBuildItems - 1) / kBuildItems);
