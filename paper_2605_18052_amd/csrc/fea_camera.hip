@@ -172,6 +172,10 @@ __device__ __forceinline__ void camera_pass(const CamArgs& a, const PosePair& pp
   int4 en_next = make_int4(0, 0, 0, 0);
   if (e < e_end) en_next = cam_ent[e];
   const bool stopped = may_stop && scene_done[scene] != 0;
+  // the current rotation's Gram-Schmidt frame for the 6D gradient below,
+  // formed now so that its square roots and divisions overlap the entries'
+  // loads instead of following the wave sums
+  const Rot6dFrame frame = rot6d_frame(a_cur);
   if (stopped) {
     // a converged scene takes no step: its poses carry over to the next
     // parity unchanged (the rotation log still records them) and its
@@ -259,7 +263,7 @@ __device__ __forceinline__ void camera_pass(const CamArgs& a, const PosePair& pp
   // every update lane forms the 6D gradient (same instructions, no
   // divergence) and steps its own coordinate
   double ga[6];
-  rot6d_vjp(a_cur, gR, ga);
+  rot6d_vjp(frame, a_cur, gR, ga);
   double g_own, lr;
   if (lane < 6) {
     g_own = ga[0];

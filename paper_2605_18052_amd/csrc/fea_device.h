@@ -401,14 +401,34 @@ __device__ __forceinline__ void rot6d_forward(const double a[6], double R[9]) {
   R[8] = b1[0] * b2[1] - b1[1] * b2[0];
 }
 
-// Vector-Jacobian product of rot6d_forward: dL/da from dL/dR.
-__device__ __forceinline__ void rot6d_vjp(const double a[6], const double gR[9], double ga[6]) {
-  const double i1 = 1.0 / sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
-  const double b1[3] = {a[0] * i1, a[1] * i1, a[2] * i1};
-  const double d = b1[0] * a[3] + b1[1] * a[4] + b1[2] * a[5];
-  const double v[3] = {a[3] - d * b1[0], a[4] - d * b1[1], a[5] - d * b1[2]};
-  const double i2 = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-  const double b2[3] = {v[0] * i2, v[1] * i2, v[2] * i2};
+// The Gram-Schmidt frame of a 6D vector that the map above builds (b1, b2,
+// the projection d = b1.a2 and the inverse norms), which its vector-Jacobian
+// product reuses; a caller that knows a early can form it ahead of dL/dR.
+struct Rot6dFrame {
+  double b1[3], b2[3], d, i1, i2;
+};
+
+__device__ __forceinline__ Rot6dFrame rot6d_frame(const double a[6]) {
+  Rot6dFrame f;
+  f.i1 = 1.0 / sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  f.b1[0] = a[0] * f.i1;
+  f.b1[1] = a[1] * f.i1;
+  f.b1[2] = a[2] * f.i1;
+  f.d = f.b1[0] * a[3] + f.b1[1] * a[4] + f.b1[2] * a[5];
+  const double v[3] = {a[3] - f.d * f.b1[0], a[4] - f.d * f.b1[1], a[5] - f.d * f.b1[2]};
+  f.i2 = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  f.b2[0] = v[0] * f.i2;
+  f.b2[1] = v[1] * f.i2;
+  f.b2[2] = v[2] * f.i2;
+  return f;
+}
+
+// Vector-Jacobian product of rot6d_forward at a (frame f = rot6d_frame(a)):
+// dL/da from dL/dR.
+__device__ __forceinline__ void rot6d_vjp(const Rot6dFrame& f, const double a[6], const double gR[9],
+                                          double ga[6]) {
+  const double* b1 = f.b1;
+  const double* b2 = f.b2;
   // columns of gR
   double g1[3] = {gR[0], gR[3], gR[6]};
   double g2[3] = {gR[1], gR[4], gR[7]};
@@ -422,18 +442,23 @@ __device__ __forceinline__ void rot6d_vjp(const double a[6], const double gR[9],
   g2[2] += g3[0] * b1[1] - g3[1] * b1[0];
   // b2 = v/|v|
   const double p2 = b2[0] * g2[0] + b2[1] * g2[1] + b2[2] * g2[2];
-  const double gv[3] = {(g2[0] - p2 * b2[0]) * i2, (g2[1] - p2 * b2[1]) * i2, (g2[2] - p2 * b2[2]) * i2};
+  const double gv[3] = {(g2[0] - p2 * b2[0]) * f.i2, (g2[1] - p2 * b2[1]) * f.i2, (g2[2] - p2 * b2[2]) * f.i2};
   // v = a2 - (b1.a2) b1
   const double q = b1[0] * gv[0] + b1[1] * gv[1] + b1[2] * gv[2];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     ga[3 + k] = gv[k] - q * b1[k];
-    g1[k] += -d * gv[k] - q * a[3 + k];
+    g1[k] += -f.d * gv[k] - q * a[3 + k];
   }
   // b1 = a1/|a1|
   const double p1 = b1[0] * g1[0] + b1[1] * g1[1] + b1[2] * g1[2];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) ga[k] = (g1[k] - p1 * b1[k]) * i1;
+  for (int k = 0; k < 3; ++k) ga[k] = (g1[k] - p1 * b1[k]) * f.i1;
+}
+
+// The same with the frame formed here.
+__device__ __forceinline__ void rot6d_vjp(const double a[6], const double gR[9], double ga[6]) {
+  rot6d_vjp(rot6d_frame(a), a, gR, ga);
 }
 
 }  // namespace fea
