@@ -289,14 +289,14 @@ def batched_vs_sequential(scenes, fastea, metrics, synth, sequential=True, **opt
 
 
 def translation_stages(sc, fastea, synth, n_cand, with_cpu, cap_px=8.0, cpu_pairs=400, reps=5):
-    from paper_2605_18052_amd import metrics
     """Relative-translation search over the scene's matches (the true
-    rotations and focal lengths stand in for the outputs of global rotation
-    alignment and focal estimation, which are not built here; each match's
-    error capped at cap_px) and
+    rotations and focal lengths are its inputs, so that the stage is judged
+    on its own; global rotation and the focal vote are timed beside it from
+    their own perturbed starts; each match's error capped at cap_px) and
     camera-centre alignment (2 random starts, default schedule) on a
     500-camera object graph (pairs within 60 degrees, true directions with 2
     degrees of noise)."""
+    from paper_2605_18052_amd import metrics
     cand = synth.sphere_candidates(n_cand)
     ctx = fastea.Context(0)
     ctx.load_intrinsics(sc.f_init, sc.cx, sc.cy)
