@@ -386,12 +386,15 @@ def test_round_threshold_uses_the_median_focal_length(n_cams):
     ctx.close()
 
 
-def test_round_threshold_host_path_for_large_scenes():
-    """A scene with more cameras than the device round start sorts in LDS
-    (9,000 here) takes the host path for its median focal length; the
-    threshold is the same expression, and steps run at that camera count."""
+@pytest.mark.parametrize("N", [1500, 3000, 8192, 9000])
+def test_round_threshold_for_large_scenes(N):
+    """Scenes of 1,500, 3,000 and 8,192 cameras take the device round start
+    (the sort in LDS with one, two and four compare-exchange pairs per thread
+    and stage; 8,192 is its limit), 9,000 the host path; the threshold is
+    tau_px over numpy's median of the library's focal lengths either way,
+    exactly, and steps run at that camera count."""
     rng = np.random.default_rng(17)
-    N, per = 9000, 8
+    per = 8
     f = rng.uniform(400.0, 1200.0, N)
     cx, cy = np.full(N, 320.0), np.full(N, 240.0)
     R = np.tile(np.eye(3), (N, 1, 1))
