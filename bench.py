@@ -69,7 +69,7 @@ BATCH_CONVERGE_DEG = 0.01
 KERNEL_SOURCES = ("paper_2605_18052_amd/csrc/fea_resgrad.hip", "paper_2605_18052_amd/csrc/fea_device.h",
                   "paper_2605_18052_amd/csrc/fea_layout.h")
 PMC_TRAFFIC = {
-    "sources_sha256": "9b43d4ce747a7c29e82444c3f9ccd47173ef521a3525905faa3e815ec3201736",
+    "sources_sha256": "0da24db5ded85a54879b5459a4eb845c5d1291db8ce787a3be8fa4edbe0aa79d",
     # retained matches per launch -> "matches x threads" -> fetched + written bytes
     "bytes_per_launch": {
         87275962: {  # traj3000_m100M, round 0

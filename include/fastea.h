@@ -226,6 +226,15 @@ fea_status fea_set_scenes(fea_ctx *ctx, int32_t n_scenes, const int32_t *cam_sce
 fea_status fea_get_scene_stats(fea_ctx *ctx, double *loss, int64_t *retained,
                                double *gauge_center, double *gauge_scale, int32_t *learned);
 
+/* The two values the learned-weight judge compared at the end of the last
+ * learned round (Method > Epipolar Adjustment, the IRLS objective with the
+ * round's plain weights): per scene, host arrays [n_scenes] (either may be
+ * NULL), the objective at the round's snapshot poses and at the poses the
+ * round ended with, before any restore.  Both come from one pass over the
+ * matches.  Zeros before the first learned round.  Synchronises the
+ * context's stream. */
+fea_status fea_get_judge_losses(fea_ctx *ctx, double *loss_snapshot, double *loss_end);
+
 /* Per-scene convergence (options.converge_deg): converged_round [n_scenes]
  * receives the round at whose start each scene was found converged (it took
  * no steps from that round on), or -1; change_deg [n_scenes] the mean

@@ -333,6 +333,7 @@ hipError_t alloc_scene_arrays(fea_ctx* c) {
   if ((e = dalloc(c->d_fallbacks, (size_t)c->S * sizeof(int32_t))) != hipSuccess) return e;
   if ((e = dalloc(c->d_judge_l0, (size_t)c->S * sizeof(double))) != hipSuccess) return e;
   if ((e = dalloc(c->d_judge_l1, (size_t)c->S * sizeof(double))) != hipSuccess) return e;
+  c->judge_written = false;
   if ((e = upload(c, c->d_cam_scene, c->cam_scene.data(), c->cam_scene.size())) != hipSuccess) return e;
   // cameras of each scene, for the device round start
   std::vector<int32_t> off(c->S + 1, 0), cams(c->N, 0);
@@ -1274,6 +1275,20 @@ fea_status fea_get_scene_stats(fea_ctx* c, double* loss, int64_t* retained, doub
   return FEA_OK;
 }
 
+fea_status fea_get_judge_losses(fea_ctx* c, double* loss_snapshot, double* loss_end) {
+  if (!c) return FEA_EINVAL;
+  DeviceGuard g(c->device);
+  for (int k = 0; k < 2; ++k) {
+    double* out = k == 0 ? loss_snapshot : loss_end;
+    const DBuf& src = k == 0 ? c->d_judge_l0 : c->d_judge_l1;
+    if (!out) continue;
+    std::vector<double> h;
+    if (c->judge_written) HIP_OR_FAIL(c, download(c, h, src, (size_t)c->S));
+    for (int s = 0; s < c->S; ++s) out[s] = h.empty() ? 0.0 : h[s];
+  }
+  return FEA_OK;
+}
+
 fea_status fea_load_matches(fea_ctx* c, int64_t n, const float* x1, const float* y1, const float* x2,
                             const float* y2, const int32_t* cam1, const int32_t* cam2) {
   if (!c) return FEA_EINVAL;
@@ -1546,19 +1561,26 @@ namespace {
 
 // Plain IRLS objective per scene at poses (R, T, F) with this round's
 // snapshot weights (loss-only pass, learned weights ignored) into the
-// device array out [S]; no host wait unless the scenes' items interleave.
-fea_status plain_loss_per_scene(fea_ctx* c, const double* R, const double* T, const double* F, DBuf& out) {
+// device array out [S], and the same objective at the round's snapshot
+// into out_snap [S] (the pass's snapshot residuals); no host wait unless
+// the scenes' items interleave.
+fea_status plain_loss_per_scene(fea_ctx* c, const double* R, const double* T, const double* F, DBuf& out,
+                                DBuf& out_snap) {
   HIP_OR_FAIL(c, fea::launch_resgrad_at(c, c->tile_cfg, R, T, F, true, true));
   if (c->scene_items_contiguous) {
-    HIP_OR_FAIL(c, fea::launch_scene_loss(c, out.as<double>()));
+    HIP_OR_FAIL(c, fea::launch_scene_loss(c, out.as<double>(), out_snap.as<double>()));
     return FEA_OK;
   }
   // scenes with interleaved camera ids: sum the item losses on the host
-  std::vector<double> part, sum(c->S, 0.0);
+  std::vector<double> part, sum(c->S, 0.0), sum_snap(c->S, 0.0);
   HIP_OR_FAIL(c, download(c, part, c->part, (size_t)c->n_items * fea::kPartStride));
-  for (int64_t it = 0; it < c->n_items; ++it)
-    sum[c->pair_scene[c->h_item_pair[it]]] += part[it * fea::kPartStride + 9];
+  for (int64_t it = 0; it < c->n_items; ++it) {
+    const int sc = c->pair_scene[c->h_item_pair[it]];
+    sum[sc] += part[it * fea::kPartStride + 9];
+    sum_snap[sc] += part[it * fea::kPartStride + 8];
+  }
   HIP_OR_FAIL(c, upload(c, out, sum.data(), (size_t)c->S));
+  HIP_OR_FAIL(c, upload(c, out_snap, sum_snap.data(), (size_t)c->S));
   return FEA_OK;
 }
 
@@ -1600,17 +1622,16 @@ fea_status fea_epipolar_adjust(fea_ctx* c, fea_report* out) {
     if (s != FEA_OK) return s;
     if (c->opt.converge_deg > 0 && c->n_done == c->S) break;  // every scene converged
     const bool judge = c->learned_any;
-    if (judge) {
-      s = plain_loss_per_scene(c, c->Rh.as<double>(), c->Th.as<double>(), c->Fh.as<double>(), c->d_judge_l0);
-      if (s != FEA_OK) return s;
-    }
     s = run_steps(c, c->opt.iters_per_round);
     if (s != FEA_OK) return s;
     if (judge) {
-      // judge: a learned round must lower the plain objective of its scene
+      // judge: a learned round must lower the plain objective of its scene;
+      // one pass gives that objective at the round's end and at its
+      // snapshot (the residual the weights are taken from)
       s = plain_loss_per_scene(c, c->R[c->pcur].as<double>(), c->T[c->pcur].as<double>(),
-                               c->Fc[c->pcur].as<double>(), c->d_judge_l1);
+                               c->Fc[c->pcur].as<double>(), c->d_judge_l1, c->d_judge_l0);
       if (s != FEA_OK) return s;
+      c->judge_written = true;
       if ((s = judge_round(c)) != FEA_OK) return s;
     }
     if (r < 64) {

@@ -505,29 +505,48 @@ constexpr int kRoundStartValues = 22;  // per camera: 9 + 3 + 1 + 6 + 3
 constexpr int kSceneSumThreads = 1024;
 
 // Loss of every scene: the sum of its items' loss partials (a scene's items
-// are contiguous, since its cameras are), one workgroup per scene.
+// are contiguous, since its cameras are), one workgroup per scene; with
+// out_snap, also the sum of a loss-only pass's snapshot losses (slot 8).
 __global__ __launch_bounds__(kSceneSumThreads) void k_scene_loss(const int32_t* __restrict__ scene_item_off,
                                                                  const double* __restrict__ part,
-                                                                 double* __restrict__ out) {
-  __shared__ double s_red[kSceneSumThreads / kWave];
+                                                                 double* __restrict__ out,
+                                                                 double* __restrict__ out_snap) {
+  __shared__ double s_red[2][kSceneSumThreads / kWave];
   constexpr int T = kSceneSumThreads;
   const int sc = blockIdx.x, tid = threadIdx.x;
   const int e = scene_item_off[sc + 1];
-  double L = 0.0;
+  const bool snap = out_snap != nullptr;
+  double L = 0.0, Ls = 0.0;
   for (int it = scene_item_off[sc] + tid; it < e; it += 4 * T) {
-    double x[4];
+    double x[4], y[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) x[r] = it + r * T < e ? part[(int64_t)(it + r * T) * kPartStride + 9] : 0.0;
+    for (int r = 0; r < 4; ++r) {
+      const bool in = it + r * T < e;
+      const double* row = part + (int64_t)(it + r * T) * kPartStride;
+      x[r] = in ? row[9] : 0.0;
+      y[r] = (in && snap) ? row[8] : 0.0;
+    }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) L += x[r];
+    for (int r = 0; r < 4; ++r) {
+      L += x[r];
+      Ls += y[r];
+    }
   }
   L = wave_sum_f64(L);
-  if ((tid & 63) == 0) s_red[tid >> 6] = L;
+  Ls = wave_sum_f64(Ls);
+  if ((tid & 63) == 0) {
+    s_red[0][tid >> 6] = L;
+    s_red[1][tid >> 6] = Ls;
+  }
   __syncthreads();
   if (tid == 0) {
-    double t = 0.0;
-    for (int w = 0; w < T / kWave; ++w) t += s_red[w];
+    double t = 0.0, ts = 0.0;
+    for (int w = 0; w < T / kWave; ++w) {
+      t += s_red[0][w];
+      ts += s_red[1][w];
+    }
     out[sc] = t;
+    if (snap) out_snap[sc] = ts;
   }
 }
 
@@ -817,10 +836,10 @@ __global__ void k_total_z(int S, int64_t* __restrict__ zs) {
 
 }  // namespace
 
-hipError_t launch_scene_loss(fea_ctx* c, double* out) {
+hipError_t launch_scene_loss(fea_ctx* c, double* out, double* out_snap) {
   if (c->S == 0) return hipSuccess;
-  k_scene_loss<<<(unsigned)c->S, kSceneSumThreads, 0, c->stream>>>(c->d_scene_item_off.as<int32_t>(), c->part.as<double>(),
-                                                      out ? out : c->scene_loss.as<double>());
+  k_scene_loss<<<(unsigned)c->S, kSceneSumThreads, 0, c->stream>>>(
+      c->d_scene_item_off.as<int32_t>(), c->part.as<double>(), out ? out : c->scene_loss.as<double>(), out_snap);
   return hipGetLastError();
 }
 

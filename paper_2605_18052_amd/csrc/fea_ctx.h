@@ -138,6 +138,7 @@ struct fea_ctx {
   fea::DBuf d_learned_ok;                 // int32 [S]: 0 once the judge rejected the scene's learned weights
   fea::DBuf d_fallbacks;                  // int32 [S]: the judge's rejections per scene
   fea::DBuf d_judge_l0, d_judge_l1;       // double [S]: plain objective at a learned round's start and end
+  bool judge_written = false;             // d_judge_l0/l1 hold a judge pass of the current scenes
   int32_t fallbacks_base = 0;             // rejections restored from a checkpoint (added to d_fallbacks)
   hipEvent_t judge_ev = nullptr;          // recorded after the judge's flags are copied to judge_ok_h
   int32_t* judge_ok_h = nullptr;          // pinned [S]: d_learned_ok as of the last judge
@@ -213,7 +214,7 @@ hipError_t launch_choose_mode(fea_ctx* c, bool enabled);
 hipError_t launch_round_start(fea_ctx* c, bool shift, bool first, bool zero);
 hipError_t launch_scene_tau(fea_ctx* c, double tau_px, bool first);
 hipError_t launch_scene_z(fea_ctx* c);
-hipError_t launch_scene_loss(fea_ctx* c, double* out = nullptr);
+hipError_t launch_scene_loss(fea_ctx* c, double* out = nullptr, double* out_snap = nullptr);
 hipError_t launch_scene_converge(fea_ctx* c, bool check, int32_t round);
 hipError_t launch_guard(fea_ctx* c, int32_t round);
 hipError_t launch_scene_loss_log(fea_ctx* c, int32_t round);

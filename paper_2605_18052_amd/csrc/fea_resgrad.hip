@@ -19,7 +19,9 @@
 // 2 c eps p2 p1^T to dL/dF and c eps^2 to L accumulate per lane in fp32.
 // The 10 sums are reduced across each wave (a reduce-scatter of lane swaps
 // and DPP), across the waves in LDS, and written as one fp64 partial per
-// item -- no atomics, so the result is deterministic.
+// item -- no atomics, so the result is deterministic.  The loss-only pass
+// sums c eps^2 and, in the slot the gradient would use, c eps_hat^2: the
+// objective at the current poses and at the round's snapshot in one read.
 #include <hip/hip_runtime.h>
 
 #include <hip/hip_ext.h>
@@ -190,6 +192,11 @@ __device__ __forceinline__ void resgrad_item(const ItemRegs<THREADS, STEPS, WEIG
         acc[6] = fmaf(k2, x1c, acc[6]);
         acc[7] = fmaf(k2, y1c, acc[7]);
         acc[8] += k2;
+      } else {
+        // the loss-only pass also sums the loss at the round's snapshot,
+        // c eps_hat^2, into slot 8 (unused there otherwise)
+        const float ehf = (float)eph;
+        acc[8] = fmaf(c * ehf, ehf, acc[8]);
       }
       acc[9] = fmaf(c * ef, ef, acc[9]);
     }

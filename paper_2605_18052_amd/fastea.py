@@ -76,6 +76,7 @@ _SIGNATURES = {
     "fea_load_intrinsics": ([_P, C.c_int32, _P, _P, _P, _P], C.c_int),
     "fea_set_scenes": ([_P, C.c_int32, _P], C.c_int),
     "fea_get_scene_stats": ([_P, _P, _P, _P, _P, _P], C.c_int),
+    "fea_get_judge_losses": ([_P, _P, _P], C.c_int),
     "fea_get_scene_convergence": ([_P, _P, _P], C.c_int),
     "fea_get_scene_nonfinite": ([_P, _P], C.c_int),
     "fea_set_params_dev": ([_P, _P, _P, _P], C.c_int),
@@ -336,6 +337,14 @@ class Context:
                                               gc.ctypes.data_as(_P), gs.ctypes.data_as(_P),
                                               lm.ctypes.data_as(_P)))
         return dict(loss=loss, retained=ret, gauge_center=gc, gauge_scale=gs, learned=lm)
+
+    def judge_losses(self):
+        """Per scene, the plain objective at the last learned round's snapshot
+        and at its end, as the judge compared them (zeros before any)."""
+        S = self.info()["n_scenes"]
+        l0, l1 = np.zeros(S), np.zeros(S)
+        self._check(lib().fea_get_judge_losses(self._h, l0.ctypes.data_as(_P), l1.ctypes.data_as(_P)))
+        return l0, l1
 
     def scene_nonfinite(self):
         """Per scene: the round at whose start the non-finite guard stopped

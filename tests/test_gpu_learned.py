@@ -190,6 +190,36 @@ def test_judge_falls_back_on_a_harmful_network():
     assert res["inlier"][1] < 1.0
 
 
+@pytest.mark.parametrize("inner_loop", [0, 1])
+def test_judge_losses_against_the_oracle(inner_loop):
+    """The two plain objectives the judge compares after a learned round come
+    from one pass over the matches: the objective at the round's end, and at
+    its snapshot from the same pass's snapshot residuals.  Both against the
+    FP64 oracle's loss with that round's plain weights (the threshold filter
+    at the snapshot, 1/Z over the retained matches) at the snapshot and at
+    the poses the round ended with."""
+    sc = synth.config1()
+    o = fastea.default_options()
+    ctx = make_context(sc, weight_mode=1, inner_loop=inner_loop, rounds=1, iters_per_round=30)
+    ctx.set_mlp(_inlier_mlp().astype(np.float32))
+    ctx.init_poses(sc.R_init, sc.t_init)
+    R0, t0, f0 = ctx.get_poses()
+    l0, l1 = ctx.judge_losses()
+    assert not l0.any() and not l1.any()  # no learned round yet
+    ctx.epipolar_adjust()
+    l0, l1 = ctx.judge_losses()
+    assert ctx.scene_stats()["learned"][0] == 1  # kept: the poses are the round's end
+    R1, t1, f1 = ctx.get_poses()
+    ctx.close()
+    pb = oracle_problem(sc)
+    mask, _ = oracle.update_mask(pb, R0, t0, f0, o.tau_px_init / np.median(f0), np.ones(sc.n_matches, bool))
+    ref0 = oracle.loss_grad(pb, R0, t0, f0, R0, t0, f0, mask, delta=o.delta)[0]
+    ref1 = oracle.loss_grad(pb, R1, t1, f1, R0, t0, f0, mask, delta=o.delta)[0]
+    assert abs(l0[0] - ref0) <= 1e-5 * abs(ref0), (l0[0], ref0)
+    assert abs(l1[0] - ref1) <= 1e-5 * abs(ref1), (l1[0], ref1)
+    assert l1[0] < l0[0]
+
+
 def _auc(score, label):
     """Probability that a random inlier scores above a random outlier."""
     order = np.argsort(score, kind="stable")
